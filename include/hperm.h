@@ -1,0 +1,213 @@
+/*
+ * hperm: exact permanents of sparse non-negative integer matrices on an AMD Instinct
+ * MI355X (gfx950), after Wang, Liang, Bai and Huo, "A load balancing strategy for
+ * parallel computation of sparse permanents" (arXiv 1112.6072).
+ *
+ * The path behind these calls:
+ *   1. validation, bounds and arithmetic mode (host);
+ *   2. expansion (2) of the paper, applied as in Algorithm H_per (Section 2.1) and the
+ *      pre-expansion of Algorithm PH (Section 2.2), splits per(A) into sub-matrix jobs
+ *      (host, C++);
+ *   3. each job's 0-1 pattern gets a KKLLL estimate (Section 2.3) on the GPU (FP32; the
+ *      estimate only orders jobs and never enters a result);
+ *   4. jobs are sorted by non-increasing estimate (the improved Step 3 of Algorithm PH,
+ *      Section 3.3) and cut into work items of a device queue;
+ *   5. every job is evaluated exactly by R-NW (Ryser's formula in Nijenhuis-Wilf form,
+ *      Introduction) in Gray-code order by HIP kernels, in modular or wrap-around integer
+ *      arithmetic chosen so that the result is exact;
+ *   6. per-job values are normalised and summed (Step 4 of Algorithm PH) into per(A).
+ *
+ * Conventions for every call: pointers are host pointers unless a parameter says
+ * "device"; inputs are only read during the call and may be freed when it returns;
+ * every call returns an hperm_status and writes outputs only on HPERM_OK (poll/wait
+ * also on HPERM_NOT_READY, leaving the output untouched); no exception crosses the ABI.
+ * A context is used by one thread at a time, except hperm_submit/poll/wait/cancel,
+ * which are internally synchronised.
+ */
+#ifndef HPERM_H
+#define HPERM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hperm_status {
+    HPERM_OK = 0,
+    HPERM_NOT_READY = 1,     /* poll: the request is still running */
+    HPERM_E_INVALID = -1,    /* bad argument: sizes, ordering, null pointers, option ranges */
+    HPERM_E_RANGE = -2,      /* the exact result or an expanded entry does not fit the
+                                supported integer range (see hperm_permanent_csr) */
+    HPERM_E_DEVICE = -3,     /* a HIP call failed; hperm_last_error names it */
+    HPERM_E_NOMEM = -4,      /* host or device memory (or the caller's arena) is too small */
+    HPERM_E_BUSY = -5,       /* serving: no free request slot */
+    HPERM_E_CANCELLED = -6,  /* serving: the request was cancelled */
+    HPERM_E_TIMEOUT = -7,    /* serving: wait timed out (the request keeps running) */
+    HPERM_E_INTERNAL = -8    /* an integrity check failed (a job value not divisible by
+                                2^(m-1), a residue check mismatch); never returned silently */
+} hperm_status;
+
+/* Job order of the device queue (Step 3 of Algorithm PH and its improved form). */
+typedef enum hperm_order {
+    HPERM_ORDER_ESTIMATE = 0,    /* non-increasing KKLLL estimate (the paper's strategy) */
+    HPERM_ORDER_NATURAL = 1,     /* expansion (depth-first) order (the original PH Step 3) */
+    HPERM_ORDER_RANDOM = 2,      /* seeded shuffle */
+    HPERM_ORDER_EXACT_COST = 3   /* non-increasing subset-term count 2^(m-1), then estimate */
+} hperm_order;
+
+/* Exact arithmetic of the R-NW kernels. AUTO picks per job from a proven bound. */
+typedef enum hperm_arith {
+    HPERM_ARITH_AUTO = 0,
+    HPERM_ARITH_W64 = 1,    /* integers mod 2^64 (exact when per * 2^(m-1) < 2^63) */
+    HPERM_ARITH_W128 = 2,   /* integers mod 2^128 (exact when per * 2^(m-1) < 2^127) */
+    HPERM_ARITH_RES = 3     /* residues mod three primes near 2^61, host CRT (per < ~2^182) */
+} hperm_arith;
+
+typedef struct hperm_opts {
+    int32_t m_cut;        /* expand while the order exceeds m_cut (1..40; default 20) */
+    int32_t m_cap;        /* largest job order (m_cut..40; default 36) */
+    int32_t s_leaf;       /* a node whose sparsest line has >= s_leaf nonzeros and whose order
+                             is <= m_cap becomes a job (Algorithm H_per uses 5; default 5) */
+    int32_t arith;        /* hperm_arith (default AUTO) */
+    int32_t order;        /* hperm_order (default ESTIMATE) */
+    int32_t trials;       /* KKLLL trials per job (1..4096; default 32) */
+    uint64_t seed;        /* seed of the KKLLL draws and of ORDER_RANDOM (default 1) */
+    int32_t chunk_log2;   /* Gray indices per lane = 2^chunk_log2; 0 = autotuned table */
+    int32_t persistent;   /* 1: one persistent launch over the queue (default);
+                             0: one launch per job (the plain comparator) */
+    int32_t host_threads; /* expansion threads (0 = hardware threads, at most 64) */
+} hperm_opts;
+
+/* Result of one permanent. The value is non-negative: magnitude limbs, little-endian. */
+typedef struct hperm_result {
+    uint64_t limb[8];       /* per(A) = sum_k limb[k] * 2^(64k) */
+    int32_t nlimb;          /* limbs in use (0 means per(A) = 0) */
+    int32_t n_jobs;         /* sub-matrix jobs evaluated on the GPU */
+    int32_t max_m;          /* largest job order */
+    int32_t arith_mask;     /* bit (1 << hperm_arith) set for every mode used */
+    uint64_t subset_terms;  /* sum over jobs of 2^(m-1): the R-NW Gray-code terms */
+    double t_expand_s;      /* host expansion + job packing */
+    double t_estimate_s;    /* KKLLL kernel */
+    double t_rnw_s;         /* R-NW kernels (HIP events on the library stream) */
+    double t_total_s;       /* the whole call */
+} hperm_result;
+
+typedef struct hperm_ctx hperm_ctx;
+typedef struct hperm_jobs hperm_jobs;
+
+/* Library version. */
+hperm_status hperm_version(int32_t *major, int32_t *minor);
+
+/* Fill *opts with the defaults listed above. */
+hperm_status hperm_default_opts(hperm_opts *opts);
+
+/* Create a context on the current HIP device. opts may be NULL (defaults). stream is a
+ * hipStream_t to run on (e.g. torch.cuda.current_stream().cuda_stream), or NULL for a
+ * library-owned stream. The context owns its device buffers (grown on demand) unless an
+ * arena is set. Errors: HPERM_E_INVALID (option out of range), HPERM_E_DEVICE, NOMEM. */
+hperm_status hperm_ctx_create(const hperm_opts *opts, void *stream, hperm_ctx **out);
+
+/* A context without a device: only the host stages (hperm_expand_batch_csr,
+ * hperm_jobs_from_dense, hperm_jobs_info/describe) work; GPU calls return HPERM_E_DEVICE. */
+hperm_status hperm_ctx_create_host(const hperm_opts *opts, hperm_ctx **out);
+void hperm_ctx_destroy(hperm_ctx *ctx);
+
+/* Replace the context's options (same ranges as hperm_ctx_create). */
+hperm_status hperm_ctx_set_opts(hperm_ctx *ctx, const hperm_opts *opts);
+
+/* Let the library sub-allocate every device buffer from [dev_ptr, dev_ptr + bytes) (device
+ * memory owned by the caller, e.g. a torch tensor), valid until the context is destroyed
+ * or the arena is replaced. dev_ptr = NULL returns to library-owned memory. A call whose
+ * buffers do not fit returns HPERM_E_NOMEM and hperm_ctx_arena_required then gives the
+ * bytes it needed. */
+hperm_status hperm_ctx_set_arena(hperm_ctx *ctx, void *dev_ptr, size_t bytes);
+size_t hperm_ctx_arena_required(const hperm_ctx *ctx);
+
+/* per(A) of one n x n matrix given in CSR form: row_ptr[n+1] (row_ptr[0] = 0, non-decreasing),
+ * col_idx[nnz] strictly increasing within a row, values val[nnz] (uint32, zeros allowed).
+ * The problem statement of Algorithm H_per (Section 2.1) with non-negative integer entries.
+ * n = 0 gives 1; a zero row or column gives 0 without GPU work.
+ * Errors: HPERM_E_INVALID (n < 0 or n > 128, malformed CSR); HPERM_E_RANGE (an expanded
+ * entry or a row sum exceeds 2^24, or the proven bound on per(A) exceeds 2^180);
+ * HPERM_E_DEVICE; HPERM_E_NOMEM; HPERM_E_INTERNAL. */
+hperm_status hperm_permanent_csr(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                                 const int32_t *col_idx, const uint32_t *val, hperm_result *out);
+
+/* per(A) of a dense row-major n x n matrix a[n*n]; same rules as hperm_permanent_csr. */
+hperm_status hperm_permanent_dense(hperm_ctx *ctx, int32_t n, const uint32_t *a,
+                                   hperm_result *out);
+
+/* A batch of problems in one device pass: all their jobs share one queue and one
+ * persistent launch (Algorithm PH over several matrices). Problem k has order n[k] and
+ * CSR arrays at row_ptr + rp_off[k], col_idx + nz_off[k], val + nz_off[k]. out[count]. */
+hperm_status hperm_permanent_batch_csr(hperm_ctx *ctx, int32_t count, const int32_t *n,
+                                       const int64_t *rp_off, const int64_t *nz_off,
+                                       const int32_t *row_ptr, const int32_t *col_idx,
+                                       const uint32_t *val, hperm_result *out);
+
+/* ---- stages (tests and benchmarks) ------------------------------------------------ */
+
+/* Expand problems into jobs (steps 1-2 above) without running them. Same inputs as
+ * hperm_permanent_batch_csr. The job table is owned by the library until hperm_jobs_free. */
+hperm_status hperm_expand_batch_csr(hperm_ctx *ctx, int32_t count, const int32_t *n,
+                                    const int64_t *rp_off, const int64_t *nz_off,
+                                    const int32_t *row_ptr, const int32_t *col_idx,
+                                    const uint32_t *val, hperm_jobs **out);
+
+/* Jobs given directly: count dense row-major matrices, matrix k of order m[k] (1..40) at
+ * a + off[k]; each job is evaluated by R-NW as it is (no expansion), as problem k. */
+hperm_status hperm_jobs_from_dense(hperm_ctx *ctx, int32_t count, const int32_t *m,
+                                   const int64_t *off, const uint32_t *a, hperm_jobs **out);
+
+/* Number of jobs; per job: order m, problem index, arithmetic mode, natural index. */
+hperm_status hperm_jobs_info(const hperm_jobs *jobs, int32_t *n_jobs, int32_t *n_problems);
+hperm_status hperm_jobs_describe(const hperm_jobs *jobs, int32_t *m, int32_t *problem,
+                                 int32_t *arith, uint64_t *terms);
+
+/* KKLLL estimates of every job's pattern (step 3): trials per job and seed as given.
+ * keys[n_jobs] (may be NULL) receives log of the mean of the trials (natural log;
+ * -INFINITY when every trial was singular). The keys are kept for ORDER_ESTIMATE. */
+hperm_status hperm_estimate(hperm_ctx *ctx, hperm_jobs *jobs, int32_t trials, uint64_t seed,
+                            float *keys);
+
+/* Evaluate all jobs (steps 4-6) in the given order, persistent (1) or one launch per job
+ * (0). per_job[n_jobs] (may be NULL) receives each job's exact permanent; totals[n_problems]
+ * receives per(A) of every problem. ORDER_ESTIMATE requires hperm_estimate first. */
+hperm_status hperm_run_jobs(hperm_ctx *ctx, hperm_jobs *jobs, int32_t order, int32_t persistent,
+                            hperm_result *per_job, hperm_result *totals);
+
+void hperm_jobs_free(hperm_jobs *jobs);
+
+/* ---- serving ------------------------------------------------------------------------ */
+
+/* Start the serving loop of a context: a background thread admits requests while free
+ * request slots (max_requests) and device memory (arena_bytes for job tables) allow,
+ * expands them on worker threads, merges their jobs into one device queue shared by all
+ * requests in flight (continuous batching), and completes each request when its last job
+ * is done. The context must not be used for blocking calls while serving. */
+hperm_status hperm_serve_start(hperm_ctx *ctx, int32_t max_requests, size_t arena_bytes);
+hperm_status hperm_serve_stop(hperm_ctx *ctx);
+
+/* Submit per(A) of a CSR matrix (copied). *ticket identifies it. HPERM_E_BUSY when the
+ * admission queue is full. */
+hperm_status hperm_submit(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                          const int32_t *col_idx, const uint32_t *val, uint64_t *ticket);
+
+/* HPERM_NOT_READY while running; on HPERM_OK fills *out once and frees the ticket. The
+ * result's timing fields hold queue wait (t_expand_s: submit to admission) and latency
+ * (t_total_s: submit to completion). */
+hperm_status hperm_poll(hperm_ctx *ctx, uint64_t ticket, hperm_result *out);
+hperm_status hperm_wait(hperm_ctx *ctx, uint64_t ticket, double timeout_s, hperm_result *out);
+hperm_status hperm_cancel(hperm_ctx *ctx, uint64_t ticket);
+
+/* ---- diagnostics -------------------------------------------------------------------- */
+const char *hperm_status_string(hperm_status s);
+/* Message of the context's last error (empty string if none); valid until the next call. */
+const char *hperm_last_error(const hperm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPERM_H */

@@ -16,11 +16,11 @@ kkl.py         the KKLLL estimator (Section 2.3): one trial |det B|^2 for given 
 ryser_c.c      plain Ryser in C with 128-bit wrap-around integers, threaded over a list
                of matrices; used only to time a CPU baseline.
 """
-from .permanent import (per_brute, per_ryser, nw_doubled_sum, per_nw, e2_children,
+from .permanent import (per_brute, per_ryser, nw_doubled_sum, per_nw, e2_children, expand_leaves,
                         choose_line, per_hybrid, per_dp, per_auto)
 from .kkl import splitmix64, kkl_exponent, kkl_trial, kkl_key
 
 __all__ = [
-    "per_brute", "per_ryser", "nw_doubled_sum", "per_nw", "e2_children", "choose_line",
+    "per_brute", "per_ryser", "nw_doubled_sum", "per_nw", "e2_children", "expand_leaves", "choose_line",
     "per_hybrid", "per_dp", "per_auto", "splitmix64", "kkl_exponent", "kkl_trial", "kkl_key",
 ]

@@ -304,3 +304,33 @@ def per_auto(A) -> int:
     """Exact per(A) by the cheapest applicable route: brute force for n <= 6, else the DP."""
     a = _as_lists(A)
     return per_brute(a) if len(a) <= 6 else per_dp(a)
+
+
+# --------------------------------------------------------------------------- jobs of PH
+def expand_leaves(A, m_cut: int, s_leaf: int = 5, m_cap: int = 40) -> list[list[list[int]]]:
+    """The sub-matrix jobs of a pre-expansion (Algorithm PH, Step 2) with a size-based stop.
+
+    Depth-first over the expansion tree, children in pair order: a node whose smallest
+    line has s = 0 nonzeros is dropped (per = 0); it is a job when its order is at most
+    m_cut (or at most 2), or when s >= s_leaf and its order is at most m_cap (Algorithm
+    H_per hands such a node to R-NW); otherwise it is split by expansion (2) along that
+    line (see ``choose_line`` and ``e2_children``). Returns the jobs in depth-first order;
+    by Step 4 of Algorithm PH their permanents sum to per(A)."""
+    out = []
+
+    def rec(a):
+        n = len(a)
+        if n == 0:
+            out.append(a)
+            return
+        kind, idx, s = choose_line(a)
+        if s == 0:
+            return
+        if n <= m_cut or n <= 2 or (s >= s_leaf and n <= m_cap):
+            out.append(a)
+            return
+        for c in e2_children(a, kind, idx):
+            rec(c)
+
+    rec(_as_lists(A))
+    return out

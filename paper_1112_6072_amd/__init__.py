@@ -1,0 +1,331 @@
+"""Python binding of libhperm: exact permanents of sparse non-negative integer matrices on MI355X.
+
+Argument marshalling only: every step of the computation runs in the C++/HIP library
+(``_build/libhperm.so``, built by ``paper_1112_6072_amd.build``). PyTorch supplies the HIP
+stream (``torch.cuda.current_stream()``) and, optionally, the device arena the library
+sub-allocates from. Importing this package fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libhperm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1112_6072_amd/build.py`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, NOT_READY = 0, 1
+ORDER_ESTIMATE, ORDER_NATURAL, ORDER_RANDOM, ORDER_EXACT_COST = 0, 1, 2, 3
+ARITH_AUTO, ARITH_W64, ARITH_W128, ARITH_RES = 0, 1, 2, 3
+ORDERS = {"estimate": 0, "natural": 1, "random": 2, "exact_cost": 3}
+ARITHS = {"auto": 0, "w64": 1, "w128": 2, "res": 3}
+
+
+class HpermError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_lib.hperm_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("m_cut", ctypes.c_int32), ("m_cap", ctypes.c_int32), ("s_leaf", ctypes.c_int32),
+                ("arith", ctypes.c_int32), ("order", ctypes.c_int32), ("trials", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("chunk_log2", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("host_threads", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("limb", ctypes.c_uint64 * 8), ("nlimb", ctypes.c_int32), ("n_jobs", ctypes.c_int32),
+                ("max_m", ctypes.c_int32), ("arith_mask", ctypes.c_int32),
+                ("subset_terms", ctypes.c_uint64), ("t_expand_s", ctypes.c_double),
+                ("t_estimate_s", ctypes.c_double), ("t_rnw_s", ctypes.c_double),
+                ("t_total_s", ctypes.c_double)]
+
+    @property
+    def value(self) -> int:
+        return sum(int(self.limb[k]) << (64 * k) for k in range(self.nlimb))
+
+    def stats(self) -> dict:
+        return {"n_jobs": self.n_jobs, "max_m": self.max_m, "arith_mask": self.arith_mask,
+                "subset_terms": int(self.subset_terms), "t_expand_s": self.t_expand_s,
+                "t_estimate_s": self.t_estimate_s, "t_rnw_s": self.t_rnw_s, "t_total_s": self.t_total_s}
+
+
+_P = ctypes.c_void_p
+_I32, _U64, _SZ = ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
+_SIGS = {
+    "hperm_version": [ctypes.POINTER(_I32), ctypes.POINTER(_I32)],
+    "hperm_default_opts": [ctypes.POINTER(Opts)],
+    "hperm_ctx_create": [ctypes.POINTER(Opts), _P, ctypes.POINTER(_P)],
+    "hperm_ctx_create_host": [ctypes.POINTER(Opts), ctypes.POINTER(_P)],
+    "hperm_ctx_set_opts": [_P, ctypes.POINTER(Opts)],
+    "hperm_ctx_set_arena": [_P, _P, _SZ],
+    "hperm_permanent_csr": [_P, _I32, _P, _P, _P, ctypes.POINTER(Result)],
+    "hperm_permanent_dense": [_P, _I32, _P, ctypes.POINTER(Result)],
+    "hperm_permanent_batch_csr": [_P, _I32, _P, _P, _P, _P, _P, _P, _P],
+    "hperm_expand_batch_csr": [_P, _I32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)],
+    "hperm_jobs_from_dense": [_P, _I32, _P, _P, _P, ctypes.POINTER(_P)],
+    "hperm_jobs_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)],
+    "hperm_jobs_describe": [_P, _P, _P, _P, _P],
+    "hperm_estimate": [_P, _P, _I32, _U64, _P],
+    "hperm_run_jobs": [_P, _P, _I32, _I32, _P, _P],
+    "hperm_serve_start": [_P, _I32, _SZ],
+    "hperm_serve_stop": [_P],
+    "hperm_submit": [_P, _I32, _P, _P, _P, ctypes.POINTER(_U64)],
+    "hperm_poll": [_P, _U64, ctypes.POINTER(Result)],
+    "hperm_wait": [_P, _U64, ctypes.c_double, ctypes.POINTER(Result)],
+    "hperm_cancel": [_P, _U64],
+}
+for _name, _args in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = ctypes.c_int
+_lib.hperm_ctx_destroy.argtypes = [_P]
+_lib.hperm_ctx_destroy.restype = None
+_lib.hperm_jobs_free.argtypes = [_P]
+_lib.hperm_jobs_free.restype = None
+_lib.hperm_status_string.argtypes = [ctypes.c_int]
+_lib.hperm_status_string.restype = ctypes.c_char_p
+_lib.hperm_last_error.argtypes = [_P]
+_lib.hperm_last_error.restype = ctypes.c_char_p
+_lib.hperm_ctx_arena_required.argtypes = [_P]
+_lib.hperm_ctx_arena_required.restype = _SZ
+
+EXPORTED = sorted(list(_SIGS) + ["hperm_ctx_destroy", "hperm_jobs_free", "hperm_status_string",
+                                 "hperm_last_error", "hperm_ctx_arena_required"])
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_P)
+
+
+def _csr(A) -> tuple[int, np.ndarray, np.ndarray, np.ndarray]:
+    A = np.asarray(A)
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("square matrix expected")
+    if A.size and (A.min() < 0):
+        raise ValueError("entries must be non-negative")
+    n = A.shape[0]
+    rows, cols = np.nonzero(A)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    np.add.at(rp, rows + 1, 1)
+    rp = np.cumsum(rp).astype(np.int32)
+    return n, rp, cols.astype(np.int32), A[rows, cols].astype(np.uint32)
+
+
+def _batch_csr(mats):
+    parts = [_csr(A) for A in mats]
+    n = np.array([p[0] for p in parts], dtype=np.int32)
+    rp_off = np.zeros(len(parts), dtype=np.int64)
+    nz_off = np.zeros(len(parts), dtype=np.int64)
+    o1 = o2 = 0
+    for k, p in enumerate(parts):
+        rp_off[k], nz_off[k] = o1, o2
+        o1 += p[1].size
+        o2 += p[2].size
+    cat = lambda xs, dt: np.concatenate(xs).astype(dt) if xs else np.zeros(1, dt)  # noqa: E731
+    rp = cat([p[1] for p in parts], np.int32)
+    ci = cat([p[2] for p in parts] + [np.zeros(1, np.int32)], np.int32)
+    va = cat([p[3] for p in parts] + [np.zeros(1, np.uint32)], np.uint32)
+    return n, rp_off, nz_off, rp, ci, va
+
+
+def default_opts() -> dict:
+    o = Opts()
+    _lib.hperm_default_opts(ctypes.byref(o))
+    return {f: getattr(o, f) for f, _ in Opts._fields_}
+
+
+def _opts(d: dict | None) -> Opts:
+    o = Opts()
+    _lib.hperm_default_opts(ctypes.byref(o))
+    for k, v in (d or {}).items():
+        if k == "order" and isinstance(v, str):
+            v = ORDERS[v]
+        if k == "arith" and isinstance(v, str):
+            v = ARITHS[v]
+        setattr(o, k, v)
+    return o
+
+
+class Jobs:
+    """A job table owned by the library (sub-matrices produced by the expansion)."""
+
+    def __init__(self, ctx: "Context", handle):
+        self._ctx = ctx
+        self.handle = handle
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.hperm_jobs_free(self.handle)
+            self.handle = None
+
+    def info(self) -> tuple[int, int]:
+        nj, npb = _I32(), _I32()
+        _lib.hperm_jobs_info(self.handle, ctypes.byref(nj), ctypes.byref(npb))
+        return nj.value, npb.value
+
+    def describe(self) -> dict:
+        nj, _ = self.info()
+        m = np.zeros(max(nj, 1), np.int32)
+        prob = np.zeros(max(nj, 1), np.int32)
+        ar = np.zeros(max(nj, 1), np.int32)
+        terms = np.zeros(max(nj, 1), np.uint64)
+        _lib.hperm_jobs_describe(self.handle, _ptr(m), _ptr(prob), _ptr(ar), _ptr(terms))
+        return {"m": m[:nj], "problem": prob[:nj], "arith": ar[:nj], "terms": terms[:nj]}
+
+
+class Context:
+    """A library context on the current HIP device, running on torch's current stream.
+
+    ``host_only=True`` makes a context without a device (host stages only)."""
+
+    def __init__(self, opts: dict | None = None, stream=None, arena_bytes: int = 0,
+                 host_only: bool = False):
+        self._opts = _opts(opts)
+        h = _P()
+        if host_only:
+            st = _lib.hperm_ctx_create_host(ctypes.byref(self._opts), ctypes.byref(h))
+        else:
+            import torch
+            if not torch.cuda.is_available():
+                raise RuntimeError("no HIP device visible")
+            if stream is None:
+                stream = torch.cuda.current_stream().cuda_stream
+            st = _lib.hperm_ctx_create(ctypes.byref(self._opts), _P(stream), ctypes.byref(h))
+        if st != OK:
+            raise HpermError(st, "hperm_ctx_create")
+        self.handle = h
+        self._arena = None
+        if arena_bytes:
+            self.set_arena(arena_bytes)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.hperm_ctx_destroy(self.handle)
+            self.handle = None
+            self._arena = None
+
+    __del__ = close
+
+    def _check(self, st: int, what: str):
+        if st not in (OK,):
+            raise HpermError(st, f"{what}: {_lib.hperm_last_error(self.handle).decode()}")
+
+    def set_opts(self, **kw):
+        o = _opts(None)
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(self._opts), ctypes.sizeof(Opts))
+        for k, v in kw.items():
+            if k == "order" and isinstance(v, str):
+                v = ORDERS[v]
+            if k == "arith" and isinstance(v, str):
+                v = ARITHS[v]
+            setattr(o, k, v)
+        self._check(_lib.hperm_ctx_set_opts(self.handle, ctypes.byref(o)), "set_opts")
+        self._opts = o
+
+    def set_arena(self, nbytes: int):
+        """Give the library a torch-allocated device arena of nbytes (0 returns to its own memory)."""
+        import torch
+        if nbytes:
+            self._arena = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+            ptr, size = self._arena.data_ptr(), self._arena.numel()
+        else:
+            self._arena, ptr, size = None, None, 0
+        self._check(_lib.hperm_ctx_set_arena(self.handle, _P(ptr) if ptr else None, size), "set_arena")
+
+    def arena_required(self) -> int:
+        return int(_lib.hperm_ctx_arena_required(self.handle))
+
+    # ---------------------------------------------------------------- blocking calls
+    def permanent(self, A) -> int:
+        return self.permanent_batch([A])[0]
+
+    def permanent_batch(self, mats, with_stats: bool = False):
+        n, rp_off, nz_off, rp, ci, va = _batch_csr(mats)
+        out = (Result * max(len(mats), 1))()
+        st = _lib.hperm_permanent_batch_csr(self.handle, len(mats), _ptr(n), _ptr(rp_off), _ptr(nz_off),
+                                            _ptr(rp), _ptr(ci), _ptr(va), out)
+        self._check(st, "permanent_batch")
+        vals = [out[k].value for k in range(len(mats))]
+        if with_stats:
+            return vals, [out[k].stats() for k in range(len(mats))]
+        return vals
+
+    def permanent_csr(self, n, row_ptr, col_idx, val) -> int:
+        rp = np.ascontiguousarray(row_ptr, np.int32)
+        ci = np.ascontiguousarray(col_idx, np.int32)
+        va = np.ascontiguousarray(val, np.uint32)
+        r = Result()
+        st = _lib.hperm_permanent_csr(self.handle, int(n), _ptr(rp), _ptr(ci) if ci.size else None,
+                                      _ptr(va) if va.size else None, ctypes.byref(r))
+        self._check(st, "permanent_csr")
+        return r.value
+
+    # ---------------------------------------------------------------- stages
+    def expand(self, mats) -> Jobs:
+        n, rp_off, nz_off, rp, ci, va = _batch_csr(mats)
+        h = _P()
+        st = _lib.hperm_expand_batch_csr(self.handle, len(mats), _ptr(n), _ptr(rp_off), _ptr(nz_off),
+                                         _ptr(rp), _ptr(ci), _ptr(va), ctypes.byref(h))
+        self._check(st, "expand")
+        return Jobs(self, h)
+
+    def jobs_from_dense(self, mats) -> Jobs:
+        mats = [np.ascontiguousarray(np.asarray(A, dtype=np.uint32)) for A in mats]
+        m = np.array([A.shape[0] for A in mats], np.int32)
+        sizes = np.array([A.size for A in mats], np.int64)
+        off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+        a = np.concatenate([A.ravel() for A in mats] + [np.zeros(1, np.uint32)])
+        h = _P()
+        st = _lib.hperm_jobs_from_dense(self.handle, len(mats), _ptr(m), _ptr(off), _ptr(a), ctypes.byref(h))
+        self._check(st, "jobs_from_dense")
+        return Jobs(self, h)
+
+    def estimate(self, jobs: Jobs, trials: int = 32, seed: int = 1) -> np.ndarray:
+        nj, _ = jobs.info()
+        keys = np.zeros(max(nj, 1), np.float32)
+        self._check(_lib.hperm_estimate(self.handle, jobs.handle, int(trials), int(seed), _ptr(keys)),
+                    "estimate")
+        return keys[:nj]
+
+    def run(self, jobs: Jobs, order="estimate", persistent: bool = True, per_job: bool = False):
+        """Evaluate all jobs; returns (totals, per_job values or None, total Result list)."""
+        nj, npb = jobs.info()
+        order = ORDERS[order] if isinstance(order, str) else int(order)
+        pj = (Result * max(nj, 1))() if per_job else None
+        tot = (Result * max(npb, 1))()
+        st = _lib.hperm_run_jobs(self.handle, jobs.handle, order, 1 if persistent else 0, pj, tot)
+        self._check(st, "run_jobs")
+        totals = [tot[k].value for k in range(npb)]
+        pjv = [pj[k].value for k in range(nj)] if per_job else None
+        return totals, pjv, [tot[k] for k in range(npb)]
+
+
+def version() -> tuple[int, int]:
+    a, b = _I32(), _I32()
+    _lib.hperm_version(ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+_default_ctx = None
+
+
+def permanent(A, **opts) -> int:
+    """per(A) of a square non-negative integer matrix (numpy array or nested lists), exact."""
+    global _default_ctx
+    if opts:
+        ctx = Context(opts)
+        try:
+            return ctx.permanent(A)
+        finally:
+            ctx.close()
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx.permanent(A)

@@ -1,0 +1,737 @@
+// C ABI of libhperm and the host side of the GPU pipeline: device buffers, job upload,
+// KKLLL keys, the job order of the device queue (Step 3 of Algorithm PH, improved form of
+// Section 3.3), R-NW launches and the exact recombination of job values into per(A)
+// (Step 4 of Algorithm PH).
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "ctx.h"
+#include "kernels.h"
+
+using namespace hp;
+
+namespace hp {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+uint64_t next_jobs_id() {
+    static std::atomic<uint64_t> ctr{1};
+    return ctr.fetch_add(1);
+}
+
+hperm_status set_error(hperm_ctx *c, hperm_status s, const std::string &msg) {
+    if (c) c->last_error = msg;
+    return s;
+}
+
+hperm_status hip_check(hperm_ctx *c, hipError_t e, const char *what) {
+    if (e == hipSuccess) return HPERM_OK;
+    if (e == hipErrorOutOfMemory)
+        return set_error(c, HPERM_E_NOMEM, std::string(what) + ": " + hipGetErrorString(e));
+    return set_error(c, HPERM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+ExpandParams expand_params(const hperm_opts &o) {
+    ExpandParams p;
+    p.m_cut = o.m_cut;
+    p.m_cap = o.m_cap;
+    p.s_leaf = o.s_leaf;
+    p.arith = o.arith;
+    p.chunk_log2 = o.chunk_log2;
+    p.threads = o.host_threads;
+    return p;
+}
+
+static const size_t kAlign = 256;
+static size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Make buffer id hold at least `bytes`. With an arena, every buffer is a slice of it and a
+// growing buffer re-lays out all slices (their contents are transient per call).
+hperm_status ensure_buf(hperm_ctx *c, BufId id, size_t bytes) {
+    bytes = align_up(std::max<size_t>(bytes, kAlign));
+    DevBuf &b = c->buf[id];
+    if (b.ptr && b.cap >= bytes) return HPERM_OK;
+    if (c->arena) {
+        size_t total = 0;
+        for (int k = 0; k < B_COUNT; ++k) total += (k == id) ? bytes : c->buf[k].cap;
+        if (total > c->arena_bytes) {
+            c->arena_required = total;
+            return set_error(c, HPERM_E_NOMEM, "the caller's arena is too small");
+        }
+        size_t off = 0;
+        for (int k = 0; k < B_COUNT; ++k) {
+            const size_t cap = (k == id) ? bytes : c->buf[k].cap;
+            c->buf[k].ptr = cap ? (char *)c->arena + off : nullptr;
+            c->buf[k].cap = cap;
+            c->buf[k].owned = false;
+            off += cap;
+        }
+        c->resident_jobs = 0;
+        return HPERM_OK;
+    }
+    if (b.ptr && b.owned) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return hip_check(c, e, "hipStreamSynchronize");
+        (void)hipFree(b.ptr);
+        b.ptr = nullptr;
+        b.cap = 0;
+    }
+    if (id == B_DESC || id == B_DATA) c->resident_jobs = 0;
+    hipError_t e = hipMalloc(&b.ptr, bytes);
+    if (e != hipSuccess) {
+        b.ptr = nullptr;
+        c->arena_required = bytes;
+        return hip_check(c, e, "hipMalloc");
+    }
+    b.cap = bytes;
+    b.owned = true;
+    return HPERM_OK;
+}
+
+hperm_status upload_jobs(hperm_ctx *c, hperm_jobs *j) {
+    if (c->resident_jobs == j->id && j->id != 0) return HPERM_OK;
+    const size_t nd = j->tab.desc.size();
+    const size_t nw = j->tab.data.size() + 64;   // padding: lanes may read a few words past a block
+    hperm_status s = ensure_buf(c, B_DESC, nd * sizeof(JobDesc));
+    if (s) return s;
+    s = ensure_buf(c, B_DATA, nw * sizeof(uint32_t));
+    if (s) return s;
+    if (nd) {
+        s = hip_check(c, hipMemcpyAsync(c->buf[B_DESC].ptr, j->tab.desc.data(), nd * sizeof(JobDesc),
+                                        hipMemcpyHostToDevice, c->stream), "upload jobs");
+        if (s) return s;
+        s = hip_check(c, hipMemcpyAsync(c->buf[B_DATA].ptr, j->tab.data.data(),
+                                        j->tab.data.size() * sizeof(uint32_t),
+                                        hipMemcpyHostToDevice, c->stream), "upload job data");
+        if (s) return s;
+        static const uint32_t zeros[64] = {0};
+        s = hip_check(c, hipMemcpyAsync((char *)c->buf[B_DATA].ptr + j->tab.data.size() * 4, zeros,
+                                        sizeof(zeros), hipMemcpyHostToDevice, c->stream),
+                      "pad job data");
+        if (s) return s;
+    }
+    c->resident_jobs = j->id;
+    return HPERM_OK;
+}
+
+hperm_status estimate_jobs(hperm_ctx *c, hperm_jobs *j, int trials, uint64_t seed) {
+    if (trials < 1 || trials > 4096) return set_error(c, HPERM_E_INVALID, "trials must be in [1, 4096]");
+    const size_t nd = j->tab.desc.size();
+    j->keys.assign(nd, -INFINITY);
+    if (nd == 0) {
+        j->has_keys = true;
+        return HPERM_OK;
+    }
+    if (nd >= (1u << 28)) return set_error(c, HPERM_E_INVALID, "too many jobs for the estimator");
+    hperm_status s = upload_jobs(c, j);
+    if (s) return s;
+    s = ensure_buf(c, B_KEYS, nd * sizeof(float));
+    if (s) return s;
+    s = ensure_buf(c, B_LIST, nd * sizeof(uint32_t));
+    if (s) return s;
+    if (c->resident_jobs != j->id) {   // the arena was re-laid out: upload again
+        s = upload_jobs(c, j);
+        if (s) return s;
+    }
+    std::vector<uint32_t> list;
+    list.reserve(nd);
+    size_t off[5] = {0, 0, 0, 0, 0};
+    for (int b = 0; b < 4; ++b) {
+        off[b] = list.size();
+        for (size_t k = 0; k < nd; ++k)
+            if (bucket_of(j->tab.desc[k].m) == b) list.push_back((uint32_t)k);
+    }
+    off[4] = list.size();
+    s = hip_check(c, hipMemcpyAsync(c->buf[B_LIST].ptr, list.data(), list.size() * 4,
+                                    hipMemcpyHostToDevice, c->stream), "upload estimate list");
+    if (s) return s;
+    for (int b = 0; b < 4; ++b) {
+        const uint32_t n = (uint32_t)(off[b + 1] - off[b]);
+        if (!n) continue;
+        s = hip_check(c, launch_estimate(b, (const JobDesc *)c->buf[B_DESC].ptr,
+                                         (const uint32_t *)c->buf[B_DATA].ptr,
+                                         (const uint32_t *)c->buf[B_LIST].ptr + off[b], n, trials, seed,
+                                         (float *)c->buf[B_KEYS].ptr, c->stream),
+                      "kkl_estimate launch");
+        if (s) return s;
+    }
+    s = hip_check(c, hipMemcpyAsync(j->keys.data(), c->buf[B_KEYS].ptr, nd * sizeof(float),
+                                    hipMemcpyDeviceToHost, c->stream), "download keys");
+    if (s) return s;
+    s = hip_check(c, hipStreamSynchronize(c->stream), "estimate");
+    if (s) return s;
+    j->has_keys = true;
+    return HPERM_OK;
+}
+
+// Job order of the device queue. Ties keep the natural (expansion) order.
+static std::vector<uint32_t> job_order(const hperm_jobs *j, int order, uint64_t seed) {
+    const size_t nd = j->tab.desc.size();
+    std::vector<uint32_t> ord(nd);
+    std::iota(ord.begin(), ord.end(), 0u);
+    auto key = [&](uint32_t k) { return j->has_keys ? j->keys[k] : 0.0f; };
+    if (order == HPERM_ORDER_ESTIMATE) {
+        std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return key(a) > key(b); });
+    } else if (order == HPERM_ORDER_EXACT_COST) {
+        std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
+            const int ma = j->tab.desc[a].m, mb = j->tab.desc[b].m;
+            if (ma != mb) return ma > mb;
+            return key(a) > key(b);
+        });
+    } else if (order == HPERM_ORDER_RANDOM) {
+        // Fisher-Yates driven by SplitMix64 outputs
+        for (size_t i = nd; i > 1; --i) {
+            uint64_t z = seed + (uint64_t)i * 0x9E3779B97F4A7C15ull;
+            z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+            z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+            z ^= z >> 31;
+            std::swap(ord[i - 1], ord[(size_t)(z % i)]);
+        }
+    }
+    return ord;
+}
+
+// Lane chunk of a job for the one-launch-per-job comparator: as many waves as the GPU
+// holds at one wave per SIMD (2^10) when the job is large enough.
+static int plain_chunk(int m) {
+    int c = m - 1 - 6 - 10;
+    if (c < 0) c = 0;
+    if (c > 10) c = 10;
+    if (c < m - 32) c = m - 32;
+    return c;
+}
+
+static uint64_t items_of(int m, int c) {
+    const int e = m - 1 - 6 - c;
+    return e > 0 ? (1ull << e) : 1ull;
+}
+
+// Exact permanent of one job from its accumulator (see JobAcc). Returns false when an
+// integrity check fails (2^(m-1) must divide V in the 2-adic rings, the value must be
+// non-negative and within the proven bound).
+static bool job_value(const JobDesc &d, const JobAcc &a, double log2_bound, U512 *out) {
+    const int m = d.m;
+    const int sh = m - 1;
+    *out = U512();
+    if (d.arith == HP_W64 || d.arith == HP_W128) {
+        i128 V;
+        if (d.arith == HP_W64) {
+            V = (int64_t)a.l[0];
+        } else {
+            u128 u = (u128)a.l[0] + ((u128)a.l[1] << 32) + ((u128)a.l[2] << 64) + ((u128)a.l[3] << 96);
+            V = (i128)u;
+        }
+        if (sh & 1) V = -V;
+        if (V < 0) return false;
+        const u128 uv = (u128)V;
+        if (sh > 0 && (uv & (((u128)1 << sh) - 1)) != 0) return false;
+        out->add_u128(uv >> sh);
+    } else {
+        const uint64_t P[3] = {(1ull << 61) - HP_C0, (1ull << 61) - HP_C1, (1ull << 61) - HP_C2};
+        uint64_t r[3];
+        for (int k = 0; k < 3; ++k) {
+            const u128 v = (u128)a.l[2 * k] + ((u128)a.l[2 * k + 1] << 32);
+            uint64_t x = (uint64_t)(v % P[k]);
+            // per = (-1)^(m-1) * (2^-1)^(m-1) * V (mod p)
+            x = mulmod(x, powmod(invmod(2, P[k]), (uint64_t)sh, P[k]), P[k]);
+            if ((sh & 1) && x) x = P[k] - x;
+            r[k] = x;
+        }
+        // Garner: x = r0 + p0 * t1 + p0 p1 * t2
+        const uint64_t t1 = mulmod((r[1] + P[1] - r[0] % P[1]) % P[1], invmod(P[0] % P[1], P[1]), P[1]);
+        const uint64_t x01_mod_p2 = (uint64_t)(((u128)r[0] + (u128)P[0] % P[2] * t1) % P[2]);
+        const uint64_t p01_mod_p2 = mulmod(P[0] % P[2], P[1] % P[2], P[2]);
+        const uint64_t t2 = mulmod((r[2] + P[2] - x01_mod_p2) % P[2], invmod(p01_mod_p2, P[2]), P[2]);
+        U512 x;
+        x.w[0] = t2;
+        x.mul_u64(P[1]);
+        U512 y;
+        y.w[0] = t1;
+        x.add(y);
+        x.mul_u64(P[0]);
+        U512 z;
+        z.w[0] = r[0];
+        x.add(z);
+        *out = x;
+    }
+    const int bits = out->bits();
+    if (bits > (int)std::ceil(log2_bound) + 1) return false;
+    return true;
+}
+
+static void fill_result(const U512 &v, hperm_result *r) {
+    for (int k = 0; k < 8; ++k) r->limb[k] = v.w[k];
+    r->nlimb = v.nlimb();
+}
+
+hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
+                      hperm_result *per_job, hperm_result *totals, double *t_rnw) {
+    const size_t nd = j->tab.desc.size();
+    const int np = j->tab.n_problems;
+    if (order < 0 || order > 3) return set_error(c, HPERM_E_INVALID, "unknown order");
+    if ((order == HPERM_ORDER_ESTIMATE) && !j->has_keys && nd)
+        return set_error(c, HPERM_E_INVALID, "ORDER_ESTIMATE needs hperm_estimate first");
+    std::vector<U512> sums(np);
+    std::vector<int> nj(np, 0), maxm(np, 0), amask(np, 0);
+    std::vector<uint64_t> terms(np, 0);
+    *t_rnw = 0.0;
+    if (nd) {
+        hperm_status s;
+        // per-mode chunk sizes: the persistent queue uses the jobs' own chunks
+        std::vector<JobDesc> desc_plain;
+        if (!persistent) {
+            desc_plain = j->tab.desc;
+            for (auto &d : desc_plain) d.chunk_log2 = (uint8_t)plain_chunk(d.m);
+        }
+        const std::vector<JobDesc> &dsc = persistent ? j->tab.desc : desc_plain;
+        // queue groups by (ring, bucket), each in the chosen job order
+        const std::vector<uint32_t> ord = job_order(j, order, c->opts.seed);
+        std::vector<uint32_t> queue;
+        std::vector<uint64_t> item_end;
+        struct Group { int ring, bucket; size_t off, n; uint64_t items; };
+        std::vector<Group> groups;
+        queue.reserve(nd);
+        item_end.reserve(nd);
+        for (int b = 3; b >= 0; --b)
+            for (int r = HP_NRING - 1; r >= 0; --r) {
+                Group g{r, b, queue.size(), 0, 0};
+                uint64_t acc = 0;
+                for (uint32_t k : ord) {
+                    const JobDesc &d = dsc[k];
+                    if (d.arith != r || bucket_of(d.m) != b) continue;
+                    acc += items_of(d.m, d.chunk_log2);
+                    queue.push_back(k);
+                    item_end.push_back(acc);
+                }
+                g.n = queue.size() - g.off;
+                g.items = acc;
+                if (g.n) groups.push_back(g);
+            }
+        s = upload_jobs(c, j);
+        if (s) return s;
+        s = ensure_buf(c, B_QUEUE, nd * sizeof(uint32_t));
+        if (s) return s;
+        s = ensure_buf(c, B_ITEMS, nd * sizeof(uint64_t));
+        if (s) return s;
+        s = ensure_buf(c, B_ACCS, nd * sizeof(JobAcc));
+        if (s) return s;
+        s = ensure_buf(c, B_HEAD, 64 * sizeof(unsigned long long));
+        if (s) return s;
+        if (!persistent) {
+            s = ensure_buf(c, B_DESC_PLAIN, nd * sizeof(JobDesc));
+            if (s) return s;
+        }
+        if (c->resident_jobs != j->id) {
+            s = upload_jobs(c, j);
+            if (s) return s;
+        }
+        const JobDesc *d_desc = (const JobDesc *)c->buf[B_DESC].ptr;
+        if (!persistent) {
+            s = hip_check(c, hipMemcpyAsync(c->buf[B_DESC_PLAIN].ptr, desc_plain.data(),
+                                            nd * sizeof(JobDesc), hipMemcpyHostToDevice, c->stream),
+                          "upload plain descriptors");
+            if (s) return s;
+            d_desc = (const JobDesc *)c->buf[B_DESC_PLAIN].ptr;
+        }
+        s = hip_check(c, hipMemcpyAsync(c->buf[B_QUEUE].ptr, queue.data(), nd * 4,
+                                        hipMemcpyHostToDevice, c->stream), "upload queue");
+        if (s) return s;
+        s = hip_check(c, hipMemcpyAsync(c->buf[B_ITEMS].ptr, item_end.data(), nd * 8,
+                                        hipMemcpyHostToDevice, c->stream), "upload item ends");
+        if (s) return s;
+        JobAcc *accs = (JobAcc *)c->buf[B_ACCS].ptr;
+        unsigned long long *head = (unsigned long long *)c->buf[B_HEAD].ptr;
+        s = hip_check(c, launch_fill_u64((unsigned long long *)accs, nd * (sizeof(JobAcc) / 8), 0ull,
+                                         c->stream), "clear accumulators");
+        if (s) return s;
+        s = hip_check(c, launch_fill_u64(head, 64, 0ull, c->stream), "clear queue heads");
+        if (s) return s;
+        const uint32_t *d_data = (const uint32_t *)c->buf[B_DATA].ptr;
+        s = hip_check(c, hipEventRecord(c->ev0, c->stream), "event");
+        if (s) return s;
+        if (persistent) {
+            for (size_t gi = 0; gi < groups.size(); ++gi) {
+                const Group &g = groups[gi];
+                s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, d_desc, d_data,
+                                                       (const uint32_t *)c->buf[B_QUEUE].ptr + g.off,
+                                                       (const uint64_t *)c->buf[B_ITEMS].ptr + g.off,
+                                                       (uint32_t)g.n, g.items, head + gi, accs, 0,
+                                                       c->stream),
+                              "rnw_persistent launch");
+                if (s) return s;
+            }
+        } else {
+            // one launch per job, natural order
+            for (size_t k = 0; k < nd; ++k) {
+                const JobDesc &d = desc_plain[k];
+                s = hip_check(c, launch_rnw_single(d.arith, bucket_of(d.m), d_desc, d_data, (uint32_t)k,
+                                                   items_of(d.m, d.chunk_log2), accs, c->stream),
+                              "rnw_single launch");
+                if (s) return s;
+            }
+        }
+        s = hip_check(c, hipEventRecord(c->ev1, c->stream), "event");
+        if (s) return s;
+        std::vector<JobAcc> host(nd);
+        s = hip_check(c, hipMemcpyAsync(host.data(), accs, nd * sizeof(JobAcc), hipMemcpyDeviceToHost,
+                                        c->stream), "download job values");
+        if (s) return s;
+        s = hip_check(c, hipStreamSynchronize(c->stream), "R-NW");
+        if (s) return s;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+        *t_rnw = ms * 1e-3;
+        for (size_t k = 0; k < nd; ++k) {
+            const JobDesc &d = j->tab.desc[k];
+            U512 v;
+            if (!job_value(d, host[k], j->tab.log2_bound[k], &v))
+                return set_error(c, HPERM_E_INTERNAL, "a job value failed its integrity check (job " +
+                                                          std::to_string(k) + ")");
+            const int p = (int)d.problem;
+            sums[p].add(v);
+            nj[p]++;
+            maxm[p] = std::max(maxm[p], (int)d.m);
+            amask[p] |= 1 << (d.arith + 1);
+            terms[p] += 1ull << (d.m - 1);
+            if (per_job) {
+                memset(&per_job[k], 0, sizeof(hperm_result));
+                fill_result(v, &per_job[k]);
+                per_job[k].n_jobs = 1;
+                per_job[k].max_m = d.m;
+                per_job[k].arith_mask = 1 << (d.arith + 1);
+                per_job[k].subset_terms = 1ull << (d.m - 1);
+            }
+        }
+    }
+    for (int p = 0; p < np; ++p) {
+        hperm_result &r = totals[p];
+        memset(&r, 0, sizeof(r));
+        U512 v = sums[p];
+        if (j->tab.direct_valid[p]) {
+            v = U512();
+            v.w[0] = j->tab.direct_value[p];
+        }
+        fill_result(v, &r);
+        r.n_jobs = nj[p];
+        r.max_m = maxm[p];
+        r.arith_mask = amask[p];
+        r.subset_terms = terms[p];
+        r.t_rnw_s = *t_rnw;
+    }
+    return HPERM_OK;
+}
+
+}  // namespace hp
+
+// ====================================================================== C ABI
+extern "C" {
+
+hperm_status hperm_version(int32_t *major, int32_t *minor) {
+    if (!major || !minor) return HPERM_E_INVALID;
+    *major = 1;
+    *minor = 0;
+    return HPERM_OK;
+}
+
+hperm_status hperm_default_opts(hperm_opts *o) {
+    if (!o) return HPERM_E_INVALID;
+    memset(o, 0, sizeof(*o));
+    o->m_cut = 20;
+    o->m_cap = 36;
+    o->s_leaf = 5;
+    o->arith = HPERM_ARITH_AUTO;
+    o->order = HPERM_ORDER_ESTIMATE;
+    o->trials = 32;
+    o->seed = 1;
+    o->chunk_log2 = 0;
+    o->persistent = 1;
+    o->host_threads = 0;
+    return HPERM_OK;
+}
+
+static const char *check_opts(const hperm_opts *o) {
+    if (o->m_cut < 1 || o->m_cut > HP_MAX_M) return "m_cut must be in [1, 40]";
+    if (o->m_cap < o->m_cut || o->m_cap > HP_MAX_M) return "m_cap must be in [m_cut, 40]";
+    if (o->s_leaf < 1) return "s_leaf must be >= 1";
+    if (o->arith < 0 || o->arith > 3) return "unknown arith";
+    if (o->order < 0 || o->order > 3) return "unknown order";
+    if (o->trials < 1 || o->trials > 4096) return "trials must be in [1, 4096]";
+    if (o->chunk_log2 < 0 || o->chunk_log2 > 20) return "chunk_log2 must be in [0, 20]";
+    if (o->host_threads < 0 || o->host_threads > 64) return "host_threads must be in [0, 64]";
+    return nullptr;
+}
+
+hperm_status hperm_ctx_create(const hperm_opts *opts, void *stream, hperm_ctx **out) {
+    if (!out) return HPERM_E_INVALID;
+    *out = nullptr;
+    hperm_opts o;
+    hperm_default_opts(&o);
+    if (opts) {
+        if (check_opts(opts)) return HPERM_E_INVALID;
+        o = *opts;
+    }
+    hperm_ctx *c = new (std::nothrow) hperm_ctx();
+    if (!c) return HPERM_E_NOMEM;
+    c->opts = o;
+    if (hipGetDevice(&c->device) != hipSuccess ||
+        hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess) {
+        delete c;
+        return HPERM_E_DEVICE;
+    }
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return HPERM_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return HPERM_E_DEVICE;
+    }
+    *out = c;
+    return HPERM_OK;
+}
+
+hperm_status hperm_ctx_create_host(const hperm_opts *opts, hperm_ctx **out) {
+    if (!out) return HPERM_E_INVALID;
+    *out = nullptr;
+    hperm_opts o;
+    hperm_default_opts(&o);
+    if (opts) {
+        if (check_opts(opts)) return HPERM_E_INVALID;
+        o = *opts;
+    }
+    hperm_ctx *c = new (std::nothrow) hperm_ctx();
+    if (!c) return HPERM_E_NOMEM;
+    c->opts = o;
+    c->host_only = true;
+    *out = c;
+    return HPERM_OK;
+}
+
+
+void hperm_ctx_destroy(hperm_ctx *c) {
+    if (!c) return;
+    if (c->host_only) {
+        delete c;
+        return;
+    }
+    hp::serve_shutdown(c);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &b : c->buf)
+        if (b.ptr && b.owned) (void)hipFree(b.ptr);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+hperm_status hperm_ctx_set_opts(hperm_ctx *c, const hperm_opts *o) {
+    if (!c || !o) return HPERM_E_INVALID;
+    if (const char *why = check_opts(o)) return set_error(c, HPERM_E_INVALID, why);
+    c->opts = *o;
+    return HPERM_OK;
+}
+
+hperm_status hperm_ctx_set_arena(hperm_ctx *c, void *dev_ptr, size_t bytes) {
+    if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
+    if (!c) return HPERM_E_INVALID;
+    if (dev_ptr && bytes < 4096) return set_error(c, HPERM_E_INVALID, "arena too small");
+    (void)hipStreamSynchronize(c->stream);
+    for (auto &b : c->buf) {
+        if (b.ptr && b.owned) (void)hipFree(b.ptr);
+        b = DevBuf();
+    }
+    c->arena = dev_ptr;
+    c->arena_bytes = dev_ptr ? bytes : 0;
+    c->resident_jobs = 0;
+    return HPERM_OK;
+}
+
+size_t hperm_ctx_arena_required(const hperm_ctx *c) { return c ? c->arena_required : 0; }
+
+static hperm_status expand_batch(hperm_ctx *c, int32_t count, const int32_t *n, const int64_t *rp_off,
+                                 const int64_t *nz_off, const int32_t *row_ptr, const int32_t *col_idx,
+                                 const uint32_t *val, hperm_jobs *j) {
+    if (count < 0 || (count > 0 && (!n || !rp_off || !nz_off))) return set_error(c, HPERM_E_INVALID, "bad batch arrays");
+    std::vector<CsrView> probs(count);
+    for (int k = 0; k < count; ++k) {
+        CsrView v{n[k], row_ptr ? row_ptr + rp_off[k] : nullptr, col_idx ? col_idx + nz_off[k] : nullptr,
+                  val ? val + nz_off[k] : nullptr};
+        const std::string why = validate_csr(v);
+        if (!why.empty()) return set_error(c, HPERM_E_INVALID, "problem " + std::to_string(k) + ": " + why);
+        probs[k] = v;
+    }
+    std::string err;
+    const int rc = expand_problems(probs, expand_params(c->opts), &j->tab, &err);
+    if (rc == -2) return set_error(c, HPERM_E_RANGE, err);
+    if (rc) return set_error(c, HPERM_E_INVALID, err);
+    j->id = next_jobs_id();
+    return HPERM_OK;
+}
+
+hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_t *n,
+                                       const int64_t *rp_off, const int64_t *nz_off,
+                                       const int32_t *row_ptr, const int32_t *col_idx,
+                                       const uint32_t *val, hperm_result *out) {
+    if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
+    if (!c || !out) return HPERM_E_INVALID;
+    if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
+    std::lock_guard<std::mutex> lk(c->call_mu);
+    c->last_error.clear();
+    const double t0 = now_s();
+    hperm_jobs j;
+    hperm_status s = expand_batch(c, count, n, rp_off, nz_off, row_ptr, col_idx, val, &j);
+    if (s) return s;
+    const double t1 = now_s();
+    double t_est = 0.0;
+    if (!j.tab.desc.empty() && (c->opts.order == HPERM_ORDER_ESTIMATE || c->opts.order == HPERM_ORDER_EXACT_COST)) {
+        s = estimate_jobs(c, &j, c->opts.trials, c->opts.seed);
+        if (s) return s;
+        t_est = now_s() - t1;
+    }
+    double t_rnw = 0.0;
+    s = run_jobs(c, &j, c->opts.order, c->opts.persistent, nullptr, out, &t_rnw);
+    if (s) return s;
+    const double t2 = now_s();
+    for (int k = 0; k < count; ++k) {
+        out[k].t_expand_s = t1 - t0;
+        out[k].t_estimate_s = t_est;
+        out[k].t_total_s = t2 - t0;
+    }
+    return HPERM_OK;
+}
+
+hperm_status hperm_permanent_csr(hperm_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                 const uint32_t *val, hperm_result *out) {
+    const int64_t z = 0;
+    return hperm_permanent_batch_csr(c, 1, &n, &z, &z, row_ptr, col_idx, val, out);
+}
+
+hperm_status hperm_permanent_dense(hperm_ctx *c, int32_t n, const uint32_t *a, hperm_result *out) {
+    if (!c || !out) return HPERM_E_INVALID;
+    if (n < 0 || n > HP_MAX_N) return set_error(c, HPERM_E_INVALID, "n must be in [0, 128]");
+    if (n > 0 && !a) return set_error(c, HPERM_E_INVALID, "a is null");
+    std::vector<int32_t> rp(n + 1, 0), ci;
+    std::vector<uint32_t> v;
+    for (int i = 0; i < n; ++i) {
+        for (int jj = 0; jj < n; ++jj)
+            if (a[(int64_t)i * n + jj]) {
+                ci.push_back(jj);
+                v.push_back(a[(int64_t)i * n + jj]);
+            }
+        rp[i + 1] = (int32_t)ci.size();
+    }
+    return hperm_permanent_csr(c, n, rp.data(), ci.data(), v.data(), out);
+}
+
+hperm_status hperm_expand_batch_csr(hperm_ctx *c, int32_t count, const int32_t *n, const int64_t *rp_off,
+                                    const int64_t *nz_off, const int32_t *row_ptr, const int32_t *col_idx,
+                                    const uint32_t *val, hperm_jobs **out) {
+    if (!c || !out) return HPERM_E_INVALID;
+    *out = nullptr;
+    hperm_jobs *j = new (std::nothrow) hperm_jobs();
+    if (!j) return HPERM_E_NOMEM;
+    hperm_status s = expand_batch(c, count, n, rp_off, nz_off, row_ptr, col_idx, val, j);
+    if (s) {
+        delete j;
+        return s;
+    }
+    *out = j;
+    return HPERM_OK;
+}
+
+hperm_status hperm_jobs_from_dense(hperm_ctx *c, int32_t count, const int32_t *m, const int64_t *off,
+                                   const uint32_t *a, hperm_jobs **out) {
+    if (!c || !out || count < 0 || (count > 0 && (!m || !off || !a))) return HPERM_E_INVALID;
+    *out = nullptr;
+    hperm_jobs *j = new (std::nothrow) hperm_jobs();
+    if (!j) return HPERM_E_NOMEM;
+    std::string err;
+    const int rc = jobs_from_dense(count, m, off, a, expand_params(c->opts), &j->tab, &err);
+    if (rc) {
+        delete j;
+        return set_error(c, rc == -2 ? HPERM_E_RANGE : HPERM_E_INVALID, err);
+    }
+    j->id = next_jobs_id();
+    *out = j;
+    return HPERM_OK;
+}
+
+hperm_status hperm_jobs_info(const hperm_jobs *j, int32_t *n_jobs, int32_t *n_problems) {
+    if (!j || !n_jobs || !n_problems) return HPERM_E_INVALID;
+    *n_jobs = (int32_t)j->tab.desc.size();
+    *n_problems = j->tab.n_problems;
+    return HPERM_OK;
+}
+
+hperm_status hperm_jobs_describe(const hperm_jobs *j, int32_t *m, int32_t *problem, int32_t *arith,
+                                 uint64_t *terms) {
+    if (!j) return HPERM_E_INVALID;
+    for (size_t k = 0; k < j->tab.desc.size(); ++k) {
+        const JobDesc &d = j->tab.desc[k];
+        if (m) m[k] = d.m;
+        if (problem) problem[k] = (int32_t)d.problem;
+        if (arith) arith[k] = d.arith + 1;
+        if (terms) terms[k] = 1ull << (d.m - 1);
+    }
+    return HPERM_OK;
+}
+
+hperm_status hperm_estimate(hperm_ctx *c, hperm_jobs *j, int32_t trials, uint64_t seed, float *keys) {
+    if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
+    if (!c || !j) return HPERM_E_INVALID;
+    std::lock_guard<std::mutex> lk(c->call_mu);
+    hperm_status s = estimate_jobs(c, j, trials, seed);
+    if (s) return s;
+    if (keys) std::copy(j->keys.begin(), j->keys.end(), keys);
+    return HPERM_OK;
+}
+
+hperm_status hperm_run_jobs(hperm_ctx *c, hperm_jobs *j, int32_t order, int32_t persistent,
+                            hperm_result *per_job, hperm_result *totals) {
+    if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
+    if (!c || !j || !totals) return HPERM_E_INVALID;
+    std::lock_guard<std::mutex> lk(c->call_mu);
+    const double t0 = now_s();
+    double t_rnw = 0.0;
+    hperm_status s = run_jobs(c, j, order, persistent, per_job, totals, &t_rnw);
+    if (s) return s;
+    const double t1 = now_s();
+    for (int p = 0; p < j->tab.n_problems; ++p) totals[p].t_total_s = t1 - t0;
+    return HPERM_OK;
+}
+
+void hperm_jobs_free(hperm_jobs *j) { delete j; }
+
+const char *hperm_status_string(hperm_status s) {
+    switch (s) {
+        case HPERM_OK: return "ok";
+        case HPERM_NOT_READY: return "not ready";
+        case HPERM_E_INVALID: return "invalid argument";
+        case HPERM_E_RANGE: return "out of the supported integer range";
+        case HPERM_E_DEVICE: return "device error";
+        case HPERM_E_NOMEM: return "out of memory";
+        case HPERM_E_BUSY: return "busy";
+        case HPERM_E_CANCELLED: return "cancelled";
+        case HPERM_E_TIMEOUT: return "timed out";
+        case HPERM_E_INTERNAL: return "internal integrity check failed";
+    }
+    return "unknown status";
+}
+
+const char *hperm_last_error(const hperm_ctx *c) { return c ? c->last_error.c_str() : ""; }
+
+}  // extern "C"

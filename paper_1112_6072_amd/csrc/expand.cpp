@@ -1,0 +1,637 @@
+// Host expansion of per(A) into sub-matrix jobs, following expansion (2) and Algorithm
+// H_per (Section 2.1) and the pre-expansion of Algorithm PH (Section 2.2).
+//
+// A node is a sparse matrix of order m (rows as sorted column lists). At each node, s is
+// the smallest number of nonzeros in a row or a column (Step 1 of H_per; ties: rows
+// first, then the lowest index). s = 0 means per = 0 and the node is dropped. The node
+// becomes a job when m <= m_cut, or when s >= s_leaf and m <= m_cap (H_per hands a node
+// with s >= 5 to R-NW). Otherwise it is split by expansion (2) along that line: its
+// nonzeros v1, v2, ... (increasing column) are taken in pairs, the pair at columns p, q
+// giving the child with the row deleted and columns p, q replaced by v_p*y_q + v_q*y_p
+// (the first two terms of (2)); repeating (2) on the remainder term A3 consumes the row, so
+// k nonzeros give ceil(k/2) children of order m-1. An odd last nonzero is paired with a
+// column whose coefficient is 0 (a zero of the row if there is one), i.e. the Laplace term
+// v_p * per(minor) with the partner column scaled by v_p. A column line is expanded by the
+// same rule on the transpose (rows p, q merged, the column deleted), written directly on
+// the row lists.
+//
+// Jobs are emitted in depth-first order of the expansion tree (the "natural order" of
+// Step 3 of Algorithm PH). The top of the tree is split breadth-first into independent
+// subtrees that worker threads expand; their job lists are concatenated in subtree order,
+// so the result does not depend on the thread count.
+#include "expand.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+namespace hp {
+
+namespace {
+
+struct Node {
+    int m = 0;
+    int nnz = 0;
+    std::vector<int32_t> rp;    // m + 1
+    std::vector<uint8_t> ci;    // nnz, sorted within a row
+    std::vector<uint32_t> v;    // nnz, all nonzero
+    void reserve(int n, int nz) {
+        rp.resize(n + 1);
+        ci.resize(std::max(nz, 1));
+        v.resize(std::max(nz, 1));
+    }
+};
+
+struct RangeError {
+    std::string msg;
+};
+
+// Proven log2 upper bound of per(B) for a non-negative integer matrix: min of the product
+// of row sums and the product of column sums; for a 0-1 matrix also Bregman's bound
+// prod_i (r_i!)^(1/r_i) (rows, and columns by transposition).
+double log2_bound(const Node &a) {
+    const int m = a.m;
+    std::vector<double> rs(m, 0.0), cs(m, 0.0);
+    std::vector<int> rc(m, 0), cc(m, 0);
+    bool zero_one = true;
+    for (int i = 0; i < m; ++i)
+        for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
+            rs[i] += a.v[e];
+            cs[a.ci[e]] += a.v[e];
+            rc[i]++;
+            cc[a.ci[e]]++;
+            if (a.v[e] != 1) zero_one = false;
+        }
+    double lr = 0, lc = 0, br = 0, bc = 0;
+    for (int i = 0; i < m; ++i) {
+        if (rs[i] == 0 || cs[i] == 0) return -INFINITY;
+        lr += std::log2(rs[i]);
+        lc += std::log2(cs[i]);
+        if (zero_one) {
+            br += std::lgamma(rc[i] + 1.0) / std::log(2.0) / rc[i];
+            bc += std::lgamma(cc[i] + 1.0) / std::log(2.0) / cc[i];
+        }
+    }
+    double b = std::min(lr, lc);
+    if (zero_one) b = std::min(b, std::min(br, bc));
+    return b + 1e-6 * (1.0 + std::fabs(b));   // rounding margin
+}
+
+// Column and row counts; returns s and the chosen line.
+int min_line(const Node &a, bool *is_col, int *idx, int *colcnt) {
+    const int m = a.m;
+    for (int j = 0; j < m; ++j) colcnt[j] = 0;
+    for (int e = 0; e < a.nnz; ++e) colcnt[a.ci[e]]++;
+    int best = m + 1;
+    for (int i = 0; i < m; ++i) {
+        int k = a.rp[i + 1] - a.rp[i];
+        if (k < best) {
+            best = k;
+            *is_col = false;
+            *idx = i;
+        }
+    }
+    for (int j = 0; j < m; ++j)
+        if (colcnt[j] < best) {
+            best = colcnt[j];
+            *is_col = true;
+            *idx = j;
+        }
+    return best;
+}
+
+
+// Child of row r with the pair (p, q): row r deleted; columns p, q replaced by
+// ca * y_q + cb * y_p placed at min(p, q); columns above max(p, q) shift down by one.
+void make_child(const Node &a, int r, int p, int q, uint64_t ca, uint64_t cb, Node *c) {
+    const int m = a.m;
+    const int keep = std::min(p, q), drop = std::max(p, q);
+    c->m = m - 1;
+    int out = 0, ri = 0;
+    for (int i = 0; i < m; ++i) {
+        if (i == r) continue;
+        c->rp[ri++] = out;
+        uint64_t aip = 0, aiq = 0;
+        for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
+            if (a.ci[e] == p) aip = a.v[e];
+            if (a.ci[e] == q) aiq = a.v[e];
+        }
+        const uint64_t mv = ca * aiq + cb * aip;
+        if (mv >= HP_MAX_ENTRY) throw RangeError{"an expanded entry reached 2^23"};
+        bool merged = false;
+        for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
+            const int col = a.ci[e];
+            if (col == p || col == q) continue;
+            if (!merged && col > keep) {
+                if (mv) {
+                    c->ci[out] = (uint8_t)keep;
+                    c->v[out++] = (uint32_t)mv;
+                }
+                merged = true;
+            }
+            c->ci[out] = (uint8_t)(col - (col > drop ? 1 : 0));
+            c->v[out++] = a.v[e];
+        }
+        if (!merged && mv) {
+            c->ci[out] = (uint8_t)keep;
+            c->v[out++] = (uint32_t)mv;
+        }
+    }
+    c->rp[ri] = out;
+    c->nnz = out;
+}
+
+// Child of column cl with the row pair (p, q): column cl deleted; rows p, q replaced by
+// ca * row_q + cb * row_p placed at min(p, q); rows above max(p, q) and columns above cl
+// shift down by one. (Expansion (2) on the transpose, transposed back.)
+void make_child_col(const Node &a, int cl, int p, int q, uint64_t ca, uint64_t cb, Node *c) {
+    const int m = a.m;
+    const int keep = std::min(p, q), drop = std::max(p, q);
+    c->m = m - 1;
+    int out = 0, ri = 0;
+    for (int i = 0; i < m; ++i) {
+        if (i == drop) continue;
+        c->rp[ri++] = out;
+        if (i != keep) {
+            for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
+                const int col = a.ci[e];
+                if (col == cl) continue;
+                c->ci[out] = (uint8_t)(col - (col > cl ? 1 : 0));
+                c->v[out++] = a.v[e];
+            }
+            continue;
+        }
+        // merged row: ca * row_q + cb * row_p, both lists sorted by column
+        int eq = a.rp[q], eq_end = a.rp[q + 1], ep = a.rp[p], ep_end = a.rp[p + 1];
+        while (eq < eq_end || ep < ep_end) {
+            const int cq = eq < eq_end ? a.ci[eq] : 1 << 30;
+            const int cp = ep < ep_end ? a.ci[ep] : 1 << 30;
+            const int col = std::min(cq, cp);
+            uint64_t mv = 0;
+            if (cq == col) mv += ca * a.v[eq++];
+            if (cp == col) mv += cb * a.v[ep++];
+            if (col == cl || mv == 0) continue;
+            if (mv >= HP_MAX_ENTRY) throw RangeError{"an expanded entry reached 2^23"};
+            c->ci[out] = (uint8_t)(col - (col > cl ? 1 : 0));
+            c->v[out++] = (uint32_t)mv;
+        }
+    }
+    c->rp[ri] = out;
+    c->nnz = out;
+}
+
+struct Pair {
+    int p, q;
+    uint64_t ca, cb;
+};
+
+// Pairs of expansion (2) along column cl: its nonzeros in increasing row order, an odd
+// last one paired (coefficient 0) with the lowest row that is zero in this column.
+int col_pairs(const Node &a, int cl, Pair *out) {
+    const int m = a.m;
+    int rows[HP_MAX_N];
+    uint32_t vals[HP_MAX_N];
+    int k = 0, zero = -1;
+    for (int i = 0; i < m; ++i) {
+        uint32_t v = 0;
+        for (int e = a.rp[i]; e < a.rp[i + 1]; ++e)
+            if (a.ci[e] == cl) {
+                v = a.v[e];
+                break;
+            }
+        if (v) {
+            rows[k] = i;
+            vals[k++] = v;
+        } else if (zero < 0) {
+            zero = i;
+        }
+    }
+    int np = 0;
+    for (int t = 0; t < k; t += 2) {
+        Pair pr;
+        pr.p = rows[t];
+        pr.ca = vals[t];
+        if (t + 1 < k) {
+            pr.q = rows[t + 1];
+            pr.cb = vals[t + 1];
+        } else {
+            pr.q = zero >= 0 ? zero : (pr.p == 0 ? 1 : 0);
+            pr.cb = 0;
+        }
+        out[np++] = pr;
+    }
+    return np;
+}
+
+// Pairs of expansion (2) along row r (see the file comment).
+int row_pairs(const Node &a, int r, Pair *out) {
+    const int m = a.m;
+    const int b = a.rp[r], e = a.rp[r + 1], k = e - b;
+    int zero = -1;
+    {
+        int expect = 0;
+        for (int t = b; t < e && zero < 0; ++t, ++expect)
+            if (a.ci[t] != expect) zero = expect;
+        if (zero < 0 && k < m) zero = k;
+    }
+    int np = 0;
+    for (int t = 0; t < k; t += 2) {
+        Pair pr;
+        pr.p = a.ci[b + t];
+        pr.ca = a.v[b + t];
+        if (t + 1 < k) {
+            pr.q = a.ci[b + t + 1];
+            pr.cb = a.v[b + t + 1];
+        } else {
+            pr.q = zero >= 0 ? zero : (pr.p == 0 ? 1 : 0);
+            pr.cb = 0;
+        }
+        out[np++] = pr;
+    }
+    return np;
+}
+
+// ------------------------------------------------------------------ leaf -> job packing
+struct JobOut {
+    std::vector<JobDesc> desc;
+    std::vector<uint32_t> data;
+    std::vector<double> bound;
+};
+
+void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &prm,
+              JobOut *out) {
+    const int m = a.m;
+    if (m > HP_MAX_M) throw RangeError{"a job exceeds the largest supported order"};
+    // column lists
+    std::vector<int> cnt(m, 0);
+    for (int e = 0; e < a.nnz; ++e) cnt[a.ci[e]]++;
+    int fixed = 0;
+    for (int j = 1; j < m; ++j)
+        if (cnt[j] > cnt[fixed]) fixed = j;
+    std::vector<int> gray;
+    for (int j = 0; j < m; ++j)
+        if (j != fixed) gray.push_back(j);
+    std::stable_sort(gray.begin(), gray.end(), [&](int x, int y) { return cnt[x] < cnt[y]; });
+    std::vector<int> slot(m, -1);
+    for (int g = 0; g < (int)gray.size(); ++g) slot[gray[g]] = g;
+
+    std::vector<uint64_t> rsum(m, 0);
+    std::vector<int64_t> bfix(m, 0);
+    int nnz_gray = 0;
+    for (int i = 0; i < m; ++i)
+        for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
+            rsum[i] += a.v[e];
+            if (a.ci[e] == fixed) bfix[i] = a.v[e];
+            else ++nnz_gray;
+        }
+    for (int i = 0; i < m; ++i)
+        if (rsum[i] >= HP_MAX_ROWSUM) throw RangeError{"a job row sum reached 2^24"};
+
+    double lb = std::min(log2_bound(a), root_log2);
+    const double need = lb + m;   // |V| <= 2^(m-1) per, plus a sign bit
+    if (lb > 180.0) throw RangeError{"the permanent bound exceeds 2^180"};
+    const int auto_ring = need <= 62.5 ? HP_W64 : (need <= 126.5 ? HP_W128 : HP_RES);
+    int ring = auto_ring;
+    if (prm.arith == 1) ring = HP_W64;
+    if (prm.arith == 2) ring = HP_W128;
+    if (prm.arith == 3) ring = HP_RES;
+    // a forced ring narrower than the bound allows could wrap: refuse it
+    if (ring < auto_ring)
+        throw RangeError{"the requested arithmetic is too narrow for this problem's bound"};
+
+    JobDesc d;
+    d.data_off = (uint32_t)out->data.size();
+    d.m = (uint8_t)m;
+    d.arith = (uint8_t)ring;
+    d.chunk_log2 = (uint8_t)(prm.chunk_log2 > 0 ? prm.chunk_log2 : default_chunk_log2(m));
+    d.flags = 0;
+    d.nnz = (uint32_t)nnz_gray;
+    d.problem = (uint32_t)problem;
+    if (d.chunk_log2 > m - 1) d.chunk_log2 = (uint8_t)std::max(0, m - 1);
+    // at most 2^25 work items per job keep the per-job limb sums below 2^64
+    if ((int)d.chunk_log2 < m - 32) d.chunk_log2 = (uint8_t)(m - 32);
+
+    const size_t base = out->data.size();
+    out->data.resize(base + hp_job_words(m, nnz_gray));
+    uint32_t *w = out->data.data() + base;
+    for (int i = 0; i < m; ++i) w[i] = (uint32_t)(int32_t)(2 * bfix[i] - (int64_t)rsum[i]);
+    // Gray column g holds the entries of original column gray[g]
+    std::vector<int> gcnt(m, 0);
+    for (int i = 0; i < m; ++i)
+        for (int e = a.rp[i]; e < a.rp[i + 1]; ++e)
+            if (a.ci[e] != fixed) gcnt[slot[a.ci[e]]]++;
+    uint32_t *cs = w + m;
+    uint32_t acc = 0;
+    for (int g = 0; g < m - 1; ++g) {
+        cs[g] = acc;
+        acc += gcnt[g];
+    }
+    cs[m - 1] = acc;
+    uint32_t *ent = w + 2 * m;
+    std::vector<uint32_t> pos(cs, cs + m);
+    for (int i = 0; i < m; ++i)
+        for (int e = a.rp[i]; e < a.rp[i + 1]; ++e)
+            if (a.ci[e] != fixed) {
+                const int g = slot[a.ci[e]];
+                ent[pos[g]++] = ((2u * a.v[e]) << 8) | (uint32_t)i;
+            }
+    // original column index of every job column (Gray slots, then the fixed column)
+    uint32_t *cm = w + 2 * m + nnz_gray;
+    for (int g = 0; g < m - 1; ++g) cm[g] = (uint32_t)gray[g];
+    cm[m - 1] = (uint32_t)fixed;
+    out->desc.push_back(d);
+    out->bound.push_back(lb);
+}
+
+// ------------------------------------------------------------------ recursive expansion
+struct Workspace {
+    std::vector<Node> depth;   // one node buffer per depth
+    std::vector<int> colcnt;
+    void init(int n, int nnz) {
+        depth.assign(n + 2, Node());
+        for (auto &x : depth) x.reserve(n, nnz);
+        colcnt.assign(n + 1, 0);
+    }
+};
+
+enum Action { DROP, LEAF, SPLIT };
+
+Action classify(const Node &a, const ExpandParams &prm, Workspace &ws, bool *is_col, int *line) {
+    if (a.m == 0) return LEAF;   // handled by the caller (per = 1)
+    const int s = min_line(a, is_col, line, ws.colcnt.data());
+    if (s == 0) return DROP;
+    if (a.m <= prm.m_cut || a.m <= 2) return LEAF;
+    if (s >= prm.s_leaf && a.m <= prm.m_cap) return LEAF;
+    return SPLIT;
+}
+
+void expand_rec(int d, const ExpandParams &prm, Workspace &ws, int problem, double root_log2,
+                JobOut *out) {
+    const Node &a = ws.depth[d];
+    bool is_col = false;
+    int line = 0;
+    const Action act = classify(a, prm, ws, &is_col, &line);
+    if (act == DROP) return;
+    if (act == LEAF) {
+        emit_job(a, problem, root_log2, prm, out);
+        return;
+    }
+    Pair pairs[HP_MAX_N / 2 + 1];
+    const int np = is_col ? col_pairs(a, line, pairs) : row_pairs(a, line, pairs);
+    for (int t = 0; t < np; ++t) {
+        if (is_col)
+            make_child_col(a, line, pairs[t].p, pairs[t].q, pairs[t].ca, pairs[t].cb, &ws.depth[d + 1]);
+        else
+            make_child(a, line, pairs[t].p, pairs[t].q, pairs[t].ca, pairs[t].cb, &ws.depth[d + 1]);
+        expand_rec(d + 1, prm, ws, problem, root_log2, out);
+    }
+}
+
+// Breadth-first split of the top of one tree into subtree roots (kept in tree order).
+struct Pending {
+    Node node;
+    int problem;
+    double root_log2;
+};
+
+}  // namespace
+
+int default_chunk_log2(int m) {
+    // lanes walk 2^c Gray indices; one work item = 64 lanes
+    int c = m - 1 - 6;
+    if (c > 10) c = 10;
+    if (c < 0) c = 0;
+    return c;
+}
+
+std::string validate_csr(const CsrView &a) {
+    if (a.n < 0 || a.n > HP_MAX_N) return "n must be in [0, 128]";
+    if (a.n == 0) return "";
+    if (!a.row_ptr) return "row_ptr is null";
+    if (a.row_ptr[0] != 0) return "row_ptr[0] must be 0";
+    for (int i = 0; i < a.n; ++i)
+        if (a.row_ptr[i + 1] < a.row_ptr[i]) return "row_ptr must be non-decreasing";
+    const int nnz = a.row_ptr[a.n];
+    if (nnz > 0 && (!a.col_idx || !a.val)) return "col_idx/val are null";
+    for (int i = 0; i < a.n; ++i)
+        for (int e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e) {
+            if (a.col_idx[e] < 0 || a.col_idx[e] >= a.n) return "col_idx out of range";
+            if (e > a.row_ptr[i] && a.col_idx[e] <= a.col_idx[e - 1])
+                return "col_idx must be strictly increasing within a row";
+            if (a.val[e] >= HP_MAX_ENTRY) return "entries must be below 2^23";
+        }
+    return "";
+}
+
+static void run_subtrees(std::vector<Pending> &pend, const ExpandParams &prm, int maxn, int maxnnz,
+                         std::vector<JobOut> &outs, std::string *err, std::atomic<int> &bad) {
+    std::atomic<size_t> next{0};
+    int threads = prm.threads > 0 ? prm.threads : (int)std::thread::hardware_concurrency();
+    threads = std::max(1, std::min(threads, 64));
+    threads = (int)std::min<size_t>((size_t)threads, std::max<size_t>(pend.size(), 1));
+    std::vector<std::string> errs(threads);
+    auto work = [&](int tid) {
+        Workspace ws;
+        ws.init(maxn, maxnnz);
+        for (;;) {
+            const size_t k = next.fetch_add(1);
+            if (k >= pend.size() || bad.load()) break;
+            Node &root = ws.depth[0];
+            const Node &src = pend[k].node;
+            root.m = src.m;
+            root.nnz = src.nnz;
+            std::copy(src.rp.begin(), src.rp.begin() + src.m + 1, root.rp.begin());
+            std::copy(src.ci.begin(), src.ci.begin() + src.nnz, root.ci.begin());
+            std::copy(src.v.begin(), src.v.begin() + src.nnz, root.v.begin());
+            try {
+                expand_rec(0, prm, ws, pend[k].problem, pend[k].root_log2, &outs[k]);
+            } catch (const RangeError &e) {
+                errs[tid] = e.msg;
+                bad.store(1);
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    for (int t = 1; t < threads; ++t) th.emplace_back(work, t);
+    work(0);
+    for (auto &t : th) t.join();
+    for (auto &e : errs)
+        if (!e.empty()) *err = e;
+}
+
+int expand_problems(const std::vector<CsrView> &probs, const ExpandParams &prm, JobTable *out,
+                    std::string *err) {
+    const int p0 = out->n_problems;
+    out->n_problems += (int)probs.size();
+    out->direct_valid.resize(out->n_problems, 0);
+    out->direct_value.resize(out->n_problems, 0);
+    out->problem_log2_bound.resize(out->n_problems, 0.0);
+    std::vector<Pending> pend;
+    int maxn = 1, maxnnz = 1;
+    for (size_t k = 0; k < probs.size(); ++k) {
+        const CsrView &a = probs[k];
+        const int pid = p0 + (int)k;
+        if (a.n == 0) {
+            out->direct_valid[pid] = 1;
+            out->direct_value[pid] = 1;
+            continue;
+        }
+        Node root;
+        int nz = 0;
+        for (int e = 0; e < a.row_ptr[a.n]; ++e) nz += a.val[e] != 0;
+        root.reserve(a.n, nz);
+        root.m = a.n;
+        int o = 0;
+        for (int i = 0; i < a.n; ++i) {
+            root.rp[i] = o;
+            for (int e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
+                if (a.val[e]) {
+                    root.ci[o] = (uint8_t)a.col_idx[e];
+                    root.v[o++] = a.val[e];
+                }
+        }
+        root.rp[a.n] = o;
+        root.nnz = o;
+        const double lb = log2_bound(root);
+        out->problem_log2_bound[pid] = lb;
+        if (lb == -INFINITY) {   // a zero row or column
+            out->direct_valid[pid] = 1;
+            out->direct_value[pid] = 0;
+            continue;
+        }
+        if (lb > 180.0) {
+            *err = "the permanent bound of a problem exceeds 2^180";
+            return -2;
+        }
+        maxn = std::max(maxn, a.n);
+        maxnnz = std::max(maxnnz, std::max(o, 1));
+        pend.push_back(Pending{std::move(root), pid, lb});
+    }
+    // breadth-first split until there are enough subtrees for the threads
+    int threads = prm.threads > 0 ? prm.threads : (int)std::thread::hardware_concurrency();
+    const size_t want = (size_t)std::max(1, threads) * 16;
+    Workspace ws;
+    ws.init(maxn, maxnnz);
+    std::vector<char> is_leaf(pend.size(), 0);
+    for (int round = 0; round < 64 && pend.size() < want; ++round) {
+        std::vector<Pending> nxt;
+        std::vector<char> nleaf;
+        bool grew = false;
+        for (size_t t = 0; t < pend.size(); ++t) {
+            if (is_leaf[t]) {
+                nxt.push_back(std::move(pend[t]));
+                nleaf.push_back(1);
+                continue;
+            }
+            Node &a = pend[t].node;
+            bool is_col = false;
+            int line = 0;
+            const Action act = classify(a, prm, ws, &is_col, &line);
+            if (act == DROP) continue;
+            if (act == LEAF) {
+                nxt.push_back(std::move(pend[t]));
+                nleaf.push_back(1);
+                continue;
+            }
+            Pair pairs[HP_MAX_N / 2 + 1];
+            const int np = is_col ? col_pairs(a, line, pairs) : row_pairs(a, line, pairs);
+            for (int c = 0; c < np; ++c) {
+                Pending ch;
+                ch.node.reserve(a.m, a.nnz);
+                try {
+                    if (is_col)
+                        make_child_col(a, line, pairs[c].p, pairs[c].q, pairs[c].ca, pairs[c].cb, &ch.node);
+                    else
+                        make_child(a, line, pairs[c].p, pairs[c].q, pairs[c].ca, pairs[c].cb, &ch.node);
+                } catch (const RangeError &e) {
+                    *err = e.msg;
+                    return -2;
+                }
+                ch.problem = pend[t].problem;
+                ch.root_log2 = pend[t].root_log2;
+                nxt.push_back(std::move(ch));
+                nleaf.push_back(0);
+            }
+            grew = true;
+        }
+        pend = std::move(nxt);
+        is_leaf = std::move(nleaf);
+        if (!grew) break;
+    }
+    std::vector<JobOut> outs(pend.size());
+    std::atomic<int> bad{0};
+    run_subtrees(pend, prm, maxn, maxnnz, outs, err, bad);
+    if (bad.load()) return -2;
+    for (auto &o : outs) {
+        const uint32_t shift = (uint32_t)out->data.size();
+        for (auto d : o.desc) {
+            d.data_off += shift;
+            out->desc.push_back(d);
+        }
+        out->data.insert(out->data.end(), o.data.begin(), o.data.end());
+        out->log2_bound.insert(out->log2_bound.end(), o.bound.begin(), o.bound.end());
+    }
+    return 0;
+}
+
+int jobs_from_dense(int count, const int32_t *m, const int64_t *off, const uint32_t *a,
+                    const ExpandParams &prm, JobTable *out, std::string *err) {
+    const int p0 = out->n_problems;
+    out->n_problems += count;
+    out->direct_valid.resize(out->n_problems, 0);
+    out->direct_value.resize(out->n_problems, 0);
+    out->problem_log2_bound.resize(out->n_problems, 0.0);
+    JobOut jo;
+    for (int k = 0; k < count; ++k) {
+        const int n = m[k];
+        if (n < 1 || n > HP_MAX_M) {
+            *err = "job order must be in [1, 40]";
+            return -1;
+        }
+        Node nd;
+        nd.reserve(n, n * n);
+        nd.m = n;
+        int o = 0;
+        for (int i = 0; i < n; ++i) {
+            nd.rp[i] = o;
+            for (int j = 0; j < n; ++j) {
+                const uint32_t v = a[off[k] + (int64_t)i * n + j];
+                if (v >= HP_MAX_ENTRY) {
+                    *err = "entries must be below 2^23";
+                    return -1;
+                }
+                if (v) {
+                    nd.ci[o] = (uint8_t)j;
+                    nd.v[o++] = v;
+                }
+            }
+        }
+        nd.rp[n] = o;
+        nd.nnz = o;
+        const double lb = log2_bound(nd);
+        out->problem_log2_bound[p0 + k] = lb;
+        if (lb == -INFINITY) {
+            out->direct_valid[p0 + k] = 1;
+            out->direct_value[p0 + k] = 0;
+            continue;
+        }
+        try {
+            emit_job(nd, p0 + k, lb, prm, &jo);
+        } catch (const RangeError &e) {
+            *err = e.msg;
+            return -2;
+        }
+    }
+    const uint32_t shift = (uint32_t)out->data.size();
+    for (auto d : jo.desc) {
+        d.data_off += shift;
+        out->desc.push_back(d);
+    }
+    out->data.insert(out->data.end(), jo.data.begin(), jo.data.end());
+    out->log2_bound.insert(out->log2_bound.end(), jo.bound.begin(), jo.bound.end());
+    return 0;
+}
+
+}  // namespace hp

@@ -1,0 +1,56 @@
+// Host side of the path: validation, expansion (2) into jobs, bounds and job packing.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "hperm_internal.h"
+
+namespace hp {
+
+struct ExpandParams {
+    int m_cut = 20;
+    int m_cap = 36;
+    int s_leaf = 5;
+    int arith = 0;        // hperm_arith: 0 auto, 1 W64, 2 W128, 3 RES
+    int chunk_log2 = 0;   // 0: table
+    int threads = 0;
+};
+
+// Host copy of the job table of one or more problems.
+struct JobTable {
+    std::vector<JobDesc> desc;        // natural (expansion) order
+    std::vector<uint32_t> data;       // data blocks
+    std::vector<double> log2_bound;   // proven log2 upper bound of each job's permanent
+    int n_problems = 0;
+    // per problem: exact value known without GPU work (n = 0, tiny problems) and whether
+    // the problem is identically zero
+    std::vector<int> direct_valid;
+    std::vector<uint64_t> direct_value;   // valid when direct_valid (value < 2^64)
+    std::vector<double> problem_log2_bound;
+};
+
+struct CsrView {
+    int n;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const uint32_t *val;
+};
+
+// Validate a CSR matrix (sizes, ordering). Empty string if fine, else the reason.
+std::string validate_csr(const CsrView &a);
+
+// Expand problems into jobs and append them to *out (out->n_problems grows by the count).
+// Returns 0 on success, or -2 (range) / -1 (invalid) with *err set.
+int expand_problems(const std::vector<CsrView> &probs, const ExpandParams &prm, JobTable *out,
+                    std::string *err);
+
+// Turn dense matrices directly into jobs (no expansion), one problem each.
+int jobs_from_dense(int count, const int32_t *m, const int64_t *off, const uint32_t *a,
+                    const ExpandParams &prm, JobTable *out, std::string *err);
+
+// Default lane chunk (log2 Gray indices per lane) for a job of order m.
+int default_chunk_log2(int m);
+
+}  // namespace hp

@@ -1,0 +1,63 @@
+// Internal layout shared by the host code and the HIP kernels of libhperm.
+//
+// A job is one sub-matrix B of order m (1..HP_MAX_M) produced by expansion (2) of the
+// paper. R-NW evaluates it with Ryser's formula in Nijenhuis-Wilf form (Introduction):
+// one column of B (the densest, index m-1 after reordering) is fixed, the other m-1
+// "Gray columns" are enumerated by a binary-reflected Gray code. With doubled factors
+//     f_i(S) = base_i + 2 * sum_{j in S} b_ij,   base_i = 2 b_{i,m-1} - R_i,
+// (R_i the row sum of B) the kernels compute the ring value
+//     V = sum_{k=0}^{2^(m-1)-1} (-1)^k prod_i f_i(gray(k)) = (-1)^(m-1) 2^(m-1) per(B).
+#pragma once
+#include <stdint.h>
+
+#define HP_MAX_M 40          // largest job order the kernels accept
+#define HP_MAX_N 128         // largest input order
+#define HP_MAX_ENTRY (1u << 23)   // expanded entries stay below this (2*b fits 24 bits)
+#define HP_MAX_ROWSUM (1u << 24)  // row sums stay below this, so |f_i| < 2^24
+
+// Arithmetic rings of the kernels (values of JobDesc::arith).
+enum : uint8_t { HP_W64 = 0, HP_W128 = 1, HP_RES = 2, HP_NRING = 3 };
+
+// Residue primes p_k = 2^61 - c_k (all three verified prime by the tests).
+#define HP_P_BITS 61
+#define HP_C0 1ull
+#define HP_C1 31ull
+#define HP_C2 45ull
+
+// One job, 16 bytes, in the device job table.
+//   data_off : offset (in 32-bit words) of the job's data block in the data array
+//   m        : order; the job has m-1 Gray columns
+//   arith    : HP_W64 / HP_W128 / HP_RES
+//   chunk_log2 : Gray indices per lane in one work item = 2^chunk_log2
+//   nnz      : number of entries in the Gray columns
+//   problem  : input problem the job belongs to
+// Data block (32-bit words, starting at data_off):
+//   [0, m)            base_i as int32
+//   [m, 2m)           col_start[j] for j = 0..m-1: entry offset (relative to the entry
+//                     block) of Gray column j; col_start[m-1] = nnz (end)
+//   [2m, 2m+nnz)      entries of Gray column 0, then 1, ...: (2*b_ij << 8) | i
+//   [2m+nnz, 3m+nnz)  original column index of Gray column g (g < m-1) and of the fixed
+//                     column (slot m-1); used only for the estimator's random draws
+struct JobDesc {
+    uint32_t data_off;
+    uint8_t m;
+    uint8_t arith;
+    uint8_t chunk_log2;
+    uint8_t flags;
+    uint32_t nnz;
+    uint32_t problem;
+};
+static_assert(sizeof(JobDesc) == 16, "JobDesc layout");
+
+static inline uint32_t hp_job_words(int m, int nnz) { return 3u * (uint32_t)m + (uint32_t)nnz; }
+
+// Per-job accumulator of the kernels: sums of 32-bit limbs of the work items' ring values
+// (integer addition is associative, so the atomic order does not change the result):
+//   W64  : l[0] = V mod 2^64 (wrap-around sum of the items' values)
+//   W128 : V = sum_k l[k] 2^(32k) mod 2^128, k = 0..3 (limb k of each item, summed)
+//   RES  : V mod p_k = (l[2k] + 2^32 l[2k+1]) mod p_k (low and high halves of residues)
+struct JobAcc {
+    unsigned long long l[6];
+    unsigned long long pad[2];
+};
+static_assert(sizeof(JobAcc) == 64, "JobAcc layout");

@@ -1,0 +1,601 @@
+// HIP kernels of libhperm for gfx950 (MI355X): R-NW Gray-code evaluation of jobs (a
+// persistent queue kernel and a one-launch-per-job kernel sharing one inner loop), the
+// KKLLL estimator in FP32, and a fill kernel.
+//
+// The file is compiled once per HP_PART so that the object files build in parallel:
+// HP_PART = 0 holds the estimator and the fill kernel, HP_PART = 1, 2, 3 the R-NW kernels
+// of the W64, W128 and residue rings.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hperm_internal.h"
+#include "kernels.h"
+
+#ifndef HP_PART
+#error "compile with -DHP_PART=0..3"
+#endif
+
+namespace {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;   // 4 waves; every wave works on its own item
+
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int mask) {
+    uint32_t lo = __shfl_xor((int)(uint32_t)x, mask, WAVE);
+    uint32_t hi = __shfl_xor((int)(uint32_t)(x >> 32), mask, WAVE);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t x) {
+#pragma unroll
+    for (int mask = 32; mask >= 1; mask >>= 1) x += shfl_xor64(x, mask);
+    return x;
+}
+
+__device__ __forceinline__ JobDesc load_job(const JobDesc *jobs, uint32_t j) {
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(jobs + j);
+    const uint32_t a = uni(p[0]), b = uni(p[1]), c = uni(p[2]), d = uni(p[3]);
+    JobDesc jd;
+    jd.data_off = a;
+    jd.m = (uint8_t)(b & 0xff);
+    jd.arith = (uint8_t)((b >> 8) & 0xff);
+    jd.chunk_log2 = (uint8_t)((b >> 16) & 0xff);
+    jd.flags = (uint8_t)(b >> 24);
+    jd.nnz = c;
+    jd.problem = d;
+    return jd;
+}
+
+#if HP_PART >= 1
+// ------------------------------------------------------------------------ rings
+// A ring multiplies a non-negative product by |f_i| (unsigned 32-bit) and adds or
+// subtracts the product into a lane accumulator. The sign of a term is tracked apart:
+// sign(prod f_i) is the parity of the negative factors, and the Gray sign is (-1)^k.
+
+struct RingW64 {
+    struct P { uint64_t v; };
+    __device__ static P one() { return {1}; }
+    __device__ static void mul(P &p, uint32_t u) { p.v *= (uint64_t)u; }
+    __device__ static void acc(P &a, const P &p, uint32_t neg) {
+        const uint64_t m = 0ull - (uint64_t)neg;           // all ones when negative
+        a.v += (p.v ^ m) - m;
+    }
+    __device__ static P zero() { return {0}; }
+    __device__ static void flush(const P &a, JobAcc *dst, int lane) {
+        const uint64_t s = wave_sum64(a.v);
+        if (lane == 0) atomicAdd(&dst->l[0], (unsigned long long)s);
+    }
+};
+
+struct RingW128 {
+    struct P { uint32_t x0, x1, x2, x3; };
+    __device__ static P one() { return {1, 0, 0, 0}; }
+    __device__ static void mul(P &p, uint32_t u) {
+        const uint64_t t0 = (uint64_t)p.x0 * u;
+        const uint64_t t1 = (uint64_t)p.x1 * u + (t0 >> 32);
+        const uint64_t t2 = (uint64_t)p.x2 * u + (t1 >> 32);
+        const uint32_t t3 = p.x3 * u + (uint32_t)(t2 >> 32);
+        p = {(uint32_t)t0, (uint32_t)t1, (uint32_t)t2, t3};
+    }
+    __device__ static void acc(P &a, const P &p, uint32_t neg) {
+        // a += neg ? -p : p  (mod 2^128):  (p xor m) - m with m = 0 or all ones
+        const uint32_t m = 0u - neg;
+        unsigned __int128 q = ((unsigned __int128)(p.x3 ^ m) << 96) |
+                              ((unsigned __int128)(p.x2 ^ m) << 64) |
+                              ((unsigned __int128)(p.x1 ^ m) << 32) | (p.x0 ^ m);
+        q += neg;
+        unsigned __int128 s = ((unsigned __int128)a.x3 << 96) | ((unsigned __int128)a.x2 << 64) |
+                              ((unsigned __int128)a.x1 << 32) | a.x0;
+        s += q;
+        a = {(uint32_t)s, (uint32_t)(s >> 32), (uint32_t)(s >> 64), (uint32_t)(s >> 96)};
+    }
+    __device__ static P zero() { return {0, 0, 0, 0}; }
+    __device__ static void flush(const P &a, JobAcc *dst, int lane) {
+        const uint64_t s0 = wave_sum64(a.x0), s1 = wave_sum64(a.x1);
+        const uint64_t s2 = wave_sum64(a.x2), s3 = wave_sum64(a.x3);
+        if (lane == 0) {
+            atomicAdd(&dst->l[0], (unsigned long long)s0);
+            atomicAdd(&dst->l[1], (unsigned long long)s1);
+            atomicAdd(&dst->l[2], (unsigned long long)s2);
+            atomicAdd(&dst->l[3], (unsigned long long)s3);
+        }
+    }
+};
+
+// Residues modulo p_k = 2^61 - c_k. A product r * u with r < p and u < 2^24 is below 2^85;
+// 2^61 = c_k (mod p_k) folds it to lo + c_k * hi < 2 p_k, then one conditional subtraction.
+template <uint64_t C>
+__device__ __forceinline__ uint64_t mulmod61(uint64_t r, uint32_t u) {
+    constexpr uint64_t P = (1ull << 61) - C;
+    const unsigned __int128 x = (unsigned __int128)r * u;
+    const uint64_t lo = (uint64_t)x & ((1ull << 61) - 1);
+    const uint64_t hi = (uint64_t)(x >> 61);
+    uint64_t s = lo + C * hi;
+    return s >= P ? s - P : s;
+}
+template <uint64_t C>
+__device__ __forceinline__ uint64_t addmod61(uint64_t a, uint64_t b, uint32_t neg) {
+    constexpr uint64_t P = (1ull << 61) - C;
+    if (neg) return a >= b ? a - b : a + P - b;
+    const uint64_t s = a + b;
+    return s >= P ? s - P : s;
+}
+
+struct RingRes {
+    struct P { uint64_t r0, r1, r2; };
+    __device__ static P one() { return {1, 1, 1}; }
+    __device__ static void mul(P &p, uint32_t u) {
+        p.r0 = mulmod61<HP_C0>(p.r0, u);
+        p.r1 = mulmod61<HP_C1>(p.r1, u);
+        p.r2 = mulmod61<HP_C2>(p.r2, u);
+    }
+    __device__ static void acc(P &a, const P &p, uint32_t neg) {
+        a.r0 = addmod61<HP_C0>(a.r0, p.r0, neg);
+        a.r1 = addmod61<HP_C1>(a.r1, p.r1, neg);
+        a.r2 = addmod61<HP_C2>(a.r2, p.r2, neg);
+    }
+    __device__ static P zero() { return {0, 0, 0}; }
+    __device__ static void flush(const P &a, JobAcc *dst, int lane) {
+        const uint64_t v[3] = {a.r0, a.r1, a.r2};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const uint64_t lo = wave_sum64(v[k] & 0xffffffffull);
+            const uint64_t hi = wave_sum64(v[k] >> 32);
+            if (lane == 0) {
+                atomicAdd(&dst->l[2 * k], (unsigned long long)lo);
+                atomicAdd(&dst->l[2 * k + 1], (unsigned long long)hi);
+            }
+        }
+    }
+};
+
+// ------------------------------------------------------------------------ row values
+// The m row values f_i of one lane live in registers. Rows are indexed by wave-uniform
+// values, which the compiler turns into M0-relative register moves; it does so only for
+// a plain local array of at most 32 elements, so rows 32..39 sit in a second array.
+#define ROWS_DECL(MAXM)                                            \
+    constexpr int NA_ = (MAXM) < 32 ? (MAXM) : 32;                 \
+    constexpr int NB_ = (MAXM) > 32 ? (MAXM) - 32 : 1;             \
+    constexpr bool SPLIT_ = (MAXM) > 32;                           \
+    int fa_[NA_];                                                  \
+    int fb_[NB_];                                                  \
+    (void)fb_
+#define ROW_GET(i) ((!SPLIT_ || (i) < NA_) ? fa_[(i)] : fb_[(i) - NA_])
+#define ROW_SET(i, v)                  \
+    do {                               \
+        if (!SPLIT_ || (i) < NA_) fa_[(i)] = (v); \
+        else fb_[(i) - NA_] = (v);     \
+    } while (0)
+#define ROW_ADD(row, d)                                      \
+    do {                                                     \
+        if (!SPLIT_ || (row) < NA_) fa_[(row)] += (d);       \
+        else fb_[(row) - NA_] += (d);                        \
+    } while (0)
+
+// ------------------------------------------------------------------------ R-NW work item
+// One work item is 64 consecutive lane chunks of one job: lane l walks the Gray indices
+// k in [k0, k0 + L) with L = 2^c and k0 = (item * 64 + l) * L. Because k0 is a multiple of
+// L, the flipped Gray column at step k0 + t is ctz(t), the same in every lane, and only its
+// direction (bit ctz(t)+1 of k) can differ between lanes. The row values f_i live in
+// registers; the rows of a flipped column come from scalar loads of the job's data.
+template <class R, int MAXM>
+__device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__restrict__ data,
+                                         uint64_t item, int lane, JobAcc *dst) {
+    const int m = jd.m;
+    const int c = jd.chunk_log2;
+    const uint64_t nterms = 1ull << (m - 1);
+    const uint64_t L = 1ull << c;
+    const uint64_t k0 = (item * WAVE + (uint64_t)lane) * L;
+    const uint32_t *w = data + jd.data_off;
+    const uint32_t *cs = w + m;
+    const uint32_t *ent = w + 2 * m;
+
+    typename R::P acc = R::zero();
+    if (k0 < nterms) {
+        ROWS_DECL(MAXM);
+#pragma unroll
+        for (int i = 0; i < MAXM; ++i)
+            if (i < m) ROW_SET(i, (int)uni(w[i]));
+        // f_i(gray(k0)) = base_i + 2 * sum over set Gray bits
+        const uint64_t g0 = k0 ^ (k0 >> 1);
+        for (int j = 0; j < m - 1; ++j) {
+            const int bit = (int)((g0 >> j) & 1);
+            const uint32_t b = uni(cs[j]);
+            const uint32_t e = uni(cs[j + 1]);
+            for (uint32_t t = b; t < e; ++t) {
+                const uint32_t pk = uni(ent[t]);
+                const int row = (int)(pk & 0xff);
+                const int d = (int)(pk >> 8);
+                ROW_ADD(row, bit ? d : 0);
+            }
+        }
+        for (uint64_t t = 0;; ++t) {
+            // term k = k0 + t: (-1)^k prod_i f_i
+            typename R::P p = R::one();
+            uint32_t neg = (uint32_t)((k0 + t) & 1);
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) {
+                if (i < m) {
+                    const int x = ROW_GET(i);
+                    neg ^= (uint32_t)x >> 31;
+                    R::mul(p, (uint32_t)(x < 0 ? -x : x));
+                }
+            }
+            R::acc(acc, p, neg);
+            if (t + 1 >= L) break;
+            // step to k + 1: flip Gray column j = ctz(t + 1)
+            const int j = __builtin_ctzll(t + 1);
+            const uint64_t kn = k0 + t + 1;
+            const int sub = (int)((kn >> (j + 1)) & 1);   // new bit = 1 - sub
+            const uint32_t b = uni(cs[j]);
+            const uint32_t e = uni(cs[j + 1]);
+            for (uint32_t q = b; q < e; ++q) {
+                const uint32_t pk = uni(ent[q]);
+                const int row = (int)(pk & 0xff);
+                const int d = (int)(pk >> 8);
+                ROW_ADD(row, sub ? -d : d);
+            }
+        }
+    }
+    R::flush(acc, dst, lane);
+}
+
+
+// Persistent kernel: every wave repeatedly takes the next work item of the queue. The
+// queue is the list of jobs in scheduling order; item_end[s] is the number of items of
+// the first s+1 queued jobs (jobs own contiguous item ranges). Every queued job has
+// order at most MAXM (the host queues jobs by order bucket).
+template <class R, int MAXM>
+__global__ __launch_bounds__(BLOCK) void rnw_persistent(const JobDesc *__restrict__ jobs,
+                                                        const uint32_t *__restrict__ data,
+                                                        const uint32_t *__restrict__ queue,
+                                                        const uint64_t *__restrict__ item_end,
+                                                        uint32_t nqueue, uint64_t total_items,
+                                                        unsigned long long *head,
+                                                        JobAcc *__restrict__ accs) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    for (;;) {
+        // Every lane takes part in the claim (lane 0 adds 1, the others 0) so that no
+        // lane-dependent branch surrounds it: the whole wave then reads lane 0's claim.
+        // With the claim inside `if (lane == 0)`, the loop can be compiled as divergent and
+        // lanes 1..63 never see a new claim.
+        const unsigned long long got = atomicAdd(head, lane == 0 ? 1ull : 0ull);
+        const uint64_t g = uni64(got);
+        if (g >= total_items) break;
+        // smallest s with item_end[s] > g
+        uint32_t lo = 0, hi = nqueue - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (uni64(item_end[mid]) > g) hi = mid;
+            else lo = mid + 1;
+        }
+        const uint64_t first = lo ? uni64(item_end[lo - 1]) : 0;
+        const uint32_t job = uni(queue[lo]);
+        const JobDesc jd = load_job(jobs, job);
+        rnw_item<R, MAXM>(jd, data, g - first, lane, accs + job);
+    }
+}
+
+// One launch per job (the plain comparator): wave w of the grid evaluates item w.
+template <class R, int MAXM>
+__global__ __launch_bounds__(BLOCK) void rnw_single(const JobDesc *__restrict__ jobs,
+                                                    const uint32_t *__restrict__ data,
+                                                    uint32_t job, uint64_t nitems,
+                                                    JobAcc *__restrict__ accs) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const uint64_t w = (uint64_t)blockIdx.x * (BLOCK / WAVE) + (threadIdx.x >> 6);
+    if (w >= nitems) return;
+    const JobDesc jd = load_job(jobs, job);
+    rnw_item<R, MAXM>(jd, data, w, lane, accs + job);
+}
+
+#endif  // HP_PART >= 1
+
+#if HP_PART == 0
+// ------------------------------------------------------------------------ KKLLL estimate
+// Counter-based SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): output k of the stream
+// seeded with s is mix(s + (k+1) * golden), golden = 0x9E3779B97F4A7C15.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Cube-root exponent of entry (i, j) of trial t of job w: counter (w<<36)|(t<<12)|(i<<6)|j,
+// exponent floor(3 * (x >> 32) / 2^32).
+__device__ __forceinline__ uint32_t kkl_u(uint64_t seed, uint32_t w, uint32_t t, uint32_t i,
+                                          uint32_t j) {
+    const uint64_t k = ((uint64_t)w << 36) | ((uint64_t)t << 12) | ((uint64_t)i << 6) | j;
+    const uint64_t x = splitmix64(seed, k);
+    return (uint32_t)(((x >> 32) * 3ull) >> 32);
+}
+
+// One block per job, 4 waves; wave v runs trials v, v+4, ... Lane i holds row i of
+// B (complex FP32). Gaussian elimination with partial pivoting: the pivot row is the
+// unused lane with the largest |B_ik|; log|det B| = sum of log|pivot|. The key is the log
+// of the mean of |det B|^2 over the trials, combined as a log-sum-exp. Every loop over
+// columns is unrolled to MAXM so the row lives in registers.
+template <int MAXM>
+__global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict__ jobs,
+                                                      const uint32_t *__restrict__ data,
+                                                      const uint32_t *__restrict__ list,
+                                                      uint32_t nlist, int trials, uint64_t seed,
+                                                      float *__restrict__ keys) {
+    __shared__ float red[2 * (BLOCK / WAVE)];
+    if (blockIdx.x >= nlist) return;
+    const uint32_t jobid = uni(list[blockIdx.x]);
+    const JobDesc jd = load_job(jobs, jobid);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wave = threadIdx.x >> 6;
+    const int m = jd.m;
+    const uint32_t *w = data + jd.data_off;
+    const uint32_t *cs = w + m;
+    const uint32_t *ent = w + 2 * m;
+    const uint32_t *cmap = w + 2 * m + jd.nnz;
+    // b_{lane, fixed} = base + sum over Gray columns of b_{lane, j}
+    int gsum = 0;
+    for (uint32_t e = 0; e < jd.nnz; ++e) {
+        const uint32_t pk = uni(ent[e]);
+        if ((int)(pk & 0xff) == lane) gsum += (int)(pk >> 9);
+    }
+    int bfix = 0;
+    if (lane < m) bfix = (int)w[lane] + gsum;
+    constexpr float kS = 0.86602540378443864676f;   // sin(2 pi / 3)
+
+    float run_max = -INFINITY, run_sum = 0.0f;
+    for (int t = wave; t < trials; t += BLOCK / WAVE) {
+        float re[MAXM], im[MAXM];
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) {
+            re[j] = 0.0f;
+            im[j] = 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < MAXM; ++j) {
+            if (j < m - 1) {   // Gray column j
+                const uint32_t b = uni(cs[j]);
+                const uint32_t e = uni(cs[j + 1]);
+                const uint32_t oc = uni(cmap[j]);
+                for (uint32_t q = b; q < e; ++q) {
+                    const uint32_t pk = uni(ent[q]);
+                    if ((int)(pk & 0xff) == lane) {
+                        const uint32_t u = kkl_u(seed, jobid, (uint32_t)t, (uint32_t)lane, oc);
+                        re[j] = u == 0 ? 1.0f : -0.5f;
+                        im[j] = u == 0 ? 0.0f : (u == 1 ? kS : -kS);
+                    }
+                }
+            } else if (j == m - 1) {   // the fixed column
+                const uint32_t oc = uni(cmap[m - 1]);
+                if (lane < m && bfix != 0) {
+                    const uint32_t u = kkl_u(seed, jobid, (uint32_t)t, (uint32_t)lane, oc);
+                    re[j] = u == 0 ? 1.0f : -0.5f;
+                    im[j] = u == 0 ? 0.0f : (u == 1 ? kS : -kS);
+                }
+            }
+        }
+        bool used = lane >= m;
+        float logabs = 0.0f;
+        int singular = 0;
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) {
+            if (k < m && !singular) {
+                float mag = used ? -1.0f : re[k] * re[k] + im[k] * im[k];
+                int idx = lane;
+#pragma unroll
+                for (int s = 32; s >= 1; s >>= 1) {
+                    const float om = __shfl_xor(mag, s, WAVE);
+                    const int oi = __shfl_xor(idx, s, WAVE);
+                    if (om > mag || (om == mag && oi < idx)) {
+                        mag = om;
+                        idx = oi;
+                    }
+                }
+                const int piv = (int)uni((uint32_t)idx);
+                const float pmag = __builtin_bit_cast(float, uni(__builtin_bit_cast(uint32_t, mag)));
+                if (!(pmag > 0.0f)) {
+                    singular = 1;
+                } else {
+                    logabs += 0.5f * logf(pmag);
+                    const float pr = __builtin_bit_cast(
+                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, re[k]), piv));
+                    const float pi = __builtin_bit_cast(
+                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, im[k]), piv));
+                    if (lane == piv) used = true;
+                    // factor = B_ik / pivot = B_ik * conj(pivot) / |pivot|^2
+                    const float ir = pr / pmag, ii = -pi / pmag;
+                    const float fr = re[k] * ir - im[k] * ii;
+                    const float fi = re[k] * ii + im[k] * ir;
+#pragma unroll
+                    for (int c = k + 1; c < MAXM; ++c) {
+                        if (c < m) {
+                            const float cr = __builtin_bit_cast(
+                                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, re[c]), piv));
+                            const float ci = __builtin_bit_cast(
+                                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, im[c]), piv));
+                            if (!used) {
+                                re[c] -= fr * cr - fi * ci;
+                                im[c] -= fr * ci + fi * cr;
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (!singular) {
+            const float l = 2.0f * logabs;   // log |det B|^2
+            if (l > run_max) {
+                run_sum = run_sum * expf(run_max - l) + 1.0f;
+                run_max = l;
+            } else {
+                run_sum += expf(l - run_max);
+            }
+        }
+    }
+    // combine the waves: (max, sum) pairs through LDS
+    if (lane == 0) {
+        red[2 * wave] = run_max;
+        red[2 * wave + 1] = run_sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float mx = -INFINITY;
+        for (int v = 0; v < BLOCK / WAVE; ++v) mx = fmaxf(mx, red[2 * v]);
+        float sum = 0.0f;
+        if (mx > -INFINITY)
+            for (int v = 0; v < BLOCK / WAVE; ++v)
+                if (red[2 * v] > -INFINITY) sum += red[2 * v + 1] * expf(red[2 * v] - mx);
+        keys[jobid] = (mx > -INFINITY && sum > 0.0f) ? mx + logf(sum) - logf((float)trials)
+                                                     : -INFINITY;
+    }
+}
+
+__global__ void fill_u64(unsigned long long *p, uint64_t n, unsigned long long v) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+#endif  // HP_PART == 0
+
+}  // namespace
+
+// ------------------------------------------------------------------------ launchers
+namespace hp {
+
+#if HP_PART == 0
+
+int bucket_of(int m) { return m <= 16 ? 0 : (m <= 24 ? 1 : (m <= 32 ? 2 : 3)); }
+
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v,
+                           hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(fill_u64, dim3((uint32_t)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data,
+                           const uint32_t *list, uint32_t nlist, int trials, uint64_t seed,
+                           float *keys, hipStream_t s) {
+    if (nlist == 0) return hipSuccess;
+    switch (bucket) {
+        case 0: hipLaunchKernelGGL(kkl_estimate<16>, dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
+        case 1: hipLaunchKernelGGL(kkl_estimate<24>, dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
+        case 2: hipLaunchKernelGGL(kkl_estimate<32>, dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
+        default: hipLaunchKernelGGL(kkl_estimate<HP_MAX_M>, dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys);
+    }
+    return hipGetLastError();
+}
+
+#endif  // HP_PART == 0
+
+#if HP_PART >= 1
+#if HP_PART == 1
+#define RING_T RingW64
+#define RING_SUFFIX w64
+#elif HP_PART == 2
+#define RING_T RingW128
+#define RING_SUFFIX w128
+#else
+#define RING_T RingRes
+#define RING_SUFFIX res
+#endif
+#define CAT2(a, b) a##_##b
+#define CAT(a, b) CAT2(a, b)
+
+static const void *persistent_fn(int bucket) {
+    switch (bucket) {
+        case 0: return (const void *)rnw_persistent<RING_T, 16>;
+        case 1: return (const void *)rnw_persistent<RING_T, 24>;
+        case 2: return (const void *)rnw_persistent<RING_T, 32>;
+        default: return (const void *)rnw_persistent<RING_T, HP_MAX_M>;
+    }
+}
+static const void *single_fn(int bucket) {
+    switch (bucket) {
+        case 0: return (const void *)rnw_single<RING_T, 16>;
+        case 1: return (const void *)rnw_single<RING_T, 24>;
+        case 2: return (const void *)rnw_single<RING_T, 32>;
+        default: return (const void *)rnw_single<RING_T, HP_MAX_M>;
+    }
+}
+
+hipError_t CAT(persistent_grid, RING_SUFFIX)(int bucket, int *grid) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_fn(bucket), BLOCK, 0);
+    if (e != hipSuccess) return e;
+    *grid = cus * (per_cu > 0 ? per_cu : 1);
+    return hipSuccess;
+}
+
+hipError_t CAT(launch_rnw_persistent, RING_SUFFIX)(int bucket, const JobDesc *jobs,
+                                                    const uint32_t *data, const uint32_t *queue,
+                                                    const uint64_t *item_end, uint32_t nqueue,
+                                                    uint64_t total_items, unsigned long long *head,
+                                                    JobAcc *accs, int grid, hipStream_t s) {
+    void *args[] = {(void *)&jobs, (void *)&data, (void *)&queue, (void *)&item_end,
+                    (void *)&nqueue, (void *)&total_items, (void *)&head, (void *)&accs};
+    hipError_t e = hipLaunchKernel(persistent_fn(bucket), dim3(grid), dim3(BLOCK), args, 0, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t CAT(launch_rnw_single, RING_SUFFIX)(int bucket, const JobDesc *jobs,
+                                                const uint32_t *data, uint32_t job, uint64_t nitems,
+                                                JobAcc *accs, hipStream_t s) {
+    const uint64_t blocks = (nitems + (BLOCK / WAVE) - 1) / (BLOCK / WAVE);
+    void *args[] = {(void *)&jobs, (void *)&data, (void *)&job, (void *)&nitems, (void *)&accs};
+    hipError_t e = hipLaunchKernel(single_fn(bucket), dim3((uint32_t)blocks), dim3(BLOCK), args, 0, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+#endif  // HP_PART >= 1
+
+#if HP_PART == 0
+hipError_t persistent_grid(int ring, int bucket, int *grid) {
+    switch (ring) {
+        case HP_W64: return persistent_grid_w64(bucket, grid);
+        case HP_W128: return persistent_grid_w128(bucket, grid);
+        default: return persistent_grid_res(bucket, grid);
+    }
+}
+
+hipError_t launch_rnw_persistent(int ring, int bucket, const JobDesc *jobs, const uint32_t *data,
+                                 const uint32_t *queue, const uint64_t *item_end, uint32_t nqueue,
+                                 uint64_t total_items, unsigned long long *head, JobAcc *accs,
+                                 int grid_override, hipStream_t s) {
+    if (nqueue == 0 || total_items == 0) return hipSuccess;
+    int grid = 0;
+    hipError_t e = persistent_grid(ring, bucket, &grid);
+    if (e != hipSuccess) return e;
+    if (grid_override > 0) grid = grid_override;
+    const uint64_t max_blocks = (total_items + (BLOCK / WAVE) - 1) / (BLOCK / WAVE);
+    if ((uint64_t)grid > max_blocks) grid = (int)max_blocks;
+    switch (ring) {
+        case HP_W64: return launch_rnw_persistent_w64(bucket, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
+        case HP_W128: return launch_rnw_persistent_w128(bucket, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
+        default: return launch_rnw_persistent_res(bucket, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
+    }
+}
+
+hipError_t launch_rnw_single(int ring, int bucket, const JobDesc *jobs, const uint32_t *data,
+                             uint32_t job, uint64_t nitems, JobAcc *accs, hipStream_t s) {
+    if (nitems == 0) return hipSuccess;
+    switch (ring) {
+        case HP_W64: return launch_rnw_single_w64(bucket, jobs, data, job, nitems, accs, s);
+        case HP_W128: return launch_rnw_single_w128(bucket, jobs, data, job, nitems, accs, s);
+        default: return launch_rnw_single_res(bucket, jobs, data, job, nitems, accs, s);
+    }
+}
+#endif  // HP_PART == 0
+
+}  // namespace hp

@@ -1,0 +1,151 @@
+"""The C-ABI library on the CPU: it loads, exports every declared call, and its host stages
+(validation, expansion, arithmetic-mode choice) behave as documented. No GPU work here."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import expand_leaves
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hperm.h")
+
+
+@pytest.fixture(scope="module")
+def hp():
+    import paper_1112_6072_amd as hp
+    return hp
+
+
+def declared_calls():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hperm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_call(hp):
+    lib = ctypes.CDLL(hp.LIB_PATH)
+    calls = declared_calls()
+    assert len(calls) >= 25
+    for name in calls:
+        assert hasattr(lib, name), name
+    assert set(calls) == set(hp.EXPORTED)
+
+
+def test_version_and_defaults(hp):
+    assert hp.version() == (1, 0)
+    d = hp.default_opts()
+    assert d["m_cut"] == 20 and d["s_leaf"] == 5 and d["persistent"] == 1 and d["trials"] == 32
+
+
+def test_status_strings(hp):
+    for s in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8):
+        assert hp._lib.hperm_status_string(s).decode() not in ("", "unknown status")
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("m_cut", [8, 12, 16])
+def test_expansion_matches_oracle_job_sequence(hp, seed, m_cut):
+    """The host expansion and the oracle's expansion follow the same rule: same jobs, same order."""
+    A = W.random_cubic_matrix(24, seed) if seed < 3 else W.permutation_union_matrix(20, 3, seed, 1, 5)
+    ctx = hp.Context({"m_cut": m_cut}, host_only=True)
+    d = ctx.expand([A]).describe()
+    leaves = expand_leaves(A, m_cut)
+    assert list(d["m"]) == [len(x) for x in leaves]
+
+
+def test_expansion_s_leaf_and_cap(hp):
+    """Dense nodes (every line >= s_leaf nonzeros) stop early when their order is <= m_cap."""
+    A = W.random_sparse_int_matrix(18, 6, 3, 1, 3)
+    for s_leaf, m_cap in ((5, 18), (5, 16), (7, 16)):
+        ctx = hp.Context({"m_cut": 8, "s_leaf": s_leaf, "m_cap": m_cap}, host_only=True)
+        d = ctx.expand([A]).describe()
+        leaves = expand_leaves(A, 8, s_leaf, m_cap)
+        assert list(d["m"]) == [len(x) for x in leaves]
+        assert d["m"].max() <= m_cap
+
+
+def test_expansion_is_thread_count_independent(hp):
+    mats = [A for _, A in W.config_n60(2)]
+    ref = None
+    for th in (1, 3, 8):
+        d = hp.Context({"m_cut": 26, "host_threads": th}, host_only=True).expand(mats).describe()
+        cur = (list(d["m"]), list(d["problem"]), list(d["arith"]))
+        assert ref is None or cur == ref
+        ref = cur
+
+
+def test_arith_mode_choice_from_bounds(hp):
+    ctx = hp.Context(host_only=True)
+    # J_12: per = 12! ~ 2^28.8, plus 12 bits of NW doubling -> 64-bit ring
+    # J_20: 20! ~ 2^61.1 + 20 -> 128-bit ring; J_34: 34! ~ 2^127.8 -> residues
+    d = ctx.jobs_from_dense([np.ones((12, 12)), np.ones((20, 20)), np.ones((34, 34))]).describe()
+    assert list(d["arith"]) == [hp.ARITH_W64, hp.ARITH_W128, hp.ARITH_RES]
+    # forcing a ring narrower than the bound is refused
+    with pytest.raises(hp.HpermError) as e:
+        hp.Context({"arith": "w64"}, host_only=True).jobs_from_dense([np.ones((20, 20))])
+    assert e.value.status == -2
+    d = hp.Context({"arith": "res"}, host_only=True).jobs_from_dense([np.ones((5, 5))]).describe()
+    assert list(d["arith"]) == [hp.ARITH_RES]
+
+
+def test_terms_and_orders(hp):
+    ctx = hp.Context({"m_cut": 14}, host_only=True)
+    d = ctx.expand([W.random_cubic_matrix(24, 0)]).describe()
+    assert all(int(t) == 1 << (int(m) - 1) for m, t in zip(d["m"], d["terms"]))
+
+
+@pytest.mark.parametrize("bad", ["unsorted", "dup", "range", "rowptr", "big_entry", "n"])
+def test_validation_errors(hp, bad):
+    ctx = hp.Context(host_only=True)
+    n = 4
+    rp = np.array([0, 2, 4, 6, 8], np.int32)
+    ci = np.array([0, 1, 1, 2, 2, 3, 0, 3], np.int32)
+    va = np.ones(8, np.uint32)
+    if bad == "unsorted":
+        ci[0], ci[1] = 1, 0
+    elif bad == "dup":
+        ci[1] = 0
+    elif bad == "range":
+        ci[7] = 9
+    elif bad == "rowptr":
+        rp[2] = 1
+    elif bad == "big_entry":
+        va[3] = 1 << 23
+    elif bad == "n":
+        n = 129
+        rp = np.zeros(130, np.int32)
+    h = ctypes.c_void_p()
+    nn = np.array([n], np.int32)
+    z = np.zeros(1, np.int64)
+    st = hp._lib.hperm_expand_batch_csr(ctx.handle, 1, hp._ptr(nn), hp._ptr(z), hp._ptr(z), hp._ptr(rp),
+                                        hp._ptr(ci), hp._ptr(va), ctypes.byref(h))
+    assert st == -1
+    assert hp._lib.hperm_last_error(ctx.handle).decode() != ""
+
+
+def test_host_only_context_refuses_gpu_calls(hp):
+    ctx = hp.Context(host_only=True)
+    J = ctx.jobs_from_dense([np.ones((3, 3))])
+    with pytest.raises(hp.HpermError) as e:
+        ctx.run(J)
+    assert e.value.status == -3
+
+
+def test_zero_and_empty_problems_need_no_jobs(hp):
+    ctx = hp.Context(host_only=True)
+    Z = np.ones((5, 5), int)
+    Z[2] = 0
+    J = ctx.expand([np.zeros((0, 0)), Z])
+    assert J.info() == (0, 2)
+
+
+def test_residue_primes_are_prime():
+    import sympy
+    for c in (1, 31, 45):
+        assert sympy.isprime(2 ** 61 - c)
+    assert math.prod(2 ** 61 - c for c in (1, 31, 45)) > 2 ** 182
