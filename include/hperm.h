@@ -203,6 +203,30 @@ hperm_status hperm_wait(hperm_ctx *ctx, uint64_t ticket, double timeout_s, hperm
 hperm_status hperm_cancel(hperm_ctx *ctx, uint64_t ticket);
 
 /* ---- diagnostics -------------------------------------------------------------------- */
+
+/* One R-NW kernel launch of the last hperm_run_jobs / hperm_permanent_* call. */
+typedef struct hperm_launch_stat {
+    int32_t ring;           /* 0: mod 2^64, 1: mod 2^128, 2: residues */
+    int32_t bucket;         /* kernel instantiation: job orders <= 16, 24, 32, 40 */
+    int32_t n_jobs;         /* jobs in the launch (1 in one-launch-per-job mode) */
+    int32_t persistent;
+    uint64_t items;         /* work items (64 lanes x 2^chunk Gray indices each) */
+    uint64_t terms;         /* subset-terms: sum of 2^(m-1) over the jobs */
+    uint64_t row_updates;   /* Gray-step row-value updates: sum over jobs and Gray columns
+                               j of nnz(column j) * 2^(m-2-j) */
+    double alg_slots;       /* algorithmic 32-bit VALU issue slots of the launch:
+                               sum over jobs of terms * ((m-1) * mul + add) + row_updates,
+                               where one ring multiply by a 32-bit factor costs mul = 5
+                               (mod 2^64), 9 (mod 2^128) or 3 * 11 (residues) slots and one
+                               ring addition add = 2, 4 or 3 * 3 slots; v_mad_u64_u32 and
+                               v_mul_lo_u32 count 2 slots (half rate), other ops 1 */
+    double ms;              /* duration from HIP events around the launch on its stream */
+} hperm_launch_stat;
+
+/* Copy up to max launch records of the last call into out; *n receives the count. */
+hperm_status hperm_last_launches(const hperm_ctx *ctx, hperm_launch_stat *out, int32_t max,
+                                 int32_t *n);
+
 const char *hperm_status_string(hperm_status s);
 /* Message of the context's last error (empty string if none); valid until the next call. */
 const char *hperm_last_error(const hperm_ctx *ctx);

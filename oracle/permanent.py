@@ -307,7 +307,8 @@ def per_auto(A) -> int:
 
 
 # --------------------------------------------------------------------------- jobs of PH
-def expand_leaves(A, m_cut: int, s_leaf: int = 5, m_cap: int = 40) -> list[list[list[int]]]:
+def expand_leaves(A, m_cut: int, s_leaf: int = 5, m_cap: int = 40,
+                  limit: int | None = None) -> list[list[list[int]]]:
     """The sub-matrix jobs of a pre-expansion (Algorithm PH, Step 2) with a size-based stop.
 
     Depth-first over the expansion tree, children in pair order: a node whose smallest
@@ -315,10 +316,13 @@ def expand_leaves(A, m_cut: int, s_leaf: int = 5, m_cap: int = 40) -> list[list[
     m_cut (or at most 2), or when s >= s_leaf and its order is at most m_cap (Algorithm
     H_per hands such a node to R-NW); otherwise it is split by expansion (2) along that
     line (see ``choose_line`` and ``e2_children``). Returns the jobs in depth-first order;
-    by Step 4 of Algorithm PH their permanents sum to per(A)."""
+    by Step 4 of Algorithm PH their permanents sum to per(A). With ``limit`` only the first
+    ``limit`` jobs are produced."""
     out = []
 
     def rec(a):
+        if limit is not None and len(out) >= limit:
+            return
         n = len(a)
         if n == 0:
             out.append(a)

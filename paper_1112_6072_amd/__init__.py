@@ -57,6 +57,15 @@ class Result(ctypes.Structure):
                 "t_estimate_s": self.t_estimate_s, "t_rnw_s": self.t_rnw_s, "t_total_s": self.t_total_s}
 
 
+class LaunchStat(ctypes.Structure):
+    _fields_ = [("ring", ctypes.c_int32), ("bucket", ctypes.c_int32), ("n_jobs", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("items", ctypes.c_uint64), ("terms", ctypes.c_uint64),
+                ("row_updates", ctypes.c_uint64), ("alg_slots", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _P = ctypes.c_void_p
 _I32, _U64, _SZ = ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
 _SIGS = {
@@ -81,6 +90,7 @@ _SIGS = {
     "hperm_poll": [_P, _U64, ctypes.POINTER(Result)],
     "hperm_wait": [_P, _U64, ctypes.c_double, ctypes.POINTER(Result)],
     "hperm_cancel": [_P, _U64],
+    "hperm_last_launches": [_P, ctypes.POINTER(LaunchStat), _I32, ctypes.POINTER(_I32)],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -239,6 +249,13 @@ class Context:
         else:
             self._arena, ptr, size = None, None, 0
         self._check(_lib.hperm_ctx_set_arena(self.handle, _P(ptr) if ptr else None, size), "set_arena")
+
+    def last_launches(self) -> list[dict]:
+        """R-NW launches of the last run: ring, bucket, jobs, items, terms, alg_slots, ms."""
+        buf = (LaunchStat * 64)()
+        n = _I32()
+        self._check(_lib.hperm_last_launches(self.handle, buf, 64, ctypes.byref(n)), "last_launches")
+        return [buf[k].as_dict() for k in range(min(n.value, 64))]
 
     def arena_required(self) -> int:
         return int(_lib.hperm_ctx_arena_required(self.handle))

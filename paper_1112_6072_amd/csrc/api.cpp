@@ -266,9 +266,40 @@ static bool job_value(const JobDesc &d, const JobAcc &a, double log2_bound, U512
     return true;
 }
 
+// Algorithmic 32-bit VALU issue slots of one ring multiply by a 32-bit factor and of one
+// ring addition. On gfx950 v_mad_u64_u32 and v_mul_lo_u32 issue at half the rate of simple
+// 32-bit operations (2 slots), other 32-bit operations take 1 slot:
+//   mod 2^64 : 64x32 product = v_mad_u64_u32 + v_mul_lo_u32 + add           -> 2 + 2 + 1 = 5
+//              64-bit addition = add with carry out + add with carry in      -> 2
+//   mod 2^128: 3 v_mad_u64_u32 + v_mul_lo_u32 + add                         -> 9; addition 4
+//   residues : per prime a 61x24-bit product (2 multiplies), the fold by 2^61 = c (shift, mask,
+//              multiply-add) and one conditional subtraction               -> 11; addition 3;
+//              three primes
+static double ring_mul_slots(int ring) { return ring == HP_W64 ? 5.0 : ring == HP_W128 ? 9.0 : 33.0; }
+static double ring_add_slots(int ring) { return ring == HP_W64 ? 2.0 : ring == HP_W128 ? 4.0 : 9.0; }
+
+// Row-value updates of a whole job: Gray column j flips 2^(m-2-j) times.
+static uint64_t job_row_updates(const JobDesc &d, const uint32_t *data) {
+    const int m = d.m;
+    const uint32_t *cs = data + d.data_off + m;
+    uint64_t u = 0;
+    for (int j = 0; j + 1 < m; ++j) u += (uint64_t)(cs[j + 1] - cs[j]) << (m - 2 - j);
+    return u;
+}
+
 static void fill_result(const U512 &v, hperm_result *r) {
     for (int k = 0; k < 8; ++k) r->limb[k] = v.w[k];
     r->nlimb = v.nlimb();
+}
+
+static hperm_status ensure_launch_events(hperm_ctx *c, size_t pairs) {
+    while (c->launch_ev.size() < 2 * pairs) {
+        hipEvent_t e;
+        hperm_status s = hip_check(c, hipEventCreate(&e), "hipEventCreate");
+        if (s) return s;
+        c->launch_ev.push_back(e);
+    }
+    return HPERM_OK;
 }
 
 hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
@@ -356,15 +387,37 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
         const uint32_t *d_data = (const uint32_t *)c->buf[B_DATA].ptr;
         s = hip_check(c, hipEventRecord(c->ev0, c->stream), "event");
         if (s) return s;
+        c->launches.clear();
         if (persistent) {
+            s = ensure_launch_events(c, groups.size());
+            if (s) return s;
             for (size_t gi = 0; gi < groups.size(); ++gi) {
                 const Group &g = groups[gi];
+                hperm_launch_stat st{};
+                st.ring = g.ring;
+                st.bucket = g.bucket;
+                st.n_jobs = (int32_t)g.n;
+                st.persistent = 1;
+                st.items = g.items;
+                for (size_t q = g.off; q < g.off + g.n; ++q) {
+                    const JobDesc &d = dsc[queue[q]];
+                    const uint64_t t = 1ull << (d.m - 1);
+                    const uint64_t u = job_row_updates(d, j->tab.data.data());
+                    st.terms += t;
+                    st.row_updates += u;
+                    st.alg_slots += (double)t * ((d.m - 1) * ring_mul_slots(d.arith) + ring_add_slots(d.arith)) + (double)u;
+                }
+                c->launches.push_back(st);
+                s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
+                if (s) return s;
                 s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, d_desc, d_data,
                                                        (const uint32_t *)c->buf[B_QUEUE].ptr + g.off,
                                                        (const uint64_t *)c->buf[B_ITEMS].ptr + g.off,
                                                        (uint32_t)g.n, g.items, head + gi, accs, 0,
                                                        c->stream),
                               "rnw_persistent launch");
+                if (s) return s;
+                s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi + 1], c->stream), "event");
                 if (s) return s;
             }
         } else {
@@ -376,6 +429,20 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
                               "rnw_single launch");
                 if (s) return s;
             }
+            hperm_launch_stat st{};
+            st.ring = -1;
+            st.bucket = -1;
+            st.n_jobs = (int32_t)nd;
+            for (size_t k = 0; k < nd; ++k) {
+                const JobDesc &d = desc_plain[k];
+                const uint64_t t = 1ull << (d.m - 1);
+                const uint64_t u = job_row_updates(d, j->tab.data.data());
+                st.items += items_of(d.m, d.chunk_log2);
+                st.terms += t;
+                st.row_updates += u;
+                st.alg_slots += (double)t * ((d.m - 1) * ring_mul_slots(d.arith) + ring_add_slots(d.arith)) + (double)u;
+            }
+            c->launches.push_back(st);   // all single launches as one record (ms = whole span)
         }
         s = hip_check(c, hipEventRecord(c->ev1, c->stream), "event");
         if (s) return s;
@@ -388,6 +455,15 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
         *t_rnw = ms * 1e-3;
+        if (persistent) {
+            for (size_t gi = 0; gi < c->launches.size(); ++gi) {
+                float lm = 0.0f;
+                (void)hipEventElapsedTime(&lm, c->launch_ev[2 * gi], c->launch_ev[2 * gi + 1]);
+                c->launches[gi].ms = lm;
+            }
+        } else if (!c->launches.empty()) {
+            c->launches[0].ms = ms;
+        }
         for (size_t k = 0; k < nd; ++k) {
             const JobDesc &d = j->tab.desc[k];
             U512 v;
@@ -532,6 +608,7 @@ void hperm_ctx_destroy(hperm_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     for (auto &b : c->buf)
         if (b.ptr && b.owned) (void)hipFree(b.ptr);
+    for (hipEvent_t e : c->launch_ev) (void)hipEventDestroy(e);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -715,6 +792,14 @@ hperm_status hperm_run_jobs(hperm_ctx *c, hperm_jobs *j, int32_t order, int32_t 
 }
 
 void hperm_jobs_free(hperm_jobs *j) { delete j; }
+
+hperm_status hperm_last_launches(const hperm_ctx *c, hperm_launch_stat *out, int32_t max, int32_t *n) {
+    if (!c || !n || max < 0 || (max > 0 && !out)) return HPERM_E_INVALID;
+    const int32_t k = (int32_t)std::min<size_t>((size_t)max, c->launches.size());
+    for (int32_t i = 0; i < k; ++i) out[i] = c->launches[i];
+    *n = (int32_t)c->launches.size();
+    return HPERM_OK;
+}
 
 const char *hperm_status_string(hperm_status s) {
     switch (s) {

@@ -49,6 +49,8 @@ struct hperm_ctx {
     std::string last_error;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hp::Serving *serving = nullptr;   // owned; created by hperm_serve_start
+    std::vector<hperm_launch_stat> launches;   // R-NW launches of the last call
+    std::vector<hipEvent_t> launch_ev;         // event pairs for the launches (grown on demand)
     std::mutex call_mu;   // serialises GPU pipelines of this context (serving thread vs callers)
 };
 
