@@ -74,7 +74,7 @@ typedef struct hperm_opts {
     int32_t order;        /* hperm_order (default ESTIMATE) */
     int32_t trials;       /* KKLLL trials per job (1..4096; default 32) */
     uint64_t seed;        /* seed of the KKLLL draws and of ORDER_RANDOM (default 1) */
-    int32_t chunk_log2;   /* Gray indices per lane = 2^chunk_log2; 0 = autotuned table */
+    int32_t chunk_log2;   /* Gray indices per lane = 2^chunk_log2 (0..12); 0 = default table */
     int32_t persistent;   /* 1: one persistent launch over the queue (default);
                              0: one launch per job (the plain comparator) */
     int32_t host_threads; /* expansion threads (0 = hardware threads, at most 64) */
@@ -130,7 +130,7 @@ size_t hperm_ctx_arena_required(const hperm_ctx *ctx);
  * The problem statement of Algorithm H_per (Section 2.1) with non-negative integer entries.
  * n = 0 gives 1; a zero row or column gives 0 without GPU work.
  * Errors: HPERM_E_INVALID (n < 0 or n > 128, malformed CSR); HPERM_E_RANGE (an expanded
- * entry or a row sum exceeds 2^24, or the proven bound on per(A) exceeds 2^180);
+ * entry reaches 2^22 or a row sum 2^24, or the proven bound on per(A) exceeds 2^180);
  * HPERM_E_DEVICE; HPERM_E_NOMEM; HPERM_E_INTERNAL. */
 hperm_status hperm_permanent_csr(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
                                  const int32_t *col_idx, const uint32_t *val, hperm_result *out);
@@ -212,11 +212,13 @@ typedef struct hperm_launch_stat {
     int32_t persistent;
     uint64_t items;         /* work items (64 lanes x 2^chunk Gray indices each) */
     uint64_t terms;         /* subset-terms: sum of 2^(m-1) over the jobs */
-    uint64_t row_updates;   /* Gray-step row-value updates: sum over jobs and Gray columns
-                               j of nnz(column j) * 2^(m-2-j) */
-    double alg_slots;       /* algorithmic 32-bit VALU issue slots of the launch:
-                               sum over jobs of terms * ((m-1) * mul + add) + row_updates,
-                               where one ring multiply by a 32-bit factor costs mul = 5
+    uint64_t row_updates;   /* row-value updates of the Gray steps inside lane chunks */
+    double alg_slots;       /* algorithmic 32-bit VALU issue slots of the launch for the
+                               suffix-product Gray walk: per lane chunk of 2^c indices, m ring
+                               multiplies to start, then for each flip of Gray column j < c
+                               its nnz(j) row updates (1 slot each) and hi[j] ring multiplies
+                               (hi[j] = rows whose first Gray column is <= j); plus one ring
+                               addition per term. One ring multiply by a 32-bit factor costs mul = 5
                                (mod 2^64), 9 (mod 2^128) or 3 * 11 (residues) slots and one
                                ring addition add = 2, 4 or 3 * 3 slots; v_mad_u64_u32 and
                                v_mul_lo_u32 count 2 slots (half rate), other ops 1 */

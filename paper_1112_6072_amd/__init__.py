@@ -172,9 +172,9 @@ class Jobs:
         self.handle = handle
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.hperm_jobs_free(self.handle)
-            self.handle = None
+        self.handle = None
 
     def info(self) -> tuple[int, int]:
         nj, npb = _I32(), _I32()
@@ -217,10 +217,10 @@ class Context:
             self.set_arena(arena_bytes)
 
     def close(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.hperm_ctx_destroy(self.handle)
-            self.handle = None
-            self._arena = None
+        self.handle = None
+        self._arena = None
 
     __del__ = close
 

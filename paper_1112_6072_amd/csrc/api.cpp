@@ -278,13 +278,26 @@ static bool job_value(const JobDesc &d, const JobAcc &a, double log2_bound, U512
 static double ring_mul_slots(int ring) { return ring == HP_W64 ? 5.0 : ring == HP_W128 ? 9.0 : 33.0; }
 static double ring_add_slots(int ring) { return ring == HP_W64 ? 2.0 : ring == HP_W128 ? 4.0 : 9.0; }
 
-// Row-value updates of a whole job: Gray column j flips 2^(m-2-j) times.
-static uint64_t job_row_updates(const JobDesc &d, const uint32_t *data) {
+// Algorithmic work of one job for the suffix-product Gray walk: every lane chunk of L = 2^c
+// Gray indices starts with the product of all m row values (m ring multiplies); inside the
+// chunk, column j < c flips L / 2^(j+1) times and each flip updates its nnz(j) row values and
+// re-multiplies the hi[j] suffix products below the changed rows.
+struct JobWork {
+    double mults, updates;
+};
+static JobWork job_work(const JobDesc &d, const uint32_t *data, int chunk) {
     const int m = d.m;
     const uint32_t *cs = data + d.data_off + m;
-    uint64_t u = 0;
-    for (int j = 0; j + 1 < m; ++j) u += (uint64_t)(cs[j + 1] - cs[j]) << (m - 2 - j);
-    return u;
+    const uint32_t *hi = cs + m;
+    const double L = std::ldexp(1.0, chunk);
+    const double chunks = std::ldexp(1.0, m - 1) / L;
+    double mults = m, updates = 0;
+    for (int j = 0; j < chunk && j + 1 < m; ++j) {
+        const double flips = L / std::ldexp(1.0, j + 1);
+        mults += flips * hi[j];
+        updates += flips * (cs[j + 1] - cs[j]);
+    }
+    return {chunks * mults, chunks * updates};
 }
 
 static void fill_result(const U512 &v, hperm_result *r) {
@@ -402,10 +415,10 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
                 for (size_t q = g.off; q < g.off + g.n; ++q) {
                     const JobDesc &d = dsc[queue[q]];
                     const uint64_t t = 1ull << (d.m - 1);
-                    const uint64_t u = job_row_updates(d, j->tab.data.data());
+                    const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2);
                     st.terms += t;
-                    st.row_updates += u;
-                    st.alg_slots += (double)t * ((d.m - 1) * ring_mul_slots(d.arith) + ring_add_slots(d.arith)) + (double)u;
+                    st.row_updates += (uint64_t)wk.updates;
+                    st.alg_slots += wk.mults * ring_mul_slots(d.arith) + (double)t * ring_add_slots(d.arith) + wk.updates;
                 }
                 c->launches.push_back(st);
                 s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
@@ -436,11 +449,11 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
             for (size_t k = 0; k < nd; ++k) {
                 const JobDesc &d = desc_plain[k];
                 const uint64_t t = 1ull << (d.m - 1);
-                const uint64_t u = job_row_updates(d, j->tab.data.data());
+                const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2);
                 st.items += items_of(d.m, d.chunk_log2);
                 st.terms += t;
-                st.row_updates += u;
-                st.alg_slots += (double)t * ((d.m - 1) * ring_mul_slots(d.arith) + ring_add_slots(d.arith)) + (double)u;
+                st.row_updates += (uint64_t)wk.updates;
+                st.alg_slots += wk.mults * ring_mul_slots(d.arith) + (double)t * ring_add_slots(d.arith) + wk.updates;
             }
             c->launches.push_back(st);   // all single launches as one record (ms = whole span)
         }
@@ -539,7 +552,7 @@ static const char *check_opts(const hperm_opts *o) {
     if (o->arith < 0 || o->arith > 3) return "unknown arith";
     if (o->order < 0 || o->order > 3) return "unknown order";
     if (o->trials < 1 || o->trials > 4096) return "trials must be in [1, 4096]";
-    if (o->chunk_log2 < 0 || o->chunk_log2 > 20) return "chunk_log2 must be in [0, 20]";
+    if (o->chunk_log2 < 0 || o->chunk_log2 > 12) return "chunk_log2 must be in [0, 12]";
     if (o->host_threads < 0 || o->host_threads > 64) return "host_threads must be in [0, 64]";
     return nullptr;
 }

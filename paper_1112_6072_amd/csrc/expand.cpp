@@ -119,7 +119,7 @@ void make_child(const Node &a, int r, int p, int q, uint64_t ca, uint64_t cb, No
             if (a.ci[e] == q) aiq = a.v[e];
         }
         const uint64_t mv = ca * aiq + cb * aip;
-        if (mv >= HP_MAX_ENTRY) throw RangeError{"an expanded entry reached 2^23"};
+        if (mv >= HP_MAX_ENTRY) throw RangeError{"an expanded entry reached 2^22"};
         bool merged = false;
         for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
             const int col = a.ci[e];
@@ -173,7 +173,7 @@ void make_child_col(const Node &a, int cl, int p, int q, uint64_t ca, uint64_t c
             if (cq == col) mv += ca * a.v[eq++];
             if (cp == col) mv += cb * a.v[ep++];
             if (col == cl || mv == 0) continue;
-            if (mv >= HP_MAX_ENTRY) throw RangeError{"an expanded entry reached 2^23"};
+            if (mv >= HP_MAX_ENTRY) throw RangeError{"an expanded entry reached 2^22"};
             c->ci[out] = (uint8_t)(col - (col > cl ? 1 : 0));
             c->v[out++] = (uint32_t)mv;
         }
@@ -260,22 +260,58 @@ struct JobOut {
     std::vector<double> bound;
 };
 
+// A job for the R-NW kernels. Column choice and order: the densest column is the fixed
+// column of the Nijenhuis-Wilf form; the other m-1 "Gray columns" are ordered greedily so
+// that each next column touches as few rows not yet touched as possible (ties: fewer
+// nonzeros, then lower index). Gray column 0 flips at every other step, column j at every
+// 2^(j+1)-th, so early columns should reach few rows. Row order: rows sorted by their level,
+// the first Gray column touching them (rows touched by none come last). Then a flip of Gray
+// column j changes only rows below hi[j] = number of rows of level <= j, and the kernels
+// recompute only the suffix products of those rows.
 void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &prm,
               JobOut *out) {
     const int m = a.m;
     if (m > HP_MAX_M) throw RangeError{"a job exceeds the largest supported order"};
-    // column lists
     std::vector<int> cnt(m, 0);
-    for (int e = 0; e < a.nnz; ++e) cnt[a.ci[e]]++;
+    std::vector<uint64_t> colrows(m, 0);
+    for (int i = 0; i < m; ++i)
+        for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
+            cnt[a.ci[e]]++;
+            colrows[a.ci[e]] |= 1ull << i;
+        }
     int fixed = 0;
     for (int j = 1; j < m; ++j)
         if (cnt[j] > cnt[fixed]) fixed = j;
     std::vector<int> gray;
-    for (int j = 0; j < m; ++j)
-        if (j != fixed) gray.push_back(j);
-    std::stable_sort(gray.begin(), gray.end(), [&](int x, int y) { return cnt[x] < cnt[y]; });
+    std::vector<char> used(m, 0);
+    used[fixed] = 1;
+    uint64_t covered = 0;
+    for (int g = 0; g + 1 < m; ++g) {
+        int best = -1, bnew = 0;
+        for (int j = 0; j < m; ++j) {
+            if (used[j]) continue;
+            const int nw = __builtin_popcountll(colrows[j] & ~covered);
+            if (best < 0 || nw < bnew || (nw == bnew && cnt[j] < cnt[best])) {
+                best = j;
+                bnew = nw;
+            }
+        }
+        used[best] = 1;
+        gray.push_back(best);
+        covered |= colrows[best];
+    }
     std::vector<int> slot(m, -1);
     for (int g = 0; g < (int)gray.size(); ++g) slot[gray[g]] = g;
+    // row levels and the row order
+    std::vector<int> level(m, m - 1);
+    for (int g = (int)gray.size() - 1; g >= 0; --g)
+        for (int i = 0; i < m; ++i)
+            if (colrows[gray[g]] >> i & 1) level[i] = g;
+    std::vector<int> order(m);
+    for (int i = 0; i < m; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return level[x] < level[y]; });
+    std::vector<int> newrow(m);
+    for (int r = 0; r < m; ++r) newrow[order[r]] = r;
 
     std::vector<uint64_t> rsum(m, 0);
     std::vector<int64_t> bfix(m, 0);
@@ -310,13 +346,15 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
     d.nnz = (uint32_t)nnz_gray;
     d.problem = (uint32_t)problem;
     if (d.chunk_log2 > m - 1) d.chunk_log2 = (uint8_t)std::max(0, m - 1);
+    if (d.chunk_log2 > 12) d.chunk_log2 = 12;   // the kernels' delta tables hold 12 columns
     // at most 2^25 work items per job keep the per-job limb sums below 2^64
     if ((int)d.chunk_log2 < m - 32) d.chunk_log2 = (uint8_t)(m - 32);
 
     const size_t base = out->data.size();
     out->data.resize(base + hp_job_words(m, nnz_gray));
     uint32_t *w = out->data.data() + base;
-    for (int i = 0; i < m; ++i) w[i] = (uint32_t)(int32_t)(2 * bfix[i] - (int64_t)rsum[i]);
+    for (int i = 0; i < m; ++i)
+        w[newrow[i]] = (uint32_t)(int32_t)(2 * bfix[i] - (int64_t)rsum[i]);
     // Gray column g holds the entries of original column gray[g]
     std::vector<int> gcnt(m, 0);
     for (int i = 0; i < m; ++i)
@@ -329,18 +367,29 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
         acc += gcnt[g];
     }
     cs[m - 1] = acc;
-    uint32_t *ent = w + 2 * m;
+    uint32_t *hi = w + 2 * m;
+    for (int g = 0; g < m; ++g) {
+        int h = 0;
+        for (int i = 0; i < m; ++i) h += level[i] <= g;
+        hi[g] = (uint32_t)(g == m - 1 ? m : h);
+    }
+    uint32_t *ent = w + 3 * m;
     std::vector<uint32_t> pos(cs, cs + m);
-    for (int i = 0; i < m; ++i)
+    for (int r = 0; r < m; ++r) {
+        const int i = order[r];
         for (int e = a.rp[i]; e < a.rp[i + 1]; ++e)
             if (a.ci[e] != fixed) {
                 const int g = slot[a.ci[e]];
-                ent[pos[g]++] = ((2u * a.v[e]) << 8) | (uint32_t)i;
+                ent[pos[g]++] = ((2u * a.v[e]) << 8) | (uint32_t)r;
             }
-    // original column index of every job column (Gray slots, then the fixed column)
-    uint32_t *cm = w + 2 * m + nnz_gray;
+    }
+    // original column of every job column (Gray slots, then the fixed one) and original row
+    // of every job row: only the estimator's random draws use them
+    uint32_t *cm = w + 3 * m + nnz_gray;
     for (int g = 0; g < m - 1; ++g) cm[g] = (uint32_t)gray[g];
     cm[m - 1] = (uint32_t)fixed;
+    uint32_t *rm = cm + m;
+    for (int r = 0; r < m; ++r) rm[r] = (uint32_t)order[r];
     out->desc.push_back(d);
     out->bound.push_back(lb);
 }
@@ -420,7 +469,7 @@ std::string validate_csr(const CsrView &a) {
             if (a.col_idx[e] < 0 || a.col_idx[e] >= a.n) return "col_idx out of range";
             if (e > a.row_ptr[i] && a.col_idx[e] <= a.col_idx[e - 1])
                 return "col_idx must be strictly increasing within a row";
-            if (a.val[e] >= HP_MAX_ENTRY) return "entries must be below 2^23";
+            if (a.val[e] >= HP_MAX_ENTRY) return "entries must be below 2^22";
         }
     return "";
 }
@@ -599,7 +648,7 @@ int jobs_from_dense(int count, const int32_t *m, const int64_t *off, const uint3
             for (int j = 0; j < n; ++j) {
                 const uint32_t v = a[off[k] + (int64_t)i * n + j];
                 if (v >= HP_MAX_ENTRY) {
-                    *err = "entries must be below 2^23";
+                    *err = "entries must be below 2^22";
                     return -1;
                 }
                 if (v) {

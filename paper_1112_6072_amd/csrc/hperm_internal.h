@@ -12,7 +12,7 @@
 
 #define HP_MAX_M 40          // largest job order the kernels accept
 #define HP_MAX_N 128         // largest input order
-#define HP_MAX_ENTRY (1u << 23)   // expanded entries stay below this (2*b fits 24 bits)
+#define HP_MAX_ENTRY (1u << 22)   // expanded entries stay below this (2*b is a 24-bit signed value)
 #define HP_MAX_ROWSUM (1u << 24)  // row sums stay below this, so |f_i| < 2^24
 
 // Arithmetic rings of the kernels (values of JobDesc::arith).
@@ -31,13 +31,18 @@ enum : uint8_t { HP_W64 = 0, HP_W128 = 1, HP_RES = 2, HP_NRING = 3 };
 //   chunk_log2 : Gray indices per lane in one work item = 2^chunk_log2
 //   nnz      : number of entries in the Gray columns
 //   problem  : input problem the job belongs to
+// Rows are sorted by level (the first Gray column that touches them); a flip of Gray column
+// j changes only rows below hi[j].
 // Data block (32-bit words, starting at data_off):
 //   [0, m)            base_i as int32
 //   [m, 2m)           col_start[j] for j = 0..m-1: entry offset (relative to the entry
 //                     block) of Gray column j; col_start[m-1] = nnz (end)
-//   [2m, 2m+nnz)      entries of Gray column 0, then 1, ...: (2*b_ij << 8) | i
-//   [2m+nnz, 3m+nnz)  original column index of Gray column g (g < m-1) and of the fixed
-//                     column (slot m-1); used only for the estimator's random draws
+//   [2m, 3m)          hi[j]: number of rows whose level is <= j (hi[m-1] = m)
+//   [3m, 3m+nnz)      entries of Gray column 0, then 1, ...: (2*b_ij << 8) | i
+//   [3m+nnz, 4m+nnz)  original column index of Gray column g (g < m-1) and of the fixed
+//                     column (slot m-1)
+//   [4m+nnz, 5m+nnz)  original row index of job row i
+//                     (the last two are used only for the estimator's random draws)
 struct JobDesc {
     uint32_t data_off;
     uint8_t m;
@@ -49,7 +54,7 @@ struct JobDesc {
 };
 static_assert(sizeof(JobDesc) == 16, "JobDesc layout");
 
-static inline uint32_t hp_job_words(int m, int nnz) { return 3u * (uint32_t)m + (uint32_t)nnz; }
+static inline uint32_t hp_job_words(int m, int nnz) { return 5u * (uint32_t)m + (uint32_t)nnz; }
 
 // Per-job accumulator of the kernels: sums of 32-bit limbs of the work items' ring values
 // (integer addition is associative, so the atomic order does not change the result):

@@ -154,38 +154,37 @@ struct RingRes {
     }
 };
 
-// ------------------------------------------------------------------------ row values
-// The m row values f_i of one lane live in registers. Rows are indexed by wave-uniform
-// values, which the compiler turns into M0-relative register moves; it does so only for
-// a plain local array of at most 32 elements, so rows 32..39 sit in a second array.
-#define ROWS_DECL(MAXM)                                            \
-    constexpr int NA_ = (MAXM) < 32 ? (MAXM) : 32;                 \
-    constexpr int NB_ = (MAXM) > 32 ? (MAXM) - 32 : 1;             \
-    constexpr bool SPLIT_ = (MAXM) > 32;                           \
-    int fa_[NA_];                                                  \
-    int fb_[NB_];                                                  \
-    (void)fb_
-#define ROW_GET(i) ((!SPLIT_ || (i) < NA_) ? fa_[(i)] : fb_[(i) - NA_])
-#define ROW_SET(i, v)                  \
-    do {                               \
-        if (!SPLIT_ || (i) < NA_) fa_[(i)] = (v); \
-        else fb_[(i) - NA_] = (v);     \
-    } while (0)
-#define ROW_ADD(row, d)                                      \
-    do {                                                     \
-        if (!SPLIT_ || (row) < NA_) fa_[(row)] += (d);       \
-        else fb_[(row) - NA_] += (d);                        \
-    } while (0)
-
 // ------------------------------------------------------------------------ R-NW work item
 // One work item is 64 consecutive lane chunks of one job: lane l walks the Gray indices
 // k in [k0, k0 + L) with L = 2^c and k0 = (item * 64 + l) * L. Because k0 is a multiple of
-// L, the flipped Gray column at step k0 + t is ctz(t), the same in every lane, and only its
-// direction (bit ctz(t)+1 of k) can differ between lanes. The row values f_i live in
-// registers; the rows of a flipped column come from scalar loads of the job's data.
+// L, the flipped Gray column at step k0 + t is j = ctz(t), the same in every lane; its
+// direction (new bit = 1 - bit j+1 of k) is bit j+1 of t for j < c-1 and, at the single step
+// with j = c-1, bit c of k0 (the only lane-dependent case).
+//
+// The term prod_i f_i is kept as suffix products S_i = prod_{i' >= i} |f_i'| (S_m = 1) and
+// sign words G_i = f_i xor G_{i+1} whose bit 31 is the parity of the negative f_i', i' >= i.
+// Rows are sorted by the first Gray column that touches them, so a flip of column j changes
+// only rows below hi[j]; S and G are recomputed for those rows, in blocks of four rows from
+// the top block that holds a changed row down to row 0 (rows of a recomputed block above
+// hi[j] are unchanged, recomputing them is redundant but exact).
+//
+// The deltas 2 b_ij of the Gray columns that flip inside the item (j < c) sit in LDS as a
+// dense table D[j][row], one table per wave, written at the start of the item; a step reads
+// four rows with one broadcast LDS load. All register arrays are indexed by constants.
+constexpr int RB = 4;       // rows per recomputed block
+constexpr int CMAX = 12;    // largest lane chunk exponent c (host clamps chunk_log2)
+
+template <int MAXM>
+struct Tab {
+    static constexpr int STRIDE = (MAXM + RB - 1) / RB * RB;   // words per Gray column
+    static constexpr int WORDS = CMAX * STRIDE;                  // per wave
+};
+
 template <class R, int MAXM>
 __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__restrict__ data,
-                                         uint64_t item, int lane, JobAcc *dst) {
+                                         uint64_t item, int lane, JobAcc *dst, int *tab) {
+    static_assert(MAXM <= 40, "job orders up to 40");
+    constexpr int STRIDE = Tab<MAXM>::STRIDE;
     const int m = jd.m;
     const int c = jd.chunk_log2;
     const uint64_t nterms = 1ull << (m - 1);
@@ -193,55 +192,89 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
     const uint64_t k0 = (item * WAVE + (uint64_t)lane) * L;
     const uint32_t *w = data + jd.data_off;
     const uint32_t *cs = w + m;
-    const uint32_t *ent = w + 2 * m;
+    const uint32_t *hi = w + 2 * m;
+    const uint32_t *ent = w + 3 * m;
+
+    // delta table of the Gray columns 0..c-1
+    for (int q = lane; q < CMAX * STRIDE; q += WAVE) tab[q] = 0;
+    __builtin_amdgcn_wave_barrier();
+    for (int j = 0; j < c; ++j) {
+        const uint32_t b = uni(cs[j]);
+        const uint32_t n = uni(cs[j + 1]) - b;
+        if ((uint32_t)lane < n) {
+            const uint32_t pk = ent[b + lane];
+            tab[j * STRIDE + (int)(pk & 0xff)] = (int)(pk >> 8);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // f_i(gray(k0)) = base_i + 2 * sum over the set Gray bits (rows selected by comparison,
+    // so that the row values stay in registers with constant indices)
+    int f[MAXM];
+#pragma unroll
+    for (int i = 0; i < MAXM; ++i) f[i] = i < m ? (int)uni(w[i]) : 1;
+    const uint64_t g0 = k0 ^ (k0 >> 1);
+    for (int j = 0; j < m - 1; ++j) {
+        const int bit = (int)((g0 >> j) & 1);
+        const uint32_t b = uni(cs[j]);
+        const uint32_t e = uni(cs[j + 1]);
+        for (uint32_t q = b; q < e; ++q) {
+            const uint32_t pk = uni(ent[q]);
+            const int row = (int)(pk & 0xff);
+            const int d = bit ? (int)(pk >> 8) : 0;
+#pragma unroll
+            for (int i = 0; i < MAXM; ++i) f[i] += row == i ? d : 0;
+        }
+    }
+    typename R::P S[MAXM + 1];
+    uint32_t G[MAXM + 1];
+    S[MAXM] = R::one();
+    G[MAXM] = 0;
+#pragma unroll
+    for (int i = MAXM - 1; i >= 0; --i) {
+        S[i] = S[i + 1];
+        G[i] = G[i + 1];
+        if (i < m) {
+            const int x = f[i];
+            G[i] ^= (uint32_t)x;
+            R::mul(S[i], (uint32_t)(x < 0 ? -x : x));
+        }
+    }
+    // direction of the step with j = c-1 (lane-dependent): +1 if bit c of k0 is 0
+    const int dir_last = ((k0 >> c) & 1) ? -1 : 1;
+    const uint32_t k0par = (uint32_t)(k0 & 1);   // k0 is odd only when L = 1
 
     typename R::P acc = R::zero();
-    if (k0 < nterms) {
-        ROWS_DECL(MAXM);
+    for (uint32_t t = 0;; ++t) {
+        // term k = k0 + t: (-1)^k prod_i f_i
+        R::acc(acc, S[0], (G[0] >> 31) ^ k0par ^ (t & 1));
+        if (t + 1 >= (uint32_t)L) break;
+        const int j = __builtin_ctz(t + 1);
+        const int dir_uni = ((t + 1) >> (j + 1)) & 1 ? -1 : 1;
+        const int dir = j == c - 1 ? dir_last : dir_uni;
+        const int h = (int)uni(hi[j]);
+        const int *dj = tab + j * STRIDE;
 #pragma unroll
-        for (int i = 0; i < MAXM; ++i)
-            if (i < m) ROW_SET(i, (int)uni(w[i]));
-        // f_i(gray(k0)) = base_i + 2 * sum over set Gray bits
-        const uint64_t g0 = k0 ^ (k0 >> 1);
-        for (int j = 0; j < m - 1; ++j) {
-            const int bit = (int)((g0 >> j) & 1);
-            const uint32_t b = uni(cs[j]);
-            const uint32_t e = uni(cs[j + 1]);
-            for (uint32_t t = b; t < e; ++t) {
-                const uint32_t pk = uni(ent[t]);
-                const int row = (int)(pk & 0xff);
-                const int d = (int)(pk >> 8);
-                ROW_ADD(row, bit ? d : 0);
-            }
-        }
-        for (uint64_t t = 0;; ++t) {
-            // term k = k0 + t: (-1)^k prod_i f_i
-            typename R::P p = R::one();
-            uint32_t neg = (uint32_t)((k0 + t) & 1);
+        for (int B = (MAXM + RB - 1) / RB - 1; B >= 0; --B) {
+            if (B * RB < h) {
+                const int4 d4 = *reinterpret_cast<const int4 *>(dj + B * RB);
+                const int dd[RB] = {d4.x, d4.y, d4.z, d4.w};
 #pragma unroll
-            for (int i = 0; i < MAXM; ++i) {
-                if (i < m) {
-                    const int x = ROW_GET(i);
-                    neg ^= (uint32_t)x >> 31;
-                    R::mul(p, (uint32_t)(x < 0 ? -x : x));
+                for (int r = RB - 1; r >= 0; --r) {
+                    const int I = B * RB + r;
+                    if (I < MAXM) {
+                        // f_I += dir * d (24-bit signed multiply-add: 0 <= d < 2^23, dir = +-1)
+                        f[I] = __mul24(dd[r], dir) + f[I];
+                        const int x = f[I];
+                        G[I] = G[I + 1] ^ (uint32_t)x;
+                        S[I] = S[I + 1];
+                        R::mul(S[I], (uint32_t)(x < 0 ? -x : x));
+                    }
                 }
-            }
-            R::acc(acc, p, neg);
-            if (t + 1 >= L) break;
-            // step to k + 1: flip Gray column j = ctz(t + 1)
-            const int j = __builtin_ctzll(t + 1);
-            const uint64_t kn = k0 + t + 1;
-            const int sub = (int)((kn >> (j + 1)) & 1);   // new bit = 1 - sub
-            const uint32_t b = uni(cs[j]);
-            const uint32_t e = uni(cs[j + 1]);
-            for (uint32_t q = b; q < e; ++q) {
-                const uint32_t pk = uni(ent[q]);
-                const int row = (int)(pk & 0xff);
-                const int d = (int)(pk >> 8);
-                ROW_ADD(row, sub ? -d : d);
             }
         }
     }
+    if (k0 >= nterms) acc = R::zero();   // lanes past the end of a short job contribute nothing
     R::flush(acc, dst, lane);
 }
 
@@ -258,7 +291,9 @@ __global__ __launch_bounds__(BLOCK) void rnw_persistent(const JobDesc *__restric
                                                         uint32_t nqueue, uint64_t total_items,
                                                         unsigned long long *head,
                                                         JobAcc *__restrict__ accs) {
+    __shared__ __attribute__((aligned(16))) int tabs[(BLOCK / WAVE) * Tab<MAXM>::WORDS];
     const int lane = threadIdx.x & (WAVE - 1);
+    int *tab = tabs + (threadIdx.x >> 6) * Tab<MAXM>::WORDS;
     for (;;) {
         // Every lane takes part in the claim (lane 0 adds 1, the others 0) so that no
         // lane-dependent branch surrounds it: the whole wave then reads lane 0's claim.
@@ -277,7 +312,7 @@ __global__ __launch_bounds__(BLOCK) void rnw_persistent(const JobDesc *__restric
         const uint64_t first = lo ? uni64(item_end[lo - 1]) : 0;
         const uint32_t job = uni(queue[lo]);
         const JobDesc jd = load_job(jobs, job);
-        rnw_item<R, MAXM>(jd, data, g - first, lane, accs + job);
+        rnw_item<R, MAXM>(jd, data, g - first, lane, accs + job, tab);
     }
 }
 
@@ -287,11 +322,13 @@ __global__ __launch_bounds__(BLOCK) void rnw_single(const JobDesc *__restrict__ 
                                                     const uint32_t *__restrict__ data,
                                                     uint32_t job, uint64_t nitems,
                                                     JobAcc *__restrict__ accs) {
+    __shared__ __attribute__((aligned(16))) int tabs[(BLOCK / WAVE) * Tab<MAXM>::WORDS];
     const int lane = threadIdx.x & (WAVE - 1);
+    int *tab = tabs + (threadIdx.x >> 6) * Tab<MAXM>::WORDS;
     const uint64_t w = (uint64_t)blockIdx.x * (BLOCK / WAVE) + (threadIdx.x >> 6);
     if (w >= nitems) return;
     const JobDesc jd = load_job(jobs, job);
-    rnw_item<R, MAXM>(jd, data, w, lane, accs + job);
+    rnw_item<R, MAXM>(jd, data, w, lane, accs + job, tab);
 }
 
 #endif  // HP_PART >= 1
@@ -336,8 +373,9 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
     const int m = jd.m;
     const uint32_t *w = data + jd.data_off;
     const uint32_t *cs = w + m;
-    const uint32_t *ent = w + 2 * m;
-    const uint32_t *cmap = w + 2 * m + jd.nnz;
+    const uint32_t *ent = w + 3 * m;
+    const uint32_t *cmap = w + 3 * m + jd.nnz;
+    const uint32_t *rmap = cmap + m;
     // b_{lane, fixed} = base + sum over Gray columns of b_{lane, j}
     int gsum = 0;
     for (uint32_t e = 0; e < jd.nnz; ++e) {
@@ -345,7 +383,11 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
         if ((int)(pk & 0xff) == lane) gsum += (int)(pk >> 9);
     }
     int bfix = 0;
-    if (lane < m) bfix = (int)w[lane] + gsum;
+    uint32_t orow = 0;   // original row of this lane's job row (for the random draws)
+    if (lane < m) {
+        bfix = (int)w[lane] + gsum;
+        orow = rmap[lane];
+    }
     constexpr float kS = 0.86602540378443864676f;   // sin(2 pi / 3)
 
     float run_max = -INFINITY, run_sum = 0.0f;
@@ -365,7 +407,7 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
                 for (uint32_t q = b; q < e; ++q) {
                     const uint32_t pk = uni(ent[q]);
                     if ((int)(pk & 0xff) == lane) {
-                        const uint32_t u = kkl_u(seed, jobid, (uint32_t)t, (uint32_t)lane, oc);
+                        const uint32_t u = kkl_u(seed, jobid, (uint32_t)t, orow, oc);
                         re[j] = u == 0 ? 1.0f : -0.5f;
                         im[j] = u == 0 ? 0.0f : (u == 1 ? kS : -kS);
                     }
@@ -373,7 +415,7 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
             } else if (j == m - 1) {   // the fixed column
                 const uint32_t oc = uni(cmap[m - 1]);
                 if (lane < m && bfix != 0) {
-                    const uint32_t u = kkl_u(seed, jobid, (uint32_t)t, (uint32_t)lane, oc);
+                    const uint32_t u = kkl_u(seed, jobid, (uint32_t)t, orow, oc);
                     re[j] = u == 0 ? 1.0f : -0.5f;
                     im[j] = u == 0 ? 0.0f : (u == 1 ? kS : -kS);
                 }
