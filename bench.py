@@ -163,11 +163,17 @@ def main():
         extra[f"persistent_{order}_rnw_ms"] = sum(L["ms"] for L in ctx.last_launches())
     plain = None
     if not args.no_plain:
-        log("plain: one launch per job, expansion order")
-        ctx.run(jobs, "natural", False)
-        plain_ms = ctx.last_launches()[0]["ms"]
-        plain = terms / (plain_ms * 1e-3)
-        extra["plain_rnw_ms"] = plain_ms
+        log("plain: one launch per job, expansion order (best lane chunk of 3, 5, 7)")
+        best = None
+        for chunk in (3, 5, 7):
+            ctx.set_opts(chunk_log2=chunk)
+            ctx.run(jobs, "natural", False)
+            ms = ctx.last_launches()[0]["ms"]
+            extra[f"plain_rnw_ms_chunk{chunk}"] = ms
+            best = ms if best is None else min(best, ms)
+        ctx.set_opts(chunk_log2=0)
+        plain = terms / (best * 1e-3)
+        extra["plain_rnw_ms"] = best
         extra["plain_terms_per_s"] = plain
     lpt_rate = terms / (rnw_ms * 1e-3)
 

@@ -178,7 +178,30 @@ static std::vector<uint32_t> job_order(const hperm_jobs *j, int order, uint64_t 
     std::iota(ord.begin(), ord.end(), 0u);
     auto key = [&](uint32_t k) { return j->has_keys ? j->keys[k] : 0.0f; };
     if (order == HPERM_ORDER_ESTIMATE) {
-        std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) { return key(a) > key(b); });
+        // stable LSD radix sort on the keys, non-increasing: map each float to an unsigned
+        // integer that increases with the float, then complement it
+        std::vector<uint32_t> kb(nd), tmp(nd);
+        for (size_t k = 0; k < nd; ++k) {
+            uint32_t b;
+            const float f = key((uint32_t)k);
+            memcpy(&b, &f, 4);
+            b = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+            kb[k] = ~b;
+        }
+        std::vector<uint32_t> cnt(1 << 16);
+        for (int pass = 0; pass < 2; ++pass) {
+            const int shift = 16 * pass;
+            std::fill(cnt.begin(), cnt.end(), 0u);
+            for (uint32_t k : ord) cnt[(kb[k] >> shift) & 0xffff]++;
+            uint32_t sum = 0;
+            for (auto &c : cnt) {
+                const uint32_t x = c;
+                c = sum;
+                sum += x;
+            }
+            for (uint32_t k : ord) tmp[cnt[(kb[k] >> shift) & 0xffff]++] = k;
+            ord.swap(tmp);
+        }
     } else if (order == HPERM_ORDER_EXACT_COST) {
         std::stable_sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
             const int ma = j->tab.desc[a].m, mb = j->tab.desc[b].m;
@@ -198,12 +221,14 @@ static std::vector<uint32_t> job_order(const hperm_jobs *j, int order, uint64_t 
     return ord;
 }
 
-// Lane chunk of a job for the one-launch-per-job comparator: as many waves as the GPU
-// holds at one wave per SIMD (2^10) when the job is large enough.
-static int plain_chunk(int m) {
-    int c = m - 1 - 6 - 10;
+// Lane chunk of a job for the one-launch-per-job comparator: the context's chunk_log2 when
+// set, else about 256 waves per launch (one per four SIMDs) when the job is large enough.
+static int plain_chunk(int m, int opt) {
+    int c = opt > 0 ? opt : m - 1 - 6 - 8;
     if (c < 0) c = 0;
-    if (c > 10) c = 10;
+    if (c > 10 && opt <= 0) c = 10;
+    if (c > 12) c = 12;
+    if (c > m - 1) c = m - 1 > 0 ? m - 1 : 0;
     if (c < m - 32) c = m - 32;
     return c;
 }
@@ -300,6 +325,28 @@ static JobWork job_work(const JobDesc &d, const uint32_t *data, int chunk) {
     return {chunks * mults, chunks * updates};
 }
 
+// The integer x in [0, p0 p1 p2) with x = (res[2k] + 2^32 res[2k+1]) mod p_k (Garner).
+static U512 crt3(const unsigned long long *res) {
+    const uint64_t P[3] = {(1ull << 61) - HP_C0, (1ull << 61) - HP_C1, (1ull << 61) - HP_C2};
+    uint64_t r[3];
+    for (int k = 0; k < 3; ++k) r[k] = (uint64_t)(((u128)res[2 * k] + ((u128)res[2 * k + 1] << 32)) % P[k]);
+    const uint64_t t1 = mulmod((r[1] + P[1] - r[0] % P[1]) % P[1], invmod(P[0] % P[1], P[1]), P[1]);
+    const uint64_t x01 = (uint64_t)(((u128)r[0] + (u128)(P[0] % P[2]) * t1) % P[2]);
+    const uint64_t p01 = mulmod(P[0] % P[2], P[1] % P[2], P[2]);
+    const uint64_t t2 = mulmod((r[2] + P[2] - x01) % P[2], invmod(p01, P[2]), P[2]);
+    U512 x;
+    x.w[0] = t2;
+    x.mul_u64(P[1]);
+    U512 y;
+    y.w[0] = t1;
+    x.add(y);
+    x.mul_u64(P[0]);
+    U512 z;
+    z.w[0] = r[0];
+    x.add(z);
+    return x;
+}
+
 static void fill_result(const U512 &v, hperm_result *r) {
     for (int k = 0; k < 8; ++k) r->limb[k] = v.w[k];
     r->nlimb = v.nlimb();
@@ -332,7 +379,7 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
         std::vector<JobDesc> desc_plain;
         if (!persistent) {
             desc_plain = j->tab.desc;
-            for (auto &d : desc_plain) d.chunk_log2 = (uint8_t)plain_chunk(d.m);
+            for (auto &d : desc_plain) d.chunk_log2 = (uint8_t)plain_chunk(d.m, c->opts.chunk_log2);
         }
         const std::vector<JobDesc> &dsc = persistent ? j->tab.desc : desc_plain;
         // queue groups by (ring, bucket), each in the chosen job order
@@ -459,10 +506,29 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
         }
         s = hip_check(c, hipEventRecord(c->ev1, c->stream), "event");
         if (s) return s;
-        std::vector<JobAcc> host(nd);
-        s = hip_check(c, hipMemcpyAsync(host.data(), accs, nd * sizeof(JobAcc), hipMemcpyDeviceToHost,
-                                        c->stream), "download job values");
-        if (s) return s;
+        std::vector<JobAcc> host;
+        std::vector<ProbAcc> pacc;
+        if (per_job) {
+            host.resize(nd);
+            s = hip_check(c, hipMemcpyAsync(host.data(), accs, nd * sizeof(JobAcc), hipMemcpyDeviceToHost,
+                                            c->stream), "download job values");
+            if (s) return s;
+        } else {
+            // Step 4 on the device: one accumulator per problem
+            s = ensure_buf(c, B_PROB, (size_t)np * sizeof(ProbAcc));
+            if (s) return s;
+            ProbAcc *pd = (ProbAcc *)c->buf[B_PROB].ptr;
+            s = hip_check(c, launch_fill_u64((unsigned long long *)pd, (uint64_t)np * (sizeof(ProbAcc) / 8), 0ull,
+                                             c->stream), "clear problem accumulators");
+            if (s) return s;
+            s = hip_check(c, launch_recombine((const JobDesc *)c->buf[B_DESC].ptr, accs, (uint32_t)nd, pd,
+                                              c->stream), "recombine launch");
+            if (s) return s;
+            pacc.resize(np);
+            s = hip_check(c, hipMemcpyAsync(pacc.data(), pd, np * sizeof(ProbAcc), hipMemcpyDeviceToHost,
+                                            c->stream), "download problem values");
+            if (s) return s;
+        }
         s = hip_check(c, hipStreamSynchronize(c->stream), "R-NW");
         if (s) return s;
         float ms = 0.0f;
@@ -479,17 +545,20 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
         }
         for (size_t k = 0; k < nd; ++k) {
             const JobDesc &d = j->tab.desc[k];
-            U512 v;
-            if (!job_value(d, host[k], j->tab.log2_bound[k], &v))
-                return set_error(c, HPERM_E_INTERNAL, "a job value failed its integrity check (job " +
-                                                          std::to_string(k) + ")");
             const int p = (int)d.problem;
-            sums[p].add(v);
             nj[p]++;
             maxm[p] = std::max(maxm[p], (int)d.m);
             amask[p] |= 1 << (d.arith + 1);
             terms[p] += 1ull << (d.m - 1);
-            if (per_job) {
+        }
+        if (per_job) {
+            for (size_t k = 0; k < nd; ++k) {
+                const JobDesc &d = j->tab.desc[k];
+                U512 v;
+                if (!job_value(d, host[k], j->tab.log2_bound[k], &v))
+                    return set_error(c, HPERM_E_INTERNAL, "a job value failed its integrity check (job " +
+                                                              std::to_string(k) + ")");
+                sums[d.problem].add(v);
                 memset(&per_job[k], 0, sizeof(hperm_result));
                 fill_result(v, &per_job[k]);
                 per_job[k].n_jobs = 1;
@@ -497,7 +566,29 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
                 per_job[k].arith_mask = 1 << (d.arith + 1);
                 per_job[k].subset_terms = 1ull << (d.m - 1);
             }
+        } else {
+            for (int p = 0; p < np; ++p) {
+                const ProbAcc &q = pacc[p];
+                if (q.err)
+                    return set_error(c, HPERM_E_INTERNAL, "a job value of problem " + std::to_string(p) +
+                                                              " failed its integrity check");
+                U512 v;
+                for (int l = 3; l >= 0; --l) {   // sum_l lim[l] 2^(32 l)
+                    U512 t;
+                    t.w[0] = q.lim[l];
+                    for (int z = 0; z < l; ++z) t.mul_u64(1ull << 32);
+                    v.add(t);
+                }
+                bool any_res = false;
+                for (int z = 0; z < 6; ++z) any_res |= q.res[z] != 0;
+                if (any_res) v.add(crt3(q.res));
+                sums[p] = v;
+            }
         }
+        for (int p = 0; p < np; ++p)
+            if (!j->tab.direct_valid[p] && sums[p].bits() > (int)std::ceil(j->tab.problem_log2_bound[p]) + 1)
+                return set_error(c, HPERM_E_INTERNAL, "a result exceeds its proven bound (problem " +
+                                                          std::to_string(p) + ")");
     }
     for (int p = 0; p < np; ++p) {
         hperm_result &r = totals[p];

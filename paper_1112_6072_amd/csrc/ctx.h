@@ -21,7 +21,7 @@ struct DevBuf {
     bool owned = false;
 };
 
-enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_COUNT };
+enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_PROB, B_COUNT };
 
 struct Serving;   // serve.cpp
 

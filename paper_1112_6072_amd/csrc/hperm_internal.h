@@ -66,3 +66,15 @@ struct JobAcc {
     unsigned long long pad[2];
 };
 static_assert(sizeof(JobAcc) == 64, "JobAcc layout");
+
+// Per-problem accumulator of the device recombination: lim[k] sums limb k (32 bits) of the
+// exact permanents of the problem's 2-adic-ring jobs; res[2k], res[2k+1] sum the low and
+// high 32-bit halves of the residues mod p_k of its residue-ring jobs; err is set when a
+// job fails its 2-adic integrity check.
+struct ProbAcc {
+    unsigned long long lim[4];
+    unsigned long long res[6];
+    unsigned int err;
+    unsigned int pad[11];
+};
+static_assert(sizeof(ProbAcc) == 128, "ProbAcc layout");

@@ -12,6 +12,10 @@ int bucket_of(int m);
 
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 
+// Normalise every job's accumulator and add it into its problem's accumulator.
+hipError_t launch_recombine(const JobDesc *jobs, const JobAcc *accs, uint32_t njobs,
+                            ProbAcc *probs, hipStream_t s);
+
 // KKLLL keys of the listed jobs of one bucket (one block of 4 waves per job); keys[job id].
 hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data,
                            const uint32_t *list, uint32_t nlist, int trials, uint64_t seed,

@@ -197,7 +197,9 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
 
     // delta table of the Gray columns 0..c-1
     for (int q = lane; q < CMAX * STRIDE; q += WAVE) tab[q] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     for (int j = 0; j < c; ++j) {
         const uint32_t b = uni(cs[j]);
         const uint32_t n = uni(cs[j + 1]) - b;
@@ -206,7 +208,9 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
             tab[j * STRIDE + (int)(pk & 0xff)] = (int)(pk >> 8);
         }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
     // f_i(gray(k0)) = base_i + 2 * sum over the set Gray bits (rows selected by comparison,
     // so that the row values stay in registers with constant indices)
@@ -353,118 +357,134 @@ __device__ __forceinline__ uint32_t kkl_u(uint64_t seed, uint32_t w, uint32_t t,
     return (uint32_t)(((x >> 32) * 3ull) >> 32);
 }
 
-// One block per job, 4 waves; wave v runs trials v, v+4, ... Lane i holds row i of
-// B (complex FP32). Gaussian elimination with partial pivoting: the pivot row is the
-// unused lane with the largest |B_ik|; log|det B| = sum of log|pivot|. The key is the log
-// of the mean of |det B|^2 over the trials, combined as a log-sum-exp. Every loop over
-// columns is unrolled to MAXM so the row lives in registers.
-template <int MAXM>
+// KKLLL on one job per block (4 waves). A wave holds 64 / GROUP trials at once, one per
+// group of GROUP lanes (GROUP >= m); lane r of a group holds row r of that trial's B in
+// registers (complex FP32, columns in job order). The matrix is written into LDS by all
+// lanes (one random draw per nonzero), then each lane loads its row. Gaussian elimination
+// with partial pivoting: the pivot row is the unused row with the largest |B_rk|, found by a
+// butterfly inside the group and broadcast with lane permutes; log|det B| is the sum of
+// log|pivot|. Trials accumulate log-sum-exp pairs; the key is log(mean |det B|^2).
+template <int MAXM, int GROUP>
+struct KklShape {
+    static_assert(MAXM <= GROUP && (GROUP == 16 || GROUP == 32 || GROUP == 64), "group size");
+    static constexpr int TPW = WAVE / GROUP;            // trials per wave pass
+    static constexpr int LD = MAXM + 1;                 // padded row length (float2)
+    static constexpr int WAVE_WORDS = TPW * MAXM * LD;  // float2 per wave
+};
+
+template <int MAXM, int GROUP>
 __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict__ jobs,
                                                       const uint32_t *__restrict__ data,
                                                       const uint32_t *__restrict__ list,
                                                       uint32_t nlist, int trials, uint64_t seed,
                                                       float *__restrict__ keys) {
-    __shared__ float red[2 * (BLOCK / WAVE)];
+    using Sh = KklShape<MAXM, GROUP>;
+    __shared__ float2 mats[(BLOCK / WAVE) * Sh::WAVE_WORDS];
+    __shared__ float red[2 * BLOCK];
     if (blockIdx.x >= nlist) return;
     const uint32_t jobid = uni(list[blockIdx.x]);
     const JobDesc jd = load_job(jobs, jobid);
     const int lane = threadIdx.x & (WAVE - 1);
     const int wave = threadIdx.x >> 6;
+    const int grp = lane / GROUP;             // trial slot inside the wave
+    const int r = lane % GROUP;               // row held by this lane
+    const int gbase = lane - r;               // first lane of the group
     const int m = jd.m;
+    const int nnz = (int)jd.nnz;
     const uint32_t *w = data + jd.data_off;
     const uint32_t *cs = w + m;
     const uint32_t *ent = w + 3 * m;
     const uint32_t *cmap = w + 3 * m + jd.nnz;
     const uint32_t *rmap = cmap + m;
-    // b_{lane, fixed} = base + sum over Gray columns of b_{lane, j}
-    int gsum = 0;
-    for (uint32_t e = 0; e < jd.nnz; ++e) {
-        const uint32_t pk = uni(ent[e]);
-        if ((int)(pk & 0xff) == lane) gsum += (int)(pk >> 9);
-    }
-    int bfix = 0;
-    uint32_t orow = 0;   // original row of this lane's job row (for the random draws)
-    if (lane < m) {
-        bfix = (int)w[lane] + gsum;
-        orow = rmap[lane];
-    }
+    float2 *wm = mats + wave * Sh::WAVE_WORDS;
     constexpr float kS = 0.86602540378443864676f;   // sin(2 pi / 3)
 
-    float run_max = -INFINITY, run_sum = 0.0f;
-    for (int t = wave; t < trials; t += BLOCK / WAVE) {
-        float re[MAXM], im[MAXM];
-#pragma unroll
-        for (int j = 0; j < MAXM; ++j) {
-            re[j] = 0.0f;
-            im[j] = 0.0f;
-        }
-#pragma unroll
-        for (int j = 0; j < MAXM; ++j) {
-            if (j < m - 1) {   // Gray column j
-                const uint32_t b = uni(cs[j]);
-                const uint32_t e = uni(cs[j + 1]);
-                const uint32_t oc = uni(cmap[j]);
-                for (uint32_t q = b; q < e; ++q) {
-                    const uint32_t pk = uni(ent[q]);
-                    if ((int)(pk & 0xff) == lane) {
-                        const uint32_t u = kkl_u(seed, jobid, (uint32_t)t, orow, oc);
-                        re[j] = u == 0 ? 1.0f : -0.5f;
-                        im[j] = u == 0 ? 0.0f : (u == 1 ? kS : -kS);
-                    }
-                }
-            } else if (j == m - 1) {   // the fixed column
-                const uint32_t oc = uni(cmap[m - 1]);
-                if (lane < m && bfix != 0) {
-                    const uint32_t u = kkl_u(seed, jobid, (uint32_t)t, orow, oc);
-                    re[j] = u == 0 ? 1.0f : -0.5f;
-                    im[j] = u == 0 ? 0.0f : (u == 1 ? kS : -kS);
-                }
+    // fixed-column entries: row i has b_i,fixed = base_i + sum of its Gray entries
+    // (computed once per lane for the row it holds; only its zero test matters)
+    int gsum = 0;
+    for (int e = 0; e < nnz; ++e) {
+        const uint32_t pk = uni(ent[e]);
+        if ((int)(pk & 0xff) == r) gsum += (int)(pk >> 9);
+    }
+    const bool fixed_nz = r < m && ((int)w[r < m ? r : 0] + gsum) != 0;
+    const uint32_t fixed_col = uni(cmap[m - 1]);
+
+    float run_max = -INFINITY, run_sum = 0.0f;   // per lane; identical within a group
+    for (int t0 = wave * Sh::TPW; t0 < trials; t0 += (BLOCK / WAVE) * Sh::TPW) {
+        const int t = t0 + grp;                      // this group's trial
+        const bool live = t < trials;
+        // zero the wave's matrices, then write the nonzeros (all lanes share the work)
+        for (int q = lane; q < Sh::WAVE_WORDS; q += WAVE) wm[q] = make_float2(0.0f, 0.0f);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int g = 0; g < Sh::TPW; ++g) {
+            const int tg = t0 + g;
+            if (tg >= trials) break;
+            float2 *mg = wm + g * MAXM * Sh::LD;
+            for (int e = lane; e < nnz; e += WAVE) {
+                const uint32_t pk = ent[e];
+                const int row = (int)(pk & 0xff);
+                // Gray column of entry e: the last j with cs[j] <= e
+                int col = 0;
+                for (int j = 1; j < m - 1; ++j) col += (int)cs[j] <= e ? 1 : 0;
+                const uint32_t u = kkl_u(seed, jobid, (uint32_t)tg, rmap[row], cmap[col]);
+                mg[row * Sh::LD + col] = make_float2(u == 0 ? 1.0f : -0.5f, u == 0 ? 0.0f : (u == 1 ? kS : -kS));
+            }
+            if (fixed_nz && grp == g) {
+                const uint32_t u = kkl_u(seed, jobid, (uint32_t)tg, rmap[r], fixed_col);
+                mg[r * Sh::LD + (m - 1)] = make_float2(u == 0 ? 1.0f : -0.5f, u == 0 ? 0.0f : (u == 1 ? kS : -kS));
             }
         }
-        bool used = lane >= m;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float re[MAXM], im[MAXM];
+        const float2 *myrow = wm + grp * MAXM * Sh::LD + (r < MAXM ? r : 0) * Sh::LD;
+#pragma unroll
+        for (int c = 0; c < MAXM; ++c) {
+            const float2 v = myrow[c];
+            re[c] = r < m ? v.x : 0.0f;
+            im[c] = r < m ? v.y : 0.0f;
+        }
+        bool used = r >= m;
         float logabs = 0.0f;
-        int singular = 0;
+        bool singular = !live;
 #pragma unroll
         for (int k = 0; k < MAXM; ++k) {
-            if (k < m && !singular) {
+            if (k < m) {
                 float mag = used ? -1.0f : re[k] * re[k] + im[k] * im[k];
-                int idx = lane;
+                int idx = r;
 #pragma unroll
-                for (int s = 32; s >= 1; s >>= 1) {
-                    const float om = __shfl_xor(mag, s, WAVE);
-                    const int oi = __shfl_xor(idx, s, WAVE);
+                for (int sft = GROUP / 2; sft >= 1; sft >>= 1) {
+                    const float om = __shfl_xor(mag, sft, WAVE);
+                    const int oi = __shfl_xor(idx, sft, WAVE);
                     if (om > mag || (om == mag && oi < idx)) {
                         mag = om;
                         idx = oi;
                     }
                 }
-                const int piv = (int)uni((uint32_t)idx);
-                const float pmag = __builtin_bit_cast(float, uni(__builtin_bit_cast(uint32_t, mag)));
-                if (!(pmag > 0.0f)) {
-                    singular = 1;
-                } else {
-                    logabs += 0.5f * logf(pmag);
-                    const float pr = __builtin_bit_cast(
-                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, re[k]), piv));
-                    const float pi = __builtin_bit_cast(
-                        float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, im[k]), piv));
-                    if (lane == piv) used = true;
-                    // factor = B_ik / pivot = B_ik * conj(pivot) / |pivot|^2
-                    const float ir = pr / pmag, ii = -pi / pmag;
-                    const float fr = re[k] * ir - im[k] * ii;
-                    const float fi = re[k] * ii + im[k] * ir;
+                // every lane of the group now holds the group's pivot row idx and |pivot|^2
+                const bool ok = !singular && mag > 0.0f;
+                singular = !ok;
+                const int src = gbase + idx;
+                const float pr = __shfl(re[k], src, WAVE);
+                const float pi = __shfl(im[k], src, WAVE);
+                if (r == idx) used = true;
+                const float pm = ok ? mag : 1.0f;
+                logabs += ok ? 0.5f * __logf(pm) : 0.0f;
+                // factor = B_rk / pivot (zero for used rows and failed groups)
+                const float ir = pr / pm, ii = -pi / pm;
+                const bool upd = ok && !used;
+                const float fr = upd ? re[k] * ir - im[k] * ii : 0.0f;
+                const float fi = upd ? re[k] * ii + im[k] * ir : 0.0f;
 #pragma unroll
-                    for (int c = k + 1; c < MAXM; ++c) {
-                        if (c < m) {
-                            const float cr = __builtin_bit_cast(
-                                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, re[c]), piv));
-                            const float ci = __builtin_bit_cast(
-                                float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, im[c]), piv));
-                            if (!used) {
-                                re[c] -= fr * cr - fi * ci;
-                                im[c] -= fr * ci + fi * cr;
-                            }
-                        }
+                for (int c = k + 1; c < MAXM; ++c) {
+                    if (c < m) {
+                        const float cr = __shfl(re[c], src, WAVE);
+                        const float ci = __shfl(im[c], src, WAVE);
+                        re[c] -= fr * cr - fi * ci;
+                        im[c] -= fr * ci + fi * cr;
                     }
                 }
             }
@@ -472,29 +492,102 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
         if (!singular) {
             const float l = 2.0f * logabs;   // log |det B|^2
             if (l > run_max) {
-                run_sum = run_sum * expf(run_max - l) + 1.0f;
+                run_sum = run_sum * __expf(run_max - l) + 1.0f;
                 run_max = l;
             } else {
-                run_sum += expf(l - run_max);
+                run_sum += __expf(l - run_max);
             }
         }
     }
-    // combine the waves: (max, sum) pairs through LDS
-    if (lane == 0) {
-        red[2 * wave] = run_max;
-        red[2 * wave + 1] = run_sum;
-    }
+    // combine the (max, sum) pairs of all groups of all waves (one per group's first lane)
+    red[2 * threadIdx.x] = r == 0 ? run_max : -INFINITY;
+    red[2 * threadIdx.x + 1] = r == 0 ? run_sum : 0.0f;
     __syncthreads();
     if (threadIdx.x == 0) {
         float mx = -INFINITY;
-        for (int v = 0; v < BLOCK / WAVE; ++v) mx = fmaxf(mx, red[2 * v]);
+        for (int v = 0; v < BLOCK; ++v) mx = fmaxf(mx, red[2 * v]);
         float sum = 0.0f;
         if (mx > -INFINITY)
-            for (int v = 0; v < BLOCK / WAVE; ++v)
-                if (red[2 * v] > -INFINITY) sum += red[2 * v + 1] * expf(red[2 * v] - mx);
-        keys[jobid] = (mx > -INFINITY && sum > 0.0f) ? mx + logf(sum) - logf((float)trials)
+            for (int v = 0; v < BLOCK; ++v)
+                if (red[2 * v] > -INFINITY) sum += red[2 * v + 1] * __expf(red[2 * v] - mx);
+        keys[jobid] = (mx > -INFINITY && sum > 0.0f) ? mx + __logf(sum) - __logf((float)trials)
                                                      : -INFINITY;
     }
+}
+
+// Step 4 of Algorithm PH on the device: every job's ring value V is turned into its
+// permanent and added into its problem's accumulator.
+//   mod 2^64 / 2^128: per = (-1)^(m-1) V / 2^(m-1); V must be divisible by 2^(m-1) with a
+//   non-negative quotient (else the problem's error flag is set); the 32-bit limbs of per are
+//   added into lim[0..3].
+//   residues: per mod p_k = (-1)^(m-1) (2^-1)^(m-1) V mod p_k, added as 32-bit halves into
+//   res[2k], res[2k+1]; the host reduces the sums and applies the CRT.
+template <uint64_t C>
+__device__ __forceinline__ uint64_t mod61(unsigned __int128 x) {
+    constexpr uint64_t P = (1ull << 61) - C;
+    // x < 2^96: fold 2^61 = C twice, then subtract
+    uint64_t lo = (uint64_t)x & ((1ull << 61) - 1);
+    unsigned __int128 hi = x >> 61;
+    unsigned __int128 y = (unsigned __int128)lo + hi * C;
+    lo = (uint64_t)y & ((1ull << 61) - 1);
+    uint64_t h2 = (uint64_t)(y >> 61);
+    uint64_t z = lo + h2 * C;   // y < 2^62, so h2 <= 1 and z < 2P
+    return z >= P ? z - P : z;
+}
+template <uint64_t C>
+__device__ __forceinline__ uint64_t mulmod_full(uint64_t a, uint64_t b) {
+    return mod61<C>((unsigned __int128)a * b);
+}
+template <uint64_t C>
+__device__ __forceinline__ uint64_t res_normalise(uint64_t lo_sum, uint64_t hi_sum, int m) {
+    constexpr uint64_t P = (1ull << 61) - C;
+    constexpr uint64_t INV2 = (P + 1) / 2;
+    uint64_t v = mod61<C>((unsigned __int128)lo_sum + ((unsigned __int128)hi_sum << 32));
+    for (int e = 0; e < m - 1; ++e) v = mulmod_full<C>(v, INV2);
+    if (((m - 1) & 1) && v) v = P - v;
+    return v;
+}
+
+__global__ void recombine(const JobDesc *__restrict__ jobs, const JobAcc *__restrict__ accs,
+                          uint32_t njobs, ProbAcc *__restrict__ probs) {
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= njobs) return;
+    const JobDesc d = jobs[k];
+    const JobAcc a = accs[k];
+    ProbAcc *pa = probs + d.problem;
+    const int sh = d.m - 1;
+    if (d.arith == HP_RES) {
+        const uint64_t r0 = res_normalise<HP_C0>(a.l[0], a.l[1], d.m);
+        const uint64_t r1 = res_normalise<HP_C1>(a.l[2], a.l[3], d.m);
+        const uint64_t r2 = res_normalise<HP_C2>(a.l[4], a.l[5], d.m);
+        atomicAdd(&pa->res[0], (unsigned long long)(r0 & 0xffffffffull));
+        atomicAdd(&pa->res[1], (unsigned long long)(r0 >> 32));
+        atomicAdd(&pa->res[2], (unsigned long long)(r1 & 0xffffffffull));
+        atomicAdd(&pa->res[3], (unsigned long long)(r1 >> 32));
+        atomicAdd(&pa->res[4], (unsigned long long)(r2 & 0xffffffffull));
+        atomicAdd(&pa->res[5], (unsigned long long)(r2 >> 32));
+        return;
+    }
+    unsigned __int128 V;
+    if (d.arith == HP_W64) {
+        const __int128 sv = (int64_t)a.l[0];
+        V = (unsigned __int128)sv;
+    } else {
+        V = (unsigned __int128)a.l[0] + ((unsigned __int128)a.l[1] << 32) +
+            ((unsigned __int128)a.l[2] << 64) + ((unsigned __int128)a.l[3] << 96);
+    }
+    if (sh & 1) V = (unsigned __int128)0 - V;
+    const bool neg = (V >> 127) != 0;
+    const bool divisible = sh == 0 || (V & (((unsigned __int128)1 << sh) - 1)) == 0;
+    if (neg || !divisible) {
+        atomicOr(&pa->err, 1u);
+        return;
+    }
+    const unsigned __int128 per = V >> sh;
+    atomicAdd(&pa->lim[0], (unsigned long long)(uint32_t)per);
+    atomicAdd(&pa->lim[1], (unsigned long long)(uint32_t)(per >> 32));
+    atomicAdd(&pa->lim[2], (unsigned long long)(uint32_t)(per >> 64));
+    atomicAdd(&pa->lim[3], (unsigned long long)(uint32_t)(per >> 96));
 }
 
 __global__ void fill_u64(unsigned long long *p, uint64_t n, unsigned long long v) {
@@ -513,6 +606,13 @@ namespace hp {
 
 int bucket_of(int m) { return m <= 16 ? 0 : (m <= 24 ? 1 : (m <= 32 ? 2 : 3)); }
 
+hipError_t launch_recombine(const JobDesc *jobs, const JobAcc *accs, uint32_t njobs,
+                            ProbAcc *probs, hipStream_t s) {
+    if (njobs == 0) return hipSuccess;
+    hipLaunchKernelGGL(recombine, dim3((njobs + 255) / 256), dim3(256), 0, s, jobs, accs, njobs, probs);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v,
                            hipStream_t s) {
     if (n == 0) return hipSuccess;
@@ -526,14 +626,13 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
                            float *keys, hipStream_t s) {
     if (nlist == 0) return hipSuccess;
     switch (bucket) {
-        case 0: hipLaunchKernelGGL(kkl_estimate<16>, dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
-        case 1: hipLaunchKernelGGL(kkl_estimate<24>, dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
-        case 2: hipLaunchKernelGGL(kkl_estimate<32>, dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
-        default: hipLaunchKernelGGL(kkl_estimate<HP_MAX_M>, dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys);
+        case 0: hipLaunchKernelGGL((kkl_estimate<16, 16>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
+        case 1: hipLaunchKernelGGL((kkl_estimate<24, 32>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
+        case 2: hipLaunchKernelGGL((kkl_estimate<32, 32>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
+        default: hipLaunchKernelGGL((kkl_estimate<HP_MAX_M, 64>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys);
     }
     return hipGetLastError();
 }
-
 #endif  // HP_PART == 0
 
 #if HP_PART >= 1
