@@ -182,22 +182,41 @@ void hperm_jobs_free(hperm_jobs *jobs);
 
 /* ---- serving ------------------------------------------------------------------------ */
 
-/* Start the serving loop of a context: a background thread admits requests while free
- * request slots (max_requests) and device memory (arena_bytes for job tables) allow,
- * expands them on worker threads, merges their jobs into one device queue shared by all
- * requests in flight (continuous batching), and completes each request when its last job
- * is done. The context must not be used for blocking calls while serving. */
+/* Start the serving loop of a context (continuous batching of requests):
+ * - a request is admitted while fewer than max_requests (1..65536) are live, else
+ *   hperm_submit returns HPERM_E_BUSY;
+ * - worker threads expand admitted requests (steps 1-2) with the context's options;
+ * - a dispatcher packs every expanded request, oldest first, into one batch while the
+ *   batch's device buffers fit a free slice of the serving arena (arena_bytes of device
+ *   memory allocated here; 0 means 2 GiB): admission by device memory. A request whose own
+ *   buffers exceed the arena completes with HPERM_E_NOMEM;
+ * - a batch is one device queue over all of its requests' jobs (steps 3-6), run on one of
+ *   two streams at the default priority, so that the next batch starts while the previous
+ *   one runs; at most two batches are in flight;
+ * - a request completes when its batch does; its result is bit-identical to the blocking
+ *   call's.
+ * While serving, the context refuses blocking GPU calls, hperm_ctx_set_opts and
+ * hperm_ctx_set_arena (HPERM_E_INVALID). hperm_serve_stop (and hperm_ctx_destroy) finish
+ * the batches in flight, drop requests not yet dispatched and free the arena; no other
+ * call on the context may be in progress then. Errors: HPERM_E_INVALID (already serving,
+ * max_requests out of range), HPERM_E_NOMEM (arena allocation), HPERM_E_DEVICE. */
 hperm_status hperm_serve_start(hperm_ctx *ctx, int32_t max_requests, size_t arena_bytes);
 hperm_status hperm_serve_stop(hperm_ctx *ctx);
 
-/* Submit per(A) of a CSR matrix (copied). *ticket identifies it. HPERM_E_BUSY when the
- * admission queue is full. */
+/* Submit per(A) of a CSR matrix (n <= 128; same layout and limits as hperm_permanent_csr;
+ * copied, so the arrays may be freed on return). *ticket identifies it. HPERM_E_BUSY when
+ * every request slot is in use; HPERM_E_INVALID for a malformed matrix or when not serving. */
 hperm_status hperm_submit(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
                           const int32_t *col_idx, const uint32_t *val, uint64_t *ticket);
 
-/* HPERM_NOT_READY while running; on HPERM_OK fills *out once and frees the ticket. The
- * result's timing fields hold queue wait (t_expand_s: submit to admission) and latency
- * (t_total_s: submit to completion). */
+/* HPERM_NOT_READY while running; once done, returns the request's status (HPERM_OK and *out
+ * filled, or its error, HPERM_E_CANCELLED for a cancelled one) exactly once and frees the
+ * ticket; an unknown or already taken ticket gives HPERM_E_INVALID. The result's timing
+ * fields hold the queue wait (t_expand_s: submit to dispatch in a batch), the batch's R-NW
+ * time (t_rnw_s) and the latency (t_total_s: submit to completion). hperm_wait blocks until
+ * done (timeout_s < 0: no limit) and returns HPERM_E_TIMEOUT when the limit passes first.
+ * hperm_cancel drops a request that is not yet dispatched; one already running completes
+ * but reports HPERM_E_CANCELLED. Submit/poll/wait/cancel may be called from any thread. */
 hperm_status hperm_poll(hperm_ctx *ctx, uint64_t ticket, hperm_result *out);
 hperm_status hperm_wait(hperm_ctx *ctx, uint64_t ticket, double timeout_s, hperm_result *out);
 hperm_status hperm_cancel(hperm_ctx *ctx, uint64_t ticket);

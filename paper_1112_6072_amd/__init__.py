@@ -324,6 +324,43 @@ class Context:
         pjv = [pj[k].value for k in range(nj)] if per_job else None
         return totals, pjv, [tot[k] for k in range(npb)]
 
+    # ---------------------------------------------------------------- serving
+    def serve_start(self, max_requests: int = 1024, arena_bytes: int = 1 << 30):
+        """Start continuous batching: requests share device queues, admitted by arena_bytes."""
+        self._check(_lib.hperm_serve_start(self.handle, int(max_requests), int(arena_bytes)), "serve_start")
+
+    def serve_stop(self):
+        self._check(_lib.hperm_serve_stop(self.handle), "serve_stop")
+
+    def submit(self, A) -> int | None:
+        """Submit per(A); returns a ticket, or None when every request slot is taken."""
+        n, rp, ci, va = _csr(A)
+        t = _U64()
+        st = _lib.hperm_submit(self.handle, n, _ptr(rp), _ptr(ci) if ci.size else None,
+                               _ptr(va) if va.size else None, ctypes.byref(t))
+        if st == -5:   # HPERM_E_BUSY
+            return None
+        self._check(st, "submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(value, stats) when done, None while running."""
+        r = Result()
+        st = _lib.hperm_poll(self.handle, int(ticket), ctypes.byref(r))
+        if st == NOT_READY:
+            return None
+        self._check(st, "poll")
+        return r.value, r.stats()
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        """Block until the request is done (timeout_s < 0: no limit); returns (value, stats)."""
+        r = Result()
+        self._check(_lib.hperm_wait(self.handle, int(ticket), float(timeout_s), ctypes.byref(r)), "wait")
+        return r.value, r.stats()
+
+    def cancel(self, ticket: int):
+        self._check(_lib.hperm_cancel(self.handle, int(ticket)), "cancel")
+
 
 def version() -> tuple[int, int]:
     a, b = _I32(), _I32()

@@ -26,12 +26,17 @@ uint64_t next_jobs_id() {
     return ctr.fetch_add(1);
 }
 
-hperm_status set_error(hperm_ctx *c, hperm_status s, const std::string &msg) {
+hperm_status set_error(Dev *c, hperm_status s, const std::string &msg) {
     if (c) c->last_error = msg;
     return s;
 }
 
-hperm_status hip_check(hperm_ctx *c, hipError_t e, const char *what) {
+hperm_status set_error(hperm_ctx *c, hperm_status s, const std::string &msg) {
+    if (c) c->dev.last_error = msg;
+    return s;
+}
+
+hperm_status hip_check(Dev *c, hipError_t e, const char *what) {
     if (e == hipSuccess) return HPERM_OK;
     if (e == hipErrorOutOfMemory)
         return set_error(c, HPERM_E_NOMEM, std::string(what) + ": " + hipGetErrorString(e));
@@ -54,7 +59,7 @@ static size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Make buffer id hold at least `bytes`. With an arena, every buffer is a slice of it and a
 // growing buffer re-lays out all slices (their contents are transient per call).
-hperm_status ensure_buf(hperm_ctx *c, BufId id, size_t bytes) {
+hperm_status ensure_buf(Dev *c, BufId id, size_t bytes) {
     bytes = align_up(std::max<size_t>(bytes, kAlign));
     DevBuf &b = c->buf[id];
     if (b.ptr && b.cap >= bytes) return HPERM_OK;
@@ -66,14 +71,17 @@ hperm_status ensure_buf(hperm_ctx *c, BufId id, size_t bytes) {
             return set_error(c, HPERM_E_NOMEM, "the caller's arena is too small");
         }
         size_t off = 0;
+        bool moved = false;
         for (int k = 0; k < B_COUNT; ++k) {
             const size_t cap = (k == id) ? bytes : c->buf[k].cap;
-            c->buf[k].ptr = cap ? (char *)c->arena + off : nullptr;
+            void *p = cap ? (char *)c->arena + off : nullptr;
+            if ((k == B_DESC || k == B_DATA) && p != c->buf[k].ptr) moved = true;
+            c->buf[k].ptr = p;
             c->buf[k].cap = cap;
             c->buf[k].owned = false;
             off += cap;
         }
-        c->resident_jobs = 0;
+        if (moved) c->resident_jobs = 0;
         return HPERM_OK;
     }
     if (b.ptr && b.owned) {
@@ -95,7 +103,7 @@ hperm_status ensure_buf(hperm_ctx *c, BufId id, size_t bytes) {
     return HPERM_OK;
 }
 
-hperm_status upload_jobs(hperm_ctx *c, hperm_jobs *j) {
+hperm_status upload_jobs(Dev *c, hperm_jobs *j) {
     if (c->resident_jobs == j->id && j->id != 0) return HPERM_OK;
     const size_t nd = j->tab.desc.size();
     const size_t nw = j->tab.data.size() + 64;   // padding: lanes may read a few words past a block
@@ -121,7 +129,7 @@ hperm_status upload_jobs(hperm_ctx *c, hperm_jobs *j) {
     return HPERM_OK;
 }
 
-hperm_status estimate_jobs(hperm_ctx *c, hperm_jobs *j, int trials, uint64_t seed) {
+hperm_status estimate_jobs(Dev *c, hperm_jobs *j, int trials, uint64_t seed) {
     if (trials < 1 || trials > 4096) return set_error(c, HPERM_E_INVALID, "trials must be in [1, 4096]");
     const size_t nd = j->tab.desc.size();
     j->keys.assign(nd, -INFINITY);
@@ -352,7 +360,7 @@ static void fill_result(const U512 &v, hperm_result *r) {
     r->nlimb = v.nlimb();
 }
 
-static hperm_status ensure_launch_events(hperm_ctx *c, size_t pairs) {
+static hperm_status ensure_launch_events(Dev *c, size_t pairs) {
     while (c->launch_ev.size() < 2 * pairs) {
         hipEvent_t e;
         hperm_status s = hip_check(c, hipEventCreate(&e), "hipEventCreate");
@@ -362,179 +370,197 @@ static hperm_status ensure_launch_events(hperm_ctx *c, size_t pairs) {
     return HPERM_OK;
 }
 
-hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
-                      hperm_result *per_job, hperm_result *totals, double *t_rnw) {
+hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool want_per_job) {
     const size_t nd = j->tab.desc.size();
     const int np = j->tab.n_problems;
     if (order < 0 || order > 3) return set_error(c, HPERM_E_INVALID, "unknown order");
     if ((order == HPERM_ORDER_ESTIMATE) && !j->has_keys && nd)
         return set_error(c, HPERM_E_INVALID, "ORDER_ESTIMATE needs hperm_estimate first");
+    c->want_per_job = want_per_job;
+    c->persistent = persistent != 0;
+    c->launches.clear();
+    if (!nd) return HPERM_OK;
+    hperm_status s;
+    if (!c->ev0) {
+        s = hip_check(c, hipEventCreate(&c->ev0), "hipEventCreate");
+        if (s) return s;
+        s = hip_check(c, hipEventCreate(&c->ev1), "hipEventCreate");
+        if (s) return s;
+    }
+    // per-mode chunk sizes: the persistent queue uses the jobs' own chunks
+    std::vector<JobDesc> &desc_plain = c->h_desc_plain;
+    if (!persistent) {
+        desc_plain = j->tab.desc;
+        for (auto &d : desc_plain) d.chunk_log2 = (uint8_t)plain_chunk(d.m, c->opts.chunk_log2);
+    }
+    const std::vector<JobDesc> &dsc = persistent ? j->tab.desc : desc_plain;
+    // queue groups by (ring, bucket), each in the chosen job order
+    const std::vector<uint32_t> ord = job_order(j, order, c->opts.seed);
+    std::vector<uint32_t> &queue = c->h_queue;
+    std::vector<uint64_t> &item_end = c->h_items;
+    queue.clear();
+    item_end.clear();
+    struct Group { int ring, bucket; size_t off, n; uint64_t items; };
+    std::vector<Group> groups;
+    queue.reserve(nd);
+    item_end.reserve(nd);
+    for (int b = 3; b >= 0; --b)
+        for (int r = HP_NRING - 1; r >= 0; --r) {
+            Group g{r, b, queue.size(), 0, 0};
+            uint64_t acc = 0;
+            for (uint32_t k : ord) {
+                const JobDesc &d = dsc[k];
+                if (d.arith != r || bucket_of(d.m) != b) continue;
+                acc += items_of(d.m, d.chunk_log2);
+                queue.push_back(k);
+                item_end.push_back(acc);
+            }
+            g.n = queue.size() - g.off;
+            g.items = acc;
+            if (g.n) groups.push_back(g);
+        }
+    s = upload_jobs(c, j);
+    if (s) return s;
+    s = ensure_buf(c, B_QUEUE, nd * sizeof(uint32_t));
+    if (s) return s;
+    s = ensure_buf(c, B_ITEMS, nd * sizeof(uint64_t));
+    if (s) return s;
+    s = ensure_buf(c, B_ACCS, nd * sizeof(JobAcc));
+    if (s) return s;
+    s = ensure_buf(c, B_HEAD, 64 * sizeof(unsigned long long));
+    if (s) return s;
+    s = ensure_buf(c, B_PROB, (size_t)np * sizeof(ProbAcc));
+    if (s) return s;
+    if (!persistent) {
+        s = ensure_buf(c, B_DESC_PLAIN, nd * sizeof(JobDesc));
+        if (s) return s;
+    }
+    if (c->resident_jobs != j->id) {   // an arena re-layout moved the job table: upload again
+        s = upload_jobs(c, j);
+        if (s) return s;
+    }
+    const JobDesc *d_desc = (const JobDesc *)c->buf[B_DESC].ptr;
+    if (!persistent) {
+        s = hip_check(c, hipMemcpyAsync(c->buf[B_DESC_PLAIN].ptr, desc_plain.data(),
+                                        nd * sizeof(JobDesc), hipMemcpyHostToDevice, c->stream),
+                      "upload plain descriptors");
+        if (s) return s;
+        d_desc = (const JobDesc *)c->buf[B_DESC_PLAIN].ptr;
+    }
+    s = hip_check(c, hipMemcpyAsync(c->buf[B_QUEUE].ptr, queue.data(), nd * 4,
+                                    hipMemcpyHostToDevice, c->stream), "upload queue");
+    if (s) return s;
+    s = hip_check(c, hipMemcpyAsync(c->buf[B_ITEMS].ptr, item_end.data(), nd * 8,
+                                    hipMemcpyHostToDevice, c->stream), "upload item ends");
+    if (s) return s;
+    JobAcc *accs = (JobAcc *)c->buf[B_ACCS].ptr;
+    unsigned long long *head = (unsigned long long *)c->buf[B_HEAD].ptr;
+    s = hip_check(c, launch_fill_u64((unsigned long long *)accs, nd * (sizeof(JobAcc) / 8), 0ull,
+                                     c->stream), "clear accumulators");
+    if (s) return s;
+    s = hip_check(c, launch_fill_u64(head, 64, 0ull, c->stream), "clear queue heads");
+    if (s) return s;
+    const uint32_t *d_data = (const uint32_t *)c->buf[B_DATA].ptr;
+    s = hip_check(c, hipEventRecord(c->ev0, c->stream), "event");
+    if (s) return s;
+    if (persistent) {
+        s = ensure_launch_events(c, groups.size());
+        if (s) return s;
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+            const Group &g = groups[gi];
+            hperm_launch_stat st{};
+            st.ring = g.ring;
+            st.bucket = g.bucket;
+            st.n_jobs = (int32_t)g.n;
+            st.persistent = 1;
+            st.items = g.items;
+            for (size_t q = g.off; q < g.off + g.n; ++q) {
+                const JobDesc &d = dsc[queue[q]];
+                const uint64_t t = 1ull << (d.m - 1);
+                const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2);
+                st.terms += t;
+                st.row_updates += (uint64_t)wk.updates;
+                st.alg_slots += wk.mults * ring_mul_slots(d.arith) + (double)t * ring_add_slots(d.arith) + wk.updates;
+            }
+            c->launches.push_back(st);
+            s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
+            if (s) return s;
+            s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, d_desc, d_data,
+                                                   (const uint32_t *)c->buf[B_QUEUE].ptr + g.off,
+                                                   (const uint64_t *)c->buf[B_ITEMS].ptr + g.off,
+                                                   (uint32_t)g.n, g.items, head + gi, accs, 0, c->stream),
+                          "rnw_persistent launch");
+            if (s) return s;
+            s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi + 1], c->stream), "event");
+            if (s) return s;
+        }
+    } else {
+        // one launch per job, natural order
+        for (size_t k = 0; k < nd; ++k) {
+            const JobDesc &d = desc_plain[k];
+            s = hip_check(c, launch_rnw_single(d.arith, bucket_of(d.m), d_desc, d_data, (uint32_t)k,
+                                               items_of(d.m, d.chunk_log2), accs, c->stream),
+                          "rnw_single launch");
+            if (s) return s;
+        }
+        hperm_launch_stat st{};
+        st.ring = -1;
+        st.bucket = -1;
+        st.n_jobs = (int32_t)nd;
+        for (size_t k = 0; k < nd; ++k) {
+            const JobDesc &d = desc_plain[k];
+            const uint64_t t = 1ull << (d.m - 1);
+            const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2);
+            st.items += items_of(d.m, d.chunk_log2);
+            st.terms += t;
+            st.row_updates += (uint64_t)wk.updates;
+            st.alg_slots += wk.mults * ring_mul_slots(d.arith) + (double)t * ring_add_slots(d.arith) + wk.updates;
+        }
+        c->launches.push_back(st);   // all single launches as one record (ms = whole span)
+    }
+    s = hip_check(c, hipEventRecord(c->ev1, c->stream), "event");
+    if (s) return s;
+    if (want_per_job) {
+        c->host_acc.resize(nd);
+        return hip_check(c, hipMemcpyAsync(c->host_acc.data(), accs, nd * sizeof(JobAcc),
+                                           hipMemcpyDeviceToHost, c->stream), "download job values");
+    }
+    // Step 4 on the device: one accumulator per problem, staged in pinned host memory
+    ProbAcc *pd = (ProbAcc *)c->buf[B_PROB].ptr;
+    s = hip_check(c, launch_fill_u64((unsigned long long *)pd, (uint64_t)np * (sizeof(ProbAcc) / 8), 0ull,
+                                     c->stream), "clear problem accumulators");
+    if (s) return s;
+    s = hip_check(c, launch_recombine((const JobDesc *)c->buf[B_DESC].ptr, accs, (uint32_t)nd, pd, c->stream),
+                  "recombine launch");
+    if (s) return s;
+    if (c->host_prob_cap < (size_t)np) {
+        if (c->host_prob) (void)hipHostFree(c->host_prob);
+        c->host_prob = nullptr;
+        c->host_prob_cap = 0;
+        s = hip_check(c, hipHostMalloc((void **)&c->host_prob, (size_t)np * sizeof(ProbAcc), hipHostMallocDefault),
+                      "hipHostMalloc");
+        if (s) return s;
+        c->host_prob_cap = (size_t)np;
+    }
+    return hip_check(c, hipMemcpyAsync(c->host_prob, pd, np * sizeof(ProbAcc), hipMemcpyDeviceToHost,
+                                       c->stream), "download problem values");
+}
+
+hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_result *totals,
+                        double *t_rnw) {
+    const size_t nd = j->tab.desc.size();
+    const int np = j->tab.n_problems;
     std::vector<U512> sums(np);
     std::vector<int> nj(np, 0), maxm(np, 0), amask(np, 0);
     std::vector<uint64_t> terms(np, 0);
     *t_rnw = 0.0;
     if (nd) {
-        hperm_status s;
-        // per-mode chunk sizes: the persistent queue uses the jobs' own chunks
-        std::vector<JobDesc> desc_plain;
-        if (!persistent) {
-            desc_plain = j->tab.desc;
-            for (auto &d : desc_plain) d.chunk_log2 = (uint8_t)plain_chunk(d.m, c->opts.chunk_log2);
-        }
-        const std::vector<JobDesc> &dsc = persistent ? j->tab.desc : desc_plain;
-        // queue groups by (ring, bucket), each in the chosen job order
-        const std::vector<uint32_t> ord = job_order(j, order, c->opts.seed);
-        std::vector<uint32_t> queue;
-        std::vector<uint64_t> item_end;
-        struct Group { int ring, bucket; size_t off, n; uint64_t items; };
-        std::vector<Group> groups;
-        queue.reserve(nd);
-        item_end.reserve(nd);
-        for (int b = 3; b >= 0; --b)
-            for (int r = HP_NRING - 1; r >= 0; --r) {
-                Group g{r, b, queue.size(), 0, 0};
-                uint64_t acc = 0;
-                for (uint32_t k : ord) {
-                    const JobDesc &d = dsc[k];
-                    if (d.arith != r || bucket_of(d.m) != b) continue;
-                    acc += items_of(d.m, d.chunk_log2);
-                    queue.push_back(k);
-                    item_end.push_back(acc);
-                }
-                g.n = queue.size() - g.off;
-                g.items = acc;
-                if (g.n) groups.push_back(g);
-            }
-        s = upload_jobs(c, j);
-        if (s) return s;
-        s = ensure_buf(c, B_QUEUE, nd * sizeof(uint32_t));
-        if (s) return s;
-        s = ensure_buf(c, B_ITEMS, nd * sizeof(uint64_t));
-        if (s) return s;
-        s = ensure_buf(c, B_ACCS, nd * sizeof(JobAcc));
-        if (s) return s;
-        s = ensure_buf(c, B_HEAD, 64 * sizeof(unsigned long long));
-        if (s) return s;
-        if (!persistent) {
-            s = ensure_buf(c, B_DESC_PLAIN, nd * sizeof(JobDesc));
-            if (s) return s;
-        }
-        if (c->resident_jobs != j->id) {
-            s = upload_jobs(c, j);
-            if (s) return s;
-        }
-        const JobDesc *d_desc = (const JobDesc *)c->buf[B_DESC].ptr;
-        if (!persistent) {
-            s = hip_check(c, hipMemcpyAsync(c->buf[B_DESC_PLAIN].ptr, desc_plain.data(),
-                                            nd * sizeof(JobDesc), hipMemcpyHostToDevice, c->stream),
-                          "upload plain descriptors");
-            if (s) return s;
-            d_desc = (const JobDesc *)c->buf[B_DESC_PLAIN].ptr;
-        }
-        s = hip_check(c, hipMemcpyAsync(c->buf[B_QUEUE].ptr, queue.data(), nd * 4,
-                                        hipMemcpyHostToDevice, c->stream), "upload queue");
-        if (s) return s;
-        s = hip_check(c, hipMemcpyAsync(c->buf[B_ITEMS].ptr, item_end.data(), nd * 8,
-                                        hipMemcpyHostToDevice, c->stream), "upload item ends");
-        if (s) return s;
-        JobAcc *accs = (JobAcc *)c->buf[B_ACCS].ptr;
-        unsigned long long *head = (unsigned long long *)c->buf[B_HEAD].ptr;
-        s = hip_check(c, launch_fill_u64((unsigned long long *)accs, nd * (sizeof(JobAcc) / 8), 0ull,
-                                         c->stream), "clear accumulators");
-        if (s) return s;
-        s = hip_check(c, launch_fill_u64(head, 64, 0ull, c->stream), "clear queue heads");
-        if (s) return s;
-        const uint32_t *d_data = (const uint32_t *)c->buf[B_DATA].ptr;
-        s = hip_check(c, hipEventRecord(c->ev0, c->stream), "event");
-        if (s) return s;
-        c->launches.clear();
-        if (persistent) {
-            s = ensure_launch_events(c, groups.size());
-            if (s) return s;
-            for (size_t gi = 0; gi < groups.size(); ++gi) {
-                const Group &g = groups[gi];
-                hperm_launch_stat st{};
-                st.ring = g.ring;
-                st.bucket = g.bucket;
-                st.n_jobs = (int32_t)g.n;
-                st.persistent = 1;
-                st.items = g.items;
-                for (size_t q = g.off; q < g.off + g.n; ++q) {
-                    const JobDesc &d = dsc[queue[q]];
-                    const uint64_t t = 1ull << (d.m - 1);
-                    const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2);
-                    st.terms += t;
-                    st.row_updates += (uint64_t)wk.updates;
-                    st.alg_slots += wk.mults * ring_mul_slots(d.arith) + (double)t * ring_add_slots(d.arith) + wk.updates;
-                }
-                c->launches.push_back(st);
-                s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
-                if (s) return s;
-                s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, d_desc, d_data,
-                                                       (const uint32_t *)c->buf[B_QUEUE].ptr + g.off,
-                                                       (const uint64_t *)c->buf[B_ITEMS].ptr + g.off,
-                                                       (uint32_t)g.n, g.items, head + gi, accs, 0,
-                                                       c->stream),
-                              "rnw_persistent launch");
-                if (s) return s;
-                s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi + 1], c->stream), "event");
-                if (s) return s;
-            }
-        } else {
-            // one launch per job, natural order
-            for (size_t k = 0; k < nd; ++k) {
-                const JobDesc &d = desc_plain[k];
-                s = hip_check(c, launch_rnw_single(d.arith, bucket_of(d.m), d_desc, d_data, (uint32_t)k,
-                                                   items_of(d.m, d.chunk_log2), accs, c->stream),
-                              "rnw_single launch");
-                if (s) return s;
-            }
-            hperm_launch_stat st{};
-            st.ring = -1;
-            st.bucket = -1;
-            st.n_jobs = (int32_t)nd;
-            for (size_t k = 0; k < nd; ++k) {
-                const JobDesc &d = desc_plain[k];
-                const uint64_t t = 1ull << (d.m - 1);
-                const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2);
-                st.items += items_of(d.m, d.chunk_log2);
-                st.terms += t;
-                st.row_updates += (uint64_t)wk.updates;
-                st.alg_slots += wk.mults * ring_mul_slots(d.arith) + (double)t * ring_add_slots(d.arith) + wk.updates;
-            }
-            c->launches.push_back(st);   // all single launches as one record (ms = whole span)
-        }
-        s = hip_check(c, hipEventRecord(c->ev1, c->stream), "event");
-        if (s) return s;
-        std::vector<JobAcc> host;
-        std::vector<ProbAcc> pacc;
-        if (per_job) {
-            host.resize(nd);
-            s = hip_check(c, hipMemcpyAsync(host.data(), accs, nd * sizeof(JobAcc), hipMemcpyDeviceToHost,
-                                            c->stream), "download job values");
-            if (s) return s;
-        } else {
-            // Step 4 on the device: one accumulator per problem
-            s = ensure_buf(c, B_PROB, (size_t)np * sizeof(ProbAcc));
-            if (s) return s;
-            ProbAcc *pd = (ProbAcc *)c->buf[B_PROB].ptr;
-            s = hip_check(c, launch_fill_u64((unsigned long long *)pd, (uint64_t)np * (sizeof(ProbAcc) / 8), 0ull,
-                                             c->stream), "clear problem accumulators");
-            if (s) return s;
-            s = hip_check(c, launch_recombine((const JobDesc *)c->buf[B_DESC].ptr, accs, (uint32_t)nd, pd,
-                                              c->stream), "recombine launch");
-            if (s) return s;
-            pacc.resize(np);
-            s = hip_check(c, hipMemcpyAsync(pacc.data(), pd, np * sizeof(ProbAcc), hipMemcpyDeviceToHost,
-                                            c->stream), "download problem values");
-            if (s) return s;
-        }
-        s = hip_check(c, hipStreamSynchronize(c->stream), "R-NW");
+        hperm_status s = hip_check(c, hipStreamSynchronize(c->stream), "R-NW");
         if (s) return s;
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
         *t_rnw = ms * 1e-3;
-        if (persistent) {
+        if (c->persistent) {
             for (size_t gi = 0; gi < c->launches.size(); ++gi) {
                 float lm = 0.0f;
                 (void)hipEventElapsedTime(&lm, c->launch_ev[2 * gi], c->launch_ev[2 * gi + 1]);
@@ -551,24 +577,26 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
             amask[p] |= 1 << (d.arith + 1);
             terms[p] += 1ull << (d.m - 1);
         }
-        if (per_job) {
+        if (c->want_per_job) {
             for (size_t k = 0; k < nd; ++k) {
                 const JobDesc &d = j->tab.desc[k];
                 U512 v;
-                if (!job_value(d, host[k], j->tab.log2_bound[k], &v))
+                if (!job_value(d, c->host_acc[k], j->tab.log2_bound[k], &v))
                     return set_error(c, HPERM_E_INTERNAL, "a job value failed its integrity check (job " +
                                                               std::to_string(k) + ")");
                 sums[d.problem].add(v);
-                memset(&per_job[k], 0, sizeof(hperm_result));
-                fill_result(v, &per_job[k]);
-                per_job[k].n_jobs = 1;
-                per_job[k].max_m = d.m;
-                per_job[k].arith_mask = 1 << (d.arith + 1);
-                per_job[k].subset_terms = 1ull << (d.m - 1);
+                if (per_job) {
+                    memset(&per_job[k], 0, sizeof(hperm_result));
+                    fill_result(v, &per_job[k]);
+                    per_job[k].n_jobs = 1;
+                    per_job[k].max_m = d.m;
+                    per_job[k].arith_mask = 1 << (d.arith + 1);
+                    per_job[k].subset_terms = 1ull << (d.m - 1);
+                }
             }
         } else {
             for (int p = 0; p < np; ++p) {
-                const ProbAcc &q = pacc[p];
+                const ProbAcc &q = c->host_prob[p];
                 if (q.err)
                     return set_error(c, HPERM_E_INTERNAL, "a job value of problem " + std::to_string(p) +
                                                               " failed its integrity check");
@@ -606,6 +634,30 @@ hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
         r.t_rnw_s = *t_rnw;
     }
     return HPERM_OK;
+}
+
+hperm_status run_jobs(Dev *c, hperm_jobs *j, int order, int persistent, hperm_result *per_job,
+                      hperm_result *totals, double *t_rnw) {
+    hperm_status s = run_enqueue(c, j, order, persistent, per_job != nullptr);
+    if (s) return s;
+    return run_finish(c, j, per_job, totals, t_rnw);
+}
+
+void dev_release(Dev *d) {
+    if (d->stream) (void)hipStreamSynchronize(d->stream);
+    for (auto &b : d->buf) {
+        if (b.ptr && b.owned) (void)hipFree(b.ptr);
+        b = DevBuf();
+    }
+    for (hipEvent_t e : d->launch_ev) (void)hipEventDestroy(e);
+    d->launch_ev.clear();
+    if (d->ev0) (void)hipEventDestroy(d->ev0);
+    if (d->ev1) (void)hipEventDestroy(d->ev1);
+    d->ev0 = d->ev1 = nullptr;
+    if (d->host_prob) (void)hipHostFree(d->host_prob);
+    d->host_prob = nullptr;
+    d->host_prob_cap = 0;
+    d->resident_jobs = 0;
 }
 
 }  // namespace hp
@@ -675,11 +727,8 @@ hperm_status hperm_ctx_create(const hperm_opts *opts, void *stream, hperm_ctx **
         }
         c->own_stream = true;
     }
-    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
-        if (c->own_stream) (void)hipStreamDestroy(c->stream);
-        delete c;
-        return HPERM_E_DEVICE;
-    }
+    c->dev.stream = c->stream;
+    c->dev.opts = c->opts;
     *out = c;
     return HPERM_OK;
 }
@@ -709,12 +758,7 @@ void hperm_ctx_destroy(hperm_ctx *c) {
         return;
     }
     hp::serve_shutdown(c);
-    (void)hipStreamSynchronize(c->stream);
-    for (auto &b : c->buf)
-        if (b.ptr && b.owned) (void)hipFree(b.ptr);
-    for (hipEvent_t e : c->launch_ev) (void)hipEventDestroy(e);
-    if (c->ev0) (void)hipEventDestroy(c->ev0);
-    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    hp::dev_release(&c->dev);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -722,6 +766,7 @@ void hperm_ctx_destroy(hperm_ctx *c) {
 hperm_status hperm_ctx_set_opts(hperm_ctx *c, const hperm_opts *o) {
     if (!c || !o) return HPERM_E_INVALID;
     if (const char *why = check_opts(o)) return set_error(c, HPERM_E_INVALID, why);
+    if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
     c->opts = *o;
     return HPERM_OK;
 }
@@ -730,18 +775,19 @@ hperm_status hperm_ctx_set_arena(hperm_ctx *c, void *dev_ptr, size_t bytes) {
     if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
     if (!c) return HPERM_E_INVALID;
     if (dev_ptr && bytes < 4096) return set_error(c, HPERM_E_INVALID, "arena too small");
+    if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
     (void)hipStreamSynchronize(c->stream);
-    for (auto &b : c->buf) {
+    for (auto &b : c->dev.buf) {
         if (b.ptr && b.owned) (void)hipFree(b.ptr);
         b = DevBuf();
     }
-    c->arena = dev_ptr;
-    c->arena_bytes = dev_ptr ? bytes : 0;
-    c->resident_jobs = 0;
+    c->dev.arena = dev_ptr;
+    c->dev.arena_bytes = dev_ptr ? bytes : 0;
+    c->dev.resident_jobs = 0;
     return HPERM_OK;
 }
 
-size_t hperm_ctx_arena_required(const hperm_ctx *c) { return c ? c->arena_required : 0; }
+size_t hperm_ctx_arena_required(const hperm_ctx *c) { return c ? c->dev.arena_required : 0; }
 
 static hperm_status expand_batch(hperm_ctx *c, int32_t count, const int32_t *n, const int64_t *rp_off,
                                  const int64_t *nz_off, const int32_t *row_ptr, const int32_t *col_idx,
@@ -771,7 +817,8 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
     if (!c || !out) return HPERM_E_INVALID;
     if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
     std::lock_guard<std::mutex> lk(c->call_mu);
-    c->last_error.clear();
+    c->dev.last_error.clear();
+    c->dev.opts = c->opts;
     const double t0 = now_s();
     hperm_jobs j;
     hperm_status s = expand_batch(c, count, n, rp_off, nz_off, row_ptr, col_idx, val, &j);
@@ -779,12 +826,12 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
     const double t1 = now_s();
     double t_est = 0.0;
     if (!j.tab.desc.empty() && (c->opts.order == HPERM_ORDER_ESTIMATE || c->opts.order == HPERM_ORDER_EXACT_COST)) {
-        s = estimate_jobs(c, &j, c->opts.trials, c->opts.seed);
+        s = estimate_jobs(&c->dev, &j, c->opts.trials, c->opts.seed);
         if (s) return s;
         t_est = now_s() - t1;
     }
     double t_rnw = 0.0;
-    s = run_jobs(c, &j, c->opts.order, c->opts.persistent, nullptr, out, &t_rnw);
+    s = run_jobs(&c->dev, &j, c->opts.order, c->opts.persistent, nullptr, out, &t_rnw);
     if (s) return s;
     const double t2 = now_s();
     for (int k = 0; k < count; ++k) {
@@ -874,8 +921,10 @@ hperm_status hperm_jobs_describe(const hperm_jobs *j, int32_t *m, int32_t *probl
 hperm_status hperm_estimate(hperm_ctx *c, hperm_jobs *j, int32_t trials, uint64_t seed, float *keys) {
     if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
     if (!c || !j) return HPERM_E_INVALID;
+    if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
     std::lock_guard<std::mutex> lk(c->call_mu);
-    hperm_status s = estimate_jobs(c, j, trials, seed);
+    c->dev.opts = c->opts;
+    hperm_status s = estimate_jobs(&c->dev, j, trials, seed);
     if (s) return s;
     if (keys) std::copy(j->keys.begin(), j->keys.end(), keys);
     return HPERM_OK;
@@ -885,10 +934,12 @@ hperm_status hperm_run_jobs(hperm_ctx *c, hperm_jobs *j, int32_t order, int32_t 
                             hperm_result *per_job, hperm_result *totals) {
     if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
     if (!c || !j || !totals) return HPERM_E_INVALID;
+    if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
     std::lock_guard<std::mutex> lk(c->call_mu);
     const double t0 = now_s();
     double t_rnw = 0.0;
-    hperm_status s = run_jobs(c, j, order, persistent, per_job, totals, &t_rnw);
+    c->dev.opts = c->opts;
+    hperm_status s = run_jobs(&c->dev, j, order, persistent, per_job, totals, &t_rnw);
     if (s) return s;
     const double t1 = now_s();
     for (int p = 0; p < j->tab.n_problems; ++p) totals[p].t_total_s = t1 - t0;
@@ -899,9 +950,9 @@ void hperm_jobs_free(hperm_jobs *j) { delete j; }
 
 hperm_status hperm_last_launches(const hperm_ctx *c, hperm_launch_stat *out, int32_t max, int32_t *n) {
     if (!c || !n || max < 0 || (max > 0 && !out)) return HPERM_E_INVALID;
-    const int32_t k = (int32_t)std::min<size_t>((size_t)max, c->launches.size());
-    for (int32_t i = 0; i < k; ++i) out[i] = c->launches[i];
-    *n = (int32_t)c->launches.size();
+    const int32_t k = (int32_t)std::min<size_t>((size_t)max, c->dev.launches.size());
+    for (int32_t i = 0; i < k; ++i) out[i] = c->dev.launches[i];
+    *n = (int32_t)c->dev.launches.size();
     return HPERM_OK;
 }
 
@@ -921,6 +972,6 @@ const char *hperm_status_string(hperm_status s) {
     return "unknown status";
 }
 
-const char *hperm_last_error(const hperm_ctx *c) { return c ? c->last_error.c_str() : ""; }
+const char *hperm_last_error(const hperm_ctx *c) { return c ? c->dev.last_error.c_str() : ""; }
 
 }  // extern "C"

@@ -34,6 +34,38 @@ struct hperm_jobs {
     uint64_t id = 0;           // identity for device residency
 };
 
+namespace hp {
+
+// One independent set of device buffers, stream and events on which the GPU pipeline runs.
+// A context owns one; the serving loop gives every batch in flight its own.
+struct Dev {
+    hperm_opts opts{};                 // options of the current run (seed, plain chunk)
+    hipStream_t stream = nullptr;
+    DevBuf buf[B_COUNT];
+    void *arena = nullptr;             // when set, every buffer is a slice of [arena, +arena_bytes)
+    size_t arena_bytes = 0;
+    size_t arena_required = 0;
+    uint64_t resident_jobs = 0;        // id of the job table currently in B_DESC/B_DATA
+    std::string last_error;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hperm_launch_stat> launches;   // R-NW launches of the last run
+    std::vector<hipEvent_t> launch_ev;         // event pairs for the launches (grown on demand)
+    // state between run_enqueue and run_finish
+    bool want_per_job = false;
+    bool persistent = true;
+    std::vector<JobAcc> host_acc;              // per-job accumulators (per-job results only)
+    ProbAcc *host_prob = nullptr;              // pinned, per-problem accumulators
+    size_t host_prob_cap = 0;
+    std::vector<uint32_t> h_queue;             // host sources of the run's uploads
+    std::vector<uint64_t> h_items;
+    std::vector<JobDesc> h_desc_plain;
+};
+
+// Release the buffers (owned ones freed), the events and the pinned staging memory.
+void dev_release(Dev *d);
+
+}  // namespace hp
+
 struct hperm_ctx {
     hperm_opts opts;
     hipStream_t stream = nullptr;
@@ -41,29 +73,27 @@ struct hperm_ctx {
     bool host_only = false;   // created by hperm_ctx_create_host: no device, no stream
     int device = 0;
     int num_cus = 0;
-    hp::DevBuf buf[hp::B_COUNT];
-    void *arena = nullptr;
-    size_t arena_bytes = 0;
-    size_t arena_required = 0;
-    uint64_t resident_jobs = 0;   // id of the job table currently in B_DESC/B_DATA
-    std::string last_error;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hp::Dev dev;              // the context's own pipeline buffers
     hp::Serving *serving = nullptr;   // owned; created by hperm_serve_start
-    std::vector<hperm_launch_stat> launches;   // R-NW launches of the last call
-    std::vector<hipEvent_t> launch_ev;         // event pairs for the launches (grown on demand)
-    std::mutex call_mu;   // serialises GPU pipelines of this context (serving thread vs callers)
+    std::mutex call_mu;       // serialises GPU pipelines of this context
 };
 
 namespace hp {
 
 // Pipeline steps shared by the blocking calls and the serving loop (api.cpp).
-hperm_status ensure_buf(hperm_ctx *c, BufId id, size_t bytes);
-hperm_status upload_jobs(hperm_ctx *c, hperm_jobs *j);
-hperm_status estimate_jobs(hperm_ctx *c, hperm_jobs *j, int trials, uint64_t seed);
-hperm_status run_jobs(hperm_ctx *c, hperm_jobs *j, int order, int persistent,
-                      hperm_result *per_job, hperm_result *totals, double *t_rnw);
+hperm_status ensure_buf(Dev *c, BufId id, size_t bytes);
+hperm_status upload_jobs(Dev *c, hperm_jobs *j);
+hperm_status estimate_jobs(Dev *c, hperm_jobs *j, int trials, uint64_t seed);
+// Launch steps 4-6 of all jobs on c->stream without waiting (results staged in c).
+hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool want_per_job);
+// Wait for c->stream and turn the staged accumulators into results.
+hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_result *totals,
+                        double *t_rnw);
+hperm_status run_jobs(Dev *c, hperm_jobs *j, int order, int persistent, hperm_result *per_job,
+                      hperm_result *totals, double *t_rnw);
+hperm_status set_error(Dev *c, hperm_status s, const std::string &msg);
 hperm_status set_error(hperm_ctx *c, hperm_status s, const std::string &msg);
-hperm_status hip_check(hperm_ctx *c, hipError_t e, const char *what);
+hperm_status hip_check(Dev *c, hipError_t e, const char *what);
 ExpandParams expand_params(const hperm_opts &o);
 void serve_shutdown(hperm_ctx *c);   // serve.cpp: stop the serving loop if running
 uint64_t next_jobs_id();

@@ -134,6 +134,13 @@ def test_host_only_context_refuses_gpu_calls(hp):
     with pytest.raises(hp.HpermError) as e:
         ctx.run(J)
     assert e.value.status == -3
+    with pytest.raises(hp.HpermError) as e:
+        ctx.serve_start(4, 1 << 20)
+    assert e.value.status == -3
+    # serving calls on a context that is not serving are refused, not crashed
+    assert hp._lib.hperm_poll(ctx.handle, 1, None) == -1
+    assert hp._lib.hperm_cancel(ctx.handle, 1) == -1
+    assert hp._lib.hperm_serve_stop(ctx.handle) == -1
 
 
 def test_zero_and_empty_problems_need_no_jobs(hp):
