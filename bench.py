@@ -76,6 +76,16 @@ def cpu_baseline(m_cut: int, budget_s: float = 20.0):
                       f"counted as 2^(m-1) per job like the GPU path"}
 
 
+def copy_probe(nbytes: int = 256 << 20, reps: int = 3):
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "reps": reps}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,7 +95,13 @@ def main():
     ap.add_argument("--trials", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a device-to-device copy of 256 MiB three times (the reference kernel "
+                         "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path shards "
               f"its job list across GPUs only in design)", file=sys.stderr)
@@ -129,11 +145,17 @@ def main():
         ctx.estimate(jobs, args.trials, 1)
         ctx.run(jobs, "estimate", True)
     launches = []
+    est_s = run_s = 0.0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ta = time.perf_counter()
         ctx.estimate(jobs, args.trials, 1)
-        tot, _, _ = ctx.run(jobs, "estimate", True)
+        tb = time.perf_counter()
+        tot, _, res = ctx.run(jobs, "estimate", True)
+        tc = time.perf_counter()
+        est_s += tb - ta
+        run_s += tc - tb
         launches.append(ctx.last_launches())
     torch.cuda.synchronize()
     step_s = (time.perf_counter() - t0) / args.steps
@@ -204,6 +226,9 @@ def main():
         "per_a_wall_ms_per_problem": e2e * 1e3 / len(mats),
         "host_expand_ms_batch": exp_s * 1e3,
         "rnw_ms_per_step": rnw_ms,
+        "step_breakdown_ms": {"estimate_call": est_s * 1e3 / args.steps, "run_call": run_s * 1e3 / args.steps,
+                              "rnw_kernels": rnw_ms,
+                              "run_host_and_other": run_s * 1e3 / args.steps - rnw_ms},
         "lpt_persistent_terms_per_s": lpt_rate,
         "lpt_vs_plain": (lpt_rate / plain) if plain else None,
         "verified_vs_oracle": verified,

@@ -78,6 +78,9 @@ typedef struct hperm_opts {
     int32_t persistent;   /* 1: one persistent launch over the queue (default);
                              0: one launch per job (the plain comparator) */
     int32_t host_threads; /* expansion threads (0 = hardware threads, at most 64) */
+    int32_t max_table_mib;/* host job-table limit per expansion call in MiB (0 = 4096): an
+                             expansion that would outgrow it stops with HPERM_E_NOMEM instead
+                             of exhausting host memory (raise m_cut to get fewer jobs) */
 } hperm_opts;
 
 /* Result of one permanent. The value is non-negative: magnitude limbs, little-endian. */
@@ -131,7 +134,8 @@ size_t hperm_ctx_arena_required(const hperm_ctx *ctx);
  * n = 0 gives 1; a zero row or column gives 0 without GPU work.
  * Errors: HPERM_E_INVALID (n < 0 or n > 128, malformed CSR); HPERM_E_RANGE (an expanded
  * entry reaches 2^22 or a row sum 2^24, or the proven bound on per(A) exceeds 2^180);
- * HPERM_E_DEVICE; HPERM_E_NOMEM; HPERM_E_INTERNAL. */
+ * HPERM_E_DEVICE; HPERM_E_NOMEM (device memory, or the job table outgrows max_table_mib);
+ * HPERM_E_INTERNAL. */
 hperm_status hperm_permanent_csr(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
                                  const int32_t *col_idx, const uint32_t *val, hperm_result *out);
 

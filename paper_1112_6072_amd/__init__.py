@@ -37,7 +37,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("m_cut", ctypes.c_int32), ("m_cap", ctypes.c_int32), ("s_leaf", ctypes.c_int32),
                 ("arith", ctypes.c_int32), ("order", ctypes.c_int32), ("trials", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("chunk_log2", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("host_threads", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("host_threads", ctypes.c_int32),
+                ("max_table_mib", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

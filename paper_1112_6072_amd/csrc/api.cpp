@@ -51,6 +51,7 @@ ExpandParams expand_params(const hperm_opts &o) {
     p.arith = o.arith;
     p.chunk_log2 = o.chunk_log2;
     p.threads = o.host_threads;
+    p.max_bytes = (size_t)(o.max_table_mib > 0 ? o.max_table_mib : 4096) << 20;
     return p;
 }
 
@@ -697,6 +698,7 @@ static const char *check_opts(const hperm_opts *o) {
     if (o->trials < 1 || o->trials > 4096) return "trials must be in [1, 4096]";
     if (o->chunk_log2 < 0 || o->chunk_log2 > 12) return "chunk_log2 must be in [0, 12]";
     if (o->host_threads < 0 || o->host_threads > 64) return "host_threads must be in [0, 64]";
+    if (o->max_table_mib < 0) return "max_table_mib must be >= 0";
     return nullptr;
 }
 
@@ -804,6 +806,7 @@ static hperm_status expand_batch(hperm_ctx *c, int32_t count, const int32_t *n, 
     std::string err;
     const int rc = expand_problems(probs, expand_params(c->opts), &j->tab, &err);
     if (rc == -2) return set_error(c, HPERM_E_RANGE, err);
+    if (rc == -3) return set_error(c, HPERM_E_NOMEM, err);
     if (rc) return set_error(c, HPERM_E_INVALID, err);
     j->id = next_jobs_id();
     return HPERM_OK;

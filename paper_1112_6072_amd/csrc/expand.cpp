@@ -48,6 +48,8 @@ struct RangeError {
     std::string msg;
 };
 
+struct LimitError {};   // the job table outgrew ExpandParams::max_bytes
+
 // Proven log2 upper bound of per(B) for a non-negative integer matrix: min of the product
 // of row sums and the product of column sums; for a 0-1 matrix also Bregman's bound
 // prod_i (r_i!)^(1/r_i) (rows, and columns by transposition).
@@ -266,8 +268,8 @@ struct JobOut {
 // nonzeros, then lower index). Gray column 0 flips at every other step, column j at every
 // 2^(j+1)-th, so early columns should reach few rows. Row order: rows sorted by their level,
 // the first Gray column touching them (rows touched by none come last). Then a flip of Gray
-// column j changes only rows below hi[j] = number of rows of level <= j, and the kernels
-// recompute only the suffix products of those rows.
+// column j changes only rows below hi[j] = 1 + the lowest row of column j (at most the number
+// of rows of level <= j), and the kernels recompute only the suffix products of those rows.
 void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &prm,
               JobOut *out) {
     const int m = a.m;
@@ -367,12 +369,16 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
         acc += gcnt[g];
     }
     cs[m - 1] = acc;
+    // hi[g]: one past the lowest job row of Gray column g, so that a flip of column g changes
+    // only rows below hi[g] (at most the number of rows of level <= g)
     uint32_t *hi = w + 2 * m;
-    for (int g = 0; g < m; ++g) {
+    for (int g = 0; g < m - 1; ++g) {
         int h = 0;
-        for (int i = 0; i < m; ++i) h += level[i] <= g;
-        hi[g] = (uint32_t)(g == m - 1 ? m : h);
+        for (int i = 0; i < m; ++i)
+            if (colrows[gray[g]] >> i & 1) h = std::max(h, newrow[i] + 1);
+        hi[g] = (uint32_t)h;
     }
+    hi[m - 1] = (uint32_t)m;
     uint32_t *ent = w + 3 * m;
     std::vector<uint32_t> pos(cs, cs + m);
     for (int r = 0; r < m; ++r) {
@@ -398,6 +404,7 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
 struct Workspace {
     std::vector<Node> depth;   // one node buffer per depth
     std::vector<int> colcnt;
+    std::atomic<size_t> *table_bytes = nullptr;   // shared by the threads of one expansion
     void init(int n, int nnz) {
         depth.assign(n + 2, Node());
         for (auto &x : depth) x.reserve(n, nnz);
@@ -424,7 +431,12 @@ void expand_rec(int d, const ExpandParams &prm, Workspace &ws, int problem, doub
     const Action act = classify(a, prm, ws, &is_col, &line);
     if (act == DROP) return;
     if (act == LEAF) {
+        const size_t w0 = out->data.size();
         emit_job(a, problem, root_log2, prm, out);
+        if (prm.max_bytes && ws.table_bytes) {
+            const size_t add = (out->data.size() - w0) * sizeof(uint32_t) + sizeof(JobDesc) + sizeof(double);
+            if (ws.table_bytes->fetch_add(add) + add > prm.max_bytes) throw LimitError{};
+        }
         return;
     }
     Pair pairs[HP_MAX_N / 2 + 1];
@@ -477,6 +489,7 @@ std::string validate_csr(const CsrView &a) {
 static void run_subtrees(std::vector<Pending> &pend, const ExpandParams &prm, int maxn, int maxnnz,
                          std::vector<JobOut> &outs, std::string *err, std::atomic<int> &bad) {
     std::atomic<size_t> next{0};
+    std::atomic<size_t> table_bytes{0};
     int threads = prm.threads > 0 ? prm.threads : (int)std::thread::hardware_concurrency();
     threads = std::max(1, std::min(threads, 64));
     threads = (int)std::min<size_t>((size_t)threads, std::max<size_t>(pend.size(), 1));
@@ -484,6 +497,7 @@ static void run_subtrees(std::vector<Pending> &pend, const ExpandParams &prm, in
     auto work = [&](int tid) {
         Workspace ws;
         ws.init(maxn, maxnnz);
+        ws.table_bytes = &table_bytes;
         for (;;) {
             const size_t k = next.fetch_add(1);
             if (k >= pend.size() || bad.load()) break;
@@ -499,6 +513,13 @@ static void run_subtrees(std::vector<Pending> &pend, const ExpandParams &prm, in
             } catch (const RangeError &e) {
                 errs[tid] = e.msg;
                 bad.store(1);
+            } catch (const LimitError &) {
+                errs[tid] = "the job table exceeds its limit of " + std::to_string(prm.max_bytes >> 20) +
+                            " MiB; raise max_table_mib or m_cut";
+                bad.store(2);
+            } catch (const std::bad_alloc &) {
+                errs[tid] = "out of host memory during expansion";
+                bad.store(2);
             }
         }
     };
@@ -612,8 +633,20 @@ int expand_problems(const std::vector<CsrView> &probs, const ExpandParams &prm, 
     std::vector<JobOut> outs(pend.size());
     std::atomic<int> bad{0};
     run_subtrees(pend, prm, maxn, maxnnz, outs, err, bad);
-    if (bad.load()) return -2;
+    if (bad.load()) return bad.load() == 2 ? -3 : -2;
+    size_t nd = out->desc.size(), nw = out->data.size();
     for (auto &o : outs) {
+        nd += o.desc.size();
+        nw += o.data.size();
+    }
+    if (nw >= (1ull << 32)) {
+        *err = "the job table exceeds 2^32 data words";
+        return -3;
+    }
+    out->desc.reserve(nd);
+    out->data.reserve(nw);
+    out->log2_bound.reserve(nd);
+    for (auto &o : outs) {   // append in tree order, freeing each part as it is copied
         const uint32_t shift = (uint32_t)out->data.size();
         for (auto d : o.desc) {
             d.data_off += shift;
@@ -621,6 +654,7 @@ int expand_problems(const std::vector<CsrView> &probs, const ExpandParams &prm, 
         }
         out->data.insert(out->data.end(), o.data.begin(), o.data.end());
         out->log2_bound.insert(out->log2_bound.end(), o.bound.begin(), o.bound.end());
+        o = JobOut();
     }
     return 0;
 }

@@ -16,6 +16,7 @@ struct ExpandParams {
     int arith = 0;        // hperm_arith: 0 auto, 1 W64, 2 W128, 3 RES
     int chunk_log2 = 0;   // 0: table
     int threads = 0;
+    size_t max_bytes = 0;   // host job-table limit (descriptors, data, bounds); 0: none
 };
 
 // Host copy of the job table of one or more problems.
@@ -42,7 +43,8 @@ struct CsrView {
 std::string validate_csr(const CsrView &a);
 
 // Expand problems into jobs and append them to *out (out->n_problems grows by the count).
-// Returns 0 on success, or -2 (range) / -1 (invalid) with *err set.
+// Returns 0 on success, or -1 (invalid), -2 (range) or -3 (the job table would exceed
+// prm.max_bytes) with *err set.
 int expand_problems(const std::vector<CsrView> &probs, const ExpandParams &prm, JobTable *out,
                     std::string *err);
 

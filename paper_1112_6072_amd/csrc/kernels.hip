@@ -53,27 +53,31 @@ __device__ __forceinline__ JobDesc load_job(const JobDesc *jobs, uint32_t j) {
 
 #if HP_PART >= 1
 // ------------------------------------------------------------------------ rings
-// A ring multiplies a non-negative product by |f_i| (unsigned 32-bit) and adds or
-// subtracts the product into a lane accumulator. The sign of a term is tracked apart:
-// sign(prod f_i) is the parity of the negative factors, and the Gray sign is (-1)^k.
+// A ring multiplies a non-negative product by |f_i| (unsigned, below 2^24) and adds or
+// subtracts the product into a lane accumulator. The sign of a term is tracked apart (the
+// parity of the negative factors and the Gray sign (-1)^k) and arrives as a mask: all ones
+// for a negative term, zero for a positive one.
 
 struct RingW64 {
     struct P { uint64_t v; };
+    // -p = (p xor ~0) + 1: the accumulator adds p xor mask and counts the +1s apart
+    struct Acc { uint64_t v; uint32_t n; };
     __device__ static P one() { return {1}; }
     __device__ static void mul(P &p, uint32_t u) { p.v *= (uint64_t)u; }
-    __device__ static void acc(P &a, const P &p, uint32_t neg) {
-        const uint64_t m = 0ull - (uint64_t)neg;           // all ones when negative
-        a.v += (p.v ^ m) - m;
+    __device__ static Acc acc_zero() { return {0, 0}; }
+    __device__ static void acc(Acc &a, const P &p, uint32_t mask) {
+        a.v += p.v ^ (((uint64_t)mask << 32) | mask);
+        a.n -= mask;
     }
-    __device__ static P zero() { return {0}; }
-    __device__ static void flush(const P &a, JobAcc *dst, int lane) {
-        const uint64_t s = wave_sum64(a.v);
+    __device__ static void flush(const Acc &a, JobAcc *dst, int lane) {
+        const uint64_t s = wave_sum64(a.v + a.n);
         if (lane == 0) atomicAdd(&dst->l[0], (unsigned long long)s);
     }
 };
 
 struct RingW128 {
     struct P { uint32_t x0, x1, x2, x3; };
+    struct Acc { unsigned __int128 v; uint32_t n; };
     __device__ static P one() { return {1, 0, 0, 0}; }
     __device__ static void mul(P &p, uint32_t u) {
         const uint64_t t0 = (uint64_t)p.x0 * u;
@@ -82,22 +86,18 @@ struct RingW128 {
         const uint32_t t3 = p.x3 * u + (uint32_t)(t2 >> 32);
         p = {(uint32_t)t0, (uint32_t)t1, (uint32_t)t2, t3};
     }
-    __device__ static void acc(P &a, const P &p, uint32_t neg) {
-        // a += neg ? -p : p  (mod 2^128):  (p xor m) - m with m = 0 or all ones
-        const uint32_t m = 0u - neg;
-        unsigned __int128 q = ((unsigned __int128)(p.x3 ^ m) << 96) |
-                              ((unsigned __int128)(p.x2 ^ m) << 64) |
-                              ((unsigned __int128)(p.x1 ^ m) << 32) | (p.x0 ^ m);
-        q += neg;
-        unsigned __int128 s = ((unsigned __int128)a.x3 << 96) | ((unsigned __int128)a.x2 << 64) |
-                              ((unsigned __int128)a.x1 << 32) | a.x0;
-        s += q;
-        a = {(uint32_t)s, (uint32_t)(s >> 32), (uint32_t)(s >> 64), (uint32_t)(s >> 96)};
+    __device__ static Acc acc_zero() { return {0, 0}; }
+    __device__ static void acc(Acc &a, const P &p, uint32_t mask) {
+        const unsigned __int128 q = ((unsigned __int128)(p.x3 ^ mask) << 96) |
+                                    ((unsigned __int128)(p.x2 ^ mask) << 64) |
+                                    ((unsigned __int128)(p.x1 ^ mask) << 32) | (p.x0 ^ mask);
+        a.v += q;
+        a.n -= mask;
     }
-    __device__ static P zero() { return {0, 0, 0, 0}; }
-    __device__ static void flush(const P &a, JobAcc *dst, int lane) {
-        const uint64_t s0 = wave_sum64(a.x0), s1 = wave_sum64(a.x1);
-        const uint64_t s2 = wave_sum64(a.x2), s3 = wave_sum64(a.x3);
+    __device__ static void flush(const Acc &a, JobAcc *dst, int lane) {
+        const unsigned __int128 v = a.v + a.n;
+        const uint64_t s0 = wave_sum64((uint32_t)v), s1 = wave_sum64((uint32_t)(v >> 32));
+        const uint64_t s2 = wave_sum64((uint32_t)(v >> 64)), s3 = wave_sum64((uint32_t)(v >> 96));
         if (lane == 0) {
             atomicAdd(&dst->l[0], (unsigned long long)s0);
             atomicAdd(&dst->l[1], (unsigned long long)s1);
@@ -128,19 +128,21 @@ __device__ __forceinline__ uint64_t addmod61(uint64_t a, uint64_t b, uint32_t ne
 
 struct RingRes {
     struct P { uint64_t r0, r1, r2; };
+    using Acc = P;
     __device__ static P one() { return {1, 1, 1}; }
     __device__ static void mul(P &p, uint32_t u) {
         p.r0 = mulmod61<HP_C0>(p.r0, u);
         p.r1 = mulmod61<HP_C1>(p.r1, u);
         p.r2 = mulmod61<HP_C2>(p.r2, u);
     }
-    __device__ static void acc(P &a, const P &p, uint32_t neg) {
+    __device__ static Acc acc_zero() { return {0, 0, 0}; }
+    __device__ static void acc(Acc &a, const P &p, uint32_t mask) {
+        const uint32_t neg = mask & 1u;
         a.r0 = addmod61<HP_C0>(a.r0, p.r0, neg);
         a.r1 = addmod61<HP_C1>(a.r1, p.r1, neg);
         a.r2 = addmod61<HP_C2>(a.r2, p.r2, neg);
     }
-    __device__ static P zero() { return {0, 0, 0}; }
-    __device__ static void flush(const P &a, JobAcc *dst, int lane) {
+    __device__ static void flush(const Acc &a, JobAcc *dst, int lane) {
         const uint64_t v[3] = {a.r0, a.r1, a.r2};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -164,27 +166,85 @@ struct RingRes {
 // The term prod_i f_i is kept as suffix products S_i = prod_{i' >= i} |f_i'| (S_m = 1) and
 // sign words G_i = f_i xor G_{i+1} whose bit 31 is the parity of the negative f_i', i' >= i.
 // Rows are sorted by the first Gray column that touches them, so a flip of column j changes
-// only rows below hi[j]; S and G are recomputed for those rows, in blocks of four rows from
-// the top block that holds a changed row down to row 0 (rows of a recomputed block above
-// hi[j] are unchanged, recomputing them is redundant but exact).
+// only rows below hi[j]. Rows are recomputed in blocks with fixed bounds, fine where most
+// flips end and coarse below them: block tops 2, 3, 4, 5, 6, 8, then every 4 rows. A flip of
+// column j recomputes S and G in every block from the one holding row hi[j]-1 down to block
+// 0 (rows of that top block above hi[j] are recomputed redundantly but exactly). Only S and
+// G at block boundaries live across steps, which keeps the register footprint small. The
+// top block of every column j < c is found once per item and packed, four bits per column,
+// into one 64-bit scalar.
+//
+// The row values f_i are integers of magnitude below 2^24 (row sums are below 2^24), held as
+// FP32, where every such integer and every sum of two of them that stays below 2^24 is exact:
+// an update is one FMA with the signed delta, |f_i| is one conversion with the absolute-value
+// source modifier, and the sign is bit 31 of the FP32 word.
 //
 // The deltas 2 b_ij of the Gray columns that flip inside the item (j < c) sit in LDS as a
-// dense table D[j][row], one table per wave, written at the start of the item; a step reads
-// four rows with one broadcast LDS load. All register arrays are indexed by constants.
-constexpr int RB = 4;       // rows per recomputed block
+// dense FP32 table D[j][row], one table per wave, written at the start of the item; a block's
+// rows are read with one broadcast LDS load. All register arrays are indexed by constants.
 constexpr int CMAX = 12;    // largest lane chunk exponent c (host clamps chunk_log2)
+
+__host__ __device__ constexpr int blk_top(int b) { return b < 5 ? b + 2 : (b == 5 ? 8 : 8 + 4 * (b - 5)); }
+__host__ __device__ constexpr int blk_lo(int b) { return b == 0 ? 0 : blk_top(b - 1); }
+
+template <int MAXM>
+struct Blocks {
+    static constexpr int count() {
+        int b = 0;
+        while (blk_top(b) < MAXM) ++b;
+        return b + 1;
+    }
+    static constexpr int N = count();   // blocks covering rows 0 .. MAXM-1
+    static_assert(N <= 15, "four bits per packed block index");
+};
 
 template <int MAXM>
 struct Tab {
-    static constexpr int STRIDE = (MAXM + RB - 1) / RB * RB;   // words per Gray column
-    static constexpr int WORDS = CMAX * STRIDE;                  // per wave
+    static constexpr int STRIDE = (blk_top(Blocks<MAXM>::N - 1) + 3) / 4 * 4;   // words per column
+    static constexpr int WORDS = CMAX * STRIDE;                                // per wave
 };
+
+// Index of the block that holds row h-1 (h >= 1; h = 0 maps to block 0).
+__device__ __forceinline__ uint32_t block_of(uint32_t h) {
+    return h <= 6 ? (h <= 2 ? 0u : h - 2) : (h <= 8 ? 5u : 5u + (h - 5) / 4);
+}
+
+// Recompute block B (rows blk_lo(B) .. blk_top(B)-1, top row first) after a flip with the
+// column's deltas dj (FP32, one per row) in direction dir.
+#define HP_BLOCK(B)                                                                        \
+    if ((B) < NB) {                                                                        \
+        const int lo_ = blk_lo(B), w_ = blk_top(B) - blk_lo(B);                            \
+        float dd_[4];                                                                      \
+        if (w_ == 4) {                                                                     \
+            const float4 v_ = *reinterpret_cast<const float4 *>(dj + lo_);                 \
+            dd_[0] = v_.x;                                                                 \
+            dd_[1] = v_.y;                                                                 \
+            dd_[2] = v_.z;                                                                 \
+            dd_[3] = v_.w;                                                                 \
+        } else if (w_ == 2) {                                                              \
+            const float2 v_ = *reinterpret_cast<const float2 *>(dj + lo_);                 \
+            dd_[0] = v_.x;                                                                 \
+            dd_[1] = v_.y;                                                                 \
+        } else {                                                                           \
+            dd_[0] = dj[lo_];                                                              \
+        }                                                                                  \
+        _Pragma("unroll") for (int r_ = 3; r_ >= 0; --r_) {                                \
+            const int I_ = lo_ + r_;                                                       \
+            if (r_ < w_ && I_ < MAXM) {                                                    \
+                f[I_] = __builtin_fmaf(dd_[r_], dir, f[I_]);                               \
+                G[I_] = G[I_ + 1] ^ __float_as_uint(f[I_]);                                \
+                S[I_] = S[I_ + 1];                                                         \
+                R::mul(S[I_], (uint32_t)fabsf(f[I_]));                                     \
+            }                                                                              \
+        }                                                                                  \
+    }
 
 template <class R, int MAXM>
 __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__restrict__ data,
-                                         uint64_t item, int lane, JobAcc *dst, int *tab) {
+                                         uint64_t item, int lane, JobAcc *dst, float *tab) {
     static_assert(MAXM <= 40, "job orders up to 40");
     constexpr int STRIDE = Tab<MAXM>::STRIDE;
+    constexpr int NB = Blocks<MAXM>::N;
     const int m = jd.m;
     const int c = jd.chunk_log2;
     const uint64_t nterms = 1ull << (m - 1);
@@ -195,39 +255,43 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
     const uint32_t *hi = w + 2 * m;
     const uint32_t *ent = w + 3 * m;
 
-    // delta table of the Gray columns 0..c-1
-    for (int q = lane; q < CMAX * STRIDE; q += WAVE) tab[q] = 0;
+    // delta table of the Gray columns 0..c-1 and their packed top blocks
+    for (int q = lane; q < CMAX * STRIDE; q += WAVE) tab[q] = 0.0f;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    uint64_t tops = 0;
     for (int j = 0; j < c; ++j) {
         const uint32_t b = uni(cs[j]);
         const uint32_t n = uni(cs[j + 1]) - b;
         if ((uint32_t)lane < n) {
             const uint32_t pk = ent[b + lane];
-            tab[j * STRIDE + (int)(pk & 0xff)] = (int)(pk >> 8);
+            tab[j * STRIDE + (int)(pk & 0xff)] = (float)(int)(pk >> 8);
         }
+        tops |= (uint64_t)block_of(uni(hi[j])) << (4 * j);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // f_i(gray(k0)) = base_i + 2 * sum over the set Gray bits (rows selected by comparison,
-    // so that the row values stay in registers with constant indices)
-    int f[MAXM];
+    // f_i(gray(k0)) = base_i + 2 * sum over the set Gray bits. Bits 0..c-2 of gray(k0) are
+    // zero (k0 is a multiple of 2^c), so only columns c-1 .. m-2 can contribute; rows are
+    // selected by comparison so that the row values stay in registers with constant indices.
+    float f[MAXM];
 #pragma unroll
-    for (int i = 0; i < MAXM; ++i) f[i] = i < m ? (int)uni(w[i]) : 1;
+    for (int i = 0; i < MAXM; ++i) f[i] = i < m ? (float)(int)uni(w[i]) : 1.0f;
     const uint64_t g0 = k0 ^ (k0 >> 1);
-    for (int j = 0; j < m - 1; ++j) {
-        const int bit = (int)((g0 >> j) & 1);
+    for (int j = c > 0 ? c - 1 : 0; j < m - 1; ++j) {
+        const bool bit = (g0 >> j) & 1;
         const uint32_t b = uni(cs[j]);
         const uint32_t e = uni(cs[j + 1]);
         for (uint32_t q = b; q < e; ++q) {
             const uint32_t pk = uni(ent[q]);
             const int row = (int)(pk & 0xff);
-            const int d = bit ? (int)(pk >> 8) : 0;
+            const float d = bit ? (float)(int)(pk >> 8) : 0.0f;
 #pragma unroll
-            for (int i = 0; i < MAXM; ++i) f[i] += row == i ? d : 0;
+            for (int i = 0; i < MAXM; ++i)
+                if (row == i) f[i] += d;
         }
     }
     typename R::P S[MAXM + 1];
@@ -239,48 +303,42 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
         S[i] = S[i + 1];
         G[i] = G[i + 1];
         if (i < m) {
-            const int x = f[i];
-            G[i] ^= (uint32_t)x;
-            R::mul(S[i], (uint32_t)(x < 0 ? -x : x));
+            G[i] ^= __float_as_uint(f[i]);
+            R::mul(S[i], (uint32_t)fabsf(f[i]));
         }
     }
     // direction of the step with j = c-1 (lane-dependent): +1 if bit c of k0 is 0
-    const int dir_last = ((k0 >> c) & 1) ? -1 : 1;
+    const float dir_last = ((k0 >> c) & 1) ? -1.0f : 1.0f;
     const uint32_t k0par = (uint32_t)(k0 & 1);   // k0 is odd only when L = 1
 
-    typename R::P acc = R::zero();
+    typename R::Acc acc = R::acc_zero();
     for (uint32_t t = 0;; ++t) {
-        // term k = k0 + t: (-1)^k prod_i f_i
-        R::acc(acc, S[0], (G[0] >> 31) ^ k0par ^ (t & 1));
+        // term k = k0 + t: (-1)^k prod_i f_i; the wave-uniform part of the sign is a mask
+        const uint32_t usign = 0u - ((k0par ^ t) & 1u);
+        R::acc(acc, S[0], (uint32_t)((int)G[0] >> 31) ^ usign);
         if (t + 1 >= (uint32_t)L) break;
         const int j = __builtin_ctz(t + 1);
-        const int dir_uni = ((t + 1) >> (j + 1)) & 1 ? -1 : 1;
-        const int dir = j == c - 1 ? dir_last : dir_uni;
-        const int h = (int)uni(hi[j]);
-        const int *dj = tab + j * STRIDE;
+        const float dir_uni = ((t + 1) >> (j + 1)) & 1 ? -1.0f : 1.0f;
+        const float dir = j == c - 1 ? dir_last : dir_uni;
+        const uint32_t top = (uint32_t)(tops >> (4 * j)) & 15u;
+        const float *dj = tab + j * STRIDE;
+        // blocks from the top one down to block 0: one guard for the coarse blocks 5 and up,
+        // then one per fine block (plain ifs keep the control flow structured)
+        if (top >= 5) {
 #pragma unroll
-        for (int B = (MAXM + RB - 1) / RB - 1; B >= 0; --B) {
-            if (B * RB < h) {
-                const int4 d4 = *reinterpret_cast<const int4 *>(dj + B * RB);
-                const int dd[RB] = {d4.x, d4.y, d4.z, d4.w};
-#pragma unroll
-                for (int r = RB - 1; r >= 0; --r) {
-                    const int I = B * RB + r;
-                    if (I < MAXM) {
-                        // f_I += dir * d (24-bit signed multiply-add: 0 <= d < 2^23, dir = +-1)
-                        f[I] = __mul24(dd[r], dir) + f[I];
-                        const int x = f[I];
-                        G[I] = G[I + 1] ^ (uint32_t)x;
-                        S[I] = S[I + 1];
-                        R::mul(S[I], (uint32_t)(x < 0 ? -x : x));
-                    }
-                }
-            }
+            for (int B = NB - 1; B >= 5; --B)
+                if ((int)top >= B) { HP_BLOCK(B) }
         }
+        if (top >= 4) { HP_BLOCK(4) }
+        if (top >= 3) { HP_BLOCK(3) }
+        if (top >= 2) { HP_BLOCK(2) }
+        if (top >= 1) { HP_BLOCK(1) }
+        HP_BLOCK(0)
     }
-    if (k0 >= nterms) acc = R::zero();   // lanes past the end of a short job contribute nothing
+    if (k0 >= nterms) acc = R::acc_zero();   // lanes past the end of a short job contribute nothing
     R::flush(acc, dst, lane);
 }
+#undef HP_BLOCK
 
 
 // Persistent kernel: every wave repeatedly takes the next work item of the queue. The
@@ -295,9 +353,9 @@ __global__ __launch_bounds__(BLOCK) void rnw_persistent(const JobDesc *__restric
                                                         uint32_t nqueue, uint64_t total_items,
                                                         unsigned long long *head,
                                                         JobAcc *__restrict__ accs) {
-    __shared__ __attribute__((aligned(16))) int tabs[(BLOCK / WAVE) * Tab<MAXM>::WORDS];
+    __shared__ __attribute__((aligned(16))) float tabs[(BLOCK / WAVE) * Tab<MAXM>::WORDS];
     const int lane = threadIdx.x & (WAVE - 1);
-    int *tab = tabs + (threadIdx.x >> 6) * Tab<MAXM>::WORDS;
+    float *tab = tabs + (threadIdx.x >> 6) * Tab<MAXM>::WORDS;
     for (;;) {
         // Every lane takes part in the claim (lane 0 adds 1, the others 0) so that no
         // lane-dependent branch surrounds it: the whole wave then reads lane 0's claim.
@@ -326,9 +384,9 @@ __global__ __launch_bounds__(BLOCK) void rnw_single(const JobDesc *__restrict__ 
                                                     const uint32_t *__restrict__ data,
                                                     uint32_t job, uint64_t nitems,
                                                     JobAcc *__restrict__ accs) {
-    __shared__ __attribute__((aligned(16))) int tabs[(BLOCK / WAVE) * Tab<MAXM>::WORDS];
+    __shared__ __attribute__((aligned(16))) float tabs[(BLOCK / WAVE) * Tab<MAXM>::WORDS];
     const int lane = threadIdx.x & (WAVE - 1);
-    int *tab = tabs + (threadIdx.x >> 6) * Tab<MAXM>::WORDS;
+    float *tab = tabs + (threadIdx.x >> 6) * Tab<MAXM>::WORDS;
     const uint64_t w = (uint64_t)blockIdx.x * (BLOCK / WAVE) + (threadIdx.x >> 6);
     if (w >= nitems) return;
     const JobDesc jd = load_job(jobs, job);

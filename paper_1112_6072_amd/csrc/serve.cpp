@@ -126,7 +126,7 @@ struct Serving {
                 r->state = Request::DONE;
                 r->t_done = now_s();
             } else if (rc) {
-                r->status = rc == -2 ? HPERM_E_RANGE : HPERM_E_INVALID;
+                r->status = rc == -2 ? HPERM_E_RANGE : rc == -3 ? HPERM_E_NOMEM : HPERM_E_INVALID;
                 r->err = err;
                 r->state = Request::DONE;
                 r->t_done = now_s();
