@@ -149,15 +149,16 @@ hperm_status estimate_jobs(Dev *c, hperm_jobs *j, int trials, uint64_t seed) {
         s = upload_jobs(c, j);
         if (s) return s;
     }
-    std::vector<uint32_t> list;
-    list.reserve(nd);
+    // jobs grouped by order bucket (one counting pass), natural order inside a bucket
+    std::vector<uint32_t> &list = c->h_queue;
+    list.resize(nd);
     size_t off[5] = {0, 0, 0, 0, 0};
-    for (int b = 0; b < 4; ++b) {
-        off[b] = list.size();
-        for (size_t k = 0; k < nd; ++k)
-            if (bucket_of(j->tab.desc[k].m) == b) list.push_back((uint32_t)k);
+    for (size_t k = 0; k < nd; ++k) off[bucket_of(j->tab.desc[k].m) + 1]++;
+    for (int b = 0; b < 4; ++b) off[b + 1] += off[b];
+    {
+        size_t pos[4] = {off[0], off[1], off[2], off[3]};
+        for (size_t k = 0; k < nd; ++k) list[pos[bucket_of(j->tab.desc[k].m)]++] = (uint32_t)k;
     }
-    off[4] = list.size();
     s = hip_check(c, hipMemcpyAsync(c->buf[B_LIST].ptr, list.data(), list.size() * 4,
                                     hipMemcpyHostToDevice, c->stream), "upload estimate list");
     if (s) return s;
@@ -402,24 +403,33 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     queue.clear();
     item_end.clear();
     struct Group { int ring, bucket; size_t off, n; uint64_t items; };
+    // one counting pass: group g = (bucket, ring) from the largest bucket and the widest ring
+    // down, each group keeping the chosen order
+    constexpr int NG = 4 * HP_NRING;
+    auto gid = [&](const JobDesc &d) { return (3 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith); };
+    size_t cnt[NG + 1] = {0};
+    for (const JobDesc &d : dsc) cnt[gid(d) + 1]++;
+    for (int g = 0; g < NG; ++g) cnt[g + 1] += cnt[g];
     std::vector<Group> groups;
-    queue.reserve(nd);
-    item_end.reserve(nd);
-    for (int b = 3; b >= 0; --b)
-        for (int r = HP_NRING - 1; r >= 0; --r) {
-            Group g{r, b, queue.size(), 0, 0};
-            uint64_t acc = 0;
-            for (uint32_t k : ord) {
-                const JobDesc &d = dsc[k];
-                if (d.arith != r || bucket_of(d.m) != b) continue;
-                acc += items_of(d.m, d.chunk_log2);
-                queue.push_back(k);
-                item_end.push_back(acc);
-            }
-            g.n = queue.size() - g.off;
-            g.items = acc;
-            if (g.n) groups.push_back(g);
+    for (int g = 0; g < NG; ++g)
+        if (cnt[g + 1] > cnt[g])
+            groups.push_back(Group{HP_NRING - 1 - g % HP_NRING, 3 - g / HP_NRING, cnt[g], cnt[g + 1] - cnt[g], 0});
+    queue.resize(nd);
+    item_end.resize(nd);
+    {
+        size_t pos[NG];
+        for (int g = 0; g < NG; ++g) pos[g] = cnt[g];
+        for (uint32_t k : ord) queue[pos[gid(dsc[k])]++] = k;
+    }
+    for (Group &g : groups) {
+        uint64_t acc = 0;
+        for (size_t q = g.off; q < g.off + g.n; ++q) {
+            const JobDesc &d = dsc[queue[q]];
+            acc += items_of(d.m, d.chunk_log2);
+            item_end[q] = acc;
         }
+        g.items = acc;
+    }
     s = upload_jobs(c, j);
     if (s) return s;
     s = ensure_buf(c, B_QUEUE, nd * sizeof(uint32_t));
@@ -467,6 +477,15 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     if (persistent) {
         s = ensure_launch_events(c, groups.size());
         if (s) return s;
+        if (j->work_mults.size() != nd) {
+            j->work_mults.resize(nd);
+            j->work_updates.resize(nd);
+            for (size_t k = 0; k < nd; ++k) {
+                const JobWork wk = job_work(dsc[k], j->tab.data.data(), dsc[k].chunk_log2);
+                j->work_mults[k] = wk.mults;
+                j->work_updates[k] = wk.updates;
+            }
+        }
         for (size_t gi = 0; gi < groups.size(); ++gi) {
             const Group &g = groups[gi];
             hperm_launch_stat st{};
@@ -475,14 +494,15 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             st.n_jobs = (int32_t)g.n;
             st.persistent = 1;
             st.items = g.items;
+            double mults = 0.0, updates = 0.0;
             for (size_t q = g.off; q < g.off + g.n; ++q) {
-                const JobDesc &d = dsc[queue[q]];
-                const uint64_t t = 1ull << (d.m - 1);
-                const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2);
-                st.terms += t;
-                st.row_updates += (uint64_t)wk.updates;
-                st.alg_slots += wk.mults * ring_mul_slots(d.arith) + (double)t * ring_add_slots(d.arith) + wk.updates;
+                const uint32_t k = queue[q];
+                st.terms += 1ull << (dsc[k].m - 1);
+                mults += j->work_mults[k];
+                updates += j->work_updates[k];
             }
+            st.row_updates = (uint64_t)updates;
+            st.alg_slots = mults * ring_mul_slots(g.ring) + (double)st.terms * ring_add_slots(g.ring) + updates;
             c->launches.push_back(st);
             s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
             if (s) return s;

@@ -32,6 +32,9 @@ struct hperm_jobs {
     std::vector<float> keys;   // KKLLL keys, natural index
     bool has_keys = false;
     uint64_t id = 0;           // identity for device residency
+    // per-job algorithmic work of the persistent walk (ring multiplies, row updates), filled
+    // on the first run
+    std::vector<double> work_mults, work_updates;
 };
 
 namespace hp {

@@ -63,7 +63,15 @@ struct RingW64 {
     // -p = (p xor ~0) + 1: the accumulator adds p xor mask and counts the +1s apart
     struct Acc { uint64_t v; uint32_t n; };
     __device__ static P one() { return {1}; }
-    __device__ static void mul(P &p, uint32_t u) { p.v *= (uint64_t)u; }
+    __device__ static void mul(P &p, uint32_t u) {
+        // low word times u as a 64-bit product; high word times u modulo 2^32 as a separate
+        // multiply (kept out of a fused multiply-add, whose 64-bit addend needs a register
+        // pair and extra moves)
+        const uint64_t lo = (uint64_t)(uint32_t)p.v * u;
+        uint32_t hi;
+        asm volatile("v_mul_lo_u32 %0, %1, %2" : "=v"(hi) : "v"((uint32_t)(p.v >> 32)), "v"(u));
+        p.v = lo + ((uint64_t)hi << 32);
+    }
     __device__ static Acc acc_zero() { return {0, 0}; }
     __device__ static void acc(Acc &a, const P &p, uint32_t mask) {
         a.v += p.v ^ (((uint64_t)mask << 32) | mask);
@@ -239,6 +247,28 @@ __device__ __forceinline__ uint32_t block_of(uint32_t h) {
         }                                                                                  \
     }
 
+// A flip: recompute the blocks from top block TOP down to block 0 with deltas DJ and
+// direction DIR (one guard for the coarse blocks 5 and up, then one per fine block; plain
+// ifs keep the control flow structured).
+#define HP_FLIP(TOP, DJ, DIR)                                                              \
+    {                                                                                      \
+        const uint32_t top_ = (TOP);                                                       \
+        const float *const dj = (DJ);                                                      \
+        const float dir_ = (DIR);                                                          \
+        const float dir = dir_;                                                            \
+        const uint32_t top = top_;                                                         \
+        if (top >= 5) {                                                                    \
+            _Pragma("unroll") for (int B = NB - 1; B >= 5; --B) if ((int)top >= B) {       \
+                HP_BLOCK(B)                                                                \
+            }                                                                              \
+        }                                                                                  \
+        if (top >= 4) { HP_BLOCK(4) }                                                      \
+        if (top >= 3) { HP_BLOCK(3) }                                                      \
+        if (top >= 2) { HP_BLOCK(2) }                                                      \
+        if (top >= 1) { HP_BLOCK(1) }                                                      \
+        HP_BLOCK(0)                                                                        \
+    }
+
 template <class R, int MAXM>
 __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__restrict__ data,
                                          uint64_t item, int lane, JobAcc *dst, float *tab) {
@@ -297,7 +327,9 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
     typename R::P S[MAXM + 1];
     uint32_t G[MAXM + 1];
     S[MAXM] = R::one();
-    G[MAXM] = 0;
+    // the sign (-1)^k0 of the first term rides in the sign chain's seed (k0 is odd only when
+    // L = 1); the sign (-1)^t of the later steps is wave-uniform
+    G[MAXM] = (uint32_t)(k0 & 1) << 31;
 #pragma unroll
     for (int i = MAXM - 1; i >= 0; --i) {
         S[i] = S[i + 1];
@@ -309,35 +341,33 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
     }
     // direction of the step with j = c-1 (lane-dependent): +1 if bit c of k0 is 0
     const float dir_last = ((k0 >> c) & 1) ? -1.0f : 1.0f;
-    const uint32_t k0par = (uint32_t)(k0 & 1);   // k0 is odd only when L = 1
 
     typename R::Acc acc = R::acc_zero();
+    const uint32_t last = (uint32_t)L - 1u;
+    const uint32_t top0 = (uint32_t)tops & 15u;
+    // Steps come in pairs: an even term, the flip of column 0 (every other step; its top
+    // block is fixed for the item), an odd term, then the flip of column j = ctz(t+1) >= 1.
     for (uint32_t t = 0;; ++t) {
-        // term k = k0 + t: (-1)^k prod_i f_i; the wave-uniform part of the sign is a mask
-        const uint32_t usign = 0u - ((k0par ^ t) & 1u);
-        R::acc(acc, S[0], (uint32_t)((int)G[0] >> 31) ^ usign);
-        if (t + 1 >= (uint32_t)L) break;
-        const int j = __builtin_ctz(t + 1);
-        const float dir_uni = ((t + 1) >> (j + 1)) & 1 ? -1.0f : 1.0f;
-        const float dir = j == c - 1 ? dir_last : dir_uni;
-        const uint32_t top = (uint32_t)(tops >> (4 * j)) & 15u;
-        const float *dj = tab + j * STRIDE;
-        // blocks from the top one down to block 0: one guard for the coarse blocks 5 and up,
-        // then one per fine block (plain ifs keep the control flow structured)
-        if (top >= 5) {
-#pragma unroll
-            for (int B = NB - 1; B >= 5; --B)
-                if ((int)top >= B) { HP_BLOCK(B) }
+        R::acc(acc, S[0], (uint32_t)((int)G[0] >> 31));   // even t: (-1)^t = +1
+        if (t == last) break;
+        {
+            const float dir0 = c == 1 ? dir_last : (((t + 1) >> 1) & 1 ? -1.0f : 1.0f);
+            HP_FLIP(top0, tab, dir0)
         }
-        if (top >= 4) { HP_BLOCK(4) }
-        if (top >= 3) { HP_BLOCK(3) }
-        if (top >= 2) { HP_BLOCK(2) }
-        if (top >= 1) { HP_BLOCK(1) }
-        HP_BLOCK(0)
+        ++t;
+        R::acc(acc, S[0], ~(uint32_t)((int)G[0] >> 31));   // odd t: (-1)^t = -1
+        if (t == last) break;
+        {
+            const int j = __builtin_ctz(t + 1);
+            const float dir_uni = ((t + 1) >> (j + 1)) & 1 ? -1.0f : 1.0f;
+            const float dirj = j == c - 1 ? dir_last : dir_uni;
+            HP_FLIP((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj)
+        }
     }
     if (k0 >= nterms) acc = R::acc_zero();   // lanes past the end of a short job contribute nothing
     R::flush(acc, dst, lane);
 }
+#undef HP_FLIP
 #undef HP_BLOCK
 
 
@@ -480,14 +510,17 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
             const int tg = t0 + g;
             if (tg >= trials) break;
             float2 *mg = wm + g * MAXM * Sh::LD;
-            for (int e = lane; e < nnz; e += WAVE) {
-                const uint32_t pk = ent[e];
-                const int row = (int)(pk & 0xff);
-                // Gray column of entry e: the last j with cs[j] <= e
-                int col = 0;
-                for (int j = 1; j < m - 1; ++j) col += (int)cs[j] <= e ? 1 : 0;
-                const uint32_t u = kkl_u(seed, jobid, (uint32_t)tg, rmap[row], cmap[col]);
-                mg[row * Sh::LD + col] = make_float2(u == 0 ? 1.0f : -0.5f, u == 0 ? 0.0f : (u == 1 ? kS : -kS));
+            // Gray column by Gray column: lane q writes the column's q-th nonzero
+            for (int col = 0; col < m - 1; ++col) {
+                const uint32_t b = uni(cs[col]);
+                const uint32_t n = uni(cs[col + 1]) - b;
+                const uint32_t ccol = uni(cmap[col]);
+                for (uint32_t q = (uint32_t)lane; q < n; q += WAVE) {
+                    const int row = (int)(ent[b + q] & 0xff);
+                    const uint32_t u = kkl_u(seed, jobid, (uint32_t)tg, rmap[row], ccol);
+                    mg[row * Sh::LD + col] =
+                        make_float2(u == 0 ? 1.0f : -0.5f, u == 0 ? 0.0f : (u == 1 ? kS : -kS));
+                }
             }
             if (fixed_nz && grp == g) {
                 const uint32_t u = kkl_u(seed, jobid, (uint32_t)tg, rmap[r], fixed_col);
@@ -608,44 +641,73 @@ __device__ __forceinline__ uint64_t res_normalise(uint64_t lo_sum, uint64_t hi_s
 
 __global__ void recombine(const JobDesc *__restrict__ jobs, const JobAcc *__restrict__ accs,
                           uint32_t njobs, ProbAcc *__restrict__ probs) {
+    // contributions of this lane's job to its problem: lim[0..3] (32-bit limbs of per(B_w))
+    // and res[0..5] (32-bit halves of the three residues of per(B_w))
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= njobs) return;
-    const JobDesc d = jobs[k];
-    const JobAcc a = accs[k];
-    ProbAcc *pa = probs + d.problem;
-    const int sh = d.m - 1;
-    if (d.arith == HP_RES) {
-        const uint64_t r0 = res_normalise<HP_C0>(a.l[0], a.l[1], d.m);
-        const uint64_t r1 = res_normalise<HP_C1>(a.l[2], a.l[3], d.m);
-        const uint64_t r2 = res_normalise<HP_C2>(a.l[4], a.l[5], d.m);
-        atomicAdd(&pa->res[0], (unsigned long long)(r0 & 0xffffffffull));
-        atomicAdd(&pa->res[1], (unsigned long long)(r0 >> 32));
-        atomicAdd(&pa->res[2], (unsigned long long)(r1 & 0xffffffffull));
-        atomicAdd(&pa->res[3], (unsigned long long)(r1 >> 32));
-        atomicAdd(&pa->res[4], (unsigned long long)(r2 & 0xffffffffull));
-        atomicAdd(&pa->res[5], (unsigned long long)(r2 >> 32));
-        return;
+    const int lane = threadIdx.x & (WAVE - 1);
+    uint64_t v[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t problem = 0;
+    bool bad = false;
+    if (k < njobs) {
+        const JobDesc d = jobs[k];
+        const JobAcc a = accs[k];
+        problem = d.problem;
+        const int sh = d.m - 1;
+        if (d.arith == HP_RES) {
+            const uint64_t r0 = res_normalise<HP_C0>(a.l[0], a.l[1], d.m);
+            const uint64_t r1 = res_normalise<HP_C1>(a.l[2], a.l[3], d.m);
+            const uint64_t r2 = res_normalise<HP_C2>(a.l[4], a.l[5], d.m);
+            v[4] = r0 & 0xffffffffull;
+            v[5] = r0 >> 32;
+            v[6] = r1 & 0xffffffffull;
+            v[7] = r1 >> 32;
+            v[8] = r2 & 0xffffffffull;
+            v[9] = r2 >> 32;
+        } else {
+            unsigned __int128 V;
+            if (d.arith == HP_W64) {
+                const __int128 sv = (int64_t)a.l[0];
+                V = (unsigned __int128)sv;
+            } else {
+                V = (unsigned __int128)a.l[0] + ((unsigned __int128)a.l[1] << 32) +
+                    ((unsigned __int128)a.l[2] << 64) + ((unsigned __int128)a.l[3] << 96);
+            }
+            if (sh & 1) V = (unsigned __int128)0 - V;
+            const bool neg = (V >> 127) != 0;
+            const bool divisible = sh == 0 || (V & (((unsigned __int128)1 << sh) - 1)) == 0;
+            if (neg || !divisible) {
+                bad = true;
+            } else {
+                const unsigned __int128 per = V >> sh;
+                v[0] = (uint32_t)per;
+                v[1] = (uint32_t)(per >> 32);
+                v[2] = (uint32_t)(per >> 64);
+                v[3] = (uint32_t)(per >> 96);
+            }
+        }
     }
-    unsigned __int128 V;
-    if (d.arith == HP_W64) {
-        const __int128 sv = (int64_t)a.l[0];
-        V = (unsigned __int128)sv;
-    } else {
-        V = (unsigned __int128)a.l[0] + ((unsigned __int128)a.l[1] << 32) +
-            ((unsigned __int128)a.l[2] << 64) + ((unsigned __int128)a.l[3] << 96);
+    if (bad) atomicOr(&probs[problem].err, 1u);
+    // jobs in natural order are grouped by problem: when the whole wave holds one problem
+    // (lanes past the end hold zeros), sum in the wave and add once per slot
+    const uint32_t p0 = uni(problem);
+    const bool same = k >= njobs || problem == p0;
+    if (__ballot(!same) == 0) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            const uint64_t t = wave_sum64(v[q]);
+            if (lane == 0 && t) {
+                if (q < 4) atomicAdd(&probs[p0].lim[q], (unsigned long long)t);
+                else atomicAdd(&probs[p0].res[q - 4], (unsigned long long)t);
+            }
+        }
+    } else if (k < njobs) {
+#pragma unroll
+        for (int q = 0; q < 10; ++q) {
+            if (!v[q]) continue;
+            if (q < 4) atomicAdd(&probs[problem].lim[q], (unsigned long long)v[q]);
+            else atomicAdd(&probs[problem].res[q - 4], (unsigned long long)v[q]);
+        }
     }
-    if (sh & 1) V = (unsigned __int128)0 - V;
-    const bool neg = (V >> 127) != 0;
-    const bool divisible = sh == 0 || (V & (((unsigned __int128)1 << sh) - 1)) == 0;
-    if (neg || !divisible) {
-        atomicOr(&pa->err, 1u);
-        return;
-    }
-    const unsigned __int128 per = V >> sh;
-    atomicAdd(&pa->lim[0], (unsigned long long)(uint32_t)per);
-    atomicAdd(&pa->lim[1], (unsigned long long)(uint32_t)(per >> 32));
-    atomicAdd(&pa->lim[2], (unsigned long long)(uint32_t)(per >> 64));
-    atomicAdd(&pa->lim[3], (unsigned long long)(uint32_t)(per >> 96));
 }
 
 __global__ void fill_u64(unsigned long long *p, uint64_t n, unsigned long long v) {
