@@ -452,23 +452,44 @@ __device__ __forceinline__ uint32_t kkl_u(uint64_t seed, uint32_t w, uint32_t t,
 // with partial pivoting: the pivot row is the unused row with the largest |B_rk|, found by a
 // butterfly inside the group and broadcast with lane permutes; log|det B| is the sum of
 // log|pivot|. Trials accumulate log-sum-exp pairs; the key is log(mean |det B|^2).
+// Maximum of a 32-bit key over aligned groups of GROUP lanes (16, 32 or 64): DPP steps
+// inside rows of 16 lanes (quad swaps, half-row and row mirrors), a swizzle across the two
+// rows of a 32-lane half, and a permute across the halves.
+template <int GROUP>
+__device__ __forceinline__ uint32_t group_max(uint32_t x) {
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));    // lane ^ 1
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));    // lane ^ 2
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false));   // 7 - lane in 8
+    x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false));   // 15 - lane in 16
+    if (GROUP >= 32) x = max(x, (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F));      // lane ^ 16
+    if (GROUP >= 64) x = max(x, (uint32_t)__shfl_xor((int)x, 32, WAVE));                     // lane ^ 32
+    return x;
+}
+
 template <int MAXM, int GROUP>
 struct KklShape {
     static_assert(MAXM <= GROUP && (GROUP == 16 || GROUP == 32 || GROUP == 64), "group size");
-    static constexpr int TPW = WAVE / GROUP;            // trials per wave pass
-    static constexpr int LD = MAXM + 1;                 // padded row length (float2)
-    static constexpr int WAVE_WORDS = TPW * MAXM * LD;  // float2 per wave
+    static constexpr int TPW = WAVE / GROUP;              // trials per wave pass
+    static constexpr int LD = (MAXM + 3) / 4 * 4;         // row length in bytes (entry codes)
+    static constexpr int WAVE_BYTES = TPW * MAXM * LD;    // entry codes per wave
 };
 
+// Entry code of a staged matrix: 0 for a structural zero, 1 + u for omega^u.
+__device__ __forceinline__ void kkl_decode(uint32_t code, float &re, float &im) {
+    constexpr float kS = 0.86602540378443864676f;   // sin(2 pi / 3)
+    re = code == 1 ? 1.0f : (code != 0 ? -0.5f : 0.0f);
+    im = code == 2 ? kS : (code == 3 ? -kS : 0.0f);
+}
+
 template <int MAXM, int GROUP>
-__global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(const JobDesc *__restrict__ jobs,
                                                       const uint32_t *__restrict__ data,
                                                       const uint32_t *__restrict__ list,
                                                       uint32_t nlist, int trials, uint64_t seed,
                                                       float *__restrict__ keys) {
     using Sh = KklShape<MAXM, GROUP>;
-    __shared__ float2 mats[(BLOCK / WAVE) * Sh::WAVE_WORDS];
-    __shared__ float red[2 * BLOCK];
+    __shared__ __attribute__((aligned(16))) uint8_t mats[(BLOCK / WAVE) * Sh::WAVE_BYTES];
+    __shared__ float red[2 * (BLOCK / WAVE)];
     if (blockIdx.x >= nlist) return;
     const uint32_t jobid = uni(list[blockIdx.x]);
     const JobDesc jd = load_job(jobs, jobid);
@@ -484,8 +505,7 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
     const uint32_t *ent = w + 3 * m;
     const uint32_t *cmap = w + 3 * m + jd.nnz;
     const uint32_t *rmap = cmap + m;
-    float2 *wm = mats + wave * Sh::WAVE_WORDS;
-    constexpr float kS = 0.86602540378443864676f;   // sin(2 pi / 3)
+    uint8_t *wm = mats + wave * Sh::WAVE_BYTES;
 
     // fixed-column entries: row i has b_i,fixed = base_i + sum of its Gray entries
     // (computed once per lane for the row it holds; only its zero test matters)
@@ -502,14 +522,14 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
         const int t = t0 + grp;                      // this group's trial
         const bool live = t < trials;
         // zero the wave's matrices, then write the nonzeros (all lanes share the work)
-        for (int q = lane; q < Sh::WAVE_WORDS; q += WAVE) wm[q] = make_float2(0.0f, 0.0f);
+        for (int q = lane; q < Sh::WAVE_BYTES / 4; q += WAVE) reinterpret_cast<uint32_t *>(wm)[q] = 0u;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         for (int g = 0; g < Sh::TPW; ++g) {
             const int tg = t0 + g;
             if (tg >= trials) break;
-            float2 *mg = wm + g * MAXM * Sh::LD;
+            uint8_t *mg = wm + g * MAXM * Sh::LD;
             // Gray column by Gray column: lane q writes the column's q-th nonzero
             for (int col = 0; col < m - 1; ++col) {
                 const uint32_t b = uni(cs[col]);
@@ -518,25 +538,26 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
                 for (uint32_t q = (uint32_t)lane; q < n; q += WAVE) {
                     const int row = (int)(ent[b + q] & 0xff);
                     const uint32_t u = kkl_u(seed, jobid, (uint32_t)tg, rmap[row], ccol);
-                    mg[row * Sh::LD + col] =
-                        make_float2(u == 0 ? 1.0f : -0.5f, u == 0 ? 0.0f : (u == 1 ? kS : -kS));
+                    mg[row * Sh::LD + col] = (uint8_t)(1 + u);
                 }
             }
             if (fixed_nz && grp == g) {
                 const uint32_t u = kkl_u(seed, jobid, (uint32_t)tg, rmap[r], fixed_col);
-                mg[r * Sh::LD + (m - 1)] = make_float2(u == 0 ? 1.0f : -0.5f, u == 0 ? 0.0f : (u == 1 ? kS : -kS));
+                mg[r * Sh::LD + (m - 1)] = (uint8_t)(1 + u);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         float re[MAXM], im[MAXM];
-        const float2 *myrow = wm + grp * MAXM * Sh::LD + (r < MAXM ? r : 0) * Sh::LD;
+        const uint32_t *myrow =
+            reinterpret_cast<const uint32_t *>(wm + grp * MAXM * Sh::LD + (r < MAXM ? r : 0) * Sh::LD);
 #pragma unroll
-        for (int c = 0; c < MAXM; ++c) {
-            const float2 v = myrow[c];
-            re[c] = r < m ? v.x : 0.0f;
-            im[c] = r < m ? v.y : 0.0f;
+        for (int q = 0; q < Sh::LD / 4; ++q) {
+            const uint32_t word = r < m ? myrow[q] : 0u;
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                if (4 * q + b < MAXM) kkl_decode((word >> (8 * b)) & 0xffu, re[4 * q + b], im[4 * q + b]);
         }
         bool used = r >= m;
         float logabs = 0.0f;
@@ -544,25 +565,20 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
 #pragma unroll
         for (int k = 0; k < MAXM; ++k) {
             if (k < m) {
-                float mag = used ? -1.0f : re[k] * re[k] + im[k] * im[k];
-                int idx = r;
-#pragma unroll
-                for (int sft = GROUP / 2; sft >= 1; sft >>= 1) {
-                    const float om = __shfl_xor(mag, sft, WAVE);
-                    const int oi = __shfl_xor(idx, sft, WAVE);
-                    if (om > mag || (om == mag && oi < idx)) {
-                        mag = om;
-                        idx = oi;
-                    }
-                }
-                // every lane of the group now holds the group's pivot row idx and |pivot|^2
-                const bool ok = !singular && mag > 0.0f;
-                singular = !ok;
-                const int src = gbase + idx;
-                const float pr = __shfl(re[k], src, WAVE);
-                const float pi = __shfl(im[k], src, WAVE);
+                // pivot: the unused row with the largest |B_rk|^2, as a packed key (the squared
+                // magnitude's FP32 bits with the low 6 bits replaced by 63 - row, so that
+                // equal magnitudes prefer the lower row) maximised inside the group
+                const float mag = re[k] * re[k] + im[k] * im[k];
+                const uint32_t key = used ? 0u : ((__float_as_uint(mag) & ~63u) | (uint32_t)(63 - r));
+                const int idx = 63 - (int)(group_max<GROUP>(key) & 63u);
+                const int src4 = (gbase + idx) << 2;
+                const float pr = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(re[k])));
+                const float pi = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(im[k])));
                 if (r == idx) used = true;
-                const float pm = ok ? mag : 1.0f;
+                const float pmag = pr * pr + pi * pi;
+                const bool ok = !singular && pmag > 0.0f;
+                singular = !ok;
+                const float pm = ok ? pmag : 1.0f;
                 logabs += ok ? 0.5f * __logf(pm) : 0.0f;
                 // factor = B_rk / pivot (zero for used rows and failed groups)
                 const float ir = pr / pm, ii = -pi / pm;
@@ -572,8 +588,8 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
 #pragma unroll
                 for (int c = k + 1; c < MAXM; ++c) {
                     if (c < m) {
-                        const float cr = __shfl(re[c], src, WAVE);
-                        const float ci = __shfl(im[c], src, WAVE);
+                        const float cr = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(re[c])));
+                        const float ci = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(im[c])));
                         re[c] -= fr * cr - fi * ci;
                         im[c] -= fr * ci + fi * cr;
                     }
@@ -590,18 +606,31 @@ __global__ __launch_bounds__(BLOCK) void kkl_estimate(const JobDesc *__restrict_
             }
         }
     }
-    // combine the (max, sum) pairs of all groups of all waves (one per group's first lane)
-    red[2 * threadIdx.x] = r == 0 ? run_max : -INFINITY;
-    red[2 * threadIdx.x + 1] = r == 0 ? run_sum : 0.0f;
+    // combine the (max, sum) pairs of all groups of all waves (one per group's first lane):
+    // log-sum-exp butterflies inside the wave, then the four waves' pairs through LDS
+    float mx = r == 0 ? run_max : -INFINITY;
+    float sm = r == 0 ? run_sum : 0.0f;
+#pragma unroll
+    for (int sft = 32; sft >= 1; sft >>= 1) {
+        const float om = __shfl_xor(mx, sft, WAVE);
+        const float os = __shfl_xor(sm, sft, WAVE);
+        const float nm = fmaxf(mx, om);
+        sm = (mx > -INFINITY ? sm * __expf(mx - nm) : 0.0f) + (om > -INFINITY ? os * __expf(om - nm) : 0.0f);
+        mx = nm;
+    }
+    if (lane == 0) {
+        red[2 * wave] = mx;
+        red[2 * wave + 1] = sm;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        float mx = -INFINITY;
-        for (int v = 0; v < BLOCK; ++v) mx = fmaxf(mx, red[2 * v]);
+        float m4 = -INFINITY;
+        for (int v = 0; v < BLOCK / WAVE; ++v) m4 = fmaxf(m4, red[2 * v]);
         float sum = 0.0f;
-        if (mx > -INFINITY)
-            for (int v = 0; v < BLOCK; ++v)
-                if (red[2 * v] > -INFINITY) sum += red[2 * v + 1] * __expf(red[2 * v] - mx);
-        keys[jobid] = (mx > -INFINITY && sum > 0.0f) ? mx + __logf(sum) - __logf((float)trials)
+        if (m4 > -INFINITY)
+            for (int v = 0; v < BLOCK / WAVE; ++v)
+                if (red[2 * v] > -INFINITY) sum += red[2 * v + 1] * __expf(red[2 * v] - m4);
+        keys[jobid] = (m4 > -INFINITY && sum > 0.0f) ? m4 + __logf(sum) - __logf((float)trials)
                                                      : -INFINITY;
     }
 }
