@@ -13,6 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libhperm.so")
 SOURCES = ["kernels.hip", "expand.cpp", "api.cpp", "serve.cpp"]
+HIP_HOST_SOURCES = {"api.cpp", "serve.cpp"}   # host code that calls the HIP runtime
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # gfx950 only; packed FP32 instructions are disabled for all device code.
@@ -39,7 +40,11 @@ def build(verbose: bool = False) -> str:
         for part in parts:
             stem = os.path.splitext(src)[0] + ("" if part is None else f"_p{part}")
             obj = os.path.join(OUT_DIR, stem + ".o")
-            cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, "-x", "hip"]
+            if src.endswith(".cpp") and src not in HIP_HOST_SOURCES:
+                # plain host C++ (no HIP runtime calls): native popcount for the expansion
+                cmd = [HIPCC, *COMMON, "-mpopcnt", "-x", "c++"]
+            else:
+                cmd = [HIPCC, *COMMON, *DEVICE_FLAGS, "-x", "hip"]
             if part is not None:
                 cmd.append(f"-DHP_PART={part}")
             cmd += ["-c", os.path.join(CSRC, src), "-o", obj]

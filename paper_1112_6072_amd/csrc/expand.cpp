@@ -53,10 +53,32 @@ struct LimitError {};   // the job table outgrew ExpandParams::max_bytes
 // Proven log2 upper bound of per(B) for a non-negative integer matrix: min of the product
 // of row sums and the product of column sums; for a 0-1 matrix also Bregman's bound
 // prod_i (r_i!)^(1/r_i) (rows, and columns by transposition).
+// log2(k!) / k for k = 0..HP_MAX_N (Bregman's factor of a line with k ones; entry 0 unused).
+static const double *bregman_table() {
+    static const std::vector<double> t = [] {
+        std::vector<double> v(HP_MAX_N + 1, 0.0);
+        for (int k = 1; k <= HP_MAX_N; ++k) v[k] = std::lgamma(k + 1.0) / std::log(2.0) / k;
+        return v;
+    }();
+    return t.data();
+}
+
+// log2(x) of a positive integer-valued line sum: a table below 4096 (the values std::log2
+// gives), std::log2 above.
+static inline double log2_sum(double x) {
+    static const std::vector<double> t = [] {
+        std::vector<double> v(4096, 0.0);
+        for (int k = 1; k < 4096; ++k) v[k] = std::log2((double)k);
+        return v;
+    }();
+    return x < 4096.0 ? t[(int)x] : std::log2(x);
+}
+
 double log2_bound(const Node &a) {
     const int m = a.m;
-    std::vector<double> rs(m, 0.0), cs(m, 0.0);
-    std::vector<int> rc(m, 0), cc(m, 0);
+    double rs[HP_MAX_N], cs[HP_MAX_N];
+    int rc[HP_MAX_N], cc[HP_MAX_N];
+    for (int i = 0; i < m; ++i) rs[i] = cs[i] = 0.0, rc[i] = cc[i] = 0;
     bool zero_one = true;
     for (int i = 0; i < m; ++i)
         for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
@@ -66,14 +88,15 @@ double log2_bound(const Node &a) {
             cc[a.ci[e]]++;
             if (a.v[e] != 1) zero_one = false;
         }
+    const double *breg = bregman_table();
     double lr = 0, lc = 0, br = 0, bc = 0;
     for (int i = 0; i < m; ++i) {
         if (rs[i] == 0 || cs[i] == 0) return -INFINITY;
-        lr += std::log2(rs[i]);
-        lc += std::log2(cs[i]);
+        lr += log2_sum(rs[i]);
+        lc += log2_sum(cs[i]);
         if (zero_one) {
-            br += std::lgamma(rc[i] + 1.0) / std::log(2.0) / rc[i];
-            bc += std::lgamma(cc[i] + 1.0) / std::log(2.0) / cc[i];
+            br += breg[rc[i]];
+            bc += breg[cc[i]];
         }
     }
     double b = std::min(lr, lc);
@@ -274,8 +297,8 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
               JobOut *out) {
     const int m = a.m;
     if (m > HP_MAX_M) throw RangeError{"a job exceeds the largest supported order"};
-    std::vector<int> cnt(m, 0);
-    std::vector<uint64_t> colrows(m, 0);
+    int cnt[HP_MAX_M] = {0};
+    uint64_t colrows[HP_MAX_M] = {0};
     for (int i = 0; i < m; ++i)
         for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
             cnt[a.ci[e]]++;
@@ -284,39 +307,46 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
     int fixed = 0;
     for (int j = 1; j < m; ++j)
         if (cnt[j] > cnt[fixed]) fixed = j;
-    std::vector<int> gray;
-    std::vector<char> used(m, 0);
-    used[fixed] = 1;
+    int gray[HP_MAX_M];
+    // greedy choice as a branch-free minimum of keys (new rows, nonzeros, column index)
+    uint64_t avail = (m == 64 ? ~0ull : ((1ull << m) - 1)) & ~(1ull << fixed);
     uint64_t covered = 0;
     for (int g = 0; g + 1 < m; ++g) {
-        int best = -1, bnew = 0;
-        for (int j = 0; j < m; ++j) {
-            if (used[j]) continue;
-            const int nw = __builtin_popcountll(colrows[j] & ~covered);
-            if (best < 0 || nw < bnew || (nw == bnew && cnt[j] < cnt[best])) {
-                best = j;
-                bnew = nw;
-            }
+        uint32_t bestkey = ~0u;
+        for (uint64_t rest = avail; rest; rest &= rest - 1) {
+            const int j = __builtin_ctzll(rest);
+            const uint32_t key = ((uint32_t)__builtin_popcountll(colrows[j] & ~covered) << 16) |
+                                 ((uint32_t)cnt[j] << 8) | (uint32_t)j;
+            bestkey = std::min(bestkey, key);
         }
-        used[best] = 1;
-        gray.push_back(best);
+        const int best = (int)(bestkey & 0xff);
+        avail &= ~(1ull << best);
+        gray[g] = best;
         covered |= colrows[best];
     }
-    std::vector<int> slot(m, -1);
-    for (int g = 0; g < (int)gray.size(); ++g) slot[gray[g]] = g;
-    // row levels and the row order
-    std::vector<int> level(m, m - 1);
-    for (int g = (int)gray.size() - 1; g >= 0; --g)
-        for (int i = 0; i < m; ++i)
-            if (colrows[gray[g]] >> i & 1) level[i] = g;
-    std::vector<int> order(m);
-    for (int i = 0; i < m; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return level[x] < level[y]; });
-    std::vector<int> newrow(m);
+    int slot[HP_MAX_M];
+    for (int j = 0; j < m; ++j) slot[j] = -1;
+    for (int g = 0; g + 1 < m; ++g) slot[gray[g]] = g;
+    // row levels (the first Gray column touching the row; m-1 if none) and the row order:
+    // a stable counting sort by level
+    int level[HP_MAX_M];
+    for (int i = 0; i < m; ++i) level[i] = m - 1;
+    for (int g = m - 2; g >= 0; --g) {
+        uint64_t rows = colrows[gray[g]];
+        while (rows) {
+            const int i = __builtin_ctzll(rows);
+            rows &= rows - 1;
+            level[i] = g;
+        }
+    }
+    int order[HP_MAX_M], newrow[HP_MAX_M], lstart[HP_MAX_M + 1] = {0};
+    for (int i = 0; i < m; ++i) lstart[level[i] + 1]++;
+    for (int g = 0; g < m; ++g) lstart[g + 1] += lstart[g];
+    for (int i = 0; i < m; ++i) order[lstart[level[i]]++] = i;
     for (int r = 0; r < m; ++r) newrow[order[r]] = r;
 
-    std::vector<uint64_t> rsum(m, 0);
-    std::vector<int64_t> bfix(m, 0);
+    uint64_t rsum[HP_MAX_M] = {0};
+    int64_t bfix[HP_MAX_M] = {0};
     int nnz_gray = 0;
     for (int i = 0; i < m; ++i)
         for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
@@ -358,7 +388,7 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
     for (int i = 0; i < m; ++i)
         w[newrow[i]] = (uint32_t)(int32_t)(2 * bfix[i] - (int64_t)rsum[i]);
     // Gray column g holds the entries of original column gray[g]
-    std::vector<int> gcnt(m, 0);
+    int gcnt[HP_MAX_M] = {0};
     for (int i = 0; i < m; ++i)
         for (int e = a.rp[i]; e < a.rp[i + 1]; ++e)
             if (a.ci[e] != fixed) gcnt[slot[a.ci[e]]]++;
@@ -374,13 +404,18 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
     uint32_t *hi = w + 2 * m;
     for (int g = 0; g < m - 1; ++g) {
         int h = 0;
-        for (int i = 0; i < m; ++i)
-            if (colrows[gray[g]] >> i & 1) h = std::max(h, newrow[i] + 1);
+        uint64_t rows = colrows[gray[g]];
+        while (rows) {
+            const int i = __builtin_ctzll(rows);
+            rows &= rows - 1;
+            h = std::max(h, newrow[i] + 1);
+        }
         hi[g] = (uint32_t)h;
     }
     hi[m - 1] = (uint32_t)m;
     uint32_t *ent = w + 3 * m;
-    std::vector<uint32_t> pos(cs, cs + m);
+    uint32_t pos[HP_MAX_M];
+    for (int g = 0; g < m; ++g) pos[g] = cs[g];
     for (int r = 0; r < m; ++r) {
         const int i = order[r];
         for (int e = a.rp[i]; e < a.rp[i + 1]; ++e)
