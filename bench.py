@@ -76,6 +76,57 @@ def cpu_baseline(m_cut: int, budget_s: float = 20.0):
                       f"counted as 2^(m-1) per job like the GPU path"}
 
 
+def serving_leg(hp, W, n_requests: int = 48, seed: int = 7, n_lo: int = 30, n_hi: int = 40):
+    """Continuous batching under a Poisson stream of mixed requests (3-regular, 4-regular and
+    small-integer sparse matrices, n uniform in [n_lo, n_hi]). First the whole stream at once
+    (capacity = requests / makespan), then Poisson arrivals at half that rate; latencies are
+    the library's submit-to-completion times."""
+    import numpy as np
+    reqs = [A for _, A in W.serving_requests(n_requests, seed, n_lo, n_hi)]
+    ctx = hp.Context({"m_cut": 20, "trials": 32, "host_threads": 4})
+    try:
+        ctx.serve_start(4 * n_requests, 4 << 30)
+        def collect(tickets):
+            out = []
+            for t in tickets:
+                try:
+                    out.append(ctx.wait(t, 600.0))
+                except hp.HpermError as e:   # a request outside the supported range
+                    out.append((None, {"t_total_s": float("nan"), "error": e.status}))
+            return out
+
+        t0 = time.perf_counter()
+        tickets = [ctx.submit(A) for A in reqs]
+        burst = collect(tickets)
+        makespan = time.perf_counter() - t0
+        capacity = n_requests / makespan
+        rate = 0.5 * capacity
+        arrivals = W.poisson_arrivals(n_requests, rate, seed + 1)
+        t0 = time.perf_counter()
+        tickets = []
+        for A, ta in zip(reqs, arrivals):
+            delay = ta - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(ctx.submit(A))
+        paced = collect(tickets)
+        wall = time.perf_counter() - t0
+        ctx.serve_stop()
+    finally:
+        ctx.close()
+    lat = np.array([st["t_total_s"] for v, st in paced if v is not None]) * 1e3
+    lat_b = np.array([st["t_total_s"] for v, st in burst if v is not None]) * 1e3
+    same = [v for v, _ in burst] == [v for v, _ in paced]
+    return {"requests": n_requests, "n_range": [n_lo, n_hi],
+            "failed": sum(v is None for v, _ in paced),
+            "mix": "1/3 each: 3-regular 0-1, 4-regular 0-1, 3-permutation union with values 1..4",
+            "capacity_problems_per_s": capacity,
+            "poisson_rate_per_s": rate, "problems_per_s": n_requests / wall,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "burst_p50_ms": float(np.percentile(lat_b, 50)), "burst_p99_ms": float(np.percentile(lat_b, 99)),
+            "burst_and_paced_results_identical": same}
+
+
 def copy_probe(nbytes: int = 256 << 20, reps: int = 3):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -95,6 +146,7 @@ def main():
     ap.add_argument("--trials", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device-to-device copy of 256 MiB three times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -199,6 +251,11 @@ def main():
         extra["plain_terms_per_s"] = plain
     lpt_rate = terms / (rnw_ms * 1e-3)
 
+    serving = None
+    if not args.no_serving:
+        log("serving: burst, then Poisson arrivals at half the measured capacity")
+        serving = serving_leg(hp, W)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -238,6 +295,7 @@ def main():
                      "kernel": f"rnw_persistent ({ring_name}, orders <= {[16, 24, 32, 40][bucket]})",
                      "avg_launch_ms": avg_ms, "alg_slots_per_launch": alg_per_launch},
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     out.update(extra)
     print(json.dumps(out), flush=True)

@@ -322,7 +322,7 @@ struct JobWork {
 };
 static JobWork job_work(const JobDesc &d, const uint32_t *data, int chunk) {
     const int m = d.m;
-    const uint32_t *cs = data + d.data_off + m;
+    const uint32_t *cs = data + hp_data_index(d) + m;
     const uint32_t *hi = cs + m;
     const double L = std::ldexp(1.0, chunk);
     const double chunks = std::ldexp(1.0, m - 1) / L;
@@ -914,7 +914,7 @@ hperm_status hperm_jobs_from_dense(hperm_ctx *c, int32_t count, const int32_t *m
     const int rc = jobs_from_dense(count, m, off, a, expand_params(c->opts), &j->tab, &err);
     if (rc) {
         delete j;
-        return set_error(c, rc == -2 ? HPERM_E_RANGE : HPERM_E_INVALID, err);
+        return set_error(c, rc == -2 ? HPERM_E_RANGE : rc == -3 ? HPERM_E_NOMEM : HPERM_E_INVALID, err);
     }
     j->id = next_jobs_id();
     *out = j;

@@ -370,7 +370,9 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
         throw RangeError{"the requested arithmetic is too narrow for this problem's bound"};
 
     JobDesc d;
-    d.data_off = (uint32_t)out->data.size();
+    const size_t base = hp_align_words(out->data.size());
+    if (base / HP_DATA_ALIGN >= (1ull << 32)) throw LimitError{};
+    d.data_off = (uint32_t)(base / HP_DATA_ALIGN);
     d.m = (uint8_t)m;
     d.arith = (uint8_t)ring;
     d.chunk_log2 = (uint8_t)(prm.chunk_log2 > 0 ? prm.chunk_log2 : default_chunk_log2(m));
@@ -382,7 +384,6 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
     // at most 2^25 work items per job keep the per-job limb sums below 2^64
     if ((int)d.chunk_log2 < m - 32) d.chunk_log2 = (uint8_t)(m - 32);
 
-    const size_t base = out->data.size();
     out->data.resize(base + hp_job_words(m, nnz_gray));
     uint32_t *w = out->data.data() + base;
     for (int i = 0; i < m; ++i)
@@ -669,20 +670,21 @@ int expand_problems(const std::vector<CsrView> &probs, const ExpandParams &prm, 
     std::atomic<int> bad{0};
     run_subtrees(pend, prm, maxn, maxnnz, outs, err, bad);
     if (bad.load()) return bad.load() == 2 ? -3 : -2;
-    size_t nd = out->desc.size(), nw = out->data.size();
+    size_t nd = out->desc.size(), nw = hp_align_words(out->data.size());
     for (auto &o : outs) {
         nd += o.desc.size();
-        nw += o.data.size();
+        nw += hp_align_words(o.data.size());
     }
-    if (nw >= (1ull << 32)) {
-        *err = "the job table exceeds 2^32 data words";
+    if (nw >= ((size_t)HP_DATA_ALIGN << 32)) {
+        *err = "the job table exceeds 2^34 data words";
         return -3;
     }
     out->desc.reserve(nd);
     out->data.reserve(nw);
     out->log2_bound.reserve(nd);
     for (auto &o : outs) {   // append in tree order, freeing each part as it is copied
-        const uint32_t shift = (uint32_t)out->data.size();
+        out->data.resize(hp_align_words(out->data.size()));
+        const uint32_t shift = (uint32_t)(out->data.size() / HP_DATA_ALIGN);
         for (auto d : o.desc) {
             d.data_off += shift;
             out->desc.push_back(d);
@@ -740,9 +742,17 @@ int jobs_from_dense(int count, const int32_t *m, const int64_t *off, const uint3
         } catch (const RangeError &e) {
             *err = e.msg;
             return -2;
+        } catch (const LimitError &) {
+            *err = "the job table exceeds 2^34 data words";
+            return -3;
         }
     }
-    const uint32_t shift = (uint32_t)out->data.size();
+    out->data.resize(hp_align_words(out->data.size()));
+    if ((out->data.size() + jo.data.size()) / HP_DATA_ALIGN >= (1ull << 32)) {
+        *err = "the job table exceeds 2^34 data words";
+        return -3;
+    }
+    const uint32_t shift = (uint32_t)(out->data.size() / HP_DATA_ALIGN);
     for (auto d : jo.desc) {
         d.data_off += shift;
         out->desc.push_back(d);

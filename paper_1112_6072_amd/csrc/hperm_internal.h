@@ -37,14 +37,14 @@ enum : uint8_t { HP_W64 = 0, HP_W128 = 1, HP_RES = 2, HP_NRING = 3 };
 //   [0, m)            base_i as int32
 //   [m, 2m)           col_start[j] for j = 0..m-1: entry offset (relative to the entry
 //                     block) of Gray column j; col_start[m-1] = nnz (end)
-//   [2m, 3m)          hi[j]: number of rows whose level is <= j (hi[m-1] = m)
+//   [2m, 3m)          hi[j]: 1 + the lowest job row of Gray column j (hi[m-1] = m)
 //   [3m, 3m+nnz)      entries of Gray column 0, then 1, ...: (2*b_ij << 8) | i
 //   [3m+nnz, 4m+nnz)  original column index of Gray column g (g < m-1) and of the fixed
 //                     column (slot m-1)
 //   [4m+nnz, 5m+nnz)  original row index of job row i
 //                     (the last two are used only for the estimator's random draws)
 struct JobDesc {
-    uint32_t data_off;
+    uint32_t data_off;   // start of the job's data block in units of HP_DATA_ALIGN words
     uint8_t m;
     uint8_t arith;
     uint8_t chunk_log2;
@@ -55,6 +55,12 @@ struct JobDesc {
 static_assert(sizeof(JobDesc) == 16, "JobDesc layout");
 
 static inline uint32_t hp_job_words(int m, int nnz) { return 5u * (uint32_t)m + (uint32_t)nnz; }
+
+// Data blocks start at multiples of 4 words (16 bytes), so that a 32-bit data_off reaches
+// 2^34 words (64 GiB of job data).
+constexpr uint32_t HP_DATA_ALIGN = 4;
+static inline size_t hp_data_index(const JobDesc &d) { return (size_t)d.data_off * HP_DATA_ALIGN; }
+static inline size_t hp_align_words(size_t n) { return (n + HP_DATA_ALIGN - 1) / HP_DATA_ALIGN * HP_DATA_ALIGN; }
 
 // Per-job accumulator of the kernels: sums of 32-bit limbs of the work items' ring values
 // (integer addition is associative, so the atomic order does not change the result):

@@ -280,7 +280,7 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
     const uint64_t nterms = 1ull << (m - 1);
     const uint64_t L = 1ull << c;
     const uint64_t k0 = (item * WAVE + (uint64_t)lane) * L;
-    const uint32_t *w = data + jd.data_off;
+    const uint32_t *w = data + (size_t)jd.data_off * HP_DATA_ALIGN;
     const uint32_t *cs = w + m;
     const uint32_t *hi = w + 2 * m;
     const uint32_t *ent = w + 3 * m;
@@ -500,7 +500,7 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
     const int gbase = lane - r;               // first lane of the group
     const int m = jd.m;
     const int nnz = (int)jd.nnz;
-    const uint32_t *w = data + jd.data_off;
+    const uint32_t *w = data + (size_t)jd.data_off * HP_DATA_ALIGN;
     const uint32_t *cs = w + m;
     const uint32_t *ent = w + 3 * m;
     const uint32_t *cmap = w + 3 * m + jd.nnz;

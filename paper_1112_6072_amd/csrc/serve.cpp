@@ -203,7 +203,8 @@ struct Serving {
             } else {
                 for (size_t k = 0; k < b->reqs.size(); ++k) {
                     JobTable &t = b->reqs[k]->jobs.tab;
-                    const uint32_t shift = (uint32_t)m.data.size();
+                    m.data.resize(hp_align_words(m.data.size()));
+                    const uint32_t shift = (uint32_t)(m.data.size() / HP_DATA_ALIGN);
                     for (JobDesc d : t.desc) {
                         d.data_off += shift;
                         d.problem = (uint32_t)k;

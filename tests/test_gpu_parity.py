@@ -246,3 +246,26 @@ def test_estimate_tracks_permanent(hperm, ctx):
     for A, key in zip(pats, keys):
         p = per_ryser(A)
         assert abs(float(key) - math.log(p)) < 0.6
+
+
+# ------------------------------------------------------------------ batched n = 80 graphs
+def test_n80_batch_end_to_end(hperm):
+    """The batched configuration: 8 random cubic girth>=5 graphs on 80 vertices in one batch
+    (3.0M jobs of order 20 per graph, 1.3e13 subset-terms in all), exact against the stored
+    oracle values; the LPT and random queue orders agree."""
+    items = W.config_n80(8)
+    say("n80 batch: expand 8 graphs")
+    c = hperm.Context({"m_cut": 20, "max_table_mib": 32768})
+    try:
+        J = c.expand([A for _, A in items])
+        nj, npb = J.info()
+        say("n80 jobs", nj)
+        c.estimate(J, 8, 1)
+        tot, _, _ = c.run(J, "estimate", True)
+        want = [int(GOLDEN[name]) for name, _ in items]
+        assert tot == want
+        say("n80 rnw ms", sum(L["ms"] for L in c.last_launches()))
+        tot2, _, _ = c.run(J, "random", True)
+        assert tot2 == want
+    finally:
+        c.close()
