@@ -8,9 +8,12 @@ HBM: KKLLL keys, non-increasing-estimate queue, persistent R-NW kernels, exact r
 `value` is the R-NW subset-terms of the batch divided by the step time. Reported beside it:
 per(A) wall time from host CSR to exact integers (expansion included, PCIe-inclusive), the
 plain one-launch-per-job comparator in expansion order, other queue orders, the roofline of
-the dominant kernel from HIP events, and the CPU oracle timed on a bounded sample.
+the dominant kernel from HIP events (HBM traffic from the committed counter summary when it
+matches the kernel source), the CPU oracle timed on a bounded sample, and a serving run
+(continuous batching of mixed requests: capacity, then Poisson arrivals with p50/p99 latency).
 
     python bench.py [--steps K] [--warmup W] [--m-cut 20] [--no-cpu-baseline] [--no-plain]
+                    [--no-serving] [--copy-probe]
 """
 import argparse
 import hashlib
