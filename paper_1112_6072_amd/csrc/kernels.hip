@@ -438,9 +438,7 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
 
 // Cube-root exponent of entry (i, j) of trial t of job w: counter (w<<36)|(t<<12)|(i<<6)|j,
 // exponent floor(3 * (x >> 32) / 2^32).
-__device__ __forceinline__ uint32_t kkl_u(uint64_t seed, uint32_t w, uint32_t t, uint32_t i,
-                                          uint32_t j) {
-    const uint64_t k = ((uint64_t)w << 36) | ((uint64_t)t << 12) | ((uint64_t)i << 6) | j;
+__device__ __forceinline__ uint32_t kkl_u_counter(uint64_t seed, uint64_t k) {
     const uint64_t x = splitmix64(seed, k);
     return (uint32_t)(((x >> 32) * 3ull) >> 32);
 }
@@ -489,6 +487,8 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
                                                       float *__restrict__ keys) {
     using Sh = KklShape<MAXM, GROUP>;
     __shared__ __attribute__((aligned(16))) uint8_t mats[(BLOCK / WAVE) * Sh::WAVE_BYTES];
+    __shared__ uint32_t ekey[MAXM * MAXM];   // Gray entries (at most m(m-1)) + m fixed slots
+    __shared__ uint16_t epos[MAXM * MAXM];
     __shared__ float red[2 * (BLOCK / WAVE)];
     if (blockIdx.x >= nlist) return;
     const uint32_t jobid = uni(list[blockIdx.x]);
@@ -507,15 +507,33 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
     const uint32_t *rmap = cmap + m;
     uint8_t *wm = mats + wave * Sh::WAVE_BYTES;
 
-    // fixed-column entries: row i has b_i,fixed = base_i + sum of its Gray entries
-    // (computed once per lane for the row it holds; only its zero test matters)
-    int gsum = 0;
-    for (int e = 0; e < nnz; ++e) {
-        const uint32_t pk = uni(ent[e]);
-        if ((int)(pk & 0xff) == r) gsum += (int)(pk >> 9);
+    // The job's nonzeros once per block: for entry e, the counter bits (original row << 6 |
+    // original column) of its random draw and its byte position in a staged matrix. Gray
+    // entries first, then one slot per row for the fixed column (b_i,fixed = base_i + the
+    // row's Gray entries; a zero entry gets no draw).
+    const int tid = threadIdx.x;
+    for (int col = 0; col < m - 1; ++col) {
+        const uint32_t b = uni(cs[col]);
+        const uint32_t n = uni(cs[col + 1]) - b;
+        const uint32_t ccol = uni(cmap[col]);
+        for (uint32_t q = (uint32_t)tid; q < n; q += BLOCK) {
+            const int row = (int)(ent[b + q] & 0xff);
+            ekey[b + q] = (rmap[row] << 6) | ccol;
+            epos[b + q] = (uint16_t)(row * Sh::LD + col);
+        }
     }
-    const bool fixed_nz = r < m && ((int)w[r < m ? r : 0] + gsum) != 0;
-    const uint32_t fixed_col = uni(cmap[m - 1]);
+    if (tid < m) {
+        int gsum = 0;
+        for (int e = 0; e < nnz; ++e) {
+            const uint32_t pk = ent[e];
+            if ((int)(pk & 0xff) == tid) gsum += (int)(pk >> 9);
+        }
+        const bool nz = ((int)w[tid] + gsum) != 0;
+        ekey[nnz + tid] = nz ? ((rmap[tid] << 6) | cmap[m - 1]) : ~0u;
+        epos[nnz + tid] = (uint16_t)(tid * Sh::LD + (m - 1));
+    }
+    __syncthreads();
+    const int nent = nnz + m;
 
     float run_max = -INFINITY, run_sum = 0.0f;   // per lane; identical within a group
     for (int t0 = wave * Sh::TPW; t0 < trials; t0 += (BLOCK / WAVE) * Sh::TPW) {
@@ -530,20 +548,10 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
             const int tg = t0 + g;
             if (tg >= trials) break;
             uint8_t *mg = wm + g * MAXM * Sh::LD;
-            // Gray column by Gray column: lane q writes the column's q-th nonzero
-            for (int col = 0; col < m - 1; ++col) {
-                const uint32_t b = uni(cs[col]);
-                const uint32_t n = uni(cs[col + 1]) - b;
-                const uint32_t ccol = uni(cmap[col]);
-                for (uint32_t q = (uint32_t)lane; q < n; q += WAVE) {
-                    const int row = (int)(ent[b + q] & 0xff);
-                    const uint32_t u = kkl_u(seed, jobid, (uint32_t)tg, rmap[row], ccol);
-                    mg[row * Sh::LD + col] = (uint8_t)(1 + u);
-                }
-            }
-            if (fixed_nz && grp == g) {
-                const uint32_t u = kkl_u(seed, jobid, (uint32_t)tg, rmap[r], fixed_col);
-                mg[r * Sh::LD + (m - 1)] = (uint8_t)(1 + u);
+            const uint64_t cbase = ((uint64_t)jobid << 36) | ((uint64_t)tg << 12);
+            for (int e = lane; e < nent; e += WAVE) {
+                const uint32_t key = ekey[e];
+                if (key != ~0u) mg[epos[e]] = (uint8_t)(1 + kkl_u_counter(seed, cbase | key));
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -580,8 +588,10 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
                 singular = !ok;
                 const float pm = ok ? pmag : 1.0f;
                 logabs += ok ? 0.5f * __logf(pm) : 0.0f;
-                // factor = B_rk / pivot (zero for used rows and failed groups)
-                const float ir = pr / pm, ii = -pi / pm;
+                // factor = B_rk / pivot (zero for used rows and failed groups); the hardware
+                // reciprocal (about 1 ulp) is ample for a key that only orders the queue
+                const float inv = __builtin_amdgcn_rcpf(pm);
+                const float ir = pr * inv, ii = -pi * inv;
                 const bool upd = ok && !used;
                 const float fr = upd ? re[k] * ir - im[k] * ii : 0.0f;
                 const float fi = upd ? re[k] * ii + im[k] * ir : 0.0f;
