@@ -220,13 +220,13 @@ def main():
     groups = {}
     for ls in launches:
         for L in ls:
-            key = (L["ring"], L["bucket"])
+            key = (L["ring"], L["bucket"], L["variant"])
             g = groups.setdefault(key, {"ms": 0.0, "alg": 0.0, "terms": 0, "n": 0})
             g["ms"] += L["ms"]
             g["alg"] += L["alg_slots"]
             g["terms"] += L["terms"]
             g["n"] += 1
-    (ring, bucket), dom = max(groups.items(), key=lambda kv: kv[1]["ms"])
+    (ring, bucket, variant), dom = max(groups.items(), key=lambda kv: kv[1]["ms"])
     avg_ms = dom["ms"] / dom["n"]
     alg_per_launch = dom["alg"] / dom["n"]
     achieved = alg_per_launch / (avg_ms * 1e-3)
@@ -295,7 +295,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK,
                      "unit": "VALU lane-slots/s", "frac": achieved / ALU_PEAK,
                      "traffic": traffic_from_profile(),
-                     "kernel": f"rnw_persistent ({ring_name}, orders <= {[16, 24, 32, 40][bucket]})",
+                     "kernel": f"rnw_persistent ({ring_name}, orders <= {[16, 24, 32, 40][bucket]}, "
+                               f"{'paired walk' if variant else 'step-pair walk'})",
                      "avg_launch_ms": avg_ms, "alg_slots_per_launch": alg_per_launch},
         "cpu_baseline": cpu,
         "serving": serving,

@@ -60,7 +60,8 @@ class Result(ctypes.Structure):
 
 class LaunchStat(ctypes.Structure):
     _fields_ = [("ring", ctypes.c_int32), ("bucket", ctypes.c_int32), ("n_jobs", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("items", ctypes.c_uint64), ("terms", ctypes.c_uint64),
+                ("persistent", ctypes.c_int32), ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("items", ctypes.c_uint64), ("terms", ctypes.c_uint64),
                 ("row_updates", ctypes.c_uint64), ("alg_slots", ctypes.c_double), ("ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:

@@ -316,23 +316,31 @@ static double ring_add_slots(int ring) { return ring == HP_W64 ? 2.0 : ring == H
 // Algorithmic work of one job for the suffix-product Gray walk: every lane chunk of L = 2^c
 // Gray indices starts with the product of all m row values (m ring multiplies); inside the
 // chunk, column j < c flips L / 2^(j+1) times and each flip updates its nnz(j) row values and
-// re-multiplies the hi[j] suffix products below the changed rows.
+// re-multiplies the hi[j] suffix products below the changed rows; every term is one ring
+// addition. In the paired walk (variant 1) the L / 2 flips of column 0 give way to one pair
+// sum each (two products of rows 0 and 1 and one multiply by the suffix above them: counted
+// as 3 ring multiplies and one ring addition per pair), and the other flips re-multiply only
+// from row 2 up.
 struct JobWork {
-    double mults, updates;
+    double mults, adds, updates;
 };
-static JobWork job_work(const JobDesc &d, const uint32_t *data, int chunk) {
+static JobWork job_work(const JobDesc &d, const uint32_t *data, int chunk, int variant) {
     const int m = d.m;
     const uint32_t *cs = data + hp_data_index(d) + m;
     const uint32_t *hi = cs + m;
     const double L = std::ldexp(1.0, chunk);
     const double chunks = std::ldexp(1.0, m - 1) / L;
-    double mults = m, updates = 0;
+    double mults = m, updates = 0, adds = L;
     for (int j = 0; j < chunk && j + 1 < m; ++j) {
         const double flips = L / std::ldexp(1.0, j + 1);
-        mults += flips * hi[j];
         updates += flips * (cs[j + 1] - cs[j]);
+        if (variant == 1)
+            mults += j == 0 ? flips * 3.0 : flips * std::max(0.0, (double)hi[j] - 2.0);
+        else
+            mults += flips * hi[j];
     }
-    return {chunks * mults, chunks * updates};
+    if (variant == 1) adds = L / 2;
+    return {chunks * mults, chunks * adds, chunks * updates};
 }
 
 // The integer x in [0, p0 p1 p2) with x = (res[2k] + 2^32 res[2k+1]) mod p_k (Garner).
@@ -402,18 +410,22 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     std::vector<uint64_t> &item_end = c->h_items;
     queue.clear();
     item_end.clear();
-    struct Group { int ring, bucket; size_t off, n; uint64_t items; };
-    // one counting pass: group g = (bucket, ring) from the largest bucket and the widest ring
-    // down, each group keeping the chosen order
-    constexpr int NG = 4 * HP_NRING;
-    auto gid = [&](const JobDesc &d) { return (3 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith); };
+    struct Group { int ring, bucket, variant; size_t off, n; uint64_t items; };
+    // one counting pass: group g = (bucket, ring, walk variant) from the largest bucket and
+    // the widest ring down, each group keeping the chosen order
+    constexpr int NV = 2;
+    constexpr int NG = 4 * HP_NRING * NV;
+    auto gid = [&](const JobDesc &d) {
+        return ((3 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith)) * NV + walk_variant(d, d.chunk_log2);
+    };
     size_t cnt[NG + 1] = {0};
     for (const JobDesc &d : dsc) cnt[gid(d) + 1]++;
     for (int g = 0; g < NG; ++g) cnt[g + 1] += cnt[g];
     std::vector<Group> groups;
     for (int g = 0; g < NG; ++g)
         if (cnt[g + 1] > cnt[g])
-            groups.push_back(Group{HP_NRING - 1 - g % HP_NRING, 3 - g / HP_NRING, cnt[g], cnt[g + 1] - cnt[g], 0});
+            groups.push_back(Group{HP_NRING - 1 - (g / NV) % HP_NRING, 3 - g / (NV * HP_NRING), g % NV, cnt[g],
+                                   cnt[g + 1] - cnt[g], 0});
     queue.resize(nd);
     item_end.resize(nd);
     {
@@ -479,10 +491,13 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         if (s) return s;
         if (j->work_mults.size() != nd) {
             j->work_mults.resize(nd);
+            j->work_adds.resize(nd);
             j->work_updates.resize(nd);
             for (size_t k = 0; k < nd; ++k) {
-                const JobWork wk = job_work(dsc[k], j->tab.data.data(), dsc[k].chunk_log2);
+                const JobWork wk = job_work(dsc[k], j->tab.data.data(), dsc[k].chunk_log2,
+                                            walk_variant(dsc[k], dsc[k].chunk_log2));
                 j->work_mults[k] = wk.mults;
+                j->work_adds[k] = wk.adds;
                 j->work_updates[k] = wk.updates;
             }
         }
@@ -493,20 +508,22 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             st.bucket = g.bucket;
             st.n_jobs = (int32_t)g.n;
             st.persistent = 1;
+            st.variant = g.variant;
             st.items = g.items;
-            double mults = 0.0, updates = 0.0;
+            double mults = 0.0, adds = 0.0, updates = 0.0;
             for (size_t q = g.off; q < g.off + g.n; ++q) {
                 const uint32_t k = queue[q];
                 st.terms += 1ull << (dsc[k].m - 1);
                 mults += j->work_mults[k];
+                adds += j->work_adds[k];
                 updates += j->work_updates[k];
             }
             st.row_updates = (uint64_t)updates;
-            st.alg_slots = mults * ring_mul_slots(g.ring) + (double)st.terms * ring_add_slots(g.ring) + updates;
+            st.alg_slots = mults * ring_mul_slots(g.ring) + adds * ring_add_slots(g.ring) + updates;
             c->launches.push_back(st);
             s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
             if (s) return s;
-            s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, d_desc, d_data,
+            s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,
                                                    (const uint32_t *)c->buf[B_QUEUE].ptr + g.off,
                                                    (const uint64_t *)c->buf[B_ITEMS].ptr + g.off,
                                                    (uint32_t)g.n, g.items, head + gi, accs, 0, c->stream),
@@ -519,7 +536,8 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         // one launch per job, natural order
         for (size_t k = 0; k < nd; ++k) {
             const JobDesc &d = desc_plain[k];
-            s = hip_check(c, launch_rnw_single(d.arith, bucket_of(d.m), d_desc, d_data, (uint32_t)k,
+            const int v = walk_variant(d, d.chunk_log2);
+            s = hip_check(c, launch_rnw_single(d.arith, bucket_of(d.m), v, d_desc, d_data, (uint32_t)k,
                                                items_of(d.m, d.chunk_log2), accs, c->stream),
                           "rnw_single launch");
             if (s) return s;
@@ -531,11 +549,11 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         for (size_t k = 0; k < nd; ++k) {
             const JobDesc &d = desc_plain[k];
             const uint64_t t = 1ull << (d.m - 1);
-            const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2);
+            const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2, walk_variant(d, d.chunk_log2));
             st.items += items_of(d.m, d.chunk_log2);
             st.terms += t;
             st.row_updates += (uint64_t)wk.updates;
-            st.alg_slots += wk.mults * ring_mul_slots(d.arith) + (double)t * ring_add_slots(d.arith) + wk.updates;
+            st.alg_slots += wk.mults * ring_mul_slots(d.arith) + wk.adds * ring_add_slots(d.arith) + wk.updates;
         }
         c->launches.push_back(st);   // all single launches as one record (ms = whole span)
     }

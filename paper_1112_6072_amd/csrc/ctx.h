@@ -34,7 +34,7 @@ struct hperm_jobs {
     uint64_t id = 0;           // identity for device residency
     // per-job algorithmic work of the persistent walk (ring multiplies, row updates), filled
     // on the first run
-    std::vector<double> work_mults, work_updates;
+    std::vector<double> work_mults, work_adds, work_updates;
 };
 
 namespace hp {

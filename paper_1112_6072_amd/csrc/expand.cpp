@@ -414,6 +414,7 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
         hi[g] = (uint32_t)h;
     }
     hi[m - 1] = (uint32_t)m;
+    if (m >= 2 && hi[0] <= 2) d.flags |= HP_FLAG_COL0_TWO_ROWS;
     uint32_t *ent = w + 3 * m;
     uint32_t pos[HP_MAX_M];
     for (int g = 0; g < m; ++g) pos[g] = cs[g];

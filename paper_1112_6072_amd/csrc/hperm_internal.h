@@ -48,11 +48,14 @@ struct JobDesc {
     uint8_t m;
     uint8_t arith;
     uint8_t chunk_log2;
-    uint8_t flags;
+    uint8_t flags;       // HP_FLAG_* bits
     uint32_t nnz;
     uint32_t problem;
 };
 static_assert(sizeof(JobDesc) == 16, "JobDesc layout");
+
+// JobDesc::flags: Gray column 0 reaches only job rows 0 and 1 (hi[0] <= 2).
+constexpr uint8_t HP_FLAG_COL0_TWO_ROWS = 1;
 
 static inline uint32_t hp_job_words(int m, int nnz) { return 5u * (uint32_t)m + (uint32_t)nnz; }
 

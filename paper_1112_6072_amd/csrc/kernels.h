@@ -21,33 +21,42 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
                            const uint32_t *list, uint32_t nlist, int trials, uint64_t seed,
                            float *keys, hipStream_t s);
 
-// Persistent R-NW over the queued jobs of one ring (queue[nqueue] job ids in scheduling
-// order, item_end[nqueue] inclusive prefix sums of their item counts). *head must be 0.
-hipError_t launch_rnw_persistent(int ring, int bucket, const JobDesc *jobs, const uint32_t *data,
-                                 const uint32_t *queue, const uint64_t *item_end, uint32_t nqueue,
-                                 uint64_t total_items, unsigned long long *head, JobAcc *accs,
-                                 int grid_override, hipStream_t s);
+// Walk variant of a job for the R-NW kernels: 1 for mod 2^64 jobs whose Gray column 0 reaches
+// at most the first 2 rows and whose lane chunk holds at least 2 Gray indices (the paired
+// walk), else 0.
+int walk_variant(const JobDesc &d, int chunk_log2);
+
+// Persistent R-NW over the queued jobs of one ring, order bucket and walk variant (queue[nqueue]
+// job ids in scheduling order, item_end[nqueue] inclusive prefix sums of their item counts).
+// *head must be 0.
+hipError_t launch_rnw_persistent(int ring, int bucket, int variant, const JobDesc *jobs,
+                                 const uint32_t *data, const uint32_t *queue,
+                                 const uint64_t *item_end, uint32_t nqueue, uint64_t total_items,
+                                 unsigned long long *head, JobAcc *accs, int grid_override,
+                                 hipStream_t s);
 
 // R-NW of one job in one launch (nitems waves).
-hipError_t launch_rnw_single(int ring, int bucket, const JobDesc *jobs, const uint32_t *data, uint32_t job,
-                             uint64_t nitems, JobAcc *accs, hipStream_t s);
+hipError_t launch_rnw_single(int ring, int bucket, int variant, const JobDesc *jobs,
+                             const uint32_t *data, uint32_t job, uint64_t nitems, JobAcc *accs,
+                             hipStream_t s);
 
 // Per-ring entry points (one object file per ring).
 #define HP_RING_DECL(sfx)                                                                       \
-    hipError_t persistent_grid_##sfx(int bucket, int *grid);                                    \
-    hipError_t launch_rnw_persistent_##sfx(int bucket, const JobDesc *jobs, const uint32_t *data, \
-                                           const uint32_t *queue, const uint64_t *item_end,     \
-                                           uint32_t nqueue, uint64_t total_items,               \
-                                           unsigned long long *head, JobAcc *accs, int grid,    \
-                                           hipStream_t s);                                      \
-    hipError_t launch_rnw_single_##sfx(int bucket, const JobDesc *jobs, const uint32_t *data,   \
-                                       uint32_t job, uint64_t nitems, JobAcc *accs, hipStream_t s);
+    hipError_t persistent_grid_##sfx(int bucket, int variant, int *grid);                       \
+    hipError_t launch_rnw_persistent_##sfx(int bucket, int variant, const JobDesc *jobs,        \
+                                           const uint32_t *data, const uint32_t *queue,         \
+                                           const uint64_t *item_end, uint32_t nqueue,           \
+                                           uint64_t total_items, unsigned long long *head,      \
+                                           JobAcc *accs, int grid, hipStream_t s);              \
+    hipError_t launch_rnw_single_##sfx(int bucket, int variant, const JobDesc *jobs,            \
+                                       const uint32_t *data, uint32_t job, uint64_t nitems,     \
+                                       JobAcc *accs, hipStream_t s);
 HP_RING_DECL(w64)
 HP_RING_DECL(w128)
 HP_RING_DECL(res)
 #undef HP_RING_DECL
 
 // Resident grid (blocks) of the persistent kernel variant.
-hipError_t persistent_grid(int ring, int bucket, int *grid);
+hipError_t persistent_grid(int ring, int bucket, int variant, int *grid);
 
 }  // namespace hp

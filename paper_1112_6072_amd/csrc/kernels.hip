@@ -269,10 +269,54 @@ __device__ __forceinline__ uint32_t block_of(uint32_t h) {
         HP_BLOCK(0)                                                                        \
     }
 
-template <class R, int MAXM>
+// Row-value update of block B only (no product), for the rows below the pair boundary in
+// the paired walk below: they take the column-0 flip of the pair (direction dir0) and this
+// flip together.
+#define HP_BLOCK_F(B)                                                                      \
+    if ((B) < NB) {                                                                        \
+        const int lo_ = blk_lo(B), w_ = blk_top(B) - blk_lo(B);                            \
+        _Pragma("unroll") for (int r_ = 3; r_ >= 0; --r_) {                                \
+            const int I_ = lo_ + r_;                                                       \
+            if (r_ < w_ && I_ < MAXM)                                                      \
+                f[I_] = __builtin_fmaf(dj[I_], dir, __builtin_fmaf(tab[I_], dir0, f[I_])); \
+        }                                                                                  \
+    }
+
+// A flip in the paired walk: blocks 1 and up are recomputed in full, block 0 (rows 0 and 1,
+// below the pair boundary) only gets its new row values.
+#define HP_FLIP_P(TOP, DJ, DIR)                                                            \
+    {                                                                                      \
+        const uint32_t top_ = (TOP);                                                       \
+        const float *const dj = (DJ);                                                      \
+        const float dir_ = (DIR);                                                          \
+        const float dir = dir_;                                                            \
+        const uint32_t top = top_;                                                         \
+        if (top >= 5) {                                                                    \
+            _Pragma("unroll") for (int B = NB - 1; B >= 5; --B) if ((int)top >= B) {       \
+                HP_BLOCK(B)                                                                \
+            }                                                                              \
+        }                                                                                  \
+        if (top >= 4) { HP_BLOCK(4) }                                                      \
+        if (top >= 3) { HP_BLOCK(3) }                                                      \
+        if (top >= 2) { HP_BLOCK(2) }                                                      \
+        if (top >= 1) {                                                                    \
+            HP_BLOCK(1)                                                                    \
+        }                                                                                  \
+        HP_BLOCK_F(0)                                                                      \
+    }
+
+// V = 0: the walk in step pairs below, for every job. V = 1 (mod 2^64 jobs whose column 0
+// reaches only the first two rows, lane chunks of at least 2 Gray indices): the paired
+// walk, in which the two terms of a pair (t even, t + 1) are summed as
+//   sign(G_b) * S_b * (P_t - P_{t+1}),  b = V + 1,
+// where P_t and P_{t+1} are the signed products of rows 0 .. b-1 before and after the flip
+// of column 0 (small integers: exact as 64-bit products) and S_b, G_b the suffix product and
+// sign word above them; the other flips recompute S and G only from row b up.
+template <class R, int MAXM, int V>
 __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__restrict__ data,
                                          uint64_t item, int lane, JobAcc *dst, float *tab) {
     static_assert(MAXM <= 40, "job orders up to 40");
+    static_assert(V == 0 || V == 1, "walk variant");
     constexpr int STRIDE = Tab<MAXM>::STRIDE;
     constexpr int NB = Blocks<MAXM>::N;
     const int m = jd.m;
@@ -345,28 +389,55 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
     typename R::Acc acc = R::acc_zero();
     const uint32_t last = (uint32_t)L - 1u;
     const uint32_t top0 = (uint32_t)tops & 15u;
-    // Steps come in pairs: an even term, the flip of column 0 (every other step; its top
-    // block is fixed for the item), an odd term, then the flip of column j = ctz(t+1) >= 1.
-    for (uint32_t t = 0;; ++t) {
-        R::acc(acc, S[0], (uint32_t)((int)G[0] >> 31));   // even t: (-1)^t = +1
-        if (t == last) break;
-        {
-            const float dir0 = c == 1 ? dir_last : (((t + 1) >> 1) & 1 ? -1.0f : 1.0f);
-            HP_FLIP(top0, tab, dir0)
+    if constexpr (V == 0) {
+        // Steps come in pairs: an even term, the flip of column 0 (every other step; its top
+        // block is fixed for the item), an odd term, then the flip of column j = ctz(t+1) >= 1.
+        for (uint32_t t = 0;; ++t) {
+            R::acc(acc, S[0], (uint32_t)((int)G[0] >> 31));   // even t: (-1)^t = +1
+            if (t == last) break;
+            {
+                const float dir0 = c == 1 ? dir_last : (((t + 1) >> 1) & 1 ? -1.0f : 1.0f);
+                HP_FLIP(top0, tab, dir0)
+            }
+            ++t;
+            R::acc(acc, S[0], ~(uint32_t)((int)G[0] >> 31));   // odd t: (-1)^t = -1
+            if (t == last) break;
+            {
+                const int j = __builtin_ctz(t + 1);
+                const float dir_uni = ((t + 1) >> (j + 1)) & 1 ? -1.0f : 1.0f;
+                const float dirj = j == c - 1 ? dir_last : dir_uni;
+                HP_FLIP((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj)
+            }
         }
-        ++t;
-        R::acc(acc, S[0], ~(uint32_t)((int)G[0] >> 31));   // odd t: (-1)^t = -1
-        if (t == last) break;
-        {
-            const int j = __builtin_ctz(t + 1);
-            const float dir_uni = ((t + 1) >> (j + 1)) & 1 ? -1.0f : 1.0f;
-            const float dirj = j == c - 1 ? dir_last : dir_uni;
-            HP_FLIP((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj)
+    } else {
+        constexpr int PB = V + 1;   // rows 0 .. PB-1 below the pair boundary
+        for (uint32_t t = 0;; t += 2) {
+            // the pair (t, t + 1) around the flip of column 0; the rows below the boundary
+            // keep their values of term t until the next flip applies both changes
+            const float dir0 = c == 1 ? dir_last : (((t + 1) >> 1) & 1 ? -1.0f : 1.0f);
+            int64_t pa = (int64_t)(int)f[0];
+            int64_t pb = (int64_t)(int)__builtin_fmaf(tab[0], dir0, f[0]);
+#pragma unroll
+            for (int i = 1; i < PB; ++i) {
+                pa *= (int64_t)(int)f[i];
+                pb *= (int64_t)(int)__builtin_fmaf(tab[i], dir0, f[i]);
+            }
+            const typename R::P pair = {S[PB].v * (uint64_t)(pa - pb)};
+            R::acc(acc, pair, (uint32_t)((int)G[PB] >> 31));
+            if (t + 1 == last) break;
+            {
+                const int j = __builtin_ctz(t + 2);
+                const float dir_uni = ((t + 2) >> (j + 1)) & 1 ? -1.0f : 1.0f;
+                const float dirj = j == c - 1 ? dir_last : dir_uni;
+                HP_FLIP_P((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj)
+            }
         }
     }
     if (k0 >= nterms) acc = R::acc_zero();   // lanes past the end of a short job contribute nothing
     R::flush(acc, dst, lane);
 }
+#undef HP_FLIP_P
+#undef HP_BLOCK_F
 #undef HP_FLIP
 #undef HP_BLOCK
 
@@ -375,7 +446,7 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
 // queue is the list of jobs in scheduling order; item_end[s] is the number of items of
 // the first s+1 queued jobs (jobs own contiguous item ranges). Every queued job has
 // order at most MAXM (the host queues jobs by order bucket).
-template <class R, int MAXM>
+template <class R, int MAXM, int V>
 __global__ __launch_bounds__(BLOCK) void rnw_persistent(const JobDesc *__restrict__ jobs,
                                                         const uint32_t *__restrict__ data,
                                                         const uint32_t *__restrict__ queue,
@@ -404,12 +475,12 @@ __global__ __launch_bounds__(BLOCK) void rnw_persistent(const JobDesc *__restric
         const uint64_t first = lo ? uni64(item_end[lo - 1]) : 0;
         const uint32_t job = uni(queue[lo]);
         const JobDesc jd = load_job(jobs, job);
-        rnw_item<R, MAXM>(jd, data, g - first, lane, accs + job, tab);
+        rnw_item<R, MAXM, V>(jd, data, g - first, lane, accs + job, tab);
     }
 }
 
 // One launch per job (the plain comparator): wave w of the grid evaluates item w.
-template <class R, int MAXM>
+template <class R, int MAXM, int V>
 __global__ __launch_bounds__(BLOCK) void rnw_single(const JobDesc *__restrict__ jobs,
                                                     const uint32_t *__restrict__ data,
                                                     uint32_t job, uint64_t nitems,
@@ -420,7 +491,7 @@ __global__ __launch_bounds__(BLOCK) void rnw_single(const JobDesc *__restrict__ 
     const uint64_t w = (uint64_t)blockIdx.x * (BLOCK / WAVE) + (threadIdx.x >> 6);
     if (w >= nitems) return;
     const JobDesc jd = load_job(jobs, job);
-    rnw_item<R, MAXM>(jd, data, w, lane, accs + job, tab);
+    rnw_item<R, MAXM, V>(jd, data, w, lane, accs + job, tab);
 }
 
 #endif  // HP_PART >= 1
@@ -765,6 +836,10 @@ namespace hp {
 
 int bucket_of(int m) { return m <= 16 ? 0 : (m <= 24 ? 1 : (m <= 32 ? 2 : 3)); }
 
+int walk_variant(const JobDesc &d, int chunk_log2) {
+    return d.arith == HP_W64 && chunk_log2 >= 1 && (d.flags & HP_FLAG_COL0_TWO_ROWS) ? 1 : 0;
+}
+
 hipError_t launch_recombine(const JobDesc *jobs, const JobAcc *accs, uint32_t njobs,
                             ProbAcc *probs, hipStream_t s) {
     if (njobs == 0) return hipSuccess;
@@ -808,92 +883,104 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
 #define CAT2(a, b) a##_##b
 #define CAT(a, b) CAT2(a, b)
 
-static const void *persistent_fn(int bucket) {
+// Kernel of an order bucket and walk variant (the paired walk exists for mod 2^64 only).
+#if HP_PART == 1
+#define HP_FN(K, MAXM) (variant == 1 ? (const void *)K<RING_T, MAXM, 1> : (const void *)K<RING_T, MAXM, 0>)
+#else
+#define HP_FN(K, MAXM) (const void *)K<RING_T, MAXM, 0>
+#endif
+static const void *persistent_fn(int bucket, int variant) {
+    (void)variant;
     switch (bucket) {
-        case 0: return (const void *)rnw_persistent<RING_T, 16>;
-        case 1: return (const void *)rnw_persistent<RING_T, 24>;
-        case 2: return (const void *)rnw_persistent<RING_T, 32>;
-        default: return (const void *)rnw_persistent<RING_T, HP_MAX_M>;
+        case 0: return HP_FN(rnw_persistent, 16);
+        case 1: return HP_FN(rnw_persistent, 24);
+        case 2: return HP_FN(rnw_persistent, 32);
+        default: return HP_FN(rnw_persistent, HP_MAX_M);
     }
 }
-static const void *single_fn(int bucket) {
+static const void *single_fn(int bucket, int variant) {
+    (void)variant;
     switch (bucket) {
-        case 0: return (const void *)rnw_single<RING_T, 16>;
-        case 1: return (const void *)rnw_single<RING_T, 24>;
-        case 2: return (const void *)rnw_single<RING_T, 32>;
-        default: return (const void *)rnw_single<RING_T, HP_MAX_M>;
+        case 0: return HP_FN(rnw_single, 16);
+        case 1: return HP_FN(rnw_single, 24);
+        case 2: return HP_FN(rnw_single, 32);
+        default: return HP_FN(rnw_single, HP_MAX_M);
     }
 }
+#undef HP_FN
 
-hipError_t CAT(persistent_grid, RING_SUFFIX)(int bucket, int *grid) {
+hipError_t CAT(persistent_grid, RING_SUFFIX)(int bucket, int variant, int *grid) {
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_fn(bucket), BLOCK, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_fn(bucket, variant), BLOCK, 0);
     if (e != hipSuccess) return e;
     *grid = cus * (per_cu > 0 ? per_cu : 1);
     return hipSuccess;
 }
 
-hipError_t CAT(launch_rnw_persistent, RING_SUFFIX)(int bucket, const JobDesc *jobs,
+hipError_t CAT(launch_rnw_persistent, RING_SUFFIX)(int bucket, int variant, const JobDesc *jobs,
                                                     const uint32_t *data, const uint32_t *queue,
                                                     const uint64_t *item_end, uint32_t nqueue,
                                                     uint64_t total_items, unsigned long long *head,
                                                     JobAcc *accs, int grid, hipStream_t s) {
     void *args[] = {(void *)&jobs, (void *)&data, (void *)&queue, (void *)&item_end,
                     (void *)&nqueue, (void *)&total_items, (void *)&head, (void *)&accs};
-    hipError_t e = hipLaunchKernel(persistent_fn(bucket), dim3(grid), dim3(BLOCK), args, 0, s);
+    hipError_t e = hipLaunchKernel(persistent_fn(bucket, variant), dim3(grid), dim3(BLOCK), args, 0, s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
-hipError_t CAT(launch_rnw_single, RING_SUFFIX)(int bucket, const JobDesc *jobs,
+hipError_t CAT(launch_rnw_single, RING_SUFFIX)(int bucket, int variant, const JobDesc *jobs,
                                                 const uint32_t *data, uint32_t job, uint64_t nitems,
                                                 JobAcc *accs, hipStream_t s) {
     const uint64_t blocks = (nitems + (BLOCK / WAVE) - 1) / (BLOCK / WAVE);
     void *args[] = {(void *)&jobs, (void *)&data, (void *)&job, (void *)&nitems, (void *)&accs};
-    hipError_t e = hipLaunchKernel(single_fn(bucket), dim3((uint32_t)blocks), dim3(BLOCK), args, 0, s);
+    hipError_t e = hipLaunchKernel(single_fn(bucket, variant), dim3((uint32_t)blocks), dim3(BLOCK), args, 0, s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 #endif  // HP_PART >= 1
 
 #if HP_PART == 0
-hipError_t persistent_grid(int ring, int bucket, int *grid) {
+hipError_t persistent_grid(int ring, int bucket, int variant, int *grid) {
     switch (ring) {
-        case HP_W64: return persistent_grid_w64(bucket, grid);
-        case HP_W128: return persistent_grid_w128(bucket, grid);
-        default: return persistent_grid_res(bucket, grid);
+        case HP_W64: return persistent_grid_w64(bucket, variant, grid);
+        case HP_W128: return persistent_grid_w128(bucket, 0, grid);
+        default: return persistent_grid_res(bucket, 0, grid);
     }
 }
 
-hipError_t launch_rnw_persistent(int ring, int bucket, const JobDesc *jobs, const uint32_t *data,
-                                 const uint32_t *queue, const uint64_t *item_end, uint32_t nqueue,
-                                 uint64_t total_items, unsigned long long *head, JobAcc *accs,
-                                 int grid_override, hipStream_t s) {
+hipError_t launch_rnw_persistent(int ring, int bucket, int variant, const JobDesc *jobs,
+                                 const uint32_t *data, const uint32_t *queue,
+                                 const uint64_t *item_end, uint32_t nqueue, uint64_t total_items,
+                                 unsigned long long *head, JobAcc *accs, int grid_override,
+                                 hipStream_t s) {
     if (nqueue == 0 || total_items == 0) return hipSuccess;
+    if (ring != HP_W64) variant = 0;
     int grid = 0;
-    hipError_t e = persistent_grid(ring, bucket, &grid);
+    hipError_t e = persistent_grid(ring, bucket, variant, &grid);
     if (e != hipSuccess) return e;
     if (grid_override > 0) grid = grid_override;
     const uint64_t max_blocks = (total_items + (BLOCK / WAVE) - 1) / (BLOCK / WAVE);
     if ((uint64_t)grid > max_blocks) grid = (int)max_blocks;
     switch (ring) {
-        case HP_W64: return launch_rnw_persistent_w64(bucket, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
-        case HP_W128: return launch_rnw_persistent_w128(bucket, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
-        default: return launch_rnw_persistent_res(bucket, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
+        case HP_W64: return launch_rnw_persistent_w64(bucket, variant, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
+        case HP_W128: return launch_rnw_persistent_w128(bucket, 0, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
+        default: return launch_rnw_persistent_res(bucket, 0, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
     }
 }
 
-hipError_t launch_rnw_single(int ring, int bucket, const JobDesc *jobs, const uint32_t *data,
-                             uint32_t job, uint64_t nitems, JobAcc *accs, hipStream_t s) {
+hipError_t launch_rnw_single(int ring, int bucket, int variant, const JobDesc *jobs,
+                             const uint32_t *data, uint32_t job, uint64_t nitems, JobAcc *accs,
+                             hipStream_t s) {
     if (nitems == 0) return hipSuccess;
     switch (ring) {
-        case HP_W64: return launch_rnw_single_w64(bucket, jobs, data, job, nitems, accs, s);
-        case HP_W128: return launch_rnw_single_w128(bucket, jobs, data, job, nitems, accs, s);
-        default: return launch_rnw_single_res(bucket, jobs, data, job, nitems, accs, s);
+        case HP_W64: return launch_rnw_single_w64(bucket, variant, jobs, data, job, nitems, accs, s);
+        case HP_W128: return launch_rnw_single_w128(bucket, 0, jobs, data, job, nitems, accs, s);
+        default: return launch_rnw_single_res(bucket, 0, jobs, data, job, nitems, accs, s);
     }
 }
 #endif  // HP_PART == 0
