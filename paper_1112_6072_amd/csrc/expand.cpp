@@ -293,10 +293,59 @@ struct JobOut {
 // the first Gray column touching them (rows touched by none come last). Then a flip of Gray
 // column j changes only rows below hi[j] = 1 + the lowest row of column j (at most the number
 // of rows of level <= j), and the kernels recompute only the suffix products of those rows.
-void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &prm,
-              JobOut *out) {
+static void emit_job_oriented(const Node &a, int problem, double root_log2, const ExpandParams &prm,
+                              bool transposed, JobOut *out);
+
+// Transpose of a node (CSR of the transposed matrix, columns sorted within a row).
+static void transpose_node(const Node &a, Node *t) {
+    const int m = a.m;
+    t->reserve(m, a.nnz);
+    t->m = m;
+    t->nnz = a.nnz;
+    int cnt[HP_MAX_M + 1] = {0};
+    for (int e = 0; e < a.nnz; ++e) cnt[a.ci[e] + 1]++;
+    for (int j = 0; j < m; ++j) cnt[j + 1] += cnt[j];
+    for (int j = 0; j <= m; ++j) t->rp[j] = cnt[j];
+    for (int i = 0; i < m; ++i)
+        for (int e = a.rp[i]; e < a.rp[i + 1]; ++e) {
+            const int pos = cnt[a.ci[e]]++;
+            t->ci[pos] = (uint8_t)i;
+            t->v[pos] = a.v[e];
+        }
+}
+
+// Orientation of a job: per(B) = per(B^T), so a job is emitted transposed when that lets its
+// first Gray column (the sparsest line other than the densest, fixed one) reach at most two
+// rows while the untransposed job's cannot; the kernels' paired walk then applies.
+void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &prm, JobOut *out) {
     const int m = a.m;
     if (m > HP_MAX_M) throw RangeError{"a job exceeds the largest supported order"};
+    if (m >= 3) {
+        int cc[HP_MAX_M] = {0}, rc[HP_MAX_M];
+        for (int e = 0; e < a.nnz; ++e) cc[a.ci[e]]++;
+        for (int i = 0; i < m; ++i) rc[i] = a.rp[i + 1] - a.rp[i];
+        auto sparsest_but_densest = [m](const int *c) {
+            int fixed = 0;
+            for (int j = 1; j < m; ++j)
+                if (c[j] > c[fixed]) fixed = j;
+            int best = INT32_MAX;
+            for (int j = 0; j < m; ++j)
+                if (j != fixed) best = std::min(best, c[j]);
+            return best;
+        };
+        if (sparsest_but_densest(cc) > 2 && sparsest_but_densest(rc) <= 2) {
+            Node t;
+            transpose_node(a, &t);
+            emit_job_oriented(t, problem, root_log2, prm, true, out);
+            return;
+        }
+    }
+    emit_job_oriented(a, problem, root_log2, prm, false, out);
+}
+
+static void emit_job_oriented(const Node &a, int problem, double root_log2, const ExpandParams &prm,
+                              bool transposed, JobOut *out) {
+    const int m = a.m;
     int cnt[HP_MAX_M] = {0};
     uint64_t colrows[HP_MAX_M] = {0};
     for (int i = 0; i < m; ++i)
@@ -415,6 +464,7 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
     }
     hi[m - 1] = (uint32_t)m;
     if (m >= 2 && hi[0] <= 2) d.flags |= HP_FLAG_COL0_TWO_ROWS;
+    if (transposed) d.flags |= HP_FLAG_TRANSPOSED;
     uint32_t *ent = w + 3 * m;
     uint32_t pos[HP_MAX_M];
     for (int g = 0; g < m; ++g) pos[g] = cs[g];
@@ -427,7 +477,8 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
             }
     }
     // original column of every job column (Gray slots, then the fixed one) and original row
-    // of every job row: only the estimator's random draws use them
+    // of every job row (of the transposed matrix when the job is transposed): only the
+    // estimator's random draws use them
     uint32_t *cm = w + 3 * m + nnz_gray;
     for (int g = 0; g < m - 1; ++g) cm[g] = (uint32_t)gray[g];
     cm[m - 1] = (uint32_t)fixed;

@@ -579,17 +579,19 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
     uint8_t *wm = mats + wave * Sh::WAVE_BYTES;
 
     // The job's nonzeros once per block: for entry e, the counter bits (original row << 6 |
-    // original column) of its random draw and its byte position in a staged matrix. Gray
+    // original column, of the untransposed sub-matrix) of its random draw and its byte
+    // position in a staged matrix. Gray
     // entries first, then one slot per row for the fixed column (b_i,fixed = base_i + the
     // row's Gray entries; a zero entry gets no draw).
     const int tid = threadIdx.x;
+    const bool tr = (jd.flags & HP_FLAG_TRANSPOSED) != 0;   // draws follow the untransposed job
     for (int col = 0; col < m - 1; ++col) {
         const uint32_t b = uni(cs[col]);
         const uint32_t n = uni(cs[col + 1]) - b;
         const uint32_t ccol = uni(cmap[col]);
         for (uint32_t q = (uint32_t)tid; q < n; q += BLOCK) {
             const int row = (int)(ent[b + q] & 0xff);
-            ekey[b + q] = (rmap[row] << 6) | ccol;
+            ekey[b + q] = tr ? ((ccol << 6) | rmap[row]) : ((rmap[row] << 6) | ccol);
             epos[b + q] = (uint16_t)(row * Sh::LD + col);
         }
     }
@@ -600,7 +602,7 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
             if ((int)(pk & 0xff) == tid) gsum += (int)(pk >> 9);
         }
         const bool nz = ((int)w[tid] + gsum) != 0;
-        ekey[nnz + tid] = nz ? ((rmap[tid] << 6) | cmap[m - 1]) : ~0u;
+        ekey[nnz + tid] = !nz ? ~0u : tr ? ((cmap[m - 1] << 6) | rmap[tid]) : ((rmap[tid] << 6) | cmap[m - 1]);
         epos[nnz + tid] = (uint16_t)(tid * Sh::LD + (m - 1));
     }
     __syncthreads();
