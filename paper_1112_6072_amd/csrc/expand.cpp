@@ -548,9 +548,11 @@ struct Pending {
 }  // namespace
 
 int default_chunk_log2(int m) {
-    // lanes walk 2^c Gray indices; one work item = 64 lanes
+    // lanes walk 2^c Gray indices (one work item = 64 lanes): one item per job up to order 19,
+    // then the largest chunk the kernels' delta tables hold (the per-item set-up is then
+    // spread over 4096 steps)
     int c = m - 1 - 6;
-    if (c > 10) c = 10;
+    if (c > 12) c = 12;
     if (c < 0) c = 0;
     return c;
 }
