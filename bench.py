@@ -130,6 +130,28 @@ def serving_leg(hp, W, n_requests: int = 48, seed: int = 7, n_lo: int = 30, n_hi
             "burst_and_paced_results_identical": same}
 
 
+def uneven_orders(hp, W, ctx, n_jobs: int = 600, seed: int = 11):
+    """Queue orders on uneven jobs: n_jobs job-like matrices (unions of 3 to 6 random
+    permutations, values 1..4) of orders uniform in 16..30, in one persistent launch per
+    order bucket; R-NW milliseconds per order (the results are checked equal)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    mats = [W.permutation_union_matrix(int(rng.integers(16, 31)), int(rng.integers(3, 7)),
+                                       int(rng.integers(0, 2 ** 31 - 1)), 1, 4) for _ in range(n_jobs)]
+    J = ctx.jobs_from_dense(mats)
+    ctx.estimate(J, 32, 1)
+    out, ref = {}, None
+    for order in ("estimate", "exact_cost", "natural", "random"):
+        tot, _, _ = ctx.run(J, order, True)
+        ref = tot if ref is None else ref
+        assert tot == ref
+        out[order + "_ms"] = sum(L["ms"] for L in ctx.last_launches())
+    d = J.describe()
+    out["jobs"] = n_jobs
+    out["subset_terms"] = int(d["terms"].astype(np.float64).sum())
+    return out
+
+
 def copy_probe(nbytes: int = 256 << 20, reps: int = 3):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -238,6 +260,7 @@ def main():
     for order in ("natural", "random", "exact_cost"):
         ctx.run(jobs, order, True)
         extra[f"persistent_{order}_rnw_ms"] = sum(L["ms"] for L in ctx.last_launches())
+    extra["uneven_jobs"] = uneven_orders(hp, W, ctx)
     plain = None
     if not args.no_plain:
         log("plain: one launch per job, expansion order (best lane chunk of 3, 5, 7)")

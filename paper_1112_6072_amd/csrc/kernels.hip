@@ -85,7 +85,10 @@ struct RingW64 {
 
 struct RingW128 {
     struct P { uint32_t x0, x1, x2, x3; };
-    struct Acc { unsigned __int128 v; uint32_t n; };
+    // The accumulator keeps four independent 64-bit sums of the 32-bit limbs of (p xor mask)
+    // (no carry chain between limbs per term; a lane adds at most 2^12 terms, so each sum
+    // stays below 2^44) and the count of the +1s of the negations.
+    struct Acc { uint64_t s0, s1, s2, s3; uint32_t n; };
     __device__ static P one() { return {1, 0, 0, 0}; }
     __device__ static void mul(P &p, uint32_t u) {
         const uint64_t t0 = (uint64_t)p.x0 * u;
@@ -94,16 +97,18 @@ struct RingW128 {
         const uint32_t t3 = p.x3 * u + (uint32_t)(t2 >> 32);
         p = {(uint32_t)t0, (uint32_t)t1, (uint32_t)t2, t3};
     }
-    __device__ static Acc acc_zero() { return {0, 0}; }
+    __device__ static Acc acc_zero() { return {0, 0, 0, 0, 0}; }
     __device__ static void acc(Acc &a, const P &p, uint32_t mask) {
-        const unsigned __int128 q = ((unsigned __int128)(p.x3 ^ mask) << 96) |
-                                    ((unsigned __int128)(p.x2 ^ mask) << 64) |
-                                    ((unsigned __int128)(p.x1 ^ mask) << 32) | (p.x0 ^ mask);
-        a.v += q;
+        a.s0 += p.x0 ^ mask;
+        a.s1 += p.x1 ^ mask;
+        a.s2 += p.x2 ^ mask;
+        a.s3 += p.x3 ^ mask;
         a.n -= mask;
     }
     __device__ static void flush(const Acc &a, JobAcc *dst, int lane) {
-        const unsigned __int128 v = a.v + a.n;
+        // the lane's value sum_k s_k 2^(32k) + n (mod 2^128), renormalised into 32-bit limbs
+        const unsigned __int128 v = (unsigned __int128)a.s0 + ((unsigned __int128)a.s1 << 32) +
+                                    ((unsigned __int128)a.s2 << 64) + ((unsigned __int128)a.s3 << 96) + a.n;
         const uint64_t s0 = wave_sum64((uint32_t)v), s1 = wave_sum64((uint32_t)(v >> 32));
         const uint64_t s2 = wave_sum64((uint32_t)(v >> 64)), s3 = wave_sum64((uint32_t)(v >> 96));
         if (lane == 0) {
