@@ -233,8 +233,8 @@ typedef struct hperm_launch_stat {
     int32_t bucket;         /* kernel instantiation: job orders <= 16, 24, 32, 40 */
     int32_t n_jobs;         /* jobs in the launch (1 in one-launch-per-job mode) */
     int32_t persistent;
-    int32_t variant;        /* walk variant: 0, or 1 for the paired walk of mod 2^64 jobs
-                               whose Gray column 0 reaches only the first 2 rows */
+    int32_t variant;        /* walk variant: 0, or 1 / 2 for the paired walk of mod 2^64 jobs
+                               whose Gray column 0 reaches only the first 2 / 3 rows */
     int32_t reserved;
     uint64_t items;         /* work items (64 lanes x 2^chunk Gray indices each) */
     uint64_t terms;         /* subset-terms: sum of 2^(m-1) over the jobs */
@@ -244,10 +244,10 @@ typedef struct hperm_launch_stat {
                                multiplies to start, then for each flip of Gray column j < c
                                its nnz(j) row updates (1 slot each) and hi[j] ring multiplies
                                (hi[j] = 1 + the lowest row of Gray column j); plus one ring
-                               addition per term. In the paired walk (variant 1) each flip of
-                               column 0 is replaced by one pair sum (3 ring multiplies, one
-                               ring addition per two terms) and the other flips multiply only
-                               hi[j] - 2 rows. One ring multiply by a 32-bit factor costs mul = 5
+                               addition per term. In the paired walk (variant v, b = v + 1)
+                               each flip of column 0 is replaced by one pair sum (2(b-1) + 1
+                               ring multiplies, one ring addition per two terms) and the other
+                               flips multiply only hi[j] - b rows. One ring multiply by a 32-bit factor costs mul = 5
                                (mod 2^64), 9 (mod 2^128) or 3 * 11 (residues) slots and one
                                ring addition add = 2, 4 or 3 * 3 slots; v_mad_u64_u32 and
                                v_mul_lo_u32 count 2 slots (half rate), other ops 1 */

@@ -317,10 +317,10 @@ static double ring_add_slots(int ring) { return ring == HP_W64 ? 2.0 : ring == H
 // Gray indices starts with the product of all m row values (m ring multiplies); inside the
 // chunk, column j < c flips L / 2^(j+1) times and each flip updates its nnz(j) row values and
 // re-multiplies the hi[j] suffix products below the changed rows; every term is one ring
-// addition. In the paired walk (variant 1) the L / 2 flips of column 0 give way to one pair
-// sum each (two products of rows 0 and 1 and one multiply by the suffix above them: counted
-// as 3 ring multiplies and one ring addition per pair), and the other flips re-multiply only
-// from row 2 up.
+// addition. In the paired walk (variant v = 1, 2; b = v + 1 rows below the pair boundary) the
+// L / 2 flips of column 0 give way to one pair sum each (two products of b rows and one
+// multiply by the suffix above them: 2(b - 1) + 1 ring multiplies and one ring addition per
+// pair), and the other flips re-multiply only from row b up.
 struct JobWork {
     double mults, adds, updates;
 };
@@ -334,12 +334,14 @@ static JobWork job_work(const JobDesc &d, const uint32_t *data, int chunk, int v
     for (int j = 0; j < chunk && j + 1 < m; ++j) {
         const double flips = L / std::ldexp(1.0, j + 1);
         updates += flips * (cs[j + 1] - cs[j]);
-        if (variant == 1)
-            mults += j == 0 ? flips * 3.0 : flips * std::max(0.0, (double)hi[j] - 2.0);
-        else
+        if (variant > 0) {
+            const double b = variant + 1;
+            mults += j == 0 ? flips * (2.0 * (b - 1.0) + 1.0) : flips * std::max(0.0, (double)hi[j] - b);
+        } else {
             mults += flips * hi[j];
+        }
     }
-    if (variant == 1) adds = L / 2;
+    if (variant > 0) adds = L / 2;
     return {chunks * mults, chunks * adds, chunks * updates};
 }
 
@@ -413,7 +415,7 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     struct Group { int ring, bucket, variant; size_t off, n; uint64_t items; };
     // one counting pass: group g = (bucket, ring, walk variant) from the largest bucket and
     // the widest ring down, each group keeping the chosen order
-    constexpr int NV = 2;
+    constexpr int NV = 3;
     constexpr int NG = 4 * HP_NRING * NV;
     auto gid = [&](const JobDesc &d) {
         return ((3 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith)) * NV + walk_variant(d, d.chunk_log2);

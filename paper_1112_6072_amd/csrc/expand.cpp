@@ -464,6 +464,7 @@ static void emit_job_oriented(const Node &a, int problem, double root_log2, cons
     }
     hi[m - 1] = (uint32_t)m;
     if (m >= 2 && hi[0] <= 2) d.flags |= HP_FLAG_COL0_TWO_ROWS;
+    else if (m >= 3 && hi[0] == 3) d.flags |= HP_FLAG_COL0_THREE_ROWS;
     if (transposed) d.flags |= HP_FLAG_TRANSPOSED;
     uint32_t *ent = w + 3 * m;
     uint32_t pos[HP_MAX_M];

@@ -58,6 +58,7 @@ static_assert(sizeof(JobDesc) == 16, "JobDesc layout");
 // the transpose of the expansion's sub-matrix (same permanent; the estimator then swaps row
 // and column in its draws so that they follow the sub-matrix).
 constexpr uint8_t HP_FLAG_COL0_TWO_ROWS = 1;
+constexpr uint8_t HP_FLAG_COL0_THREE_ROWS = 2;   // hi[0] = 3
 constexpr uint8_t HP_FLAG_TRANSPOSED = 4;
 
 static inline uint32_t hp_job_words(int m, int nnz) { return 5u * (uint32_t)m + (uint32_t)nnz; }

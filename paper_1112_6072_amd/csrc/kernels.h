@@ -21,9 +21,9 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
                            const uint32_t *list, uint32_t nlist, int trials, uint64_t seed,
                            float *keys, hipStream_t s);
 
-// Walk variant of a job for the R-NW kernels: 1 for mod 2^64 jobs whose Gray column 0 reaches
-// at most the first 2 rows and whose lane chunk holds at least 2 Gray indices (the paired
-// walk), else 0.
+// Walk variant of a job for the R-NW kernels: 1 (2) for mod 2^64 jobs whose Gray column 0
+// reaches at most the first 2 (exactly the first 3) rows and whose lane chunk holds at least
+// 2 Gray indices (the paired walk), else 0.
 int walk_variant(const JobDesc &d, int chunk_log2);
 
 // Persistent R-NW over the queued jobs of one ring, order bucket and walk variant (queue[nqueue]

@@ -287,8 +287,9 @@ __device__ __forceinline__ uint32_t block_of(uint32_t h) {
         }                                                                                  \
     }
 
-// A flip in the paired walk: blocks 1 and up are recomputed in full, block 0 (rows 0 and 1,
-// below the pair boundary) only gets its new row values.
+// A flip in the paired walk: blocks V and up are recomputed in full, the blocks below the
+// pair boundary (rows 0 .. V) only get their new row values, always (they also carry the
+// pair's column-0 change).
 #define HP_FLIP_P(TOP, DJ, DIR)                                                            \
     {                                                                                      \
         const uint32_t top_ = (TOP);                                                       \
@@ -304,14 +305,16 @@ __device__ __forceinline__ uint32_t block_of(uint32_t h) {
         if (top >= 4) { HP_BLOCK(4) }                                                      \
         if (top >= 3) { HP_BLOCK(3) }                                                      \
         if (top >= 2) { HP_BLOCK(2) }                                                      \
-        if (top >= 1) {                                                                    \
-            HP_BLOCK(1)                                                                    \
+        if (V == 1) {                                                                      \
+            if (top >= 1) { HP_BLOCK(1) }                                                  \
+        } else {                                                                           \
+            HP_BLOCK_F(1)                                                                  \
         }                                                                                  \
         HP_BLOCK_F(0)                                                                      \
     }
 
-// V = 0: the walk in step pairs below, for every job. V = 1 (mod 2^64 jobs whose column 0
-// reaches only the first two rows, lane chunks of at least 2 Gray indices): the paired
+// V = 0: the walk in step pairs below, for every job. V = 1, 2 (mod 2^64 jobs whose column 0
+// reaches only the first V + 1 rows, lane chunks of at least 2 Gray indices): the paired
 // walk, in which the two terms of a pair (t even, t + 1) are summed as
 //   sign(G_b) * S_b * (P_t - P_{t+1}),  b = V + 1,
 // where P_t and P_{t+1} are the signed products of rows 0 .. b-1 before and after the flip
@@ -321,7 +324,7 @@ template <class R, int MAXM, int V>
 __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__restrict__ data,
                                          uint64_t item, int lane, JobAcc *dst, float *tab) {
     static_assert(MAXM <= 40, "job orders up to 40");
-    static_assert(V == 0 || V == 1, "walk variant");
+    static_assert(V == 0 || V == 1 || V == 2, "walk variant");
     constexpr int STRIDE = Tab<MAXM>::STRIDE;
     constexpr int NB = Blocks<MAXM>::N;
     const int m = jd.m;
@@ -416,27 +419,33 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
         }
     } else {
         constexpr int PB = V + 1;   // rows 0 .. PB-1 below the pair boundary
-        for (uint32_t t = 0;; t += 2) {
-            // the pair (t, t + 1) around the flip of column 0; the rows below the boundary
-            // keep their values of term t until the next flip applies both changes
-            const float dir0 = c == 1 ? dir_last : (((t + 1) >> 1) & 1 ? -1.0f : 1.0f);
-            int64_t pa = (int64_t)(int)f[0];
-            int64_t pb = (int64_t)(int)__builtin_fmaf(tab[0], dir0, f[0]);
-#pragma unroll
-            for (int i = 1; i < PB; ++i) {
-                pa *= (int64_t)(int)f[i];
-                pb *= (int64_t)(int)__builtin_fmaf(tab[i], dir0, f[i]);
-            }
-            const typename R::P pair = {S[PB].v * (uint64_t)(pa - pb)};
-            R::acc(acc, pair, (uint32_t)((int)G[PB] >> 31));
-            if (t + 1 == last) break;
-            {
-                const int j = __builtin_ctz(t + 2);
-                const float dir_uni = ((t + 2) >> (j + 1)) & 1 ? -1.0f : 1.0f;
-                const float dirj = j == c - 1 ? dir_last : dir_uni;
-                HP_FLIP_P((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj)
-            }
+        // The pair (t, t + 1) around the flip of column 0: the rows below the boundary keep
+        // their values of term t until the next flip applies both changes. The loop is
+        // rotated (flip, then pair) so that it has a single exit at its end.
+#define HP_PAIR()                                                                          \
+    {                                                                                      \
+        int64_t pa = (int64_t)(int)f[0];                                                   \
+        int64_t pb = (int64_t)(int)__builtin_fmaf(tab[0], dir0, f[0]);                     \
+        _Pragma("unroll") for (int i = 1; i < PB; ++i) {                                   \
+            pa *= (int64_t)(int)f[i];                                                      \
+            pb *= (int64_t)(int)__builtin_fmaf(tab[i], dir0, f[i]);                        \
+        }                                                                                  \
+        const typename R::P pair = {S[PB].v * (uint64_t)(pa - pb)};                        \
+        R::acc(acc, pair, (uint32_t)((int)G[PB] >> 31));                                   \
+    }
+        uint32_t t = 0;
+        float dir0 = c == 1 ? dir_last : 1.0f;   // the first column-0 flip sets bit 0
+        HP_PAIR()
+        while (t + 1 != last) {
+            const int j = __builtin_ctz(t + 2);
+            const float dir_uni = ((t + 2) >> (j + 1)) & 1 ? -1.0f : 1.0f;
+            const float dirj = j == c - 1 ? dir_last : dir_uni;
+            HP_FLIP_P((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj)
+            t += 2;
+            dir0 = ((t + 1) >> 1) & 1 ? -1.0f : 1.0f;
+            HP_PAIR()
         }
+#undef HP_PAIR
     }
     if (k0 >= nterms) acc = R::acc_zero();   // lanes past the end of a short job contribute nothing
     R::flush(acc, dst, lane);
@@ -844,7 +853,8 @@ namespace hp {
 int bucket_of(int m) { return m <= 16 ? 0 : (m <= 24 ? 1 : (m <= 32 ? 2 : 3)); }
 
 int walk_variant(const JobDesc &d, int chunk_log2) {
-    return d.arith == HP_W64 && chunk_log2 >= 1 && (d.flags & HP_FLAG_COL0_TWO_ROWS) ? 1 : 0;
+    if (d.arith != HP_W64 || chunk_log2 < 1) return 0;
+    return (d.flags & HP_FLAG_COL0_TWO_ROWS) ? 1 : (d.flags & HP_FLAG_COL0_THREE_ROWS) ? 2 : 0;
 }
 
 hipError_t launch_recombine(const JobDesc *jobs, const JobAcc *accs, uint32_t njobs,
@@ -892,7 +902,9 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
 
 // Kernel of an order bucket and walk variant (the paired walk exists for mod 2^64 only).
 #if HP_PART == 1
-#define HP_FN(K, MAXM) (variant == 1 ? (const void *)K<RING_T, MAXM, 1> : (const void *)K<RING_T, MAXM, 0>)
+#define HP_FN(K, MAXM)                                                                     \
+    (variant == 1 ? (const void *)K<RING_T, MAXM, 1>                                       \
+                  : variant == 2 ? (const void *)K<RING_T, MAXM, 2> : (const void *)K<RING_T, MAXM, 0>)
 #else
 #define HP_FN(K, MAXM) (const void *)K<RING_T, MAXM, 0>
 #endif
