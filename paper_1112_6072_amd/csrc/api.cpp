@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <thread>
 
 #include "ctx.h"
 #include "kernels.h"
@@ -859,27 +860,57 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
     if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
     if (!c || !out) return HPERM_E_INVALID;
     if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
+    if (count < 0 || (count > 0 && (!n || !rp_off || !nz_off))) return set_error(c, HPERM_E_INVALID, "bad batch arrays");
     std::lock_guard<std::mutex> lk(c->call_mu);
     c->dev.last_error.clear();
     c->dev.opts = c->opts;
     const double t0 = now_s();
-    hperm_jobs j;
-    hperm_status s = expand_batch(c, count, n, rp_off, nz_off, row_ptr, col_idx, val, &j);
-    if (s) return s;
-    const double t1 = now_s();
-    double t_est = 0.0;
-    if (!j.tab.desc.empty() && (c->opts.order == HPERM_ORDER_ESTIMATE || c->opts.order == HPERM_ORDER_EXACT_COST)) {
-        s = estimate_jobs(&c->dev, &j, c->opts.trials, c->opts.seed);
-        if (s) return s;
-        t_est = now_s() - t1;
+    // Problems are processed in up to four groups: the host expands group g + 1 on a thread of
+    // its own while the device estimates and evaluates group g (each group has its own queue
+    // in the chosen order). One group when the batch is small or runs one launch per job.
+    const int groups = (c->opts.persistent && count >= 4) ? 4 : 1;
+    std::vector<hperm_result> res(std::max(count, 1));   // copied to out only on success
+    std::vector<hperm_jobs> tabs(groups);
+    std::vector<hperm_status> est(groups, HPERM_OK);
+    std::vector<double> t_exp(groups, 0.0);
+    auto lo = [&](int g) { return (int)((int64_t)count * g / groups); };
+    auto expand_group = [&](int g) {
+        const double ta = now_s();
+        est[g] = expand_batch(c, lo(g + 1) - lo(g), n + lo(g), rp_off + lo(g), nz_off + lo(g), row_ptr,
+                              col_idx, val, &tabs[g]);
+        t_exp[g] = now_s() - ta;
+    };
+    expand_group(0);
+    double t_est = 0.0, t_rnw_all = 0.0;
+    hperm_status s = est[0];
+    for (int g = 0; g < groups && !s; ++g) {
+        std::thread next;
+        if (g + 1 < groups) next = std::thread(expand_group, g + 1);
+        hperm_jobs &j = tabs[g];
+        if (!j.tab.desc.empty() && (c->opts.order == HPERM_ORDER_ESTIMATE || c->opts.order == HPERM_ORDER_EXACT_COST)) {
+            const double ta = now_s();
+            s = estimate_jobs(&c->dev, &j, c->opts.trials, c->opts.seed);
+            t_est += now_s() - ta;
+        }
+        double t_rnw = 0.0;
+        if (!s) s = run_jobs(&c->dev, &j, c->opts.order, c->opts.persistent, nullptr, res.data() + lo(g), &t_rnw);
+        t_rnw_all += t_rnw;
+        j = hperm_jobs();   // release the group's host table
+        if (next.joinable()) next.join();
+        if (!s && g + 1 < groups) s = est[g + 1];
     }
-    double t_rnw = 0.0;
-    s = run_jobs(&c->dev, &j, c->opts.order, c->opts.persistent, nullptr, out, &t_rnw);
-    if (s) return s;
+    if (s) {
+        if (c->dev.last_error.empty()) c->dev.last_error = "batch failed";
+        return s;
+    }
     const double t2 = now_s();
+    double t_exp_all = 0.0;
+    for (double t : t_exp) t_exp_all += t;
     for (int k = 0; k < count; ++k) {
-        out[k].t_expand_s = t1 - t0;
+        out[k] = res[k];
+        out[k].t_expand_s = t_exp_all;
         out[k].t_estimate_s = t_est;
+        out[k].t_rnw_s = t_rnw_all;
         out[k].t_total_s = t2 - t0;
     }
     return HPERM_OK;
