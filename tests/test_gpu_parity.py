@@ -269,3 +269,22 @@ def test_n80_batch_end_to_end(hperm):
         assert tot2 == want
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 5])
+def test_paired_walk_small_chunks(hperm, chunk):
+    """Jobs of cubic graphs take the paired walk (column 0 reaching two or three rows, some
+    jobs transposed); with lane chunks of 2 and 4 Gray indices the pair straddles the
+    lane-dependent direction of the chunk's last column. Job by job against the oracle."""
+    A = W.random_cubic_matrix(24, 7)
+    say("paired walk, chunk", chunk)
+    c = hperm.Context({"m_cut": 14, "chunk_log2": chunk})
+    try:
+        J = c.expand([A])
+        totals, per_job, _ = c.run(J, "natural", True, per_job=True)
+        variants = {L["variant"] for L in c.last_launches()}
+    finally:
+        c.close()
+    assert per_job == native.ryser_batch(expand_leaves(A, 14), threads=8)
+    assert totals == [int(GOLDEN["cubic24_seed7"])]
+    assert variants & {1, 2}
