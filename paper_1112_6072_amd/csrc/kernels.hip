@@ -51,6 +51,23 @@ __device__ __forceinline__ JobDesc load_job(const JobDesc *jobs, uint32_t j) {
     return jd;
 }
 
+// x mod p for p = 2^61 - C (residue ring and Step 4 normalisation).
+template <uint64_t C>
+__device__ __forceinline__ uint64_t mod61(unsigned __int128 x) {
+    constexpr uint64_t P = (1ull << 61) - C;
+    // x < 2^122: fold 2^61 = C twice (the second fold leaves less than 2P), then subtract
+    uint64_t lo = (uint64_t)x & ((1ull << 61) - 1);
+    unsigned __int128 hi = x >> 61;
+    unsigned __int128 y = (unsigned __int128)lo + hi * C;
+    lo = (uint64_t)y & ((1ull << 61) - 1);
+    uint64_t h2 = (uint64_t)(y >> 61);
+    uint64_t z = lo + h2 * C;   // y < 2^68, so h2 < 2^7 and z < 2P
+    return z >= P ? z - P : z;
+}
+template <uint64_t C>
+__device__ __forceinline__ uint64_t mulmod_full(uint64_t a, uint64_t b) {
+    return mod61<C>((unsigned __int128)a * b);
+}
 #if HP_PART >= 1
 // ------------------------------------------------------------------------ rings
 // A ring multiplies a non-negative product by |f_i| (unsigned, below 2^24) and adds or
@@ -58,8 +75,13 @@ __device__ __forceinline__ JobDesc load_job(const JobDesc *jobs, uint32_t j) {
 // parity of the negative factors and the Gray sign (-1)^k) and arrives as a mask: all ones
 // for a negative term, zero for a positive one.
 
+// pair_mul(s, d): s times the signed integer d (|d| < 2^74) in the ring; the paired walk's
+// sum of two terms is S_b * (P_t - P_{t+1}). Small is wide enough for the products P of up to
+// three row values (exact below 2^72; mod 2^64 wrap-around is exact for that ring).
 struct RingW64 {
     struct P { uint64_t v; };
+    using Small = int64_t;
+    __device__ static P pair_mul(const P &s, Small d) { return {s.v * (uint64_t)d}; }
     // -p = (p xor ~0) + 1: the accumulator adds p xor mask and counts the +1s apart
     struct Acc { uint64_t v; uint32_t n; };
     __device__ static P one() { return {1}; }
@@ -85,6 +107,12 @@ struct RingW64 {
 
 struct RingW128 {
     struct P { uint32_t x0, x1, x2, x3; };
+    using Small = __int128;
+    __device__ static P pair_mul(const P &s, Small d) {
+        const unsigned __int128 v = (((unsigned __int128)s.x3 << 96) | ((unsigned __int128)s.x2 << 64) |
+                                     ((unsigned __int128)s.x1 << 32) | s.x0) * (unsigned __int128)d;
+        return {(uint32_t)v, (uint32_t)(v >> 32), (uint32_t)(v >> 64), (uint32_t)(v >> 96)};
+    }
     // The accumulator keeps four independent 64-bit sums of the 32-bit limbs of (p xor mask)
     // (no carry chain between limbs per term; a lane adds at most 2^12 terms, so each sum
     // stays below 2^44) and the count of the +1s of the negations.
@@ -139,9 +167,22 @@ __device__ __forceinline__ uint64_t addmod61(uint64_t a, uint64_t b, uint32_t ne
     return s >= P ? s - P : s;
 }
 
+template <uint64_t C>
+__device__ __forceinline__ uint64_t mulmod_signed(uint64_t r, __int128 d) {
+    constexpr uint64_t P = (1ull << 61) - C;
+    const bool neg = d < 0;
+    uint64_t a = mod61<C>((unsigned __int128)(neg ? -d : d));
+    if (neg && a) a = P - a;
+    return mulmod_full<C>(r, a);
+}
+
 struct RingRes {
     struct P { uint64_t r0, r1, r2; };
     using Acc = P;
+    using Small = __int128;
+    __device__ static P pair_mul(const P &s, Small d) {
+        return {mulmod_signed<HP_C0>(s.r0, d), mulmod_signed<HP_C1>(s.r1, d), mulmod_signed<HP_C2>(s.r2, d)};
+    }
     __device__ static P one() { return {1, 1, 1}; }
     __device__ static void mul(P &p, uint32_t u) {
         p.r0 = mulmod61<HP_C0>(p.r0, u);
@@ -313,12 +354,12 @@ __device__ __forceinline__ uint32_t block_of(uint32_t h) {
         HP_BLOCK_F(0)                                                                      \
     }
 
-// V = 0: the walk in step pairs below, for every job. V = 1, 2 (mod 2^64 jobs whose column 0
-// reaches only the first V + 1 rows, lane chunks of at least 2 Gray indices): the paired
-// walk, in which the two terms of a pair (t even, t + 1) are summed as
+// V = 0: the walk in step pairs below, for every job. V = 1, 2 (jobs whose column 0 reaches
+// only the first V + 1 rows, lane chunks of at least 2 Gray indices): the paired walk, in
+// which the two terms of a pair (t even, t + 1) are summed as
 //   sign(G_b) * S_b * (P_t - P_{t+1}),  b = V + 1,
 // where P_t and P_{t+1} are the signed products of rows 0 .. b-1 before and after the flip
-// of column 0 (small integers: exact as 64-bit products) and S_b, G_b the suffix product and
+// of column 0 (small integers, exact in the ring's Small type) and S_b, G_b the suffix product and
 // sign word above them; the other flips recompute S and G only from row b up.
 template <class R, int MAXM, int V>
 __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__restrict__ data,
@@ -424,13 +465,14 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
         // rotated (flip, then pair) so that it has a single exit at its end.
 #define HP_PAIR()                                                                          \
     {                                                                                      \
-        int64_t pa = (int64_t)(int)f[0];                                                   \
-        int64_t pb = (int64_t)(int)__builtin_fmaf(tab[0], dir0, f[0]);                     \
+        using Sm = typename R::Small;                                                      \
+        Sm pa = (Sm)(int)f[0];                                                             \
+        Sm pb = (Sm)(int)__builtin_fmaf(tab[0], dir0, f[0]);                               \
         _Pragma("unroll") for (int i = 1; i < PB; ++i) {                                   \
-            pa *= (int64_t)(int)f[i];                                                      \
-            pb *= (int64_t)(int)__builtin_fmaf(tab[i], dir0, f[i]);                        \
+            pa *= (Sm)(int)f[i];                                                           \
+            pb *= (Sm)(int)__builtin_fmaf(tab[i], dir0, f[i]);                             \
         }                                                                                  \
-        const typename R::P pair = {S[PB].v * (uint64_t)(pa - pb)};                        \
+        const typename R::P pair = R::pair_mul(S[PB], pa - pb);                            \
         R::acc(acc, pair, (uint32_t)((int)G[PB] >> 31));                                   \
     }
         uint32_t t = 0;
@@ -740,22 +782,6 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
 //   residues: per mod p_k = (-1)^(m-1) (2^-1)^(m-1) V mod p_k, added as 32-bit halves into
 //   res[2k], res[2k+1]; the host reduces the sums and applies the CRT.
 template <uint64_t C>
-__device__ __forceinline__ uint64_t mod61(unsigned __int128 x) {
-    constexpr uint64_t P = (1ull << 61) - C;
-    // x < 2^96: fold 2^61 = C twice, then subtract
-    uint64_t lo = (uint64_t)x & ((1ull << 61) - 1);
-    unsigned __int128 hi = x >> 61;
-    unsigned __int128 y = (unsigned __int128)lo + hi * C;
-    lo = (uint64_t)y & ((1ull << 61) - 1);
-    uint64_t h2 = (uint64_t)(y >> 61);
-    uint64_t z = lo + h2 * C;   // y < 2^62, so h2 <= 1 and z < 2P
-    return z >= P ? z - P : z;
-}
-template <uint64_t C>
-__device__ __forceinline__ uint64_t mulmod_full(uint64_t a, uint64_t b) {
-    return mod61<C>((unsigned __int128)a * b);
-}
-template <uint64_t C>
 __device__ __forceinline__ uint64_t res_normalise(uint64_t lo_sum, uint64_t hi_sum, int m) {
     constexpr uint64_t P = (1ull << 61) - C;
     constexpr uint64_t INV2 = (P + 1) / 2;
@@ -853,7 +879,7 @@ namespace hp {
 int bucket_of(int m) { return m <= 16 ? 0 : (m <= 24 ? 1 : (m <= 32 ? 2 : 3)); }
 
 int walk_variant(const JobDesc &d, int chunk_log2) {
-    if (d.arith != HP_W64 || chunk_log2 < 1) return 0;
+    if (chunk_log2 < 1) return 0;
     return (d.flags & HP_FLAG_COL0_TWO_ROWS) ? 1 : (d.flags & HP_FLAG_COL0_THREE_ROWS) ? 2 : 0;
 }
 
@@ -900,16 +926,11 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
 #define CAT2(a, b) a##_##b
 #define CAT(a, b) CAT2(a, b)
 
-// Kernel of an order bucket and walk variant (the paired walk exists for mod 2^64 only).
-#if HP_PART == 1
+// Kernel of an order bucket and walk variant.
 #define HP_FN(K, MAXM)                                                                     \
     (variant == 1 ? (const void *)K<RING_T, MAXM, 1>                                       \
                   : variant == 2 ? (const void *)K<RING_T, MAXM, 2> : (const void *)K<RING_T, MAXM, 0>)
-#else
-#define HP_FN(K, MAXM) (const void *)K<RING_T, MAXM, 0>
-#endif
 static const void *persistent_fn(int bucket, int variant) {
-    (void)variant;
     switch (bucket) {
         case 0: return HP_FN(rnw_persistent, 16);
         case 1: return HP_FN(rnw_persistent, 24);
@@ -918,7 +939,6 @@ static const void *persistent_fn(int bucket, int variant) {
     }
 }
 static const void *single_fn(int bucket, int variant) {
-    (void)variant;
     switch (bucket) {
         case 0: return HP_FN(rnw_single, 16);
         case 1: return HP_FN(rnw_single, 24);
@@ -967,8 +987,8 @@ hipError_t CAT(launch_rnw_single, RING_SUFFIX)(int bucket, int variant, const Jo
 hipError_t persistent_grid(int ring, int bucket, int variant, int *grid) {
     switch (ring) {
         case HP_W64: return persistent_grid_w64(bucket, variant, grid);
-        case HP_W128: return persistent_grid_w128(bucket, 0, grid);
-        default: return persistent_grid_res(bucket, 0, grid);
+        case HP_W128: return persistent_grid_w128(bucket, variant, grid);
+        default: return persistent_grid_res(bucket, variant, grid);
     }
 }
 
@@ -978,7 +998,6 @@ hipError_t launch_rnw_persistent(int ring, int bucket, int variant, const JobDes
                                  unsigned long long *head, JobAcc *accs, int grid_override,
                                  hipStream_t s) {
     if (nqueue == 0 || total_items == 0) return hipSuccess;
-    if (ring != HP_W64) variant = 0;
     int grid = 0;
     hipError_t e = persistent_grid(ring, bucket, variant, &grid);
     if (e != hipSuccess) return e;
@@ -987,8 +1006,8 @@ hipError_t launch_rnw_persistent(int ring, int bucket, int variant, const JobDes
     if ((uint64_t)grid > max_blocks) grid = (int)max_blocks;
     switch (ring) {
         case HP_W64: return launch_rnw_persistent_w64(bucket, variant, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
-        case HP_W128: return launch_rnw_persistent_w128(bucket, 0, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
-        default: return launch_rnw_persistent_res(bucket, 0, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
+        case HP_W128: return launch_rnw_persistent_w128(bucket, variant, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
+        default: return launch_rnw_persistent_res(bucket, variant, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
     }
 }
 
@@ -998,8 +1017,8 @@ hipError_t launch_rnw_single(int ring, int bucket, int variant, const JobDesc *j
     if (nitems == 0) return hipSuccess;
     switch (ring) {
         case HP_W64: return launch_rnw_single_w64(bucket, variant, jobs, data, job, nitems, accs, s);
-        case HP_W128: return launch_rnw_single_w128(bucket, 0, jobs, data, job, nitems, accs, s);
-        default: return launch_rnw_single_res(bucket, 0, jobs, data, job, nitems, accs, s);
+        case HP_W128: return launch_rnw_single_w128(bucket, variant, jobs, data, job, nitems, accs, s);
+        default: return launch_rnw_single_res(bucket, variant, jobs, data, job, nitems, accs, s);
     }
 }
 #endif  // HP_PART == 0
