@@ -243,8 +243,9 @@ def main():
     for ls in launches:
         for L in ls:
             key = (L["ring"], L["bucket"], L["variant"])
-            g = groups.setdefault(key, {"ms": 0.0, "alg": 0.0, "terms": 0, "n": 0})
+            g = groups.setdefault(key, {"ms": 0.0, "alg": 0.0, "terms": 0, "jobs": 0, "n": 0})
             g["ms"] += L["ms"]
+            g["jobs"] += L["n_jobs"]
             g["alg"] += L["alg_slots"]
             g["terms"] += L["terms"]
             g["n"] += 1
@@ -319,8 +320,9 @@ def main():
                      "unit": "VALU lane-slots/s", "frac": achieved / ALU_PEAK,
                      "traffic": traffic_from_profile(),
                      "kernel": f"rnw_persistent ({ring_name}, orders <= {[16, 24, 32, 40][bucket]}, "
-                               f"{'paired walk' if variant else 'step-pair walk'})",
-                     "avg_launch_ms": avg_ms, "alg_slots_per_launch": alg_per_launch},
+                               f"{['step-pair walk', 'paired walk, two-row column 0', 'paired walk, three-row column 0'][variant]})",
+                     "avg_launch_ms": avg_ms, "alg_slots_per_launch": alg_per_launch,
+                     "jobs_per_launch": dom["jobs"] // dom["n"], "terms_per_launch": dom["terms"] // dom["n"]},
         "cpu_baseline": cpu,
         "serving": serving,
     }

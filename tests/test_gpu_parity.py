@@ -288,3 +288,23 @@ def test_paired_walk_small_chunks(hperm, chunk):
     assert per_job == native.ryser_batch(expand_leaves(A, 14), threads=8)
     assert totals == [int(GOLDEN["cubic24_seed7"])]
     assert variants & {1, 2}
+
+
+def test_largest_orders_and_sizes(hperm, ctx):
+    """Jobs of order 40 (the largest) and inputs of order 128 (the largest): closed forms
+    per(a I + P) = a^n + 1 for the cyclic shift P, and the 3-band circulant I + P + P^2
+    against the oracle; an input whose proven bound exceeds 2^180 is refused."""
+    say("largest orders")
+    n40 = [3 * np.eye(40, dtype=np.uint32) + np.roll(np.eye(40, dtype=np.uint32), 1, axis=1),
+           sum(np.roll(np.eye(40, dtype=np.uint32), s, axis=1) for s in range(3))]
+    J = ctx.jobs_from_dense(n40)
+    assert list(J.describe()["m"]) == [40, 40]
+    totals, _, _ = ctx.run(J, "natural", True)
+    assert totals[0] == 3 ** 40 + 1
+    assert totals[1] == native.hper_batch([n40[1]])[0]
+    say("largest inputs")
+    big = [np.eye(128, dtype=np.uint32) + np.roll(np.eye(128, dtype=np.uint32), 1, axis=1)]
+    assert ctx.permanent_batch(big) == [2]
+    with pytest.raises(hperm.HpermError) as e:
+        ctx.permanent(2 * np.eye(128, dtype=np.uint32) + np.roll(np.eye(128, dtype=np.uint32), 1, axis=1))
+    assert e.value.status == -2
