@@ -211,11 +211,15 @@ struct RingRes {
 };
 
 // ------------------------------------------------------------------------ R-NW work item
-// One work item is 64 consecutive lane chunks of one job: lane l walks the Gray indices
-// k in [k0, k0 + L) with L = 2^c and k0 = (item * 64 + l) * L. Because k0 is a multiple of
-// L, the flipped Gray column at step k0 + t is j = ctz(t), the same in every lane; its
-// direction (new bit = 1 - bit j+1 of k) is bit j+1 of t for j < c-1 and, at the single step
-// with j = c-1, bit c of k0 (the only lane-dependent case).
+// One work item is 64 consecutive lane chunks of one job: lane l covers the Gray indices
+// [zL, zL + L) of chunk z = item * 64 + l, L = 2^c. An even chunk is walked forwards from
+// k = zL, an odd one backwards from k = zL + L - 1. For c >= 1 the reflected Gray code makes
+// the odd chunk's walk the even chunk's walk with Gray bit c set: at step t both have the
+// low c Gray bits gray(t), so the column flipped after step t is j = ctz(t + 1) and its
+// direction (+1 when bit j + 1 of t + 1 is 0) are the same in every lane, for every j < c.
+// The lanes differ only in the Gray bits c and up of their first index, which fix their
+// starting row values, and in the sign (-1)^k of their first term (odd chunks start at an
+// odd k), after which the sign of step t is (-1)^t in every lane.
 //
 // The term prod_i f_i is kept as suffix products S_i = prod_{i' >= i} |f_i'| (S_m = 1) and
 // sign words G_i = f_i xor G_{i+1} whose bit 31 is the parity of the negative f_i', i' >= i.
@@ -316,21 +320,18 @@ __device__ __forceinline__ uint32_t block_of(uint32_t h) {
     }
 
 // Row-value update of block B only (no product), for the rows below the pair boundary in
-// the paired walk below: they take the column-0 flip of the pair (direction dir0) and this
-// flip together.
+// the paired walk below.
 #define HP_BLOCK_F(B)                                                                      \
     if ((B) < NB) {                                                                        \
         const int lo_ = blk_lo(B), w_ = blk_top(B) - blk_lo(B);                            \
         _Pragma("unroll") for (int r_ = 3; r_ >= 0; --r_) {                                \
             const int I_ = lo_ + r_;                                                       \
-            if (r_ < w_ && I_ < MAXM)                                                      \
-                f[I_] = __builtin_fmaf(dj[I_], dir, __builtin_fmaf(tab[I_], dir0, f[I_])); \
+            if (r_ < w_ && I_ < MAXM) f[I_] = __builtin_fmaf(dj[I_], dir, f[I_]);          \
         }                                                                                  \
     }
 
 // A flip in the paired walk: blocks V and up are recomputed in full, the blocks below the
-// pair boundary (rows 0 .. V) only get their new row values, always (they also carry the
-// pair's column-0 change).
+// pair boundary (rows 0 .. V) only get their new row values.
 #define HP_FLIP_P(TOP, DJ, DIR)                                                            \
     {                                                                                      \
         const uint32_t top_ = (TOP);                                                       \
@@ -355,12 +356,14 @@ __device__ __forceinline__ uint32_t block_of(uint32_t h) {
     }
 
 // V = 0: the walk in step pairs below, for every job. V = 1, 2 (jobs whose column 0 reaches
-// only the first V + 1 rows, lane chunks of at least 2 Gray indices): the paired walk, in
-// which the two terms of a pair (t even, t + 1) are summed as
-//   sign(G_b) * S_b * (P_t - P_{t+1}),  b = V + 1,
-// where P_t and P_{t+1} are the signed products of rows 0 .. b-1 before and after the flip
-// of column 0 (small integers, exact in the ring's Small type) and S_b, G_b the suffix product and
-// sign word above them; the other flips recompute S and G only from row b up.
+// only the first b = V + 1 rows, lane chunks of at least 2 Gray indices): the paired walk.
+// The two terms of a pair (t even, t + 1) differ only in Gray column 0, so rows 0 .. b-1 are
+// held without it (g_i; column 0's deltas are d_i) and the pair is summed at once as
+//   +-sign(G_b) * S_b * X,  X = prod_{i<b} (g_i + d_i) - prod_{i<b} g_i,
+// with the plus sign when column 0 is set in the first term of the pair, and S_b, G_b the
+// suffix product and sign word of the rows above. X is a small integer, exact in the ring's
+// Small type; for b = 2 it is d_0 g_1 + d_1 g_0 + d_0 d_1. The other flips recompute S and G
+// only from row b up and move g_0 .. g_{b-1}.
 template <class R, int MAXM, int V>
 __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__restrict__ data,
                                          uint64_t item, int lane, JobAcc *dst, float *tab) {
@@ -372,7 +375,9 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
     const int c = jd.chunk_log2;
     const uint64_t nterms = 1ull << (m - 1);
     const uint64_t L = 1ull << c;
-    const uint64_t k0 = (item * WAVE + (uint64_t)lane) * L;
+    const uint64_t z = item * WAVE + (uint64_t)lane;   // the lane's chunk
+    const uint64_t k0 = z * L;
+    const uint64_t kfirst = (z & 1) ? k0 + L - 1 : k0;   // the lane's first Gray index
     const uint32_t *w = data + (size_t)jd.data_off * HP_DATA_ALIGN;
     const uint32_t *cs = w + m;
     const uint32_t *hi = w + 2 * m;
@@ -397,14 +402,14 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-    // f_i(gray(k0)) = base_i + 2 * sum over the set Gray bits. Bits 0..c-2 of gray(k0) are
-    // zero (k0 is a multiple of 2^c), so only columns c-1 .. m-2 can contribute; rows are
-    // selected by comparison so that the row values stay in registers with constant indices.
+    // f_i(gray(kfirst)) = base_i + 2 * sum over the set Gray bits. Bits 0..c-1 of
+    // gray(kfirst) are zero, so only columns c .. m-2 can contribute; rows are selected by
+    // comparison so that the row values stay in registers with constant indices.
     float f[MAXM];
 #pragma unroll
     for (int i = 0; i < MAXM; ++i) f[i] = i < m ? (float)(int)uni(w[i]) : 1.0f;
-    const uint64_t g0 = k0 ^ (k0 >> 1);
-    for (int j = c > 0 ? c - 1 : 0; j < m - 1; ++j) {
+    const uint64_t g0 = kfirst ^ (kfirst >> 1);
+    for (int j = c; j < m - 1; ++j) {
         const bool bit = (g0 >> j) & 1;
         const uint32_t b = uni(cs[j]);
         const uint32_t e = uni(cs[j + 1]);
@@ -420,9 +425,9 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
     typename R::P S[MAXM + 1];
     uint32_t G[MAXM + 1];
     S[MAXM] = R::one();
-    // the sign (-1)^k0 of the first term rides in the sign chain's seed (k0 is odd only when
-    // L = 1); the sign (-1)^t of the later steps is wave-uniform
-    G[MAXM] = (uint32_t)(k0 & 1) << 31;
+    // the sign (-1)^kfirst of the lane's first term rides in the sign chain's seed; the sign
+    // (-1)^t of step t relative to it is wave-uniform
+    G[MAXM] = (uint32_t)(kfirst & 1) << 31;
 #pragma unroll
     for (int i = MAXM - 1; i >= 0; --i) {
         S[i] = S[i + 1];
@@ -432,8 +437,6 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
             R::mul(S[i], (uint32_t)fabsf(f[i]));
         }
     }
-    // direction of the step with j = c-1 (lane-dependent): +1 if bit c of k0 is 0
-    const float dir_last = ((k0 >> c) & 1) ? -1.0f : 1.0f;
 
     typename R::Acc acc = R::acc_zero();
     const uint32_t last = (uint32_t)L - 1u;
@@ -445,7 +448,7 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
             R::acc(acc, S[0], (uint32_t)((int)G[0] >> 31));   // even t: (-1)^t = +1
             if (t == last) break;
             {
-                const float dir0 = c == 1 ? dir_last : (((t + 1) >> 1) & 1 ? -1.0f : 1.0f);
+                const float dir0 = __uint_as_float(0x3f800000u | ((((t + 1) >> 1) & 1u) << 31));
                 HP_FLIP(top0, tab, dir0)
             }
             ++t;
@@ -453,38 +456,48 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
             if (t == last) break;
             {
                 const int j = __builtin_ctz(t + 1);
-                const float dir_uni = ((t + 1) >> (j + 1)) & 1 ? -1.0f : 1.0f;
-                const float dirj = j == c - 1 ? dir_last : dir_uni;
+                const float dirj = __uint_as_float(0x3f800000u | ((((t + 1) >> (j + 1)) & 1u) << 31));
                 HP_FLIP((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj)
             }
         }
     } else {
         constexpr int PB = V + 1;   // rows 0 .. PB-1 below the pair boundary
-        // The pair (t, t + 1) around the flip of column 0: the rows below the boundary keep
-        // their values of term t until the next flip applies both changes. The loop is
-        // rotated (flip, then pair) so that it has a single exit at its end.
+        using Sm = typename R::Small;
+        // column 0's deltas d_i (wave-uniform) and, for PB = 2, d_0 d_1
+        int dcol[PB];
+#pragma unroll
+        for (int i = 0; i < PB; ++i) dcol[i] = (int)__uint_as_float(uni(__float_as_uint(tab[i])));
+        // (read back through the scalar unit so that the compiler keeps d_0 g_1 and d_1 g_0 as
+        // two 32 x 32 -> 64-bit products instead of factoring d_0 (g_1 + d_1))
+        const Sm k01 = (Sm)(int64_t)uni64((uint64_t)((int64_t)dcol[0] * dcol[1]));
+        // Pair at t: column 0 is set in term t when bit 1 of t is (in every lane); the pair's
+        // first term has the sign (-1)^kfirst of G's seed.
 #define HP_PAIR()                                                                          \
     {                                                                                      \
-        using Sm = typename R::Small;                                                      \
-        Sm pa = (Sm)(int)f[0];                                                             \
-        Sm pb = (Sm)(int)__builtin_fmaf(tab[0], dir0, f[0]);                               \
-        _Pragma("unroll") for (int i = 1; i < PB; ++i) {                                   \
-            pa *= (Sm)(int)f[i];                                                           \
-            pb *= (Sm)(int)__builtin_fmaf(tab[i], dir0, f[i]);                             \
+        Sm x;                                                                              \
+        if constexpr (PB == 2) {                                                           \
+            x = k01 + (Sm)dcol[0] * (Sm)(int)f[1] + (Sm)dcol[1] * (Sm)(int)f[0];           \
+        } else {                                                                           \
+            Sm pg = (Sm)(int)f[0];                                                         \
+            Sm ph = (Sm)((int)f[0] + dcol[0]);                                             \
+            _Pragma("unroll") for (int i = 1; i < PB; ++i) {                               \
+                const int gi_ = (int)f[i];                                                 \
+                pg *= (Sm)gi_;                                                             \
+                ph *= (Sm)(gi_ + dcol[i]);                                                 \
+            }                                                                              \
+            x = ph - pg;                                                                   \
         }                                                                                  \
-        const typename R::P pair = R::pair_mul(S[PB], pa - pb);                            \
-        R::acc(acc, pair, (uint32_t)((int)G[PB] >> 31));                                   \
+        const uint32_t smask = ((t >> 1) & 1u) - 1u;   /* all ones: minus */               \
+        R::acc(acc, R::pair_mul(S[PB], x), (uint32_t)((int)G[PB] >> 31) ^ smask);          \
     }
+        // Flips between pairs: column j = ctz(t + 2) >= 1, direction from bit j + 1 of t + 2.
         uint32_t t = 0;
-        float dir0 = c == 1 ? dir_last : 1.0f;   // the first column-0 flip sets bit 0
         HP_PAIR()
         while (t + 1 != last) {
             const int j = __builtin_ctz(t + 2);
-            const float dir_uni = ((t + 2) >> (j + 1)) & 1 ? -1.0f : 1.0f;
-            const float dirj = j == c - 1 ? dir_last : dir_uni;
+            const float dirj = __uint_as_float(0x3f800000u | ((((t + 2) >> (j + 1)) & 1u) << 31));
             HP_FLIP_P((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj)
             t += 2;
-            dir0 = ((t + 1) >> 1) & 1 ? -1.0f : 1.0f;
             HP_PAIR()
         }
 #undef HP_PAIR
