@@ -153,17 +153,18 @@ hperm_status estimate_jobs(Dev *c, hperm_jobs *j, int trials, uint64_t seed) {
     // jobs grouped by order bucket (one counting pass), natural order inside a bucket
     std::vector<uint32_t> &list = c->h_queue;
     list.resize(nd);
-    size_t off[5] = {0, 0, 0, 0, 0};
-    for (size_t k = 0; k < nd; ++k) off[bucket_of(j->tab.desc[k].m) + 1]++;
-    for (int b = 0; b < 4; ++b) off[b + 1] += off[b];
+    size_t off[HP_EST_BUCKETS + 1] = {};
+    for (size_t k = 0; k < nd; ++k) off[est_bucket_of(j->tab.desc[k].m) + 1]++;
+    for (int b = 0; b < HP_EST_BUCKETS; ++b) off[b + 1] += off[b];
     {
-        size_t pos[4] = {off[0], off[1], off[2], off[3]};
-        for (size_t k = 0; k < nd; ++k) list[pos[bucket_of(j->tab.desc[k].m)]++] = (uint32_t)k;
+        size_t pos[HP_EST_BUCKETS];
+        for (int b = 0; b < HP_EST_BUCKETS; ++b) pos[b] = off[b];
+        for (size_t k = 0; k < nd; ++k) list[pos[est_bucket_of(j->tab.desc[k].m)]++] = (uint32_t)k;
     }
     s = hip_check(c, hipMemcpyAsync(c->buf[B_LIST].ptr, list.data(), list.size() * 4,
                                     hipMemcpyHostToDevice, c->stream), "upload estimate list");
     if (s) return s;
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < HP_EST_BUCKETS; ++b) {
         const uint32_t n = (uint32_t)(off[b + 1] - off[b]);
         if (!n) continue;
         s = hip_check(c, launch_estimate(b, (const JobDesc *)c->buf[B_DESC].ptr,

@@ -7,8 +7,12 @@
 
 namespace hp {
 
-// Order bucket of a job: kernels are instantiated for m <= 16, 24, 32, 40.
+// Order bucket of a job: the R-NW kernels are instantiated for m <= 16, 24, 32, 40.
 int bucket_of(int m);
+
+// Order bucket of the estimator: m <= 16, 20, 24, 32, 40 (HP_EST_BUCKETS of them).
+constexpr int HP_EST_BUCKETS = 5;
+int est_bucket_of(int m);
 
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t s);
 
@@ -16,14 +20,15 @@ hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
 hipError_t launch_recombine(const JobDesc *jobs, const JobAcc *accs, uint32_t njobs,
                             ProbAcc *probs, hipStream_t s);
 
-// KKLLL keys of the listed jobs of one bucket (one block of 4 waves per job); keys[job id].
+// KKLLL keys of the listed jobs of one estimator bucket (one block of 4 waves per job);
+// keys[job id].
 hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data,
                            const uint32_t *list, uint32_t nlist, int trials, uint64_t seed,
                            float *keys, hipStream_t s);
 
-// Walk variant of a job for the R-NW kernels: 1 (2) for mod 2^64 jobs whose Gray column 0
-// reaches at most the first 2 (exactly the first 3) rows and whose lane chunk holds at least
-// 2 Gray indices (the paired walk), else 0.
+// Walk variant of a job for the R-NW kernels: 1 (2) for jobs whose Gray column 0 reaches at
+// most the first 2 (exactly the first 3) rows and whose lane chunk holds at least 2 Gray
+// indices (the paired walk), else 0.
 int walk_variant(const JobDesc &d, int chunk_log2);
 
 // Persistent R-NW over the queued jobs of one ring, order bucket and walk variant (queue[nqueue]

@@ -619,6 +619,55 @@ __device__ __forceinline__ void kkl_decode(uint32_t code, float &re, float &im) 
     im = code == 2 ? kS : (code == 3 ? -kS : 0.0f);
 }
 
+// Gaussian elimination with partial pivoting of one trial's B, held one row per lane of a
+// group (re, im: this lane's row), returning log2 |det B|^2 (the sum of log2 |pivot|^2).
+// `singular` is set when a pivot is zero (and must come in set for a group without a trial).
+template <int MAXM, int GROUP>
+__device__ __forceinline__ float kkl_eliminate(float (&re)[MAXM], float (&im)[MAXM], int m, int r,
+                                               int gbase, bool &singular) {
+    bool used = r >= m;
+    float l2 = 0.0f;
+#pragma unroll
+    for (int k = 0; k < MAXM; ++k) {
+        if (k < m) {
+            // pivot: the unused row with the largest |B_rk|^2, as a packed key (the squared
+            // magnitude's FP32 bits with the low 6 bits replaced by 63 - row, so that equal
+            // magnitudes prefer the lower row) maximised inside the group
+            const float mag = __builtin_fmaf(re[k], re[k], im[k] * im[k]);
+            const uint32_t key = used ? 0u : ((__float_as_uint(mag) & ~63u) | (uint32_t)(63 - r));
+            const int idx = 63 - (int)(group_max<GROUP>(key) & 63u);
+            const int src4 = (gbase + idx) << 2;
+            const float pr = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(re[k])));
+            const float pi = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(im[k])));
+            if (r == idx) used = true;
+            const float pmag = __builtin_fmaf(pr, pr, pi * pi);
+            const bool ok = !singular && pmag > 0.0f;
+            singular = !ok;
+            const float pm = ok ? pmag : 1.0f;
+            // hardware log2 and reciprocal (about 1 ulp): ample for a key that only orders
+            // the queue
+            l2 += __builtin_amdgcn_logf(pm);
+            const float inv = __builtin_amdgcn_rcpf(pm);
+            // factor = B_rk / pivot (zero for used rows and failed groups)
+            const float ir = pr * inv, ii = -pi * inv;
+            const bool upd = ok && !used;
+            const float fr = upd ? __builtin_fmaf(re[k], ir, -im[k] * ii) : 0.0f;
+            const float fi = upd ? __builtin_fmaf(re[k], ii, im[k] * ir) : 0.0f;
+#pragma unroll
+            for (int c = k + 1; c < MAXM; ++c) {
+                if (c < m) {
+                    const float cr = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(re[c])));
+                    const float ci = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(im[c])));
+                    // B_rc -= f * B_pc as two fused multiply-adds per part
+                    re[c] = __builtin_fmaf(-fr, cr, __builtin_fmaf(fi, ci, re[c]));
+                    im[c] = __builtin_fmaf(-fr, ci, __builtin_fmaf(-fi, cr, im[c]));
+                }
+            }
+        }
+    }
+    return l2;
+}
+
 template <int MAXM, int GROUP>
 __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(const JobDesc *__restrict__ jobs,
                                                       const uint32_t *__restrict__ data,
@@ -709,47 +758,10 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
             for (int b = 0; b < 4; ++b)
                 if (4 * q + b < MAXM) kkl_decode((word >> (8 * b)) & 0xffu, re[4 * q + b], im[4 * q + b]);
         }
-        bool used = r >= m;
-        float logabs = 0.0f;
         bool singular = !live;
-#pragma unroll
-        for (int k = 0; k < MAXM; ++k) {
-            if (k < m) {
-                // pivot: the unused row with the largest |B_rk|^2, as a packed key (the squared
-                // magnitude's FP32 bits with the low 6 bits replaced by 63 - row, so that
-                // equal magnitudes prefer the lower row) maximised inside the group
-                const float mag = re[k] * re[k] + im[k] * im[k];
-                const uint32_t key = used ? 0u : ((__float_as_uint(mag) & ~63u) | (uint32_t)(63 - r));
-                const int idx = 63 - (int)(group_max<GROUP>(key) & 63u);
-                const int src4 = (gbase + idx) << 2;
-                const float pr = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(re[k])));
-                const float pi = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(im[k])));
-                if (r == idx) used = true;
-                const float pmag = pr * pr + pi * pi;
-                const bool ok = !singular && pmag > 0.0f;
-                singular = !ok;
-                const float pm = ok ? pmag : 1.0f;
-                logabs += ok ? 0.5f * __logf(pm) : 0.0f;
-                // factor = B_rk / pivot (zero for used rows and failed groups); the hardware
-                // reciprocal (about 1 ulp) is ample for a key that only orders the queue
-                const float inv = __builtin_amdgcn_rcpf(pm);
-                const float ir = pr * inv, ii = -pi * inv;
-                const bool upd = ok && !used;
-                const float fr = upd ? re[k] * ir - im[k] * ii : 0.0f;
-                const float fi = upd ? re[k] * ii + im[k] * ir : 0.0f;
-#pragma unroll
-                for (int c = k + 1; c < MAXM; ++c) {
-                    if (c < m) {
-                        const float cr = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(re[c])));
-                        const float ci = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(im[c])));
-                        re[c] -= fr * cr - fi * ci;
-                        im[c] -= fr * ci + fi * cr;
-                    }
-                }
-            }
-        }
+        const float l2 = kkl_eliminate<MAXM, GROUP>(re, im, m, r, gbase, singular);   // log2 |det B|^2
         if (!singular) {
-            const float l = 2.0f * logabs;   // log |det B|^2
+            const float l = l2 * 0.69314718055994531f;   // log |det B|^2
             if (l > run_max) {
                 run_sum = run_sum * __expf(run_max - l) + 1.0f;
                 run_max = l;
@@ -891,6 +903,8 @@ namespace hp {
 
 int bucket_of(int m) { return m <= 16 ? 0 : (m <= 24 ? 1 : (m <= 32 ? 2 : 3)); }
 
+int est_bucket_of(int m) { return m <= 16 ? 0 : (m <= 20 ? 1 : (m <= 24 ? 2 : (m <= 32 ? 3 : 4))); }
+
 int walk_variant(const JobDesc &d, int chunk_log2) {
     if (chunk_log2 < 1) return 0;
     return (d.flags & HP_FLAG_COL0_TWO_ROWS) ? 1 : (d.flags & HP_FLAG_COL0_THREE_ROWS) ? 2 : 0;
@@ -917,8 +931,9 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
     if (nlist == 0) return hipSuccess;
     switch (bucket) {
         case 0: hipLaunchKernelGGL((kkl_estimate<16, 16>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
-        case 1: hipLaunchKernelGGL((kkl_estimate<24, 32>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
-        case 2: hipLaunchKernelGGL((kkl_estimate<32, 32>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
+        case 1: hipLaunchKernelGGL((kkl_estimate<20, 32>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
+        case 2: hipLaunchKernelGGL((kkl_estimate<24, 32>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
+        case 3: hipLaunchKernelGGL((kkl_estimate<32, 32>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys); break;
         default: hipLaunchKernelGGL((kkl_estimate<HP_MAX_M, 64>), dim3(nlist), dim3(BLOCK), 0, s, jobs, data, list, nlist, trials, seed, keys);
     }
     return hipGetLastError();

@@ -237,6 +237,19 @@ def test_estimate_matches_oracle(hperm, ctx):
         assert abs(float(key) - want) < 2e-3, (job, key, want)
 
 
+def test_estimate_matches_oracle_larger_orders(hperm, ctx):
+    """The same for the estimator's order buckets 17..20 and 21..24 (orders 17, 20, 22, 24).
+
+    FP32 rounding grows like m^2 * 2^-24 (about 3e-5 at m = 24), still far inside 2e-3."""
+    mats = [leaf_like(m, 350 + m, k=3) for m in (17, 20, 22, 24)]
+    say("estimate parity, orders 17..24")
+    J = ctx.jobs_from_dense(mats)
+    keys = ctx.estimate(J, 16, 777)
+    for job, (A, key) in enumerate(zip(mats, keys)):
+        want = kkl_key(A, 16, 777, job)
+        assert abs(float(key) - want) < 2e-3, (job, key, want)
+
+
 def test_estimate_tracks_permanent(hperm, ctx):
     """With many trials the key approaches log per of the pattern (the estimator is unbiased)."""
     say("estimate vs per")
