@@ -620,11 +620,16 @@ __device__ __forceinline__ void kkl_decode(uint32_t code, float &re, float &im) 
 }
 
 // Gaussian elimination with partial pivoting of one trial's B, held one row per lane of a
-// group (re, im: this lane's row), returning log2 |det B|^2 (the sum of log2 |pivot|^2).
-// `singular` is set when a pivot is zero (and must come in set for a group without a trial).
+// group (z: this lane's row, real and imaginary parts interleaved), returning
+// log2 |det B|^2 (the sum of log2 |pivot|^2). `singular` is set when a pivot is zero (and must
+// come in set for a group without a trial). At every step the pivot lane writes its row, from
+// the aligned column pair holding the pivot column on, into the group's LDS row `prow` with
+// 16-byte stores, and the group reads it back with 16-byte broadcast loads (two columns per
+// load: half the LDS cycles of moving the values one 32-bit lane permute at a time).
 template <int MAXM, int GROUP>
-__device__ __forceinline__ float kkl_eliminate(float (&re)[MAXM], float (&im)[MAXM], int m, int r,
-                                               int gbase, bool &singular) {
+__device__ __forceinline__ float kkl_eliminate(float (&z)[2 * MAXM], int m, int r, bool &singular,
+                                               float *prow) {
+    static_assert(MAXM % 2 == 0, "rows are written in column pairs");
     bool used = r >= m;
     float l2 = 0.0f;
 #pragma unroll
@@ -633,13 +638,23 @@ __device__ __forceinline__ float kkl_eliminate(float (&re)[MAXM], float (&im)[MA
             // pivot: the unused row with the largest |B_rk|^2, as a packed key (the squared
             // magnitude's FP32 bits with the low 6 bits replaced by 63 - row, so that equal
             // magnitudes prefer the lower row) maximised inside the group
-            const float mag = __builtin_fmaf(re[k], re[k], im[k] * im[k]);
+            const float mag = __builtin_fmaf(z[2 * k], z[2 * k], z[2 * k + 1] * z[2 * k + 1]);
             const uint32_t key = used ? 0u : ((__float_as_uint(mag) & ~63u) | (uint32_t)(63 - r));
             const int idx = 63 - (int)(group_max<GROUP>(key) & 63u);
-            const int src4 = (gbase + idx) << 2;
-            const float pr = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(re[k])));
-            const float pi = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(im[k])));
-            if (r == idx) used = true;
+            const int k0 = k & ~1;   // a constant once the loop is unrolled
+            if (r == idx) {
+#pragma unroll
+                for (int c = k0; c < MAXM; c += 2)
+                    if (c < m)
+                        *reinterpret_cast<float4 *>(prow + 2 * c) =
+                            make_float4(z[2 * c], z[2 * c + 1], z[2 * c + 2], z[2 * c + 3]);
+                used = true;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const float4 q0 = *reinterpret_cast<const float4 *>(prow + 2 * k0);
+            const float pr = (k & 1) ? q0.z : q0.x, pi = (k & 1) ? q0.w : q0.y;
             const float pmag = __builtin_fmaf(pr, pr, pi * pi);
             const bool ok = !singular && pmag > 0.0f;
             singular = !ok;
@@ -651,18 +666,28 @@ __device__ __forceinline__ float kkl_eliminate(float (&re)[MAXM], float (&im)[MA
             // factor = B_rk / pivot (zero for used rows and failed groups)
             const float ir = pr * inv, ii = -pi * inv;
             const bool upd = ok && !used;
-            const float fr = upd ? __builtin_fmaf(re[k], ir, -im[k] * ii) : 0.0f;
-            const float fi = upd ? __builtin_fmaf(re[k], ii, im[k] * ir) : 0.0f;
+            const float fr = upd ? __builtin_fmaf(z[2 * k], ir, -z[2 * k + 1] * ii) : 0.0f;
+            const float fi = upd ? __builtin_fmaf(z[2 * k], ii, z[2 * k + 1] * ir) : 0.0f;
+            // B_rc -= f * B_pc for c > k, as two fused multiply-adds per part
+#define HP_KKL_UPD(C, CR, CI)                                                                  \
+    z[2 * (C)] = __builtin_fmaf(-fr, (CR), __builtin_fmaf(fi, (CI), z[2 * (C)]));              \
+    z[2 * (C) + 1] = __builtin_fmaf(-fr, (CI), __builtin_fmaf(-fi, (CR), z[2 * (C) + 1]));
+            // (a pair's second column may lie past m: its entries are zero in every row and
+            // stay zero, and no later step reads it)
+            if (k == k0) { HP_KKL_UPD(k + 1, q0.z, q0.w) }
 #pragma unroll
-            for (int c = k + 1; c < MAXM; ++c) {
+            for (int c = k0 + 2; c < MAXM; c += 2) {
                 if (c < m) {
-                    const float cr = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(re[c])));
-                    const float ci = __int_as_float(__builtin_amdgcn_ds_bpermute(src4, __float_as_int(im[c])));
-                    // B_rc -= f * B_pc as two fused multiply-adds per part
-                    re[c] = __builtin_fmaf(-fr, cr, __builtin_fmaf(fi, ci, re[c]));
-                    im[c] = __builtin_fmaf(-fr, ci, __builtin_fmaf(-fi, cr, im[c]));
+                    const float4 q = *reinterpret_cast<const float4 *>(prow + 2 * c);
+                    HP_KKL_UPD(c, q.x, q.y)
+                    HP_KKL_UPD(c + 1, q.z, q.w)
                 }
             }
+#undef HP_KKL_UPD
+            // the next pivot lane may overwrite the row only after every lane has read it
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
     return l2;
@@ -679,6 +704,7 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
     __shared__ uint32_t ekey[MAXM * MAXM];   // Gray entries (at most m(m-1)) + m fixed slots
     __shared__ uint16_t epos[MAXM * MAXM];
     __shared__ float red[2 * (BLOCK / WAVE)];
+    __shared__ __attribute__((aligned(16))) float prows[(BLOCK / WAVE) * Sh::TPW * 2 * MAXM];
     if (blockIdx.x >= nlist) return;
     const uint32_t jobid = uni(list[blockIdx.x]);
     const JobDesc jd = load_job(jobs, jobid);
@@ -748,7 +774,7 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        float re[MAXM], im[MAXM];
+        float z[2 * MAXM];   // this lane's row: real and imaginary parts interleaved
         const uint32_t *myrow =
             reinterpret_cast<const uint32_t *>(wm + grp * MAXM * Sh::LD + (r < MAXM ? r : 0) * Sh::LD);
 #pragma unroll
@@ -756,10 +782,11 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
             const uint32_t word = r < m ? myrow[q] : 0u;
 #pragma unroll
             for (int b = 0; b < 4; ++b)
-                if (4 * q + b < MAXM) kkl_decode((word >> (8 * b)) & 0xffu, re[4 * q + b], im[4 * q + b]);
+                if (4 * q + b < MAXM) kkl_decode((word >> (8 * b)) & 0xffu, z[2 * (4 * q + b)], z[2 * (4 * q + b) + 1]);
         }
         bool singular = !live;
-        const float l2 = kkl_eliminate<MAXM, GROUP>(re, im, m, r, gbase, singular);   // log2 |det B|^2
+        // log2 |det B|^2
+        const float l2 = kkl_eliminate<MAXM, GROUP>(z, m, r, singular, prows + (wave * Sh::TPW + grp) * 2 * MAXM);
         if (!singular) {
             const float l = l2 * 0.69314718055994531f;   // log |det B|^2
             if (l > run_max) {
