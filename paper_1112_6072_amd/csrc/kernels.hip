@@ -591,16 +591,23 @@ __device__ __forceinline__ uint32_t kkl_u_counter(uint64_t seed, uint64_t k) {
 // butterfly inside the group and broadcast with lane permutes; log|det B| is the sum of
 // log|pivot|. Trials accumulate log-sum-exp pairs; the key is log(mean |det B|^2).
 // Maximum of a 32-bit key over aligned groups of GROUP lanes (16, 32 or 64): DPP steps
-// inside rows of 16 lanes (quad swaps, half-row and row mirrors), a swizzle across the two
-// rows of a 32-lane half, and a permute across the halves.
+// inside rows of 16 lanes (quad swaps, half-row and row mirrors), then the row swaps of
+// gfx950 (v_permlane16_swap: neighbouring 16-lane rows; v_permlane32_swap: the two halves),
+// whose two results hold each lane's value and its partner's, so their maximum is the pair's.
 template <int GROUP>
 __device__ __forceinline__ uint32_t group_max(uint32_t x) {
     x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));    // lane ^ 1
     x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false));    // lane ^ 2
     x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false));   // 7 - lane in 8
     x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false));   // 15 - lane in 16
-    if (GROUP >= 32) x = max(x, (uint32_t)__builtin_amdgcn_ds_swizzle((int)x, 0x401F));      // lane ^ 16
-    if (GROUP >= 64) x = max(x, (uint32_t)__shfl_xor((int)x, 32, WAVE));                     // lane ^ 32
+    if (GROUP >= 32) {   // lane ^ 16
+        const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        x = max((uint32_t)s[0], (uint32_t)s[1]);
+    }
+    if (GROUP >= 64) {   // lane ^ 32
+        const auto s = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        x = max((uint32_t)s[0], (uint32_t)s[1]);
+    }
     return x;
 }
 
