@@ -81,6 +81,9 @@ typedef struct hperm_opts {
     int32_t max_table_mib;/* host job-table limit per expansion call in MiB (0 = 4096): an
                              expansion that would outgrow it stops with HPERM_E_NOMEM instead
                              of exhausting host memory (raise m_cut to get fewer jobs) */
+    int32_t time_jobs;    /* 1: persistent runs of hperm_run_jobs record each job's work time
+                             (hperm_jobs_cycles; the scheduling study of the paper's load
+                             balancing section); 0: off (default). Ignored while serving. */
 } hperm_opts;
 
 /* Result of one permanent. The value is non-negative: magnitude limbs, little-endian. */
@@ -184,6 +187,32 @@ hperm_status hperm_run_jobs(hperm_ctx *ctx, hperm_jobs *jobs, int32_t order, int
 
 void hperm_jobs_free(hperm_jobs *jobs);
 
+/* ---- scheduling study (the paper's load-balancing analysis) --------------------------- */
+
+/* Work time of every job (natural index) in the last persistent hperm_run_jobs on these jobs
+ * with opts.time_jobs = 1: the sum over the job's work items of the shader-clock cycles its
+ * wave spent from taking the item to finishing it (waves sharing a SIMD stretch each other's
+ * items, so the figures rank jobs and compare orders; they are not isolated times).
+ * cycles[n_jobs]. HPERM_E_INVALID when no timed run has been made on the jobs. */
+hperm_status hperm_jobs_cycles(const hperm_jobs *jobs, uint64_t *cycles);
+
+/* List scheduling as in Step 3 of Algorithm PH: jobs are taken in the given order and each is
+ * assigned to the machine with the smallest load so far (ties: the lowest machine index).
+ * times[n] are the job times (any unit), order[n] a permutation of 0..n-1, machines >= 1.
+ * *makespan receives the largest machine load; loads[machines] (may be NULL) every load.
+ * Errors: HPERM_E_INVALID (n < 0, machines < 1, order not a permutation, NULL arrays). */
+hperm_status hperm_list_schedule(int32_t n, const uint64_t *times, const int32_t *order,
+                                 int32_t machines, uint64_t *makespan, uint64_t *loads);
+
+/* Kendall's rank correlation of x[n] and y[n] with the tie correction of the paper's
+ * equations for tied ranks: tau = S / sqrt((n(n-1)/2 - T)(n(n-1)/2 - U)), S the number of
+ * concordant minus discordant pairs, T and U the pairs tied in x and in y (tau_b); O(n log n).
+ * *z receives tau / sqrt(2(2n+5) / (9n(n-1))), the normal score under independence, and *p
+ * the two-sided normal p-value. NaN inputs are rejected. Errors: HPERM_E_INVALID (n < 2, NULL
+ * arrays, NaN, or every pair tied in x or in y). */
+hperm_status hperm_kendall_tau(int32_t n, const double *x, const double *y, double *tau,
+                               double *z, double *p);
+
 /* ---- serving ------------------------------------------------------------------------ */
 
 /* Start the serving loop of a context (continuous batching of requests):
@@ -233,8 +262,8 @@ typedef struct hperm_launch_stat {
     int32_t bucket;         /* kernel instantiation: job orders <= 16, 24, 32, 40 */
     int32_t n_jobs;         /* jobs in the launch (1 in one-launch-per-job mode) */
     int32_t persistent;
-    int32_t variant;        /* walk variant: 0, or 1 / 2 for the paired walk of mod 2^64 jobs
-                               whose Gray column 0 reaches only the first 2 / 3 rows */
+    int32_t variant;        /* walk variant: 0, or 1 / 2 for the paired walk of jobs whose
+                               Gray column 0 reaches only the first 2 / 3 rows */
     int32_t reserved;
     uint64_t items;         /* work items (64 lanes x 2^chunk Gray indices each) */
     uint64_t terms;         /* subset-terms: sum of 2^(m-1) over the jobs */

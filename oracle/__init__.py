@@ -15,12 +15,17 @@ kkl.py         the KKLLL estimator (Section 2.3): one trial |det B|^2 for given 
                log-mean key used to order jobs.
 ryser_c.c      plain Ryser in C with 128-bit wrap-around integers, threaded over a list
                of matrices; used only to time a CPU baseline.
+schedule.py    the scheduling study (Sections 3.2-3.3): list scheduling to the least-loaded
+               processor (Step 3 of Algorithm PH), brute-force optimal makespans, and
+               Kendall's tau with the paper's tie correction.
 """
 from .permanent import (per_brute, per_ryser, nw_doubled_sum, per_nw, e2_children, expand_leaves,
                         choose_line, per_hybrid, per_dp, per_auto)
 from .kkl import splitmix64, kkl_exponent, kkl_trial, kkl_key
+from .schedule import list_schedule, efficiency, kendall_tau, opt_makespan_brute
 
 __all__ = [
     "per_brute", "per_ryser", "nw_doubled_sum", "per_nw", "e2_children", "expand_leaves", "choose_line",
     "per_hybrid", "per_dp", "per_auto", "splitmix64", "kkl_exponent", "kkl_trial", "kkl_key",
+    "list_schedule", "efficiency", "kendall_tau", "opt_makespan_brute",
 ]

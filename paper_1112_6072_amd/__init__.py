@@ -38,7 +38,7 @@ class Opts(ctypes.Structure):
                 ("arith", ctypes.c_int32), ("order", ctypes.c_int32), ("trials", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("chunk_log2", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("host_threads", ctypes.c_int32),
-                ("max_table_mib", ctypes.c_int32)]
+                ("max_table_mib", ctypes.c_int32), ("time_jobs", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -93,6 +93,10 @@ _SIGS = {
     "hperm_wait": [_P, _U64, ctypes.c_double, ctypes.POINTER(Result)],
     "hperm_cancel": [_P, _U64],
     "hperm_last_launches": [_P, ctypes.POINTER(LaunchStat), _I32, ctypes.POINTER(_I32)],
+    "hperm_jobs_cycles": [_P, _P],
+    "hperm_list_schedule": [_I32, _P, _P, _I32, ctypes.POINTER(_U64), _P],
+    "hperm_kendall_tau": [_I32, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                          ctypes.POINTER(ctypes.c_double)],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -191,6 +195,15 @@ class Jobs:
         terms = np.zeros(max(nj, 1), np.uint64)
         _lib.hperm_jobs_describe(self.handle, _ptr(m), _ptr(prob), _ptr(ar), _ptr(terms))
         return {"m": m[:nj], "problem": prob[:nj], "arith": ar[:nj], "terms": terms[:nj]}
+
+    def cycles(self) -> np.ndarray:
+        """Per-job work cycles of the last timed persistent run (opts time_jobs=1)."""
+        nj, _ = self.info()
+        out = np.zeros(max(nj, 1), np.uint64)
+        st = _lib.hperm_jobs_cycles(self.handle, _ptr(out))
+        if st != OK:
+            raise HpermError(st, "no timed run on these jobs (set time_jobs=1 and run persistent)")
+        return out[:nj]
 
 
 class Context:
@@ -385,3 +398,32 @@ def permanent(A, **opts) -> int:
     if _default_ctx is None:
         _default_ctx = Context()
     return _default_ctx.permanent(A)
+
+
+def list_schedule(times, order, machines: int) -> tuple[int, np.ndarray]:
+    """List scheduling (Step 3 of Algorithm PH): (makespan, per-machine loads) of the jobs with
+    the given integer times assigned in `order` to the least-loaded of `machines` machines."""
+    t = np.ascontiguousarray(times, dtype=np.uint64)
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    if t.ndim != 1 or o.shape != t.shape:
+        raise ValueError("times and order must be 1-D of equal length")
+    loads = np.zeros(max(int(machines), 1), np.uint64)
+    ms = _U64()
+    st = _lib.hperm_list_schedule(int(t.size), _ptr(t), _ptr(o), int(machines), ctypes.byref(ms), _ptr(loads))
+    if st != OK:
+        raise HpermError(st, "list_schedule")
+    return int(ms.value), loads
+
+
+def kendall_tau(x, y) -> tuple[float, float, float]:
+    """Kendall's tau with tie correction (tau_b), its normal score under independence and the
+    two-sided p-value."""
+    a = np.ascontiguousarray(x, dtype=np.float64)
+    b = np.ascontiguousarray(y, dtype=np.float64)
+    if a.ndim != 1 or a.shape != b.shape:
+        raise ValueError("x and y must be 1-D of equal length")
+    tau, z, p = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    st = _lib.hperm_kendall_tau(int(a.size), _ptr(a), _ptr(b), ctypes.byref(tau), ctypes.byref(z), ctypes.byref(p))
+    if st != OK:
+        raise HpermError(st, "kendall_tau")
+    return tau.value, z.value, p.value

@@ -462,6 +462,11 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         s = ensure_buf(c, B_DESC_PLAIN, nd * sizeof(JobDesc));
         if (s) return s;
     }
+    c->timed = persistent && c->opts.time_jobs != 0;
+    if (c->timed) {
+        s = ensure_buf(c, B_CYCLES, nd * sizeof(unsigned long long));
+        if (s) return s;
+    }
     if (c->resident_jobs != j->id) {   // an arena re-layout moved the job table: upload again
         s = upload_jobs(c, j);
         if (s) return s;
@@ -487,6 +492,13 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     if (s) return s;
     s = hip_check(c, launch_fill_u64(head, 64, 0ull, c->stream), "clear queue heads");
     if (s) return s;
+    // per-job work cycles (opt-in, persistent runs): cleared here, downloaded by run_finish
+    unsigned long long *cyc = nullptr;
+    if (c->timed) {
+        cyc = (unsigned long long *)c->buf[B_CYCLES].ptr;
+        s = hip_check(c, launch_fill_u64(cyc, nd, 0ull, c->stream), "clear job cycles");
+        if (s) return s;
+    }
     const uint32_t *d_data = (const uint32_t *)c->buf[B_DATA].ptr;
     s = hip_check(c, hipEventRecord(c->ev0, c->stream), "event");
     if (s) return s;
@@ -530,7 +542,8 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,
                                                    (const uint32_t *)c->buf[B_QUEUE].ptr + g.off,
                                                    (const uint64_t *)c->buf[B_ITEMS].ptr + g.off,
-                                                   (uint32_t)g.n, g.items, head + gi, accs, 0, c->stream),
+                                                   (uint32_t)g.n, g.items, head + gi, accs, cyc, 0,
+                                                   c->stream),
                           "rnw_persistent launch");
             if (s) return s;
             s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi + 1], c->stream), "event");
@@ -611,6 +624,13 @@ hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_resu
             }
         } else if (!c->launches.empty()) {
             c->launches[0].ms = ms;
+        }
+        if (c->timed) {
+            j->cycles.resize(nd);
+            s = hip_check(c, hipMemcpy(j->cycles.data(), c->buf[B_CYCLES].ptr, nd * sizeof(uint64_t),
+                                       hipMemcpyDeviceToHost), "download job cycles");
+            if (s) return s;
+            j->has_cycles = true;
         }
         for (size_t k = 0; k < nd; ++k) {
             const JobDesc &d = j->tab.desc[k];
@@ -741,6 +761,7 @@ static const char *check_opts(const hperm_opts *o) {
     if (o->chunk_log2 < 0 || o->chunk_log2 > 12) return "chunk_log2 must be in [0, 12]";
     if (o->host_threads < 0 || o->host_threads > 64) return "host_threads must be in [0, 64]";
     if (o->max_table_mib < 0) return "max_table_mib must be >= 0";
+    if (o->time_jobs != 0 && o->time_jobs != 1) return "time_jobs must be 0 or 1";
     return nullptr;
 }
 
@@ -1022,6 +1043,12 @@ hperm_status hperm_run_jobs(hperm_ctx *c, hperm_jobs *j, int32_t order, int32_t 
 }
 
 void hperm_jobs_free(hperm_jobs *j) { delete j; }
+
+hperm_status hperm_jobs_cycles(const hperm_jobs *j, uint64_t *cycles) {
+    if (!j || !cycles || !j->has_cycles || j->cycles.size() != j->tab.desc.size()) return HPERM_E_INVALID;
+    std::copy(j->cycles.begin(), j->cycles.end(), cycles);
+    return HPERM_OK;
+}
 
 hperm_status hperm_last_launches(const hperm_ctx *c, hperm_launch_stat *out, int32_t max, int32_t *n) {
     if (!c || !n || max < 0 || (max > 0 && !out)) return HPERM_E_INVALID;

@@ -21,7 +21,7 @@ struct DevBuf {
     bool owned = false;
 };
 
-enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_PROB, B_COUNT };
+enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_PROB, B_CYCLES, B_COUNT };
 
 struct Serving;   // serve.cpp
 
@@ -35,6 +35,9 @@ struct hperm_jobs {
     // per-job algorithmic work of the persistent walk (ring multiplies, row updates), filled
     // on the first run
     std::vector<double> work_mults, work_adds, work_updates;
+    // per-job work cycles of the last timed persistent run (natural index)
+    std::vector<uint64_t> cycles;
+    bool has_cycles = false;
 };
 
 namespace hp {
@@ -56,6 +59,7 @@ struct Dev {
     // state between run_enqueue and run_finish
     bool want_per_job = false;
     bool persistent = true;
+    bool timed = false;                        // per-job work cycles recorded (B_CYCLES)
     std::vector<JobAcc> host_acc;              // per-job accumulators (per-job results only)
     ProbAcc *host_prob = nullptr;              // pinned, per-problem accumulators
     size_t host_prob_cap = 0;

@@ -33,12 +33,12 @@ int walk_variant(const JobDesc &d, int chunk_log2);
 
 // Persistent R-NW over the queued jobs of one ring, order bucket and walk variant (queue[nqueue]
 // job ids in scheduling order, item_end[nqueue] inclusive prefix sums of their item counts).
-// *head must be 0.
+// *head must be 0. cycles (may be null): per-job work cycles are added into cycles[job id].
 hipError_t launch_rnw_persistent(int ring, int bucket, int variant, const JobDesc *jobs,
                                  const uint32_t *data, const uint32_t *queue,
                                  const uint64_t *item_end, uint32_t nqueue, uint64_t total_items,
-                                 unsigned long long *head, JobAcc *accs, int grid_override,
-                                 hipStream_t s);
+                                 unsigned long long *head, JobAcc *accs,
+                                 unsigned long long *cycles, int grid_override, hipStream_t s);
 
 // R-NW of one job in one launch (nitems waves).
 hipError_t launch_rnw_single(int ring, int bucket, int variant, const JobDesc *jobs,
@@ -52,7 +52,8 @@ hipError_t launch_rnw_single(int ring, int bucket, int variant, const JobDesc *j
                                            const uint32_t *data, const uint32_t *queue,         \
                                            const uint64_t *item_end, uint32_t nqueue,           \
                                            uint64_t total_items, unsigned long long *head,      \
-                                           JobAcc *accs, int grid, hipStream_t s);              \
+                                           JobAcc *accs, unsigned long long *cycles, int grid,  \
+                                           hipStream_t s);                                      \
     hipError_t launch_rnw_single_##sfx(int bucket, int variant, const JobDesc *jobs,            \
                                        const uint32_t *data, uint32_t job, uint64_t nitems,     \
                                        JobAcc *accs, hipStream_t s);

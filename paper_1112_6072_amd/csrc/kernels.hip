@@ -548,6 +548,42 @@ __global__ __launch_bounds__(BLOCK) void rnw_persistent(const JobDesc *__restric
     }
 }
 
+// The same queue walk that also adds the shader-clock cycles from taking an item to finishing
+// it into cycles[job] (the per-job work times of the scheduling study). It is a kernel of its
+// own: sharing one loop body with the untimed kernel changed that kernel's register
+// allocation by one scalar register, enough to cost it one wave per SIMD.
+template <class R, int MAXM, int V>
+__global__ __launch_bounds__(BLOCK) void rnw_persistent_timed(const JobDesc *__restrict__ jobs,
+                                                              const uint32_t *__restrict__ data,
+                                                              const uint32_t *__restrict__ queue,
+                                                              const uint64_t *__restrict__ item_end,
+                                                              uint32_t nqueue, uint64_t total_items,
+                                                              unsigned long long *head,
+                                                              JobAcc *__restrict__ accs,
+                                                              unsigned long long *__restrict__ cycles) {
+    __shared__ __attribute__((aligned(16))) float tabs[(BLOCK / WAVE) * Tab<MAXM>::WORDS];
+    const int lane = threadIdx.x & (WAVE - 1);
+    float *tab = tabs + (threadIdx.x >> 6) * Tab<MAXM>::WORDS;
+    for (;;) {
+        const unsigned long long got = atomicAdd(head, lane == 0 ? 1ull : 0ull);
+        const uint64_t g = uni64(got);
+        if (g >= total_items) break;
+        uint32_t lo = 0, hi = nqueue - 1;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (uni64(item_end[mid]) > g) hi = mid;
+            else lo = mid + 1;
+        }
+        const uint64_t first = lo ? uni64(item_end[lo - 1]) : 0;
+        const uint32_t job = uni(queue[lo]);
+        const JobDesc jd = load_job(jobs, job);
+        const uint64_t t0 = (uint64_t)clock64();
+        rnw_item<R, MAXM, V>(jd, data, g - first, lane, accs + job, tab);
+        const unsigned long long dt = (unsigned long long)((uint64_t)clock64() - t0);
+        atomicAdd(cycles + job, lane == 0 ? dt : 0ull);
+    }
+}
+
 // One launch per job (the plain comparator): wave w of the grid evaluates item w.
 template <class R, int MAXM, int V>
 __global__ __launch_bounds__(BLOCK) void rnw_single(const JobDesc *__restrict__ jobs,
@@ -992,12 +1028,20 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
 #define HP_FN(K, MAXM)                                                                     \
     (variant == 1 ? (const void *)K<RING_T, MAXM, 1>                                       \
                   : variant == 2 ? (const void *)K<RING_T, MAXM, 2> : (const void *)K<RING_T, MAXM, 0>)
-static const void *persistent_fn(int bucket, int variant) {
+static const void *persistent_fn(int bucket, int variant, bool timed) {
+    if (!timed) {
+        switch (bucket) {
+            case 0: return HP_FN(rnw_persistent, 16);
+            case 1: return HP_FN(rnw_persistent, 24);
+            case 2: return HP_FN(rnw_persistent, 32);
+            default: return HP_FN(rnw_persistent, HP_MAX_M);
+        }
+    }
     switch (bucket) {
-        case 0: return HP_FN(rnw_persistent, 16);
-        case 1: return HP_FN(rnw_persistent, 24);
-        case 2: return HP_FN(rnw_persistent, 32);
-        default: return HP_FN(rnw_persistent, HP_MAX_M);
+        case 0: return HP_FN(rnw_persistent_timed, 16);
+        case 1: return HP_FN(rnw_persistent_timed, 24);
+        case 2: return HP_FN(rnw_persistent_timed, 32);
+        default: return HP_FN(rnw_persistent_timed, HP_MAX_M);
     }
 }
 static const void *single_fn(int bucket, int variant) {
@@ -1016,7 +1060,7 @@ hipError_t CAT(persistent_grid, RING_SUFFIX)(int bucket, int variant, int *grid)
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_fn(bucket, variant), BLOCK, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_fn(bucket, variant, false), BLOCK, 0);
     if (e != hipSuccess) return e;
     *grid = cus * (per_cu > 0 ? per_cu : 1);
     return hipSuccess;
@@ -1026,10 +1070,13 @@ hipError_t CAT(launch_rnw_persistent, RING_SUFFIX)(int bucket, int variant, cons
                                                     const uint32_t *data, const uint32_t *queue,
                                                     const uint64_t *item_end, uint32_t nqueue,
                                                     uint64_t total_items, unsigned long long *head,
-                                                    JobAcc *accs, int grid, hipStream_t s) {
-    void *args[] = {(void *)&jobs, (void *)&data, (void *)&queue, (void *)&item_end,
-                    (void *)&nqueue, (void *)&total_items, (void *)&head, (void *)&accs};
-    hipError_t e = hipLaunchKernel(persistent_fn(bucket, variant), dim3(grid), dim3(BLOCK), args, 0, s);
+                                                    JobAcc *accs, unsigned long long *cycles, int grid,
+                                                    hipStream_t s) {
+    void *args[] = {(void *)&jobs,   (void *)&data,        (void *)&queue, (void *)&item_end,
+                    (void *)&nqueue, (void *)&total_items, (void *)&head,  (void *)&accs,
+                    (void *)&cycles};   // the untimed kernel takes the first eight
+    hipError_t e = hipLaunchKernel(persistent_fn(bucket, variant, cycles != nullptr), dim3(grid),
+                                   dim3(BLOCK), args, 0, s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -1057,8 +1104,8 @@ hipError_t persistent_grid(int ring, int bucket, int variant, int *grid) {
 hipError_t launch_rnw_persistent(int ring, int bucket, int variant, const JobDesc *jobs,
                                  const uint32_t *data, const uint32_t *queue,
                                  const uint64_t *item_end, uint32_t nqueue, uint64_t total_items,
-                                 unsigned long long *head, JobAcc *accs, int grid_override,
-                                 hipStream_t s) {
+                                 unsigned long long *head, JobAcc *accs,
+                                 unsigned long long *cycles, int grid_override, hipStream_t s) {
     if (nqueue == 0 || total_items == 0) return hipSuccess;
     int grid = 0;
     hipError_t e = persistent_grid(ring, bucket, variant, &grid);
@@ -1067,9 +1114,9 @@ hipError_t launch_rnw_persistent(int ring, int bucket, int variant, const JobDes
     const uint64_t max_blocks = (total_items + (BLOCK / WAVE) - 1) / (BLOCK / WAVE);
     if ((uint64_t)grid > max_blocks) grid = (int)max_blocks;
     switch (ring) {
-        case HP_W64: return launch_rnw_persistent_w64(bucket, variant, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
-        case HP_W128: return launch_rnw_persistent_w128(bucket, variant, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
-        default: return launch_rnw_persistent_res(bucket, variant, jobs, data, queue, item_end, nqueue, total_items, head, accs, grid, s);
+        case HP_W64: return launch_rnw_persistent_w64(bucket, variant, jobs, data, queue, item_end, nqueue, total_items, head, accs, cycles, grid, s);
+        case HP_W128: return launch_rnw_persistent_w128(bucket, variant, jobs, data, queue, item_end, nqueue, total_items, head, accs, cycles, grid, s);
+        default: return launch_rnw_persistent_res(bucket, variant, jobs, data, queue, item_end, nqueue, total_items, head, accs, cycles, grid, s);
     }
 }
 

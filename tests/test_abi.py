@@ -156,3 +156,15 @@ def test_residue_primes_are_prime():
     for c in (1, 31, 45):
         assert sympy.isprime(2 ** 61 - c)
     assert math.prod(2 ** 61 - c for c in (1, 31, 45)) > 2 ** 182
+
+
+def test_job_cycles_need_a_timed_run(hp):
+    c = hp.Context(host_only=True)
+    try:
+        J = c.jobs_from_dense([np.ones((3, 3), np.uint32)])
+        with pytest.raises(hp.HpermError):
+            J.cycles()
+        with pytest.raises(hp.HpermError):
+            c.set_opts(time_jobs=2)
+    finally:
+        c.close()

@@ -321,3 +321,24 @@ def test_largest_orders_and_sizes(hperm, ctx):
     with pytest.raises(hperm.HpermError) as e:
         ctx.permanent(2 * np.eye(128, dtype=np.uint32) + np.roll(np.eye(128, dtype=np.uint32), 1, axis=1))
     assert e.value.status == -2
+
+
+def test_job_timing(hperm):
+    """time_jobs = 1: every job of a timed persistent run gets positive work cycles, the values
+    are unchanged, and jobs with 64 times the subset-terms take many times longer."""
+    say("job timing")
+    c = hperm.Context({"time_jobs": 1})
+    try:
+        mats = [leaf_like(m, 500 + i, k=3) for i, m in enumerate((14, 20, 14, 20))]
+        J = c.jobs_from_dense(mats)
+        totals, per_job, _ = c.run(J, "natural", True, per_job=True)
+        cyc = J.cycles()
+        assert per_job == native.ryser_batch(mats, threads=8)
+        assert (cyc > 0).all()
+        assert min(cyc[1], cyc[3]) > 10 * max(cyc[0], cyc[2]), cyc
+        c.set_opts(time_jobs=0)
+        totals2, _, _ = c.run(J, "natural", True)
+        assert totals2 == totals
+        assert (J.cycles() == cyc).all()   # an untimed run keeps the last timing
+    finally:
+        c.close()
