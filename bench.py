@@ -374,7 +374,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK,
                      "unit": "VALU lane-slots/s", "frac": achieved / ALU_PEAK,
                      "traffic": traffic_from_profile(),
-                     "kernel": f"rnw_persistent ({ring_name}, orders <= {[16, 24, 32, 40][bucket]}, "
+                     "kernel": f"rnw_persistent ({ring_name}, orders <= {[16, 20, 24, 32, 40][bucket]}, "
                                f"{['step-pair walk', 'paired walk, two-row column 0', 'paired walk, three-row column 0'][variant]})",
                      "avg_launch_ms": avg_ms, "alg_slots_per_launch": alg_per_launch,
                      "jobs_per_launch": dom["jobs"] // dom["n"], "terms_per_launch": dom["terms"] // dom["n"]},

@@ -259,7 +259,7 @@ hperm_status hperm_cancel(hperm_ctx *ctx, uint64_t ticket);
 /* One R-NW kernel launch of the last hperm_run_jobs / hperm_permanent_* call. */
 typedef struct hperm_launch_stat {
     int32_t ring;           /* 0: mod 2^64, 1: mod 2^128, 2: residues */
-    int32_t bucket;         /* kernel instantiation: job orders <= 16, 24, 32, 40 */
+    int32_t bucket;         /* kernel instantiation: job orders <= 16, 20, 24, 32, 40 */
     int32_t n_jobs;         /* jobs in the launch (1 in one-launch-per-job mode) */
     int32_t persistent;
     int32_t variant;        /* walk variant: 0, or 1 / 2 for the paired walk of jobs whose

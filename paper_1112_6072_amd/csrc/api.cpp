@@ -418,9 +418,10 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     // one counting pass: group g = (bucket, ring, walk variant) from the largest bucket and
     // the widest ring down, each group keeping the chosen order
     constexpr int NV = 3;
-    constexpr int NG = 4 * HP_NRING * NV;
+    constexpr int NG = HP_RNW_BUCKETS * HP_NRING * NV;
     auto gid = [&](const JobDesc &d) {
-        return ((3 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith)) * NV + walk_variant(d, d.chunk_log2);
+        return ((HP_RNW_BUCKETS - 1 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith)) * NV +
+               walk_variant(d, d.chunk_log2);
     };
     size_t cnt[NG + 1] = {0};
     for (const JobDesc &d : dsc) cnt[gid(d) + 1]++;
@@ -428,8 +429,8 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     std::vector<Group> groups;
     for (int g = 0; g < NG; ++g)
         if (cnt[g + 1] > cnt[g])
-            groups.push_back(Group{HP_NRING - 1 - (g / NV) % HP_NRING, 3 - g / (NV * HP_NRING), g % NV, cnt[g],
-                                   cnt[g + 1] - cnt[g], 0});
+            groups.push_back(Group{HP_NRING - 1 - (g / NV) % HP_NRING, HP_RNW_BUCKETS - 1 - g / (NV * HP_NRING),
+                                   g % NV, cnt[g], cnt[g + 1] - cnt[g], 0});
     queue.resize(nd);
     item_end.resize(nd);
     {

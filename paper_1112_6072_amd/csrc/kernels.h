@@ -7,7 +7,9 @@
 
 namespace hp {
 
-// Order bucket of a job: the R-NW kernels are instantiated for m <= 16, 24, 32, 40.
+// Order bucket of a job: the R-NW kernels are instantiated for m <= 16, 20, 24, 32, 40
+// (HP_RNW_BUCKETS of them).
+constexpr int HP_RNW_BUCKETS = 5;
 int bucket_of(int m);
 
 // Order bucket of the estimator: m <= 16, 20, 24, 32, 40 (HP_EST_BUCKETS of them).

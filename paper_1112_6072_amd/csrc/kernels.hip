@@ -514,9 +514,12 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
 // Persistent kernel: every wave repeatedly takes the next work item of the queue. The
 // queue is the list of jobs in scheduling order; item_end[s] is the number of items of
 // the first s+1 queued jobs (jobs own contiguous item ranges). Every queued job has
-// order at most MAXM (the host queues jobs by order bucket).
+// order at most MAXM (the host queues jobs by order bucket). The two-row paired walk of the
+// order-20 bucket (the default cut-off's jobs) is held to 64 VGPRs, 8 waves per SIMD: it needs
+// 66 unconstrained, and the one value that then spills is stored and reloaded once per item,
+// outside the Gray loop. (The same limit made the three-row walk slower.)
 template <class R, int MAXM, int V>
-__global__ __launch_bounds__(BLOCK) void rnw_persistent(const JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(BLOCK, (MAXM == 20 && V == 1 ? 8 : 1)) void rnw_persistent(const JobDesc *__restrict__ jobs,
                                                         const uint32_t *__restrict__ data,
                                                         const uint32_t *__restrict__ queue,
                                                         const uint64_t *__restrict__ item_end,
@@ -971,7 +974,7 @@ namespace hp {
 
 #if HP_PART == 0
 
-int bucket_of(int m) { return m <= 16 ? 0 : (m <= 24 ? 1 : (m <= 32 ? 2 : 3)); }
+int bucket_of(int m) { return m <= 16 ? 0 : (m <= 20 ? 1 : (m <= 24 ? 2 : (m <= 32 ? 3 : 4))); }
 
 int est_bucket_of(int m) { return m <= 16 ? 0 : (m <= 20 ? 1 : (m <= 24 ? 2 : (m <= 32 ? 3 : 4))); }
 
@@ -1032,23 +1035,26 @@ static const void *persistent_fn(int bucket, int variant, bool timed) {
     if (!timed) {
         switch (bucket) {
             case 0: return HP_FN(rnw_persistent, 16);
-            case 1: return HP_FN(rnw_persistent, 24);
-            case 2: return HP_FN(rnw_persistent, 32);
+            case 1: return HP_FN(rnw_persistent, 20);
+            case 2: return HP_FN(rnw_persistent, 24);
+            case 3: return HP_FN(rnw_persistent, 32);
             default: return HP_FN(rnw_persistent, HP_MAX_M);
         }
     }
     switch (bucket) {
         case 0: return HP_FN(rnw_persistent_timed, 16);
-        case 1: return HP_FN(rnw_persistent_timed, 24);
-        case 2: return HP_FN(rnw_persistent_timed, 32);
+        case 1: return HP_FN(rnw_persistent_timed, 20);
+        case 2: return HP_FN(rnw_persistent_timed, 24);
+        case 3: return HP_FN(rnw_persistent_timed, 32);
         default: return HP_FN(rnw_persistent_timed, HP_MAX_M);
     }
 }
 static const void *single_fn(int bucket, int variant) {
     switch (bucket) {
         case 0: return HP_FN(rnw_single, 16);
-        case 1: return HP_FN(rnw_single, 24);
-        case 2: return HP_FN(rnw_single, 32);
+        case 1: return HP_FN(rnw_single, 20);
+        case 2: return HP_FN(rnw_single, 24);
+        case 3: return HP_FN(rnw_single, 32);
         default: return HP_FN(rnw_single, HP_MAX_M);
     }
 }
