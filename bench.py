@@ -314,6 +314,20 @@ def main():
         walls1.append(time.perf_counter() - t0)
     e2e_c60 = sorted(walls1)[2]
     verified = verified and c60 == vals[0]
+    # permanental polynomial per(xI - A) of a random cubic graph on 24 vertices (25 exact
+    # evaluations of per(xI + A) in one batch, then exact interpolation); median of 5
+    G24 = W.random_cubic_matrix(24, 0)
+    poly = ctx.permanental_polynomial(G24)
+    wp = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.permanental_polynomial(G24)
+        wp.append(time.perf_counter() - t0)
+    extra["permanental_polynomial"] = {
+        "graph": "random cubic, n=24, seed 0", "ms": sorted(wp)[2] * 1e3,
+        "checks": {"leading_1": poly[24] == 1, "trace_0": poly[23] == 0, "edges_36": poly[22] == 36,
+                   "constant_is_per": poly[0] == ctx.permanent(G24)}}
     log("scheduling study on the n60 jobs")
     extra["schedule_study_n60"] = schedule_study(hp, ctx, jobs, ctx.estimate(jobs, args.trials, 1))
     plain = None

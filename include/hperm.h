@@ -123,6 +123,9 @@ void hperm_ctx_destroy(hperm_ctx *ctx);
 /* Replace the context's options (same ranges as hperm_ctx_create). */
 hperm_status hperm_ctx_set_opts(hperm_ctx *ctx, const hperm_opts *opts);
 
+/* Copy the context's current options into *opts. */
+hperm_status hperm_ctx_get_opts(const hperm_ctx *ctx, hperm_opts *opts);
+
 /* Let the library sub-allocate every device buffer from [dev_ptr, dev_ptr + bytes) (device
  * memory owned by the caller, e.g. a torch tensor), valid until the context is destroyed
  * or the arena is replaced. dev_ptr = NULL returns to library-owned memory. A call whose
@@ -153,6 +156,40 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *ctx, int32_t count, const int3
                                        const int64_t *rp_off, const int64_t *nz_off,
                                        const int32_t *row_ptr, const int32_t *col_idx,
                                        const uint32_t *val, hperm_result *out);
+
+/* One signed integer coefficient: |c| = sum_k limb[k] * 2^(64k), negative when c < 0. */
+typedef struct hperm_coeff {
+    uint64_t limb[8];
+    int32_t nlimb;          /* limbs in use (0 means c = 0) */
+    int32_t negative;
+} hperm_coeff;
+
+/* Permanental polynomial (the paper's application to chemical graphs): coeffs[k] = c_k with
+ * per(xI - A) = sum_{k=0..n} c_k x^k, exactly, for a non-negative integer matrix A (CSR as for
+ * hperm_permanent_csr). Computed from per(xI + A) at x = 0..n, n + 1 problems of one batched
+ * pass (xI + A has non-negative entries; per(xI + A) = sum_k a_k x^k with a_k the sum of the
+ * permanents of the principal sub-matrices of order n - k, and c_k = (-1)^(n-k) a_k), then
+ * exact integer interpolation on the host. For n <= 40 the evaluations run with m_cut raised
+ * to n (each xI + A is one R-NW job: no expansion, whose merges would multiply the large
+ * diagonal entries); the context's options are restored afterwards. coeffs[n + 1] is
+ * caller-owned. The bound of per(nI + A) must stay below 2^180 (e.g. cubic graphs up to
+ * n = 34). Must not be called while serving or concurrently with other calls on the context.
+ * Errors: as for
+ * hperm_permanent_batch_csr; HPERM_E_RANGE when a bound or an intermediate exceeds the
+ * supported range; HPERM_E_INTERNAL when the interpolation fails its exactness checks. */
+hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                                          const int32_t *col_idx, const uint32_t *val,
+                                          hperm_coeff *coeffs);
+
+/* The host step of hperm_permanental_polynomial on its own: the coefficients of the integer
+ * polynomial p of degree <= n with p(x) = values[x] for x = 0..n (values[(n + 1) * 8]: each a
+ * non-negative little-endian 512-bit integer), by forward differences and the Newton
+ * (falling-factorial) form, exactly; with alternate != 0 coefficient k is negated when n - k is
+ * odd (p(x) = per(xI + A) then gives per(xI - A)). coeffs[n + 1]. Errors: HPERM_E_INVALID
+ * (n out of 0..128, NULL arrays, or values that no integer-coefficient polynomial of degree n
+ * takes), HPERM_E_RANGE (an intermediate beyond 500 bits). */
+hperm_status hperm_polynomial_interpolate(int32_t n, const uint64_t *values, int32_t alternate,
+                                          hperm_coeff *coeffs);
 
 /* ---- stages (tests and benchmarks) ------------------------------------------------ */
 

@@ -18,6 +18,11 @@ LIB_PATH = os.path.join(_HERE, "_build", "libhperm.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1112_6072_amd/build.py`")
 
+# torch first: its HIP runtime is then the one the library binds to, whichever of the two is
+# used first in the process (loading the library first left two runtimes, and contexts created
+# afterwards saw no device)
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, NOT_READY = 0, 1
@@ -39,6 +44,15 @@ class Opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("chunk_log2", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("host_threads", ctypes.c_int32),
                 ("max_table_mib", ctypes.c_int32), ("time_jobs", ctypes.c_int32)]
+
+
+class Coeff(ctypes.Structure):
+    _fields_ = [("limb", ctypes.c_uint64 * 8), ("nlimb", ctypes.c_int32), ("negative", ctypes.c_int32)]
+
+    @property
+    def value(self) -> int:
+        v = sum(int(self.limb[k]) << (64 * k) for k in range(self.nlimb))
+        return -v if self.negative else v
 
 
 class Result(ctypes.Structure):
@@ -76,6 +90,7 @@ _SIGS = {
     "hperm_ctx_create": [ctypes.POINTER(Opts), _P, ctypes.POINTER(_P)],
     "hperm_ctx_create_host": [ctypes.POINTER(Opts), ctypes.POINTER(_P)],
     "hperm_ctx_set_opts": [_P, ctypes.POINTER(Opts)],
+    "hperm_ctx_get_opts": [_P, ctypes.POINTER(Opts)],
     "hperm_ctx_set_arena": [_P, _P, _SZ],
     "hperm_permanent_csr": [_P, _I32, _P, _P, _P, ctypes.POINTER(Result)],
     "hperm_permanent_dense": [_P, _I32, _P, ctypes.POINTER(Result)],
@@ -94,6 +109,8 @@ _SIGS = {
     "hperm_cancel": [_P, _U64],
     "hperm_last_launches": [_P, ctypes.POINTER(LaunchStat), _I32, ctypes.POINTER(_I32)],
     "hperm_jobs_cycles": [_P, _P],
+    "hperm_permanental_polynomial": [_P, _I32, _P, _P, _P, _P],
+    "hperm_polynomial_interpolate": [_I32, _P, _I32, _P],
     "hperm_list_schedule": [_I32, _P, _P, _I32, ctypes.POINTER(_U64), _P],
     "hperm_kendall_tau": [_I32, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_double)],
@@ -290,6 +307,16 @@ class Context:
             return vals, [out[k].stats() for k in range(len(mats))]
         return vals
 
+    def permanental_polynomial(self, A) -> list[int]:
+        """Exact coefficients c_0..c_n of per(xI - A) = sum_k c_k x^k (c_k of x^k)."""
+        n, rp, ci, va = _csr(A)
+        ci = ci if ci.size else np.zeros(1, np.int32)
+        va = va if va.size else np.zeros(1, np.uint32)
+        out = (Coeff * (n + 1))()
+        self._check(_lib.hperm_permanental_polynomial(self.handle, n, _ptr(rp), _ptr(ci), _ptr(va), out),
+                    "permanental_polynomial")
+        return [out[k].value for k in range(n + 1)]
+
     def permanent_csr(self, n, row_ptr, col_idx, val) -> int:
         rp = np.ascontiguousarray(row_ptr, np.int32)
         ci = np.ascontiguousarray(col_idx, np.int32)
@@ -427,3 +454,24 @@ def kendall_tau(x, y) -> tuple[float, float, float]:
     if st != OK:
         raise HpermError(st, "kendall_tau")
     return tau.value, z.value, p.value
+
+
+def polynomial_interpolate(values, alternate: bool = False) -> list[int]:
+    """Integer coefficients (low to high) of the degree-n polynomial through (x, values[x]),
+    x = 0..n, for non-negative integer values below 2^512 (the host step of the permanental
+    polynomial; with alternate, coefficient k is negated when n - k is odd)."""
+    n = len(values) - 1
+    if n < 0:
+        raise ValueError("at least one value")
+    limbs = np.zeros((n + 1) * 8, dtype=np.uint64)
+    for x, v in enumerate(values):
+        v = int(v)
+        if v < 0 or v >> 512:
+            raise ValueError("values must be non-negative and below 2^512")
+        for k in range(8):
+            limbs[8 * x + k] = (v >> (64 * k)) & ((1 << 64) - 1)
+    out = (Coeff * (n + 1))()
+    st = _lib.hperm_polynomial_interpolate(n, _ptr(limbs), 1 if alternate else 0, out)
+    if st != OK:
+        raise HpermError(st, "polynomial_interpolate")
+    return [out[k].value for k in range(n + 1)]

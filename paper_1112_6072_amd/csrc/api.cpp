@@ -829,6 +829,12 @@ void hperm_ctx_destroy(hperm_ctx *c) {
     delete c;
 }
 
+hperm_status hperm_ctx_get_opts(const hperm_ctx *c, hperm_opts *o) {
+    if (!c || !o) return HPERM_E_INVALID;
+    *o = c->opts;
+    return HPERM_OK;
+}
+
 hperm_status hperm_ctx_set_opts(hperm_ctx *c, const hperm_opts *o) {
     if (!c || !o) return HPERM_E_INVALID;
     if (const char *why = check_opts(o)) return set_error(c, HPERM_E_INVALID, why);

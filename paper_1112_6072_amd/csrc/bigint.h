@@ -44,6 +44,80 @@ struct U512 {
     }
 };
 
+// Compare magnitudes: -1, 0, 1.
+inline int cmp(const U512 &a, const U512 &b) {
+    for (int k = 7; k >= 0; --k)
+        if (a.w[k] != b.w[k]) return a.w[k] < b.w[k] ? -1 : 1;
+    return 0;
+}
+
+// a - b for a >= b.
+inline U512 sub(const U512 &a, const U512 &b) {
+    U512 r;
+    uint64_t borrow = 0;
+    for (int k = 0; k < 8; ++k) {
+        const u128 t = (u128)a.w[k] - b.w[k] - borrow;
+        r.w[k] = (uint64_t)t;
+        borrow = (uint64_t)(t >> 64) ? 1 : 0;
+    }
+    return r;
+}
+
+// Signed 512-bit integer in sign-magnitude form (the exact interpolation of the permanental
+// polynomial). Operations report overflow of the 512-bit magnitude by returning false.
+struct S512 {
+    U512 mag;
+    bool neg = false;
+    bool is_zero() const { return mag.nlimb() == 0; }
+    S512 operator-() const {
+        S512 r = *this;
+        if (!r.is_zero()) r.neg = !r.neg;
+        return r;
+    }
+};
+
+inline S512 add(const S512 &a, const S512 &b) {
+    S512 r;
+    if (a.neg == b.neg) {
+        r.mag = a.mag;
+        r.mag.add(b.mag);
+        r.neg = a.neg;
+    } else if (cmp(a.mag, b.mag) >= 0) {
+        r.mag = sub(a.mag, b.mag);
+        r.neg = a.neg;
+    } else {
+        r.mag = sub(b.mag, a.mag);
+        r.neg = b.neg;
+    }
+    if (r.is_zero()) r.neg = false;
+    return r;
+}
+
+inline S512 sub(const S512 &a, const S512 &b) { return add(a, -b); }
+
+// a * m; false when the magnitude leaves 512 bits.
+inline bool mul_u64(S512 &a, uint64_t m) {
+    u128 c = 0;
+    for (int k = 0; k < 8; ++k) {
+        c += (u128)a.mag.w[k] * m;
+        a.mag.w[k] = (uint64_t)c;
+        c >>= 64;
+    }
+    if (a.is_zero()) a.neg = false;
+    return c == 0;
+}
+
+// a / m when m divides a exactly; false otherwise.
+inline bool divexact_u64(S512 &a, uint64_t m) {
+    u128 rem = 0;
+    for (int k = 7; k >= 0; --k) {
+        const u128 cur = (rem << 64) | a.mag.w[k];
+        a.mag.w[k] = (uint64_t)(cur / m);
+        rem = cur % m;
+    }
+    return rem == 0;
+}
+
 inline uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p) { return (uint64_t)((u128)a * b % p); }
 
 inline uint64_t powmod(uint64_t a, uint64_t e, uint64_t p) {

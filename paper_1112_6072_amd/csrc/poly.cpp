@@ -1,0 +1,172 @@
+// The permanental polynomial per(xI - A) of a non-negative integer matrix (the paper's
+// application section, where it is evaluated at complex points in floating point). Here it
+// is exact: per(xI + A) = sum_k a_k x^k, where a_k is the sum of the permanents of the
+// principal sub-matrices of A of order n - k (every term of the permanent takes, for each row,
+// either the x of the diagonal or an entry of A), so a_k >= 0 and
+// per(xI - A) = sum_k (-1)^(n-k) a_k x^k. The matrices xI + A for x = 0..n have non-negative
+// entries: they are n + 1 problems of one batched device pass (steps 1-6 of the hot path),
+// and the n + 1 values determine the degree-n polynomial. The coefficients come from exact
+// integer interpolation: forward differences give the Newton coefficients e_k =
+// Delta^k p(0) / k! (integers, as p has integer coefficients), and p(x) = sum_k e_k x(x-1)..(x-k+1)
+// is expanded by Horner's rule in that basis, p = e_0 + x(e_1 + (x-1)(e_2 + ...)).
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/hperm.h"
+#include "bigint.h"
+#include "expand.h"
+
+using hp::S512;
+using hp::U512;
+
+namespace {
+
+// The CSR arrays of xI + A (entries of A on the diagonal are increased by x).
+void add_diagonal(int32_t n, const int32_t *rp, const int32_t *ci, const uint32_t *va, uint32_t x,
+                  std::vector<int32_t> &orp, std::vector<int32_t> &oci, std::vector<uint32_t> &ova) {
+    const size_t base = oci.size();
+    for (int32_t i = 0; i < n; ++i) {
+        orp.push_back((int32_t)(oci.size() - base));
+        bool placed = false;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (!placed && ci[e] >= i) {
+                if (ci[e] == i) {
+                    oci.push_back(i);
+                    ova.push_back(va[e] + x);
+                    placed = true;
+                    continue;
+                }
+                if (x) {
+                    oci.push_back(i);
+                    ova.push_back(x);
+                }
+                placed = true;
+            }
+            oci.push_back(ci[e]);
+            ova.push_back(va[e]);
+        }
+        if (!placed && x) {
+            oci.push_back(i);
+            ova.push_back(x);
+        }
+    }
+    orp.push_back((int32_t)(oci.size() - base));
+}
+
+S512 from_limbs(const uint64_t *limb) {
+    S512 v;
+    for (int k = 0; k < 8; ++k) v.mag.w[k] = limb[k];
+    return v;
+}
+
+}  // namespace
+
+hperm_status hperm_polynomial_interpolate(int32_t n, const uint64_t *values, int32_t alternate,
+                                          hperm_coeff *coeffs) {
+    if (n < 0 || n > 128 || !values || !coeffs) return HPERM_E_INVALID;
+    const int np = n + 1;
+    // forward differences d[k] = Delta^k p(0)
+    std::vector<S512> d((size_t)np);
+    for (int x = 0; x < np; ++x) d[(size_t)x] = from_limbs(values + 8 * (size_t)x);
+    for (int k = 1; k < np; ++k)
+        for (int i = n; i >= k; --i) d[(size_t)i] = hp::sub(d[(size_t)i], d[(size_t)i - 1]);
+    // Newton coefficients e_k = d[k] / k!
+    for (int k = 2; k < np; ++k)
+        for (int j = 2; j <= k; ++j)
+            if (!hp::divexact_u64(d[(size_t)k], (uint64_t)j)) return HPERM_E_INVALID;
+    // Horner in the falling-factorial basis: poly = e_k + (x - k) poly, k = n-1 .. 0
+    std::vector<S512> poly((size_t)np);
+    poly[0] = d[(size_t)n];
+    for (int k = n - 1; k >= 0; --k) {
+        const int deg = n - 1 - k;   // degree of poly before this step
+        std::vector<S512> next((size_t)deg + 2);
+        for (int j = deg; j >= 0; --j) {
+            next[(size_t)j + 1] = hp::add(next[(size_t)j + 1], poly[(size_t)j]);
+            S512 t = poly[(size_t)j];
+            if (!hp::mul_u64(t, (uint64_t)k)) return HPERM_E_RANGE;
+            next[(size_t)j] = hp::sub(next[(size_t)j], t);
+        }
+        next[0] = hp::add(next[0], d[(size_t)k]);
+        for (int j = 0; j <= deg + 1; ++j) {
+            poly[(size_t)j] = next[(size_t)j];
+            if (poly[(size_t)j].mag.bits() > 500) return HPERM_E_RANGE;
+        }
+    }
+    // exactness: the polynomial reproduces every value
+    for (int x = 0; x < np; ++x) {
+        S512 v = poly[(size_t)n];
+        for (int j = n - 1; j >= 0; --j) {
+            if (!hp::mul_u64(v, (uint64_t)x)) return HPERM_E_RANGE;
+            v = hp::add(v, poly[(size_t)j]);
+        }
+        const S512 want = from_limbs(values + 8 * (size_t)x);
+        if (v.neg || hp::cmp(v.mag, want.mag) != 0) return HPERM_E_INVALID;
+    }
+    for (int j = 0; j < np; ++j) {
+        memset(&coeffs[j], 0, sizeof(hperm_coeff));
+        for (int k = 0; k < 8; ++k) coeffs[j].limb[k] = poly[(size_t)j].mag.w[k];
+        coeffs[j].nlimb = poly[(size_t)j].mag.nlimb();
+        bool neg = poly[(size_t)j].neg;
+        if (alternate && ((n - j) & 1)) neg = !neg;
+        coeffs[j].negative = (neg && coeffs[j].nlimb) ? 1 : 0;
+    }
+    return HPERM_OK;
+}
+
+hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                                          const int32_t *col_idx, const uint32_t *val,
+                                          hperm_coeff *coeffs) {
+    if (!ctx || !coeffs || n < 0 || n > 128) return HPERM_E_INVALID;
+    if (n > 0 && (!row_ptr || !col_idx || !val)) return HPERM_E_INVALID;
+    if (n > 0 && !hp::validate_csr(hp::CsrView{n, row_ptr, col_idx, val}).empty()) return HPERM_E_INVALID;
+    for (int32_t i = 0; n > 0 && i < n; ++i)
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            if (col_idx[e] == i && val[e] > UINT32_MAX - (uint32_t)n) return HPERM_E_RANGE;
+    const int np = n + 1;
+    // the n + 1 problems xI + A, concatenated
+    std::vector<int32_t> rp, ci, sizes((size_t)np, n);
+    std::vector<uint32_t> va;
+    std::vector<int64_t> rp_off((size_t)np), nz_off((size_t)np);
+    for (int x = 0; x < np; ++x) {
+        rp_off[(size_t)x] = (int64_t)rp.size();
+        nz_off[(size_t)x] = (int64_t)ci.size();
+        add_diagonal(n, row_ptr, col_idx, val, (uint32_t)x, rp, ci, va);
+    }
+    ci.push_back(0);   // non-empty arrays for the empty matrix
+    va.push_back(0);
+    std::vector<hperm_result> res((size_t)np);
+    // up to order 40 every xI + A is a single job (m_cut = n): no expansion merges, which would
+    // multiply the diagonal's large entries together
+    hperm_opts saved, o;
+    hperm_status s = hperm_ctx_get_opts(ctx, &saved);
+    if (s) return s;
+    o = saved;
+    if (n <= 40) {
+        o.m_cut = std::max(o.m_cut, n);
+        o.m_cap = std::max(o.m_cap, o.m_cut);
+        s = hperm_ctx_set_opts(ctx, &o);
+        if (s) return s;
+    }
+    s = hperm_permanent_batch_csr(ctx, np, sizes.data(), rp_off.data(), nz_off.data(), rp.data(),
+                                  ci.data(), va.data(), res.data());
+    if (n <= 40) {
+        const hperm_status r = hperm_ctx_set_opts(ctx, &saved);
+        if (!s) s = r;
+    }
+    if (s) return s;
+    std::vector<uint64_t> values((size_t)np * 8);
+    for (int x = 0; x < np; ++x)
+        for (int k = 0; k < 8; ++k) values[(size_t)x * 8 + k] = res[(size_t)x].limb[k];
+    // p(x) = per(xI + A); c_k = (-1)^(n-k) a_k
+    const hperm_status si = hperm_polynomial_interpolate(n, values.data(), 1, coeffs);
+    if (si == HPERM_E_INVALID) return HPERM_E_INTERNAL;   // values from the device that no
+                                                          // integer polynomial of degree n fits
+    if (si) return si;
+    for (int j = 0; j < np; ++j)   // a_k >= 0: the sign must be exactly the alternation
+        if (coeffs[j].nlimb && coeffs[j].negative != ((n - j) & 1)) return HPERM_E_INTERNAL;
+    return HPERM_OK;
+}
