@@ -423,8 +423,24 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         return ((HP_RNW_BUCKETS - 1 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith)) * NV +
                walk_variant(d, d.chunk_log2);
     };
+    size_t cnt_raw[NG] = {0};
+    uint64_t items_raw[NG] = {0};
+    for (const JobDesc &d : dsc) {
+        const int g = gid(d);
+        cnt_raw[g]++;
+        items_raw[g] += items_of(d.m, d.chunk_log2);
+    }
+    // The order-20 bucket exists for the many jobs of the default cut-off; when a (ring, walk)
+    // group of it is small, its jobs join the order-24 group instead (whose kernel takes them
+    // too), saving a launch and its drain tail.
+    constexpr uint64_t kSmallGroupItems = 65536;
+    int remap[NG];
+    for (int g = 0; g < NG; ++g) {
+        const int bucket = HP_RNW_BUCKETS - 1 - g / (NV * HP_NRING);
+        remap[g] = (bucket == 1 && items_raw[g] < kSmallGroupItems) ? g - NV * HP_NRING : g;
+    }
     size_t cnt[NG + 1] = {0};
-    for (const JobDesc &d : dsc) cnt[gid(d) + 1]++;
+    for (int g = 0; g < NG; ++g) cnt[remap[g] + 1] += cnt_raw[g];
     for (int g = 0; g < NG; ++g) cnt[g + 1] += cnt[g];
     std::vector<Group> groups;
     for (int g = 0; g < NG; ++g)
@@ -436,7 +452,7 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     {
         size_t pos[NG];
         for (int g = 0; g < NG; ++g) pos[g] = cnt[g];
-        for (uint32_t k : ord) queue[pos[gid(dsc[k])]++] = k;
+        for (uint32_t k : ord) queue[pos[remap[gid(dsc[k])]]++] = k;
     }
     for (Group &g : groups) {
         uint64_t acc = 0;

@@ -151,8 +151,14 @@ hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32
         s = hperm_ctx_set_opts(ctx, &o);
         if (s) return s;
     }
-    s = hperm_permanent_batch_csr(ctx, np, sizes.data(), rp_off.data(), nz_off.data(), rp.data(),
-                                  ci.data(), va.data(), res.data());
+    // the bound grows with x: check the last problem (x = n) on the host before any device work
+    hperm_jobs *probe = nullptr;
+    s = hperm_expand_batch_csr(ctx, 1, sizes.data() + n, rp_off.data() + n, nz_off.data() + n, rp.data(),
+                               ci.data(), va.data(), &probe);
+    if (probe) hperm_jobs_free(probe);
+    if (!s)
+        s = hperm_permanent_batch_csr(ctx, np, sizes.data(), rp_off.data(), nz_off.data(), rp.data(),
+                                      ci.data(), va.data(), res.data());
     if (n <= 40) {
         const hperm_status r = hperm_ctx_set_opts(ctx, &saved);
         if (!s) s = r;
