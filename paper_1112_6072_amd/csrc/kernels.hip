@@ -76,11 +76,13 @@ __device__ __forceinline__ uint64_t mulmod_full(uint64_t a, uint64_t b) {
 // for a negative term, zero for a positive one.
 
 // pair_mul(s, d): s times the signed integer d (|d| < 2^74) in the ring; the paired walk's
-// sum of two terms is S_b * (P_t - P_{t+1}). Small is wide enough for the products P of up to
-// three row values (exact below 2^72; mod 2^64 wrap-around is exact for that ring).
+// sum of two terms is S_b * X. Small holds X exactly (below 2^74) in the wide rings and modulo
+// 2^64 in the 64-bit one, which is all that ring needs; USmall is its unsigned twin, in which
+// the wrapping arithmetic is done.
 struct RingW64 {
     struct P { uint64_t v; };
     using Small = int64_t;
+    using USmall = uint64_t;
     __device__ static P pair_mul(const P &s, Small d) { return {s.v * (uint64_t)d}; }
     // -p = (p xor ~0) + 1: the accumulator adds p xor mask and counts the +1s apart
     struct Acc { uint64_t v; uint32_t n; };
@@ -108,6 +110,7 @@ struct RingW64 {
 struct RingW128 {
     struct P { uint32_t x0, x1, x2, x3; };
     using Small = __int128;
+    using USmall = unsigned __int128;
     __device__ static P pair_mul(const P &s, Small d) {
         const unsigned __int128 v = (((unsigned __int128)s.x3 << 96) | ((unsigned __int128)s.x2 << 64) |
                                      ((unsigned __int128)s.x1 << 32) | s.x0) * (unsigned __int128)d;
@@ -180,6 +183,7 @@ struct RingRes {
     struct P { uint64_t r0, r1, r2; };
     using Acc = P;
     using Small = __int128;
+    using USmall = unsigned __int128;
     __device__ static P pair_mul(const P &s, Small d) {
         return {mulmod_signed<HP_C0>(s.r0, d), mulmod_signed<HP_C1>(s.r1, d), mulmod_signed<HP_C2>(s.r2, d)};
     }
@@ -478,14 +482,18 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
         if constexpr (PB == 2) {                                                           \
             x = k01 + (Sm)dcol[0] * (Sm)(int)f[1] + (Sm)dcol[1] * (Sm)(int)f[0];           \
         } else {                                                                           \
-            Sm pg = (Sm)(int)f[0];                                                         \
-            Sm ph = (Sm)((int)f[0] + dcol[0]);                                             \
-            _Pragma("unroll") for (int i = 1; i < PB; ++i) {                               \
-                const int gi_ = (int)f[i];                                                 \
-                pg *= (Sm)gi_;                                                             \
-                ph *= (Sm)(gi_ + dcol[i]);                                                 \
-            }                                                                              \
-            x = ph - pg;                                                                   \
+            /* X = d0 h1 h2 + g0 (d1 h2 + g1 d2), h = g + d: two 32 x 32 -> 64-bit       */ \
+            /* products and two wider ones, in unsigned arithmetic (|X| < 2^74 wraps      */ \
+            /* modulo 2^64 in the 64-bit ring, exactly what that ring needs)             */ \
+            using Um = typename R::USmall;                                                 \
+            const int g0_ = (int)f[0], g1_ = (int)f[1], g2_ = (int)f[2];                   \
+            const int h2_ = g2_ + dcol[2];                                                 \
+            Sm a_ = (Sm)(g1_ + dcol[1]) * (Sm)h2_;                                         \
+            /* keep h1 h2 one 32 x 32 -> 64-bit product (the compiler would otherwise form */ \
+            /* d0 h2 first and multiply 64 x 64 bits)                                    */ \
+            if constexpr (sizeof(Sm) == 8) asm("" : "+v"(a_));                             \
+            const Sm b_ = (Sm)dcol[1] * (Sm)h2_ + (Sm)g1_ * (Sm)dcol[2];                   \
+            x = (Sm)((Um)(uint32_t)dcol[0] * (Um)a_ + (Um)(Sm)g0_ * (Um)b_);               \
         }                                                                                  \
         const uint32_t smask = ((t >> 1) & 1u) - 1u;   /* all ones: minus */               \
         R::acc(acc, R::pair_mul(S[PB], x), (uint32_t)((int)G[PB] >> 31) ^ smask);          \
