@@ -384,6 +384,58 @@ static hperm_status ensure_launch_events(Dev *c, size_t pairs) {
     return HPERM_OK;
 }
 
+// The persistent queue's launch groups of a job table (independent of the job order): group
+// g = (order bucket, ring, walk variant) from the largest bucket and the widest ring down. The
+// order-20 bucket exists for the many jobs of the default cut-off; when a (ring, walk) group of
+// it is small, its jobs join the order-24 group instead (whose kernel takes them too), saving
+// a launch and its drain tail.
+static void build_queue_groups(hperm_jobs *j) {
+    const std::vector<JobDesc> &dsc = j->tab.desc;
+    const size_t nd = dsc.size();
+    constexpr int NV = 3;
+    constexpr int NG = HP_RNW_BUCKETS * HP_NRING * NV;
+    constexpr uint64_t kSmallGroupItems = 65536;
+    std::vector<uint8_t> raw(nd);
+    j->qitems.resize(nd);
+    uint64_t items_raw[NG] = {0};
+    for (size_t k = 0; k < nd; ++k) {
+        const JobDesc &d = dsc[k];
+        const int g = ((HP_RNW_BUCKETS - 1 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith)) * NV +
+                      walk_variant(d, d.chunk_log2);
+        raw[k] = (uint8_t)g;
+        j->qitems[k] = items_of(d.m, d.chunk_log2);
+        items_raw[g] += j->qitems[k];
+    }
+    int remap[NG];
+    for (int g = 0; g < NG; ++g) {
+        const int bucket = HP_RNW_BUCKETS - 1 - g / (NV * HP_NRING);
+        remap[g] = (bucket == 1 && items_raw[g] < kSmallGroupItems) ? g - NV * HP_NRING : g;
+    }
+    hperm_jobs::QueueGroup acc[NG];
+    for (int g = 0; g < NG; ++g)
+        acc[g] = hperm_jobs::QueueGroup{HP_NRING - 1 - (g / NV) % HP_NRING, HP_RNW_BUCKETS - 1 - g / (NV * HP_NRING),
+                                        g % NV, 0, 0, 0, 0.0, 0.0, 0.0};
+    for (size_t k = 0; k < nd; ++k) {
+        const JobDesc &d = dsc[k];
+        hperm_jobs::QueueGroup &q = acc[remap[raw[k]]];
+        const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2, walk_variant(d, d.chunk_log2));
+        q.n++;
+        q.items += j->qitems[k];
+        q.terms += 1ull << (d.m - 1);
+        q.mults += wk.mults;
+        q.adds += wk.adds;
+        q.updates += wk.updates;
+    }
+    int index[NG];
+    j->qgroups.clear();
+    for (int g = 0; g < NG; ++g) {
+        index[g] = (int)j->qgroups.size();
+        if (acc[g].n) j->qgroups.push_back(acc[g]);
+    }
+    j->qgroup.resize(nd);
+    for (size_t k = 0; k < nd; ++k) j->qgroup[k] = (uint8_t)index[remap[raw[k]]];
+}
+
 hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool want_per_job) {
     const size_t nd = j->tab.desc.size();
     const int np = j->tab.n_problems;
@@ -407,68 +459,34 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         desc_plain = j->tab.desc;
         for (auto &d : desc_plain) d.chunk_log2 = (uint8_t)plain_chunk(d.m, c->opts.chunk_log2);
     }
-    const std::vector<JobDesc> &dsc = persistent ? j->tab.desc : desc_plain;
-    // queue groups by (ring, bucket), each in the chosen job order
-    const std::vector<uint32_t> ord = job_order(j, order, c->opts.seed);
+    // the persistent queue: the launch groups (cached per job table), each group's jobs in
+    // the chosen order, and inclusive prefix sums of their work items
     std::vector<uint32_t> &queue = c->h_queue;
     std::vector<uint64_t> &item_end = c->h_items;
-    queue.clear();
-    item_end.clear();
-    struct Group { int ring, bucket, variant; size_t off, n; uint64_t items; };
-    // one counting pass: group g = (bucket, ring, walk variant) from the largest bucket and
-    // the widest ring down, each group keeping the chosen order
-    constexpr int NV = 3;
-    constexpr int NG = HP_RNW_BUCKETS * HP_NRING * NV;
-    auto gid = [&](const JobDesc &d) {
-        return ((HP_RNW_BUCKETS - 1 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith)) * NV +
-               walk_variant(d, d.chunk_log2);
-    };
-    size_t cnt_raw[NG] = {0};
-    uint64_t items_raw[NG] = {0};
-    for (const JobDesc &d : dsc) {
-        const int g = gid(d);
-        cnt_raw[g]++;
-        items_raw[g] += items_of(d.m, d.chunk_log2);
-    }
-    // The order-20 bucket exists for the many jobs of the default cut-off; when a (ring, walk)
-    // group of it is small, its jobs join the order-24 group instead (whose kernel takes them
-    // too), saving a launch and its drain tail.
-    constexpr uint64_t kSmallGroupItems = 65536;
-    int remap[NG];
-    for (int g = 0; g < NG; ++g) {
-        const int bucket = HP_RNW_BUCKETS - 1 - g / (NV * HP_NRING);
-        remap[g] = (bucket == 1 && items_raw[g] < kSmallGroupItems) ? g - NV * HP_NRING : g;
-    }
-    size_t cnt[NG + 1] = {0};
-    for (int g = 0; g < NG; ++g) cnt[remap[g] + 1] += cnt_raw[g];
-    for (int g = 0; g < NG; ++g) cnt[g + 1] += cnt[g];
-    std::vector<Group> groups;
-    for (int g = 0; g < NG; ++g)
-        if (cnt[g + 1] > cnt[g])
-            groups.push_back(Group{HP_NRING - 1 - (g / NV) % HP_NRING, HP_RNW_BUCKETS - 1 - g / (NV * HP_NRING),
-                                   g % NV, cnt[g], cnt[g + 1] - cnt[g], 0});
-    queue.resize(nd);
-    item_end.resize(nd);
-    {
-        size_t pos[NG];
-        for (int g = 0; g < NG; ++g) pos[g] = cnt[g];
-        for (uint32_t k : ord) queue[pos[remap[gid(dsc[k])]]++] = k;
-    }
-    for (Group &g : groups) {
-        uint64_t acc = 0;
-        for (size_t q = g.off; q < g.off + g.n; ++q) {
-            const JobDesc &d = dsc[queue[q]];
-            acc += items_of(d.m, d.chunk_log2);
-            item_end[q] = acc;
+    std::vector<size_t> goff;
+    if (persistent) {
+        if (j->qgroup.size() != nd) build_queue_groups(j);
+        const std::vector<uint32_t> ord = job_order(j, order, c->opts.seed);
+        const size_t ng = j->qgroups.size();
+        goff.assign(ng + 1, 0);
+        for (size_t g = 0; g < ng; ++g) goff[g + 1] = goff[g] + j->qgroups[g].n;
+        std::vector<size_t> pos(goff.begin(), goff.end() - 1);
+        queue.resize(nd);
+        item_end.resize(nd);
+        for (uint32_t k : ord) queue[pos[j->qgroup[k]]++] = k;
+        for (size_t g = 0; g < ng; ++g) {
+            uint64_t acc = 0;
+            for (size_t q = goff[g]; q < goff[g + 1]; ++q) item_end[q] = acc += j->qitems[queue[q]];
         }
-        g.items = acc;
     }
     s = upload_jobs(c, j);
     if (s) return s;
-    s = ensure_buf(c, B_QUEUE, nd * sizeof(uint32_t));
-    if (s) return s;
-    s = ensure_buf(c, B_ITEMS, nd * sizeof(uint64_t));
-    if (s) return s;
+    if (persistent) {
+        s = ensure_buf(c, B_QUEUE, nd * sizeof(uint32_t));
+        if (s) return s;
+        s = ensure_buf(c, B_ITEMS, nd * sizeof(uint64_t));
+        if (s) return s;
+    }
     s = ensure_buf(c, B_ACCS, nd * sizeof(JobAcc));
     if (s) return s;
     s = ensure_buf(c, B_HEAD, 64 * sizeof(unsigned long long));
@@ -496,12 +514,14 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         if (s) return s;
         d_desc = (const JobDesc *)c->buf[B_DESC_PLAIN].ptr;
     }
-    s = hip_check(c, hipMemcpyAsync(c->buf[B_QUEUE].ptr, queue.data(), nd * 4,
-                                    hipMemcpyHostToDevice, c->stream), "upload queue");
-    if (s) return s;
-    s = hip_check(c, hipMemcpyAsync(c->buf[B_ITEMS].ptr, item_end.data(), nd * 8,
-                                    hipMemcpyHostToDevice, c->stream), "upload item ends");
-    if (s) return s;
+    if (persistent) {
+        s = hip_check(c, hipMemcpyAsync(c->buf[B_QUEUE].ptr, queue.data(), nd * 4,
+                                        hipMemcpyHostToDevice, c->stream), "upload queue");
+        if (s) return s;
+        s = hip_check(c, hipMemcpyAsync(c->buf[B_ITEMS].ptr, item_end.data(), nd * 8,
+                                        hipMemcpyHostToDevice, c->stream), "upload item ends");
+        if (s) return s;
+    }
     JobAcc *accs = (JobAcc *)c->buf[B_ACCS].ptr;
     unsigned long long *head = (unsigned long long *)c->buf[B_HEAD].ptr;
     s = hip_check(c, launch_fill_u64((unsigned long long *)accs, nd * (sizeof(JobAcc) / 8), 0ull,
@@ -520,22 +540,10 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     s = hip_check(c, hipEventRecord(c->ev0, c->stream), "event");
     if (s) return s;
     if (persistent) {
-        s = ensure_launch_events(c, groups.size());
+        s = ensure_launch_events(c, j->qgroups.size());
         if (s) return s;
-        if (j->work_mults.size() != nd) {
-            j->work_mults.resize(nd);
-            j->work_adds.resize(nd);
-            j->work_updates.resize(nd);
-            for (size_t k = 0; k < nd; ++k) {
-                const JobWork wk = job_work(dsc[k], j->tab.data.data(), dsc[k].chunk_log2,
-                                            walk_variant(dsc[k], dsc[k].chunk_log2));
-                j->work_mults[k] = wk.mults;
-                j->work_adds[k] = wk.adds;
-                j->work_updates[k] = wk.updates;
-            }
-        }
-        for (size_t gi = 0; gi < groups.size(); ++gi) {
-            const Group &g = groups[gi];
+        for (size_t gi = 0; gi < j->qgroups.size(); ++gi) {
+            const hperm_jobs::QueueGroup &g = j->qgroups[gi];
             hperm_launch_stat st{};
             st.ring = g.ring;
             st.bucket = g.bucket;
@@ -543,22 +551,15 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             st.persistent = 1;
             st.variant = g.variant;
             st.items = g.items;
-            double mults = 0.0, adds = 0.0, updates = 0.0;
-            for (size_t q = g.off; q < g.off + g.n; ++q) {
-                const uint32_t k = queue[q];
-                st.terms += 1ull << (dsc[k].m - 1);
-                mults += j->work_mults[k];
-                adds += j->work_adds[k];
-                updates += j->work_updates[k];
-            }
-            st.row_updates = (uint64_t)updates;
-            st.alg_slots = mults * ring_mul_slots(g.ring) + adds * ring_add_slots(g.ring) + updates;
+            st.terms = g.terms;
+            st.row_updates = (uint64_t)g.updates;
+            st.alg_slots = g.mults * ring_mul_slots(g.ring) + g.adds * ring_add_slots(g.ring) + g.updates;
             c->launches.push_back(st);
             s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
             if (s) return s;
             s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,
-                                                   (const uint32_t *)c->buf[B_QUEUE].ptr + g.off,
-                                                   (const uint64_t *)c->buf[B_ITEMS].ptr + g.off,
+                                                   (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi],
+                                                   (const uint64_t *)c->buf[B_ITEMS].ptr + goff[gi],
                                                    (uint32_t)g.n, g.items, head + gi, accs, cyc, 0,
                                                    c->stream),
                           "rnw_persistent launch");

@@ -32,9 +32,18 @@ struct hperm_jobs {
     std::vector<float> keys;   // KKLLL keys, natural index
     bool has_keys = false;
     uint64_t id = 0;           // identity for device residency
-    // per-job algorithmic work of the persistent walk (ring multiplies, row updates), filled
-    // on the first run
-    std::vector<double> work_mults, work_adds, work_updates;
+    // The persistent queue's grouping, which does not depend on the job order: per job its
+    // launch group and work items; per group its ring, order bucket, walk and totals (jobs,
+    // items, subset-terms, algorithmic work). Filled on the first persistent run.
+    struct QueueGroup {
+        int ring, bucket, variant;
+        size_t n;
+        uint64_t items, terms;
+        double mults, adds, updates;
+    };
+    std::vector<uint8_t> qgroup;
+    std::vector<uint64_t> qitems;
+    std::vector<QueueGroup> qgroups;
     // per-job work cycles of the last timed persistent run (natural index)
     std::vector<uint64_t> cycles;
     bool has_cycles = false;
