@@ -84,6 +84,7 @@ hperm_status ensure_buf(Dev *c, BufId id, size_t bytes) {
             off += cap;
         }
         if (moved) c->resident_jobs = 0;
+        c->resident_list = 0;
         return HPERM_OK;
     }
     if (b.ptr && b.owned) {
@@ -94,6 +95,7 @@ hperm_status ensure_buf(Dev *c, BufId id, size_t bytes) {
         b.cap = 0;
     }
     if (id == B_DESC || id == B_DATA) c->resident_jobs = 0;
+    if (id == B_LIST) c->resident_list = 0;
     hipError_t e = hipMalloc(&b.ptr, bytes);
     if (e != hipSuccess) {
         b.ptr = nullptr;
@@ -150,20 +152,25 @@ hperm_status estimate_jobs(Dev *c, hperm_jobs *j, int trials, uint64_t seed) {
         s = upload_jobs(c, j);
         if (s) return s;
     }
-    // jobs grouped by order bucket (one counting pass), natural order inside a bucket
-    std::vector<uint32_t> &list = c->h_queue;
-    list.resize(nd);
-    size_t off[HP_EST_BUCKETS + 1] = {};
-    for (size_t k = 0; k < nd; ++k) off[est_bucket_of(j->tab.desc[k].m) + 1]++;
-    for (int b = 0; b < HP_EST_BUCKETS; ++b) off[b + 1] += off[b];
-    {
-        size_t pos[HP_EST_BUCKETS];
-        for (int b = 0; b < HP_EST_BUCKETS; ++b) pos[b] = off[b];
-        for (size_t k = 0; k < nd; ++k) list[pos[est_bucket_of(j->tab.desc[k].m)]++] = (uint32_t)k;
+    // jobs grouped by order bucket (one counting pass, once per job table), natural order
+    // inside a bucket; uploaded when not already in place
+    if (j->elist.size() != nd) {
+        std::vector<size_t> &off = j->eoff;
+        off.assign(HP_EST_BUCKETS + 1, 0);
+        for (size_t k = 0; k < nd; ++k) off[est_bucket_of(j->tab.desc[k].m) + 1]++;
+        for (int b = 0; b < HP_EST_BUCKETS; ++b) off[b + 1] += off[b];
+        std::vector<size_t> pos(off.begin(), off.end() - 1);
+        j->elist.resize(nd);
+        for (size_t k = 0; k < nd; ++k) j->elist[pos[est_bucket_of(j->tab.desc[k].m)]++] = (uint32_t)k;
     }
-    s = hip_check(c, hipMemcpyAsync(c->buf[B_LIST].ptr, list.data(), list.size() * 4,
-                                    hipMemcpyHostToDevice, c->stream), "upload estimate list");
-    if (s) return s;
+    const std::vector<size_t> &off = j->eoff;
+    if (c->resident_list != j->id || c->resident_list_ptr != c->buf[B_LIST].ptr || j->id == 0) {
+        s = hip_check(c, hipMemcpyAsync(c->buf[B_LIST].ptr, j->elist.data(), nd * 4, hipMemcpyHostToDevice,
+                                        c->stream), "upload estimate list");
+        if (s) return s;
+        c->resident_list = j->id;
+        c->resident_list_ptr = c->buf[B_LIST].ptr;
+    }
     for (int b = 0; b < HP_EST_BUCKETS; ++b) {
         const uint32_t n = (uint32_t)(off[b + 1] - off[b]);
         if (!n) continue;
@@ -739,6 +746,7 @@ void dev_release(Dev *d) {
     d->host_prob = nullptr;
     d->host_prob_cap = 0;
     d->resident_jobs = 0;
+    d->resident_list = 0;
 }
 
 }  // namespace hp
@@ -873,6 +881,7 @@ hperm_status hperm_ctx_set_arena(hperm_ctx *c, void *dev_ptr, size_t bytes) {
     c->dev.arena = dev_ptr;
     c->dev.arena_bytes = dev_ptr ? bytes : 0;
     c->dev.resident_jobs = 0;
+    c->dev.resident_list = 0;
     return HPERM_OK;
 }
 

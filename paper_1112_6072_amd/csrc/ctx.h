@@ -41,6 +41,10 @@ struct hperm_jobs {
         uint64_t items, terms;
         double mults, adds, updates;
     };
+    // the estimator's job list (jobs grouped by its order buckets, natural order inside) and
+    // the bucket offsets, also filled once
+    std::vector<uint32_t> elist;
+    std::vector<size_t> eoff;
     std::vector<uint8_t> qgroup;
     std::vector<uint64_t> qitems;
     std::vector<QueueGroup> qgroups;
@@ -61,6 +65,8 @@ struct Dev {
     size_t arena_bytes = 0;
     size_t arena_required = 0;
     uint64_t resident_jobs = 0;        // id of the job table currently in B_DESC/B_DATA
+    uint64_t resident_list = 0;        // id of the job table whose estimator list is in B_LIST
+    void *resident_list_ptr = nullptr; // ... and where it was uploaded
     std::string last_error;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<hperm_launch_stat> launches;   // R-NW launches of the last run
