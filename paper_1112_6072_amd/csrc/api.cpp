@@ -401,7 +401,7 @@ static void build_queue_groups(hperm_jobs *j) {
     const size_t nd = dsc.size();
     constexpr int NV = 3;
     constexpr int NG = HP_RNW_BUCKETS * HP_NRING * NV;
-    constexpr uint64_t kSmallGroupItems = 65536;
+    constexpr uint64_t kSmallGroupItems = 16384;
     std::vector<uint8_t> raw(nd);
     j->qitems.resize(nd);
     uint64_t items_raw[NG] = {0};
