@@ -84,6 +84,12 @@ typedef struct hperm_opts {
     int32_t time_jobs;    /* 1: persistent runs of hperm_run_jobs record each job's work time
                              (hperm_jobs_cycles; the scheduling study of the paper's load
                              balancing section); 0: off (default). Ignored while serving. */
+    int32_t split_order;  /* 0: off (default). t in [7, 19]: persistent runs continue Algorithm
+                             H_per (Section 2.1) on the device for every mod-2^64 job of order
+                             t+1..20, splitting it by expansion (2) down to order t, and evaluate
+                             the leaves by R-NW inside the same kernel (one wave per job); other
+                             jobs take the R-NW queue. Results are unchanged (the expansion is an
+                             identity); needs s_leaf <= 5. Ignored by one-launch-per-job runs. */
 } hperm_opts;
 
 /* Result of one permanent. The value is non-negative: magnitude limbs, little-endian. */
@@ -210,6 +216,12 @@ hperm_status hperm_jobs_info(const hperm_jobs *jobs, int32_t *n_jobs, int32_t *n
 hperm_status hperm_jobs_describe(const hperm_jobs *jobs, int32_t *m, int32_t *problem,
                                  int32_t *arith, uint64_t *terms);
 
+/* The sub-matrix of job `job` as the kernels hold it, row-major m x m into a[m*m] (m from
+ * hperm_jobs_describe): rows in the job's order, Gray columns 0..m-2, then the fixed column.
+ * It is a row and column permutation of the expansion's sub-matrix or of its transpose (the
+ * same permanent). Host only. */
+hperm_status hperm_jobs_matrix(const hperm_jobs *jobs, int32_t job, uint32_t *a);
+
 /* KKLLL estimates of every job's pattern (step 3): trials per job and seed as given.
  * keys[n_jobs] (may be NULL) receives log of the mean of the trials (natural log;
  * -INFINITY when every trial was singular). The keys are kept for ORDER_ESTIMATE. */
@@ -318,6 +330,12 @@ typedef struct hperm_launch_stat {
                                ring addition add = 2, 4 or 3 * 3 slots; v_mad_u64_u32 and
                                v_mul_lo_u32 count 2 slots (half rate), other ops 1 */
     double ms;              /* duration from HIP events around the launch on its stream */
+    /* device H_per launches (variant 3) only; items = jobs, terms = sum of 2^(m-1) over them: */
+    uint64_t leaves;        /* leaves evaluated by R-NW */
+    uint64_t leaf_terms;    /* subset-terms of those leaves: sum of 2^(p-1), p the leaf order */
+    uint64_t splits;        /* nodes split by expansion (2) */
+    uint64_t split_stops;   /* nodes evaluated whole because a child would break the entry
+                               (2^22) or row-sum (2^24) bound */
 } hperm_launch_stat;
 
 /* Copy up to max launch records of the last call into out; *n receives the count. */

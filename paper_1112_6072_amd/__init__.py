@@ -43,7 +43,8 @@ class Opts(ctypes.Structure):
                 ("arith", ctypes.c_int32), ("order", ctypes.c_int32), ("trials", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("chunk_log2", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("host_threads", ctypes.c_int32),
-                ("max_table_mib", ctypes.c_int32), ("time_jobs", ctypes.c_int32)]
+                ("max_table_mib", ctypes.c_int32), ("time_jobs", ctypes.c_int32),
+                ("split_order", ctypes.c_int32)]
 
 
 class Coeff(ctypes.Structure):
@@ -76,7 +77,9 @@ class LaunchStat(ctypes.Structure):
     _fields_ = [("ring", ctypes.c_int32), ("bucket", ctypes.c_int32), ("n_jobs", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("items", ctypes.c_uint64), ("terms", ctypes.c_uint64),
-                ("row_updates", ctypes.c_uint64), ("alg_slots", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("row_updates", ctypes.c_uint64), ("alg_slots", ctypes.c_double), ("ms", ctypes.c_double),
+                ("leaves", ctypes.c_uint64), ("leaf_terms", ctypes.c_uint64), ("splits", ctypes.c_uint64),
+                ("split_stops", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -109,6 +112,7 @@ _SIGS = {
     "hperm_cancel": [_P, _U64],
     "hperm_last_launches": [_P, ctypes.POINTER(LaunchStat), _I32, ctypes.POINTER(_I32)],
     "hperm_jobs_cycles": [_P, _P],
+    "hperm_jobs_matrix": [_P, _I32, _P],
     "hperm_permanental_polynomial": [_P, _I32, _P, _P, _P, _P],
     "hperm_polynomial_interpolate": [_I32, _P, _I32, _P],
     "hperm_list_schedule": [_I32, _P, _P, _I32, ctypes.POINTER(_U64), _P],
@@ -212,6 +216,17 @@ class Jobs:
         terms = np.zeros(max(nj, 1), np.uint64)
         _lib.hperm_jobs_describe(self.handle, _ptr(m), _ptr(prob), _ptr(ar), _ptr(terms))
         return {"m": m[:nj], "problem": prob[:nj], "arith": ar[:nj], "terms": terms[:nj]}
+
+    def matrix(self, k: int) -> np.ndarray:
+        """Job k's sub-matrix as the kernels hold it (rows in job order, Gray columns, then the
+        fixed column)."""
+        d = self.describe()["m"]
+        m = int(d[k]) if 0 <= k < len(d) else 0
+        out = np.zeros(max(m * m, 1), np.uint32)
+        st = _lib.hperm_jobs_matrix(self.handle, int(k), _ptr(out))
+        if st != OK:
+            raise HpermError(st, "job index out of range")
+        return out[:m * m].reshape(m, m)
 
     def cycles(self) -> np.ndarray:
         """Per-job work cycles of the last timed persistent run (opts time_jobs=1)."""

@@ -395,52 +395,68 @@ static hperm_status ensure_launch_events(Dev *c, size_t pairs) {
 // g = (order bucket, ring, walk variant) from the largest bucket and the widest ring down. The
 // order-20 bucket exists for the many jobs of the default cut-off; when a (ring, walk) group of
 // it is small, its jobs join the order-24 group instead (whose kernel takes them too), saving
-// a launch and its drain tail.
-static void build_queue_groups(hperm_jobs *j) {
+// a launch and its drain tail. With split_order t > 0 the mod-2^64 jobs of order t+1..20 form
+// one more group, last, for the device continuation of H_per (variant 3, one item per job).
+static constexpr int kSplitVariant = 3;
+static bool split_eligible(const JobDesc &d, int split) {
+    return split > 0 && d.arith == HP_W64 && d.m > split && d.m <= HP_SPLIT_MAX_M;
+}
+static void build_queue_groups(hperm_jobs *j, int split) {
     const std::vector<JobDesc> &dsc = j->tab.desc;
     const size_t nd = dsc.size();
     constexpr int NV = 3;
     constexpr int NG = HP_RNW_BUCKETS * HP_NRING * NV;
+    constexpr int SPLIT_G = NG;   // the device H_per group
     constexpr uint64_t kSmallGroupItems = 16384;
     std::vector<uint8_t> raw(nd);
     j->qitems.resize(nd);
-    uint64_t items_raw[NG] = {0};
+    uint64_t items_raw[NG + 1] = {0};
     for (size_t k = 0; k < nd; ++k) {
         const JobDesc &d = dsc[k];
-        const int g = ((HP_RNW_BUCKETS - 1 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith)) * NV +
-                      walk_variant(d, d.chunk_log2);
+        int g;
+        if (split_eligible(d, split)) {
+            g = SPLIT_G;
+            j->qitems[k] = 1;
+        } else {
+            g = ((HP_RNW_BUCKETS - 1 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith)) * NV +
+                walk_variant(d, d.chunk_log2);
+            j->qitems[k] = items_of(d.m, d.chunk_log2);
+        }
         raw[k] = (uint8_t)g;
-        j->qitems[k] = items_of(d.m, d.chunk_log2);
         items_raw[g] += j->qitems[k];
     }
-    int remap[NG];
+    int remap[NG + 1];
     for (int g = 0; g < NG; ++g) {
         const int bucket = HP_RNW_BUCKETS - 1 - g / (NV * HP_NRING);
         remap[g] = (bucket == 1 && items_raw[g] < kSmallGroupItems) ? g - NV * HP_NRING : g;
     }
-    hperm_jobs::QueueGroup acc[NG];
+    remap[SPLIT_G] = SPLIT_G;
+    hperm_jobs::QueueGroup acc[NG + 1];
     for (int g = 0; g < NG; ++g)
         acc[g] = hperm_jobs::QueueGroup{HP_NRING - 1 - (g / NV) % HP_NRING, HP_RNW_BUCKETS - 1 - g / (NV * HP_NRING),
                                         g % NV, 0, 0, 0, 0.0, 0.0, 0.0};
+    acc[SPLIT_G] = hperm_jobs::QueueGroup{HP_W64, bucket_of(HP_SPLIT_MAX_M), kSplitVariant, 0, 0, 0, 0.0, 0.0, 0.0};
     for (size_t k = 0; k < nd; ++k) {
         const JobDesc &d = dsc[k];
         hperm_jobs::QueueGroup &q = acc[remap[raw[k]]];
-        const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2, walk_variant(d, d.chunk_log2));
         q.n++;
         q.items += j->qitems[k];
         q.terms += 1ull << (d.m - 1);
+        if (raw[k] == SPLIT_G) continue;   // its work is known only after the run
+        const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2, walk_variant(d, d.chunk_log2));
         q.mults += wk.mults;
         q.adds += wk.adds;
         q.updates += wk.updates;
     }
-    int index[NG];
+    int index[NG + 1];
     j->qgroups.clear();
-    for (int g = 0; g < NG; ++g) {
+    for (int g = 0; g <= NG; ++g) {
         index[g] = (int)j->qgroups.size();
         if (acc[g].n) j->qgroups.push_back(acc[g]);
     }
     j->qgroup.resize(nd);
     for (size_t k = 0; k < nd; ++k) j->qgroup[k] = (uint8_t)index[remap[raw[k]]];
+    j->qsplit = split;
 }
 
 hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool want_per_job) {
@@ -472,7 +488,7 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     std::vector<uint64_t> &item_end = c->h_items;
     std::vector<size_t> goff;
     if (persistent) {
-        if (j->qgroup.size() != nd) build_queue_groups(j);
+        if (j->qgroup.size() != nd || j->qsplit != c->opts.split_order) build_queue_groups(j, c->opts.split_order);
         const std::vector<uint32_t> ord = job_order(j, order, c->opts.seed);
         const size_t ng = j->qgroups.size();
         goff.assign(ng + 1, 0);
@@ -505,6 +521,11 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         if (s) return s;
     }
     c->timed = persistent && c->opts.time_jobs != 0;
+    c->split_launch = -1;
+    if (persistent && c->opts.split_order) {
+        s = ensure_buf(c, B_SPLIT, 4 * sizeof(unsigned long long));
+        if (s) return s;
+    }
     if (c->timed) {
         s = ensure_buf(c, B_CYCLES, nd * sizeof(unsigned long long));
         if (s) return s;
@@ -562,14 +583,27 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             st.row_updates = (uint64_t)g.updates;
             st.alg_slots = g.mults * ring_mul_slots(g.ring) + g.adds * ring_add_slots(g.ring) + g.updates;
             c->launches.push_back(st);
+            if (g.variant == kSplitVariant) {
+                c->split_launch = (int)gi;
+                s = hip_check(c, launch_fill_u64((unsigned long long *)c->buf[B_SPLIT].ptr, 4, 0ull, c->stream),
+                              "clear split counters");
+                if (s) return s;
+            }
             s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
             if (s) return s;
-            s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,
-                                                   (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi],
-                                                   (const uint64_t *)c->buf[B_ITEMS].ptr + goff[gi],
-                                                   (uint32_t)g.n, g.items, head + gi, accs, cyc, 0,
-                                                   c->stream),
-                          "rnw_persistent launch");
+            if (g.variant == kSplitVariant)
+                s = hip_check(c, launch_split_w64(d_desc, d_data, (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi],
+                                                  (uint32_t)g.n, c->opts.split_order, c->opts.s_leaf, head + gi,
+                                                  accs, (unsigned long long *)c->buf[B_SPLIT].ptr, cyc,
+                                                  c->stream),
+                              "device H_per launch");
+            else
+                s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,
+                                                       (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi],
+                                                       (const uint64_t *)c->buf[B_ITEMS].ptr + goff[gi],
+                                                       (uint32_t)g.n, g.items, head + gi, accs, cyc, 0,
+                                                       c->stream),
+                              "rnw_persistent launch");
             if (s) return s;
             s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi + 1], c->stream), "event");
             if (s) return s;
@@ -601,6 +635,11 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     }
     s = hip_check(c, hipEventRecord(c->ev1, c->stream), "event");
     if (s) return s;
+    if (c->split_launch >= 0) {
+        s = hip_check(c, hipMemcpyAsync(c->split_stats, c->buf[B_SPLIT].ptr, sizeof(c->split_stats),
+                                        hipMemcpyDeviceToHost, c->stream), "download split counters");
+        if (s) return s;
+    }
     if (want_per_job) {
         c->host_acc.resize(nd);
         return hip_check(c, hipMemcpyAsync(c->host_acc.data(), accs, nd * sizeof(JobAcc),
@@ -646,6 +685,13 @@ hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_resu
                 float lm = 0.0f;
                 (void)hipEventElapsedTime(&lm, c->launch_ev[2 * gi], c->launch_ev[2 * gi + 1]);
                 c->launches[gi].ms = lm;
+            }
+            if (c->split_launch >= 0) {
+                hperm_launch_stat &st = c->launches[(size_t)c->split_launch];
+                st.leaves = c->split_stats[0];
+                st.leaf_terms = c->split_stats[1];
+                st.splits = c->split_stats[2];
+                st.split_stops = c->split_stats[3];
             }
         } else if (!c->launches.empty()) {
             c->launches[0].ms = ms;
@@ -788,6 +834,9 @@ static const char *check_opts(const hperm_opts *o) {
     if (o->host_threads < 0 || o->host_threads > 64) return "host_threads must be in [0, 64]";
     if (o->max_table_mib < 0) return "max_table_mib must be >= 0";
     if (o->time_jobs != 0 && o->time_jobs != 1) return "time_jobs must be 0 or 1";
+    if (o->split_order != 0 && (o->split_order < HP_SPLIT_MIN_T || o->split_order >= HP_SPLIT_MAX_M))
+        return "split_order must be 0 or in [7, 19]";
+    if (o->split_order != 0 && o->s_leaf > 5) return "split_order needs s_leaf <= 5";
     return nullptr;
 }
 
@@ -1043,6 +1092,25 @@ hperm_status hperm_jobs_describe(const hperm_jobs *j, int32_t *m, int32_t *probl
         if (problem) problem[k] = (int32_t)d.problem;
         if (arith) arith[k] = d.arith + 1;
         if (terms) terms[k] = 1ull << (d.m - 1);
+    }
+    return HPERM_OK;
+}
+
+hperm_status hperm_jobs_matrix(const hperm_jobs *j, int32_t job, uint32_t *a) {
+    if (!j || !a || job < 0 || (size_t)job >= j->tab.desc.size()) return HPERM_E_INVALID;
+    const JobDesc &d = j->tab.desc[(size_t)job];
+    const int m = d.m;
+    const uint32_t *blk = j->tab.data.data() + hp_data_index(d);
+    std::fill(a, a + (size_t)m * m, 0u);
+    for (int g = 0; g + 1 < m; ++g)   // Gray column g: entries (2 b_ig << 8) | i
+        for (uint32_t e = blk[m + g]; e < blk[m + g + 1]; ++e) {
+            const uint32_t w = blk[3 * m + e];
+            a[(size_t)(w & 0xffu) * m + g] = w >> 9;
+        }
+    for (int i = 0; i < m; ++i) {     // fixed column: b_i = base_i + sum of the Gray entries
+        int64_t v = (int32_t)blk[i];
+        for (int g = 0; g + 1 < m; ++g) v += a[(size_t)i * m + g];
+        a[(size_t)i * m + m - 1] = (uint32_t)v;
     }
     return HPERM_OK;
 }

@@ -21,7 +21,7 @@ struct DevBuf {
     bool owned = false;
 };
 
-enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_PROB, B_CYCLES, B_COUNT };
+enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_PROB, B_CYCLES, B_SPLIT, B_COUNT };
 
 struct Serving;   // serve.cpp
 
@@ -48,6 +48,7 @@ struct hperm_jobs {
     std::vector<uint8_t> qgroup;
     std::vector<uint64_t> qitems;
     std::vector<QueueGroup> qgroups;
+    int qsplit = -1;   // split_order the launch groups were built for
     // per-job work cycles of the last timed persistent run (natural index)
     std::vector<uint64_t> cycles;
     bool has_cycles = false;
@@ -75,6 +76,8 @@ struct Dev {
     bool want_per_job = false;
     bool persistent = true;
     bool timed = false;                        // per-job work cycles recorded (B_CYCLES)
+    int split_launch = -1;                     // index of the device H_per launch, or -1
+    unsigned long long split_stats[4] = {0, 0, 0, 0};   // its counters (B_SPLIT)
     std::vector<JobAcc> host_acc;              // per-job accumulators (per-job results only)
     ProbAcc *host_prob = nullptr;              // pinned, per-problem accumulators
     size_t host_prob_cap = 0;

@@ -67,4 +67,17 @@ HP_RING_DECL(res)
 // Resident grid (blocks) of the persistent kernel variant.
 hipError_t persistent_grid(int ring, int bucket, int variant, int *grid);
 
+// Device continuation of H_per (split.hip): mod-2^64 jobs of order HP_SPLIT_MIN_T + 1 ..
+// HP_SPLIT_MAX_M are split on the device down to order t (HP_SPLIT_MIN_T <= t < HP_SPLIT_MAX_M)
+// and their leaves evaluated; each job's value lands in accs[job].l[0] as for the R-NW
+// kernels. queue[0..n) lists the jobs; head is a cleared counter; stats[0..4) (cleared by the
+// caller) receive leaves, leaf subset-terms, splits and splits refused by the entry bounds;
+// cycles (nullable) receives each job's shader-clock cycles.
+constexpr int HP_SPLIT_MAX_M = 20;
+constexpr int HP_SPLIT_MIN_T = 7;
+size_t split_lds_bytes(int t);
+hipError_t launch_split_w64(const JobDesc *jobs, const uint32_t *data, const uint32_t *queue, uint32_t n,
+                            int t, int s_leaf, unsigned long long *head, JobAcc *accs,
+                            unsigned long long *stats, unsigned long long *cycles, hipStream_t s);
+
 }  // namespace hp

@@ -1,0 +1,158 @@
+"""GPU parity of the device continuation of Algorithm H_per (split_order): each job is split
+on the device by expansion (2) down to the target order and its leaves evaluated by R-NW in
+the same kernel. Per-job values are compared bit-exact with the oracle's permanent of the job's
+sub-matrix; the traversal (number of leaves and their subset-terms) with the oracle's own
+H_per expansion of the same sub-matrix (``expand_leaves``, the same splitting rule)."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import expand_leaves, native
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                     "oracle_values.json")))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def job_mats(J):
+    return [J.matrix(k).astype(np.int64).tolist() for k in range(J.info()[0])]
+
+
+def oracle_traversal(mats, t):
+    """(leaves, leaf subset-terms) of the oracle's H_per expansion of the jobs of order > t."""
+    leaves = terms = 0
+    for B in mats:
+        if len(B) <= t:
+            continue
+        for leaf in expand_leaves(B, t, 5, 40):
+            leaves += 1
+            terms += 1 << (len(leaf) - 1)
+    return leaves, terms
+
+
+def split_launch(ctx):
+    ls = [l for l in ctx.last_launches() if l["variant"] == 3]
+    assert len(ls) == 1
+    return ls[0]
+
+
+@pytest.fixture(scope="module")
+def ctx(hperm):
+    c = hperm.Context()
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("t", [7, 10, 12])
+def test_split_jobs_match_oracle(hperm, ctx, t):
+    """Cubic graphs on 26 vertices expanded to jobs of order <= 16 on the host, continued on the
+    device to order t: every job's value and the totals equal the oracle's, and the device
+    reaches exactly the oracle's leaves."""
+    for seed in range(3):
+        A = W.random_cubic_matrix(26, seed)
+        say("split parity", t, "seed", seed)
+        ctx.set_opts(m_cut=16, split_order=t)
+        try:
+            J = ctx.expand([A])
+            totals, per_job, _ = ctx.run(J, "natural", True, per_job=True)
+            st = split_launch(ctx)
+        finally:
+            ctx.set_opts(m_cut=20, split_order=0)
+        mats = job_mats(J)
+        assert per_job == native.ryser_batch(mats, threads=8)
+        assert totals == [sum(per_job)]
+        assert st["n_jobs"] == sum(1 for B in mats if len(B) > t)
+        assert st["split_stops"] == 0
+        assert (st["leaves"], st["leaf_terms"]) == oracle_traversal(mats, t)
+
+
+def test_split_n24_golden(hperm, ctx):
+    """Ten cubic graphs on 24 vertices end to end with the default cut-off and split order 12."""
+    mats = W.config_n24()
+    say("split n24 golden")
+    ctx.set_opts(split_order=12)
+    try:
+        got = ctx.permanent_batch(mats)
+    finally:
+        ctx.set_opts(split_order=0)
+    assert got == [int(GOLDEN[f"cubic24_seed{s}"]) for s in range(10)]
+
+
+def test_split_mixed_table(hperm, ctx):
+    """A job table mixing jobs the device splits (mod 2^64, order 13..20), jobs too small to
+    split, dense jobs that are leaves at their own order (every line >= 5 nonzeros: the 16- and
+    20-row leaf walks) and jobs of wider rings: all values equal the oracle's."""
+    mats = []
+    for i, m in enumerate((5, 8, 12, 13, 15, 17, 19, 20)):
+        mats.append(W.permutation_union_matrix(m, 3, 700 + i, 1, 3))
+    for m in (13, 14):                            # all-ones: leaves at their own order
+        mats.append(np.ones((m, m), np.uint32))
+    for i, m in enumerate((16, 17, 18)):          # eight permutations: most lines >= 5 nonzeros
+        mats.append(W.permutation_union_matrix(m, 8, 800 + i, 1, 1))
+    mats.append(W.permutation_union_matrix(14, 3, 900, 20, 60))       # entries force a wider ring
+    J = ctx.jobs_from_dense(mats)
+    d = J.describe()
+    say("split mixed", list(d["m"]), list(d["arith"]))
+    ctx.set_opts(split_order=12)
+    try:
+        totals, per_job, _ = ctx.run(J, "natural", True, per_job=True)
+        st = split_launch(ctx)
+    finally:
+        ctx.set_opts(split_order=0)
+    stored = job_mats(J)
+    assert per_job == native.ryser_batch(stored, threads=8)
+    eligible = [B for B, a in zip(stored, d["arith"]) if a == 1 and 12 < len(B) <= 20]
+    assert st["n_jobs"] == len(eligible)
+    assert (st["leaves"], st["leaf_terms"]) == oracle_traversal(eligible, 12)
+    assert max(len(x) for B in eligible for x in expand_leaves(B, 12, 5, 40)) > 16   # wide leaves ran
+    assert max(d["arith"]) > 1
+
+
+@pytest.mark.parametrize("order", ["natural", "estimate", "random", "exact_cost"])
+def test_split_n60_bench_workload(hperm, ctx, order):
+    """The benchmark workload (17 cubic graphs on 60 vertices, 324386 jobs of order 20)
+    continued to order 12: totals equal the oracle's, and sampled jobs equal the oracle's
+    permanent of their sub-matrices."""
+    items = W.config_n60(16)
+    say("split n60", order)
+    J = ctx.expand([A for _, A in items])
+    if order == "estimate":
+        ctx.estimate(J, 32, 1)
+    ctx.set_opts(split_order=12)
+    try:
+        totals, per_job, _ = ctx.run(J, order, True, per_job=(order == "natural"))
+        st = split_launch(ctx)
+    finally:
+        ctx.set_opts(split_order=0)
+    assert totals == [int(GOLDEN[name]) for name, _ in items]
+    say("split n60 leaves", st["leaves"], "leaf terms", st["leaf_terms"], "ms", st["ms"],
+        "stops", st["split_stops"])
+    if per_job is not None:
+        rng = np.random.default_rng(3)
+        pick = sorted(rng.choice(len(per_job), 24, replace=False).tolist())
+        mats = [J.matrix(k).astype(np.int64).tolist() for k in pick]
+        assert [per_job[k] for k in pick] == native.ryser_batch(mats, threads=8)
+
+
+def test_split_job_timing(hperm):
+    """time_jobs = 1 with split_order: every split job gets positive work cycles; values
+    unchanged."""
+    c = hperm.Context({"time_jobs": 1, "split_order": 10})
+    try:
+        mats = [W.permutation_union_matrix(m, 3, 600 + m, 1, 2) for m in (14, 18, 20)]
+        J = c.jobs_from_dense(mats)
+        _, per_job, _ = c.run(J, "natural", True, per_job=True)
+        assert per_job == native.ryser_batch(job_mats(J), threads=8)
+        assert (J.cycles() > 0).all()
+    finally:
+        c.close()
