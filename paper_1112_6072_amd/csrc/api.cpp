@@ -523,7 +523,10 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     c->timed = persistent && c->opts.time_jobs != 0;
     c->split_launch = -1;
     if (persistent && c->opts.split_order) {
-        s = ensure_buf(c, B_SPLIT, 4 * sizeof(unsigned long long));
+        s = ensure_buf(c, B_SPLIT, 8 * sizeof(unsigned long long));
+        if (s) return s;
+        const hperm_jobs::QueueGroup &last = j->qgroups.back();
+        s = ensure_buf(c, B_SPLIT_WIDE, split_wide_bytes(last.variant == kSplitVariant ? (uint32_t)last.n : 1));
         if (s) return s;
     }
     if (c->timed) {
@@ -585,7 +588,7 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             c->launches.push_back(st);
             if (g.variant == kSplitVariant) {
                 c->split_launch = (int)gi;
-                s = hip_check(c, launch_fill_u64((unsigned long long *)c->buf[B_SPLIT].ptr, 4, 0ull, c->stream),
+                s = hip_check(c, launch_fill_u64((unsigned long long *)c->buf[B_SPLIT].ptr, 8, 0ull, c->stream),
                               "clear split counters");
                 if (s) return s;
             }
@@ -593,9 +596,9 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             if (s) return s;
             if (g.variant == kSplitVariant)
                 s = hip_check(c, launch_split_w64(d_desc, d_data, (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi],
-                                                  (uint32_t)g.n, c->opts.split_order, c->opts.s_leaf, head + gi,
-                                                  accs, (unsigned long long *)c->buf[B_SPLIT].ptr, cyc,
-                                                  c->stream),
+                                                  (uint32_t)g.n, (uint32_t)nd, c->opts.split_order, c->opts.s_leaf,
+                                                  head + gi, accs, (unsigned long long *)c->buf[B_SPLIT].ptr,
+                                                  c->buf[B_SPLIT_WIDE].ptr, cyc, c->stream),
                               "device H_per launch");
             else
                 s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,

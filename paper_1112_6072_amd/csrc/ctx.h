@@ -21,7 +21,7 @@ struct DevBuf {
     bool owned = false;
 };
 
-enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_PROB, B_CYCLES, B_SPLIT, B_COUNT };
+enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_PROB, B_CYCLES, B_SPLIT, B_SPLIT_WIDE, B_COUNT };
 
 struct Serving;   // serve.cpp
 
@@ -77,7 +77,7 @@ struct Dev {
     bool persistent = true;
     bool timed = false;                        // per-job work cycles recorded (B_CYCLES)
     int split_launch = -1;                     // index of the device H_per launch, or -1
-    unsigned long long split_stats[4] = {0, 0, 0, 0};   // its counters (B_SPLIT)
+    unsigned long long split_stats[5] = {0, 0, 0, 0, 0};   // its counters (B_SPLIT)
     std::vector<JobAcc> host_acc;              // per-job accumulators (per-job results only)
     ProbAcc *host_prob = nullptr;              // pinned, per-problem accumulators
     size_t host_prob_cap = 0;

@@ -70,14 +70,18 @@ hipError_t persistent_grid(int ring, int bucket, int variant, int *grid);
 // Device continuation of H_per (split.hip): mod-2^64 jobs of order HP_SPLIT_MIN_T + 1 ..
 // HP_SPLIT_MAX_M are split on the device down to order t (HP_SPLIT_MIN_T <= t < HP_SPLIT_MAX_M)
 // and their leaves evaluated; each job's value lands in accs[job].l[0] as for the R-NW
-// kernels. queue[0..n) lists the jobs; head is a cleared counter; stats[0..4) (cleared by the
-// caller) receive leaves, leaf subset-terms, splits and splits refused by the entry bounds;
-// cycles (nullable) receives each job's shader-clock cycles.
+// kernels. queue[0..n) lists the jobs (indices < njobs); head is a cleared counter;
+// stats[0..5) (cleared by the caller) receive leaves, leaf subset-terms, splits, splits refused
+// by the entry bounds and the wide leaves deferred to the second kernel; wide is a buffer of
+// split_wide_bytes(n) bytes; cycles (nullable) receives each job's shader-clock cycles (first
+// kernel only). Two launches on stream s.
 constexpr int HP_SPLIT_MAX_M = 20;
 constexpr int HP_SPLIT_MIN_T = 7;
 size_t split_lds_bytes(int t);
+size_t split_wide_bytes(uint32_t n);
 hipError_t launch_split_w64(const JobDesc *jobs, const uint32_t *data, const uint32_t *queue, uint32_t n,
-                            int t, int s_leaf, unsigned long long *head, JobAcc *accs,
-                            unsigned long long *stats, unsigned long long *cycles, hipStream_t s);
+                            uint32_t njobs, int t, int s_leaf, unsigned long long *head, JobAcc *accs,
+                            unsigned long long *stats, void *wide, unsigned long long *cycles,
+                            hipStream_t s);
 
 }  // namespace hp

@@ -11,8 +11,14 @@
 // an odd last nonzero paired at weight 0 with the lowest zero of the line. This is the rule of
 // the host expansion. The nodes on the current path all have different orders, so each order
 // has one LDS slot: the node of order o and its control state (line, pairs, next child) live
-// at slot o. A split whose children would hold an entry >= 2^22 or a row sum >= 2^24 is not
-// made: the node becomes a leaf (the bounds the host keeps for every job).
+// at slot o, with the nonzero bit masks of its rows and columns and its row sums, which the
+// child construction keeps up to date (so the line choice and the bound checks cost O(1) per
+// lane). A split whose children would hold an entry >= 2^22 or a row sum >= 2^24 is not made:
+// the node becomes a leaf (the bounds the host keeps for every job). Leaves above order 16
+// (rare: nodes whose lines all hold >= 5 nonzeros, or refused splits) are not evaluated by
+// this kernel: it records the job, the leaf's order and the path of child choices to it, and a
+// second kernel replays the path from the job's matrix and evaluates the leaf, which keeps
+// the wide row arrays out of the main kernel's registers.
 //
 // A leaf of order p is evaluated by the whole wave with the doubled Nijenhuis-Wilf form of
 // Ryser's formula (fixed column p - 1, Gray columns 0..p-2):
@@ -38,6 +44,8 @@ constexpr int SW = 64;                   // one wave per block
 constexpr int SMAX = HP_SPLIT_MAX_M;     // largest job order
 constexpr int DSTRIDE = 20;              // words per Gray column in a leaf's delta table
 constexpr int CTL = 12;                  // control words per order
+constexpr int META = 60;                 // per order: row masks, column masks, row sums (20 each)
+constexpr int PMAX = 16;                 // widest leaf the main kernel evaluates
 
 // LDS words of the node slots of orders o + 1 .. SMAX (the slot of order o starts there).
 __host__ __device__ constexpr int slot_off(int o) {
@@ -45,9 +53,9 @@ __host__ __device__ constexpr int slot_off(int o) {
 }
 __host__ __device__ constexpr int align4(int w) { return (w + 3) & ~3; }
 // Per-wave region for target order t: slots of orders t..SMAX, the leaf's delta table and
-// base values, and the control words.
+// base values, and per order t..SMAX the control words, masks and row sums.
 __host__ __device__ constexpr int region_words(int t) {
-    return align4(slot_off(t - 1)) + SMAX * DSTRIDE + SMAX + (SMAX + 1) * CTL;
+    return align4(slot_off(t - 1)) + SMAX * DSTRIDE + SMAX + (SMAX + 1 - t) * (CTL + META);
 }
 static_assert(align4(SMAX * DSTRIDE + SMAX) == SMAX * DSTRIDE + SMAX, "16-byte alignment of the tables");
 
@@ -104,29 +112,14 @@ __device__ __forceinline__ void add_rows(int32_t (&f)[R], const int32_t *d, bool
     }
 }
 
-// This lane's share of V for the leaf of order p (7 <= p <= R) stored row-major at M.
+// Row values of this lane's first Gray index (no Gray column below p - 7 is set in it).
 template <int R>
-__device__ uint64_t eval_leaf(const uint32_t *M, int p, int lane, int32_t *D, int32_t *base) {
-    // delta table D[j][i] = 2 b_ij (Gray column j, padded rows 0) and base_i = 2 b_i,p-1 - R_i
-    for (int e = lane; e < (p - 1) * DSTRIDE; e += SW) {
-        const int j = e / DSTRIDE, i = e - j * DSTRIDE;
-        D[e] = i < p ? 2 * (int32_t)M[i * p + j] : 0;
-    }
-    if (lane < R) {
-        int32_t b = 1;
-        if (lane < p) {
-            uint32_t rs = 0;
-            for (int j = 0; j < p; ++j) rs += M[lane * p + j];
-            b = 2 * (int32_t)M[lane * p + p - 1] - (int32_t)rs;
-        }
-        base[lane] = b;
-    }
-    wave_sync();
+__device__ __forceinline__ void start_rows(int32_t (&f)[R], int p, int lane, const int32_t *D,
+                                           const int32_t *base) {
     const int c = p - 7;
     const uint32_t L = 1u << c;
     const uint32_t kfirst = (lane & 1) ? (uint32_t)lane * L + L - 1 : (uint32_t)lane * L;
     const uint32_t s0 = kfirst ^ (kfirst >> 1);
-    int32_t f[R];
 #pragma unroll
     for (int i = 0; i < R; i += 4) {
         const int4 w = *(const int4 *)(base + i);
@@ -141,6 +134,14 @@ __device__ uint64_t eval_leaf(const uint32_t *M, int p, int lane, int32_t *D, in
 #pragma unroll
         for (int i = 0; i < R; ++i) f[i] += in ? dj[i] : 0;
     }
+}
+
+// This lane's share of V for a leaf of order p (7 <= p <= R): one term per step.
+template <int R>
+__device__ __forceinline__ uint64_t walk_plain(int p, int lane, const int32_t *D, const int32_t *base) {
+    const uint32_t L = 1u << (p - 7);
+    int32_t f[R];
+    start_rows<R>(f, p, lane, D, base);
     uint64_t acc0 = row_product<R>(f), acc1 = 0;
     for (uint32_t s = 1; s < L; s += 2) {
         add_rows<R>(f, D, ((s >> 1) & 1) == 0);   // odd steps flip Gray column 0
@@ -152,35 +153,297 @@ __device__ uint64_t eval_leaf(const uint32_t *M, int p, int lane, int32_t *D, in
             acc0 += row_product<R>(f);
         }
     }
-    wave_sync();   // D and base are rewritten by the next leaf
     return (lane & 1) ? acc1 - acc0 : acc0 - acc1;
 }
+
+// The same share with the steps taken in pairs (8 <= p <= R; Gray column 0 touches only rows
+// 0..BB-1). Steps s (even) and s + 1 differ only by Gray column 0, so their terms are A*P and
+// B*P with P the product of rows BB..R-1 and A, B the products of rows 0..BB-1 before and after
+// the flip: each pair costs one product of the other rows and one of the small block twice.
+template <int R, int BB>
+__device__ __forceinline__ uint64_t walk_paired(int p, int lane, const int32_t *D, const int32_t *base) {
+    const uint32_t L = 1u << (p - 7);
+    int32_t f[R];
+    start_rows<R>(f, p, lane, D, base);
+    int32_t d0[BB];
+#pragma unroll
+    for (int i = 0; i < BB; ++i) d0[i] = D[i];
+    uint64_t acc = 0;
+    for (uint32_t s = 0; s < L; s += 2) {
+        if (s) {   // step s flips Gray column ctz(s) >= 1
+            const int j = __builtin_ctz(s);
+            add_rows<R>(f, D + j * DSTRIDE, ((s >> (j + 1)) & 1) == 0);
+        }
+        const bool add0 = (((s + 1) >> 1) & 1) == 0;   // step s + 1 adds Gray column 0
+        int32_t g[BB];
+#pragma unroll
+        for (int i = 0; i < BB; ++i) g[i] = add0 ? f[i] + d0[i] : f[i] - d0[i];
+        uint64_t rest = (uint64_t)((int64_t)f[BB] * (int64_t)f[BB + 1]);
+#pragma unroll
+        for (int k = BB / 2 + 1; k < R / 2; ++k) rest *= (uint64_t)((int64_t)f[2 * k] * (int64_t)f[2 * k + 1]);
+        uint64_t a, b;
+        if constexpr (BB == 2) {
+            a = (uint64_t)((int64_t)f[0] * (int64_t)f[1]);
+            b = (uint64_t)((int64_t)g[0] * (int64_t)g[1]);
+        } else {
+            a = (uint64_t)((int64_t)f[0] * (int64_t)f[1]) * (uint64_t)((int64_t)f[2] * (int64_t)f[3]);
+            b = (uint64_t)((int64_t)g[0] * (int64_t)g[1]) * (uint64_t)((int64_t)g[2] * (int64_t)g[3]);
+        }
+        acc += (a - b) * rest;
+#pragma unroll
+        for (int i = 0; i < BB; ++i) f[i] = g[i];   // step s + 1 leaves Gray column 0 flipped
+    }
+    return (lane & 1) ? (uint64_t)0 - acc : acc;
+}
+
+
+// ------------------------------------------------------------------ per-wave LDS region
+struct Region {
+    uint32_t *lds;
+    int32_t *D, *base;
+    uint32_t *ctl_all, *meta_all;   // indexed by order - t
+    __device__ Region(uint32_t *l, int t) : lds(l) {
+        D = (int32_t *)(l + align4(slot_off(t - 1)));
+        base = D + SMAX * DSTRIDE;
+        ctl_all = (uint32_t *)(base + SMAX) - t * CTL;
+        meta_all = (uint32_t *)(base + SMAX) + (SMAX + 1 - t) * CTL - t * META;
+    }
+    __device__ uint32_t *slot(int o) const { return lds + slot_off(o); }
+    __device__ uint32_t *ctl(int o) const { return ctl_all + o * CTL; }
+    __device__ uint32_t *rmask(int o) const { return meta_all + o * META; }
+    __device__ uint32_t *cmask(int o) const { return meta_all + o * META + 20; }
+    __device__ uint32_t *rsum(int o) const { return meta_all + o * META + 40; }
+};
 
 struct SplitCtl {   // word offsets in a control block
     enum { IS_COL, IDX, NP, P0, Q0, CA0, CB0, P1, Q1, CA1, CB1, NEXT };
 };
 
-// Child `ch` of the node of order o at M (line and pairs in ctl) written at C (order o - 1).
-__device__ void make_child(const uint32_t *M, int o, const uint32_t *ctl, int ch, uint32_t *C, int lane) {
+// Job `job` as a dense m x m matrix in slot m (Gray columns 0..m-2, then the fixed column),
+// with its masks and row sums. Returns m.
+__device__ __forceinline__ int load_job(const Region &rg, const JobDesc *jobs, const uint32_t *data, uint32_t job, int lane) {
+    const JobDesc jd = jobs[job];
+    const int m = (int)uni(jd.m);
+    const uint32_t nnz = uni(jd.nnz);
+    const uint32_t *blk = data + (size_t)uni(jd.data_off) * HP_DATA_ALIGN;
+    uint32_t *M = rg.slot(m);
+    for (int e = lane; e < m * m; e += SW) M[e] = 0;
+    if (lane < 20) {
+        rg.rmask(m)[lane] = 0;
+        rg.cmask(m)[lane] = 0;
+        rg.rsum(m)[lane] = 0;
+    }
+    const uint32_t cs = lane < m ? blk[m + lane] : 0xffffffffu;   // column starts, end at m-1
+    wave_sync();
+    for (uint32_t e0 = 0; e0 < nnz; e0 += SW) {
+        const uint32_t e = e0 + (uint32_t)lane;
+        uint32_t g = 0;   // Gray column of entry e: the last start <= e among columns 1..m-2
+        for (int k = 1; k + 1 < m; ++k) g += (uint32_t)__shfl((int)cs, k) <= e;
+        if (e < nnz) {
+            const uint32_t w = blk[3 * m + e], i = w & 0xffu, b = w >> 9;
+            M[i * m + g] = b;
+            atomicOr(rg.rmask(m) + i, 1u << g);
+            atomicOr(rg.cmask(m) + g, 1u << i);
+            atomicAdd(rg.rsum(m) + i, b);
+        }
+    }
+    wave_sync();
+    uint32_t bf = 0;
+    if (lane < m) {   // fixed column: b_i = base_i + the row's Gray entries
+        bf = (uint32_t)((int32_t)blk[lane] + (int32_t)rg.rsum(m)[lane]);
+        M[lane * m + m - 1] = bf;
+        rg.rsum(m)[lane] += bf;
+        if (bf) rg.rmask(m)[lane] |= 1u << (m - 1);
+    }
+    const uint64_t fixed_rows = __ballot(lane < m && bf != 0);
+    if (lane == 0) rg.cmask(m)[m - 1] = (uint32_t)fixed_rows;
+    wave_sync();
+    return m;
+}
+
+// Step 1 of H_per at the node of order o: returns (count << 6) | (32 * is_col + index) of the
+// sparsest line (rows before columns, then the lowest index).
+__device__ __forceinline__ uint32_t sparsest_line(const Region &rg, int o, int lane) {
+    uint32_t key = 0xffffffffu;
+    if (lane < o) key = ((uint32_t)__popc(rg.rmask(o)[lane]) << 6) | (uint32_t)lane;
+    else if (lane >= 32 && lane < 32 + o) key = ((uint32_t)__popc(rg.cmask(o)[lane - 32]) << 6) | (uint32_t)lane;
+    return uni(wave_min(key));
+}
+
+// Pairs of expansion (2) along the line (nonzeros in increasing index order; an odd last one
+// with the lowest zero of the line at weight 0) into ctl, the child counter cleared. Returns
+// false when a child would break the entry or row-sum bound (ctl then unused).
+__device__ __forceinline__ bool plan_split(const Region &rg, int o, uint32_t key, int lane) {
+    const uint32_t s = key >> 6, is_col = (key >> 5) & 1, line = key & 31;
+    const uint32_t *M = rg.slot(o);
+    uint32_t nz = uni(is_col ? rg.cmask(o)[line] : rg.rmask(o)[line]);
+    const uint32_t zero = (uint32_t)__builtin_ctz(~nz & ((1u << o) - 1));
+    uint32_t pos[4], val[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        pos[k] = zero;
+        val[k] = 0;
+        if ((uint32_t)k < s) {
+            pos[k] = (uint32_t)__builtin_ctz(nz);
+            nz &= nz - 1;
+            val[k] = uni(is_col ? M[pos[k] * o + line] : M[line * o + pos[k]]);
+        }
+    }
+    const uint32_t np = (s + 1) / 2;
+    bool fail = false;
+    for (uint32_t ch = 0; ch < np; ++ch) {
+        const uint32_t P = pos[2 * ch], Q = pos[2 * ch + 1];
+        const uint64_t ca = val[2 * ch], cb = val[2 * ch + 1];
+        if (!is_col) {   // merged column; each other row loses P and Q and gains the merge
+            if (lane < o && (uint32_t)lane != line) {
+                const uint64_t mq = M[lane * o + Q], mp = M[lane * o + P];
+                const uint64_t mv = ca * mq + cb * mp;
+                fail = fail || mv >= HP_MAX_ENTRY || rg.rsum(o)[lane] - mq - mp + mv >= HP_MAX_ROWSUM;
+            }
+        } else {         // merged row; its sum is known from the rows P and Q
+            if (lane < o && (uint32_t)lane != line) {
+                const uint64_t mv = ca * M[Q * o + lane] + cb * M[P * o + lane];
+                fail = fail || mv >= HP_MAX_ENTRY;
+            }
+            const uint64_t rq = uni(rg.rsum(o)[Q]) - (uint64_t)uni(M[Q * o + line]);
+            const uint64_t rp = uni(rg.rsum(o)[P]) - (uint64_t)uni(M[P * o + line]);
+            fail = fail || ca * rq + cb * rp >= HP_MAX_ROWSUM;
+        }
+    }
+    if (__ballot(fail) != 0) return false;
+    uint32_t *ctl = rg.ctl(o);
+    if (lane == 0) {
+        ctl[SplitCtl::IS_COL] = is_col;
+        ctl[SplitCtl::IDX] = line;
+        ctl[SplitCtl::NP] = np;
+        ctl[SplitCtl::P0] = pos[0];
+        ctl[SplitCtl::Q0] = pos[1];
+        ctl[SplitCtl::CA0] = val[0];
+        ctl[SplitCtl::CB0] = val[1];
+        ctl[SplitCtl::P1] = pos[2];
+        ctl[SplitCtl::Q1] = pos[3];
+        ctl[SplitCtl::CA1] = val[2];
+        ctl[SplitCtl::CB1] = val[3];
+        ctl[SplitCtl::NEXT] = 0;
+    }
+    wave_sync();
+    return true;
+}
+
+// Child `ch` of the node of order o (plan in its ctl) into slot o - 1 with its masks and row
+// sums. Lanes cover three child rows per pass (lane = 21 * r + column).
+__device__ __forceinline__ void make_child(const Region &rg, int o, int ch, int lane) {
+    const uint32_t *ctl = rg.ctl(o);
+    const uint32_t *M = rg.slot(o);
+    uint32_t *C = rg.slot(o - 1);
     const uint32_t is_col = uni(ctl[SplitCtl::IS_COL]), line = uni(ctl[SplitCtl::IDX]);
     const uint32_t P = uni(ctl[SplitCtl::P0 + 4 * ch]), Q = uni(ctl[SplitCtl::Q0 + 4 * ch]);
     const uint32_t ca = uni(ctl[SplitCtl::CA0 + 4 * ch]), cb = uni(ctl[SplitCtl::CB0 + 4 * ch]);
     const uint32_t keep = min(P, Q), drop = max(P, Q);
-    const uint32_t co = (uint32_t)o - 1, inv = ((1u << 20) + co - 1) / co;
-    for (uint32_t e = lane; e < co * co; e += SW) {
-        const uint32_t ip = div_small(e, inv), jp = e - ip * co;
-        uint32_t v;
-        if (!is_col) {   // row `line` deleted, columns P, Q merged at min(P, Q)
-            const uint32_t i = ip + (ip >= line), j = jp + (jp >= drop);
-            v = j == keep ? ca * M[i * o + Q] + cb * M[i * o + P] : M[i * o + j];
-        } else {         // column `line` deleted, rows P, Q merged at min(P, Q)
-            const uint32_t i = ip + (ip >= drop), j = jp + (jp >= line);
-            v = i == keep ? ca * M[Q * o + j] + cb * M[P * o + j] : M[i * o + j];
+    const uint32_t co = (uint32_t)o - 1;
+    const uint32_t r3 = (uint32_t)lane / 21, jp = (uint32_t)lane - 21 * r3;
+    uint32_t cm = 0;
+    for (uint32_t ip0 = 0; ip0 < co; ip0 += 3) {
+        const uint32_t ip = ip0 + r3;
+        const bool ok = r3 < 3 && ip < co && jp < co;
+        uint32_t v = 0;
+        if (ok) {
+            if (!is_col) {   // row `line` deleted, columns P, Q merged at min(P, Q)
+                const uint32_t i = ip + (ip >= line), j = jp + (jp >= drop);
+                v = j == keep ? ca * M[i * o + Q] + cb * M[i * o + P] : M[i * o + j];
+            } else {         // column `line` deleted, rows P, Q merged at min(P, Q)
+                const uint32_t i = ip + (ip >= drop), j = jp + (jp >= line);
+                v = i == keep ? ca * M[Q * o + j] + cb * M[P * o + j] : M[i * o + j];
+            }
+            C[ip * co + jp] = v;
+            cm |= (uint32_t)(v != 0) << ip;
         }
-        C[e] = v;
+        const uint64_t bal = __ballot(v != 0);
+        if (ok && jp == 0) rg.rmask(o - 1)[ip] = (uint32_t)(bal >> (21 * r3)) & ((1u << 21) - 1);
+    }
+    cm |= (uint32_t)__shfl((int)cm, lane + 21) | (uint32_t)__shfl((int)cm, lane + 42);
+    if ((uint32_t)lane < co) rg.cmask(o - 1)[lane] = cm;
+    if ((uint32_t)lane < co) {   // row sums from the parent's
+        const uint32_t ip = (uint32_t)lane;
+        uint32_t rs;
+        if (!is_col) {
+            const uint32_t i = ip + (ip >= line);
+            const uint32_t mq = M[i * o + Q], mp = M[i * o + P];
+            rs = rg.rsum(o)[i] - mq - mp + ca * mq + cb * mp;
+        } else {
+            const uint32_t i = ip + (ip >= drop);
+            if (i == keep)
+                rs = ca * (rg.rsum(o)[Q] - M[Q * o + line]) + cb * (rg.rsum(o)[P] - M[P * o + line]);
+            else
+                rs = rg.rsum(o)[i] - M[i * o + line];
+        }
+        rg.rsum(o - 1)[ip] = rs;
     }
     wave_sync();
 }
+
+// Leaf tables in LDS: D[j][i] = 2 b_ij for Gray column j (rows beyond p: 0) and
+// base_i = 2 b_{i,p-1} - R_i (rows beyond p: 1, so f = 1), with the leaf's sparsest Gray
+// column moved to Gray column 0 and the rows it touches moved to the front (the product is
+// invariant under both permutations). Returns that column's nonzero count b.
+__device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, int lane) {
+    const uint32_t *M = rg.slot(p);
+    uint32_t key = 0xffffffffu;
+    if (lane < p - 1) key = ((uint32_t)__popc(rg.cmask(p)[lane]) << 6) | (uint32_t)lane;
+    key = uni(wave_min(key));
+    const uint32_t c0 = key & 63, b = key >> 6;
+    const uint32_t touched = uni(rg.cmask(p)[c0]);
+    const uint32_t rows = (1u << p) - 1;
+    for (int e = lane; e < (p - 1) * DSTRIDE; e += SW) {
+        const int j = e / DSTRIDE, i = e - j * DSTRIDE;
+        if (i < p) {
+            const uint32_t below = (1u << i) - 1;
+            const int pos = ((touched >> i) & 1) ? __popc(touched & below) : (int)b + __popc(~touched & rows & below);
+            const int g = j == 0 ? (int)c0 : (j == (int)c0 ? 0 : j);
+            rg.D[j * DSTRIDE + pos] = 2 * (int32_t)M[i * p + g];
+        } else {
+            rg.D[j * DSTRIDE + i] = 0;
+        }
+    }
+    if (lane < DSTRIDE) {
+        if (lane < p) {
+            const uint32_t below = (1u << lane) - 1;
+            const int pos = ((touched >> lane) & 1) ? __popc(touched & below) : (int)b + __popc(~touched & rows & below);
+            rg.base[pos] = 2 * (int32_t)M[lane * p + p - 1] - (int32_t)rg.rsum(p)[lane];
+        } else {
+            rg.base[lane] = 1;
+        }
+    }
+    wave_sync();
+    return b;
+}
+
+// This lane's share of V = (-1)^(p-1) 2^(p-1) per(leaf) for a leaf of order 7 <= p <= PMAX.
+__device__ __forceinline__ uint64_t eval_leaf(const Region &rg, int p, int lane) {
+    const uint32_t b = leaf_tables(rg, p, lane);
+    uint64_t v;
+    if (p >= 8 && p <= 12 && b <= 2) v = walk_paired<12, 2>(p, lane, rg.D, rg.base);
+    else if (p >= 8 && p <= 12 && b <= 4) v = walk_paired<12, 4>(p, lane, rg.D, rg.base);
+    else if (p <= 12) v = walk_plain<12>(p, lane, rg.D, rg.base);
+    else if (b <= 2) v = walk_paired<16, 2>(p, lane, rg.D, rg.base);
+    else if (b <= 4) v = walk_paired<16, 4>(p, lane, rg.D, rg.base);
+    else v = walk_plain<16>(p, lane, rg.D, rg.base);
+    wave_sync();   // the tables are rewritten by the next leaf
+    return v;
+}
+
+__device__ __forceinline__ uint64_t scale_to_job(uint64_t v, int m, int p) {
+    const int sh = m - p;
+    v <<= sh;
+    return (sh & 1) ? (uint64_t)0 - v : v;
+}
+
+// A deferred wide leaf: the job, the leaf's order and the child index taken at every order
+// above it (bit m - o for the split at order o).
+struct WideLeaf {
+    uint32_t job;
+    uint32_t order_path;   // order | path << 8
+};
 
 __global__ __launch_bounds__(SW) void hper_split_w64(const JobDesc *__restrict__ jobs,
                                                      const uint32_t *__restrict__ data,
@@ -188,154 +451,61 @@ __global__ __launch_bounds__(SW) void hper_split_w64(const JobDesc *__restrict__
                                                      int t, int s_leaf, unsigned long long *head,
                                                      JobAcc *__restrict__ accs,
                                                      unsigned long long *__restrict__ stats,
+                                                     WideLeaf *__restrict__ wide, uint32_t wide_cap,
                                                      unsigned long long *__restrict__ cycles) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    uint32_t *slots = lds;
-    int32_t *D = (int32_t *)(lds + align4(slot_off(t - 1)));
-    int32_t *base = D + SMAX * DSTRIDE;
-    uint32_t *ctl_all = (uint32_t *)(base + SMAX);
-    auto slot = [&](int o) { return slots + (slot_off(o) - slot_off(SMAX)); };
+    const Region rg(lds, t);
     uint64_t n_leaves = 0, n_terms = 0, n_splits = 0, n_stops = 0;
     for (;;) {
         const unsigned long long got = atomicAdd(head, lane == 0 ? 1ull : 0ull);
         const uint64_t qi = uni64(got);
         if (qi >= nqueue) break;
         const uint32_t job = uni(queue[qi]);
-        const JobDesc jd = jobs[job];
-        const int m0 = (int)uni(jd.m);
-        const uint32_t *blk = data + (size_t)uni(jd.data_off) * HP_DATA_ALIGN;
         const uint64_t t0 = (uint64_t)clock64();
-        // the job as a dense m0 x m0 matrix: Gray columns 0..m0-2, then the fixed column
-        uint32_t *R0 = slot(m0);
-        for (int e = lane; e < m0 * m0; e += SW) R0[e] = 0;
-        wave_sync();
-        if (lane < m0 - 1) {
-            const uint32_t b = blk[m0 + lane], en = blk[m0 + lane + 1];
-            for (uint32_t e = b; e < en; ++e) {
-                const uint32_t w = blk[3 * m0 + e];
-                R0[(w & 0xffu) * m0 + lane] = w >> 9;
-            }
-        }
-        wave_sync();
-        if (lane < m0) {
-            int32_t sg = 0;
-            for (int g = 0; g < m0 - 1; ++g) sg += (int32_t)R0[lane * m0 + g];
-            R0[lane * m0 + m0 - 1] = (uint32_t)((int32_t)blk[lane] + sg);
-        }
-        wave_sync();
+        const int m0 = load_job(rg, jobs, data, job, lane);
         uint64_t acc = 0;
         int o = m0;
         for (;;) {
-            const uint32_t *M = slot(o);
-            // Step 1 of H_per: the sparsest line (rows on lanes 0..o-1, columns on 32..32+o-1)
-            uint32_t key = 0xffffffffu;
-            if (lane < o) {
-                uint32_t k = 0;
-                for (int j = 0; j < o; ++j) k += M[lane * o + j] != 0;
-                key = (k << 6) | (uint32_t)lane;
-            } else if (lane >= 32 && lane < 32 + o) {
-                uint32_t k = 0;
-                for (int i = 0; i < o; ++i) k += M[i * o + (lane - 32)] != 0;
-                key = (k << 6) | (uint32_t)lane;
-            }
-            key = uni(wave_min(key));
-            const uint32_t s = key >> 6, is_col = (key >> 5) & 1, line = key & 31;
+            const uint32_t key = sparsest_line(rg, o, lane);
+            const uint32_t s = key >> 6;
             bool leaf = false;
             if (s == 0) {
                 // dropped: per = 0
             } else if (o <= t || o <= 2 || (int)s >= s_leaf || s > 4) {
                 leaf = true;
+            } else if (plan_split(rg, o, key, lane)) {
+                make_child(rg, o, 0, lane);
+                ++n_splits;
+                --o;
+                continue;
             } else {
-                // the line's nonzeros in increasing index order, pairs, and the bound check
-                uint32_t v = 0;
-                if (lane < o) v = is_col ? M[lane * o + line] : M[line * o + lane];
-                uint64_t nz = __ballot(v != 0);
-                const uint64_t all = (1ull << o) - 1;
-                const uint32_t zero = (uint32_t)__builtin_ctzll(~nz & all);
-                uint32_t pos[4], val[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    pos[k] = zero;
-                    val[k] = 0;
-                    if ((uint32_t)k < s) {
-                        pos[k] = (uint32_t)__builtin_ctzll(nz);
-                        nz &= nz - 1;
-                        val[k] = uni((uint32_t)__shfl((int)v, (int)pos[k]));
-                    }
-                }
-                const uint32_t np = (s + 1) / 2;
-                bool bad = false;
-                for (uint32_t ch = 0; ch < np; ++ch) {
-                    const uint32_t P = pos[2 * ch], Q = pos[2 * ch + 1];
-                    const uint64_t ca = val[2 * ch], cb = val[2 * ch + 1];
-                    bool fail = false;
-                    if (!is_col) {
-                        if (lane < o && (uint32_t)lane != line) {
-                            const uint32_t *row = M + lane * o;
-                            uint64_t rs = 0;
-                            for (int j = 0; j < o; ++j) rs += row[j];
-                            const uint64_t mv = ca * row[Q] + cb * row[P];
-                            fail = mv >= HP_MAX_ENTRY || rs - row[P] - row[Q] + mv >= HP_MAX_ROWSUM;
-                        }
-                    } else {
-                        uint64_t mv = 0;
-                        if (lane < o && (uint32_t)lane != line) {
-                            mv = ca * M[Q * o + lane] + cb * M[P * o + lane];
-                            fail = mv >= HP_MAX_ENTRY;
-                        }
-                        const uint64_t merged_sum = wave_sum64(mv);   // every lane takes part
-                        fail = fail || merged_sum >= HP_MAX_ROWSUM;
-                    }
-                    const bool any = __ballot(fail) != 0;
-                    bad = bad || any;
-                }
-                if (bad) {
-                    leaf = true;
-                    ++n_stops;
-                } else {
-                    uint32_t *ctl = ctl_all + o * CTL;
-                    if (lane == 0) {
-                        ctl[SplitCtl::IS_COL] = is_col;
-                        ctl[SplitCtl::IDX] = line;
-                        ctl[SplitCtl::NP] = np;
-                        ctl[SplitCtl::P0] = pos[0];
-                        ctl[SplitCtl::Q0] = pos[1];
-                        ctl[SplitCtl::CA0] = val[0];
-                        ctl[SplitCtl::CB0] = val[1];
-                        ctl[SplitCtl::P1] = pos[2];
-                        ctl[SplitCtl::Q1] = pos[3];
-                        ctl[SplitCtl::CA1] = val[2];
-                        ctl[SplitCtl::CB1] = val[3];
-                        ctl[SplitCtl::NEXT] = 0;
-                    }
-                    wave_sync();
-                    make_child(M, o, ctl, 0, slot(o - 1), lane);
-                    ++n_splits;
-                    --o;
-                    continue;
-                }
+                leaf = true;
+                ++n_stops;
             }
             if (leaf) {
-                uint64_t v;
-                if (o <= 12) v = eval_leaf<12>(M, o, lane, D, base);
-                else if (o <= 16) v = eval_leaf<16>(M, o, lane, D, base);
-                else v = eval_leaf<20>(M, o, lane, D, base);
-                const int sh = m0 - o;
-                v <<= sh;
-                acc += (sh & 1) ? (uint64_t)0 - v : v;
                 ++n_leaves;
                 n_terms += 1ull << (o - 1);
+                if (o <= PMAX) {
+                    acc += scale_to_job(eval_leaf(rg, o, lane), m0, o);
+                } else {
+                    uint32_t path = 0;
+                    for (int u = o + 1; u <= m0; ++u) path |= uni(rg.ctl(u)[SplitCtl::NEXT]) << (m0 - u);
+                    if (lane == 0) {
+                        const unsigned long long w = atomicAdd(stats + 4, 1ull);
+                        if (w < wide_cap) wide[w] = WideLeaf{job, (uint32_t)o | (path << 8)};
+                    }
+                }
             }
             // back up to the nearest node on the path with a child left
             int up = o + 1;
             for (; up <= m0; ++up) {
-                uint32_t *ctl = ctl_all + up * CTL;
+                uint32_t *ctl = rg.ctl(up);
                 const uint32_t nx = uni(ctl[SplitCtl::NEXT]) + 1;
                 if (nx < uni(ctl[SplitCtl::NP])) {
                     if (lane == 0) ctl[SplitCtl::NEXT] = nx;
                     wave_sync();
-                    make_child(slot(up), up, ctl, (int)nx, slot(up - 1), lane);
+                    make_child(rg, up, (int)nx, lane);
                     break;
                 }
             }
@@ -356,27 +526,74 @@ __global__ __launch_bounds__(SW) void hper_split_w64(const JobDesc *__restrict__
     }
 }
 
+// The deferred wide leaves: each wave replays one leaf's path from its job's matrix (the same
+// line choices and pairs) and adds the leaf's scaled value to the job.
+__global__ __launch_bounds__(SW) void hper_split_wide_w64(const JobDesc *__restrict__ jobs,
+                                                          const uint32_t *__restrict__ data, int t,
+                                                          const unsigned long long *__restrict__ stats,
+                                                          const WideLeaf *__restrict__ wide, uint32_t wide_cap,
+                                                          uint32_t njobs, JobAcc *__restrict__ accs) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    const int lane = threadIdx.x;
+    const Region rg(lds, t);
+    const uint64_t n = min((uint64_t)stats[4], (uint64_t)wide_cap);
+    for (uint64_t w = blockIdx.x; w < n; w += gridDim.x) {
+        const WideLeaf wl = wide[w];
+        const uint32_t job = uni(wl.job), op = uni(wl.order_path);
+        const int p = (int)(op & 0xffu);
+        const uint32_t path = op >> 8;
+        if (job >= njobs) continue;
+        const int m0 = load_job(rg, jobs, data, job, lane);
+        if (p < HP_SPLIT_MIN_T || p > m0) continue;
+        for (int o = m0; o > p; --o) {
+            if (!plan_split(rg, o, sparsest_line(rg, o, lane), lane)) break;   // not reached: the
+            make_child(rg, o, (int)((path >> (m0 - o)) & 1), lane);           // first pass split here
+        }
+        const uint32_t b = leaf_tables(rg, p, lane);
+        const uint64_t v = b <= 4 && p >= 8 ? walk_paired<SMAX, 4>(p, lane, rg.D, rg.base)
+                                            : walk_plain<SMAX>(p, lane, rg.D, rg.base);
+        const uint64_t total = wave_sum64(scale_to_job(v, m0, p));
+        if (lane == 0) atomicAdd(&accs[job].l[0], (unsigned long long)total);
+    }
+}
+
 }  // namespace
 
 size_t split_lds_bytes(int t) { return (size_t)region_words(t) * sizeof(uint32_t); }
+size_t split_wide_bytes(uint32_t n) { return (size_t)n * 15 * sizeof(WideLeaf); }
 
-hipError_t launch_split_w64(const JobDesc *jobs, const uint32_t *data, const uint32_t *queue, uint32_t n,
-                            int t, int s_leaf, unsigned long long *head, JobAcc *accs,
-                            unsigned long long *stats, unsigned long long *cycles, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    if (t < HP_SPLIT_MIN_T || t >= HP_SPLIT_MAX_M) return hipErrorInvalidValue;
-    const size_t lds = split_lds_bytes(t);
+static hipError_t resident_grid(const void *fn, size_t lds, uint64_t *grid) {
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, hper_split_w64, SW, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, SW, lds);
     if (e != hipSuccess) return e;
-    uint64_t grid = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 1);
+    *grid = (uint64_t)cus * (uint64_t)(per_cu > 0 ? per_cu : 1);
+    return hipSuccess;
+}
+
+hipError_t launch_split_w64(const JobDesc *jobs, const uint32_t *data, const uint32_t *queue, uint32_t n,
+                            uint32_t njobs, int t, int s_leaf, unsigned long long *head, JobAcc *accs,
+                            unsigned long long *stats, void *wide, unsigned long long *cycles,
+                            hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (t < HP_SPLIT_MIN_T || t >= HP_SPLIT_MAX_M) return hipErrorInvalidValue;
+    const size_t lds = split_lds_bytes(t);
+    const uint32_t cap = n * 15;   // at most 1 + 2 + 4 + 8 nodes of orders 17..20 per job
+    uint64_t grid = 0;
+    hipError_t e = resident_grid((const void *)hper_split_w64, lds, &grid);
+    if (e != hipSuccess) return e;
     if (grid > n) grid = n;
     hipLaunchKernelGGL(hper_split_w64, dim3((uint32_t)grid), dim3(SW), lds, s, jobs, data, queue, n, t, s_leaf,
-                       head, accs, stats, cycles);
+                       head, accs, stats, (WideLeaf *)wide, cap, cycles);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = resident_grid((const void *)hper_split_wide_w64, lds, &grid);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(hper_split_wide_w64, dim3((uint32_t)grid), dim3(SW), lds, s, jobs, data, t,
+                       (const unsigned long long *)stats, (const WideLeaf *)wide, cap, njobs, accs);
     return hipGetLastError();
 }
 
