@@ -194,6 +194,53 @@ def schedule_study(hp, ctx, jobs, keys, machines=(1, 2, 4, 8, 16, 32)):
     return out
 
 
+def device_hper(hp, ctx, jobs, want, mats, golden_vals, keys, targets=(10, 12, 14), main=12):
+    """The device continuation of H_per (split_order) on the resident jobs: each job is split on
+    the device by expansion (2) down to the target order and its leaves evaluated there. Per
+    target: the split launches' time (HIP events, median of 3), leaves, their subset-terms,
+    splits, splits refused by the entry bounds, and whether the totals equal the R-NW run's.
+    At the main target also the wall time of the run call, the per(A) batch wall time, and the
+    scheduling study with T = each job's wave time."""
+    import numpy as np
+    import torch
+    out = {"target_order": main, "by_target": {}}
+    for t in targets:
+        ctx.set_opts(split_order=t)
+        try:
+            ms, walls, ok = [], [], True
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                tot, _, _ = ctx.run(jobs, "natural", True)
+                walls.append(time.perf_counter() - t0)
+                L = [x for x in ctx.last_launches() if x["variant"] == 3][0]
+                ms.append(L["ms"])
+                ok = ok and tot == want
+        finally:
+            ctx.set_opts(split_order=0)
+        out["by_target"][str(t)] = {
+            "split_ms": sorted(ms)[1], "run_call_ms": sorted(walls)[1] * 1e3, "leaves": int(L["leaves"]),
+            "leaf_terms": int(L["leaf_terms"]), "splits": int(L["splits"]),
+            "refused_splits": int(L["split_stops"]), "jobs": int(L["n_jobs"]), "totals_equal_rnw": ok}
+    ctx.set_opts(split_order=main)
+    try:
+        ctx.permanent_batch(mats)   # warm-up
+        walls = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            vals = ctx.permanent_batch(mats)
+            walls.append(time.perf_counter() - t0)
+        out["per_a_wall_ms_batch"] = sorted(walls)[2] * 1e3
+        out["per_a_verified"] = bool(golden_vals) and vals == golden_vals
+        st = schedule_study(hp, ctx, jobs, keys)
+        st["time_unit"] = "shader-clock cycles of the job's wave (split, leaves and their walks)"
+        out["schedule_study"] = st
+    finally:
+        ctx.set_opts(split_order=0)
+    return out
+
+
 def copy_probe(nbytes: int = 256 << 20, reps: int = 3):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -329,7 +376,11 @@ def main():
         "checks": {"leading_1": poly[24] == 1, "trace_0": poly[23] == 0, "edges_36": poly[22] == 36,
                    "constant_is_per": poly[0] == ctx.permanent(G24)}}
     log("scheduling study on the n60 jobs")
-    extra["schedule_study_n60"] = schedule_study(hp, ctx, jobs, ctx.estimate(jobs, args.trials, 1))
+    keys = ctx.estimate(jobs, args.trials, 1)
+    extra["schedule_study_n60"] = schedule_study(hp, ctx, jobs, keys)
+    log("device continuation of H_per on the n60 jobs")
+    golden_vals = [int(golden[n]) for n in names] if golden else None
+    extra["device_hper_n60"] = device_hper(hp, ctx, jobs, tot, mats, golden_vals, keys)
     plain = None
     if not args.no_plain:
         log("plain: one launch per job, expansion order (best lane chunk of 3, 5, 7)")
