@@ -194,16 +194,16 @@ def schedule_study(hp, ctx, jobs, keys, machines=(1, 2, 4, 8, 16, 32)):
     return out
 
 
-def device_hper(hp, ctx, jobs, want, mats, golden_vals, keys, targets=(10, 12, 14), main=12):
+def device_hper(hp, ctx, jobs, want, mats, golden_vals, keys, targets=(10, 12, 13, 14, 15, 16)):
     """The device continuation of H_per (split_order) on the resident jobs: each job is split on
     the device by expansion (2) down to the target order and its leaves evaluated there. Per
     target: the split launches' time (HIP events, median of 3), leaves, their subset-terms,
     splits, splits refused by the entry bounds, and whether the totals equal the R-NW run's.
-    At the main target also the wall time of the run call, the per(A) batch wall time, and the
-    scheduling study with T = each job's wave time."""
+    At the fastest target also the per(A) batch wall time and the scheduling study with T =
+    each job's wave time."""
     import numpy as np
     import torch
-    out = {"target_order": main, "by_target": {}}
+    out = {"by_target": {}}
     for t in targets:
         ctx.set_opts(split_order=t)
         try:
@@ -222,6 +222,8 @@ def device_hper(hp, ctx, jobs, want, mats, golden_vals, keys, targets=(10, 12, 1
             "split_ms": sorted(ms)[1], "run_call_ms": sorted(walls)[1] * 1e3, "leaves": int(L["leaves"]),
             "leaf_terms": int(L["leaf_terms"]), "splits": int(L["splits"]),
             "refused_splits": int(L["split_stops"]), "jobs": int(L["n_jobs"]), "totals_equal_rnw": ok}
+    main = min(targets, key=lambda t: out["by_target"][str(t)]["split_ms"])
+    out["target_order"] = main
     ctx.set_opts(split_order=main)
     try:
         ctx.permanent_batch(mats)   # warm-up

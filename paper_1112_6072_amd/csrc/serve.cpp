@@ -16,6 +16,7 @@
 #include <unordered_map>
 
 #include "ctx.h"
+#include "kernels.h"
 
 namespace hp {
 
@@ -46,12 +47,15 @@ struct Batch {
 };
 
 // Device bytes of one batch part: the buffers of the pipeline for nd jobs, `words` data words
-// and np problems, each buffer rounded up to 256 bytes.
-size_t part_bytes(size_t nd, size_t words, size_t np) {
+// and np problems, each buffer rounded up to 256 bytes (with split_order, also the device
+// H_per counters and its record buffer for the leaves above order 16).
+size_t part_bytes(size_t nd, size_t words, size_t np, bool split) {
     auto al = [](size_t x) { return (std::max<size_t>(x, 1) + 255) / 256 * 256; };
-    return al(nd * sizeof(JobDesc)) + al((words + 64) * 4) + al(nd * 4) /*keys*/ + al(nd * 4) /*list*/ +
-           al(nd * 4) /*queue*/ + al(nd * 8) /*items*/ + al(nd * sizeof(JobAcc)) + al(64 * 8) /*heads*/ +
-           al(np * sizeof(ProbAcc)) + 2048;
+    size_t b = al(nd * sizeof(JobDesc)) + al((words + 64) * 4) + al(nd * 4) /*keys*/ + al(nd * 4) /*list*/ +
+               al(nd * 4) /*queue*/ + al(nd * 8) /*items*/ + al(nd * sizeof(JobAcc)) + al(64 * 8) /*heads*/ +
+               al(np * sizeof(ProbAcc)) + 2048;
+    if (split) b += al(8 * 8) + al(split_wide_bytes((uint32_t)std::max<size_t>(nd, 1)));
+    return b;
 }
 
 }  // namespace
@@ -140,7 +144,7 @@ struct Serving {
                 r->t_done = now_s();
             } else {
                 const auto &t = r->jobs.tab;
-                r->bytes = part_bytes(t.desc.size(), t.data.size(), 1);
+                r->bytes = part_bytes(t.desc.size(), t.data.size(), 1, ctx->opts.split_order != 0);
                 if (r->bytes > arena_bytes) {
                     r->status = HPERM_E_NOMEM;
                     r->err = "request needs " + std::to_string(r->bytes) + " device bytes; the serving arena holds " +
@@ -175,7 +179,8 @@ struct Serving {
                 for (auto &f : free_list) largest = std::max(largest, f.second);
                 for (Request *r : ready) {
                     const auto &t = r->jobs.tab;
-                    const size_t cand = part_bytes(nd + t.desc.size(), words + t.data.size(), take.size() + 1);
+                    const size_t cand = part_bytes(nd + t.desc.size(), words + t.data.size(), take.size() + 1,
+                                                   ctx->opts.split_order != 0);
                     if (cand > largest) break;
                     take.push_back(r);
                     nd += t.desc.size();

@@ -71,13 +71,23 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-    for (int o = 32; o; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o));
-    return v;
-}
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
     for (int o = 32; o; o >>= 1) v += (uint64_t)__shfl_xor((unsigned long long)v, o);
     return v;
+}
+
+// Among the lanes with `valid`, the lowest one holding the smallest count (count < 32): a
+// search over the count's bits with ballots (no LDS round trips). Writes that count.
+__device__ __forceinline__ uint32_t argmin_lane(uint32_t count, bool valid, uint32_t *minval) {
+    uint64_t set = __ballot(valid);
+#pragma unroll
+    for (int b = 4; b >= 0; --b) {
+        const uint64_t zero = __ballot(((count >> b) & 1u) == 0) & set;
+        if (zero) set = zero;
+    }
+    const uint32_t w = (uint32_t)__builtin_ctzll(set);
+    *minval = (uint32_t)__builtin_amdgcn_readlane((int)count, (int)w);
+    return w;
 }
 
 // floor(e / d) for e < 1024, 1 <= d <= 32 (multiply by the rounded-up reciprocal: exact here).
@@ -264,18 +274,45 @@ __device__ __forceinline__ int load_job(const Region &rg, const JobDesc *jobs, c
 // Step 1 of H_per at the node of order o: returns (count << 6) | (32 * is_col + index) of the
 // sparsest line (rows before columns, then the lowest index).
 __device__ __forceinline__ uint32_t sparsest_line(const Region &rg, int o, int lane) {
-    uint32_t key = 0xffffffffu;
-    if (lane < o) key = ((uint32_t)__popc(rg.rmask(o)[lane]) << 6) | (uint32_t)lane;
-    else if (lane >= 32 && lane < 32 + o) key = ((uint32_t)__popc(rg.cmask(o)[lane - 32]) << 6) | (uint32_t)lane;
-    return uni(wave_min(key));
+    uint32_t cnt = 0;
+    const bool row = lane < o, col = lane >= 32 && lane < 32 + o;
+    if (row) cnt = (uint32_t)__popc(rg.rmask(o)[lane]);
+    else if (col) cnt = (uint32_t)__popc(rg.cmask(o)[lane - 32]);
+    uint32_t s;
+    const uint32_t w = argmin_lane(cnt, row || col, &s);
+    return (s << 6) | w;
+}
+
+// A split: the line (row or column index), its pairs (positions P, Q and weights ca, cb of
+// the merge ca * y_Q + cb * y_P) and their number.
+struct Plan {
+    uint32_t is_col, line, np;
+    uint32_t P[2], Q[2], ca[2], cb[2];
+};
+
+__device__ __forceinline__ Plan load_plan(const Region &rg, int o) {
+    const uint32_t *ctl = rg.ctl(o);
+    Plan pl;
+    pl.is_col = uni(ctl[SplitCtl::IS_COL]);
+    pl.line = uni(ctl[SplitCtl::IDX]);
+    pl.np = uni(ctl[SplitCtl::NP]);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        pl.P[c] = uni(ctl[SplitCtl::P0 + 4 * c]);
+        pl.Q[c] = uni(ctl[SplitCtl::Q0 + 4 * c]);
+        pl.ca[c] = uni(ctl[SplitCtl::CA0 + 4 * c]);
+        pl.cb[c] = uni(ctl[SplitCtl::CB0 + 4 * c]);
+    }
+    return pl;
 }
 
 // Pairs of expansion (2) along the line (nonzeros in increasing index order; an odd last one
 // with the lowest zero of the line at weight 0) into ctl, the child counter cleared. Returns
 // false when a child would break the entry or row-sum bound (ctl then unused).
-__device__ __forceinline__ bool plan_split(const Region &rg, int o, uint32_t key, int lane) {
+__device__ __forceinline__ bool plan_split(const Region &rg, int o, uint32_t key, int lane, Plan &pl) {
     const uint32_t s = key >> 6, is_col = (key >> 5) & 1, line = key & 31;
     const uint32_t *M = rg.slot(o);
+    const uint32_t lv = lane < o ? (is_col ? M[lane * o + line] : M[line * o + lane]) : 0u;   // the line
     uint32_t nz = uni(is_col ? rg.cmask(o)[line] : rg.rmask(o)[line]);
     const uint32_t zero = (uint32_t)__builtin_ctz(~nz & ((1u << o) - 1));
     uint32_t pos[4], val[4];
@@ -286,7 +323,7 @@ __device__ __forceinline__ bool plan_split(const Region &rg, int o, uint32_t key
         if ((uint32_t)k < s) {
             pos[k] = (uint32_t)__builtin_ctz(nz);
             nz &= nz - 1;
-            val[k] = uni(is_col ? M[pos[k] * o + line] : M[line * o + pos[k]]);
+            val[k] = (uint32_t)__builtin_amdgcn_readlane((int)lv, (int)pos[k]);
         }
     }
     const uint32_t np = (s + 1) / 2;
@@ -311,6 +348,16 @@ __device__ __forceinline__ bool plan_split(const Region &rg, int o, uint32_t key
         }
     }
     if (__ballot(fail) != 0) return false;
+    pl.is_col = is_col;
+    pl.line = line;
+    pl.np = np;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        pl.P[c] = pos[2 * c];
+        pl.Q[c] = pos[2 * c + 1];
+        pl.ca[c] = val[2 * c];
+        pl.cb[c] = val[2 * c + 1];
+    }
     uint32_t *ctl = rg.ctl(o);
     if (lane == 0) {
         ctl[SplitCtl::IS_COL] = is_col;
@@ -330,15 +377,14 @@ __device__ __forceinline__ bool plan_split(const Region &rg, int o, uint32_t key
     return true;
 }
 
-// Child `ch` of the node of order o (plan in its ctl) into slot o - 1 with its masks and row
+// Child `ch` of the node of order o (split by plan pl) into slot o - 1 with its masks and row
 // sums. Lanes cover three child rows per pass (lane = 21 * r + column).
-__device__ __forceinline__ void make_child(const Region &rg, int o, int ch, int lane) {
-    const uint32_t *ctl = rg.ctl(o);
+__device__ __forceinline__ void make_child(const Region &rg, int o, const Plan &pl, int ch, int lane) {
     const uint32_t *M = rg.slot(o);
     uint32_t *C = rg.slot(o - 1);
-    const uint32_t is_col = uni(ctl[SplitCtl::IS_COL]), line = uni(ctl[SplitCtl::IDX]);
-    const uint32_t P = uni(ctl[SplitCtl::P0 + 4 * ch]), Q = uni(ctl[SplitCtl::Q0 + 4 * ch]);
-    const uint32_t ca = uni(ctl[SplitCtl::CA0 + 4 * ch]), cb = uni(ctl[SplitCtl::CB0 + 4 * ch]);
+    const uint32_t is_col = pl.is_col, line = pl.line;
+    const uint32_t P = ch ? pl.P[1] : pl.P[0], Q = ch ? pl.Q[1] : pl.Q[0];
+    const uint32_t ca = ch ? pl.ca[1] : pl.ca[0], cb = ch ? pl.cb[1] : pl.cb[0];
     const uint32_t keep = min(P, Q), drop = max(P, Q);
     const uint32_t co = (uint32_t)o - 1;
     const uint32_t r3 = (uint32_t)lane / 21, jp = (uint32_t)lane - 21 * r3;
@@ -362,7 +408,6 @@ __device__ __forceinline__ void make_child(const Region &rg, int o, int ch, int 
         if (ok && jp == 0) rg.rmask(o - 1)[ip] = (uint32_t)(bal >> (21 * r3)) & ((1u << 21) - 1);
     }
     cm |= (uint32_t)__shfl((int)cm, lane + 21) | (uint32_t)__shfl((int)cm, lane + 42);
-    if ((uint32_t)lane < co) rg.cmask(o - 1)[lane] = cm;
     if ((uint32_t)lane < co) {   // row sums from the parent's
         const uint32_t ip = (uint32_t)lane;
         uint32_t rs;
@@ -377,6 +422,7 @@ __device__ __forceinline__ void make_child(const Region &rg, int o, int ch, int 
             else
                 rs = rg.rsum(o)[i] - M[i * o + line];
         }
+        rg.cmask(o - 1)[lane] = cm;
         rg.rsum(o - 1)[ip] = rs;
     }
     wave_sync();
@@ -388,11 +434,10 @@ __device__ __forceinline__ void make_child(const Region &rg, int o, int ch, int 
 // invariant under both permutations). Returns that column's nonzero count b.
 __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, int lane) {
     const uint32_t *M = rg.slot(p);
-    uint32_t key = 0xffffffffu;
-    if (lane < p - 1) key = ((uint32_t)__popc(rg.cmask(p)[lane]) << 6) | (uint32_t)lane;
-    key = uni(wave_min(key));
-    const uint32_t c0 = key & 63, b = key >> 6;
-    const uint32_t touched = uni(rg.cmask(p)[c0]);
+    const uint32_t cmk = lane < p - 1 ? rg.cmask(p)[lane] : 0u;
+    uint32_t b;
+    const uint32_t c0 = argmin_lane((uint32_t)__popc(cmk), lane < p - 1, &b);
+    const uint32_t touched = (uint32_t)__builtin_amdgcn_readlane((int)cmk, (int)c0);
     const uint32_t rows = (1u << p) - 1;
     for (int e = lane; e < (p - 1) * DSTRIDE; e += SW) {
         const int j = e / DSTRIDE, i = e - j * DSTRIDE;
@@ -402,7 +447,7 @@ __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, int lan
             const int g = j == 0 ? (int)c0 : (j == (int)c0 ? 0 : j);
             rg.D[j * DSTRIDE + pos] = 2 * (int32_t)M[i * p + g];
         } else {
-            rg.D[j * DSTRIDE + i] = 0;
+            rg.D[e] = 0;
         }
     }
     if (lane < DSTRIDE) {
@@ -466,6 +511,7 @@ __global__ __launch_bounds__(SW) void hper_split_w64(const JobDesc *__restrict__
         const int m0 = load_job(rg, jobs, data, job, lane);
         uint64_t acc = 0;
         int o = m0;
+        Plan pl;
         for (;;) {
             const uint32_t key = sparsest_line(rg, o, lane);
             const uint32_t s = key >> 6;
@@ -474,8 +520,8 @@ __global__ __launch_bounds__(SW) void hper_split_w64(const JobDesc *__restrict__
                 // dropped: per = 0
             } else if (o <= t || o <= 2 || (int)s >= s_leaf || s > 4) {
                 leaf = true;
-            } else if (plan_split(rg, o, key, lane)) {
-                make_child(rg, o, 0, lane);
+            } else if (plan_split(rg, o, key, lane, pl)) {
+                make_child(rg, o, pl, 0, lane);
                 ++n_splits;
                 --o;
                 continue;
@@ -504,8 +550,7 @@ __global__ __launch_bounds__(SW) void hper_split_w64(const JobDesc *__restrict__
                 const uint32_t nx = uni(ctl[SplitCtl::NEXT]) + 1;
                 if (nx < uni(ctl[SplitCtl::NP])) {
                     if (lane == 0) ctl[SplitCtl::NEXT] = nx;
-                    wave_sync();
-                    make_child(rg, up, (int)nx, lane);
+                    make_child(rg, up, load_plan(rg, up), (int)nx, lane);
                     break;
                 }
             }
@@ -545,9 +590,10 @@ __global__ __launch_bounds__(SW) void hper_split_wide_w64(const JobDesc *__restr
         if (job >= njobs) continue;
         const int m0 = load_job(rg, jobs, data, job, lane);
         if (p < HP_SPLIT_MIN_T || p > m0) continue;
+        Plan pl;
         for (int o = m0; o > p; --o) {
-            if (!plan_split(rg, o, sparsest_line(rg, o, lane), lane)) break;   // not reached: the
-            make_child(rg, o, (int)((path >> (m0 - o)) & 1), lane);           // first pass split here
+            if (!plan_split(rg, o, sparsest_line(rg, o, lane), lane, pl)) break;   // not reached: the
+            make_child(rg, o, pl, (int)((path >> (m0 - o)) & 1), lane);           // first pass split here
         }
         const uint32_t b = leaf_tables(rg, p, lane);
         const uint64_t v = b <= 4 && p >= 8 ? walk_paired<SMAX, 4>(p, lane, rg.D, rg.base)

@@ -156,3 +156,62 @@ def test_split_job_timing(hperm):
         assert (J.cycles() > 0).all()
     finally:
         c.close()
+
+
+def test_split_serving_and_arena(hperm):
+    """The serving loop and a caller-owned device arena with split_order: served values and
+    batch values equal the oracle's (mixed 3-regular, 4-regular and small-integer requests)."""
+    reqs = [A for _, A in W.serving_requests(24, 11, 18, 32)]
+    want = native.hper_batch(reqs, threads=8)
+    say("split serving", len(reqs))
+    c = hperm.Context({"m_cut": 16, "split_order": 10})
+    try:
+        c.serve_start(32, 64 << 20)
+        tickets = [c.submit(A) for A in reqs]
+        assert all(t is not None for t in tickets)
+        got = [c.wait(t, 120.0)[0] for t in tickets]
+        c.serve_stop()
+        assert got == want
+        c.set_arena(4096)
+        got, seen = None, []
+        for _ in range(8):   # each refusal reports what its allocation needed
+            try:
+                got = c.permanent_batch(reqs)
+                break
+            except hperm.HpermError as e:
+                seen.append((e.status, str(e)[-60:], c.arena_required()))
+                assert e.status == -4, seen
+                c.set_arena(c.arena_required() * 2)
+        say("arena attempts", seen)
+        assert got == want, seen
+    finally:
+        c.close()
+
+
+def test_split_extremes(hperm, ctx):
+    """Target 19 (one split level below order 20), target 7 (the smallest), and job tables
+    with nothing to split (no device H_per launch): values equal the oracle's."""
+    mats = [W.permutation_union_matrix(20, 3, 30 + i, 1, 2) for i in range(4)]
+    mats += [W.permutation_union_matrix(m, 3, 40 + m, 1, 2) for m in (8, 9, 11)]
+    J = ctx.jobs_from_dense(mats)
+    stored = job_mats(J)
+    want = native.ryser_batch(stored, threads=8)
+    eligible = lambda t: [B for B, a in zip(stored, J.describe()["arith"]) if a == 1 and t < len(B) <= 20]
+    for t in (19, 7):
+        say("split extreme", t)
+        ctx.set_opts(split_order=t)
+        try:
+            _, per_job, _ = ctx.run(J, "natural", True, per_job=True)
+            st = split_launch(ctx)
+        finally:
+            ctx.set_opts(split_order=0)
+        assert per_job == want
+        assert (st["leaves"], st["leaf_terms"]) == oracle_traversal(eligible(t), t)
+    small = ctx.jobs_from_dense([W.permutation_union_matrix(m, 3, 50 + m, 1, 2) for m in (5, 9, 12)])
+    ctx.set_opts(split_order=12)
+    try:
+        _, per_job, _ = ctx.run(small, "natural", True, per_job=True)
+        assert not [l for l in ctx.last_launches() if l["variant"] == 3]
+    finally:
+        ctx.set_opts(split_order=0)
+    assert per_job == native.ryser_batch(job_mats(small), threads=8)
