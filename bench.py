@@ -288,20 +288,29 @@ def main():
     golden_path = os.path.join(ROOT, "tests", "golden", "oracle_values.json")
     golden = json.load(open(golden_path)) if os.path.exists(golden_path) else {}
 
-    ctx = hp.Context({"m_cut": args.m_cut, "trials": args.trials})
+    # the R-NW measurements run with the device continuation of H_per off (split_order 0);
+    # per(A) is timed on the library's default path (split_order 12) and on the R-NW-only one
+    ctx = hp.Context({"m_cut": args.m_cut, "trials": args.trials, "split_order": 0})
 
     # ---- per(A) wall time, host CSR -> exact integers (expansion and copies included)
+    def per_a_batch(split):
+        ctx.set_opts(split_order=split)
+        try:
+            ctx.permanent_batch(mats)   # warm-up
+            walls = []
+            for _ in range(5):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                v, st = ctx.permanent_batch(mats, with_stats=True)
+                walls.append(time.perf_counter() - t0)
+        finally:
+            ctx.set_opts(split_order=0)
+        return sorted(walls)[2], v, st   # median of 5
     log("per(A) end to end")
-    ctx.permanent_batch(mats)   # warm-up
-    walls, vals = [], None
-    for _ in range(5):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        vals, stats = ctx.permanent_batch(mats, with_stats=True)
-        walls.append(time.perf_counter() - t0)
-    e2e = sorted(walls)[2]   # median of 5
+    e2e, vals, stats = per_a_batch(12)
+    e2e_rnw, vals_rnw, _ = per_a_batch(0)
     exp_s = stats[0]["t_expand_s"]
-    verified = bool(golden) and all(int(golden[n]) == v for n, v in zip(names, vals))
+    verified = bool(golden) and all(int(golden[n]) == v for n, v in zip(names, vals)) and vals_rnw == vals
 
     # ---- the timed step: jobs resident in HBM
     jobs = ctx.expand(mats)
@@ -353,16 +362,24 @@ def main():
         ctx.run(jobs, order, True)
         extra[f"persistent_{order}_rnw_ms"] = sum(L["ms"] for L in ctx.last_launches())
     extra["uneven_jobs"] = uneven_orders(hp, W, ctx)
-    # one problem alone: the truncated icosahedron (C60), median of 5 after a warm-up
-    ctx.permanent(mats[0])
-    walls1 = []
-    for _ in range(5):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        c60 = ctx.permanent(mats[0])
-        walls1.append(time.perf_counter() - t0)
-    e2e_c60 = sorted(walls1)[2]
-    verified = verified and c60 == vals[0]
+    # one problem alone: the truncated icosahedron (C60), median of 5 after a warm-up, on the
+    # default path and on the R-NW-only one
+    def c60_alone(split):
+        ctx.set_opts(split_order=split)
+        try:
+            ctx.permanent(mats[0])
+            walls1 = []
+            for _ in range(5):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                v = ctx.permanent(mats[0])
+                walls1.append(time.perf_counter() - t0)
+        finally:
+            ctx.set_opts(split_order=0)
+        return sorted(walls1)[2], v
+    e2e_c60, c60 = c60_alone(12)
+    e2e_c60_rnw, c60_rnw = c60_alone(0)
+    verified = verified and c60 == vals[0] and c60_rnw == vals[0]
     # permanental polynomial per(xI - A) of a random cubic graph on 24 vertices (25 exact
     # evaluations of per(xI + A) in one batch, then exact interpolation); median of 5
     G24 = W.random_cubic_matrix(24, 0)
@@ -430,6 +447,9 @@ def main():
         "per_a_wall_ms_batch": e2e * 1e3,
         "per_a_wall_ms_per_problem": e2e * 1e3 / len(mats),
         "per_a_wall_ms_c60_alone": e2e_c60 * 1e3,
+        "per_a_path": "library default: jobs of order 20 continued by H_per on the device to order 12",
+        "per_a_wall_ms_batch_rnw_only": e2e_rnw * 1e3,
+        "per_a_wall_ms_c60_alone_rnw_only": e2e_c60_rnw * 1e3,
         "host_expand_ms_batch": exp_s * 1e3,
         "rnw_ms_per_step": rnw_ms,
         "step_breakdown_ms": {"estimate_call": est_s * 1e3 / args.steps, "run_call": run_s * 1e3 / args.steps,

@@ -401,6 +401,9 @@ static constexpr int kSplitVariant = 3;
 static bool split_eligible(const JobDesc &d, int split) {
     return split > 0 && d.arith == HP_W64 && d.m > split && d.m <= HP_SPLIT_MAX_M;
 }
+// The split order in effect: the device continuation follows H_per's rule only for s_leaf <= 5
+// (its nodes have at most two children).
+static int split_in_effect(const hperm_opts &o) { return o.s_leaf <= 5 ? o.split_order : 0; }
 static void build_queue_groups(hperm_jobs *j, int split) {
     const std::vector<JobDesc> &dsc = j->tab.desc;
     const size_t nd = dsc.size();
@@ -488,7 +491,8 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     std::vector<uint64_t> &item_end = c->h_items;
     std::vector<size_t> goff;
     if (persistent) {
-        if (j->qgroup.size() != nd || j->qsplit != c->opts.split_order) build_queue_groups(j, c->opts.split_order);
+        const int split = split_in_effect(c->opts);
+        if (j->qgroup.size() != nd || j->qsplit != split) build_queue_groups(j, split);
         const std::vector<uint32_t> ord = job_order(j, order, c->opts.seed);
         const size_t ng = j->qgroups.size();
         goff.assign(ng + 1, 0);
@@ -522,7 +526,7 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     }
     c->timed = persistent && c->opts.time_jobs != 0;
     c->split_launch = -1;
-    if (persistent && c->opts.split_order) {
+    if (persistent && split_in_effect(c->opts)) {
         s = ensure_buf(c, B_SPLIT, 8 * sizeof(unsigned long long));
         if (s) return s;
         const hperm_jobs::QueueGroup &last = j->qgroups.back();
@@ -823,6 +827,7 @@ hperm_status hperm_default_opts(hperm_opts *o) {
     o->chunk_log2 = 0;
     o->persistent = 1;
     o->host_threads = 0;
+    o->split_order = 12;
     return HPERM_OK;
 }
 
@@ -839,7 +844,6 @@ static const char *check_opts(const hperm_opts *o) {
     if (o->time_jobs != 0 && o->time_jobs != 1) return "time_jobs must be 0 or 1";
     if (o->split_order != 0 && (o->split_order < HP_SPLIT_MIN_T || o->split_order >= HP_SPLIT_MAX_M))
         return "split_order must be 0 or in [7, 19]";
-    if (o->split_order != 0 && o->s_leaf > 5) return "split_order needs s_leaf <= 5";
     return nullptr;
 }
 

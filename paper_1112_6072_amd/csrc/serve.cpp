@@ -144,7 +144,7 @@ struct Serving {
                 r->t_done = now_s();
             } else {
                 const auto &t = r->jobs.tab;
-                r->bytes = part_bytes(t.desc.size(), t.data.size(), 1, ctx->opts.split_order != 0);
+                r->bytes = part_bytes(t.desc.size(), t.data.size(), 1, ctx->opts.split_order != 0 && ctx->opts.s_leaf <= 5);
                 if (r->bytes > arena_bytes) {
                     r->status = HPERM_E_NOMEM;
                     r->err = "request needs " + std::to_string(r->bytes) + " device bytes; the serving arena holds " +
@@ -180,7 +180,7 @@ struct Serving {
                 for (Request *r : ready) {
                     const auto &t = r->jobs.tab;
                     const size_t cand = part_bytes(nd + t.desc.size(), words + t.data.size(), take.size() + 1,
-                                                   ctx->opts.split_order != 0);
+                                                   ctx->opts.split_order != 0 && ctx->opts.s_leaf <= 5);
                     if (cand > largest) break;
                     take.push_back(r);
                     nd += t.desc.size();

@@ -33,7 +33,7 @@ def leaf_like(m, seed, k=4, hi=8):
 
 @pytest.fixture(scope="module")
 def ctx(hperm):
-    c = hperm.Context()
+    c = hperm.Context({"split_order": 0})   # these tests cover the R-NW kernels
     yield c
     c.close()
 
@@ -207,7 +207,7 @@ def test_caller_arena(hperm):
     NOMEM with the bytes needed."""
     say("arena")
     mats = W.config_n24(range(3))
-    c = hperm.Context({"m_cut": 12})
+    c = hperm.Context({"m_cut": 12, "split_order": 0})
     try:
         c.set_arena(4096)
         with pytest.raises(hperm.HpermError) as e:
@@ -268,7 +268,7 @@ def test_n80_batch_end_to_end(hperm):
     oracle values; the LPT and random queue orders agree."""
     items = W.config_n80(8)
     say("n80 batch: expand 8 graphs")
-    c = hperm.Context({"m_cut": 20, "max_table_mib": 32768})
+    c = hperm.Context({"m_cut": 20, "max_table_mib": 32768, "split_order": 0})
     try:
         J = c.expand([A for _, A in items])
         nj, npb = J.info()
@@ -291,7 +291,7 @@ def test_paired_walk_small_chunks(hperm, chunk):
     lane-dependent direction of the chunk's last column. Job by job against the oracle."""
     A = W.random_cubic_matrix(24, 7)
     say("paired walk, chunk", chunk)
-    c = hperm.Context({"m_cut": 14, "chunk_log2": chunk})
+    c = hperm.Context({"m_cut": 14, "chunk_log2": chunk, "split_order": 0})
     try:
         J = c.expand([A])
         totals, per_job, _ = c.run(J, "natural", True, per_job=True)
@@ -327,7 +327,7 @@ def test_job_timing(hperm):
     """time_jobs = 1: every job of a timed persistent run gets positive work cycles, the values
     are unchanged, and jobs with 64 times the subset-terms take many times longer."""
     say("job timing")
-    c = hperm.Context({"time_jobs": 1})
+    c = hperm.Context({"time_jobs": 1, "split_order": 0})
     try:
         mats = [leaf_like(m, 500 + i, k=3) for i, m in enumerate((14, 20, 14, 20))]
         J = c.jobs_from_dense(mats)

@@ -34,7 +34,7 @@ def test_serving_mixed_stream_matches_oracle(hperm):
     mats = stream(30, 5)
     want = native.hper_batch(mats, threads=8)
     say("serving mixed stream", len(mats))
-    c = hperm.Context({"m_cut": 16})
+    c = hperm.Context({"m_cut": 16, "split_order": 0})
     try:
         c.serve_start(64, 64 << 20)
         tickets = [c.submit(A) for A in mats]
@@ -56,7 +56,7 @@ def test_serving_arrivals_over_time(hperm):
     want = native.hper_batch(mats, threads=8)
     gaps = np.diff(np.concatenate([[0.0], W.poisson_arrivals(len(mats), 400.0, 3)]))
     say("serving arrivals", len(mats))
-    c = hperm.Context({"m_cut": 14})
+    c = hperm.Context({"m_cut": 14, "split_order": 0})
     try:
         c.serve_start(64, 32 << 20)
         tickets = []
@@ -76,7 +76,7 @@ def test_serving_small_arena_admission(hperm):
     want = native.hper_batch(mats, threads=8)
     big = W.config_n60(1)[0][1]
     say("serving small arena")
-    c = hperm.Context({"m_cut": 16})
+    c = hperm.Context({"m_cut": 16, "split_order": 0})
     try:
         c.serve_start(32, 1 << 20)
         tb = c.submit(big)
@@ -94,7 +94,7 @@ def test_serving_slots_cancel_and_errors(hperm):
     A = stream(1, 2, 20, 20)[0]
     want = native.hper_batch([A])[0]
     say("serving slots/cancel")
-    c = hperm.Context({"m_cut": 16})
+    c = hperm.Context({"m_cut": 16, "split_order": 0})
     try:
         with pytest.raises(hperm.HpermError):
             c.poll(1)   # not serving

@@ -18,10 +18,11 @@ def test_split_order_checked(hp):
     for bad in (-1, 1, 6, 20, 40):
         with pytest.raises(hp.HpermError):
             c.set_opts(split_order=bad)
-    with pytest.raises(hp.HpermError):
-        c.set_opts(split_order=12, s_leaf=6)
+    c.set_opts(split_order=12, s_leaf=6)   # accepted; the device continuation is then off
+    c.set_opts(s_leaf=5)
     for good in (0, 7, 12, 19):
         c.set_opts(split_order=good)
+    assert hp.Context(host_only=True)._opts.split_order == 12   # the default
 
 
 @pytest.mark.parametrize("m_cut", [10, 14])
