@@ -84,8 +84,8 @@ typedef struct hperm_opts {
     int32_t time_jobs;    /* 1: persistent runs of hperm_run_jobs record each job's work time
                              (hperm_jobs_cycles; the scheduling study of the paper's load
                              balancing section); 0: off (default). Ignored while serving. */
-    int32_t split_order;  /* t in [7, 19] (default 12): persistent runs continue Algorithm H_per
-                             (Section 2.1) on the device for every mod-2^64 job of order t+1..20,
+    int32_t split_order;  /* t in [7, 23] (default 12): persistent runs continue Algorithm H_per
+                             (Section 2.1) on the device for every mod-2^64 job of order t+1..24,
                              splitting it by expansion (2) down to order t, and evaluate the
                              leaves by R-NW inside the same kernel (one wave per job); other jobs
                              take the R-NW queue. Results are unchanged (the expansion is an

@@ -404,6 +404,14 @@ static bool split_eligible(const JobDesc &d, int split) {
 // The split order in effect: the device continuation follows H_per's rule only for s_leaf <= 5
 // (its nodes have at most two children).
 static int split_in_effect(const hperm_opts &o) { return o.s_leaf <= 5 ? o.split_order : 0; }
+uint64_t split_wide_total(const std::vector<JobDesc> &desc, const hperm_opts &o) {
+    const int split = split_in_effect(o);
+    uint64_t w = 0;
+    for (const JobDesc &d : desc)
+        if (split_eligible(d, split)) w += split_wide_entries(d.m);
+    return w;
+}
+
 static void build_queue_groups(hperm_jobs *j, int split) {
     const std::vector<JobDesc> &dsc = j->tab.desc;
     const size_t nd = dsc.size();
@@ -445,7 +453,11 @@ static void build_queue_groups(hperm_jobs *j, int split) {
         q.n++;
         q.items += j->qitems[k];
         q.terms += 1ull << (d.m - 1);
-        if (raw[k] == SPLIT_G) continue;   // its work is known only after the run
+        if (raw[k] == SPLIT_G) {   // its work is known only after the run
+            q.mmax = std::max(q.mmax, (int)d.m);
+            q.wide += split_wide_entries(d.m);
+            continue;
+        }
         const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2, walk_variant(d, d.chunk_log2));
         q.mults += wk.mults;
         q.adds += wk.adds;
@@ -530,7 +542,7 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         s = ensure_buf(c, B_SPLIT, 8 * sizeof(unsigned long long));
         if (s) return s;
         const hperm_jobs::QueueGroup &last = j->qgroups.back();
-        s = ensure_buf(c, B_SPLIT_WIDE, split_wide_bytes(last.variant == kSplitVariant ? (uint32_t)last.n : 1));
+        s = ensure_buf(c, B_SPLIT_WIDE, split_wide_bytes(last.variant == kSplitVariant ? last.wide : 0));
         if (s) return s;
     }
     if (c->timed) {
@@ -600,9 +612,10 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             if (s) return s;
             if (g.variant == kSplitVariant)
                 s = hip_check(c, launch_split_w64(d_desc, d_data, (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi],
-                                                  (uint32_t)g.n, (uint32_t)nd, c->opts.split_order, c->opts.s_leaf,
-                                                  head + gi, accs, (unsigned long long *)c->buf[B_SPLIT].ptr,
-                                                  c->buf[B_SPLIT_WIDE].ptr, cyc, c->stream),
+                                                  (uint32_t)g.n, (uint32_t)nd, split_in_effect(c->opts), g.mmax,
+                                                  c->opts.s_leaf, head + gi, accs,
+                                                  (unsigned long long *)c->buf[B_SPLIT].ptr,
+                                                  c->buf[B_SPLIT_WIDE].ptr, g.wide, cyc, c->stream),
                               "device H_per launch");
             else
                 s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,
@@ -699,6 +712,7 @@ hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_resu
                 st.leaf_terms = c->split_stats[1];
                 st.splits = c->split_stats[2];
                 st.split_stops = c->split_stats[3];
+                if (c->split_stats[5]) return set_error(c, HPERM_E_INTERNAL, "device H_per: leaf records lost");
             }
         } else if (!c->launches.empty()) {
             c->launches[0].ms = ms;
@@ -843,7 +857,7 @@ static const char *check_opts(const hperm_opts *o) {
     if (o->max_table_mib < 0) return "max_table_mib must be >= 0";
     if (o->time_jobs != 0 && o->time_jobs != 1) return "time_jobs must be 0 or 1";
     if (o->split_order != 0 && (o->split_order < HP_SPLIT_MIN_T || o->split_order >= HP_SPLIT_MAX_M))
-        return "split_order must be 0 or in [7, 19]";
+        return "split_order must be 0 or in [7, 23]";
     return nullptr;
 }
 

@@ -40,6 +40,8 @@ struct hperm_jobs {
         size_t n;
         uint64_t items, terms;
         double mults, adds, updates;
+        int mmax = 0;        // device H_per group: largest job order
+        uint64_t wide = 0;   // ... and the bound on its deferred wide leaves
     };
     // the estimator's job list (jobs grouped by its order buckets, natural order inside) and
     // the bucket offsets, also filled once
@@ -77,7 +79,7 @@ struct Dev {
     bool persistent = true;
     bool timed = false;                        // per-job work cycles recorded (B_CYCLES)
     int split_launch = -1;                     // index of the device H_per launch, or -1
-    unsigned long long split_stats[5] = {0, 0, 0, 0, 0};   // its counters (B_SPLIT)
+    unsigned long long split_stats[6] = {0, 0, 0, 0, 0, 0};   // its counters (B_SPLIT)
     std::vector<JobAcc> host_acc;              // per-job accumulators (per-job results only)
     ProbAcc *host_prob = nullptr;              // pinned, per-problem accumulators
     size_t host_prob_cap = 0;
@@ -111,6 +113,9 @@ hperm_status upload_jobs(Dev *c, hperm_jobs *j);
 hperm_status estimate_jobs(Dev *c, hperm_jobs *j, int trials, uint64_t seed);
 // Launch steps 4-6 of all jobs on c->stream without waiting (results staged in c).
 hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool want_per_job);
+// Bound on the leaves above order 16 that the device continuation of H_per may defer for
+// these jobs under these options (0 when it is off).
+uint64_t split_wide_total(const std::vector<JobDesc> &desc, const hperm_opts &o);
 // Wait for c->stream and turn the staged accumulators into results.
 hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_result *totals,
                         double *t_rnw);

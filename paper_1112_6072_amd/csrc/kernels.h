@@ -70,18 +70,22 @@ hipError_t persistent_grid(int ring, int bucket, int variant, int *grid);
 // Device continuation of H_per (split.hip): mod-2^64 jobs of order HP_SPLIT_MIN_T + 1 ..
 // HP_SPLIT_MAX_M are split on the device down to order t (HP_SPLIT_MIN_T <= t < HP_SPLIT_MAX_M)
 // and their leaves evaluated; each job's value lands in accs[job].l[0] as for the R-NW
-// kernels. queue[0..n) lists the jobs (indices < njobs); head is a cleared counter;
-// stats[0..5) (cleared by the caller) receive leaves, leaf subset-terms, splits, splits refused
-// by the entry bounds and the wide leaves deferred to the second kernel; wide is a buffer of
-// split_wide_bytes(n) bytes; cycles (nullable) receives each job's shader-clock cycles (first
-// kernel only). Two launches on stream s.
-constexpr int HP_SPLIT_MAX_M = 20;
+// kernels. queue[0..n) lists the jobs (indices < njobs), mm is their largest order (> t);
+// head is a cleared counter; stats[0..6) (cleared by the caller) receive leaves, leaf
+// subset-terms, splits, splits refused by the entry bounds, the wide leaves deferred to the
+// second kernel, and deferred leaves that found the record buffer full (0 when the buffer holds
+// split_wide_entries summed over the jobs); wide is a buffer of split_wide_bytes(entries)
+// bytes; cycles (nullable) receives each job's shader-clock cycles (first kernel only). Two
+// launches on stream s.
+constexpr int HP_SPLIT_MAX_M = 24;
 constexpr int HP_SPLIT_MIN_T = 7;
-size_t split_lds_bytes(int t);
-size_t split_wide_bytes(uint32_t n);
+// Most leaves above order 16 a job of order m can defer: the nodes of orders 17..m.
+inline uint64_t split_wide_entries(int m) { return m > 16 ? (1ull << (m - 16)) - 1 : 0; }
+size_t split_lds_bytes(int t, int mm);
+size_t split_wide_bytes(uint64_t entries);
 hipError_t launch_split_w64(const JobDesc *jobs, const uint32_t *data, const uint32_t *queue, uint32_t n,
-                            uint32_t njobs, int t, int s_leaf, unsigned long long *head, JobAcc *accs,
-                            unsigned long long *stats, void *wide, unsigned long long *cycles,
-                            hipStream_t s);
+                            uint32_t njobs, int t, int mm, int s_leaf, unsigned long long *head, JobAcc *accs,
+                            unsigned long long *stats, void *wide, uint64_t wide_entries,
+                            unsigned long long *cycles, hipStream_t s);
 
 }  // namespace hp

@@ -31,6 +31,7 @@ struct Request {
     bool cancelled = false;
     hperm_jobs jobs;
     size_t bytes = 0;   // device bytes of this request's share of a batch
+    uint64_t wide = 0;  // bound on its deferred wide leaves (device H_per)
     hperm_result result{};
     hperm_status status = HPERM_OK;
     std::string err;
@@ -48,13 +49,13 @@ struct Batch {
 
 // Device bytes of one batch part: the buffers of the pipeline for nd jobs, `words` data words
 // and np problems, each buffer rounded up to 256 bytes (with split_order, also the device
-// H_per counters and its record buffer for the leaves above order 16).
-size_t part_bytes(size_t nd, size_t words, size_t np, bool split) {
+// H_per counters and its record buffer for `wide` leaves above order 16).
+size_t part_bytes(size_t nd, size_t words, size_t np, bool split, uint64_t wide) {
     auto al = [](size_t x) { return (std::max<size_t>(x, 1) + 255) / 256 * 256; };
     size_t b = al(nd * sizeof(JobDesc)) + al((words + 64) * 4) + al(nd * 4) /*keys*/ + al(nd * 4) /*list*/ +
                al(nd * 4) /*queue*/ + al(nd * 8) /*items*/ + al(nd * sizeof(JobAcc)) + al(64 * 8) /*heads*/ +
                al(np * sizeof(ProbAcc)) + 2048;
-    if (split) b += al(8 * 8) + al(split_wide_bytes((uint32_t)std::max<size_t>(nd, 1)));
+    if (split) b += al(8 * 8) + al(split_wide_bytes(wide));
     return b;
 }
 
@@ -144,7 +145,9 @@ struct Serving {
                 r->t_done = now_s();
             } else {
                 const auto &t = r->jobs.tab;
-                r->bytes = part_bytes(t.desc.size(), t.data.size(), 1, ctx->opts.split_order != 0 && ctx->opts.s_leaf <= 5);
+                r->wide = split_wide_total(t.desc, ctx->opts);
+                r->bytes = part_bytes(t.desc.size(), t.data.size(), 1, ctx->opts.split_order != 0 && ctx->opts.s_leaf <= 5,
+                                      r->wide);
                 if (r->bytes > arena_bytes) {
                     r->status = HPERM_E_NOMEM;
                     r->err = "request needs " + std::to_string(r->bytes) + " device bytes; the serving arena holds " +
@@ -174,17 +177,19 @@ struct Serving {
                 if (stopping) break;
                 // take the oldest ready requests while the batch fits a free arena slice
                 size_t need = 0, nd = 0, words = 0;
+                uint64_t wide = 0;
                 std::vector<Request *> take;
                 size_t largest = 0;
                 for (auto &f : free_list) largest = std::max(largest, f.second);
                 for (Request *r : ready) {
                     const auto &t = r->jobs.tab;
                     const size_t cand = part_bytes(nd + t.desc.size(), words + t.data.size(), take.size() + 1,
-                                                   ctx->opts.split_order != 0 && ctx->opts.s_leaf <= 5);
+                                                   ctx->opts.split_order != 0 && ctx->opts.s_leaf <= 5, wide + r->wide);
                     if (cand > largest) break;
                     take.push_back(r);
                     nd += t.desc.size();
                     words += t.data.size();
+                    wide += r->wide;
                     need = cand;
                 }
                 if (take.empty()) continue;

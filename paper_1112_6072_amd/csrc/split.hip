@@ -42,22 +42,22 @@ namespace {
 
 constexpr int SW = 64;                   // one wave per block
 constexpr int SMAX = HP_SPLIT_MAX_M;     // largest job order
-constexpr int DSTRIDE = 20;              // words per Gray column in a leaf's delta table
 constexpr int CTL = 12;                  // control words per order
-constexpr int META = 60;                 // per order: row masks, column masks, row sums (20 each)
 constexpr int PMAX = 16;                 // widest leaf the main kernel evaluates
+// Words per Gray column of a leaf's delta table (every row; a multiple of 4 for the 16-byte
+// loads), for jobs of order <= mm.
+__host__ __device__ constexpr int dstride(int mm) { return mm <= 20 ? 20 : 24; }
+static_assert(dstride(SMAX) >= SMAX && dstride(SMAX) % 4 == 0, "a delta-table column holds every row");
 
-// LDS words of the node slots of orders o + 1 .. SMAX (the slot of order o starts there).
-__host__ __device__ constexpr int slot_off(int o) {
-    return (SMAX * (SMAX + 1) * (2 * SMAX + 1) - o * (o + 1) * (2 * o + 1)) / 6;
-}
+// Squares 1 + 4 + ... + x^2: the node slots of orders o + 1 .. mm take sq(mm) - sq(o) words.
+__host__ __device__ constexpr int sq(int x) { return x * (x + 1) * (2 * x + 1) / 6; }
 __host__ __device__ constexpr int align4(int w) { return (w + 3) & ~3; }
-// Per-wave region for target order t: slots of orders t..SMAX, the leaf's delta table and
-// base values, and per order t..SMAX the control words, masks and row sums.
-__host__ __device__ constexpr int region_words(int t) {
-    return align4(slot_off(t - 1)) + SMAX * DSTRIDE + SMAX + (SMAX + 1 - t) * (CTL + META);
+// Per-wave region for target order t and largest job order mm: slots of orders t..mm (order
+// mm first), the leaf's delta table (mm - 1 columns) and base values, and per order t..mm the
+// control words and the row masks, column masks and row sums (mm words each).
+__host__ __device__ constexpr int region_words(int t, int mm) {
+    return align4(sq(mm) - sq(t - 1)) + mm * dstride(mm) + (mm + 1 - t) * (CTL + 3 * mm);
 }
-static_assert(align4(SMAX * DSTRIDE + SMAX) == SMAX * DSTRIDE + SMAX, "16-byte alignment of the tables");
 
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ uint64_t uni64(uint64_t x) {
@@ -125,7 +125,7 @@ __device__ __forceinline__ void add_rows(int32_t (&f)[R], const int32_t *d, bool
 // Row values of this lane's first Gray index (no Gray column below p - 7 is set in it).
 template <int R>
 __device__ __forceinline__ void start_rows(int32_t (&f)[R], int p, int lane, const int32_t *D,
-                                           const int32_t *base) {
+                                           const int32_t *base, int ds) {
     const int c = p - 7;
     const uint32_t L = 1u << c;
     const uint32_t kfirst = (lane & 1) ? (uint32_t)lane * L + L - 1 : (uint32_t)lane * L;
@@ -140,7 +140,7 @@ __device__ __forceinline__ void start_rows(int32_t (&f)[R], int p, int lane, con
     }
     for (int j = c; j < p - 1; ++j) {
         const bool in = (s0 >> j) & 1;
-        const int32_t *dj = D + j * DSTRIDE;
+        const int32_t *dj = D + j * ds;
 #pragma unroll
         for (int i = 0; i < R; ++i) f[i] += in ? dj[i] : 0;
     }
@@ -148,10 +148,10 @@ __device__ __forceinline__ void start_rows(int32_t (&f)[R], int p, int lane, con
 
 // This lane's share of V for a leaf of order p (7 <= p <= R): one term per step.
 template <int R>
-__device__ __forceinline__ uint64_t walk_plain(int p, int lane, const int32_t *D, const int32_t *base) {
+__device__ __forceinline__ uint64_t walk_plain(int p, int lane, const int32_t *D, const int32_t *base, int ds) {
     const uint32_t L = 1u << (p - 7);
     int32_t f[R];
-    start_rows<R>(f, p, lane, D, base);
+    start_rows<R>(f, p, lane, D, base, ds);
     uint64_t acc0 = row_product<R>(f), acc1 = 0;
     for (uint32_t s = 1; s < L; s += 2) {
         add_rows<R>(f, D, ((s >> 1) & 1) == 0);   // odd steps flip Gray column 0
@@ -159,7 +159,7 @@ __device__ __forceinline__ uint64_t walk_plain(int p, int lane, const int32_t *D
         if (s + 1 < L) {
             const uint32_t s2 = s + 1;
             const int j = __builtin_ctz(s2);
-            add_rows<R>(f, D + j * DSTRIDE, ((s2 >> (j + 1)) & 1) == 0);
+            add_rows<R>(f, D + j * ds, ((s2 >> (j + 1)) & 1) == 0);
             acc0 += row_product<R>(f);
         }
     }
@@ -171,10 +171,10 @@ __device__ __forceinline__ uint64_t walk_plain(int p, int lane, const int32_t *D
 // B*P with P the product of rows BB..R-1 and A, B the products of rows 0..BB-1 before and after
 // the flip: each pair costs one product of the other rows and one of the small block twice.
 template <int R, int BB>
-__device__ __forceinline__ uint64_t walk_paired(int p, int lane, const int32_t *D, const int32_t *base) {
+__device__ __forceinline__ uint64_t walk_paired(int p, int lane, const int32_t *D, const int32_t *base, int ds) {
     const uint32_t L = 1u << (p - 7);
     int32_t f[R];
-    start_rows<R>(f, p, lane, D, base);
+    start_rows<R>(f, p, lane, D, base, ds);
     int32_t d0[BB];
 #pragma unroll
     for (int i = 0; i < BB; ++i) d0[i] = D[i];
@@ -182,7 +182,7 @@ __device__ __forceinline__ uint64_t walk_paired(int p, int lane, const int32_t *
     for (uint32_t s = 0; s < L; s += 2) {
         if (s) {   // step s flips Gray column ctz(s) >= 1
             const int j = __builtin_ctz(s);
-            add_rows<R>(f, D + j * DSTRIDE, ((s >> (j + 1)) & 1) == 0);
+            add_rows<R>(f, D + j * ds, ((s >> (j + 1)) & 1) == 0);
         }
         const bool add0 = (((s + 1) >> 1) & 1) == 0;   // step s + 1 adds Gray column 0
         int32_t g[BB];
@@ -212,17 +212,19 @@ struct Region {
     uint32_t *lds;
     int32_t *D, *base;
     uint32_t *ctl_all, *meta_all;   // indexed by order - t
-    __device__ Region(uint32_t *l, int t) : lds(l) {
-        D = (int32_t *)(l + align4(slot_off(t - 1)));
-        base = D + SMAX * DSTRIDE;
-        ctl_all = (uint32_t *)(base + SMAX) - t * CTL;
-        meta_all = (uint32_t *)(base + SMAX) + (SMAX + 1 - t) * CTL - t * META;
+    int top;                        // sq of the largest job order
+    int ds, mw;                     // delta-table stride; words per mask array (= mm)
+    __device__ Region(uint32_t *l, int t, int mm) : lds(l), top(sq(mm)), ds(dstride(mm)), mw(mm) {
+        D = (int32_t *)(l + align4(sq(mm) - sq(t - 1)));
+        base = D + (mm - 1) * ds;
+        ctl_all = (uint32_t *)(base + ds) - t * CTL;
+        meta_all = (uint32_t *)(base + ds) + (mm + 1 - t) * CTL - t * 3 * mm;
     }
-    __device__ uint32_t *slot(int o) const { return lds + slot_off(o); }
+    __device__ uint32_t *slot(int o) const { return lds + (top - sq(o)); }
     __device__ uint32_t *ctl(int o) const { return ctl_all + o * CTL; }
-    __device__ uint32_t *rmask(int o) const { return meta_all + o * META; }
-    __device__ uint32_t *cmask(int o) const { return meta_all + o * META + 20; }
-    __device__ uint32_t *rsum(int o) const { return meta_all + o * META + 40; }
+    __device__ uint32_t *rmask(int o) const { return meta_all + o * 3 * mw; }
+    __device__ uint32_t *cmask(int o) const { return meta_all + o * 3 * mw + mw; }
+    __device__ uint32_t *rsum(int o) const { return meta_all + o * 3 * mw + 2 * mw; }
 };
 
 struct SplitCtl {   // word offsets in a control block
@@ -238,7 +240,7 @@ __device__ __forceinline__ int load_job(const Region &rg, const JobDesc *jobs, c
     const uint32_t *blk = data + (size_t)uni(jd.data_off) * HP_DATA_ALIGN;
     uint32_t *M = rg.slot(m);
     for (int e = lane; e < m * m; e += SW) M[e] = 0;
-    if (lane < 20) {
+    if (lane < rg.mw) {
         rg.rmask(m)[lane] = 0;
         rg.cmask(m)[lane] = 0;
         rg.rsum(m)[lane] = 0;
@@ -378,7 +380,8 @@ __device__ __forceinline__ bool plan_split(const Region &rg, int o, uint32_t key
 }
 
 // Child `ch` of the node of order o (split by plan pl) into slot o - 1 with its masks and row
-// sums. Lanes cover three child rows per pass (lane = 21 * r + column).
+// sums. Lanes cover three child rows per pass (lane = 21 * r + column) while a row has at most
+// 21 columns, else two (lane = 32 * r + column).
 __device__ __forceinline__ void make_child(const Region &rg, int o, const Plan &pl, int ch, int lane) {
     const uint32_t *M = rg.slot(o);
     uint32_t *C = rg.slot(o - 1);
@@ -387,11 +390,14 @@ __device__ __forceinline__ void make_child(const Region &rg, int o, const Plan &
     const uint32_t ca = ch ? pl.ca[1] : pl.ca[0], cb = ch ? pl.cb[1] : pl.cb[0];
     const uint32_t keep = min(P, Q), drop = max(P, Q);
     const uint32_t co = (uint32_t)o - 1;
-    const uint32_t r3 = (uint32_t)lane / 21, jp = (uint32_t)lane - 21 * r3;
+    const bool three = co <= 21;
+    const uint32_t rw = three ? 21u : 32u, nr = three ? 3u : 2u;
+    const uint32_t r3 = three ? (uint32_t)lane / 21 : (uint32_t)lane >> 5, jp = (uint32_t)lane - rw * r3;
+    const uint32_t rmk = three ? (1u << 21) - 1 : 0xffffffffu;
     uint32_t cm = 0;
-    for (uint32_t ip0 = 0; ip0 < co; ip0 += 3) {
+    for (uint32_t ip0 = 0; ip0 < co; ip0 += nr) {
         const uint32_t ip = ip0 + r3;
-        const bool ok = r3 < 3 && ip < co && jp < co;
+        const bool ok = r3 < nr && ip < co && jp < co;
         uint32_t v = 0;
         if (ok) {
             if (!is_col) {   // row `line` deleted, columns P, Q merged at min(P, Q)
@@ -405,9 +411,10 @@ __device__ __forceinline__ void make_child(const Region &rg, int o, const Plan &
             cm |= (uint32_t)(v != 0) << ip;
         }
         const uint64_t bal = __ballot(v != 0);
-        if (ok && jp == 0) rg.rmask(o - 1)[ip] = (uint32_t)(bal >> (21 * r3)) & ((1u << 21) - 1);
+        if (ok && jp == 0) rg.rmask(o - 1)[ip] = (uint32_t)(bal >> (rw * r3)) & rmk;
     }
-    cm |= (uint32_t)__shfl((int)cm, lane + 21) | (uint32_t)__shfl((int)cm, lane + 42);
+    if (three) cm |= (uint32_t)__shfl((int)cm, lane + 21) | (uint32_t)__shfl((int)cm, lane + 42);
+    else cm |= (uint32_t)__shfl((int)cm, lane + 32);
     if ((uint32_t)lane < co) {   // row sums from the parent's
         const uint32_t ip = (uint32_t)lane;
         uint32_t rs;
@@ -439,18 +446,19 @@ __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, int lan
     const uint32_t c0 = argmin_lane((uint32_t)__popc(cmk), lane < p - 1, &b);
     const uint32_t touched = (uint32_t)__builtin_amdgcn_readlane((int)cmk, (int)c0);
     const uint32_t rows = (1u << p) - 1;
-    for (int e = lane; e < (p - 1) * DSTRIDE; e += SW) {
-        const int j = e / DSTRIDE, i = e - j * DSTRIDE;
+    const int ds = rg.ds;
+    for (int e = lane; e < (p - 1) * ds; e += SW) {
+        const int j = e / ds, i = e - j * ds;
         if (i < p) {
             const uint32_t below = (1u << i) - 1;
             const int pos = ((touched >> i) & 1) ? __popc(touched & below) : (int)b + __popc(~touched & rows & below);
             const int g = j == 0 ? (int)c0 : (j == (int)c0 ? 0 : j);
-            rg.D[j * DSTRIDE + pos] = 2 * (int32_t)M[i * p + g];
+            rg.D[j * ds + pos] = 2 * (int32_t)M[i * p + g];
         } else {
             rg.D[e] = 0;
         }
     }
-    if (lane < DSTRIDE) {
+    if (lane < ds) {
         if (lane < p) {
             const uint32_t below = (1u << lane) - 1;
             const int pos = ((touched >> lane) & 1) ? __popc(touched & below) : (int)b + __popc(~touched & rows & below);
@@ -467,12 +475,12 @@ __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, int lan
 __device__ __forceinline__ uint64_t eval_leaf(const Region &rg, int p, int lane) {
     const uint32_t b = leaf_tables(rg, p, lane);
     uint64_t v;
-    if (p >= 8 && p <= 12 && b <= 2) v = walk_paired<12, 2>(p, lane, rg.D, rg.base);
-    else if (p >= 8 && p <= 12 && b <= 4) v = walk_paired<12, 4>(p, lane, rg.D, rg.base);
-    else if (p <= 12) v = walk_plain<12>(p, lane, rg.D, rg.base);
-    else if (b <= 2) v = walk_paired<16, 2>(p, lane, rg.D, rg.base);
-    else if (b <= 4) v = walk_paired<16, 4>(p, lane, rg.D, rg.base);
-    else v = walk_plain<16>(p, lane, rg.D, rg.base);
+    if (p >= 8 && p <= 12 && b <= 2) v = walk_paired<12, 2>(p, lane, rg.D, rg.base, rg.ds);
+    else if (p >= 8 && p <= 12 && b <= 4) v = walk_paired<12, 4>(p, lane, rg.D, rg.base, rg.ds);
+    else if (p <= 12) v = walk_plain<12>(p, lane, rg.D, rg.base, rg.ds);
+    else if (b <= 2) v = walk_paired<16, 2>(p, lane, rg.D, rg.base, rg.ds);
+    else if (b <= 4) v = walk_paired<16, 4>(p, lane, rg.D, rg.base, rg.ds);
+    else v = walk_plain<16>(p, lane, rg.D, rg.base, rg.ds);
     wave_sync();   // the tables are rewritten by the next leaf
     return v;
 }
@@ -484,7 +492,8 @@ __device__ __forceinline__ uint64_t scale_to_job(uint64_t v, int m, int p) {
 }
 
 // A deferred wide leaf: the job, the leaf's order and the child index taken at every order
-// above it (bit m - o for the split at order o).
+// above it (bit m - o for the split at order o). A job of order m can defer at most
+// 2^(m-16) - 1 of them (the nodes of orders 17..m, at most two children per split).
 struct WideLeaf {
     uint32_t job;
     uint32_t order_path;   // order | path << 8
@@ -497,10 +506,10 @@ __global__ __launch_bounds__(SW) void hper_split_w64(const JobDesc *__restrict__
                                                      JobAcc *__restrict__ accs,
                                                      unsigned long long *__restrict__ stats,
                                                      WideLeaf *__restrict__ wide, uint32_t wide_cap,
-                                                     unsigned long long *__restrict__ cycles) {
+                                                     unsigned long long *__restrict__ cycles, int mm) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    const Region rg(lds, t);
+    const Region rg(lds, t, mm);
     uint64_t n_leaves = 0, n_terms = 0, n_splits = 0, n_stops = 0;
     for (;;) {
         const unsigned long long got = atomicAdd(head, lane == 0 ? 1ull : 0ull);
@@ -540,6 +549,7 @@ __global__ __launch_bounds__(SW) void hper_split_w64(const JobDesc *__restrict__
                     if (lane == 0) {
                         const unsigned long long w = atomicAdd(stats + 4, 1ull);
                         if (w < wide_cap) wide[w] = WideLeaf{job, (uint32_t)o | (path << 8)};
+                        else atomicAdd(stats + 5, 1ull);   // never: the buffer holds the bound
                     }
                 }
             }
@@ -577,10 +587,10 @@ __global__ __launch_bounds__(SW) void hper_split_wide_w64(const JobDesc *__restr
                                                           const uint32_t *__restrict__ data, int t,
                                                           const unsigned long long *__restrict__ stats,
                                                           const WideLeaf *__restrict__ wide, uint32_t wide_cap,
-                                                          uint32_t njobs, JobAcc *__restrict__ accs) {
+                                                          uint32_t njobs, JobAcc *__restrict__ accs, int mm) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    const Region rg(lds, t);
+    const Region rg(lds, t, mm);
     const uint64_t n = min((uint64_t)stats[4], (uint64_t)wide_cap);
     for (uint64_t w = blockIdx.x; w < n; w += gridDim.x) {
         const WideLeaf wl = wide[w];
@@ -589,15 +599,20 @@ __global__ __launch_bounds__(SW) void hper_split_wide_w64(const JobDesc *__restr
         const uint32_t path = op >> 8;
         if (job >= njobs) continue;
         const int m0 = load_job(rg, jobs, data, job, lane);
-        if (p < HP_SPLIT_MIN_T || p > m0) continue;
+        if (p < HP_SPLIT_MIN_T || p > m0 || m0 > mm) continue;
         Plan pl;
         for (int o = m0; o > p; --o) {
             if (!plan_split(rg, o, sparsest_line(rg, o, lane), lane, pl)) break;   // not reached: the
             make_child(rg, o, pl, (int)((path >> (m0 - o)) & 1), lane);           // first pass split here
         }
         const uint32_t b = leaf_tables(rg, p, lane);
-        const uint64_t v = b <= 4 && p >= 8 ? walk_paired<SMAX, 4>(p, lane, rg.D, rg.base)
-                                            : walk_plain<SMAX>(p, lane, rg.D, rg.base);
+        uint64_t v;   // rows padded to the table's stride (20 or 24), never beyond it
+        if (rg.ds == 20)
+            v = b <= 4 && p >= 8 ? walk_paired<20, 4>(p, lane, rg.D, rg.base, rg.ds)
+                                 : walk_plain<20>(p, lane, rg.D, rg.base, rg.ds);
+        else
+            v = b <= 4 && p >= 8 ? walk_paired<SMAX, 4>(p, lane, rg.D, rg.base, rg.ds)
+                                 : walk_plain<SMAX>(p, lane, rg.D, rg.base, rg.ds);
         const uint64_t total = wave_sum64(scale_to_job(v, m0, p));
         if (lane == 0) atomicAdd(&accs[job].l[0], (unsigned long long)total);
     }
@@ -605,8 +620,8 @@ __global__ __launch_bounds__(SW) void hper_split_wide_w64(const JobDesc *__restr
 
 }  // namespace
 
-size_t split_lds_bytes(int t) { return (size_t)region_words(t) * sizeof(uint32_t); }
-size_t split_wide_bytes(uint32_t n) { return (size_t)n * 15 * sizeof(WideLeaf); }
+size_t split_lds_bytes(int t, int mm) { return (size_t)region_words(t, mm) * sizeof(uint32_t); }
+size_t split_wide_bytes(uint64_t entries) { return (size_t)(entries ? entries : 1) * sizeof(WideLeaf); }
 
 static hipError_t resident_grid(const void *fn, size_t lds, uint64_t *grid) {
     int dev = 0, cus = 0, per_cu = 0;
@@ -621,25 +636,25 @@ static hipError_t resident_grid(const void *fn, size_t lds, uint64_t *grid) {
 }
 
 hipError_t launch_split_w64(const JobDesc *jobs, const uint32_t *data, const uint32_t *queue, uint32_t n,
-                            uint32_t njobs, int t, int s_leaf, unsigned long long *head, JobAcc *accs,
-                            unsigned long long *stats, void *wide, unsigned long long *cycles,
-                            hipStream_t s) {
+                            uint32_t njobs, int t, int mm, int s_leaf, unsigned long long *head, JobAcc *accs,
+                            unsigned long long *stats, void *wide, uint64_t wide_entries,
+                            unsigned long long *cycles, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    if (t < HP_SPLIT_MIN_T || t >= HP_SPLIT_MAX_M) return hipErrorInvalidValue;
-    const size_t lds = split_lds_bytes(t);
-    const uint32_t cap = n * 15;   // at most 1 + 2 + 4 + 8 nodes of orders 17..20 per job
+    if (t < HP_SPLIT_MIN_T || t >= HP_SPLIT_MAX_M || mm <= t || mm > HP_SPLIT_MAX_M) return hipErrorInvalidValue;
+    const size_t lds = split_lds_bytes(t, mm);
+    const uint32_t cap = (uint32_t)(wide_entries < 0xffffffffull ? wide_entries : 0xffffffffull);
     uint64_t grid = 0;
     hipError_t e = resident_grid((const void *)hper_split_w64, lds, &grid);
     if (e != hipSuccess) return e;
     if (grid > n) grid = n;
     hipLaunchKernelGGL(hper_split_w64, dim3((uint32_t)grid), dim3(SW), lds, s, jobs, data, queue, n, t, s_leaf,
-                       head, accs, stats, (WideLeaf *)wide, cap, cycles);
+                       head, accs, stats, (WideLeaf *)wide, cap, cycles, mm);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = resident_grid((const void *)hper_split_wide_w64, lds, &grid);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(hper_split_wide_w64, dim3((uint32_t)grid), dim3(SW), lds, s, jobs, data, t,
-                       (const unsigned long long *)stats, (const WideLeaf *)wide, cap, njobs, accs);
+                       (const unsigned long long *)stats, (const WideLeaf *)wide, cap, njobs, accs, mm);
     return hipGetLastError();
 }
 

@@ -215,3 +215,45 @@ def test_split_extremes(hperm, ctx):
     finally:
         ctx.set_opts(split_order=0)
     assert per_job == native.ryser_batch(job_mats(small), threads=8)
+
+
+def test_split_from_order_24(hperm, ctx):
+    """Jobs of order 21..24 split on the device: ten cubic graphs on 24 vertices, each a single
+    job (m_cut 24), and the benchmark's graphs expanded by the host only down to order 24;
+    per-job values and the traversal against the oracle's, totals against the stored values."""
+    mats = W.config_n24()
+    say("split from 24: n24 single jobs")
+    ctx.set_opts(m_cut=24, split_order=12)
+    try:
+        J = ctx.expand(mats)
+        totals, per_job, _ = ctx.run(J, "natural", True, per_job=True)
+        st = split_launch(ctx)
+    finally:
+        ctx.set_opts(m_cut=20, split_order=0)
+    stored = job_mats(J)
+    assert sorted(len(B) for B in stored)[-1] == 24
+    assert totals == [int(GOLDEN[f"cubic24_seed{s}"]) for s in range(10)]
+    assert per_job == native.ryser_batch(stored, threads=8)
+    eligible = [B for B, a in zip(stored, J.describe()["arith"]) if a == 1 and 12 < len(B) <= 24]
+    assert st["n_jobs"] == len(eligible)
+    assert (st["leaves"], st["leaf_terms"]) == oracle_traversal(eligible, 12)
+    mixed = [W.permutation_union_matrix(m, 3, 70 + m, 1, 1) for m in (21, 22, 23, 24)]   # 0-1: mod 2^64
+    J2 = ctx.jobs_from_dense(mixed)
+    ctx.set_opts(split_order=14)
+    try:
+        _, pj2, _ = ctx.run(J2, "natural", True, per_job=True)
+        st2 = split_launch(ctx)
+    finally:
+        ctx.set_opts(split_order=0)
+    stored2 = job_mats(J2)
+    assert pj2 == native.ryser_batch(stored2, threads=8)
+    el2 = [B for B, a in zip(stored2, J2.describe()["arith"]) if a == 1 and 14 < len(B) <= 24]
+    assert (st2["leaves"], st2["leaf_terms"]) == oracle_traversal(el2, 14)
+    items = W.config_n60(16)
+    say("split from 24: n60")
+    ctx.set_opts(m_cut=24, split_order=12)
+    try:
+        got = ctx.permanent_batch([A for _, A in items])
+    finally:
+        ctx.set_opts(m_cut=20, split_order=0)
+    assert got == [int(GOLDEN[name]) for name, _ in items]

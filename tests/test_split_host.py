@@ -15,12 +15,12 @@ def hp():
 
 def test_split_order_checked(hp):
     c = hp.Context(host_only=True)
-    for bad in (-1, 1, 6, 20, 40):
+    for bad in (-1, 1, 6, 24, 40):
         with pytest.raises(hp.HpermError):
             c.set_opts(split_order=bad)
     c.set_opts(split_order=12, s_leaf=6)   # accepted; the device continuation is then off
     c.set_opts(s_leaf=5)
-    for good in (0, 7, 12, 19):
+    for good in (0, 7, 12, 19, 23):
         c.set_opts(split_order=good)
     assert hp.Context(host_only=True)._opts.split_order == 12   # the default
 
