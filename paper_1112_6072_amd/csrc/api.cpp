@@ -395,7 +395,7 @@ static hperm_status ensure_launch_events(Dev *c, size_t pairs) {
 // g = (order bucket, ring, walk variant) from the largest bucket and the widest ring down. The
 // order-20 bucket exists for the many jobs of the default cut-off; when a (ring, walk) group of
 // it is small, its jobs join the order-24 group instead (whose kernel takes them too), saving
-// a launch and its drain tail. With split_order t > 0 the mod-2^64 jobs of order t+1..20 form
+// a launch and its drain tail. With split_order t > 0 the mod-2^64 jobs of order t+1..24 form
 // one more group, last, for the device continuation of H_per (variant 3, one item per job).
 static constexpr int kSplitVariant = 3;
 static bool split_eligible(const JobDesc &d, int split) {
