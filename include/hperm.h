@@ -220,7 +220,8 @@ hperm_status hperm_jobs_describe(const hperm_jobs *jobs, int32_t *m, int32_t *pr
 /* The sub-matrix of job `job` as the kernels hold it, row-major m x m into a[m*m] (m from
  * hperm_jobs_describe): rows in the job's order, Gray columns 0..m-2, then the fixed column.
  * It is a row and column permutation of the expansion's sub-matrix or of its transpose (the
- * same permanent). Host only. */
+ * same permanent). Host only; the caller owns a. HPERM_E_INVALID for a null pointer or a job
+ * index out of range. */
 hperm_status hperm_jobs_matrix(const hperm_jobs *jobs, int32_t job, uint32_t *a);
 
 /* KKLLL estimates of every job's pattern (step 3): trials per job and seed as given.
@@ -313,7 +314,8 @@ typedef struct hperm_launch_stat {
     int32_t n_jobs;         /* jobs in the launch (1 in one-launch-per-job mode) */
     int32_t persistent;
     int32_t variant;        /* walk variant: 0, or 1 / 2 for the paired walk of jobs whose
-                               Gray column 0 reaches only the first 2 / 3 rows */
+                               Gray column 0 reaches only the first 2 / 3 rows; 3 for the
+                               device continuation of H_per (split_order) */
     int32_t reserved;
     uint64_t items;         /* work items (64 lanes x 2^chunk Gray indices each) */
     uint64_t terms;         /* subset-terms: sum of 2^(m-1) over the jobs */
