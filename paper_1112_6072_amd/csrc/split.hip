@@ -56,7 +56,7 @@ __host__ __device__ constexpr int align4(int w) { return (w + 3) & ~3; }
 // mm first), the leaf's delta table (mm - 1 columns) and base values, and per order t..mm the
 // control words and the row masks, column masks and row sums (mm words each).
 __host__ __device__ constexpr int region_words(int t, int mm) {
-    return align4(sq(mm) - sq(t - 1)) + mm * dstride(mm) + (mm + 1 - t) * (CTL + 3 * mm);
+    return align4(sq(mm) - sq(t - 1)) + mm * dstride(mm) + (mm + 1 - t) * (CTL + 3 * mm) + SW;
 }
 
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -214,11 +214,13 @@ struct Region {
     uint32_t *ctl_all, *meta_all;   // indexed by order - t
     int top;                        // sq of the largest job order
     int ds, mw;                     // delta-table stride; words per mask array (= mm)
+    uint32_t *dummy;                // one word per lane: the target of idle lanes' stores
     __device__ Region(uint32_t *l, int t, int mm) : lds(l), top(sq(mm)), ds(dstride(mm)), mw(mm) {
         D = (int32_t *)(l + align4(sq(mm) - sq(t - 1)));
         base = D + (mm - 1) * ds;
         ctl_all = (uint32_t *)(base + ds) - t * CTL;
         meta_all = (uint32_t *)(base + ds) + (mm + 1 - t) * CTL - t * 3 * mm;
+        dummy = meta_all + (mm + 1) * 3 * mm;
     }
     __device__ uint32_t *slot(int o) const { return lds + (top - sq(o)); }
     __device__ uint32_t *ctl(int o) const { return ctl_all + o * CTL; }
@@ -395,23 +397,30 @@ __device__ __forceinline__ void make_child(const Region &rg, int o, const Plan &
     const uint32_t r3 = three ? (uint32_t)lane / 21 : (uint32_t)lane >> 5, jp = (uint32_t)lane - rw * r3;
     const uint32_t rmk = three ? (1u << 21) - 1 : 0xffffffffu;
     uint32_t cm = 0;
-    for (uint32_t ip0 = 0; ip0 < co; ip0 += nr) {
-        const uint32_t ip = ip0 + r3;
+    uint32_t *const dummy = rg.dummy + lane;
+    for (uint32_t ip0 = 0; ip0 < co; ip0 += nr) {   // branch-free: idle lanes read a valid entry
+        const uint32_t ip = ip0 + r3;                // and store to their dummy word
         const bool ok = r3 < nr && ip < co && jp < co;
-        uint32_t v = 0;
-        if (ok) {
-            if (!is_col) {   // row `line` deleted, columns P, Q merged at min(P, Q)
-                const uint32_t i = ip + (ip >= line), j = jp + (jp >= drop);
-                v = j == keep ? ca * M[i * o + Q] + cb * M[i * o + P] : M[i * o + j];
-            } else {         // column `line` deleted, rows P, Q merged at min(P, Q)
-                const uint32_t i = ip + (ip >= drop), j = jp + (jp >= line);
-                v = i == keep ? ca * M[Q * o + j] + cb * M[P * o + j] : M[i * o + j];
-            }
-            C[ip * co + jp] = v;
-            cm |= (uint32_t)(v != 0) << ip;
+        const uint32_t ipc = ok ? ip : 0, jpc = ok ? jp : 0;
+        uint32_t x, y, merged;
+        bool at_merge;
+        if (!is_col) {   // row `line` deleted, columns P, Q merged at keep = min(P, Q)
+            const uint32_t i = ipc + (ipc >= line), j = jpc + (jpc >= drop);
+            x = M[i * o + j];      // at j == keep: the entry of column keep
+            y = M[i * o + drop];   // the entry of column drop (the pair's other column)
+            at_merge = j == keep;
+        } else {         // column `line` deleted, rows P, Q merged at keep = min(P, Q)
+            const uint32_t i = ipc + (ipc >= drop), j = jpc + (jpc >= line);
+            x = M[i * o + j];
+            y = M[drop * o + j];
+            at_merge = i == keep;
         }
+        merged = keep == P ? ca * y + cb * x : ca * x + cb * y;   // ca * (entry at Q) + cb * (entry at P)
+        const uint32_t v = ok ? (at_merge ? merged : x) : 0u;
+        *(ok ? C + ip * co + jp : dummy) = v;
+        cm |= v ? 1u << ipc : 0u;
         const uint64_t bal = __ballot(v != 0);
-        if (ok && jp == 0) rg.rmask(o - 1)[ip] = (uint32_t)(bal >> (rw * r3)) & rmk;
+        *(ok && jp == 0 ? rg.rmask(o - 1) + ip : dummy) = (uint32_t)(bal >> (rw * r3)) & rmk;
     }
     if (three) cm |= (uint32_t)__shfl((int)cm, lane + 21) | (uint32_t)__shfl((int)cm, lane + 42);
     else cm |= (uint32_t)__shfl((int)cm, lane + 32);
