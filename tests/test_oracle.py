@@ -256,3 +256,113 @@ def test_kkl_single_permutation_gives_one():
     for t in range(5):
         u = np.random.default_rng(t).integers(0, 3, size=(9, 9))
         assert abs(kkl_trial(A, u) - 1.0) < 1e-12
+
+
+# --------------------------------------------------------------------------- jobs of PH (expand_leaves)
+def _line_counts(job):
+    J = np.asarray(job)
+    return np.count_nonzero(J, axis=1), np.count_nonzero(J, axis=0)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_expand_leaves_sum_to_permanent_random_integer(seed):
+    """Step 4 of Algorithm PH: the pre-expansion's jobs sum to per(A), checked against the
+    definition (eq. 1) on non-symmetric integer matrices, at several cut-off orders."""
+    n = 5 + seed % 5
+    A = rand_int(n, 3000 + seed, hi=6, density=0.5)
+    want = per_brute(A)
+    for m_cut in range(1, n + 1):
+        jobs = P.expand_leaves(A, m_cut)
+        assert sum(per_brute(j) for j in jobs) == want
+        for j in jobs:
+            rows, cols = _line_counts(j)
+            assert len(j) <= max(m_cut, 2)          # the size stop (no s >= 5 line here)
+            assert rows.min() > 0 and cols.min() > 0   # a node with an empty line is dropped
+
+
+@pytest.mark.parametrize("m_cut", [4, 8, 12, 16, 20])
+def test_expand_leaves_sum_to_permanent_cubic_n24(m_cut):
+    """The same identity on cubic graphs of 24 vertices against the independent frontier DP."""
+    for s in range(2):
+        A = W.random_cubic_matrix(24, s)
+        jobs = P.expand_leaves(A, m_cut)
+        assert all(len(j) == m_cut for j in jobs)   # cubic: every line has <= 4 nonzeros above m_cut
+        assert sum(per_dp(j) for j in jobs) == per_dp(A)
+
+
+def test_expand_leaves_s_leaf_branch_and_forced_split():
+    """H_per's R-NW condition (every line has >= s_leaf nonzeros) makes a node a job while its
+    order is <= m_cap; above m_cap such a node is split anyway. Dense 8 x 8 integer matrix:
+    every line holds 8 nonzeros."""
+    rng = np.random.default_rng(11)
+    A = rng.integers(1, 4, size=(8, 8))
+    want = per_brute(A)
+    # s >= 5 and order <= m_cap: the root itself is the only job
+    jobs = P.expand_leaves(A, m_cut=2, s_leaf=5, m_cap=8)
+    assert len(jobs) == 1 and np.array_equal(np.asarray(jobs[0]), A)
+    # m_cap = 7: the root is split (a full row gives ceil(8/2) = 4 children of order 7), each
+    # child still has every line >= 5 nonzeros and order 7 <= m_cap, so each is a job
+    jobs = P.expand_leaves(A, m_cut=2, s_leaf=5, m_cap=7)
+    assert [len(j) for j in jobs] == [7, 7, 7, 7]
+    assert sum(per_brute(j) for j in jobs) == want
+    # m_cap = 5: forced splits continue down to order 5
+    jobs = P.expand_leaves(A, m_cut=2, s_leaf=5, m_cap=5)
+    assert jobs and all(len(j) == 5 for j in jobs)
+    assert all(_line_counts(j)[0].min() >= 5 for j in jobs)
+    assert sum(per_brute(j) for j in jobs) == want
+    # s_leaf above every line count: plain size stop
+    jobs = P.expand_leaves(A, m_cut=6, s_leaf=9, m_cap=8)
+    assert all(len(j) == 6 for j in jobs) and sum(per_brute(j) for j in jobs) == want
+
+
+def test_expand_leaves_drops_zero_nodes_and_limit():
+    """A matrix with a zero column has no jobs (per = 0); ``limit`` keeps a prefix of the sequence."""
+    A = rand_int(7, 77, hi=3, density=0.8)
+    A[:, 3] = 0
+    assert P.expand_leaves(A, 3) == []
+    B = W.random_cubic_matrix(24, 5)
+    full = P.expand_leaves(B, 16)
+    assert P.expand_leaves(B, 16, limit=7) == full[:7]
+
+
+# --------------------------------------------------------------------------- KKLLL key
+def test_kkl_key_is_zero_for_permutation_patterns():
+    """Every trial of a permutation (or of a block-diagonal of 1 x 1 blocks after any row and
+    column shuffle) has |det B|^2 = 1, so the log-mean key is exactly 0."""
+    from oracle import kkl_key
+    rng = np.random.default_rng(5)
+    for n in (1, 4, 9, 16):
+        p = rng.permutation(n)
+        A = np.zeros((n, n), int)
+        A[np.arange(n), p] = 3   # the pattern is what counts, not the value
+        for job in (0, 17):
+            assert abs(kkl_key(A, 24, seed=9, job=job)) < 1e-12
+
+
+@pytest.mark.parametrize("k,per,hadamard", [(2, 2, 4), (3, 6, 27)])
+def test_kkl_key_mean_within_clt_interval(k, per, hadamard):
+    """exp(key) is the mean of T independent trials of X = |det B|^2 with E[X] = per(J_k) = k!.
+    Each X lies in [0, k^k] (Hadamard's inequality on rows of modulus-one entries), so its
+    variance is at most (k^k)^2 / 4 (Popoviciu): the mean lies within 5 standard errors of k!."""
+    from oracle import kkl_key
+    T = 3000
+    mean = math.exp(kkl_key(np.ones((k, k), int), T, seed=3, job=k))
+    se = math.sqrt(hadamard ** 2 / 4 / T)
+    assert abs(mean - per) < 5 * se
+    # J_2 in closed form: X = |w^a w^d - w^b w^c|^2 is 0 (prob 1/3) or 3 (prob 2/3): variance 2
+    if k == 2:
+        assert abs(mean - 2) < 5 * math.sqrt(2 / T)
+
+
+def test_kkl_key_is_log_of_the_trial_mean():
+    """The key aggregates trials as the log of their arithmetic mean (not a mean of logs): for a
+    matrix whose trials are 0 or 3 the mean of logs would be -inf."""
+    from oracle import kkl_key
+    from oracle.kkl import kkl_exponents
+    A = np.ones((2, 2), int)
+    xs = [kkl_trial(A, kkl_exponents(A, 4, 2, t)) for t in range(12)]
+    assert set(round(x, 9) for x in xs) <= {0.0, 3.0} and 0.0 in [round(x, 9) for x in xs]
+    assert abs(kkl_key(A, 12, 4, 2) - math.log(sum(xs) / 12)) < 1e-12
+    Z = np.zeros((3, 3), int)
+    Z[0, 0] = Z[1, 1] = 1   # a zero row: every trial is 0
+    assert kkl_key(Z, 5, 1, 0) == float("-inf")
