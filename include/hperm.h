@@ -156,6 +156,24 @@ hperm_status hperm_permanent_csr(hperm_ctx *ctx, int32_t n, const int32_t *row_p
 hperm_status hperm_permanent_dense(hperm_ctx *ctx, int32_t n, const uint32_t *a,
                                    hperm_result *out);
 
+/* For callers that cannot allocate memory during the call (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): per(A) of one dense row-major
+ * n x n matrix a[n*n] (host memory, borrowed for the call), 0 <= n <= 40, evaluated as a
+ * single R-NW job (no expansion), with the same value as hperm_permanent_dense. The call makes
+ * no hipMalloc/hipFree and no other allocation of device or pinned memory: every device buffer
+ * of the run (job descriptor and data, queue, queue heads, job and problem accumulators) is a
+ * slice of one fixed library array of 16 KiB per GPU (held until the process ends), and the
+ * host side packs the job on the stack. Heads and accumulators are cleared at the start of
+ * every call (the array keeps the previous call's contents). All calls on one GPU share that
+ * array: calls that overlap on the same GPU (from different contexts or threads) race and
+ * must be serialised by the caller; calls on one context are serialised by the library.
+ * Runs on the context's stream and waits for it. Errors: HPERM_E_INVALID (n outside 0..40,
+ * a NULL pointer, an entry >= 2^22, or the context is serving), HPERM_E_RANGE (a row sum
+ * reaches 2^24, the bound exceeds 2^180, or a forced ring is too narrow), HPERM_E_DEVICE
+ * (a HIP call failed, or the array's address could not be obtained), HPERM_E_INTERNAL. */
+hperm_status hperm_permanent_dense_noalloc(hperm_ctx *ctx, int32_t n, const uint32_t *a,
+                                           hperm_result *out);
+
 /* A batch of problems in one device pass: all their jobs share one queue and one
  * persistent launch (Algorithm PH over several matrices). Problem k has order n[k] and
  * CSR arrays at row_ptr + rp_off[k], col_idx + nz_off[k], val + nz_off[k]. out[count]. */

@@ -97,6 +97,7 @@ _SIGS = {
     "hperm_ctx_set_arena": [_P, _P, _SZ],
     "hperm_permanent_csr": [_P, _I32, _P, _P, _P, ctypes.POINTER(Result)],
     "hperm_permanent_dense": [_P, _I32, _P, ctypes.POINTER(Result)],
+    "hperm_permanent_dense_noalloc": [_P, _I32, _P, ctypes.POINTER(Result)],
     "hperm_permanent_batch_csr": [_P, _I32, _P, _P, _P, _P, _P, _P, _P],
     "hperm_expand_batch_csr": [_P, _I32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)],
     "hperm_jobs_from_dense": [_P, _I32, _P, _P, _P, ctypes.POINTER(_P)],
@@ -321,6 +322,25 @@ class Context:
         if with_stats:
             return vals, [out[k].stats() for k in range(len(mats))]
         return vals
+
+    def permanent_dense(self, A) -> int:
+        """per(A) through hperm_permanent_dense (expansion as the options say)."""
+        a = np.ascontiguousarray(np.asarray(A, dtype=np.uint32))
+        r = Result()
+        self._check(_lib.hperm_permanent_dense(self.handle, int(a.shape[0]), _ptr(a) if a.size else None,
+                                               ctypes.byref(r)), "permanent_dense")
+        return r.value
+
+    def permanent_dense_noalloc(self, A) -> int:
+        """per(A) of a dense matrix of order <= 40 as one job, with no allocation in the call
+        (the library's fixed scratch array per GPU; overlapping calls on one GPU race)."""
+        a = np.ascontiguousarray(np.asarray(A, dtype=np.uint32))
+        if a.ndim != 2 or a.shape[0] != a.shape[1]:
+            raise ValueError("square matrix expected")
+        r = Result()
+        self._check(_lib.hperm_permanent_dense_noalloc(self.handle, int(a.shape[0]), _ptr(a) if a.size else None,
+                                                       ctypes.byref(r)), "permanent_dense_noalloc")
+        return r.value
 
     def permanental_polynomial(self, A) -> list[int]:
         """Exact coefficients c_0..c_n of per(xI - A) = sum_k c_k x^k (c_k of x^k)."""

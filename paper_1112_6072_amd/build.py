@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libhperm.so")
-SOURCES = ["kernels.hip", "split.hip", "expand.cpp", "api.cpp", "serve.cpp", "sched.cpp", "poly.cpp"]
+SOURCES = ["kernels.hip", "split.hip", "noalloc.hip", "expand.cpp", "api.cpp", "serve.cpp", "sched.cpp",
+           "poly.cpp"]
 HIP_HOST_SOURCES = {"api.cpp", "serve.cpp"}   # host code that calls the HIP runtime
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -256,6 +256,7 @@ static uint64_t items_of(int m, int c) {
     const int e = m - 1 - 6 - c;
     return e > 0 ? (1ull << e) : 1ull;
 }
+uint64_t job_items(int m, int c) { return items_of(m, c); }
 
 // Exact permanent of one job from its accumulator (see JobAcc). Returns false when an
 // integrity check fails (2^(m-1) must divide V in the 2-adic rings, the value must be
@@ -376,7 +377,23 @@ static U512 crt3(const unsigned long long *res) {
     return x;
 }
 
-static void fill_result(const U512 &v, hperm_result *r) {
+// per(A) of a problem from its device accumulator: the 32-bit limb sums of its 2-adic-ring
+// jobs plus the CRT of its residue sums.
+U512 prob_value(const ProbAcc &q) {
+    U512 v;
+    for (int l = 3; l >= 0; --l) {   // sum_l lim[l] 2^(32 l)
+        U512 t;
+        t.w[0] = q.lim[l];
+        for (int z = 0; z < l; ++z) t.mul_u64(1ull << 32);
+        v.add(t);
+    }
+    bool any_res = false;
+    for (int z = 0; z < 6; ++z) any_res |= q.res[z] != 0;
+    if (any_res) v.add(crt3(q.res));
+    return v;
+}
+
+void fill_result(const U512 &v, hperm_result *r) {
     for (int k = 0; k < 8; ++k) r->limb[k] = v.w[k];
     r->nlimb = v.nlimb();
 }
@@ -755,17 +772,7 @@ hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_resu
                 if (q.err)
                     return set_error(c, HPERM_E_INTERNAL, "a job value of problem " + std::to_string(p) +
                                                               " failed its integrity check");
-                U512 v;
-                for (int l = 3; l >= 0; --l) {   // sum_l lim[l] 2^(32 l)
-                    U512 t;
-                    t.w[0] = q.lim[l];
-                    for (int z = 0; z < l; ++z) t.mul_u64(1ull << 32);
-                    v.add(t);
-                }
-                bool any_res = false;
-                for (int z = 0; z < 6; ++z) any_res |= q.res[z] != 0;
-                if (any_res) v.add(crt3(q.res));
-                sums[p] = v;
+                sums[p] = prob_value(q);
             }
         }
         for (int p = 0; p < np; ++p)
@@ -890,6 +897,8 @@ hperm_status hperm_ctx_create(const hperm_opts *opts, void *stream, hperm_ctx **
     }
     c->dev.stream = c->stream;
     c->dev.opts = c->opts;
+    c->dev.last_error.reserve(256);   // short error messages then need no allocation
+    (void)noalloc_scratch(c->device);  // the no-allocation entry point's array, once per device
     *out = c;
     return HPERM_OK;
 }

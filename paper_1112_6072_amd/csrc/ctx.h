@@ -121,6 +121,14 @@ hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_resu
                         double *t_rnw);
 hperm_status run_jobs(Dev *c, hperm_jobs *j, int order, int persistent, hperm_result *per_job,
                       hperm_result *totals, double *t_rnw);
+// per(A) of a problem from its device accumulator (limb sums + CRT of the residue sums).
+U512 prob_value(const ProbAcc &q);
+void fill_result(const U512 &v, hperm_result *r);
+// Work items of a job of order m with lane chunk 2^c (64 lanes per item).
+uint64_t job_items(int m, int c);
+// Device address of this device's no-allocation scratch array, looked up once per device
+// (noalloc.hip); nullptr when the lookup failed.
+void *noalloc_scratch(int device);
 hperm_status set_error(Dev *c, hperm_status s, const std::string &msg);
 hperm_status set_error(hperm_ctx *c, hperm_status s, const std::string &msg);
 hperm_status hip_check(Dev *c, hipError_t e, const char *what);

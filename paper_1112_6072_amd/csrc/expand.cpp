@@ -55,26 +55,31 @@ struct LimitError {};   // the job table outgrew ExpandParams::max_bytes
 // prod_i (r_i!)^(1/r_i) (rows, and columns by transposition).
 // log2(k!) / k for k = 0..HP_MAX_N (Bregman's factor of a line with k ones; entry 0 unused).
 static const double *bregman_table() {
-    static const std::vector<double> t = [] {
-        std::vector<double> v(HP_MAX_N + 1, 0.0);
-        for (int k = 1; k <= HP_MAX_N; ++k) v[k] = std::lgamma(k + 1.0) / std::log(2.0) / k;
-        return v;
-    }();
-    return t.data();
+    static const struct Table {
+        double v[HP_MAX_N + 1];
+        Table() {
+            v[0] = 0.0;
+            for (int k = 1; k <= HP_MAX_N; ++k) v[k] = std::lgamma(k + 1.0) / std::log(2.0) / k;
+        }
+    } t;
+    return t.v;
 }
 
 // log2(x) of a positive integer-valued line sum: a table below 4096 (the values std::log2
 // gives), std::log2 above.
 static inline double log2_sum(double x) {
-    static const std::vector<double> t = [] {
-        std::vector<double> v(4096, 0.0);
-        for (int k = 1; k < 4096; ++k) v[k] = std::log2((double)k);
-        return v;
-    }();
-    return x < 4096.0 ? t[(int)x] : std::log2(x);
+    static const struct Table {
+        double v[4096];
+        Table() {
+            v[0] = 0.0;
+            for (int k = 1; k < 4096; ++k) v[k] = std::log2((double)k);
+        }
+    } t;
+    return x < 4096.0 ? t.v[(int)x] : std::log2(x);
 }
 
-double log2_bound(const Node &a) {
+template <class NodeT>
+double log2_bound(const NodeT &a) {
     const int m = a.m;
     double rs[HP_MAX_N], cs[HP_MAX_N];
     int rc[HP_MAX_N], cc[HP_MAX_N];
@@ -293,11 +298,13 @@ struct JobOut {
 // the first Gray column touching them (rows touched by none come last). Then a flip of Gray
 // column j changes only rows below hi[j] = 1 + the lowest row of column j (at most the number
 // of rows of level <= j), and the kernels recompute only the suffix products of those rows.
-static void emit_job_oriented(const Node &a, int problem, double root_log2, const ExpandParams &prm,
-                              bool transposed, JobOut *out);
+template <class NodeT, class OutT>
+static void emit_job_oriented(const NodeT &a, int problem, double root_log2, const ExpandParams &prm,
+                              bool transposed, OutT *out);
 
 // Transpose of a node (CSR of the transposed matrix, columns sorted within a row).
-static void transpose_node(const Node &a, Node *t) {
+template <class NodeT>
+static void transpose_node(const NodeT &a, NodeT *t) {
     const int m = a.m;
     t->reserve(m, a.nnz);
     t->m = m;
@@ -317,7 +324,8 @@ static void transpose_node(const Node &a, Node *t) {
 // Orientation of a job: per(B) = per(B^T), so a job is emitted transposed when that lets its
 // first Gray column (the sparsest line other than the densest, fixed one) reach at most two
 // rows while the untransposed job's cannot; the kernels' paired walk then applies.
-void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &prm, JobOut *out) {
+template <class NodeT, class OutT>
+void emit_job(const NodeT &a, int problem, double root_log2, const ExpandParams &prm, OutT *out) {
     const int m = a.m;
     if (m > HP_MAX_M) throw RangeError{"a job exceeds the largest supported order"};
     if (m >= 3) {
@@ -334,7 +342,7 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
             return best;
         };
         if (sparsest_but_densest(cc) > 2 && sparsest_but_densest(rc) <= 2) {
-            Node t;
+            NodeT t;
             transpose_node(a, &t);
             emit_job_oriented(t, problem, root_log2, prm, true, out);
             return;
@@ -343,8 +351,9 @@ void emit_job(const Node &a, int problem, double root_log2, const ExpandParams &
     emit_job_oriented(a, problem, root_log2, prm, false, out);
 }
 
-static void emit_job_oriented(const Node &a, int problem, double root_log2, const ExpandParams &prm,
-                              bool transposed, JobOut *out) {
+template <class NodeT, class OutT>
+static void emit_job_oriented(const NodeT &a, int problem, double root_log2, const ExpandParams &prm,
+                              bool transposed, OutT *out) {
     const int m = a.m;
     int cnt[HP_MAX_M] = {0};
     uint64_t colrows[HP_MAX_M] = {0};
@@ -814,6 +823,95 @@ int jobs_from_dense(int count, const int32_t *m, const int64_t *off, const uint3
     }
     out->data.insert(out->data.end(), jo.data.begin(), jo.data.end());
     out->log2_bound.insert(out->log2_bound.end(), jo.bound.begin(), jo.bound.end());
+    return 0;
+}
+
+// ------------------------------------------------------------------ packing without the heap
+namespace {
+
+// Fixed-capacity stand-ins for the vectors of Node and JobOut, so that one dense job can be
+// packed on the stack by the same code (no allocation).
+template <class T, size_t N>
+struct FixedVec {
+    T a[N];
+    size_t n = 0;
+    size_t size() const { return n; }
+    void resize(size_t k) {
+        if (k > N) throw LimitError{};   // never for a job of order <= HP_MAX_M (sized below)
+        for (size_t i = n; i < k; ++i) a[i] = T();
+        n = k;
+    }
+    void push_back(const T &x) {
+        resize(n + 1);
+        a[n - 1] = x;
+    }
+    T *data() { return a; }
+    const T *data() const { return a; }
+    T &operator[](size_t i) { return a[i]; }
+    const T &operator[](size_t i) const { return a[i]; }
+};
+
+struct FixedNode {
+    int m = 0;
+    int nnz = 0;
+    int32_t rp[HP_MAX_M + 1];
+    uint8_t ci[HP_MAX_M * HP_MAX_M];
+    uint32_t v[HP_MAX_M * HP_MAX_M];
+    void reserve(int, int) {}
+};
+
+constexpr size_t kFixedJobWords = 5 * HP_MAX_M + HP_MAX_M * HP_MAX_M + HP_DATA_ALIGN;
+struct FixedJobOut {
+    FixedVec<JobDesc, 1> desc;
+    FixedVec<uint32_t, kFixedJobWords> data;
+    FixedVec<double, 1> bound;
+};
+
+}  // namespace
+
+size_t fixed_job_words() { return kFixedJobWords; }
+
+int pack_dense_job(int n, const uint32_t *a, int arith, JobDesc *desc, uint32_t *data, size_t cap_words,
+                   size_t *nwords, double *log2b) {
+    if (n < 1 || n > HP_MAX_M || !a || !desc || !data || !nwords || !log2b) return -1;
+    FixedNode nd;
+    nd.m = n;
+    int o = 0;
+    for (int i = 0; i < n; ++i) {
+        nd.rp[i] = o;
+        uint64_t rs = 0;
+        for (int j = 0; j < n; ++j) {
+            const uint32_t v = a[(size_t)i * n + j];
+            if (v >= HP_MAX_ENTRY) return -1;
+            rs += v;
+            if (v) {
+                nd.ci[o] = (uint8_t)j;
+                nd.v[o++] = v;
+            }
+        }
+        if (rs >= HP_MAX_ROWSUM) return -2;
+    }
+    nd.rp[n] = o;
+    nd.nnz = o;
+    const double lb = log2_bound(nd);
+    *log2b = lb;
+    if (lb == -INFINITY) return 1;   // a zero row or column: per = 0, no job
+    if (lb > 180.0) return -2;
+    // the ring emit_job picks for this bound (a forced narrower ring is refused there)
+    const int auto_ring = lb + n <= 62.5 ? HP_W64 : (lb + n <= 126.5 ? HP_W128 : HP_RES);
+    if (arith > 0 && arith - 1 < auto_ring) return -2;
+    ExpandParams prm;
+    prm.arith = arith;
+    FixedJobOut out;
+    try {
+        emit_job(nd, 0, lb, prm, &out);
+    } catch (...) {
+        return -2;
+    }
+    if (out.data.size() > cap_words || out.desc.size() != 1) return -2;
+    *desc = out.desc[0];
+    for (size_t k = 0; k < out.data.size(); ++k) data[k] = out.data[k];
+    *nwords = out.data.size();
     return 0;
 }
 

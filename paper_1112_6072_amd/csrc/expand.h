@@ -52,6 +52,14 @@ int expand_problems(const std::vector<CsrView> &probs, const ExpandParams &prm, 
 int jobs_from_dense(int count, const int32_t *m, const int64_t *off, const uint32_t *a,
                     const ExpandParams &prm, JobTable *out, std::string *err);
 
+// One dense matrix of order n (1..HP_MAX_M) packed as a single job without heap allocation
+// (the packing of jobs_from_dense, problem 0): *desc, data[0..*nwords) (data_off 0; at most
+// fixed_job_words() words), *log2b the proven bound. Returns 0, 1 (a zero line: per = 0, no
+// job), -1 (invalid argument or entry >= 2^22) or -2 (range: row sum, bound, forced ring).
+size_t fixed_job_words();
+int pack_dense_job(int n, const uint32_t *a, int arith, JobDesc *desc, uint32_t *data, size_t cap_words,
+                   size_t *nwords, double *log2b);
+
 // Default lane chunk (log2 Gray indices per lane) for a job of order m.
 int default_chunk_log2(int m);
 
