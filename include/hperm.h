@@ -91,6 +91,16 @@ typedef struct hperm_opts {
                              take the R-NW queue. Results are unchanged (the expansion is an
                              identity). 0: off, every job by R-NW. Ignored when s_leaf > 5 and by
                              one-launch-per-job runs. */
+    int32_t device_expand;/* T in [split_order + 1, 24], or 0 (default: off): the blocking calls
+                             (hperm_permanent_csr / _dense / _batch_csr) expand every problem of
+                             order n > T whose proven bound is below 2^102 on the device instead
+                             of the host: expansion (2) with Algorithm H_per's line rule (Section
+                             2.1) level by level down to sub-matrices of order T, which the device
+                             continuation of H_per finishes (split_order must be set); the whole
+                             tree stays on the GPU in bounded memory. Other problems take the host
+                             path. Results are the same integers. */
+    int32_t device_expand_mib; /* device memory for the expansion's level buffers in MiB
+                             (0 = 8192); more memory means fewer, larger launches */
 } hperm_opts;
 
 /* Result of one permanent. The value is non-negative: magnitude limbs, little-endian. */
@@ -256,6 +266,23 @@ hperm_status hperm_run_jobs(hperm_ctx *ctx, hperm_jobs *jobs, int32_t order, int
 
 void hperm_jobs_free(hperm_jobs *jobs);
 
+/* The device expansion as a stage (opts.device_expand = T and opts.split_order = t set; n > T):
+ * per(A) of one CSR matrix (layout as hperm_permanent_csr) with the expansion tree built on the
+ * GPU (expansion (2) with Algorithm H_per's line rule, Section 2.1, down to order T, then the
+ * device continuation of H_per), keeping its first max_jobs jobs of order T in tree order (the
+ * depth-first order of the expansion): mats[max_jobs * T * T] receives them as dense row-major
+ * T x T matrices and values[max_jobs] their exact permanents; *n_sampled how many were kept.
+ * stop_early != 0 ends the run once they are kept: *total then holds no value and has
+ * max_m = 0; otherwise *total is per(A) (max_m = T) with n_jobs the jobs of order T and
+ * subset_terms the leaves' subset-terms. Needs library-owned device memory (no arena).
+ * Errors: HPERM_E_INVALID (options, malformed input, n <= T, an arena is set),
+ * HPERM_E_RANGE (an entry or row sum beyond the kernels' limits, a bound beyond 2^102),
+ * HPERM_E_DEVICE, HPERM_E_NOMEM, HPERM_E_INTERNAL. */
+hperm_status hperm_device_expand_sample(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
+                                        const int32_t *col_idx, const uint32_t *val, int32_t max_jobs,
+                                        int32_t stop_early, uint32_t *mats, hperm_result *values,
+                                        int32_t *n_sampled, hperm_result *total);
+
 /* ---- scheduling study (the paper's load-balancing analysis) --------------------------- */
 
 /* Work time of every job (natural index) in the last persistent hperm_run_jobs on these jobs
@@ -333,7 +360,11 @@ typedef struct hperm_launch_stat {
     int32_t persistent;
     int32_t variant;        /* walk variant: 0, or 1 / 2 for the paired walk of jobs whose
                                Gray column 0 reaches only the first 2 / 3 rows; 3 for the
-                               device continuation of H_per (split_order) */
+                               device continuation of H_per (split_order); 4 for one problem of
+                               the device expansion (device_expand): then n_jobs = its jobs of
+                               order T, items = the nodes it wrote, row_updates = its device
+                               H_per launches, ms = the whole problem on the device and
+                               alg_slots = the milliseconds of its device H_per launches */
     int32_t reserved;
     uint64_t items;         /* work items (64 lanes x 2^chunk Gray indices each) */
     uint64_t terms;         /* subset-terms: sum of 2^(m-1) over the jobs */

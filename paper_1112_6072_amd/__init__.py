@@ -44,7 +44,8 @@ class Opts(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("chunk_log2", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("host_threads", ctypes.c_int32),
                 ("max_table_mib", ctypes.c_int32), ("time_jobs", ctypes.c_int32),
-                ("split_order", ctypes.c_int32)]
+                ("split_order", ctypes.c_int32), ("device_expand", ctypes.c_int32),
+                ("device_expand_mib", ctypes.c_int32)]
 
 
 class Coeff(ctypes.Structure):
@@ -114,6 +115,8 @@ _SIGS = {
     "hperm_last_launches": [_P, ctypes.POINTER(LaunchStat), _I32, ctypes.POINTER(_I32)],
     "hperm_jobs_cycles": [_P, _P],
     "hperm_jobs_matrix": [_P, _I32, _P],
+    "hperm_device_expand_sample": [_P, _I32, _P, _P, _P, _I32, _I32, _P, _P, ctypes.POINTER(_I32),
+                                   ctypes.POINTER(Result)],
     "hperm_permanental_polynomial": [_P, _I32, _P, _P, _P, _P],
     "hperm_polynomial_interpolate": [_I32, _P, _I32, _P],
     "hperm_list_schedule": [_I32, _P, _P, _I32, ctypes.POINTER(_U64), _P],
@@ -361,6 +364,26 @@ class Context:
                                       _ptr(va) if va.size else None, ctypes.byref(r))
         self._check(st, "permanent_csr")
         return r.value
+
+    def device_expand_sample(self, A, max_jobs: int, stop_early: bool = False):
+        """The device expansion (options device_expand = T, split_order = t) of one matrix,
+        keeping its first max_jobs jobs of order T in tree order: returns (total or None when
+        stopped early, list of T x T job matrices, their exact values, stats of the total)."""
+        n, rp, ci, va = _csr(A)
+        T = int(self._opts.device_expand)
+        k = max(int(max_jobs), 0)
+        mats = np.zeros(max(k * T * T, 1), np.uint32)
+        vals = (Result * max(k, 1))()
+        got = _I32()
+        tot = Result()
+        st = _lib.hperm_device_expand_sample(self.handle, n, _ptr(rp), _ptr(ci) if ci.size else None,
+                                             _ptr(va) if va.size else None, k, 1 if stop_early else 0,
+                                             _ptr(mats), vals, ctypes.byref(got), ctypes.byref(tot))
+        self._check(st, "device_expand_sample")
+        g = got.value
+        jobs = [mats[q * T * T:(q + 1) * T * T].reshape(T, T).copy() for q in range(g)]
+        total = tot.value if tot.max_m else None
+        return total, jobs, [vals[q].value for q in range(g)], tot.stats()
 
     # ---------------------------------------------------------------- stages
     def expand(self, mats) -> Jobs:

@@ -11,6 +11,7 @@
 #include <thread>
 
 #include "ctx.h"
+#include "expand.h"
 #include "kernels.h"
 
 using namespace hp;
@@ -115,6 +116,8 @@ hperm_status upload_jobs(Dev *c, hperm_jobs *j) {
     if (s) return s;
     s = ensure_buf(c, B_DATA, nw * sizeof(uint32_t));
     if (s) return s;
+    s = ensure_buf(c, B_BOUND, nd * sizeof(float));
+    if (s) return s;
     if (nd) {
         s = hip_check(c, hipMemcpyAsync(c->buf[B_DESC].ptr, j->tab.desc.data(), nd * sizeof(JobDesc),
                                         hipMemcpyHostToDevice, c->stream), "upload jobs");
@@ -127,6 +130,19 @@ hperm_status upload_jobs(Dev *c, hperm_jobs *j) {
         s = hip_check(c, hipMemcpyAsync((char *)c->buf[B_DATA].ptr + j->tab.data.size() * 4, zeros,
                                         sizeof(zeros), hipMemcpyHostToDevice, c->stream),
                       "pad job data");
+        if (s) return s;
+        // the proven bounds as floats rounded up (the device continuation of H_per admits a
+        // leaf to its 64-bit walk by them); kept with the table until it is uploaded again
+        if (j->fbound.size() != nd) {
+            j->fbound.resize(nd);
+            for (size_t k = 0; k < nd; ++k) {
+                float f = (float)j->tab.log2_bound[k];
+                if ((double)f < j->tab.log2_bound[k]) f = std::nextafter(f, INFINITY);
+                j->fbound[k] = f;
+            }
+        }
+        s = hip_check(c, hipMemcpyAsync(c->buf[B_BOUND].ptr, j->fbound.data(), nd * sizeof(float),
+                                        hipMemcpyHostToDevice, c->stream), "upload job bounds");
         if (s) return s;
     }
     c->resident_jobs = j->id;
@@ -265,7 +281,14 @@ static bool job_value(const JobDesc &d, const JobAcc &a, double log2_bound, U512
     const int m = d.m;
     const int sh = m - 1;
     *out = U512();
-    if (d.arith == HP_W64 || d.arith == HP_W128) {
+    if (a.flag == HP_ACC_NORMALISED) {   // per(B) itself, as 32-bit limb sums
+        for (int l = 3; l >= 0; --l) {
+            U512 t;
+            t.w[0] = a.l[l];
+            for (int z = 0; z < l; ++z) t.mul_u64(1ull << 32);
+            out->add(t);
+        }
+    } else if (d.arith == HP_W64 || d.arith == HP_W128) {
         i128 V;
         if (d.arith == HP_W64) {
             V = (int64_t)a.l[0];
@@ -556,10 +579,11 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     c->timed = persistent && c->opts.time_jobs != 0;
     c->split_launch = -1;
     if (persistent && split_in_effect(c->opts)) {
-        s = ensure_buf(c, B_SPLIT, 8 * sizeof(unsigned long long));
+        s = ensure_buf(c, B_SPLIT, HP_SPLIT_STATS * sizeof(unsigned long long));
         if (s) return s;
         const hperm_jobs::QueueGroup &last = j->qgroups.back();
-        s = ensure_buf(c, B_SPLIT_WIDE, split_wide_bytes(last.variant == kSplitVariant ? last.wide : 0));
+        s = ensure_buf(c, B_SPLIT_WIDE,
+                       split_wide_bytes(last.variant == kSplitVariant ? split_wide_capacity(last.wide, last.n) : 0));
         if (s) return s;
     }
     if (c->timed) {
@@ -621,18 +645,19 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             c->launches.push_back(st);
             if (g.variant == kSplitVariant) {
                 c->split_launch = (int)gi;
-                s = hip_check(c, launch_fill_u64((unsigned long long *)c->buf[B_SPLIT].ptr, 8, 0ull, c->stream),
+                s = hip_check(c, launch_fill_u64((unsigned long long *)c->buf[B_SPLIT].ptr, HP_SPLIT_STATS, 0ull, c->stream),
                               "clear split counters");
                 if (s) return s;
             }
             s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
             if (s) return s;
             if (g.variant == kSplitVariant)
-                s = hip_check(c, launch_split_w64(d_desc, d_data, (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi],
-                                                  (uint32_t)g.n, (uint32_t)nd, split_in_effect(c->opts), g.mmax,
-                                                  c->opts.s_leaf, head + gi, accs,
-                                                  (unsigned long long *)c->buf[B_SPLIT].ptr,
-                                                  c->buf[B_SPLIT_WIDE].ptr, g.wide, cyc, c->stream),
+                s = hip_check(c, launch_split_jobs(d_desc, d_data, (const float *)c->buf[B_BOUND].ptr,
+                                                   (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi], (uint32_t)g.n,
+                                                   (uint32_t)nd, split_in_effect(c->opts), g.mmax, c->opts.s_leaf,
+                                                   head + gi, accs, (unsigned long long *)c->buf[B_SPLIT].ptr,
+                                                   c->buf[B_SPLIT_WIDE].ptr, split_wide_capacity(g.wide, g.n), cyc,
+                                                   c->stream),
                               "device H_per launch");
             else
                 s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,
@@ -730,6 +755,8 @@ hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_resu
                 st.splits = c->split_stats[2];
                 st.split_stops = c->split_stats[3];
                 if (c->split_stats[5]) return set_error(c, HPERM_E_INTERNAL, "device H_per: leaf records lost");
+                if (c->split_stats[6])
+                    return set_error(c, HPERM_E_INTERNAL, "device H_per: a leaf value failed its integrity check");
             }
         } else if (!c->launches.empty()) {
             c->launches[0].ms = ms;
@@ -865,6 +892,10 @@ static const char *check_opts(const hperm_opts *o) {
     if (o->time_jobs != 0 && o->time_jobs != 1) return "time_jobs must be 0 or 1";
     if (o->split_order != 0 && (o->split_order < HP_SPLIT_MIN_T || o->split_order >= HP_SPLIT_MAX_M))
         return "split_order must be 0 or in [7, 23]";
+    if (o->device_expand != 0 &&
+        (o->split_order == 0 || o->device_expand <= o->split_order || o->device_expand > HP_SPLIT_MAX_M))
+        return "device_expand must be 0 or in [split_order + 1, 24] with split_order set";
+    if (o->device_expand_mib < 0) return "device_expand_mib must be >= 0";
     return nullptr;
 }
 
@@ -987,17 +1018,10 @@ static hperm_status expand_batch(hperm_ctx *c, int32_t count, const int32_t *n, 
     return HPERM_OK;
 }
 
-hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_t *n,
-                                       const int64_t *rp_off, const int64_t *nz_off,
-                                       const int32_t *row_ptr, const int32_t *col_idx,
-                                       const uint32_t *val, hperm_result *out) {
-    if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
-    if (!c || !out) return HPERM_E_INVALID;
-    if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
-    if (count < 0 || (count > 0 && (!n || !rp_off || !nz_off))) return set_error(c, HPERM_E_INVALID, "bad batch arrays");
-    std::lock_guard<std::mutex> lk(c->call_mu);
-    c->dev.last_error.clear();
-    c->dev.opts = c->opts;
+// The host-expansion path of a batch (the caller holds call_mu).
+static hperm_status batch_host_path(hperm_ctx *c, int32_t count, const int32_t *n, const int64_t *rp_off,
+                                    const int64_t *nz_off, const int32_t *row_ptr, const int32_t *col_idx,
+                                    const uint32_t *val, hperm_result *out) {
     const double t0 = now_s();
     // Problems are processed in up to four groups: the host expands group g + 1 on a thread of
     // its own while the device estimates and evaluates group g (each group has its own queue
@@ -1047,6 +1071,135 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
         out[k].t_rnw_s = t_rnw_all;
         out[k].t_total_s = t2 - t0;
     }
+    return HPERM_OK;
+}
+
+// Problems the device expansion takes: order above T and a proven bound below 2^102.
+static bool device_path(const hperm_opts &o, const CsrView &v) {
+    if (o.device_expand <= 0 || split_in_effect(o) <= 0 || v.n <= o.device_expand) return false;
+    std::vector<uint32_t> root;
+    double lb = 0.0;
+    const int rc = pack_root_node(v, &root, &lb);
+    return rc == 0 && lb <= 102.0;
+}
+
+hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_t *n,
+                                       const int64_t *rp_off, const int64_t *nz_off,
+                                       const int32_t *row_ptr, const int32_t *col_idx,
+                                       const uint32_t *val, hperm_result *out) {
+    if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
+    if (!c || !out) return HPERM_E_INVALID;
+    if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
+    if (count < 0 || (count > 0 && (!n || !rp_off || !nz_off))) return set_error(c, HPERM_E_INVALID, "bad batch arrays");
+    std::lock_guard<std::mutex> lk(c->call_mu);
+    c->dev.last_error.clear();
+    c->dev.opts = c->opts;
+    // problems for the device expansion, one at a time; the others in one host-path batch
+    std::vector<int> dev_idx, host_idx;
+    for (int k = 0; k < count; ++k) {
+        CsrView v{n[k], row_ptr ? row_ptr + rp_off[k] : nullptr, col_idx ? col_idx + nz_off[k] : nullptr,
+                  val ? val + nz_off[k] : nullptr};
+        const std::string why = validate_csr(v);
+        if (!why.empty()) return set_error(c, HPERM_E_INVALID, "problem " + std::to_string(k) + ": " + why);
+        (device_path(c->opts, v) ? dev_idx : host_idx).push_back(k);
+    }
+    if (dev_idx.empty()) return batch_host_path(c, count, n, rp_off, nz_off, row_ptr, col_idx, val, out);
+    std::vector<hperm_result> res(count);
+    if (!host_idx.empty()) {
+        std::vector<int32_t> hn;
+        std::vector<int64_t> hr, hz;
+        for (int k : host_idx) {
+            hn.push_back(n[k]);
+            hr.push_back(rp_off[k]);
+            hz.push_back(nz_off[k]);
+        }
+        std::vector<hperm_result> hres(host_idx.size());
+        hperm_status s = batch_host_path(c, (int32_t)host_idx.size(), hn.data(), hr.data(), hz.data(), row_ptr, col_idx,
+                                         val, hres.data());
+        if (s) return s;
+        for (size_t q = 0; q < host_idx.size(); ++q) res[host_idx[q]] = hres[q];
+    }
+    if (host_idx.empty()) c->dev.launches.clear();
+    const size_t budget = (size_t)(c->opts.device_expand_mib > 0 ? c->opts.device_expand_mib : 8192) << 20;
+    for (int k : dev_idx) {
+        const double t0 = now_s();
+        CsrView v{n[k], row_ptr + rp_off[k], col_idx + nz_off[k], val + nz_off[k]};
+        U512 total;
+        DexpStats st;
+        hperm_status s = device_expand_problem(&c->dev, v, c->opts.device_expand, split_in_effect(c->opts),
+                                               c->opts.s_leaf, budget, &total, &st);
+        if (s) return s;
+        hperm_result &r = res[k];
+        memset(&r, 0, sizeof(r));
+        fill_result(total, &r);
+        r.n_jobs = (int32_t)std::min<uint64_t>(st.jobs, 0x7fffffff);
+        r.max_m = c->opts.device_expand;
+        r.arith_mask = 1 << (HPERM_ARITH_W64);
+        r.subset_terms = st.leaf_terms;
+        r.t_rnw_s = st.split_s;
+        r.t_expand_s = st.total_s - st.split_s;
+        r.t_total_s = now_s() - t0;
+        hperm_launch_stat ls{};
+        ls.ring = HP_W64;
+        ls.bucket = bucket_of(c->opts.device_expand);
+        ls.n_jobs = r.n_jobs;
+        ls.persistent = 1;
+        ls.variant = 4;
+        ls.items = st.nodes;
+        ls.terms = st.leaf_terms;
+        ls.row_updates = st.launches;
+        ls.ms = st.total_s * 1e3;
+        ls.leaves = st.leaves;
+        ls.leaf_terms = st.leaf_terms;
+        ls.splits = st.splits;
+        ls.split_stops = st.split_stops;
+        ls.alg_slots = st.split_s * 1e3;   // the device H_per launches' share of ms
+        c->dev.launches.push_back(ls);
+    }
+    for (int k = 0; k < count; ++k) out[k] = res[k];
+    return HPERM_OK;
+}
+
+hperm_status hperm_device_expand_sample(hperm_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                        const uint32_t *val, int32_t max_jobs, int32_t stop_early, uint32_t *mats,
+                                        hperm_result *values, int32_t *n_sampled, hperm_result *total) {
+    if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
+    if (!c || !n_sampled || !total || max_jobs < 0 || (max_jobs > 0 && (!mats || !values))) return HPERM_E_INVALID;
+    if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
+    const int T = c->opts.device_expand, t = split_in_effect(c->opts);
+    if (T <= 0 || t <= 0) return set_error(c, HPERM_E_INVALID, "device_expand and split_order must be set");
+    CsrView v{n, row_ptr, col_idx, val};
+    const std::string why = validate_csr(v);
+    if (!why.empty()) return set_error(c, HPERM_E_INVALID, why);
+    if (n <= T) return set_error(c, HPERM_E_INVALID, "the order must exceed device_expand");
+    std::lock_guard<std::mutex> lk(c->call_mu);
+    c->dev.last_error.clear();
+    c->dev.opts = c->opts;
+    const size_t budget = (size_t)(c->opts.device_expand_mib > 0 ? c->opts.device_expand_mib : 8192) << 20;
+    DexpSample smp;
+    smp.max_jobs = (uint64_t)max_jobs;
+    smp.stop_early = stop_early != 0;
+    U512 tot;
+    DexpStats st;
+    const double t0 = now_s();
+    hperm_status s = device_expand_problem(&c->dev, v, T, t, c->opts.s_leaf, budget, &tot, &st, &smp);
+    if (s) return s;
+    const size_t k = smp.vals.size();
+    std::copy(smp.mats.begin(), smp.mats.end(), mats);
+    for (size_t q = 0; q < k; ++q) {
+        memset(&values[q], 0, sizeof(hperm_result));
+        fill_result(smp.vals[q], &values[q]);
+        values[q].n_jobs = 1;
+        values[q].max_m = T;
+    }
+    *n_sampled = (int32_t)k;
+    memset(total, 0, sizeof(*total));
+    if (smp.complete) fill_result(tot, total);
+    total->n_jobs = (int32_t)std::min<uint64_t>(st.jobs, 0x7fffffff);
+    total->max_m = smp.complete ? T : 0;   // 0: stopped early, the value is not per(A)
+    total->subset_terms = st.leaf_terms;
+    total->t_rnw_s = st.split_s;
+    total->t_total_s = now_s() - t0;
     return HPERM_OK;
 }
 

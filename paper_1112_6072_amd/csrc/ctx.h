@@ -21,7 +21,8 @@ struct DevBuf {
     bool owned = false;
 };
 
-enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_PROB, B_CYCLES, B_SPLIT, B_SPLIT_WIDE, B_COUNT };
+enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_BOUND, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_PROB, B_CYCLES,
+             B_SPLIT, B_SPLIT_WIDE, B_DX_LEVELS, B_DX_OFFS, B_DX_AUX, B_COUNT };
 
 struct Serving;   // serve.cpp
 
@@ -30,6 +31,7 @@ struct Serving;   // serve.cpp
 struct hperm_jobs {
     hp::JobTable tab;
     std::vector<float> keys;   // KKLLL keys, natural index
+    std::vector<float> fbound; // proven log2 bounds of the jobs as floats rounded up
     bool has_keys = false;
     uint64_t id = 0;           // identity for device residency
     // The persistent queue's grouping, which does not depend on the job order: per job its
@@ -79,7 +81,7 @@ struct Dev {
     bool persistent = true;
     bool timed = false;                        // per-job work cycles recorded (B_CYCLES)
     int split_launch = -1;                     // index of the device H_per launch, or -1
-    unsigned long long split_stats[6] = {0, 0, 0, 0, 0, 0};   // its counters (B_SPLIT)
+    unsigned long long split_stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // its counters (B_SPLIT)
     std::vector<JobAcc> host_acc;              // per-job accumulators (per-job results only)
     ProbAcc *host_prob = nullptr;              // pinned, per-problem accumulators
     size_t host_prob_cap = 0;
@@ -121,6 +123,31 @@ hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_resu
                         double *t_rnw);
 hperm_status run_jobs(Dev *c, hperm_jobs *j, int order, int persistent, hperm_result *per_job,
                       hperm_result *totals, double *t_rnw);
+// Counters of one device expansion (dexpand_host.cpp).
+struct DexpStats {
+    uint64_t jobs = 0;             // nodes of the job order handed to the device H_per
+    uint64_t nodes = 0;            // nodes written by the expansion (all levels)
+    uint64_t max_level_nodes = 0;  // the most nodes a level held at once
+    uint64_t launches = 0, relaunches = 0;
+    uint64_t leaves = 0, leaf_terms = 0, splits = 0, split_stops = 0, deferred = 0, deferred_bound = 0;
+    double split_s = 0.0, total_s = 0.0;
+};
+// per(A) of one problem (n > T) with the whole expansion tree on the device: the expansion
+// down to order T, then the device continuation of H_per to order t (7 <= t < T <= 24); the
+// level buffers take about budget_bytes. Requires a proven bound below 2^102.
+// With a sample, the first max_jobs jobs of the tree (in tree order, the depth-first order of
+// the expansion) are kept as dense T x T matrices with their exact values; stop_early ends the
+// run once they are in (complete then reports whether the whole tree was evaluated).
+struct DexpSample {
+    uint64_t max_jobs = 0;
+    bool stop_early = false;
+    bool complete = false;
+    std::vector<uint32_t> mats;
+    std::vector<U512> vals;
+};
+hperm_status device_expand_problem(Dev *c, const CsrView &a, int T, int t, int s_leaf, size_t budget_bytes, U512 *out,
+                                   DexpStats *stats, DexpSample *sample = nullptr);
+
 // per(A) of a problem from its device accumulator (limb sums + CRT of the residue sums).
 U512 prob_value(const ProbAcc &q);
 void fill_result(const U512 &v, hperm_result *r);

@@ -1,0 +1,334 @@
+// Host driver of the device expansion (dexpand.hip) and of the device continuation of H_per on
+// its nodes (split.hip): per(A) of one problem with every node of the expansion tree built on
+// the GPU.
+//
+// Level o of the tree (nodes of order o) has a buffer of W words and N node offsets. The root
+// (order n) is uploaded; a level is expanded chunk by chunk into the level below, and each
+// chunk's children are processed completely (recursively, down to the job order T) before the
+// next chunk of the level is expanded into the same buffer, so the memory in use is bounded by
+// the level buffers whatever the size of the tree. At order T the nodes are the jobs of the
+// device continuation of H_per, which splits them down to order t and evaluates the leaves;
+// every such launch sums into a staging accumulator that is checked (integrity counters,
+// record overflow) before its value joins the problem's exact total on the host.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "ctx.h"
+#include "expand.h"
+#include "kernels.h"
+
+namespace hp {
+
+hipError_t launch_dexp_plan(const uint32_t *lvl, const uint64_t *off, uint64_t first, uint32_t n, uint32_t *keys,
+                            uint64_t *packed, hipStream_t s);
+size_t dexp_scan_tiles(uint32_t n);
+hipError_t launch_dexp_scan(const uint64_t *in, uint32_t n, uint64_t *tile_sums, uint64_t *out, uint64_t *grand,
+                            hipStream_t s);
+// flags[0] |= 1 on a range error; flags[1] = max(flags[1], the words of every child written).
+hipError_t launch_dexp_write(const uint32_t *lvl, const uint64_t *off, uint64_t first, uint32_t n, const uint32_t *keys,
+                             const uint64_t *place, uint32_t *out, uint64_t *out_off, unsigned long long *flags,
+                             hipStream_t s);
+
+namespace {
+
+// Small device block read back after each step: scan total, range flag, split counters and the
+// staging accumulator of the last launch.
+struct Misc {
+    unsigned long long grand;          // packed (children << 36 | words) of the last scan
+    unsigned long long flags;          // bit 0: an entry or row sum out of range
+    unsigned long long maxw;           // the largest child (words) of the last write
+    unsigned long long head;           // queue counter of the split launch
+    unsigned long long stats[HP_SPLIT_STATS];
+    ProbAcc prob;                      // the split launch's sum
+};
+
+struct Plan {
+    int n = 0, T = 0, t = 0, s_leaf = 5;
+    uint64_t W = 0, N = 0;             // words and node offsets per level
+    uint32_t *levels = nullptr;        // level o at levels + (o - T) * W
+    uint64_t *offs = nullptr;          // level o's offsets at offs + (o - T) * N
+    uint32_t *keys = nullptr;          // plan of a chunk (N / 2 entries)
+    uint64_t *packed = nullptr, *place = nullptr, *tiles = nullptr;
+    Misc *misc = nullptr;              // device
+    void *wide = nullptr;
+    uint64_t wide_entries = 0;
+    std::vector<uint32_t> maxw;        // per level: the largest node (words) of its current contents
+};
+
+}  // namespace
+
+struct DexpRun {
+    Dev *c;
+    Plan P;
+    U512 total;
+    DexpStats st;
+    std::string err;
+    hperm_status status = HPERM_OK;
+    // the first sample_max jobs (tree order): dense T x T matrices and their values
+    uint64_t sample_max = 0;
+    bool stop_after_sample = false;
+    std::vector<uint32_t> *sample_mats = nullptr;
+    std::vector<U512> *sample_vals = nullptr;
+    bool stopped = false;
+
+    hperm_status fail(hperm_status s, const std::string &m) {
+        status = s;
+        err = m;
+        return s;
+    }
+    hperm_status hip(hipError_t e, const char *what) {
+        if (e == hipSuccess) return HPERM_OK;
+        return fail(e == hipErrorOutOfMemory ? HPERM_E_NOMEM : HPERM_E_DEVICE,
+                    std::string(what) + ": " + hipGetErrorString(e));
+    }
+
+    uint32_t *level(int o) const { return P.levels + (size_t)(o - P.T) * P.W; }
+    uint64_t *offs(int o) const { return P.offs + (size_t)(o - P.T) * P.N; }
+
+    // The jobs of level T [0, n): the device continuation of H_per, checked and summed.
+    hperm_status run_jobs(uint64_t n) {
+        hipStream_t s = c->stream;
+        Misc *m = P.misc;
+        Misc h;
+        const uint64_t have = sample_vals ? sample_vals->size() : 0;
+        const uint64_t take = sample_max > have ? std::min<uint64_t>(sample_max - have, n) : 0;
+        JobAcc *accs = nullptr;
+        if (take) {   // per-node values of this launch are kept (the first jobs of the tree)
+            hperm_status r = ensure_buf(c, B_ACCS, n * sizeof(JobAcc));
+            if (r) return fail(r, c->last_error);
+            if (c->arena) return fail(HPERM_E_INVALID, "sampling device jobs needs library-owned memory");
+            accs = (JobAcc *)c->buf[B_ACCS].ptr;
+            r = hip(launch_fill_u64((unsigned long long *)accs, n * (sizeof(JobAcc) / 8), 0ull, s), "clear accumulators");
+            if (r) return r;
+        }
+        for (int attempt = 0;; ++attempt) {
+            hperm_status r = hip(launch_fill_u64((unsigned long long *)&m->head,
+                                                 (sizeof(Misc) - offsetof(Misc, head)) / 8, 0ull, s),
+                                 "clear split counters");
+            if (r) return r;
+            const double t0 = now_s();
+            if (accs && attempt) {
+                r = hip(launch_fill_u64((unsigned long long *)accs, n * (sizeof(JobAcc) / 8), 0ull, s),
+                        "clear accumulators");
+                if (r) return r;
+            }
+            r = hip(launch_split_nodes(level(P.T), offs(P.T), (uint32_t)n, P.t, P.T, P.s_leaf, &m->head, accs,
+                                       &m->prob, m->stats, P.wide, P.wide_entries, s),
+                    "device H_per launch");
+            if (r) return r;
+            r = hip(hipMemcpyAsync(&h, m, sizeof(Misc), hipMemcpyDeviceToHost, s), "download split results");
+            if (r) return r;
+            r = hip(hipStreamSynchronize(s), "device H_per");
+            if (r) return r;
+            st.split_s += now_s() - t0;
+            if (h.stats[6]) return fail(HPERM_E_INTERNAL, "device H_per: a leaf value failed its integrity check");
+            if (!h.stats[5]) break;
+            // the record buffer overflowed: the launch's sum is dropped and the launch repeated
+            // with room for every deferred leaf it reported
+            if (attempt >= 2) return fail(HPERM_E_INTERNAL, "device H_per: leaf records lost");
+            const uint64_t need = h.stats[4] + 1024;
+            r = ensure_buf(c, B_SPLIT_WIDE, split_wide_bytes(need));
+            if (r) return fail(r, c->last_error);
+            if (!c->arena) {   // a fresh allocation moves only this buffer
+                P.wide = c->buf[B_SPLIT_WIDE].ptr;
+                P.wide_entries = need;
+            } else {
+                return fail(HPERM_E_NOMEM, "device H_per: the arena cannot hold the leaf records");
+            }
+            ++st.relaunches;
+        }
+        if (take) {
+            std::vector<uint64_t> off(take);
+            std::vector<JobAcc> acc(take);
+            hperm_status r = hip(hipMemcpy(off.data(), offs(P.T), take * 8, hipMemcpyDeviceToHost), "download offsets");
+            if (r) return r;
+            r = hip(hipMemcpy(acc.data(), accs, take * sizeof(JobAcc), hipMemcpyDeviceToHost), "download values");
+            if (r) return r;
+            const int T = P.T;
+            std::vector<uint32_t> node(hp_node_words(T, T * T));
+            for (uint64_t q = 0; q < take; ++q) {
+                r = hip(hipMemcpy(node.data(), level(T) + off[q], 16, hipMemcpyDeviceToHost), "download node header");
+                if (r) return r;
+                const uint32_t words = hp_node_words((int)(node[0] & 0xffu), (int)(node[0] >> 8));
+                if ((node[0] & 0xffu) != (uint32_t)T || words > node.size())
+                    return fail(HPERM_E_INTERNAL, "device expansion: a job node has the wrong order");
+                r = hip(hipMemcpy(node.data(), level(T) + off[q], words * 4, hipMemcpyDeviceToHost), "download node");
+                if (r) return r;
+                const size_t base = sample_mats->size();
+                sample_mats->resize(base + (size_t)T * T, 0u);
+                const uint32_t *ent = node.data() + 4 + (T + 3) / 4;
+                uint32_t e = 0;
+                for (int i = 0; i < T; ++i) {
+                    const uint32_t len = (node[4 + i / 4] >> (8 * (i & 3))) & 0xffu;
+                    for (uint32_t z = 0; z < len; ++z, ++e) (*sample_mats)[base + (size_t)i * T + (ent[e] & 0xffu)] = ent[e] >> 8;
+                }
+                U512 v;
+                for (int l = 3; l >= 0; --l) {
+                    U512 t;
+                    t.w[0] = acc[q].l[l];
+                    for (int z = 0; z < l; ++z) t.mul_u64(1ull << 32);
+                    v.add(t);
+                }
+                sample_vals->push_back(v);
+            }
+            if (stop_after_sample && sample_vals->size() >= sample_max) stopped = true;
+        }
+        total.add(prob_value(h.prob));
+        st.jobs += n;
+        st.launches++;
+        st.leaves += h.stats[0];
+        st.leaf_terms += h.stats[1];
+        st.splits += h.stats[2];
+        st.split_stops += h.stats[3];
+        st.deferred += h.stats[4];
+        st.deferred_bound += h.stats[7];
+        return HPERM_OK;
+    }
+
+    // Expand nodes [lo, hi) of level o (o > T) into level o - 1 chunk by chunk, each chunk's
+    // subtree finished before the next.
+    hperm_status process(int o, uint64_t lo, uint64_t hi) {
+        hipStream_t s = c->stream;
+        uint64_t k = lo;
+        while (k < hi) {
+            const uint64_t mw = std::max<uint64_t>(P.maxw[o - P.T], 8);
+            uint64_t chunk = std::min<uint64_t>(hi - k, std::min<uint64_t>(P.N / 2, P.W / (2 * mw)));
+            chunk = std::max<uint64_t>(chunk, 1);
+            for (;;) {
+                unsigned long long tot[2];
+                hperm_status r = hip(launch_dexp_plan(level(o), offs(o), k, (uint32_t)chunk, P.keys, P.packed, s),
+                                     "expansion plan");
+                if (r) return r;
+                r = hip(launch_dexp_scan(P.packed, (uint32_t)chunk, P.tiles, P.place, (uint64_t *)&P.misc->grand, s),
+                        "expansion scan");
+                if (r) return r;
+                r = hip(hipMemcpyAsync(tot, &P.misc->grand, sizeof(tot), hipMemcpyDeviceToHost, s),
+                        "download expansion totals");
+                if (r) return r;
+                r = hip(hipStreamSynchronize(s), "expansion plan");
+                if (r) return r;
+                const uint64_t kids = tot[0] >> 36, words = tot[0] & ((1ull << 36) - 1);
+                if (kids <= P.N && words <= P.W) {
+                    st.nodes += kids;
+                    st.max_level_nodes = std::max<uint64_t>(st.max_level_nodes, kids);
+                    if (kids) {
+                        r = hip(launch_fill_u64(&P.misc->maxw, 1, 0ull, s), "clear size");
+                        if (r) return r;
+                        r = hip(launch_dexp_write(level(o), offs(o), k, (uint32_t)chunk, P.keys, P.place,
+                                                  level(o - 1), offs(o - 1), &P.misc->flags, s),
+                                "expansion write");
+                        if (r) return r;
+                        r = hip(hipMemcpyAsync(tot, &P.misc->flags, sizeof(tot), hipMemcpyDeviceToHost, s),
+                                "download expansion flags");
+                        if (r) return r;
+                        r = hip(hipStreamSynchronize(s), "expansion write");
+                        if (r) return r;
+                        if (tot[0] & 1) return fail(HPERM_E_RANGE, "an expanded entry reached 2^22 or a row sum 2^24");
+                        P.maxw[o - 1 - P.T] = (uint32_t)tot[1];   // the largest child of the chunk
+                        r = o - 1 == P.T ? run_jobs(kids) : process(o - 1, 0, kids);
+                        if (r) return r;
+                        if (stopped) return HPERM_OK;
+                    }
+                    break;
+                }
+                if (chunk == 1) return fail(HPERM_E_NOMEM, "device expansion: one node's children exceed a level buffer");
+                chunk /= 2;   // nodes with more than two children (lines of five or more nonzeros)
+            }
+            k += chunk;
+        }
+        return HPERM_OK;
+    }
+};
+
+hperm_status device_expand_problem(Dev *c, const CsrView &a, int T, int t, int s_leaf, size_t budget_bytes, U512 *out,
+                                   DexpStats *stats, DexpSample *sample) {
+    DexpRun run{c, Plan{}, U512(), DexpStats{}, std::string(), HPERM_OK};
+    if (sample) {
+        run.sample_max = sample->max_jobs;
+        run.stop_after_sample = sample->stop_early;
+        run.sample_mats = &sample->mats;
+        run.sample_vals = &sample->vals;
+        sample->mats.clear();
+        sample->vals.clear();
+    }
+    Plan &P = run.P;
+    const int n = a.n;
+    if (n <= T || T > HP_SPLIT_MAX_M || t < HP_SPLIT_MIN_T || t >= T)
+        return set_error(c, HPERM_E_INVALID, "device expansion: needs t < T <= 24 < n");
+    // the root node, its bound (rows, columns and Bregman's for 0-1 inputs) and its size
+    std::vector<uint32_t> root;
+    double lb = 0.0;
+    int rc = pack_root_node(a, &root, &lb);
+    if (rc == 1) {   // a zero row or column
+        *out = U512();
+        if (stats) *stats = run.st;
+        return HPERM_OK;
+    }
+    if (rc) return set_error(c, rc == -2 ? HPERM_E_RANGE : HPERM_E_INVALID, "device expansion: input out of range");
+    if (lb > 102.0)
+        return set_error(c, HPERM_E_RANGE, "device expansion: the permanent bound exceeds 2^102");
+    P.n = n;
+    P.T = T;
+    P.t = t;
+    P.s_leaf = s_leaf;
+    const int L = n - T + 1;
+    // per level: 7/8 of its share in words, 1/8 in 8-byte offsets; the plan arrays for half a
+    // level's offsets; the record buffer
+    const size_t share = budget_bytes / (size_t)(L + 1);
+    P.W = std::min<uint64_t>((share * 7 / 8) / 4, (uint64_t)1 << 29);
+    P.N = std::max<uint64_t>(std::min<uint64_t>((share / 8) / 8, (uint64_t)1 << 26), 64);
+    P.W = std::max<uint64_t>(P.W, 2 * (uint64_t)root.size() + 64);
+    const size_t half = P.N / 2 + 1;
+    const size_t tiles = dexp_scan_tiles((uint32_t)half) + 1;
+    hperm_status s = ensure_buf(c, B_DX_LEVELS, (size_t)L * P.W * 4);
+    if (s) return s;
+    s = ensure_buf(c, B_DX_OFFS, (size_t)L * P.N * 8);
+    if (s) return s;
+    s = ensure_buf(c, B_DX_AUX, half * 4 + 256 + 2 * half * 8 + 512 + tiles * 8 + 256 + sizeof(Misc) + 256);
+    if (s) return s;
+    // deferred leaves are rare (orders above 16, or bounds beyond 64 bits): a first buffer of
+    // 2^20 records, grown when a launch reports more
+    P.wide_entries = (uint64_t)1 << 20;
+    s = ensure_buf(c, B_SPLIT_WIDE, split_wide_bytes(P.wide_entries));
+    if (s) return s;
+    // (an arena re-layout may move any buffer: take every pointer after the last ensure_buf)
+    P.levels = (uint32_t *)c->buf[B_DX_LEVELS].ptr;
+    P.offs = (uint64_t *)c->buf[B_DX_OFFS].ptr;
+    char *aux = (char *)c->buf[B_DX_AUX].ptr;
+    auto take = [&aux](size_t bytes) {
+        char *p = aux;
+        aux += (bytes + 255) / 256 * 256;
+        return (void *)p;
+    };
+    P.keys = (uint32_t *)take(half * 4);
+    P.packed = (uint64_t *)take(half * 8);
+    P.place = (uint64_t *)take(half * 8);
+    P.tiles = (uint64_t *)take(tiles * 8);
+    P.misc = (Misc *)take(sizeof(Misc));
+    P.wide = c->buf[B_SPLIT_WIDE].ptr;
+    P.maxw.assign((size_t)L, 0);
+    P.maxw[(size_t)L - 1] = (uint32_t)root.size();
+    c->resident_jobs = 0;   // the arena's layout may have moved the job table
+    c->resident_list = 0;
+    const double t0 = now_s();
+    s = run.hip(hipMemcpyAsync(run.level(n), root.data(), root.size() * 4, hipMemcpyHostToDevice, c->stream),
+                "upload root");
+    if (!s) {
+        const uint64_t zero = 0;
+        s = run.hip(hipMemcpyAsync(run.offs(n), &zero, 8, hipMemcpyHostToDevice, c->stream), "upload root offset");
+    }
+    if (!s) s = run.hip(launch_fill_u64(&P.misc->grand, 3, 0ull, c->stream), "clear flags");
+    if (!s) s = run.process(n, 0, 1);
+    run.st.total_s = now_s() - t0;
+    if (s) return set_error(c, s, run.err);
+    if (sample) sample->complete = !run.stopped;
+    if (!run.stopped && run.total.bits() > (int)std::ceil(lb) + 1)
+        return set_error(c, HPERM_E_INTERNAL, "device expansion: the result exceeds its proven bound");
+    *out = run.total;
+    if (stats) *stats = run.st;
+    return HPERM_OK;
+}
+
+}  // namespace hp

@@ -915,4 +915,45 @@ int pack_dense_job(int n, const uint32_t *a, int arith, JobDesc *desc, uint32_t 
     return 0;
 }
 
+int pack_root_node(const CsrView &a, std::vector<uint32_t> *out, double *log2b) {
+    const int n = a.n;
+    Node root;
+    int nz = 0;
+    for (int e = 0; e < a.row_ptr[n]; ++e) nz += a.val[e] != 0;
+    root.reserve(n, nz);
+    root.m = n;
+    int o = 0;
+    for (int i = 0; i < n; ++i) {
+        root.rp[i] = o;
+        uint64_t rs = 0;
+        for (int e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
+            if (a.val[e]) {
+                if (a.val[e] >= HP_MAX_ENTRY) return -2;
+                rs += a.val[e];
+                root.ci[o] = (uint8_t)a.col_idx[e];
+                root.v[o++] = a.val[e];
+            }
+        if (rs >= HP_MAX_ROWSUM) return -2;
+    }
+    root.rp[n] = o;
+    root.nnz = o;
+    const double lb = log2_bound(root);
+    *log2b = lb;
+    if (lb == -INFINITY) return 1;
+    out->assign(hp_node_words(n, o), 0u);
+    uint32_t *w = out->data();
+    float fb = (float)lb;
+    if ((double)fb < lb) fb = std::nextafter(fb, INFINITY);
+    uint32_t fbits;
+    memcpy(&fbits, &fb, 4);
+    w[0] = (uint32_t)n | ((uint32_t)o << 8);
+    w[1] = fbits;
+    w[2] = 0;
+    w[3] = 0;
+    for (int i = 0; i < n; ++i) w[4 + i / 4] |= (uint32_t)(root.rp[i + 1] - root.rp[i]) << (8 * (i & 3));
+    uint32_t *ent = w + 4 + (n + 3) / 4;
+    for (int e = 0; e < o; ++e) ent[e] = (root.v[e] << 8) | root.ci[e];
+    return 0;
+}
+
 }  // namespace hp

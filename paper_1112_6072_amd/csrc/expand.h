@@ -60,6 +60,11 @@ size_t fixed_job_words();
 int pack_dense_job(int n, const uint32_t *a, int arith, JobDesc *desc, uint32_t *data, size_t cap_words,
                    size_t *nwords, double *log2b);
 
+// The root node of the device expansion (hp_node_words layout, problem 0) of a validated CSR
+// matrix, and its proven log2 bound. Returns 0, 1 (a zero row or column: per = 0) or -2 (an
+// entry or row sum beyond the kernels' limits).
+int pack_root_node(const CsrView &a, std::vector<uint32_t> *node, double *log2b);
+
 // Default lane chunk (log2 Gray indices per lane) for a job of order m.
 int default_chunk_log2(int m);
 

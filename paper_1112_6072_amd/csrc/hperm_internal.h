@@ -74,11 +74,33 @@ static inline size_t hp_align_words(size_t n) { return (n + HP_DATA_ALIGN - 1) /
 //   W64  : l[0] = V mod 2^64 (wrap-around sum of the items' values)
 //   W128 : V = sum_k l[k] 2^(32k) mod 2^128, k = 0..3 (limb k of each item, summed)
 //   RES  : V mod p_k = (l[2k] + 2^32 l[2k+1]) mod p_k (low and high halves of residues)
+//   normalised (flag == HP_ACC_NORMALISED, written by the device continuation of H_per):
+//          per(B) itself = sum_k l[k] 2^(32k), k = 0..3, whatever the job's ring
 struct JobAcc {
     unsigned long long l[6];
-    unsigned long long pad[2];
+    unsigned long long flag;
+    unsigned long long pad;
 };
+constexpr unsigned long long HP_ACC_NORMALISED = 1;
 static_assert(sizeof(JobAcc) == 64, "JobAcc layout");
+
+// A sub-matrix node of the device expansion (one per node, 16-byte aligned, 32-bit words):
+//   w[0]  order o (bits 0..7) | nnz << 8
+//   w[1]  proven upper bound of log2 per(node), as float bits (the smallest of the bounds of
+//         the node's ancestors and its own row-sum bound; per(child) <= per(parent) since all
+//         entries are non-negative)
+//   w[2]  problem index
+//   w[3]  zero
+//   w[4 .. 4 + ceil(o/4))  row lengths, one byte per row (row i: byte i % 4 of word 4 + i / 4)
+//   then the nnz entries row by row, columns increasing: (value << 8) | column
+#if defined(__HIPCC__)
+#define HP_HOST_DEVICE __host__ __device__
+#else
+#define HP_HOST_DEVICE
+#endif
+HP_HOST_DEVICE static inline uint32_t hp_node_words(int o, int nnz) {
+    return (4u + ((uint32_t)o + 3u) / 4u + (uint32_t)nnz + 3u) & ~3u;
+}
 
 // Per-problem accumulator of the device recombination: lim[k] sums limb k (32 bits) of the
 // exact permanents of the problem's 2-adic-ring jobs; res[2k], res[2k+1] sum the low and

@@ -67,25 +67,39 @@ HP_RING_DECL(res)
 // Resident grid (blocks) of the persistent kernel variant.
 hipError_t persistent_grid(int ring, int bucket, int variant, int *grid);
 
-// Device continuation of H_per (split.hip): mod-2^64 jobs of order HP_SPLIT_MIN_T + 1 ..
-// HP_SPLIT_MAX_M are split on the device down to order t (HP_SPLIT_MIN_T <= t < HP_SPLIT_MAX_M)
-// and their leaves evaluated; each job's value lands in accs[job].l[0] as for the R-NW
-// kernels. queue[0..n) lists the jobs (indices < njobs), mm is their largest order (> t);
-// head is a cleared counter; stats[0..6) (cleared by the caller) receive leaves, leaf
-// subset-terms, splits, splits refused by the entry bounds, the wide leaves deferred to the
-// second kernel, and deferred leaves that found the record buffer full (0 when the buffer holds
-// split_wide_entries summed over the jobs); wide is a buffer of split_wide_bytes(entries)
-// bytes; cycles (nullable) receives each job's shader-clock cycles (first kernel only). Two
-// launches on stream s.
+// Device continuation of H_per (split.hip): jobs of order HP_SPLIT_MIN_T + 1 .. HP_SPLIT_MAX_M
+// are split on the device down to order t (HP_SPLIT_MIN_T <= t < HP_SPLIT_MAX_M) and their
+// leaves evaluated; each job's exact permanent per(B) lands in its accumulator as 32-bit limb
+// sums flagged HP_ACC_NORMALISED (whatever its ring). The job's proven bound must stay below
+// 2^102 (the leaves the 64-bit walk cannot take exactly are replayed modulo 2^128).
+// stats[0..8) (cleared by the caller) receive leaves, leaf subset-terms, splits, splits refused
+// by the entry bounds, deferred leaves, deferred leaves that found the record buffer full,
+// leaves that failed their integrity check, and leaves deferred for want of a 64-bit bound; the
+// last three must be 0 (else the result is not to be used). wide is a record buffer of
+// split_wide_bytes(entries) bytes; two launches on stream s.
 constexpr int HP_SPLIT_MAX_M = 24;
 constexpr int HP_SPLIT_MIN_T = 7;
+constexpr int HP_SPLIT_STATS = 8;
 // Most leaves above order 16 a job of order m can defer: the nodes of orders 17..m.
 inline uint64_t split_wide_entries(int m) { return m > 16 ? (1ull << (m - 16)) - 1 : 0; }
+// Record buffer entries for jobs whose wide-leaf bounds sum to `wide`: room besides for one
+// leaf per job deferred for want of a 64-bit bound (a job whose own bound admits it can defer
+// at most its own root that way, when the rounding of the bound to float costs the margin).
+inline uint64_t split_wide_capacity(uint64_t wide, uint64_t njobs) { return wide + njobs + 1024; }
 size_t split_lds_bytes(int t, int mm);
 size_t split_wide_bytes(uint64_t entries);
-hipError_t launch_split_w64(const JobDesc *jobs, const uint32_t *data, const uint32_t *queue, uint32_t n,
-                            uint32_t njobs, int t, int mm, int s_leaf, unsigned long long *head, JobAcc *accs,
-                            unsigned long long *stats, void *wide, uint64_t wide_entries,
-                            unsigned long long *cycles, hipStream_t s);
+// Jobs of a host job table: queue[0..n) lists them (indices < njobs), mm is their largest order
+// (> t), job_bound[job] their proven log2 bounds (float, rounded up); per-job values into accs;
+// cycles (nullable) receives each job's shader-clock cycles.
+hipError_t launch_split_jobs(const JobDesc *jobs, const uint32_t *data, const float *job_bound, const uint32_t *queue,
+                             uint32_t n, uint32_t njobs, int t, int mm, int s_leaf, unsigned long long *head,
+                             JobAcc *accs, unsigned long long *stats, void *wide, uint64_t wide_entries,
+                             unsigned long long *cycles, hipStream_t s);
+// Nodes of the device expansion: node k at nodes + node_off[k], k < n, all of order mm (> t);
+// their values are summed into probs[problem of the node]; accs (nullable) receives each
+// node's value.
+hipError_t launch_split_nodes(const uint32_t *nodes, const uint64_t *node_off, uint32_t n, int t, int mm, int s_leaf,
+                              unsigned long long *head, JobAcc *accs, ProbAcc *probs, unsigned long long *stats,
+                              void *wide, uint64_t wide_entries, hipStream_t s);
 
 }  // namespace hp

@@ -881,7 +881,8 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
 }
 
 // Step 4 of Algorithm PH on the device: every job's ring value V is turned into its
-// permanent and added into its problem's accumulator.
+// permanent and added into its problem's accumulator (a normalised accumulator already holds
+// the permanent).
 //   mod 2^64 / 2^128: per = (-1)^(m-1) V / 2^(m-1); V must be divisible by 2^(m-1) with a
 //   non-negative quotient (else the problem's error flag is set); the 32-bit limbs of per are
 //   added into lim[0..3].
@@ -911,7 +912,14 @@ __global__ void recombine(const JobDesc *__restrict__ jobs, const JobAcc *__rest
         const JobAcc a = accs[k];
         problem = d.problem;
         const int sh = d.m - 1;
-        if (d.arith == HP_RES) {
+        if (a.flag == HP_ACC_NORMALISED) {   // per(B) itself (device continuation of H_per)
+            const unsigned __int128 per = (unsigned __int128)a.l[0] + ((unsigned __int128)a.l[1] << 32) +
+                                          ((unsigned __int128)a.l[2] << 64) + ((unsigned __int128)a.l[3] << 96);
+            v[0] = (uint32_t)per;
+            v[1] = (uint32_t)(per >> 32);
+            v[2] = (uint32_t)(per >> 64);
+            v[3] = (uint32_t)(per >> 96);
+        } else if (d.arith == HP_RES) {
             const uint64_t r0 = res_normalise<HP_C0>(a.l[0], a.l[1], d.m);
             const uint64_t r1 = res_normalise<HP_C1>(a.l[2], a.l[3], d.m);
             const uint64_t r2 = res_normalise<HP_C2>(a.l[4], a.l[5], d.m);

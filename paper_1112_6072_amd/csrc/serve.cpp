@@ -52,10 +52,11 @@ struct Batch {
 // H_per counters and its record buffer for `wide` leaves above order 16).
 size_t part_bytes(size_t nd, size_t words, size_t np, bool split, uint64_t wide) {
     auto al = [](size_t x) { return (std::max<size_t>(x, 1) + 255) / 256 * 256; };
-    size_t b = al(nd * sizeof(JobDesc)) + al((words + 64) * 4) + al(nd * 4) /*keys*/ + al(nd * 4) /*list*/ +
+    size_t b = al(nd * sizeof(JobDesc)) + al((words + 64) * 4) + al(nd * 4) /*bounds*/ + al(nd * 4) /*keys*/ +
+               al(nd * 4) /*list*/ +
                al(nd * 4) /*queue*/ + al(nd * 8) /*items*/ + al(nd * sizeof(JobAcc)) + al(64 * 8) /*heads*/ +
                al(np * sizeof(ProbAcc)) + 2048;
-    if (split) b += al(8 * 8) + al(split_wide_bytes(wide));
+    if (split) b += al(8 * 8) + al(split_wide_bytes(split_wide_capacity(wide, nd)));
     return b;
 }
 

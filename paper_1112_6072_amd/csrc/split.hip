@@ -1,10 +1,12 @@
-// Device continuation of Algorithm H_per (Section 2.1) below the host's cut-off, R-NW on the
-// leaves it reaches, and their sum per job (Step 4 of Algorithm PH, inside one job).
+// Device continuation of Algorithm H_per (Section 2.1) below the host's (or the device
+// expansion's) cut-off, R-NW on the leaves it reaches, and their exact sum per job (Step 4 of
+// Algorithm PH, inside one job).
 //
-// One wave takes one job (a sub-matrix B of order m <= HP_SPLIT_MAX_M, mod-2^64 arithmetic)
-// from a queue and rebuilds it densely in its LDS region. It walks the H_per expansion tree
-// of B depth first. At a node of order o, s is the smallest number of nonzeros in a row or a
-// column (ties: rows first, then the lowest index). s = 0 drops the node (per = 0); a node with
+// One wave takes one job (a sub-matrix B of order m <= HP_SPLIT_MAX_M) from a queue and
+// rebuilds it densely in its LDS region, from the R-NW job table of the host expansion or from
+// a node of the device expansion (hp_node_words). It walks the H_per expansion tree of B depth
+// first. At a node of order o, s is the smallest number of nonzeros in a row or a column
+// (ties: rows first, then the lowest index). s = 0 drops the node (per = 0); a node with
 // o <= t (the target order), o <= 2 or s >= s_leaf is a leaf; otherwise expansion (2) along
 // that line gives ceil(s/2) <= 2 children of order o - 1: consecutive nonzeros of the line are
 // paired and each pair's two columns (rows, for a column line) merged with crossed weights,
@@ -14,23 +16,29 @@
 // at slot o, with the nonzero bit masks of its rows and columns and its row sums, which the
 // child construction keeps up to date (so the line choice and the bound checks cost O(1) per
 // lane). A split whose children would hold an entry >= 2^22 or a row sum >= 2^24 is not made:
-// the node becomes a leaf (the bounds the host keeps for every job). Leaves above order 16
-// (rare: nodes whose lines all hold >= 5 nonzeros, or refused splits) are not evaluated by
-// this kernel: it records the job, the leaf's order and the path of child choices to it, and a
-// second kernel replays the path from the job's matrix and evaluates the leaf, which keeps
-// the wide row arrays out of the main kernel's registers.
+// the node becomes a leaf (the bounds the host keeps for every job).
 //
-// A leaf of order p is evaluated by the whole wave with the doubled Nijenhuis-Wilf form of
-// Ryser's formula (fixed column p - 1, Gray columns 0..p-2):
-//     V = sum_k (-1)^k prod_i f_i(gray(k)) = (-1)^(p-1) 2^(p-1) per(leaf).
-// Lane z walks the 2^(p-7) Gray indices of chunk z, odd chunks backwards. Then at step s every
-// lane flips Gray column ctz(s) and adds it exactly when bit ctz(s) + 1 of s is clear (both
-// hold in either direction of the reflected code), no lane's start subset holds a column below
-// p - 7, and the term of step s has the sign (-1)^(s + z). Rows beyond p are padded with f = 1.
-// Leaves are summed in the scale of the job,
-//     (-1)^(m-1) 2^(m-1) per(B) = sum_leaves (-1)^(m-p) 2^(m-p) V_leaf   (mod 2^64),
-// which is the value the per-item R-NW kernels leave in a job's accumulator, so the 2-adic
-// check and the recombination of the jobs are shared with them.
+// Exactness. Each leaf is normalised on its own: a leaf of order p is evaluated with the
+// doubled Nijenhuis-Wilf form of Ryser's formula (fixed column p - 1, Gray columns 0..p-2),
+//     V = sum_k (-1)^k prod_i f_i(gray(k)) = (-1)^(p-1) 2^(p-1) per(leaf),
+// modulo 2^64, which is exact when per(leaf) 2^(p-1) < 2^63. A proven bound decides it: the
+// smaller of the job's bound (per(leaf) <= per(B), all entries being non-negative) and the
+// leaf's product of row sums. Then per(leaf) = (-1)^(p-1) V / 2^(p-1), checked (non-negative,
+// divisible; a failure is counted and reported, never summed), and added to the job's sum in
+// 128-bit integers. For a leaf the bound does not admit, and for leaves above order 16, the
+// wave records the job, the leaf's order and the path of child choices to it, and a second
+// kernel replays the path and evaluates the leaf modulo 2^128 (exact for jobs whose bound is
+// below 2^102, which the host requires).
+//
+// Lane z of a leaf of order p >= 7 walks the 2^(p-7) Gray indices of chunk z, odd chunks
+// backwards. Then at step s every lane flips Gray column ctz(s) and adds it exactly when bit
+// ctz(s) + 1 of s is clear (both hold in either direction of the reflected code), no lane's
+// start subset holds a column below p - 7, and the term of step s has the sign (-1)^(s + z).
+// Rows beyond p are padded with f = 1. Leaves have order p >= t >= 7.
+//
+// Results: per-job values (JobAcc, flagged normalised) for the host's job tables; for the
+// device expansion's nodes, each wave sums its jobs' values per problem and adds them into the
+// problem accumulators (ProbAcc), and per-node values are written only when asked for.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -59,6 +67,8 @@ __host__ __device__ constexpr int region_words(int t, int mm) {
     return align4(sq(mm) - sq(t - 1)) + mm * dstride(mm) + (mm + 1 - t) * (CTL + 3 * mm) + SW;
 }
 
+typedef unsigned __int128 u128;
+
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ uint64_t uni64(uint64_t x) {
     return (uint64_t)uni((uint32_t)x) | ((uint64_t)uni((uint32_t)(x >> 32)) << 32);
@@ -76,6 +86,27 @@ __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
     return v;
 }
 
+__device__ __forceinline__ float wave_sumf(float v) {
+    for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Inclusive prefix sum over the lanes.
+__device__ __forceinline__ uint32_t wave_scan(uint32_t v, int lane) {
+    for (int o = 1; o < SW; o <<= 1) {
+        const uint32_t u = (uint32_t)__shfl_up((int)v, o);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// 128-bit sum over the lanes (as four 32-bit limb sums).
+__device__ __forceinline__ u128 wave_sum128(u128 v) {
+    const uint64_t a = wave_sum64((uint32_t)v), b = wave_sum64((uint32_t)(v >> 32));
+    const uint64_t c = wave_sum64((uint32_t)(v >> 64)), d = wave_sum64((uint32_t)(v >> 96));
+    return (u128)a + ((u128)b << 32) + ((u128)c << 64) + ((u128)d << 96);
+}
+
 // Among the lanes with `valid`, the lowest one holding the smallest count (count < 32): a
 // search over the count's bits with ballots (no LDS round trips). Writes that count.
 __device__ __forceinline__ uint32_t argmin_lane(uint32_t count, bool valid, uint32_t *minval) {
@@ -90,15 +121,21 @@ __device__ __forceinline__ uint32_t argmin_lane(uint32_t count, bool valid, uint
     return w;
 }
 
-// floor(e / d) for e < 1024, 1 <= d <= 32 (multiply by the rounded-up reciprocal: exact here).
-__device__ __forceinline__ uint32_t div_small(uint32_t e, uint32_t inv20) { return (e * inv20) >> 20; }
-
 // Product of the R row values modulo 2^64: pairs exactly in 64 bits (|f| < 2^24), then a chain.
 template <int R>
 __device__ __forceinline__ uint64_t row_product(const int32_t (&f)[R]) {
     uint64_t p = (uint64_t)((int64_t)f[0] * (int64_t)f[1]);
 #pragma unroll
     for (int k = 1; k < R / 2; ++k) p *= (uint64_t)((int64_t)f[2 * k] * (int64_t)f[2 * k + 1]);
+    return p;
+}
+
+// The same product modulo 2^128.
+template <int R>
+__device__ __forceinline__ u128 row_product128(const int32_t (&f)[R]) {
+    u128 p = (u128)(__int128)((int64_t)f[0] * (int64_t)f[1]);
+#pragma unroll
+    for (int k = 1; k < R / 2; ++k) p *= (u128)(__int128)((int64_t)f[2 * k] * (int64_t)f[2 * k + 1]);
     return p;
 }
 
@@ -161,6 +198,26 @@ __device__ __forceinline__ uint64_t walk_plain(int p, int lane, const int32_t *D
             const int j = __builtin_ctz(s2);
             add_rows<R>(f, D + j * ds, ((s2 >> (j + 1)) & 1) == 0);
             acc0 += row_product<R>(f);
+        }
+    }
+    return (lane & 1) ? acc1 - acc0 : acc0 - acc1;
+}
+
+// The same share modulo 2^128.
+template <int R>
+__device__ __forceinline__ u128 walk_plain128(int p, int lane, const int32_t *D, const int32_t *base, int ds) {
+    const uint32_t L = 1u << (p - 7);
+    int32_t f[R];
+    start_rows<R>(f, p, lane, D, base, ds);
+    u128 acc0 = row_product128<R>(f), acc1 = 0;
+    for (uint32_t s = 1; s < L; s += 2) {
+        add_rows<R>(f, D, ((s >> 1) & 1) == 0);
+        acc1 += row_product128<R>(f);
+        if (s + 1 < L) {
+            const uint32_t s2 = s + 1;
+            const int j = __builtin_ctz(s2);
+            add_rows<R>(f, D + j * ds, ((s2 >> (j + 1)) & 1) == 0);
+            acc0 += row_product128<R>(f);
         }
     }
     return (lane & 1) ? acc1 - acc0 : acc0 - acc1;
@@ -233,8 +290,8 @@ struct SplitCtl {   // word offsets in a control block
     enum { IS_COL, IDX, NP, P0, Q0, CA0, CB0, P1, Q1, CA1, CB1, NEXT };
 };
 
-// Job `job` as a dense m x m matrix in slot m (Gray columns 0..m-2, then the fixed column),
-// with its masks and row sums. Returns m.
+// Job `job` of a host job table as a dense m x m matrix in slot m (Gray columns 0..m-2, then
+// the fixed column), with its masks and row sums. Returns m.
 __device__ __forceinline__ int load_job(const Region &rg, const JobDesc *jobs, const uint32_t *data, uint32_t job, int lane) {
     const JobDesc jd = jobs[job];
     const int m = (int)uni(jd.m);
@@ -273,6 +330,37 @@ __device__ __forceinline__ int load_job(const Region &rg, const JobDesc *jobs, c
     if (lane == 0) rg.cmask(m)[m - 1] = (uint32_t)fixed_rows;
     wave_sync();
     return m;
+}
+
+// A node of the device expansion (hp_node_words) as a dense matrix in slot o, with its masks
+// and row sums: lane i reads row i. Returns o; *bound and *problem receive its header words.
+__device__ __forceinline__ int load_node(const Region &rg, const uint32_t *node, int lane, float *bound,
+                                         uint32_t *problem) {
+    const uint32_t h0 = uni(node[0]);
+    const int o = (int)(h0 & 0xffu);
+    *bound = __uint_as_float(uni(node[1]));
+    *problem = uni(node[2]);
+    uint32_t *M = rg.slot(o);
+    for (int e = lane; e < o * o; e += SW) M[e] = 0;
+    if (lane < rg.mw) rg.cmask(o)[lane] = 0;
+    const uint32_t len = lane < o ? (node[4 + lane / 4] >> (8 * (lane & 3))) & 0xffu : 0u;
+    const uint32_t start = wave_scan(len, lane) - len;
+    const uint32_t *ent = node + 4 + (o + 3) / 4;
+    wave_sync();
+    uint32_t rm = 0, rs = 0;
+    for (uint32_t e = 0; e < len; ++e) {
+        const uint32_t w = ent[start + e], j = w & 0xffu, v = w >> 8;
+        M[lane * o + j] = v;
+        rm |= 1u << j;
+        rs += v;
+        atomicOr(rg.cmask(o) + j, 1u << lane);
+    }
+    if (lane < o) {
+        rg.rmask(o)[lane] = rm;
+        rg.rsum(o)[lane] = rs;
+    }
+    wave_sync();
+    return o;
 }
 
 // Step 1 of H_per at the node of order o: returns (count << 6) | (32 * is_col + index) of the
@@ -447,7 +535,7 @@ __device__ __forceinline__ void make_child(const Region &rg, int o, const Plan &
 // Leaf tables in LDS: D[j][i] = 2 b_ij for Gray column j (rows beyond p: 0) and
 // base_i = 2 b_{i,p-1} - R_i (rows beyond p: 1, so f = 1), with the leaf's sparsest Gray
 // column moved to Gray column 0 and the rows it touches moved to the front (the product is
-// invariant under both permutations). Returns that column's nonzero count b.
+// invariant under both permutations). Returns that column's nonzero count b. Needs p >= 2.
 __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, int lane) {
     const uint32_t *M = rg.slot(p);
     const uint32_t cmk = lane < p - 1 ? rg.cmask(p)[lane] : 0u;
@@ -480,7 +568,8 @@ __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, int lan
     return b;
 }
 
-// This lane's share of V = (-1)^(p-1) 2^(p-1) per(leaf) for a leaf of order 7 <= p <= PMAX.
+// This lane's share of V = (-1)^(p-1) 2^(p-1) per(leaf) modulo 2^64 for a leaf of order
+// 7 <= p <= PMAX.
 __device__ __forceinline__ uint64_t eval_leaf(const Region &rg, int p, int lane) {
     const uint32_t b = leaf_tables(rg, p, lane);
     uint64_t v;
@@ -494,71 +583,137 @@ __device__ __forceinline__ uint64_t eval_leaf(const Region &rg, int p, int lane)
     return v;
 }
 
-__device__ __forceinline__ uint64_t scale_to_job(uint64_t v, int m, int p) {
-    const int sh = m - p;
-    v <<= sh;
-    return (sh & 1) ? (uint64_t)0 - v : v;
+// Proven log2 upper bound of the product of the row sums of the node of order o.
+__device__ __forceinline__ float rowsum_log2(const Region &rg, int o, int lane) {
+    const float x = lane < o ? __log2f((float)rg.rsum(o)[lane]) : 0.0f;   // row sums < 2^24: exact
+    return wave_sumf(x) + 1e-3f;   // margin for the hardware logarithm and the float sum
 }
 
-// A deferred wide leaf: the job, the leaf's order and the child index taken at every order
-// above it (bit m - o for the split at order o). A job of order m can defer at most
-// 2^(m-16) - 1 of them (the nodes of orders 17..m, at most two children per split).
+// per(leaf) from its wave-summed V modulo 2^64: (-1)^(p-1) V / 2^(p-1) after the checks that
+// the bound guarantees (non-negative, divisible). *bad is set when a check fails.
+__device__ __forceinline__ uint64_t normalise64(uint64_t V, int p, bool *bad) {
+    const int sh = p - 1;
+    if (sh & 1) V = (uint64_t)0 - V;
+    const bool ok = (int64_t)V >= 0 && (sh == 0 || (V & ((1ull << sh) - 1)) == 0);
+    *bad = !ok;
+    return ok ? V >> sh : 0;
+}
+
+__device__ __forceinline__ u128 normalise128(u128 V, int p, bool *bad) {
+    const int sh = p - 1;
+    if (sh & 1) V = (u128)0 - V;
+    const bool ok = (V >> 127) == 0 && (sh == 0 || (V & (((u128)1 << sh) - 1)) == 0);
+    *bad = !ok;
+    return ok ? V >> sh : 0;
+}
+
+// Adds v (a 128-bit per value) as 32-bit limbs into four 64-bit limb sums.
+__device__ __forceinline__ void add_limbs(unsigned long long *l, u128 v) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const unsigned long long x = (uint32_t)(v >> (32 * k));
+        if (x) atomicAdd(l + k, x);
+    }
+}
+
+// A deferred leaf: the job, the leaf's order and the child index taken at every order above it
+// (bit m - o for the split at order o).
 struct WideLeaf {
     uint32_t job;
     uint32_t order_path;   // order | path << 8
 };
 
-__global__ __launch_bounds__(SW) void hper_split_w64(const JobDesc *__restrict__ jobs,
-                                                     const uint32_t *__restrict__ data,
-                                                     const uint32_t *__restrict__ queue, uint32_t nqueue,
-                                                     int t, int s_leaf, unsigned long long *head,
-                                                     JobAcc *__restrict__ accs,
-                                                     unsigned long long *__restrict__ stats,
-                                                     WideLeaf *__restrict__ wide, uint32_t wide_cap,
-                                                     unsigned long long *__restrict__ cycles, int mm) {
+}  // namespace
+
+// Arguments of the two kernels (shared by both job sources).
+struct SplitArgs {
+    const JobDesc *jobs;          // host job table (node source: null)
+    const uint32_t *data;
+    const float *job_bound;       // per host job: its proven log2 bound (rounded up)
+    const uint32_t *nodes;        // device expansion's nodes (host source: null)
+    const uint64_t *node_off;     // word offset of every node
+    const uint32_t *queue;        // host source: job ids in queue order
+    uint32_t n;                   // jobs in the queue, or nodes
+    uint32_t njobs;               // host source: size of the job table
+    int t, s_leaf, mm;
+    unsigned long long *head;     // cleared queue counter
+    JobAcc *accs;                 // per-job values (nullable for nodes)
+    ProbAcc *probs;               // per-problem sums (nodes only)
+    unsigned long long *stats;    // 8 counters, cleared
+    WideLeaf *wide;
+    uint32_t wide_cap;
+    unsigned long long *cycles;   // nullable
+};
+
+namespace {
+
+// The job's dense matrix in its top slot, its bound and its problem; returns its order.
+template <bool NODES>
+__device__ __forceinline__ int load_source(const Region &rg, const SplitArgs &a, uint32_t job, int lane,
+                                           float *jb, uint32_t *problem) {
+    if constexpr (NODES) {
+        return load_node(rg, a.nodes + uni64(a.node_off[job]), lane, jb, problem);
+    } else {
+        *jb = __uint_as_float(uni(__float_as_uint(a.job_bound[job])));
+        *problem = 0;
+        return load_job(rg, a.jobs, a.data, job, lane);
+    }
+}
+
+template <bool NODES>
+__global__ __launch_bounds__(SW) void hper_split(SplitArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    const Region rg(lds, t, mm);
-    uint64_t n_leaves = 0, n_terms = 0, n_splits = 0, n_stops = 0;
+    const Region rg(lds, a.t, a.mm);
+    uint64_t n_leaves = 0, n_terms = 0, n_splits = 0, n_stops = 0, n_bad = 0, n_wide = 0;
+    u128 pacc = 0;            // this wave's sum for problem pcur (nodes)
+    uint32_t pcur = 0xffffffffu;
     for (;;) {
-        const unsigned long long got = atomicAdd(head, lane == 0 ? 1ull : 0ull);
+        const unsigned long long got = atomicAdd(a.head, lane == 0 ? 1ull : 0ull);
         const uint64_t qi = uni64(got);
-        if (qi >= nqueue) break;
-        const uint32_t job = uni(queue[qi]);
+        if (qi >= a.n) break;
+        const uint32_t job = NODES ? (uint32_t)qi : uni(a.queue[qi]);
         const uint64_t t0 = (uint64_t)clock64();
-        const int m0 = load_job(rg, jobs, data, job, lane);
-        uint64_t acc = 0;
+        float jb;
+        uint32_t problem;
+        const int m0 = load_source<NODES>(rg, a, job, lane, &jb, &problem);
+        u128 acc = 0;   // per(B): the sum of the normalised leaves (wave-uniform)
         int o = m0;
         Plan pl;
         for (;;) {
             const uint32_t key = sparsest_line(rg, o, lane);
             const uint32_t s = key >> 6;
-            bool leaf = false;
-            if (s == 0) {
-                // dropped: per = 0
-            } else if (o <= t || o <= 2 || (int)s >= s_leaf || s > 4) {
-                leaf = true;
-            } else if (plan_split(rg, o, key, lane, pl)) {
-                make_child(rg, o, pl, 0, lane);
-                ++n_splits;
-                --o;
-                continue;
-            } else {
-                leaf = true;
-                ++n_stops;
-            }
-            if (leaf) {
-                ++n_leaves;
-                n_terms += 1ull << (o - 1);
-                if (o <= PMAX) {
-                    acc += scale_to_job(eval_leaf(rg, o, lane), m0, o);
-                } else {
-                    uint32_t path = 0;
-                    for (int u = o + 1; u <= m0; ++u) path |= uni(rg.ctl(u)[SplitCtl::NEXT]) << (m0 - u);
-                    if (lane == 0) {
-                        const unsigned long long w = atomicAdd(stats + 4, 1ull);
-                        if (w < wide_cap) wide[w] = WideLeaf{job, (uint32_t)o | (path << 8)};
-                        else atomicAdd(stats + 5, 1ull);   // never: the buffer holds the bound
+            if (s != 0) {
+                bool leaf = o <= a.t || o <= 2 || (int)s >= a.s_leaf || s > 4;
+                if (!leaf) {
+                    if (plan_split(rg, o, key, lane, pl)) {
+                        make_child(rg, o, pl, 0, lane);
+                        ++n_splits;
+                        --o;
+                        continue;
+                    }
+                    ++n_stops;   // refused by the entry bounds: evaluated whole
+                }
+                {
+                    ++n_leaves;
+                    n_terms += 1ull << (o - 1);
+                    // exact modulo 2^64 when per(leaf) 2^(o-1) < 2^63 (bound: the job's, or the
+                    // leaf's product of row sums)
+                    const bool ok64 = fminf(jb, rowsum_log2(rg, o, lane)) + (float)o <= 62.5f;
+                    if (ok64 && o <= PMAX) {
+                        bool bad;
+                        const uint64_t per = normalise64(uni64(wave_sum64(eval_leaf(rg, o, lane))), o, &bad);
+                        n_bad += bad;
+                        acc += per;
+                    } else {   // replayed by the second kernel in 128-bit arithmetic
+                        ++n_wide;
+                        uint32_t path = 0;
+                        for (int u = o + 1; u <= m0; ++u) path |= uni(rg.ctl(u)[SplitCtl::NEXT]) << (m0 - u);
+                        if (lane == 0) {
+                            const unsigned long long w = atomicAdd(a.stats + 4, 1ull);
+                            if (w < a.wide_cap) a.wide[w] = WideLeaf{job, (uint32_t)o | (path << 8)};
+                            else atomicAdd(a.stats + 5, 1ull);   // reported as an error
+                        }
                     }
                 }
             }
@@ -576,54 +731,72 @@ __global__ __launch_bounds__(SW) void hper_split_w64(const JobDesc *__restrict__
             if (up > m0) break;
             o = up - 1;
         }
-        const uint64_t total = wave_sum64(acc);
         if (lane == 0) {
-            accs[job].l[0] = total;
-            if (cycles) cycles[job] = (unsigned long long)((uint64_t)clock64() - t0);
+            if (a.accs) {
+                JobAcc *ja = a.accs + job;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) ja->l[k] = (uint32_t)(acc >> (32 * k));
+                ja->flag = HP_ACC_NORMALISED;
+            }
+            if (a.cycles) a.cycles[job] = (unsigned long long)((uint64_t)clock64() - t0);
+        }
+        if constexpr (NODES) {
+            if (problem != pcur) {
+                if (lane == 0 && pcur != 0xffffffffu) add_limbs(a.probs[pcur].lim, pacc);
+                pcur = problem;
+                pacc = 0;
+            }
+            pacc += acc;
         }
     }
     if (lane == 0) {
-        atomicAdd(stats + 0, (unsigned long long)n_leaves);
-        atomicAdd(stats + 1, (unsigned long long)n_terms);
-        atomicAdd(stats + 2, (unsigned long long)n_splits);
-        atomicAdd(stats + 3, (unsigned long long)n_stops);
+        if (NODES && pcur != 0xffffffffu) add_limbs(a.probs[pcur].lim, pacc);
+        atomicAdd(a.stats + 0, (unsigned long long)n_leaves);
+        atomicAdd(a.stats + 1, (unsigned long long)n_terms);
+        atomicAdd(a.stats + 2, (unsigned long long)n_splits);
+        atomicAdd(a.stats + 3, (unsigned long long)n_stops);
+        if (n_bad) atomicAdd(a.stats + 6, (unsigned long long)n_bad);
+        if (n_wide) atomicAdd(a.stats + 7, (unsigned long long)n_wide);
     }
 }
 
-// The deferred wide leaves: each wave replays one leaf's path from its job's matrix (the same
-// line choices and pairs) and adds the leaf's scaled value to the job.
-__global__ __launch_bounds__(SW) void hper_split_wide_w64(const JobDesc *__restrict__ jobs,
-                                                          const uint32_t *__restrict__ data, int t,
-                                                          const unsigned long long *__restrict__ stats,
-                                                          const WideLeaf *__restrict__ wide, uint32_t wide_cap,
-                                                          uint32_t njobs, JobAcc *__restrict__ accs, int mm) {
+// The deferred leaves: each wave replays one leaf's path from its job's matrix (the same
+// line choices and pairs), evaluates the leaf modulo 2^128 and adds its normalised value to
+// the job (and, for nodes, to the problem).
+template <bool NODES>
+__global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    const Region rg(lds, t, mm);
-    const uint64_t n = min((uint64_t)stats[4], (uint64_t)wide_cap);
+    const Region rg(lds, a.t, a.mm);
+    const uint64_t n = min((uint64_t)a.stats[4], (uint64_t)a.wide_cap);
     for (uint64_t w = blockIdx.x; w < n; w += gridDim.x) {
-        const WideLeaf wl = wide[w];
+        const WideLeaf wl = a.wide[w];
         const uint32_t job = uni(wl.job), op = uni(wl.order_path);
         const int p = (int)(op & 0xffu);
         const uint32_t path = op >> 8;
-        if (job >= njobs) continue;
-        const int m0 = load_job(rg, jobs, data, job, lane);
-        if (p < HP_SPLIT_MIN_T || p > m0 || m0 > mm) continue;
+        if (job >= (NODES ? a.n : a.njobs)) continue;
+        float jb;
+        uint32_t problem;
+        const int m0 = load_source<NODES>(rg, a, job, lane, &jb, &problem);
+        if (p < 7 || p > m0 || m0 > a.mm) continue;
         Plan pl;
         for (int o = m0; o > p; --o) {
             if (!plan_split(rg, o, sparsest_line(rg, o, lane), lane, pl)) break;   // not reached: the
             make_child(rg, o, pl, (int)((path >> (m0 - o)) & 1), lane);           // first pass split here
         }
-        const uint32_t b = leaf_tables(rg, p, lane);
-        uint64_t v;   // rows padded to the table's stride (20 or 24), never beyond it
-        if (rg.ds == 20)
-            v = b <= 4 && p >= 8 ? walk_paired<20, 4>(p, lane, rg.D, rg.base, rg.ds)
-                                 : walk_plain<20>(p, lane, rg.D, rg.base, rg.ds);
-        else
-            v = b <= 4 && p >= 8 ? walk_paired<SMAX, 4>(p, lane, rg.D, rg.base, rg.ds)
-                                 : walk_plain<SMAX>(p, lane, rg.D, rg.base, rg.ds);
-        const uint64_t total = wave_sum64(scale_to_job(v, m0, p));
-        if (lane == 0) atomicAdd(&accs[job].l[0], (unsigned long long)total);
+        leaf_tables(rg, p, lane);
+        u128 v;   // rows padded to the table's stride (20 or 24), never beyond it
+        if (rg.ds == 20) v = walk_plain128<20>(p, lane, rg.D, rg.base, rg.ds);
+        else v = walk_plain128<SMAX>(p, lane, rg.D, rg.base, rg.ds);
+        const u128 V = wave_sum128(v);
+        bool bad;
+        const u128 per = normalise128(V, p, &bad);
+        if (lane == 0) {
+            if (bad) atomicAdd(a.stats + 6, 1ull);
+            if (a.accs) add_limbs(a.accs[job].l, per);
+            if (NODES) add_limbs(a.probs[problem].lim, per);
+        }
+        wave_sync();
     }
 }
 
@@ -644,27 +817,65 @@ static hipError_t resident_grid(const void *fn, size_t lds, uint64_t *grid) {
     return hipSuccess;
 }
 
-hipError_t launch_split_w64(const JobDesc *jobs, const uint32_t *data, const uint32_t *queue, uint32_t n,
-                            uint32_t njobs, int t, int mm, int s_leaf, unsigned long long *head, JobAcc *accs,
-                            unsigned long long *stats, void *wide, uint64_t wide_entries,
-                            unsigned long long *cycles, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    if (t < HP_SPLIT_MIN_T || t >= HP_SPLIT_MAX_M || mm <= t || mm > HP_SPLIT_MAX_M) return hipErrorInvalidValue;
-    const size_t lds = split_lds_bytes(t, mm);
-    const uint32_t cap = (uint32_t)(wide_entries < 0xffffffffull ? wide_entries : 0xffffffffull);
+template <bool NODES>
+static hipError_t launch_split_pair(const SplitArgs &a, hipStream_t s) {
+    if (a.n == 0) return hipSuccess;
+    if (a.t < HP_SPLIT_MIN_T || a.t >= HP_SPLIT_MAX_M || a.mm <= a.t || a.mm > HP_SPLIT_MAX_M) return hipErrorInvalidValue;
+    const size_t lds = split_lds_bytes(a.t, a.mm);
     uint64_t grid = 0;
-    hipError_t e = resident_grid((const void *)hper_split_w64, lds, &grid);
+    hipError_t e = resident_grid((const void *)hper_split<NODES>, lds, &grid);
     if (e != hipSuccess) return e;
-    if (grid > n) grid = n;
-    hipLaunchKernelGGL(hper_split_w64, dim3((uint32_t)grid), dim3(SW), lds, s, jobs, data, queue, n, t, s_leaf,
-                       head, accs, stats, (WideLeaf *)wide, cap, cycles, mm);
+    if (grid > a.n) grid = a.n;
+    hipLaunchKernelGGL(hper_split<NODES>, dim3((uint32_t)grid), dim3(SW), lds, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = resident_grid((const void *)hper_split_wide_w64, lds, &grid);
+    e = resident_grid((const void *)hper_split_wide<NODES>, lds, &grid);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hper_split_wide_w64, dim3((uint32_t)grid), dim3(SW), lds, s, jobs, data, t,
-                       (const unsigned long long *)stats, (const WideLeaf *)wide, cap, njobs, accs, mm);
+    hipLaunchKernelGGL(hper_split_wide<NODES>, dim3((uint32_t)grid), dim3(SW), lds, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_split_jobs(const JobDesc *jobs, const uint32_t *data, const float *job_bound, const uint32_t *queue,
+                             uint32_t n, uint32_t njobs, int t, int mm, int s_leaf, unsigned long long *head,
+                             JobAcc *accs, unsigned long long *stats, void *wide, uint64_t wide_entries,
+                             unsigned long long *cycles, hipStream_t s) {
+    SplitArgs a{};
+    a.jobs = jobs;
+    a.data = data;
+    a.job_bound = job_bound;
+    a.queue = queue;
+    a.n = n;
+    a.njobs = njobs;
+    a.t = t;
+    a.s_leaf = s_leaf;
+    a.mm = mm;
+    a.head = head;
+    a.accs = accs;
+    a.stats = stats;
+    a.wide = (WideLeaf *)wide;
+    a.wide_cap = (uint32_t)(wide_entries < 0xffffffffull ? wide_entries : 0xffffffffull);
+    a.cycles = cycles;
+    return launch_split_pair<false>(a, s);
+}
+
+hipError_t launch_split_nodes(const uint32_t *nodes, const uint64_t *node_off, uint32_t n, int t, int mm, int s_leaf,
+                              unsigned long long *head, JobAcc *accs, ProbAcc *probs, unsigned long long *stats,
+                              void *wide, uint64_t wide_entries, hipStream_t s) {
+    SplitArgs a{};
+    a.nodes = nodes;
+    a.node_off = node_off;
+    a.n = n;
+    a.njobs = n;
+    a.t = t;
+    a.s_leaf = s_leaf;
+    a.mm = mm;
+    a.head = head;
+    a.accs = accs;
+    a.probs = probs;
+    a.stats = stats;
+    a.wide = (WideLeaf *)wide;
+    a.wide_cap = (uint32_t)(wide_entries < 0xffffffffull ? wide_entries : 0xffffffffull);
+    return launch_split_pair<true>(a, s);
 }
 
 }  // namespace hp
