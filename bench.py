@@ -56,11 +56,39 @@ def traffic_from_profile():
         return None
 
 
+def cpu_threads() -> int:
+    """Host threads of the oracle: the job's CPU share (OMP_NUM_THREADS, set to the box's share),
+    else every core."""
+    n = os.cpu_count() or 1
+    try:
+        share = int(os.environ.get("OMP_NUM_THREADS", "0"))
+    except ValueError:
+        share = 0
+    return max(1, min(n, share) if share > 0 else n)
+
+
+def cpu_oracle_batch(mats, terms):
+    """The oracle's C Algorithm H_per (oracle/hper_c.c) over the whole benchmark batch on the
+    host's cores: its per(A) wall time, and the batch's R-NW subset-terms divided by it (the
+    rate at which the oracle finishes the same work, in the metric's unit)."""
+    from oracle import native
+    threads = cpu_threads()
+    native.hper_batch(mats[:1], threads=threads)   # load and warm the library
+    t0 = time.time()
+    vals = native.hper_batch(mats, threads=threads)
+    dt = time.time() - t0
+    return vals, {"value": terms / dt, "unit": "subset-terms/s", "cores": threads, "kind": "oracle",
+                  "nproc": os.cpu_count(), "per_a_wall_ms_batch": dt * 1e3,
+                  "sample": f"the whole benchmark batch (17 cubic graphs on 60 vertices) by the C H_per "
+                            f"oracle on {threads} threads: per(A) of every problem in {dt:.2f} s; value = "
+                            f"the batch's {terms:.3e} R-NW subset-terms of order-20 jobs / that time"}
+
+
 def cpu_baseline(m_cut: int, budget_s: float = 20.0):
     """The C Ryser oracle on the first jobs (expansion order) of the truncated icosahedron."""
     import workloads as W
     from oracle import expand_leaves, native
-    threads = max(1, min(os.cpu_count() or 1, 16))
+    threads = cpu_threads()
     A = W.adjacency_matrix(W.truncated_icosahedron())
     leaves = expand_leaves(A, m_cut, limit=512)
     # size the sample from a one-job probe so the run stays near the budget
@@ -243,6 +271,40 @@ def device_hper(hp, ctx, jobs, want, mats, golden_vals, keys, targets=(10, 12, 1
     return out
 
 
+def large_single(hp, W, seeds=(0,)):
+    """The large single problems on the device path (expansion on the device to order 22, the
+    device continuation of H_per to order 12): the paper's C100 (its printed per(A) is the
+    check) and random cubic graphs on 100 vertices (checked against the Schrijver and Bregman
+    bounds; their first jobs equal the oracle's in the tests). One run each."""
+    import torch
+    C100 = 149364113290700
+    out = {}
+    ctx = hp.Context({"split_order": 12, "device_expand": 22, "device_expand_mib": 16384})
+    try:
+        probs = [("c100", W.adjacency_matrix(W.read_appendix_adjacency("c100")))]
+        probs += [(f"cubic100_seed{s}", W.random_cubic_matrix(100, s)) for s in seeds]
+        for name, A in probs:
+            log("large single problem", name)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v, st = ctx.permanent_batch([A], with_stats=True)
+            wall = time.perf_counter() - t0
+            L = [l for l in ctx.last_launches() if l["variant"] == 4][-1]
+            n = A.shape[0]
+            rec = {"per": str(v[0]), "per_a_wall_s": wall, "jobs_order22": int(L["n_jobs"]),
+                   "expansion_nodes": int(L["items"]), "device_hper_launches": int(L["row_updates"]),
+                   "leaves": int(L["leaves"]), "leaf_subset_terms": int(L["leaf_terms"]),
+                   "splits": int(L["splits"]), "device_hper_s": L["alg_slots"] * 1e-3}
+            if name == "c100":
+                rec["equals_paper"] = v[0] == C100
+            else:
+                rec["within_schrijver_bregman"] = (4 / 3) ** n <= v[0] <= 6 ** (n / 3)
+            out[name] = rec
+    finally:
+        ctx.close()
+    return out
+
+
 def copy_probe(nbytes: int = 256 << 20, reps: int = 3):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -263,6 +325,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip C100 and the random cubic n=100 problem")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device-to-device copy of 256 MiB three times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -289,12 +352,13 @@ def main():
     golden = json.load(open(golden_path)) if os.path.exists(golden_path) else {}
 
     # the R-NW measurements run with the device continuation of H_per off (split_order 0);
-    # per(A) is timed on the library's default path (split_order 12) and on the R-NW-only one
-    ctx = hp.Context({"m_cut": args.m_cut, "trials": args.trials, "split_order": 0})
+    # per(A) is timed on the library's default path (device expansion to order 22, device H_per
+    # to order 12) and beside it on the host-expansion paths and the R-NW-only one
+    ctx = hp.Context({"m_cut": args.m_cut, "trials": args.trials, "split_order": 0, "device_expand": 0})
 
     # ---- per(A) wall time, host CSR -> exact integers (expansion and copies included)
-    def per_a_batch(split, m_cut=args.m_cut):
-        ctx.set_opts(split_order=split, m_cut=m_cut)
+    def per_a_batch(split, m_cut=args.m_cut, dexp=0):
+        ctx.set_opts(split_order=split, m_cut=m_cut, device_expand=dexp)
         try:
             ctx.permanent_batch(mats)   # warm-up
             walls = []
@@ -304,17 +368,18 @@ def main():
                 v, st = ctx.permanent_batch(mats, with_stats=True)
                 walls.append(time.perf_counter() - t0)
         finally:
-            ctx.set_opts(split_order=0, m_cut=args.m_cut)
+            ctx.set_opts(split_order=0, m_cut=args.m_cut, device_expand=0)
         return sorted(walls)[2], v, st   # median of 5
     log("per(A) end to end")
-    # the host expands to order 22 (fewer jobs: its time is linear in them) and the device
-    # continues H_per down to order 12; beside it the library defaults (host to 20) and R-NW only
-    e2e, vals, stats = per_a_batch(12, 22)
+    e2e, vals, _ = per_a_batch(12, dexp=22)          # the library default
+    # the host expands to order 22 (fewer jobs: its time is linear in them), the device
+    # continues H_per to order 12; the host to order 20; every job by R-NW
+    e2e_h22, vals_h22, stats = per_a_batch(12, 22)
     e2e_m20, vals_m20, _ = per_a_batch(12)
     e2e_rnw, vals_rnw, _ = per_a_batch(0)
     exp_s = stats[0]["t_expand_s"]
     verified = (bool(golden) and all(int(golden[n]) == v for n, v in zip(names, vals)) and vals_rnw == vals
-                and vals_m20 == vals)
+                and vals_m20 == vals and vals_h22 == vals)
 
     # ---- the timed step: jobs resident in HBM
     jobs = ctx.expand(mats)
@@ -368,8 +433,8 @@ def main():
     extra["uneven_jobs"] = uneven_orders(hp, W, ctx)
     # one problem alone: the truncated icosahedron (C60), median of 5 after a warm-up, on the
     # default path and on the R-NW-only one
-    def c60_alone(split):
-        ctx.set_opts(split_order=split)
+    def c60_alone(split, dexp=0):
+        ctx.set_opts(split_order=split, device_expand=dexp)
         try:
             ctx.permanent(mats[0])
             walls1 = []
@@ -379,11 +444,12 @@ def main():
                 v = ctx.permanent(mats[0])
                 walls1.append(time.perf_counter() - t0)
         finally:
-            ctx.set_opts(split_order=0)
+            ctx.set_opts(split_order=0, device_expand=0)
         return sorted(walls1)[2], v
-    e2e_c60, c60 = c60_alone(12)
+    e2e_c60, c60 = c60_alone(12, 22)
+    e2e_c60_host, c60_host = c60_alone(12)
     e2e_c60_rnw, c60_rnw = c60_alone(0)
-    verified = verified and c60 == vals[0] and c60_rnw == vals[0]
+    verified = verified and c60 == vals[0] and c60_rnw == vals[0] and c60_host == vals[0]
     # permanental polynomial per(xI - A) of a random cubic graph on 24 vertices (25 exact
     # evaluations of per(xI + A) in one batch, then exact interpolation); median of 5
     G24 = W.random_cubic_matrix(24, 0)
@@ -425,10 +491,17 @@ def main():
         log("serving: burst, then Poisson arrivals at half the measured capacity")
         serving = serving_leg(hp, W)
 
-    cpu = None
+    large = None
+    if not args.no_large:
+        large = large_single(hp, W)
+
+    cpu = cpu_ryser = None
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle)")
-        cpu = cpu_baseline(args.m_cut)
+        log("cpu baseline (oracle): C H_per over the whole batch")
+        cpu_vals, cpu = cpu_oracle_batch(mats, terms)
+        verified = verified and cpu_vals == vals
+        log("cpu baseline (oracle): plain Ryser on a sample of jobs")
+        cpu_ryser = cpu_baseline(args.m_cut)
 
     out = {
         "metric": "Ryser subset-terms/sec + per(A) wall time (n=60 cubic), batched-LPT vs plain",
@@ -451,9 +524,13 @@ def main():
         "per_a_wall_ms_batch": e2e * 1e3,
         "per_a_wall_ms_per_problem": e2e * 1e3 / len(mats),
         "per_a_wall_ms_c60_alone": e2e_c60 * 1e3,
-        "per_a_path": "host expansion to order 22, H_per continued on the device to order 12",
+        "per_a_path": "the library default: expansion on the device to order 22, H_per continued on "
+                      "the device to order 12",
+        "per_a_wall_ms_batch_host22": e2e_h22 * 1e3,
         "per_a_wall_ms_batch_m_cut20": e2e_m20 * 1e3,
         "per_a_wall_ms_batch_rnw_only": e2e_rnw * 1e3,
+        "per_a_wall_ms_batch_cpu_oracle": cpu["per_a_wall_ms_batch"] if cpu else None,
+        "per_a_wall_ms_c60_alone_host22": e2e_c60_host * 1e3,
         "per_a_wall_ms_c60_alone_rnw_only": e2e_c60_rnw * 1e3,
         "host_expand_ms_batch": exp_s * 1e3,
         "rnw_ms_per_step": rnw_ms,
@@ -471,6 +548,8 @@ def main():
                      "avg_launch_ms": avg_ms, "alg_slots_per_launch": alg_per_launch,
                      "jobs_per_launch": dom["jobs"] // dom["n"], "terms_per_launch": dom["terms"] // dom["n"]},
         "cpu_baseline": cpu,
+        "cpu_baseline_ryser_sample": cpu_ryser,
+        "large_single_problems": large,
         "serving": serving,
     }
     out.update(extra)

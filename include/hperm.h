@@ -91,14 +91,15 @@ typedef struct hperm_opts {
                              take the R-NW queue. Results are unchanged (the expansion is an
                              identity). 0: off, every job by R-NW. Ignored when s_leaf > 5 and by
                              one-launch-per-job runs. */
-    int32_t device_expand;/* T in [split_order + 1, 24], or 0 (default: off): the blocking calls
-                             (hperm_permanent_csr / _dense / _batch_csr) expand every problem of
-                             order n > T whose proven bound is below 2^102 on the device instead
-                             of the host: expansion (2) with Algorithm H_per's line rule (Section
-                             2.1) level by level down to sub-matrices of order T, which the device
-                             continuation of H_per finishes (split_order must be set); the whole
-                             tree stays on the GPU in bounded memory. Other problems take the host
-                             path. Results are the same integers. */
+    int32_t device_expand;/* T in [0, 24] (default 22): when T exceeds the split order in
+                             effect, the blocking calls (hperm_permanent_csr / _dense / _batch_csr)
+                             expand every problem of order n > T whose proven bound is below
+                             2^102 on the device instead of the host: expansion (2) with Algorithm
+                             H_per's line rule (Section 2.1) level by level down to sub-matrices
+                             of order T, which the device continuation of H_per finishes; the
+                             whole tree stays on the GPU in bounded memory. Other problems (and
+                             the serving loop) take the host path. Results are the same
+                             integers. 0 (or T <= split order): off. */
     int32_t device_expand_mib; /* device memory for the expansion's level buffers in MiB
                              (0 = 8192); more memory means fewer, larger launches */
 } hperm_opts;

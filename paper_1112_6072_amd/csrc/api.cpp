@@ -876,6 +876,8 @@ hperm_status hperm_default_opts(hperm_opts *o) {
     o->persistent = 1;
     o->host_threads = 0;
     o->split_order = 12;
+    o->device_expand = 22;
+    o->device_expand_mib = 0;
     return HPERM_OK;
 }
 
@@ -892,9 +894,7 @@ static const char *check_opts(const hperm_opts *o) {
     if (o->time_jobs != 0 && o->time_jobs != 1) return "time_jobs must be 0 or 1";
     if (o->split_order != 0 && (o->split_order < HP_SPLIT_MIN_T || o->split_order >= HP_SPLIT_MAX_M))
         return "split_order must be 0 or in [7, 23]";
-    if (o->device_expand != 0 &&
-        (o->split_order == 0 || o->device_expand <= o->split_order || o->device_expand > HP_SPLIT_MAX_M))
-        return "device_expand must be 0 or in [split_order + 1, 24] with split_order set";
+    if (o->device_expand < 0 || o->device_expand > HP_SPLIT_MAX_M) return "device_expand must be in [0, 24]";
     if (o->device_expand_mib < 0) return "device_expand_mib must be >= 0";
     return nullptr;
 }
@@ -1074,9 +1074,17 @@ static hperm_status batch_host_path(hperm_ctx *c, int32_t count, const int32_t *
     return HPERM_OK;
 }
 
+// The job order of the device expansion in effect: device_expand when it exceeds the split
+// order in effect, else 0 (off).
+static int device_in_effect(const hperm_opts &o) {
+    const int t = split_in_effect(o);
+    return (t > 0 && o.device_expand > t) ? o.device_expand : 0;
+}
+
 // Problems the device expansion takes: order above T and a proven bound below 2^102.
 static bool device_path(const hperm_opts &o, const CsrView &v) {
-    if (o.device_expand <= 0 || split_in_effect(o) <= 0 || v.n <= o.device_expand) return false;
+    const int T = device_in_effect(o);
+    if (T <= 0 || v.n <= T) return false;
     std::vector<uint32_t> root;
     double lb = 0.0;
     const int rc = pack_root_node(v, &root, &lb);
@@ -1126,14 +1134,14 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
         CsrView v{n[k], row_ptr + rp_off[k], col_idx + nz_off[k], val + nz_off[k]};
         U512 total;
         DexpStats st;
-        hperm_status s = device_expand_problem(&c->dev, v, c->opts.device_expand, split_in_effect(c->opts),
+        hperm_status s = device_expand_problem(&c->dev, v, device_in_effect(c->opts), split_in_effect(c->opts),
                                                c->opts.s_leaf, budget, &total, &st);
         if (s) return s;
         hperm_result &r = res[k];
         memset(&r, 0, sizeof(r));
         fill_result(total, &r);
         r.n_jobs = (int32_t)std::min<uint64_t>(st.jobs, 0x7fffffff);
-        r.max_m = c->opts.device_expand;
+        r.max_m = device_in_effect(c->opts);
         r.arith_mask = 1 << (HPERM_ARITH_W64);
         r.subset_terms = st.leaf_terms;
         r.t_rnw_s = st.split_s;
@@ -1141,7 +1149,7 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
         r.t_total_s = now_s() - t0;
         hperm_launch_stat ls{};
         ls.ring = HP_W64;
-        ls.bucket = bucket_of(c->opts.device_expand);
+        ls.bucket = bucket_of(device_in_effect(c->opts));
         ls.n_jobs = r.n_jobs;
         ls.persistent = 1;
         ls.variant = 4;
@@ -1166,8 +1174,9 @@ hperm_status hperm_device_expand_sample(hperm_ctx *c, int32_t n, const int32_t *
     if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
     if (!c || !n_sampled || !total || max_jobs < 0 || (max_jobs > 0 && (!mats || !values))) return HPERM_E_INVALID;
     if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
-    const int T = c->opts.device_expand, t = split_in_effect(c->opts);
-    if (T <= 0 || t <= 0) return set_error(c, HPERM_E_INVALID, "device_expand and split_order must be set");
+    const int T = device_in_effect(c->opts), t = split_in_effect(c->opts);
+    if (T <= 0 || t <= 0)
+        return set_error(c, HPERM_E_INVALID, "device_expand must exceed a split_order in effect");
     CsrView v{n, row_ptr, col_idx, val};
     const std::string why = validate_csr(v);
     if (!why.empty()) return set_error(c, HPERM_E_INVALID, why);

@@ -145,12 +145,13 @@ hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32
     hperm_status s = hperm_ctx_get_opts(ctx, &saved);
     if (s) return s;
     o = saved;
+    o.device_expand = 0;   // the host expansion keeps the single-job rule below (and its bounds)
     if (n <= 40) {
         o.m_cut = std::max(o.m_cut, n);
         o.m_cap = std::max(o.m_cap, o.m_cut);
-        s = hperm_ctx_set_opts(ctx, &o);
-        if (s) return s;
     }
+    s = hperm_ctx_set_opts(ctx, &o);
+    if (s) return s;
     // the bound grows with x: check the last problem (x = n) on the host before any device work
     hperm_jobs *probe = nullptr;
     s = hperm_expand_batch_csr(ctx, 1, sizes.data() + n, rp_off.data() + n, nz_off.data() + n, rp.data(),
@@ -159,7 +160,7 @@ hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32
     if (!s)
         s = hperm_permanent_batch_csr(ctx, np, sizes.data(), rp_off.data(), nz_off.data(), rp.data(),
                                       ci.data(), va.data(), res.data());
-    if (n <= 40) {
+    {
         const hperm_status r = hperm_ctx_set_opts(ctx, &saved);
         if (!s) s = r;
     }

@@ -164,9 +164,15 @@ def test_device_expansion_limits(hperm):
     with a zero column takes the host path; merged entries reaching 2^22 in the device
     expansion are refused with HPERM_E_RANGE, never a wrong value."""
     with pytest.raises(hperm.HpermError):
-        hperm.Context({"split_order": 12, "device_expand": 12})
-    with pytest.raises(hperm.HpermError):
-        hperm.Context({"split_order": 0, "device_expand": 20})
+        hperm.Context({"split_order": 12, "device_expand": 25})
+    for opts in ({"split_order": 12, "device_expand": 12}, {"split_order": 0, "device_expand": 20}):
+        off = hperm.Context(opts)   # not in effect: the host path
+        try:
+            A = W.random_cubic_matrix(30, 2)
+            assert off.permanent(A) == native.hper_batch([A])[0]
+            assert not [l for l in off.last_launches() if l["variant"] == 4]
+        finally:
+            off.close()
     c = device_ctx(hperm, 20)
     try:
         small = W.random_cubic_matrix(20, 3)
