@@ -50,22 +50,14 @@ namespace {
 
 constexpr int SW = 64;                   // one wave per block
 constexpr int SMAX = HP_SPLIT_MAX_M;     // largest job order
-constexpr int CTL = 12;                  // control words per order
+constexpr int CTL = 16;                  // control words of an undo record
 constexpr int PMAX = 16;                 // widest leaf the main kernel evaluates
 // Words per Gray column of a leaf's delta table (every row; a multiple of 4 for the 16-byte
 // loads), for jobs of order <= mm.
 __host__ __device__ constexpr int dstride(int mm) { return mm <= 20 ? 20 : 24; }
 static_assert(dstride(SMAX) >= SMAX && dstride(SMAX) % 4 == 0, "a delta-table column holds every row");
 
-// Squares 1 + 4 + ... + x^2: the node slots of orders o + 1 .. mm take sq(mm) - sq(o) words.
-__host__ __device__ constexpr int sq(int x) { return x * (x + 1) * (2 * x + 1) / 6; }
 __host__ __device__ constexpr int align4(int w) { return (w + 3) & ~3; }
-// Per-wave region for target order t and largest job order mm: slots of orders t..mm (order
-// mm first), the leaf's delta table (mm - 1 columns) and base values, and per order t..mm the
-// control words and the row masks, column masks and row sums (mm words each).
-__host__ __device__ constexpr int region_words(int t, int mm) {
-    return align4(sq(mm) - sq(t - 1)) + mm * dstride(mm) + (mm + 1 - t) * (CTL + 3 * mm) + SW;
-}
 
 typedef unsigned __int128 u128;
 
@@ -265,111 +257,132 @@ __device__ __forceinline__ uint64_t walk_paired(int p, int lane, const int32_t *
 
 
 // ------------------------------------------------------------------ per-wave LDS region
+// The node being walked lives in one physical mm x mm matrix M (row stride S = dstride(mm))
+// with masks of its alive rows and columns: a split marks its deleted row (or column) and the
+// merged pair's second line dead and writes the merged line over the pair's first one, so the
+// lines keep their relative order (the line order of the node is the physical order of its
+// alive lines) and a child costs O(mm) instead of a copy. Per alive row i: rmask[i], the alive
+// columns holding a nonzero of row i; per alive column j: cmask[j], the alive rows holding a
+// nonzero of column j; rsum[i], the sum of row i over alive columns. Every split node of the
+// path keeps an undo record at its order u: its plan, its alive masks, copies of rmask, cmask
+// and rsum, and the lines its children overwrite.
+__host__ __device__ constexpr int lvl_words(int mm) { return align4(CTL + 5 * mm); }
+__host__ __device__ constexpr int region_words2(int t, int mm) {
+    return mm * dstride(mm) + mm * dstride(mm) + align4(3 * mm) + 64 + (mm - t) * lvl_words(mm) + SW;
+}
+
 struct Region {
-    uint32_t *lds;
-    int32_t *D, *base;
-    uint32_t *ctl_all, *meta_all;   // indexed by order - t
-    int top;                        // sq of the largest job order
-    int ds, mw;                     // delta-table stride; words per mask array (= mm)
-    uint32_t *dummy;                // one word per lane: the target of idle lanes' stores
-    __device__ Region(uint32_t *l, int t, int mm) : lds(l), top(sq(mm)), ds(dstride(mm)), mw(mm) {
-        D = (int32_t *)(l + align4(sq(mm) - sq(t - 1)));
-        base = D + (mm - 1) * ds;
-        ctl_all = (uint32_t *)(base + ds) - t * CTL;
-        meta_all = (uint32_t *)(base + ds) + (mm + 1 - t) * CTL - t * 3 * mm;
-        dummy = meta_all + (mm + 1) * 3 * mm;
+    uint32_t *M;                    // mm x S
+    int32_t *D, *base;              // leaf tables: (mm - 1) x S Gray-column deltas, S base values
+    uint32_t *rmask, *cmask, *rsum; // the current node
+    uint32_t *rmap, *cmap;          // leaf compaction: alive row / column of each logical index
+    uint32_t *lv0;                  // undo record of order t + 1
+    int S, mm, t, lw;
+    __device__ Region(uint32_t *l, int t_, int mm_) : S(dstride(mm_)), mm(mm_), t(t_), lw(lvl_words(mm_)) {
+        M = l;
+        D = (int32_t *)(l + mm * S);
+        base = D + (mm - 1) * S;
+        rmask = (uint32_t *)(base + S);
+        cmask = rmask + mm;
+        rsum = cmask + mm;
+        rmap = rmask + align4(3 * mm);
+        cmap = rmap + 32;
+        lv0 = cmap + 32;
     }
-    __device__ uint32_t *slot(int o) const { return lds + (top - sq(o)); }
-    __device__ uint32_t *ctl(int o) const { return ctl_all + o * CTL; }
-    __device__ uint32_t *rmask(int o) const { return meta_all + o * 3 * mw; }
-    __device__ uint32_t *cmask(int o) const { return meta_all + o * 3 * mw + mw; }
-    __device__ uint32_t *rsum(int o) const { return meta_all + o * 3 * mw + 2 * mw; }
+    __device__ uint32_t *lvl(int u) const { return lv0 + (u - t - 1) * lw; }   // u in t+1 .. mm
 };
 
-struct SplitCtl {   // word offsets in a control block
-    enum { IS_COL, IDX, NP, P0, Q0, CA0, CB0, P1, Q1, CA1, CB1, NEXT };
+struct Ctl {   // word offsets in an undo record
+    enum { IS_COL, IDX, NP, P0, Q0, CA0, CB0, P1, Q1, CA1, CB1, NEXT, AR, AC };
 };
+__device__ __forceinline__ uint32_t *sv_r(const Region &rg, int u) { return rg.lvl(u) + CTL; }
+__device__ __forceinline__ uint32_t *sv_c(const Region &rg, int u) { return rg.lvl(u) + CTL + rg.mm; }
+__device__ __forceinline__ uint32_t *sv_s(const Region &rg, int u) { return rg.lvl(u) + CTL + 2 * rg.mm; }
+__device__ __forceinline__ uint32_t *sv_line(const Region &rg, int u, int ch) { return rg.lvl(u) + CTL + (3 + ch) * rg.mm; }
 
-// Job `job` of a host job table as a dense m x m matrix in slot m (Gray columns 0..m-2, then
-// the fixed column), with its masks and row sums. Returns m.
+// Clears the m x m corner of M; returns the alive mask of m lines.
+__device__ __forceinline__ uint32_t clear_node(const Region &rg, int m, int lane) {
+    for (int e = lane; e < m * rg.S; e += SW) rg.M[e] = 0;
+    if (lane < rg.mm) {
+        rg.rmask[lane] = 0;
+        rg.cmask[lane] = 0;
+        rg.rsum[lane] = 0;
+    }
+    wave_sync();
+    return m >= 32 ? 0xffffffffu : (1u << m) - 1;
+}
+
+// Job `job` of a host job table as a dense m x m matrix (Gray columns 0..m-2, then the fixed
+// column), with its masks and row sums. Returns m.
 __device__ __forceinline__ int load_job(const Region &rg, const JobDesc *jobs, const uint32_t *data, uint32_t job, int lane) {
     const JobDesc jd = jobs[job];
     const int m = (int)uni(jd.m);
     const uint32_t nnz = uni(jd.nnz);
     const uint32_t *blk = data + (size_t)uni(jd.data_off) * HP_DATA_ALIGN;
-    uint32_t *M = rg.slot(m);
-    for (int e = lane; e < m * m; e += SW) M[e] = 0;
-    if (lane < rg.mw) {
-        rg.rmask(m)[lane] = 0;
-        rg.cmask(m)[lane] = 0;
-        rg.rsum(m)[lane] = 0;
-    }
+    const int S = rg.S;
+    clear_node(rg, m, lane);
     const uint32_t cs = lane < m ? blk[m + lane] : 0xffffffffu;   // column starts, end at m-1
-    wave_sync();
     for (uint32_t e0 = 0; e0 < nnz; e0 += SW) {
         const uint32_t e = e0 + (uint32_t)lane;
         uint32_t g = 0;   // Gray column of entry e: the last start <= e among columns 1..m-2
         for (int k = 1; k + 1 < m; ++k) g += (uint32_t)__shfl((int)cs, k) <= e;
         if (e < nnz) {
             const uint32_t w = blk[3 * m + e], i = w & 0xffu, b = w >> 9;
-            M[i * m + g] = b;
-            atomicOr(rg.rmask(m) + i, 1u << g);
-            atomicOr(rg.cmask(m) + g, 1u << i);
-            atomicAdd(rg.rsum(m) + i, b);
+            rg.M[i * S + g] = b;
+            atomicOr(rg.rmask + i, 1u << g);
+            atomicOr(rg.cmask + g, 1u << i);
+            atomicAdd(rg.rsum + i, b);
         }
     }
     wave_sync();
     uint32_t bf = 0;
     if (lane < m) {   // fixed column: b_i = base_i + the row's Gray entries
-        bf = (uint32_t)((int32_t)blk[lane] + (int32_t)rg.rsum(m)[lane]);
-        M[lane * m + m - 1] = bf;
-        rg.rsum(m)[lane] += bf;
-        if (bf) rg.rmask(m)[lane] |= 1u << (m - 1);
+        bf = (uint32_t)((int32_t)blk[lane] + (int32_t)rg.rsum[lane]);
+        rg.M[lane * S + m - 1] = bf;
+        rg.rsum[lane] += bf;
+        if (bf) rg.rmask[lane] |= 1u << (m - 1);
     }
     const uint64_t fixed_rows = __ballot(lane < m && bf != 0);
-    if (lane == 0) rg.cmask(m)[m - 1] = (uint32_t)fixed_rows;
+    if (lane == 0) rg.cmask[m - 1] = (uint32_t)fixed_rows;
     wave_sync();
     return m;
 }
 
-// A node of the device expansion (hp_node_words) as a dense matrix in slot o, with its masks
-// and row sums: lane i reads row i. Returns o; *bound and *problem receive its header words.
+// A node of the device expansion (hp_node_words) as a dense matrix, with its masks and row
+// sums: lane i reads row i. Returns its order; *bound and *problem receive its header words.
 __device__ __forceinline__ int load_node(const Region &rg, const uint32_t *node, int lane, float *bound,
                                          uint32_t *problem) {
     const uint32_t h0 = uni(node[0]);
     const int o = (int)(h0 & 0xffu);
     *bound = __uint_as_float(uni(node[1]));
     *problem = uni(node[2]);
-    uint32_t *M = rg.slot(o);
-    for (int e = lane; e < o * o; e += SW) M[e] = 0;
-    if (lane < rg.mw) rg.cmask(o)[lane] = 0;
+    clear_node(rg, o, lane);
     const uint32_t len = lane < o ? (node[4 + lane / 4] >> (8 * (lane & 3))) & 0xffu : 0u;
     const uint32_t start = wave_scan(len, lane) - len;
     const uint32_t *ent = node + 4 + (o + 3) / 4;
-    wave_sync();
     uint32_t rm = 0, rs = 0;
     for (uint32_t e = 0; e < len; ++e) {
         const uint32_t w = ent[start + e], j = w & 0xffu, v = w >> 8;
-        M[lane * o + j] = v;
+        rg.M[lane * rg.S + j] = v;
         rm |= 1u << j;
         rs += v;
-        atomicOr(rg.cmask(o) + j, 1u << lane);
+        atomicOr(rg.cmask + j, 1u << lane);
     }
     if (lane < o) {
-        rg.rmask(o)[lane] = rm;
-        rg.rsum(o)[lane] = rs;
+        rg.rmask[lane] = rm;
+        rg.rsum[lane] = rs;
     }
     wave_sync();
     return o;
 }
 
-// Step 1 of H_per at the node of order o: returns (count << 6) | (32 * is_col + index) of the
-// sparsest line (rows before columns, then the lowest index).
-__device__ __forceinline__ uint32_t sparsest_line(const Region &rg, int o, int lane) {
+// Step 1 of H_per at the current node: (count << 6) | (32 * is_col + index) of the sparsest
+// line (rows before columns, then the lowest index; physical order is the node's line order).
+__device__ __forceinline__ uint32_t sparsest_line(const Region &rg, uint32_t AR, uint32_t AC, int lane) {
+    const bool row = lane < 32 && ((AR >> lane) & 1), col = lane >= 32 && ((AC >> (lane - 32)) & 1);
     uint32_t cnt = 0;
-    const bool row = lane < o, col = lane >= 32 && lane < 32 + o;
-    if (row) cnt = (uint32_t)__popc(rg.rmask(o)[lane]);
-    else if (col) cnt = (uint32_t)__popc(rg.cmask(o)[lane - 32]);
+    if (row) cnt = (uint32_t)__popc(rg.rmask[lane]);
+    else if (col) cnt = (uint32_t)__popc(rg.cmask[lane - 32]);
     uint32_t s;
     const uint32_t w = argmin_lane(cnt, row || col, &s);
     return (s << 6) | w;
@@ -382,31 +395,35 @@ struct Plan {
     uint32_t P[2], Q[2], ca[2], cb[2];
 };
 
-__device__ __forceinline__ Plan load_plan(const Region &rg, int o) {
-    const uint32_t *ctl = rg.ctl(o);
+__device__ __forceinline__ Plan load_plan(const Region &rg, int u) {
+    const uint32_t *ctl = rg.lvl(u);
     Plan pl;
-    pl.is_col = uni(ctl[SplitCtl::IS_COL]);
-    pl.line = uni(ctl[SplitCtl::IDX]);
-    pl.np = uni(ctl[SplitCtl::NP]);
+    pl.is_col = uni(ctl[Ctl::IS_COL]);
+    pl.line = uni(ctl[Ctl::IDX]);
+    pl.np = uni(ctl[Ctl::NP]);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        pl.P[c] = uni(ctl[SplitCtl::P0 + 4 * c]);
-        pl.Q[c] = uni(ctl[SplitCtl::Q0 + 4 * c]);
-        pl.ca[c] = uni(ctl[SplitCtl::CA0 + 4 * c]);
-        pl.cb[c] = uni(ctl[SplitCtl::CB0 + 4 * c]);
+        pl.P[c] = uni(ctl[Ctl::P0 + 4 * c]);
+        pl.Q[c] = uni(ctl[Ctl::Q0 + 4 * c]);
+        pl.ca[c] = uni(ctl[Ctl::CA0 + 4 * c]);
+        pl.cb[c] = uni(ctl[Ctl::CB0 + 4 * c]);
     }
     return pl;
 }
 
 // Pairs of expansion (2) along the line (nonzeros in increasing index order; an odd last one
-// with the lowest zero of the line at weight 0) into ctl, the child counter cleared. Returns
-// false when a child would break the entry or row-sum bound (ctl then unused).
-__device__ __forceinline__ bool plan_split(const Region &rg, int o, uint32_t key, int lane, Plan &pl) {
+// with the lowest zero of the line at weight 0). Returns false when a child would break the
+// entry or row-sum bound. With `record` (a split of the main walk at order u) the plan, the
+// alive masks and the parent's state that the children overwrite go to the undo record.
+__device__ __forceinline__ bool plan_split(const Region &rg, uint32_t AR, uint32_t AC, uint32_t key, int lane,
+                                          Plan &pl, bool record, int u) {
     const uint32_t s = key >> 6, is_col = (key >> 5) & 1, line = key & 31;
-    const uint32_t *M = rg.slot(o);
-    const uint32_t lv = lane < o ? (is_col ? M[lane * o + line] : M[line * o + lane]) : 0u;   // the line
-    uint32_t nz = uni(is_col ? rg.cmask(o)[line] : rg.rmask(o)[line]);
-    const uint32_t zero = (uint32_t)__builtin_ctz(~nz & ((1u << o) - 1));
+    const int S = rg.S;
+    const uint32_t *M = rg.M;
+    const uint32_t other = is_col ? AR : AC;   // the positions along the line
+    const uint32_t lv = lane < 32 && ((other >> lane) & 1) ? (is_col ? M[lane * S + line] : M[line * S + lane]) : 0u;
+    uint32_t nz = uni(is_col ? rg.cmask[line] : rg.rmask[line]);
+    const uint32_t zero = (uint32_t)__builtin_ctz(~nz & other);
     uint32_t pos[4], val[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -420,22 +437,24 @@ __device__ __forceinline__ bool plan_split(const Region &rg, int o, uint32_t key
     }
     const uint32_t np = (s + 1) / 2;
     bool fail = false;
+    const bool arow = lane < 32 && ((AR >> lane) & 1) && (uint32_t)lane != line;   // other alive rows
+    const bool acol = lane < 32 && ((AC >> lane) & 1) && (uint32_t)lane != line;   // other alive columns
     for (uint32_t ch = 0; ch < np; ++ch) {
         const uint32_t P = pos[2 * ch], Q = pos[2 * ch + 1];
         const uint64_t ca = val[2 * ch], cb = val[2 * ch + 1];
         if (!is_col) {   // merged column; each other row loses P and Q and gains the merge
-            if (lane < o && (uint32_t)lane != line) {
-                const uint64_t mq = M[lane * o + Q], mp = M[lane * o + P];
+            if (arow) {
+                const uint64_t mq = M[lane * S + Q], mp = M[lane * S + P];
                 const uint64_t mv = ca * mq + cb * mp;
-                fail = fail || mv >= HP_MAX_ENTRY || rg.rsum(o)[lane] - mq - mp + mv >= HP_MAX_ROWSUM;
+                fail = fail || mv >= HP_MAX_ENTRY || rg.rsum[lane] - mq - mp + mv >= HP_MAX_ROWSUM;
             }
-        } else {         // merged row; its sum is known from the rows P and Q
-            if (lane < o && (uint32_t)lane != line) {
-                const uint64_t mv = ca * M[Q * o + lane] + cb * M[P * o + lane];
+        } else {         // merged row (its entries column by column); its sum from rows P and Q
+            if (acol) {
+                const uint64_t mv = ca * M[Q * S + lane] + cb * M[P * S + lane];
                 fail = fail || mv >= HP_MAX_ENTRY;
             }
-            const uint64_t rq = uni(rg.rsum(o)[Q]) - (uint64_t)uni(M[Q * o + line]);
-            const uint64_t rp = uni(rg.rsum(o)[P]) - (uint64_t)uni(M[P * o + line]);
+            const uint64_t rq = uni(rg.rsum[Q]) - (uint64_t)uni(M[Q * S + line]);
+            const uint64_t rp = uni(rg.rsum[P]) - (uint64_t)uni(M[P * S + line]);
             fail = fail || ca * rq + cb * rp >= HP_MAX_ROWSUM;
         }
     }
@@ -450,116 +469,158 @@ __device__ __forceinline__ bool plan_split(const Region &rg, int o, uint32_t key
         pl.ca[c] = val[2 * c];
         pl.cb[c] = val[2 * c + 1];
     }
-    uint32_t *ctl = rg.ctl(o);
-    if (lane == 0) {
-        ctl[SplitCtl::IS_COL] = is_col;
-        ctl[SplitCtl::IDX] = line;
-        ctl[SplitCtl::NP] = np;
-        ctl[SplitCtl::P0] = pos[0];
-        ctl[SplitCtl::Q0] = pos[1];
-        ctl[SplitCtl::CA0] = val[0];
-        ctl[SplitCtl::CB0] = val[1];
-        ctl[SplitCtl::P1] = pos[2];
-        ctl[SplitCtl::Q1] = pos[3];
-        ctl[SplitCtl::CA1] = val[2];
-        ctl[SplitCtl::CB1] = val[3];
-        ctl[SplitCtl::NEXT] = 0;
+    if (record) {
+        uint32_t *ctl = rg.lvl(u);
+        if (lane == 0) {
+            ctl[Ctl::IS_COL] = is_col;
+            ctl[Ctl::IDX] = line;
+            ctl[Ctl::NP] = np;
+            ctl[Ctl::P0] = pos[0];
+            ctl[Ctl::Q0] = pos[1];
+            ctl[Ctl::CA0] = val[0];
+            ctl[Ctl::CB0] = val[1];
+            ctl[Ctl::P1] = pos[2];
+            ctl[Ctl::Q1] = pos[3];
+            ctl[Ctl::CA1] = val[2];
+            ctl[Ctl::CB1] = val[3];
+            ctl[Ctl::NEXT] = 0;
+            ctl[Ctl::AR] = AR;
+            ctl[Ctl::AC] = AC;
+        }
+        if (lane < rg.mm) {
+            sv_r(rg, u)[lane] = rg.rmask[lane];
+            sv_c(rg, u)[lane] = rg.cmask[lane];
+            sv_s(rg, u)[lane] = rg.rsum[lane];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {   // the lines the children overwrite
+                const uint32_t keep = min(pos[2 * c], pos[2 * c + 1]);
+                sv_line(rg, u, c)[lane] = is_col ? M[keep * S + lane] : M[lane * S + keep];
+            }
+        }
+        wave_sync();
     }
-    wave_sync();
     return true;
 }
 
-// Child `ch` of the node of order o (split by plan pl) into slot o - 1 with its masks and row
-// sums. Lanes cover three child rows per pass (lane = 21 * r + column) while a row has at most
-// 21 columns, else two (lane = 32 * r + column).
-__device__ __forceinline__ void make_child(const Region &rg, int o, const Plan &pl, int ch, int lane) {
-    const uint32_t *M = rg.slot(o);
-    uint32_t *C = rg.slot(o - 1);
-    const uint32_t is_col = pl.is_col, line = pl.line;
+// Child `ch` of the current node (plan pl; alive masks AR, AC updated in place): the merged
+// line over the pair's first line, the other line and the split line dead, masks and row sums
+// updated.
+__device__ __forceinline__ void apply_child(const Region &rg, const Plan &pl, int ch, uint32_t &AR, uint32_t &AC, int lane) {
+    const int S = rg.S;
+    uint32_t *M = rg.M;
+    const uint32_t line = pl.line;
     const uint32_t P = ch ? pl.P[1] : pl.P[0], Q = ch ? pl.Q[1] : pl.Q[0];
     const uint32_t ca = ch ? pl.ca[1] : pl.ca[0], cb = ch ? pl.cb[1] : pl.cb[0];
     const uint32_t keep = min(P, Q), drop = max(P, Q);
-    const uint32_t co = (uint32_t)o - 1;
-    const bool three = co <= 21;
-    const uint32_t rw = three ? 21u : 32u, nr = three ? 3u : 2u;
-    const uint32_t r3 = three ? (uint32_t)lane / 21 : (uint32_t)lane >> 5, jp = (uint32_t)lane - rw * r3;
-    const uint32_t rmk = three ? (1u << 21) - 1 : 0xffffffffu;
-    uint32_t cm = 0;
-    uint32_t *const dummy = rg.dummy + lane;
-    for (uint32_t ip0 = 0; ip0 < co; ip0 += nr) {   // branch-free: idle lanes read a valid entry
-        const uint32_t ip = ip0 + r3;                // and store to their dummy word
-        const bool ok = r3 < nr && ip < co && jp < co;
-        const uint32_t ipc = ok ? ip : 0, jpc = ok ? jp : 0;
-        uint32_t x, y, merged;
-        bool at_merge;
-        if (!is_col) {   // row `line` deleted, columns P, Q merged at keep = min(P, Q)
-            const uint32_t i = ipc + (ipc >= line), j = jpc + (jpc >= drop);
-            x = M[i * o + j];      // at j == keep: the entry of column keep
-            y = M[i * o + drop];   // the entry of column drop (the pair's other column)
-            at_merge = j == keep;
-        } else {         // column `line` deleted, rows P, Q merged at keep = min(P, Q)
-            const uint32_t i = ipc + (ipc >= drop), j = jpc + (jpc >= line);
-            x = M[i * o + j];
-            y = M[drop * o + j];
-            at_merge = i == keep;
+    if (!pl.is_col) {   // row `line` deleted; columns P, Q merged into column keep
+        const uint32_t AR2 = AR & ~(1u << line), AC2 = AC & ~(1u << drop);
+        const bool row = lane < 32 && ((AR2 >> lane) & 1);
+        uint32_t mv = 0, rm = 0, rs = 0;
+        if (row) {
+            const uint32_t mq = M[lane * S + Q], mp = M[lane * S + P];
+            mv = ca * mq + cb * mp;
+            rm = (rg.rmask[lane] & ~((1u << keep) | (1u << drop))) | (mv ? 1u << keep : 0u);
+            rs = rg.rsum[lane] - mq - mp + mv;
         }
-        merged = keep == P ? ca * y + cb * x : ca * x + cb * y;   // ca * (entry at Q) + cb * (entry at P)
-        const uint32_t v = ok ? (at_merge ? merged : x) : 0u;
-        *(ok ? C + ip * co + jp : dummy) = v;
-        cm |= v ? 1u << ipc : 0u;
-        const uint64_t bal = __ballot(v != 0);
-        *(ok && jp == 0 ? rg.rmask(o - 1) + ip : dummy) = (uint32_t)(bal >> (rw * r3)) & rmk;
-    }
-    if (three) cm |= (uint32_t)__shfl((int)cm, lane + 21) | (uint32_t)__shfl((int)cm, lane + 42);
-    else cm |= (uint32_t)__shfl((int)cm, lane + 32);
-    if ((uint32_t)lane < co) {   // row sums from the parent's
-        const uint32_t ip = (uint32_t)lane;
-        uint32_t rs;
-        if (!is_col) {
-            const uint32_t i = ip + (ip >= line);
-            const uint32_t mq = M[i * o + Q], mp = M[i * o + P];
-            rs = rg.rsum(o)[i] - mq - mp + ca * mq + cb * mp;
-        } else {
-            const uint32_t i = ip + (ip >= drop);
-            if (i == keep)
-                rs = ca * (rg.rsum(o)[Q] - M[Q * o + line]) + cb * (rg.rsum(o)[P] - M[P * o + line]);
-            else
-                rs = rg.rsum(o)[i] - M[i * o + line];
+        const uint32_t newcol = (uint32_t)__ballot(row && mv != 0);
+        const bool col = lane < 32 && ((AC2 >> lane) & 1);
+        uint32_t cm = 0;
+        if (col) cm = (uint32_t)lane == keep ? newcol : rg.cmask[lane] & ~(1u << line);
+        wave_sync();
+        if (row) {
+            M[lane * S + keep] = mv;
+            rg.rmask[lane] = rm;
+            rg.rsum[lane] = rs;
         }
-        rg.cmask(o - 1)[lane] = cm;
-        rg.rsum(o - 1)[ip] = rs;
+        if (col) rg.cmask[lane] = cm;
+        AR = AR2;
+        AC = AC2;
+    } else {            // column `line` deleted; rows P, Q merged into row keep
+        const uint32_t AR2 = AR & ~(1u << drop), AC2 = AC & ~(1u << line);
+        const bool col = lane < 32 && ((AC2 >> lane) & 1);
+        uint32_t mv = 0, cm = 0;
+        if (col) {
+            mv = ca * M[Q * S + lane] + cb * M[P * S + lane];
+            cm = (rg.cmask[lane] & ~((1u << keep) | (1u << drop))) | (mv ? 1u << keep : 0u);
+        }
+        const uint32_t newrow = (uint32_t)__ballot(col && mv != 0);
+        const bool row = lane < 32 && ((AR2 >> lane) & 1);
+        uint32_t rm = 0, rs = 0;
+        if (row) {
+            if ((uint32_t)lane == keep) {
+                rm = newrow;
+                rs = ca * (rg.rsum[Q] - M[Q * S + line]) + cb * (rg.rsum[P] - M[P * S + line]);
+            } else {
+                rm = rg.rmask[lane] & ~(1u << line);
+                rs = rg.rsum[lane] - M[lane * S + line];
+            }
+        }
+        wave_sync();
+        if (col) {
+            M[keep * S + lane] = mv;
+            rg.cmask[lane] = cm;
+        }
+        if (row) {
+            rg.rmask[lane] = rm;
+            rg.rsum[lane] = rs;
+        }
+        AR = AR2;
+        AC = AC2;
     }
     wave_sync();
 }
 
-// Leaf tables in LDS: D[j][i] = 2 b_ij for Gray column j (rows beyond p: 0) and
-// base_i = 2 b_{i,p-1} - R_i (rows beyond p: 1, so f = 1), with the leaf's sparsest Gray
-// column moved to Gray column 0 and the rows it touches moved to the front (the product is
-// invariant under both permutations). Returns that column's nonzero count b. Needs p >= 2.
-__device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, int lane) {
-    const uint32_t *M = rg.slot(p);
-    const uint32_t cmk = lane < p - 1 ? rg.cmask(p)[lane] : 0u;
+// Back to the state of the split node at order u before child ch was applied: its masks, row
+// sums and alive lines, and the line child ch overwrote.
+__device__ __forceinline__ void restore_node(const Region &rg, int u, int ch, bool masks, int lane) {
+    const uint32_t *ctl = rg.lvl(u);
+    const uint32_t is_col = uni(ctl[Ctl::IS_COL]);
+    const uint32_t keep = min(uni(ctl[Ctl::P0 + 4 * ch]), uni(ctl[Ctl::Q0 + 4 * ch]));
+    if (lane < rg.mm) {
+        const uint32_t v = sv_line(rg, u, ch)[lane];
+        if (is_col) rg.M[keep * rg.S + lane] = v;
+        else rg.M[lane * rg.S + keep] = v;
+        if (masks) {
+            rg.rmask[lane] = sv_r(rg, u)[lane];
+            rg.cmask[lane] = sv_c(rg, u)[lane];
+            rg.rsum[lane] = sv_s(rg, u)[lane];
+        }
+    }
+    wave_sync();
+}
+
+// Leaf tables in LDS for the current node of order p: D[j][i] = 2 b_ij for Gray column j (rows
+// beyond p: 0) and base_i = 2 b_{i,p-1} - R_i (rows beyond p: 1, so f = 1), the node's last
+// alive column being the fixed one, with its sparsest Gray column moved to Gray column 0 and
+// the rows it touches moved to the front (the product is invariant under both permutations).
+// Returns that column's nonzero count b. Needs p >= 2.
+__device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane) {
+    const uint32_t fx = 31u - (uint32_t)__builtin_clz(AC);   // the fixed (last) column
+    const uint32_t below = lane < 32 ? (1u << lane) - 1 : 0xffffffffu;
+    if (lane < 32 && ((AC >> lane) & 1) && (uint32_t)lane != fx) rg.cmap[__popc(AC & below)] = (uint32_t)lane;
+    if (lane < 32 && ((AR >> lane) & 1)) rg.rmap[__popc(AR & below)] = (uint32_t)lane;
+    wave_sync();
+    const uint32_t cmk = lane < p - 1 ? rg.cmask[rg.cmap[lane]] : 0u;
     uint32_t b;
     const uint32_t c0 = argmin_lane((uint32_t)__popc(cmk), lane < p - 1, &b);
-    const uint32_t touched = (uint32_t)__builtin_amdgcn_readlane((int)cmk, (int)c0);
-    const uint32_t rows = (1u << p) - 1;
-    const int ds = rg.ds;
-    for (int e = lane; e < (p - 1) * ds; e += SW) {
-        const int j = e / ds, i = e - j * ds;
+    const uint32_t touched = (uint32_t)__builtin_amdgcn_readlane((int)cmk, (int)c0);   // physical rows
+    const int S = rg.S;
+    for (int e = lane; e < (p - 1) * S; e += SW) {
+        const int j = e / S, i = e - j * S;
         if (i < p) {
-            const uint32_t below = (1u << i) - 1;
-            const int pos = ((touched >> i) & 1) ? __popc(touched & below) : (int)b + __popc(~touched & rows & below);
+            const uint32_t r = rg.rmap[i], rb = (1u << r) - 1;
+            const int pos = ((touched >> r) & 1) ? __popc(touched & rb) : (int)b + __popc(~touched & AR & rb);
             const int g = j == 0 ? (int)c0 : (j == (int)c0 ? 0 : j);
-            rg.D[j * ds + pos] = 2 * (int32_t)M[i * p + g];
+            rg.D[j * S + pos] = 2 * (int32_t)rg.M[r * S + rg.cmap[g]];
         } else {
             rg.D[e] = 0;
         }
     }
-    if (lane < ds) {
+    if (lane < S) {
         if (lane < p) {
-            const uint32_t below = (1u << lane) - 1;
-            const int pos = ((touched >> lane) & 1) ? __popc(touched & below) : (int)b + __popc(~touched & rows & below);
-            rg.base[pos] = 2 * (int32_t)M[lane * p + p - 1] - (int32_t)rg.rsum(p)[lane];
+            const uint32_t r = rg.rmap[lane], rb = (1u << r) - 1;
+            const int pos = ((touched >> r) & 1) ? __popc(touched & rb) : (int)b + __popc(~touched & AR & rb);
+            rg.base[pos] = 2 * (int32_t)rg.M[r * S + fx] - (int32_t)rg.rsum[r];
         } else {
             rg.base[lane] = 1;
         }
@@ -570,22 +631,22 @@ __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, int lan
 
 // This lane's share of V = (-1)^(p-1) 2^(p-1) per(leaf) modulo 2^64 for a leaf of order
 // 7 <= p <= PMAX.
-__device__ __forceinline__ uint64_t eval_leaf(const Region &rg, int p, int lane) {
-    const uint32_t b = leaf_tables(rg, p, lane);
+__device__ __forceinline__ uint64_t eval_leaf(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane) {
+    const uint32_t b = leaf_tables(rg, p, AR, AC, lane);
     uint64_t v;
-    if (p >= 8 && p <= 12 && b <= 2) v = walk_paired<12, 2>(p, lane, rg.D, rg.base, rg.ds);
-    else if (p >= 8 && p <= 12 && b <= 4) v = walk_paired<12, 4>(p, lane, rg.D, rg.base, rg.ds);
-    else if (p <= 12) v = walk_plain<12>(p, lane, rg.D, rg.base, rg.ds);
-    else if (b <= 2) v = walk_paired<16, 2>(p, lane, rg.D, rg.base, rg.ds);
-    else if (b <= 4) v = walk_paired<16, 4>(p, lane, rg.D, rg.base, rg.ds);
-    else v = walk_plain<16>(p, lane, rg.D, rg.base, rg.ds);
+    if (p >= 8 && p <= 12 && b <= 2) v = walk_paired<12, 2>(p, lane, rg.D, rg.base, rg.S);
+    else if (p >= 8 && p <= 12 && b <= 4) v = walk_paired<12, 4>(p, lane, rg.D, rg.base, rg.S);
+    else if (p <= 12) v = walk_plain<12>(p, lane, rg.D, rg.base, rg.S);
+    else if (b <= 2) v = walk_paired<16, 2>(p, lane, rg.D, rg.base, rg.S);
+    else if (b <= 4) v = walk_paired<16, 4>(p, lane, rg.D, rg.base, rg.S);
+    else v = walk_plain<16>(p, lane, rg.D, rg.base, rg.S);
     wave_sync();   // the tables are rewritten by the next leaf
     return v;
 }
 
-// Proven log2 upper bound of the product of the row sums of the node of order o.
-__device__ __forceinline__ float rowsum_log2(const Region &rg, int o, int lane) {
-    const float x = lane < o ? __log2f((float)rg.rsum(o)[lane]) : 0.0f;   // row sums < 2^24: exact
+// Proven log2 upper bound of the product of the row sums of the current node.
+__device__ __forceinline__ float rowsum_log2(const Region &rg, uint32_t AR, int lane) {
+    const float x = lane < 32 && ((AR >> lane) & 1) ? __log2f((float)rg.rsum[lane]) : 0.0f;   // < 2^24: exact
     return wave_sumf(x) + 1e-3f;   // margin for the hardware logarithm and the float sum
 }
 
@@ -677,56 +738,60 @@ __global__ __launch_bounds__(SW) void hper_split(SplitArgs a) {
         float jb;
         uint32_t problem;
         const int m0 = load_source<NODES>(rg, a, job, lane, &jb, &problem);
+        uint32_t AR = (1u << m0) - 1, AC = AR;   // alive rows and columns of the current node
         u128 acc = 0;   // per(B): the sum of the normalised leaves (wave-uniform)
         int o = m0;
         Plan pl;
         for (;;) {
-            const uint32_t key = sparsest_line(rg, o, lane);
+            const uint32_t key = sparsest_line(rg, AR, AC, lane);
             const uint32_t s = key >> 6;
             if (s != 0) {
-                bool leaf = o <= a.t || o <= 2 || (int)s >= a.s_leaf || s > 4;
+                const bool leaf = o <= a.t || o <= 2 || (int)s >= a.s_leaf || s > 4;
                 if (!leaf) {
-                    if (plan_split(rg, o, key, lane, pl)) {
-                        make_child(rg, o, pl, 0, lane);
+                    if (plan_split(rg, AR, AC, key, lane, pl, true, o)) {
+                        apply_child(rg, pl, 0, AR, AC, lane);
                         ++n_splits;
                         --o;
                         continue;
                     }
                     ++n_stops;   // refused by the entry bounds: evaluated whole
                 }
-                {
-                    ++n_leaves;
-                    n_terms += 1ull << (o - 1);
-                    // exact modulo 2^64 when per(leaf) 2^(o-1) < 2^63 (bound: the job's, or the
-                    // leaf's product of row sums)
-                    const bool ok64 = fminf(jb, rowsum_log2(rg, o, lane)) + (float)o <= 62.5f;
-                    if (ok64 && o <= PMAX) {
-                        bool bad;
-                        const uint64_t per = normalise64(uni64(wave_sum64(eval_leaf(rg, o, lane))), o, &bad);
-                        n_bad += bad;
-                        acc += per;
-                    } else {   // replayed by the second kernel in 128-bit arithmetic
-                        ++n_wide;
-                        uint32_t path = 0;
-                        for (int u = o + 1; u <= m0; ++u) path |= uni(rg.ctl(u)[SplitCtl::NEXT]) << (m0 - u);
-                        if (lane == 0) {
-                            const unsigned long long w = atomicAdd(a.stats + 4, 1ull);
-                            if (w < a.wide_cap) a.wide[w] = WideLeaf{job, (uint32_t)o | (path << 8)};
-                            else atomicAdd(a.stats + 5, 1ull);   // reported as an error
-                        }
+                ++n_leaves;
+                n_terms += 1ull << (o - 1);
+                // exact modulo 2^64 when per(leaf) 2^(o-1) < 2^63 (bound: the job's, or the
+                // leaf's product of row sums)
+                const bool ok64 = fminf(jb, rowsum_log2(rg, AR, lane)) + (float)o <= 62.5f;
+                if (ok64 && o <= PMAX) {
+                    bool bad;
+                    const uint64_t per = normalise64(uni64(wave_sum64(eval_leaf(rg, o, AR, AC, lane))), o, &bad);
+                    n_bad += bad;
+                    acc += per;
+                } else {   // replayed by the second kernel in 128-bit arithmetic
+                    ++n_wide;
+                    uint32_t path = 0;
+                    for (int u = o + 1; u <= m0; ++u) path |= uni(rg.lvl(u)[Ctl::NEXT]) << (m0 - u);
+                    if (lane == 0) {
+                        const unsigned long long w = atomicAdd(a.stats + 4, 1ull);
+                        if (w < a.wide_cap) a.wide[w] = WideLeaf{job, (uint32_t)o | (path << 8)};
+                        else atomicAdd(a.stats + 5, 1ull);   // reported as an error
                     }
                 }
             }
-            // back up to the nearest node on the path with a child left
+            // back up to the nearest split node of the path with a child left, undoing the
+            // lines the children on the way overwrote (the deepest first)
             int up = o + 1;
             for (; up <= m0; ++up) {
-                uint32_t *ctl = rg.ctl(up);
-                const uint32_t nx = uni(ctl[SplitCtl::NEXT]) + 1;
-                if (nx < uni(ctl[SplitCtl::NP])) {
-                    if (lane == 0) ctl[SplitCtl::NEXT] = nx;
-                    make_child(rg, up, load_plan(rg, up), (int)nx, lane);
+                uint32_t *ctl = rg.lvl(up);
+                const uint32_t cur = uni(ctl[Ctl::NEXT]), nx = cur + 1;
+                if (nx < uni(ctl[Ctl::NP])) {
+                    restore_node(rg, up, (int)cur, true, lane);
+                    AR = uni(ctl[Ctl::AR]);
+                    AC = uni(ctl[Ctl::AC]);
+                    if (lane == 0) ctl[Ctl::NEXT] = nx;
+                    apply_child(rg, load_plan(rg, up), (int)nx, AR, AC, lane);
                     break;
                 }
+                restore_node(rg, up, (int)cur, false, lane);
             }
             if (up > m0) break;
             o = up - 1;
@@ -779,15 +844,16 @@ __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
         uint32_t problem;
         const int m0 = load_source<NODES>(rg, a, job, lane, &jb, &problem);
         if (p < 7 || p > m0 || m0 > a.mm) continue;
+        uint32_t AR = (1u << m0) - 1, AC = AR;
         Plan pl;
         for (int o = m0; o > p; --o) {
-            if (!plan_split(rg, o, sparsest_line(rg, o, lane), lane, pl)) break;   // not reached: the
-            make_child(rg, o, pl, (int)((path >> (m0 - o)) & 1), lane);           // first pass split here
+            if (!plan_split(rg, AR, AC, sparsest_line(rg, AR, AC, lane), lane, pl, false, o)) break;   // not reached:
+            apply_child(rg, pl, (int)((path >> (m0 - o)) & 1), AR, AC, lane);   // the first pass split here
         }
-        leaf_tables(rg, p, lane);
+        leaf_tables(rg, p, AR, AC, lane);
         u128 v;   // rows padded to the table's stride (20 or 24), never beyond it
-        if (rg.ds == 20) v = walk_plain128<20>(p, lane, rg.D, rg.base, rg.ds);
-        else v = walk_plain128<SMAX>(p, lane, rg.D, rg.base, rg.ds);
+        if (rg.S == 20) v = walk_plain128<20>(p, lane, rg.D, rg.base, rg.S);
+        else v = walk_plain128<SMAX>(p, lane, rg.D, rg.base, rg.S);
         const u128 V = wave_sum128(v);
         bool bad;
         const u128 per = normalise128(V, p, &bad);
@@ -802,7 +868,7 @@ __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
 
 }  // namespace
 
-size_t split_lds_bytes(int t, int mm) { return (size_t)region_words(t, mm) * sizeof(uint32_t); }
+size_t split_lds_bytes(int t, int mm) { return (size_t)region_words2(t, mm) * sizeof(uint32_t); }
 size_t split_wide_bytes(uint64_t entries) { return (size_t)(entries ? entries : 1) * sizeof(WideLeaf); }
 
 static hipError_t resident_grid(const void *fn, size_t lds, uint64_t *grid) {
