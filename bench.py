@@ -326,12 +326,22 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip C100 and the random cubic n=100 problem")
+    ap.add_argument("--large-only", choices=["c100", "all"], default=None,
+                    help="only run the large single problems (C100, or C100 and random cubic n=100) and "
+                         "print their record (for profiling)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device-to-device copy of 256 MiB three times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.large_only:
+        import paper_1112_6072_amd as hp
+        import workloads as W
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(large_single(hp, W, seeds=() if args.large_only == "c100" else (0,))), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported (the path shards "

@@ -389,6 +389,9 @@ typedef struct hperm_launch_stat {
     uint64_t splits;        /* nodes split by expansion (2) */
     uint64_t split_stops;   /* nodes evaluated whole because a child would break the entry
                                (2^22) or row-sum (2^24) bound */
+    uint64_t deferred;      /* leaves replayed and evaluated modulo 2^128 by the second kernel
+                               (orders above 16, or no bound admitting the 64-bit walk) */
+    uint64_t deferred_bound;/* ... of which for want of a bound admitting the 64-bit walk */
 } hperm_launch_stat;
 
 /* Copy up to max launch records of the last call into out; *n receives the count. */

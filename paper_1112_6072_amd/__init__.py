@@ -80,7 +80,8 @@ class LaunchStat(ctypes.Structure):
                 ("items", ctypes.c_uint64), ("terms", ctypes.c_uint64),
                 ("row_updates", ctypes.c_uint64), ("alg_slots", ctypes.c_double), ("ms", ctypes.c_double),
                 ("leaves", ctypes.c_uint64), ("leaf_terms", ctypes.c_uint64), ("splits", ctypes.c_uint64),
-                ("split_stops", ctypes.c_uint64)]
+                ("split_stops", ctypes.c_uint64), ("deferred", ctypes.c_uint64),
+                ("deferred_bound", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

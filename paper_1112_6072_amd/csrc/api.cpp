@@ -754,6 +754,8 @@ hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_resu
                 st.leaf_terms = c->split_stats[1];
                 st.splits = c->split_stats[2];
                 st.split_stops = c->split_stats[3];
+                st.deferred = c->split_stats[4];
+                st.deferred_bound = c->split_stats[7];
                 if (c->split_stats[5]) return set_error(c, HPERM_E_INTERNAL, "device H_per: leaf records lost");
                 if (c->split_stats[6])
                     return set_error(c, HPERM_E_INTERNAL, "device H_per: a leaf value failed its integrity check");
@@ -1161,6 +1163,8 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
         ls.leaf_terms = st.leaf_terms;
         ls.splits = st.splits;
         ls.split_stops = st.split_stops;
+        ls.deferred = st.deferred;
+        ls.deferred_bound = st.deferred_bound;
         ls.alg_slots = st.split_s * 1e3;   // the device H_per launches' share of ms
         c->dev.launches.push_back(ls);
     }

@@ -75,6 +75,12 @@ __device__ __forceinline__ Rows node_rows(const uint32_t *node, int o, int lane)
     return r;
 }
 
+// Value of line i (two per lane: lanes hold lines lane and lane + 64) from the lane holding it.
+__device__ __forceinline__ uint32_t pick(const uint32_t (&v)[2], uint32_t i) {
+    const uint32_t a = (uint32_t)__shfl((int)v[0], (int)(i & 63)), b = (uint32_t)__shfl((int)v[1], (int)(i & 63));
+    return i >= 64 ? b : a;
+}
+
 __device__ __forceinline__ const uint32_t *node_entries(const uint32_t *node, int o) { return node + 4 + (o + 3) / 4; }
 
 // Step 1 of H_per: the key (s << 9) | (is_col << 8) | index of the sparsest line. hist is the
@@ -226,27 +232,19 @@ __device__ __forceinline__ uint32_t nth_bit(uint64_t lo, uint64_t hi, uint32_t k
     return (uint32_t)__builtin_ctzll(m) + (k < nlo ? 0u : 64u);
 }
 
-__global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ lvl, const uint64_t *__restrict__ off,
-                                                  uint64_t first, uint32_t n, const uint32_t *__restrict__ keys,
-                                                  const uint64_t *__restrict__ place,
-                                                  uint32_t *__restrict__ out, uint64_t *__restrict__ out_off,
-                                                  unsigned long long *__restrict__ flags) {
-    __shared__ uint32_t len_all[BLK / WV][MAXO];
-    const int lane = threadIdx.x & (WV - 1), wv = threadIdx.x / WV;
-    const uint32_t k = blockIdx.x * (BLK / WV) + wv;
-    if (k >= n) return;
-    uint32_t *lenb = len_all[wv];
-    const uint32_t *node = lvl + uni64(off[first + k]);
+// The children of one node (its words at `node`, read from LDS when staged) by expansion (2)
+// along the line of `key`. With a staging buffer `cst`, each child is built there and copied
+// to its place in `out` with coalesced stores; else it is written to `out` directly.
+__device__ __forceinline__ void write_children(const uint32_t *node, uint32_t key, uint64_t child_idx, uint64_t wbase,
+                                               uint32_t *lenb, uint32_t *cst, uint32_t *__restrict__ out,
+                                               uint64_t *__restrict__ out_off, unsigned long long *__restrict__ flags,
+                                               int lane) {
     const uint32_t h0 = uni(node[0]);
     const int o = (int)(h0 & 0xffu);
     const float pbound = __uint_as_float(uni(node[1]));
     const uint32_t problem = uni(node[2]);
-    const uint32_t key = uni(keys[k]);
     const uint32_t s = key >> 9, is_col = (key >> 8) & 1u, line = key & 0xffu;
     const uint32_t np = (s + 1) / 2;
-    if (np == 0) return;
-    const uint64_t pl = uni64(place[k]);
-    const uint64_t child_idx = pl >> 36, wbase = pl & ((1ull << 36) - 1);
     const uint32_t pw = hp_node_words(o, (int)(h0 >> 8));
     const uint32_t *ent = node_entries(node, o);
     const Rows r = node_rows(node, o, lane);
@@ -255,8 +253,8 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
     uint64_t cl_lo = 0, cl_hi = 0;   // rows holding the column line
     uint32_t cval[2] = {0, 0};       // this lane's rows' entries in the column line
     if (!is_col) {
-        rstart = uni((uint32_t)__shfl((int)r.start[line >> 6], (int)(line & 63)));
-        rlen = uni((uint32_t)__shfl((int)r.len[line >> 6], (int)(line & 63)));
+        rstart = uni((uint32_t)pick(r.start, line));
+        rlen = uni((uint32_t)pick(r.len, line));
     } else {
 #pragma unroll
         for (int h = 0; h < 2; ++h)
@@ -275,10 +273,10 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
             pr = row_pair(ent, rstart, rlen, o, c);
         } else {
             pr.P = nth_bit(cl_lo, cl_hi, 2 * c);
-            pr.ca = uni((uint32_t)__shfl((int)cval[pr.P >> 6], (int)(pr.P & 63)));
+            pr.ca = uni((uint32_t)pick(cval, pr.P));
             if (2 * c + 1 < s) {
                 pr.Q = nth_bit(cl_lo, cl_hi, 2 * c + 1);
-                pr.cb = uni((uint32_t)__shfl((int)cval[pr.Q >> 6], (int)(pr.Q & 63)));
+                pr.cb = uni((uint32_t)pick(cval, pr.Q));
             } else {   // the lowest row that is zero in the column (or the lowest other row)
                 const uint64_t vlo = o >= 64 ? ~0ull : ((1ull << o) - 1);
                 const uint64_t vhi = o > 64 ? (o >= 128 ? ~0ull : ((1ull << (o - 64)) - 1)) : 0ull;
@@ -288,7 +286,8 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
             }
         }
         const uint32_t keep = min(pr.P, pr.Q), drop = max(pr.P, pr.Q);
-        uint32_t *C = out + wbase + (uint64_t)c * pw;
+        uint32_t *const Cg = out + wbase + (uint64_t)c * pw;
+        uint32_t *C = cst ? cst : Cg;
         // pass 1: each lane's output rows, their lengths and sums
         uint32_t olen[2] = {0, 0}, orow[2] = {0xffffffffu, 0xffffffffu};
         uint64_t osum[2] = {0, 0};
@@ -337,10 +336,10 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
         // lengths of rows P and Q come from their owners
         uint32_t qs = 0, ql = 0, ps = 0, plen = 0;
         if (is_col) {
-            qs = uni((uint32_t)__shfl((int)r.start[pr.Q >> 6], (int)(pr.Q & 63)));
-            ql = uni((uint32_t)__shfl((int)r.len[pr.Q >> 6], (int)(pr.Q & 63)));
-            ps = uni((uint32_t)__shfl((int)r.start[pr.P >> 6], (int)(pr.P & 63)));
-            plen = uni((uint32_t)__shfl((int)r.len[pr.P >> 6], (int)(pr.P & 63)));
+            qs = uni((uint32_t)pick(r.start, pr.Q));
+            ql = uni((uint32_t)pick(r.len, pr.Q));
+            ps = uni((uint32_t)pick(r.start, pr.P));
+            plen = uni((uint32_t)pick(r.len, pr.P));
             if ((uint32_t)lane == (keep & 63)) {
                 const int h = keep >> 6;
                 uint32_t a = 0, b = 0, cnt = 0;
@@ -363,8 +362,13 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
                     ++cnt;
                     sum += mv;
                 }
-                olen[h] = cnt;
-                osum[h] = sum;
+                if (h) {
+                    olen[1] = cnt;
+                    osum[1] = sum;
+                } else {
+                    olen[0] = cnt;
+                    osum[0] = sum;
+                }
                 bad = bad || sum >= HP_MAX_ROWSUM;
             }
         }
@@ -392,8 +396,8 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
                 if (4 * q + b < co) wd |= (lenb[4 * q + b] & 0xffu) << (8 * b);
             C[4 + q] = wd;
         }
+        const uint32_t cwords = hp_node_words((int)co, (int)onnz);
         if (lane == 0) {
-            atomicMax(flags + 1, (unsigned long long)hp_node_words((int)co, (int)onnz));
             C[0] = co | (onnz << 8);
             C[1] = __float_as_uint(cbound < -1e29f ? -INFINITY : cbound);
             C[2] = problem;
@@ -453,9 +457,44 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
                 }
             }
         }
-        wave_sync();   // lenb is rewritten by the next child
+        wave_sync();   // lenb (and the staging buffer) are rewritten by the next child
+        if (cst) {
+            for (uint32_t q = (uint32_t)lane; q < cwords; q += WV) Cg[q] = cst[q];
+            wave_sync();
+        }
     }
     if (__ballot(bad) != 0 && lane == 0) atomicOr(flags, 1ull);
+}
+
+// Nodes up to this many words are staged in LDS (a cubic graph on 128 vertices takes about 420).
+constexpr int NODE_LDS = 512;
+
+__global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ lvl, const uint64_t *__restrict__ off,
+                                                  uint64_t first, uint32_t n, const uint32_t *__restrict__ keys,
+                                                  const uint64_t *__restrict__ place,
+                                                  uint32_t *__restrict__ out, uint64_t *__restrict__ out_off,
+                                                  unsigned long long *__restrict__ flags) {
+    __shared__ uint32_t len_all[BLK / WV][MAXO];
+    __shared__ __attribute__((aligned(16))) uint32_t node_all[BLK / WV][NODE_LDS];
+    __shared__ __attribute__((aligned(16))) uint32_t child_all[BLK / WV][NODE_LDS];
+    const int lane = threadIdx.x & (WV - 1), wv = threadIdx.x / WV;
+    const uint32_t k = blockIdx.x * (BLK / WV) + wv;
+    if (k >= n) return;
+    const uint32_t key = uni(keys[k]);
+    if ((key >> 9) == 0) return;   // a line without nonzeros: no children (per = 0)
+    const uint32_t *node = lvl + uni64(off[first + k]);
+    const uint32_t h0 = uni(node[0]);
+    const uint32_t pw = hp_node_words((int)(h0 & 0xffu), (int)(h0 >> 8));
+    const uint64_t pl = uni64(place[k]);
+    const uint64_t child_idx = pl >> 36, wbase = pl & ((1ull << 36) - 1);
+    if (pw <= (uint32_t)NODE_LDS) {   // coalesced copy in, children built in LDS, copied out
+        uint32_t *nb = node_all[wv];
+        for (uint32_t q = (uint32_t)lane; q < pw; q += WV) nb[q] = node[q];
+        wave_sync();
+        write_children(nb, key, child_idx, wbase, len_all[wv], child_all[wv], out, out_off, flags, lane);
+    } else {
+        write_children(node, key, child_idx, wbase, len_all[wv], nullptr, out, out_off, flags, lane);
+    }
 }
 
 }  // namespace

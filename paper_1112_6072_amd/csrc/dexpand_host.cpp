@@ -26,7 +26,7 @@ hipError_t launch_dexp_plan(const uint32_t *lvl, const uint64_t *off, uint64_t f
 size_t dexp_scan_tiles(uint32_t n);
 hipError_t launch_dexp_scan(const uint64_t *in, uint32_t n, uint64_t *tile_sums, uint64_t *out, uint64_t *grand,
                             hipStream_t s);
-// flags[0] |= 1 on a range error; flags[1] = max(flags[1], the words of every child written).
+// flags[0] |= 1 on a range error.
 hipError_t launch_dexp_write(const uint32_t *lvl, const uint64_t *off, uint64_t first, uint32_t n, const uint32_t *keys,
                              const uint64_t *place, uint32_t *out, uint64_t *out_off, unsigned long long *flags,
                              hipStream_t s);
@@ -38,7 +38,7 @@ namespace {
 struct Misc {
     unsigned long long grand;          // packed (children << 36 | words) of the last scan
     unsigned long long flags;          // bit 0: an entry or row sum out of range
-    unsigned long long maxw;           // the largest child (words) of the last write
+    unsigned long long pad;
     unsigned long long head;           // queue counter of the split launch
     unsigned long long stats[HP_SPLIT_STATS];
     ProbAcc prob;                      // the split launch's sum
@@ -54,7 +54,7 @@ struct Plan {
     Misc *misc = nullptr;              // device
     void *wide = nullptr;
     uint64_t wide_entries = 0;
-    std::vector<uint32_t> maxw;        // per level: the largest node (words) of its current contents
+    std::vector<uint32_t> maxw;        // per level: words per node to size its chunks by
 };
 
 }  // namespace
@@ -214,19 +214,19 @@ struct DexpRun {
                     st.nodes += kids;
                     st.max_level_nodes = std::max<uint64_t>(st.max_level_nodes, kids);
                     if (kids) {
-                        r = hip(launch_fill_u64(&P.misc->maxw, 1, 0ull, s), "clear size");
-                        if (r) return r;
                         r = hip(launch_dexp_write(level(o), offs(o), k, (uint32_t)chunk, P.keys, P.place,
                                                   level(o - 1), offs(o - 1), &P.misc->flags, s),
                                 "expansion write");
                         if (r) return r;
-                        r = hip(hipMemcpyAsync(tot, &P.misc->flags, sizeof(tot), hipMemcpyDeviceToHost, s),
+                        r = hip(hipMemcpyAsync(tot, &P.misc->flags, 8, hipMemcpyDeviceToHost, s),
                                 "download expansion flags");
                         if (r) return r;
                         r = hip(hipStreamSynchronize(s), "expansion write");
                         if (r) return r;
                         if (tot[0] & 1) return fail(HPERM_E_RANGE, "an expanded entry reached 2^22 or a row sum 2^24");
-                        P.maxw[o - 1 - P.T] = (uint32_t)tot[1];   // the largest child of the chunk
+                        // chunks of the next level are sized by the average room its nodes were
+                        // given (the parent's words); a plan that outgrows a buffer halves them
+                        P.maxw[o - 1 - P.T] = (uint32_t)((words + kids - 1) / kids);
                         r = o - 1 == P.T ? run_jobs(kids) : process(o - 1, 0, kids);
                         if (r) return r;
                         if (stopped) return HPERM_OK;

@@ -644,10 +644,19 @@ __device__ __forceinline__ uint64_t eval_leaf(const Region &rg, int p, uint32_t 
     return v;
 }
 
-// Proven log2 upper bound of the product of the row sums of the current node.
+// Proven log2 upper bounds of per(node): the product of its row sums, and of its column sums.
 __device__ __forceinline__ float rowsum_log2(const Region &rg, uint32_t AR, int lane) {
     const float x = lane < 32 && ((AR >> lane) & 1) ? __log2f((float)rg.rsum[lane]) : 0.0f;   // < 2^24: exact
     return wave_sumf(x) + 1e-3f;   // margin for the hardware logarithm and the float sum
+}
+__device__ __forceinline__ float colsum_log2(const Region &rg, uint32_t AR, uint32_t AC, int lane) {
+    float x = 0.0f;
+    if (lane < 32 && ((AC >> lane) & 1)) {
+        uint32_t cs = 0;   // below 24 * 2^22 < 2^27: the float is within one part in 2^24
+        for (uint32_t rows = AR; rows; rows &= rows - 1) cs += rg.M[(uint32_t)__builtin_ctz(rows) * rg.S + lane];
+        x = __log2f((float)cs) + 1e-6f;
+    }
+    return wave_sumf(x) + 1e-3f;
 }
 
 // per(leaf) from its wave-summed V modulo 2^64: (-1)^(p-1) V / 2^(p-1) after the checks that
@@ -760,7 +769,8 @@ __global__ __launch_bounds__(SW) void hper_split(SplitArgs a) {
                 n_terms += 1ull << (o - 1);
                 // exact modulo 2^64 when per(leaf) 2^(o-1) < 2^63 (bound: the job's, or the
                 // leaf's product of row sums)
-                const bool ok64 = fminf(jb, rowsum_log2(rg, AR, lane)) + (float)o <= 62.5f;
+                bool ok64 = fminf(jb, rowsum_log2(rg, AR, lane)) + (float)o <= 62.5f;
+                if (!ok64 && o <= PMAX) ok64 = colsum_log2(rg, AR, AC, lane) + (float)o <= 62.5f;
                 if (ok64 && o <= PMAX) {
                     bool bad;
                     const uint64_t per = normalise64(uni64(wave_sum64(eval_leaf(rg, o, AR, AC, lane))), o, &bad);
