@@ -97,9 +97,11 @@ typedef struct hperm_opts {
                              2^102 on the device instead of the host: expansion (2) with Algorithm
                              H_per's line rule (Section 2.1) level by level down to sub-matrices
                              of order T, which the device continuation of H_per finishes; the
-                             whole tree stays on the GPU in bounded memory. Other problems (and
-                             the serving loop) take the host path. Results are the same
-                             integers. 0 (or T <= split order): off. */
+                             whole tree stays on the GPU in bounded memory; problems of one
+                             order share one expansion (their results then report the group's
+                             job and subset-term counts and times). Other problems (and the
+                             serving loop) take the host path. Results are the same integers.
+                             0 (or T <= split order): off. */
     int32_t device_expand_mib; /* device memory for the expansion's level buffers in MiB
                              (0 = 8192); more memory means fewer, larger launches */
 } hperm_opts;
@@ -361,12 +363,13 @@ typedef struct hperm_launch_stat {
     int32_t persistent;
     int32_t variant;        /* walk variant: 0, or 1 / 2 for the paired walk of jobs whose
                                Gray column 0 reaches only the first 2 / 3 rows; 3 for the
-                               device continuation of H_per (split_order); 4 for one problem of
-                               the device expansion (device_expand): then n_jobs = its jobs of
-                               order T, items = the nodes it wrote, row_updates = its device
-                               H_per launches, ms = the whole problem on the device and
-                               alg_slots = the milliseconds of its device H_per launches */
-    int32_t reserved;
+                               device continuation of H_per (split_order); 4 for one group of
+                               problems of one order run by the device expansion
+                               (device_expand): then n_jobs = its jobs of order T, items = the
+                               nodes it wrote, row_updates = its device H_per launches, ms =
+                               the whole group on the device and alg_slots = the milliseconds
+                               of its device H_per launches */
+    int32_t reserved;       /* variant 4: the problems of the group */
     uint64_t items;         /* work items (64 lanes x 2^chunk Gray indices each) */
     uint64_t terms;         /* subset-terms: sum of 2^(m-1) over the jobs */
     uint64_t row_updates;   /* row-value updates of the Gray steps inside lane chunks */

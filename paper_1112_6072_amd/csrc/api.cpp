@@ -1131,30 +1131,43 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
     }
     if (host_idx.empty()) c->dev.launches.clear();
     const size_t budget = (size_t)(c->opts.device_expand_mib > 0 ? c->opts.device_expand_mib : 8192) << 20;
-    for (int k : dev_idx) {
+    // problems of one order share one device expansion
+    std::vector<int> order_of(dev_idx);
+    std::stable_sort(order_of.begin(), order_of.end(), [&](int x, int y) { return n[x] < n[y]; });
+    for (size_t g0 = 0; g0 < order_of.size();) {
+        size_t g1 = g0;
+        while (g1 < order_of.size() && n[order_of[g1]] == n[order_of[g0]]) ++g1;
         const double t0 = now_s();
-        CsrView v{n[k], row_ptr + rp_off[k], col_idx + nz_off[k], val + nz_off[k]};
-        U512 total;
+        std::vector<CsrView> grp;
+        for (size_t q = g0; q < g1; ++q) {
+            const int k = order_of[q];
+            grp.push_back(CsrView{n[k], row_ptr + rp_off[k], col_idx + nz_off[k], val + nz_off[k]});
+        }
+        std::vector<U512> totals;
         DexpStats st;
-        hperm_status s = device_expand_problem(&c->dev, v, device_in_effect(c->opts), split_in_effect(c->opts),
-                                               c->opts.s_leaf, budget, &total, &st);
+        hperm_status s = device_expand_group(&c->dev, grp, device_in_effect(c->opts), split_in_effect(c->opts),
+                                             c->opts.s_leaf, budget, &totals, &st);
         if (s) return s;
-        hperm_result &r = res[k];
-        memset(&r, 0, sizeof(r));
-        fill_result(total, &r);
-        r.n_jobs = (int32_t)std::min<uint64_t>(st.jobs, 0x7fffffff);
-        r.max_m = device_in_effect(c->opts);
-        r.arith_mask = 1 << (HPERM_ARITH_W64);
-        r.subset_terms = st.leaf_terms;
-        r.t_rnw_s = st.split_s;
-        r.t_expand_s = st.total_s - st.split_s;
-        r.t_total_s = now_s() - t0;
+        const double t1 = now_s();
+        for (size_t q = g0; q < g1; ++q) {
+            hperm_result &r = res[order_of[q]];
+            memset(&r, 0, sizeof(r));
+            fill_result(totals[q - g0], &r);
+            r.n_jobs = (int32_t)std::min<uint64_t>(st.jobs, 0x7fffffff);   // the group's figures
+            r.max_m = device_in_effect(c->opts);
+            r.arith_mask = 1 << (HPERM_ARITH_W64);
+            r.subset_terms = st.leaf_terms;
+            r.t_rnw_s = st.split_s;
+            r.t_expand_s = st.total_s - st.split_s;
+            r.t_total_s = t1 - t0;
+        }
         hperm_launch_stat ls{};
         ls.ring = HP_W64;
         ls.bucket = bucket_of(device_in_effect(c->opts));
-        ls.n_jobs = r.n_jobs;
+        ls.n_jobs = (int32_t)std::min<uint64_t>(st.jobs, 0x7fffffff);
         ls.persistent = 1;
         ls.variant = 4;
+        ls.reserved = (int32_t)(g1 - g0);
         ls.items = st.nodes;
         ls.terms = st.leaf_terms;
         ls.row_updates = st.launches;
@@ -1167,6 +1180,7 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
         ls.deferred_bound = st.deferred_bound;
         ls.alg_slots = st.split_s * 1e3;   // the device H_per launches' share of ms
         c->dev.launches.push_back(ls);
+        g0 = g1;
     }
     for (int k = 0; k < count; ++k) out[k] = res[k];
     return HPERM_OK;

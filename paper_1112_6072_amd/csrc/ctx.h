@@ -147,6 +147,11 @@ struct DexpSample {
 };
 hperm_status device_expand_problem(Dev *c, const CsrView &a, int T, int t, int s_leaf, size_t budget_bytes, U512 *out,
                                    DexpStats *stats, DexpSample *sample = nullptr);
+// The same for several problems of one order n > T at once: their trees share the level
+// buffers and the launches; out[k] receives per(A_k).
+hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int T, int t, int s_leaf,
+                                 size_t budget_bytes, std::vector<U512> *out, DexpStats *stats,
+                                 DexpSample *sample = nullptr);
 
 // per(A) of a problem from its device accumulator (limb sums + CRT of the residue sums).
 U512 prob_value(const ProbAcc &q);

@@ -41,7 +41,6 @@ struct Misc {
     unsigned long long pad;
     unsigned long long head;           // queue counter of the split launch
     unsigned long long stats[HP_SPLIT_STATS];
-    ProbAcc prob;                      // the split launch's sum
 };
 
 struct Plan {
@@ -52,6 +51,8 @@ struct Plan {
     uint32_t *keys = nullptr;          // plan of a chunk (N / 2 entries)
     uint64_t *packed = nullptr, *place = nullptr, *tiles = nullptr;
     Misc *misc = nullptr;              // device
+    ProbAcc *probs = nullptr;          // device: one split launch's sums, one per problem
+    int nprob = 1;
     void *wide = nullptr;
     uint64_t wide_entries = 0;
     std::vector<uint32_t> maxw;        // per level: words per node to size its chunks by
@@ -62,7 +63,7 @@ struct Plan {
 struct DexpRun {
     Dev *c;
     Plan P;
-    U512 total;
+    std::vector<U512> total;           // per problem of the group
     DexpStats st;
     std::string err;
     hperm_status status = HPERM_OK;
@@ -103,10 +104,14 @@ struct DexpRun {
             r = hip(launch_fill_u64((unsigned long long *)accs, n * (sizeof(JobAcc) / 8), 0ull, s), "clear accumulators");
             if (r) return r;
         }
+        std::vector<ProbAcc> hp_((size_t)P.nprob);
         for (int attempt = 0;; ++attempt) {
             hperm_status r = hip(launch_fill_u64((unsigned long long *)&m->head,
                                                  (sizeof(Misc) - offsetof(Misc, head)) / 8, 0ull, s),
                                  "clear split counters");
+            if (r) return r;
+            r = hip(launch_fill_u64((unsigned long long *)P.probs, (uint64_t)P.nprob * (sizeof(ProbAcc) / 8), 0ull, s),
+                    "clear problem sums");
             if (r) return r;
             const double t0 = now_s();
             if (accs && attempt) {
@@ -115,10 +120,13 @@ struct DexpRun {
                 if (r) return r;
             }
             r = hip(launch_split_nodes(level(P.T), offs(P.T), (uint32_t)n, P.t, P.T, P.s_leaf, &m->head, accs,
-                                       &m->prob, m->stats, P.wide, P.wide_entries, s),
+                                       P.probs, m->stats, P.wide, P.wide_entries, s),
                     "device H_per launch");
             if (r) return r;
             r = hip(hipMemcpyAsync(&h, m, sizeof(Misc), hipMemcpyDeviceToHost, s), "download split results");
+            if (r) return r;
+            r = hip(hipMemcpyAsync(hp_.data(), P.probs, hp_.size() * sizeof(ProbAcc), hipMemcpyDeviceToHost, s),
+                    "download problem sums");
             if (r) return r;
             r = hip(hipStreamSynchronize(s), "device H_per");
             if (r) return r;
@@ -175,7 +183,7 @@ struct DexpRun {
             }
             if (stop_after_sample && sample_vals->size() >= sample_max) stopped = true;
         }
-        total.add(prob_value(h.prob));
+        for (int k = 0; k < P.nprob; ++k) total[(size_t)k].add(prob_value(hp_[(size_t)k]));
         st.jobs += n;
         st.launches++;
         st.leaves += h.stats[0];
@@ -242,9 +250,9 @@ struct DexpRun {
     }
 };
 
-hperm_status device_expand_problem(Dev *c, const CsrView &a, int T, int t, int s_leaf, size_t budget_bytes, U512 *out,
-                                   DexpStats *stats, DexpSample *sample) {
-    DexpRun run{c, Plan{}, U512(), DexpStats{}, std::string(), HPERM_OK};
+hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int T, int t, int s_leaf,
+                                 size_t budget_bytes, std::vector<U512> *out, DexpStats *stats, DexpSample *sample) {
+    DexpRun run{c, Plan{}, {}, DexpStats{}, std::string(), HPERM_OK};
     if (sample) {
         run.sample_max = sample->max_jobs;
         run.stop_after_sample = sample->stop_early;
@@ -254,39 +262,60 @@ hperm_status device_expand_problem(Dev *c, const CsrView &a, int T, int t, int s
         sample->vals.clear();
     }
     Plan &P = run.P;
-    const int n = a.n;
+    const int count = (int)probs.size();
+    out->assign((size_t)count, U512());
+    if (count == 0) return HPERM_OK;
+    const int n = probs[0].n;
     if (n <= T || T > HP_SPLIT_MAX_M || t < HP_SPLIT_MIN_T || t >= T)
         return set_error(c, HPERM_E_INVALID, "device expansion: needs t < T <= 24 < n");
-    // the root node, its bound (rows, columns and Bregman's for 0-1 inputs) and its size
-    std::vector<uint32_t> root;
-    double lb = 0.0;
-    int rc = pack_root_node(a, &root, &lb);
-    if (rc == 1) {   // a zero row or column
-        *out = U512();
+    // the roots (problem k's carries k), their bounds (rows, columns and Bregman's for 0-1
+    // inputs); problems with a zero line are 0 without device work
+    std::vector<uint32_t> roots;
+    std::vector<uint64_t> root_off;
+    std::vector<double> bounds((size_t)count, 0.0);
+    std::vector<int> live;
+    uint32_t maxroot = 0;
+    for (int k = 0; k < count; ++k) {
+        if (probs[(size_t)k].n != n) return set_error(c, HPERM_E_INVALID, "device expansion: a group has one order");
+        std::vector<uint32_t> root;
+        const int rc = pack_root_node(probs[(size_t)k], &root, &bounds[(size_t)k]);
+        if (rc == 1) continue;
+        if (rc) return set_error(c, rc == -2 ? HPERM_E_RANGE : HPERM_E_INVALID, "device expansion: input out of range");
+        if (bounds[(size_t)k] > 102.0)
+            return set_error(c, HPERM_E_RANGE, "device expansion: the permanent bound exceeds 2^102");
+        root[2] = (uint32_t)k;
+        root_off.push_back(roots.size());
+        roots.insert(roots.end(), root.begin(), root.end());
+        maxroot = std::max<uint32_t>(maxroot, (uint32_t)root.size());
+        live.push_back(k);
+    }
+    if (live.empty()) {
         if (stats) *stats = run.st;
+        if (sample) sample->complete = true;
         return HPERM_OK;
     }
-    if (rc) return set_error(c, rc == -2 ? HPERM_E_RANGE : HPERM_E_INVALID, "device expansion: input out of range");
-    if (lb > 102.0)
-        return set_error(c, HPERM_E_RANGE, "device expansion: the permanent bound exceeds 2^102");
+    run.total.assign((size_t)count, U512());
     P.n = n;
     P.T = T;
     P.t = t;
     P.s_leaf = s_leaf;
+    P.nprob = count;
     const int L = n - T + 1;
     // per level: 7/8 of its share in words, 1/8 in 8-byte offsets; the plan arrays for half a
     // level's offsets; the record buffer
     const size_t share = budget_bytes / (size_t)(L + 1);
     P.W = std::min<uint64_t>((share * 7 / 8) / 4, (uint64_t)1 << 29);
     P.N = std::max<uint64_t>(std::min<uint64_t>((share / 8) / 8, (uint64_t)1 << 26), 64);
-    P.W = std::max<uint64_t>(P.W, 2 * (uint64_t)root.size() + 64);
+    P.W = std::max<uint64_t>(P.W, 2 * (uint64_t)roots.size() + 64);
+    P.N = std::max<uint64_t>(P.N, 2 * (uint64_t)live.size() + 64);
     const size_t half = P.N / 2 + 1;
     const size_t tiles = dexp_scan_tiles((uint32_t)half) + 1;
     hperm_status s = ensure_buf(c, B_DX_LEVELS, (size_t)L * P.W * 4);
     if (s) return s;
     s = ensure_buf(c, B_DX_OFFS, (size_t)L * P.N * 8);
     if (s) return s;
-    s = ensure_buf(c, B_DX_AUX, half * 4 + 256 + 2 * half * 8 + 512 + tiles * 8 + 256 + sizeof(Misc) + 256);
+    s = ensure_buf(c, B_DX_AUX, half * 4 + 256 + 2 * half * 8 + 512 + tiles * 8 + 256 + sizeof(Misc) + 256 +
+                                    (size_t)count * sizeof(ProbAcc) + 256);
     if (s) return s;
     // deferred leaves are rare (orders above 16, or bounds beyond 64 bits): a first buffer of
     // 2^20 records, grown when a launch reports more
@@ -307,27 +336,38 @@ hperm_status device_expand_problem(Dev *c, const CsrView &a, int T, int t, int s
     P.place = (uint64_t *)take(half * 8);
     P.tiles = (uint64_t *)take(tiles * 8);
     P.misc = (Misc *)take(sizeof(Misc));
+    P.probs = (ProbAcc *)take((size_t)count * sizeof(ProbAcc));
     P.wide = c->buf[B_SPLIT_WIDE].ptr;
     P.maxw.assign((size_t)L, 0);
-    P.maxw[(size_t)L - 1] = (uint32_t)root.size();
+    P.maxw[(size_t)L - 1] = maxroot;
     c->resident_jobs = 0;   // the arena's layout may have moved the job table
     c->resident_list = 0;
     const double t0 = now_s();
-    s = run.hip(hipMemcpyAsync(run.level(n), root.data(), root.size() * 4, hipMemcpyHostToDevice, c->stream),
-                "upload root");
-    if (!s) {
-        const uint64_t zero = 0;
-        s = run.hip(hipMemcpyAsync(run.offs(n), &zero, 8, hipMemcpyHostToDevice, c->stream), "upload root offset");
-    }
+    s = run.hip(hipMemcpyAsync(run.level(n), roots.data(), roots.size() * 4, hipMemcpyHostToDevice, c->stream),
+                "upload roots");
+    if (!s)
+        s = run.hip(hipMemcpyAsync(run.offs(n), root_off.data(), root_off.size() * 8, hipMemcpyHostToDevice, c->stream),
+                    "upload root offsets");
     if (!s) s = run.hip(launch_fill_u64(&P.misc->grand, 3, 0ull, c->stream), "clear flags");
-    if (!s) s = run.process(n, 0, 1);
+    if (!s) s = run.process(n, 0, live.size());
     run.st.total_s = now_s() - t0;
     if (s) return set_error(c, s, run.err);
     if (sample) sample->complete = !run.stopped;
-    if (!run.stopped && run.total.bits() > (int)std::ceil(lb) + 1)
-        return set_error(c, HPERM_E_INTERNAL, "device expansion: the result exceeds its proven bound");
+    if (!run.stopped)
+        for (int k : live)
+            if (run.total[(size_t)k].bits() > (int)std::ceil(bounds[(size_t)k]) + 1)
+                return set_error(c, HPERM_E_INTERNAL, "device expansion: a result exceeds its proven bound");
     *out = run.total;
     if (stats) *stats = run.st;
+    return HPERM_OK;
+}
+
+hperm_status device_expand_problem(Dev *c, const CsrView &a, int T, int t, int s_leaf, size_t budget_bytes, U512 *out,
+                                   DexpStats *stats, DexpSample *sample) {
+    std::vector<U512> v;
+    const hperm_status s = device_expand_group(c, std::vector<CsrView>{a}, T, t, s_leaf, budget_bytes, &v, stats, sample);
+    if (s) return s;
+    *out = v[0];
     return HPERM_OK;
 }
 

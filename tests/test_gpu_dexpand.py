@@ -58,7 +58,9 @@ def test_device_expansion_small_problems(hperm, T, t):
     finally:
         c.close()
     assert got == want
-    assert len(dev) == sum(1 for A in mats if A.shape[0] > T)
+    big = [A.shape[0] for A in mats if A.shape[0] > T]
+    assert len(dev) == len(set(big))                 # one expansion per order
+    assert sum(l["reserved"] for l in dev) == len(big)
 
 
 @pytest.mark.parametrize("kind", ["cubic", "integer"])
@@ -103,7 +105,7 @@ def test_device_expansion_n60_and_mixed_batch(hperm):
     finally:
         c.close()
     assert got == [int(GOLDEN[f"cubic24_seed{s}"]) for s in range(3)] + [int(GOLDEN[n]) for n, _ in items[:2]]
-    assert len(dev) == 2
+    assert len(dev) == 1 and dev[0]["reserved"] == 2   # the two graphs on 60 vertices together
 
 
 def test_device_expansion_n80_golden(hperm):
