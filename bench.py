@@ -302,6 +302,16 @@ def large_single(hp, W, seeds=(0,)):
             out[name] = rec
     finally:
         ctx.close()
+    # random cubic graphs on 120 vertices: the library's own estimate of their trees (Knuth's
+    # random descents) and the time it implies at the rate just measured
+    rates = [r["leaves"] / r["device_hper_s"] for r in out.values() if r.get("device_hper_s")]
+    rate = max(rates) if rates else None
+    for s in (0, 1):
+        A = W.random_cubic_matrix(120, s)
+        _, lv = hp.tree_estimate(A, samples=20000, seed=3, split_order=12, device_expand=22)
+        out[f"cubic120_seed{s}"] = {"run": False, "estimated_leaves": float(lv.sum()),
+                                    "projected_s_at_measured_leaf_rate": float(lv.sum() / rate) if rate else None,
+                                    "estimator": "20000 random descents of the expansion tree (hperm_tree_estimate)"}
     return out
 
 

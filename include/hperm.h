@@ -286,6 +286,21 @@ hperm_status hperm_device_expand_sample(hperm_ctx *ctx, int32_t n, const int32_t
                                         int32_t stop_early, uint32_t *mats, hperm_result *values,
                                         int32_t *n_sampled, hperm_result *total);
 
+/* Work estimate before a run (host only; Knuth's estimator of a search tree's size): `samples`
+ * random descents from the root of per(A)'s expansion tree, each taking one child of a node
+ * with equal probability, under the rule of the default path for the options given (opts may
+ * be NULL for the defaults): every node above the device expansion's order T is split (the
+ * host cut-off m_cut when the device expansion is off), then Algorithm H_per's rule (Section
+ * 2.1: split while the sparsest line has 1..4 nonzeros) down to the target order t of the device
+ * continuation (m_cut when it is off). Along a descent the product of the child counts above a
+ * node estimates the number of nodes at its order without bias. nodes[n + 1] and leaves[n + 1]
+ * receive the estimated nodes and leaves of each order 0..n (mean over the descents). seed
+ * drives SplitMix64. Errors: HPERM_E_INVALID (options, malformed matrix, NULL arrays,
+ * samples < 1), HPERM_E_RANGE (an expanded entry beyond the supported range). */
+hperm_status hperm_tree_estimate(const hperm_opts *opts, int32_t n, const int32_t *row_ptr,
+                                 const int32_t *col_idx, const uint32_t *val, int32_t samples,
+                                 uint64_t seed, double *nodes, double *leaves);
+
 /* ---- scheduling study (the paper's load-balancing analysis) --------------------------- */
 
 /* Work time of every job (natural index) in the last persistent hperm_run_jobs on these jobs

@@ -121,6 +121,7 @@ _SIGS = {
     "hperm_permanental_polynomial": [_P, _I32, _P, _P, _P, _P],
     "hperm_polynomial_interpolate": [_I32, _P, _I32, _P],
     "hperm_list_schedule": [_I32, _P, _P, _I32, ctypes.POINTER(_U64), _P],
+    "hperm_tree_estimate": [ctypes.POINTER(Opts), _I32, _P, _P, _P, _I32, _U64, _P, _P],
     "hperm_kendall_tau": [_I32, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_double)],
 }
@@ -484,6 +485,20 @@ def permanent(A, **opts) -> int:
     if _default_ctx is None:
         _default_ctx = Context()
     return _default_ctx.permanent(A)
+
+
+def tree_estimate(A, samples: int = 2000, seed: int = 1, **opts) -> tuple[np.ndarray, np.ndarray]:
+    """Knuth's estimate of per(A)'s expansion tree under the default path's rule (options as
+    for Context): (nodes per order, leaves per order), arrays of length n + 1."""
+    n, rp, ci, va = _csr(A)
+    o = _opts(opts)
+    nodes = np.zeros(n + 1, np.float64)
+    leaves = np.zeros(n + 1, np.float64)
+    st = _lib.hperm_tree_estimate(ctypes.byref(o), n, _ptr(rp), _ptr(ci) if ci.size else None,
+                                  _ptr(va) if va.size else None, int(samples), int(seed), _ptr(nodes), _ptr(leaves))
+    if st != OK:
+        raise HpermError(st, "tree_estimate")
+    return nodes, leaves
 
 
 def list_schedule(times, order, machines: int) -> tuple[int, np.ndarray]:

@@ -1230,6 +1230,22 @@ hperm_status hperm_device_expand_sample(hperm_ctx *c, int32_t n, const int32_t *
     return HPERM_OK;
 }
 
+hperm_status hperm_tree_estimate(const hperm_opts *opts, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                                 const uint32_t *val, int32_t samples, uint64_t seed, double *nodes, double *leaves) {
+    if (!nodes || !leaves || samples < 1) return HPERM_E_INVALID;
+    hperm_opts o;
+    hperm_default_opts(&o);
+    if (opts) {
+        if (check_opts(opts)) return HPERM_E_INVALID;
+        o = *opts;
+    }
+    CsrView v{n, row_ptr, col_idx, val};
+    if (!validate_csr(v).empty()) return HPERM_E_INVALID;
+    const int t = split_in_effect(o) > 0 ? split_in_effect(o) : o.m_cut;
+    const int T = device_in_effect(o) > 0 ? device_in_effect(o) : o.m_cut;
+    return estimate_tree(v, std::max(T, t), t, o.s_leaf, samples, seed, nodes, leaves) ? HPERM_E_RANGE : HPERM_OK;
+}
+
 hperm_status hperm_permanent_csr(hperm_ctx *c, int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
                                  const uint32_t *val, hperm_result *out) {
     const int64_t z = 0;

@@ -956,4 +956,79 @@ int pack_root_node(const CsrView &a, std::vector<uint32_t> *out, double *log2b) 
     return 0;
 }
 
+// Knuth's estimator of the size of the expansion tree: random root-to-leaf descents, each child
+// taken with equal probability; along a path, the product of the child counts of the nodes
+// above a node is an unbiased estimate of the number of nodes at that depth (here: order).
+int estimate_tree(const CsrView &a, int T, int t, int s_leaf, int samples, uint64_t seed, double *nodes,
+                  double *leaves) {
+    const int n = a.n;
+    for (int o = 0; o <= n; ++o) nodes[o] = leaves[o] = 0.0;
+    if (n == 0 || samples <= 0) return 0;
+    Node root;
+    int nz = 0;
+    for (int e = 0; e < a.row_ptr[n]; ++e) nz += a.val[e] != 0;
+    root.reserve(n, nz);
+    root.m = n;
+    int o = 0;
+    for (int i = 0; i < n; ++i) {
+        root.rp[i] = o;
+        for (int e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
+            if (a.val[e]) {
+                root.ci[o] = (uint8_t)a.col_idx[e];
+                root.v[o++] = a.val[e];
+            }
+    }
+    root.rp[n] = o;
+    root.nnz = o;
+    Node cur, nxt;
+    cur.reserve(n, nz);
+    nxt.reserve(n, nz);
+    std::vector<int> colcnt(n + 1);
+    uint64_t state = seed;
+    auto next_u64 = [&state]() {   // SplitMix64 (Steele, Lea and Flood)
+        uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    try {
+        for (int smp = 0; smp < samples; ++smp) {
+            cur.m = root.m;
+            cur.nnz = root.nnz;
+            std::copy(root.rp.begin(), root.rp.begin() + root.m + 1, cur.rp.begin());
+            std::copy(root.ci.begin(), root.ci.begin() + root.nnz, cur.ci.begin());
+            std::copy(root.v.begin(), root.v.begin() + root.nnz, cur.v.begin());
+            double w = 1.0;
+            for (;;) {
+                bool is_col = false;
+                int line = 0;
+                const int s = min_line(cur, &is_col, &line, colcnt.data());
+                if (s == 0) break;
+                nodes[cur.m] += w;
+                const bool split = cur.m > T || (cur.m > t && cur.m > 2 && s < s_leaf && s <= 4);
+                if (!split) {
+                    leaves[cur.m] += w;
+                    break;
+                }
+                Pair pairs[HP_MAX_N / 2 + 1];
+                const int np = is_col ? col_pairs(cur, line, pairs) : row_pairs(cur, line, pairs);
+                const int k = (int)(next_u64() % (uint64_t)np);
+                if (is_col)
+                    make_child_col(cur, line, pairs[k].p, pairs[k].q, pairs[k].ca, pairs[k].cb, &nxt);
+                else
+                    make_child(cur, line, pairs[k].p, pairs[k].q, pairs[k].ca, pairs[k].cb, &nxt);
+                std::swap(cur, nxt);
+                w *= np;
+            }
+        }
+    } catch (const RangeError &) {
+        return -2;
+    }
+    for (int q = 0; q <= n; ++q) {
+        nodes[q] /= samples;
+        leaves[q] /= samples;
+    }
+    return 0;
+}
+
 }  // namespace hp

@@ -65,6 +65,13 @@ int pack_dense_job(int n, const uint32_t *a, int arith, JobDesc *desc, uint32_t 
 // entry or row sum beyond the kernels' limits).
 int pack_root_node(const CsrView &a, std::vector<uint32_t> *node, double *log2b);
 
+// Knuth's random-descent estimate of the expansion tree of a validated CSR matrix under the
+// rule of the device path (split every node above order T, then H_per's rule down to order
+// t): nodes[o] and leaves[o] (o = 0..n) receive the estimated nodes and leaves of each order.
+// Returns 0, or -2 when an expanded entry leaves the supported range on a sampled path.
+int estimate_tree(const CsrView &a, int T, int t, int s_leaf, int samples, uint64_t seed, double *nodes,
+                  double *leaves);
+
 // Default lane chunk (log2 Gray indices per lane) for a job of order m.
 int default_chunk_log2(int m);
 

@@ -168,3 +168,20 @@ def test_job_cycles_need_a_timed_run(hp):
             c.set_opts(time_jobs=2)
     finally:
         c.close()
+
+
+def test_tree_estimate_exact_and_unbiased(hp):
+    """Knuth's estimate of the expansion tree (host): exact for a tree without branching (a
+    permutation matrix: one node per order), and close to the oracle's exact job count for
+    cubic graphs (every node above the cut-off split, as expand_leaves does with no s_leaf
+    stop)."""
+    n = 20
+    P = np.zeros((n, n), np.uint32)
+    P[np.arange(n), (np.arange(n) * 7) % n] = 3
+    nodes, leaves = hp.tree_estimate(P, samples=50, seed=2, split_order=8, device_expand=12)
+    assert nodes[8:].tolist() == [1.0] * (n - 7) and leaves[8] == 1.0 and leaves.sum() == 1.0
+    for seed in (0, 1):
+        A = W.random_cubic_matrix(30, seed)
+        exact = len(expand_leaves(np.asarray(A, dtype=np.int64), 12, 10 ** 9, 40))
+        _, lv = hp.tree_estimate(A, samples=20000, seed=5, split_order=12, device_expand=12, m_cut=12)
+        assert abs(lv.sum() - exact) <= 0.05 * exact, (lv.sum(), exact)
