@@ -182,6 +182,35 @@ def uneven_orders(hp, W, ctx, n_jobs: int = 600, seed: int = 11):
     return out
 
 
+def autotune_leg(hp, W, ctx, jobs, trials, want):
+    """The autotuner on the benchmark's jobs and on the 600 uneven jobs: its table, and the R-NW
+    milliseconds of the whole persistent run (estimate order, median of 3) with the defaults and
+    with the tuned lane chunks and grids (the values must not change)."""
+    import numpy as np
+    def rnw_ms(J):
+        ms = []
+        for _ in range(3):
+            tot, _, _ = ctx.run(J, "estimate", True)
+            ms.append(sum(L["ms"] for L in ctx.last_launches()))
+        return sorted(ms)[1], tot
+    out = {}
+    rng = np.random.default_rng(11)
+    uneven = [W.permutation_union_matrix(int(rng.integers(16, 31)), int(rng.integers(3, 7)),
+                                         int(rng.integers(0, 2 ** 31 - 1)), 1, 4) for _ in range(600)]
+    for name, J in (("n60", jobs), ("uneven", ctx.jobs_from_dense(uneven))):
+        ctx.tune_clear()
+        ctx.estimate(J, trials, 1)
+        d_ms, d_tot = rnw_ms(J)
+        t0 = time.perf_counter()
+        table = ctx.autotune(J)
+        tune_s = time.perf_counter() - t0
+        t_ms, t_tot = rnw_ms(J)
+        out[name] = {"default_rnw_ms": d_ms, "tuned_rnw_ms": t_ms, "tuning_s": tune_s, "table": table,
+                     "values_equal": t_tot == d_tot and (name != "n60" or t_tot == want)}
+    ctx.tune_clear()
+    return out
+
+
 def schedule_study(hp, ctx, jobs, keys, machines=(1, 2, 4, 8, 16, 32)):
     """The paper's load-balancing study on our jobs. One persistent run in natural order with
     per-job work timing gives T (work cycles), P (the exact job permanents) and, from the
@@ -451,6 +480,7 @@ def main():
         ctx.run(jobs, order, True)
         extra[f"persistent_{order}_rnw_ms"] = sum(L["ms"] for L in ctx.last_launches())
     extra["uneven_jobs"] = uneven_orders(hp, W, ctx)
+    extra["autotune"] = autotune_leg(hp, W, ctx, jobs, args.trials, tot)
     # one problem alone: the truncated icosahedron (C60), median of 5 after a warm-up, on the
     # default path and on the R-NW-only one
     def c60_alone(split, dexp=0):

@@ -301,6 +301,39 @@ hperm_status hperm_tree_estimate(const hperm_opts *opts, int32_t n, const int32_
                                  const int32_t *col_idx, const uint32_t *val, int32_t samples,
                                  uint64_t seed, double *nodes, double *leaves);
 
+/* ---- autotuning of the persistent R-NW launches -------------------------------------- */
+
+/* One tuned launch group: its ring (0: mod 2^64, 1: mod 2^128, 2: residues), order bucket
+ * (0..4: orders <= 16, 20, 24, 32, 40) and walk variant (as in hperm_launch_stat); the lane
+ * chunk as an offset from each job's own (2^chunk Gray indices per lane, so 2^(m-7-chunk) work
+ * items of 64 lanes, i.e. waves, per job of order m) and the persistent grid as a percentage of
+ * the resident one; the sample's R-NW milliseconds with the defaults and with the choice (both
+ * 0 when the entry came from a cache). */
+typedef struct hperm_tune_entry {
+    int32_t ring, bucket, variant;
+    int32_t chunk_delta;
+    int32_t grid_pct;
+    int32_t from_cache;
+    double ms_default, ms_tuned;
+} hperm_tune_entry;
+
+/* Autotune the persistent R-NW launches (the work decomposition of Step 3, Section 3.3) for the
+ * launch groups of a job table: per group, the kernel runs on a sample of the group's jobs
+ * (natural order, about 2^33 subset-terms) with lane-chunk offsets -3..+1 and grids of 100, 75
+ * and 50 % of the resident one, twice each; the fastest pair (kept only when 2 % faster than
+ * the defaults) enters the context's tuning table, which every later persistent run on the
+ * context applies (results never change: the chunk only regroups the same Gray indices). With
+ * cache_path (may be NULL), entries for this GPU architecture are first read from that JSON
+ * file (groups found there are not re-timed unless force != 0) and the table is written back
+ * after tuning. jobs may be NULL: only the cache is read. out[max] receives the table (may be
+ * NULL when max = 0) and *n its size. Errors: HPERM_E_INVALID (arguments, serving, an
+ * unwritable cache), HPERM_E_DEVICE, HPERM_E_NOMEM. */
+hperm_status hperm_autotune(hperm_ctx *ctx, hperm_jobs *jobs, const char *cache_path, int32_t force,
+                            hperm_tune_entry *out, int32_t max, int32_t *n);
+
+/* Forget the context's tuning (later runs use the expansion's chunks and resident grids). */
+hperm_status hperm_tune_clear(hperm_ctx *ctx);
+
 /* ---- scheduling study (the paper's load-balancing analysis) --------------------------- */
 
 /* Work time of every job (natural index) in the last persistent hperm_run_jobs on these jobs

@@ -87,6 +87,15 @@ class LaunchStat(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("ring", ctypes.c_int32), ("bucket", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("chunk_delta", ctypes.c_int32), ("grid_pct", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("ms_default", ctypes.c_double), ("ms_tuned", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _P = ctypes.c_void_p
 _I32, _U64, _SZ = ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
 _SIGS = {
@@ -122,6 +131,8 @@ _SIGS = {
     "hperm_polynomial_interpolate": [_I32, _P, _I32, _P],
     "hperm_list_schedule": [_I32, _P, _P, _I32, ctypes.POINTER(_U64), _P],
     "hperm_tree_estimate": [ctypes.POINTER(Opts), _I32, _P, _P, _P, _I32, _U64, _P, _P],
+    "hperm_autotune": [_P, _P, ctypes.c_char_p, _I32, ctypes.POINTER(TuneEntry), _I32, ctypes.POINTER(_I32)],
+    "hperm_tune_clear": [_P],
     "hperm_kendall_tau": [_I32, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_double)],
 }
@@ -425,6 +436,19 @@ class Context:
         totals = [tot[k].value for k in range(npb)]
         pjv = [pj[k].value for k in range(nj)] if per_job else None
         return totals, pjv, [tot[k] for k in range(npb)]
+
+    def autotune(self, jobs: "Jobs | None" = None, cache_path: str | None = None, force: bool = False) -> list[dict]:
+        """Tune the persistent R-NW launches on a job table's launch groups (or only load a
+        cache); returns the context's tuning table."""
+        buf = (TuneEntry * 64)()
+        n = _I32()
+        self._check(_lib.hperm_autotune(self.handle, jobs.handle if jobs is not None else None,
+                                        cache_path.encode() if cache_path else None, 1 if force else 0,
+                                        buf, 64, ctypes.byref(n)), "autotune")
+        return [buf[k].as_dict() for k in range(min(n.value, 64))]
+
+    def tune_clear(self):
+        self._check(_lib.hperm_tune_clear(self.handle), "tune_clear")
 
     # ---------------------------------------------------------------- serving
     def serve_start(self, max_requests: int = 1024, arena_bytes: int = 1 << 30):

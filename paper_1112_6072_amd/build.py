@@ -13,8 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libhperm.so")
 SOURCES = ["kernels.hip", "split.hip", "dexpand.hip", "noalloc.hip", "expand.cpp", "api.cpp", "serve.cpp",
-           "dexpand_host.cpp", "sched.cpp", "poly.cpp"]
-HIP_HOST_SOURCES = {"api.cpp", "serve.cpp", "dexpand_host.cpp"}   # host code that calls the HIP runtime
+           "dexpand_host.cpp", "tune.cpp", "sched.cpp", "poly.cpp"]
+HIP_HOST_SOURCES = {"api.cpp", "serve.cpp", "dexpand_host.cpp", "tune.cpp"}   # host code that calls the HIP runtime
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # gfx950 only; packed FP32 instructions are disabled for all device code.

@@ -514,6 +514,66 @@ static void build_queue_groups(hperm_jobs *j, int split) {
     j->qsplit = split;
 }
 
+// The lane chunk of a job under a tuning offset (the limits of the expansion's own choice:
+// at most 12, at most m - 1, at least m - 32).
+static int tuned_chunk(int m, int c0, int delta) {
+    int c = c0 + delta;
+    if (c > 12) c = 12;
+    if (c > m - 1) c = std::max(0, m - 1);
+    if (c < 1) c = std::min(1, std::max(0, m - 1));
+    if (c < m - 32) c = m - 32;
+    return c;
+}
+
+// Brings the job table's lane chunks in line with the context's tuning table (each job's own
+// chunk plus its group's offset; the expansion's chunks when untuned).
+static void apply_tuning(Dev *c, hperm_jobs *j) {
+    const size_t nd = j->tab.desc.size();
+    TuneTable *tt = c->tune.get();
+    uint64_t ver = 0;
+    std::map<int, TuneEntry> table;
+    if (tt) {
+        std::lock_guard<std::mutex> lk(tt->mu);
+        ver = tt->version;
+        table = tt->e;
+    }
+    if (j->tune_table == (const void *)tt && j->tune_version == ver) return;
+    if (j->chunk0.size() != nd) {
+        j->chunk0.resize(nd);
+        for (size_t k = 0; k < nd; ++k) j->chunk0[k] = j->tab.desc[k].chunk_log2;
+    }
+    bool changed = false;
+    for (size_t k = 0; k < nd; ++k) {
+        JobDesc &d = j->tab.desc[k];
+        JobDesc d0 = d;
+        d0.chunk_log2 = j->chunk0[k];
+        int want = d0.chunk_log2;
+        const auto it = table.find(tune_key(d.arith, bucket_of(d.m), walk_variant(d0, d0.chunk_log2)));
+        if (it != table.end() && d0.chunk_log2 > 0) want = tuned_chunk(d.m, d0.chunk_log2, it->second.chunk_delta);
+        if (d.chunk_log2 != want) {
+            d.chunk_log2 = (uint8_t)want;
+            changed = true;
+        }
+    }
+    if (changed) {   // new chunks: new work items and groups, and the descriptors go up again
+        j->qgroup.clear();
+        if (c->resident_jobs == j->id) c->resident_jobs = 0;
+    }
+    j->tune_table = tt;
+    j->tune_version = ver;
+}
+
+// The persistent grid of a launch group under the tuning table (0: the resident grid).
+static int tuned_grid(Dev *c, int ring, int bucket, int variant) {
+    if (!c->tune) return 0;
+    std::lock_guard<std::mutex> lk(c->tune->mu);
+    const auto it = c->tune->e.find(tune_key(ring, bucket, variant));
+    if (it == c->tune->e.end() || it->second.grid_pct == 100) return 0;
+    int full = 0;
+    if (persistent_grid(ring, bucket, variant, &full) != hipSuccess) return 0;
+    return std::max(1, full * it->second.grid_pct / 100);
+}
+
 hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool want_per_job) {
     const size_t nd = j->tab.desc.size();
     const int np = j->tab.n_problems;
@@ -544,6 +604,7 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
     std::vector<size_t> goff;
     if (persistent) {
         const int split = split_in_effect(c->opts);
+        apply_tuning(c, j);
         if (j->qgroup.size() != nd || j->qsplit != split) build_queue_groups(j, split);
         const std::vector<uint32_t> ord = job_order(j, order, c->opts.seed);
         const size_t ng = j->qgroups.size();
@@ -663,8 +724,8 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
                 s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,
                                                        (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi],
                                                        (const uint64_t *)c->buf[B_ITEMS].ptr + goff[gi],
-                                                       (uint32_t)g.n, g.items, head + gi, accs, cyc, 0,
-                                                       c->stream),
+                                                       (uint32_t)g.n, g.items, head + gi, accs, cyc,
+                                                       tuned_grid(c, g.ring, g.bucket, g.variant), c->stream),
                               "rnw_persistent launch");
             if (s) return s;
             s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi + 1], c->stream), "event");
@@ -931,6 +992,7 @@ hperm_status hperm_ctx_create(const hperm_opts *opts, void *stream, hperm_ctx **
     c->dev.stream = c->stream;
     c->dev.opts = c->opts;
     c->dev.last_error.reserve(256);   // short error messages then need no allocation
+    c->dev.tune = std::make_shared<TuneTable>();
     (void)noalloc_scratch(c->device);  // the no-allocation entry point's array, once per device
     *out = c;
     return HPERM_OK;

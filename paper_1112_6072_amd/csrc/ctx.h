@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -22,9 +23,25 @@ struct DevBuf {
 };
 
 enum BufId { B_DESC, B_DESC_PLAIN, B_DATA, B_BOUND, B_KEYS, B_LIST, B_QUEUE, B_ITEMS, B_ACCS, B_HEAD, B_PROB, B_CYCLES,
-             B_SPLIT, B_SPLIT_WIDE, B_DX_LEVELS, B_DX_OFFS, B_DX_AUX, B_COUNT };
+             B_SPLIT, B_SPLIT_WIDE, B_DX_LEVELS, B_DX_OFFS, B_DX_AUX, B_TUNE_DESC, B_TUNE_QUEUE, B_COUNT };
 
 struct Serving;   // serve.cpp
+
+// Tuned launch settings of the persistent R-NW kernels, per launch group (ring, order bucket,
+// walk variant): the lane chunk as an offset from each job's default chunk (which sets the
+// Gray indices per lane and so the work items, i.e. the waves, of a job) and the persistent
+// grid as a percentage of the resident one.
+struct TuneEntry {
+    int chunk_delta = 0;
+    int grid_pct = 100;
+    double ms_default = 0.0, ms_tuned = 0.0;   // the timed trials that chose it (0: from a cache)
+};
+struct TuneTable {
+    std::mutex mu;
+    std::map<int, TuneEntry> e;   // key: tune_key(ring, bucket, variant)
+    uint64_t version = 0;         // bumped on every change
+};
+inline int tune_key(int ring, int bucket, int variant) { return (ring * 8 + bucket) * 4 + variant; }
 
 }  // namespace hp
 
@@ -56,6 +73,11 @@ struct hperm_jobs {
     // per-job work cycles of the last timed persistent run (natural index)
     std::vector<uint64_t> cycles;
     bool has_cycles = false;
+    // the lane chunks the expansion chose (restored when the tuning changes) and the tuning
+    // version the table's chunks follow
+    std::vector<uint8_t> chunk0;
+    uint64_t tune_version = 0;
+    const void *tune_table = nullptr;
 };
 
 namespace hp {
@@ -88,6 +110,7 @@ struct Dev {
     std::vector<uint32_t> h_queue;             // host sources of the run's uploads
     std::vector<uint64_t> h_items;
     std::vector<JobDesc> h_desc_plain;
+    std::shared_ptr<TuneTable> tune;           // tuned launch settings (shared by the context's pipelines)
 };
 
 // Release the buffers (owned ones freed), the events and the pinned staging memory.

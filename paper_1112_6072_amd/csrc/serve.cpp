@@ -237,6 +237,7 @@ struct Serving {
             d.arena_bytes = b->bytes;
             d.resident_jobs = 0;
             d.opts = ctx->opts;
+            d.tune = ctx->dev.tune;
             d.opts.time_jobs = 0;   // job timing is for the blocking stage calls only
             hperm_status s = HPERM_OK;
             if (d.opts.order == HPERM_ORDER_ESTIMATE || d.opts.order == HPERM_ORDER_EXACT_COST)
