@@ -211,6 +211,40 @@ def autotune_leg(hp, W, ctx, jobs, trials, want):
     return out
 
 
+def graph_leg(hp, W):
+    """HIP graph replay against eager launches: wall time of one persistent run call on a
+    resident job table (median of 9 after a warm-up; the first graph run captures), on the
+    benchmark's jobs and on a small table of 64 jobs of order 16 (where launch and host
+    overhead dominate); the values are checked equal."""
+    import numpy as np
+    import torch
+    out = {}
+    items = W.config_n60(16)
+    small = [W.permutation_union_matrix(16, 3, 900 + i, 1, 3) for i in range(64)]
+    for name, build in (("n60_jobs", lambda c: c.expand([A for _, A in items])),
+                        ("small64_order16", lambda c: c.jobs_from_dense(small))):
+        rec = {}
+        ref = None
+        for mode in ("eager", "graph"):
+            c = hp.Context({"split_order": 0, "device_expand": 0, "use_graphs": int(mode == "graph")})
+            try:
+                J = build(c)
+                c.run(J, "natural", True)
+                walls = []
+                for _ in range(9):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    tot, _, _ = c.run(J, "natural", True)
+                    walls.append(time.perf_counter() - t0)
+                ref = tot if ref is None else ref
+                rec[f"{mode}_run_call_ms"] = sorted(walls)[4] * 1e3
+                rec[f"{mode}_equal"] = tot == ref
+            finally:
+                c.close()
+        out[name] = rec
+    return out
+
+
 def schedule_study(hp, ctx, jobs, keys, machines=(1, 2, 4, 8, 16, 32)):
     """The paper's load-balancing study on our jobs. One persistent run in natural order with
     per-job work timing gives T (work cycles), P (the exact job permanents) and, from the
@@ -481,6 +515,7 @@ def main():
         extra[f"persistent_{order}_rnw_ms"] = sum(L["ms"] for L in ctx.last_launches())
     extra["uneven_jobs"] = uneven_orders(hp, W, ctx)
     extra["autotune"] = autotune_leg(hp, W, ctx, jobs, args.trials, tot)
+    extra["hip_graphs"] = graph_leg(hp, W)
     # one problem alone: the truncated icosahedron (C60), median of 5 after a warm-up, on the
     # default path and on the R-NW-only one
     def c60_alone(split, dexp=0):

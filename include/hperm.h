@@ -104,6 +104,14 @@ typedef struct hperm_opts {
                              0 (or T <= split order): off. */
     int32_t device_expand_mib; /* device memory for the expansion's level buffers in MiB
                              (0 = 8192); more memory means fewer, larger launches */
+    int32_t use_graphs;   /* 1: the device part of a persistent run on a job table (clears,
+                             every launch group, the recombination and the result download) is
+                             captured once as a HIP graph and replayed by later runs with the
+                             same table, buffers, launch groups and tuning (the queue upload stays
+                             outside, so the job order may change between replays); per-launch
+                             times are then not available (the run's whole span is reported in
+                             its first launch record). Not for runs with per-job results or job
+                             timing. 0: every launch issued (default). */
 } hperm_opts;
 
 /* Result of one permanent. The value is non-negative: magnitude limbs, little-endian. */

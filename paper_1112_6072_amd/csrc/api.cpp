@@ -574,6 +574,142 @@ static int tuned_grid(Dev *c, int ring, int bucket, int variant) {
     return std::max(1, full * it->second.grid_pct / 100);
 }
 
+static hperm_status ensure_host_prob(Dev *c, size_t np) {
+    if (c->host_prob_cap >= np && c->host_split) return HPERM_OK;
+    if (c->host_prob_cap < np) {
+        if (c->host_prob) (void)hipHostFree(c->host_prob);
+        c->host_prob = nullptr;
+        c->host_prob_cap = 0;
+        hperm_status s = hip_check(c, hipHostMalloc((void **)&c->host_prob, std::max<size_t>(np, 1) * sizeof(ProbAcc),
+                                                    hipHostMallocDefault), "hipHostMalloc");
+        if (s) return s;
+        c->host_prob_cap = std::max<size_t>(np, 1);
+    }
+    if (!c->host_split)
+        return hip_check(c, hipHostMalloc((void **)&c->host_split, HP_SPLIT_STATS * sizeof(unsigned long long),
+                                          hipHostMallocDefault), "hipHostMalloc");
+    return HPERM_OK;
+}
+
+// Step 4 and the downloads after the launches: per-job accumulators, or the per-problem sums
+// of the recombination (into pinned host memory).
+static hperm_status enqueue_results(Dev *c, hperm_jobs *j, JobAcc *accs, bool want_per_job) {
+    const size_t nd = j->tab.desc.size();
+    const int np = j->tab.n_problems;
+    hperm_status s;
+    if (c->split_launch >= 0) {
+        s = hip_check(c, hipMemcpyAsync(c->host_split, c->buf[B_SPLIT].ptr, HP_SPLIT_STATS * sizeof(unsigned long long),
+                                        hipMemcpyDeviceToHost, c->stream), "download split counters");
+        if (s) return s;
+    }
+    if (want_per_job) {
+        c->host_acc.resize(nd);
+        return hip_check(c, hipMemcpyAsync(c->host_acc.data(), accs, nd * sizeof(JobAcc),
+                                           hipMemcpyDeviceToHost, c->stream), "download job values");
+    }
+    ProbAcc *pd = (ProbAcc *)c->buf[B_PROB].ptr;
+    s = hip_check(c, launch_fill_u64((unsigned long long *)pd, (uint64_t)np * (sizeof(ProbAcc) / 8), 0ull,
+                                     c->stream), "clear problem accumulators");
+    if (s) return s;
+    s = hip_check(c, launch_recombine((const JobDesc *)c->buf[B_DESC].ptr, accs, (uint32_t)nd, pd, c->stream),
+                  "recombine launch");
+    if (s) return s;
+    return hip_check(c, hipMemcpyAsync(c->host_prob, pd, np * sizeof(ProbAcc), hipMemcpyDeviceToHost,
+                                       c->stream), "download problem values");
+}
+
+// The device operations of a persistent run after the queue upload: clears, the launches of
+// the groups (with an event pair around each when `events`), Step 4 and the downloads. Only
+// stream work (kernels and copies between device and pinned memory): capturable in a graph.
+static hperm_status enqueue_persistent_ops(Dev *c, hperm_jobs *j, const JobDesc *d_desc, const uint32_t *d_data,
+                                           const std::vector<size_t> &goff, bool events, bool want_per_job) {
+    const size_t nd = j->tab.desc.size();
+    JobAcc *accs = (JobAcc *)c->buf[B_ACCS].ptr;
+    unsigned long long *head = (unsigned long long *)c->buf[B_HEAD].ptr;
+    hperm_status s = hip_check(c, launch_fill_u64((unsigned long long *)accs, nd * (sizeof(JobAcc) / 8), 0ull,
+                                                  c->stream), "clear accumulators");
+    if (s) return s;
+    s = hip_check(c, launch_fill_u64(head, 64, 0ull, c->stream), "clear queue heads");
+    if (s) return s;
+    // per-job work cycles (opt-in): cleared here, downloaded by run_finish
+    unsigned long long *cyc = nullptr;
+    if (c->timed) {
+        cyc = (unsigned long long *)c->buf[B_CYCLES].ptr;
+        s = hip_check(c, launch_fill_u64(cyc, nd, 0ull, c->stream), "clear job cycles");
+        if (s) return s;
+    }
+    if (events) {
+        s = hip_check(c, hipEventRecord(c->ev0, c->stream), "event");
+        if (s) return s;
+    }
+    for (size_t gi = 0; gi < j->qgroups.size(); ++gi) {
+        const hperm_jobs::QueueGroup &g = j->qgroups[gi];
+        if (g.variant == kSplitVariant) {
+            s = hip_check(c, launch_fill_u64((unsigned long long *)c->buf[B_SPLIT].ptr, HP_SPLIT_STATS, 0ull, c->stream),
+                          "clear split counters");
+            if (s) return s;
+        }
+        if (events) {
+            s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
+            if (s) return s;
+        }
+        if (g.variant == kSplitVariant)
+            s = hip_check(c, launch_split_jobs(d_desc, d_data, (const float *)c->buf[B_BOUND].ptr,
+                                               (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi], (uint32_t)g.n,
+                                               (uint32_t)nd, split_in_effect(c->opts), g.mmax, c->opts.s_leaf,
+                                               head + gi, accs, (unsigned long long *)c->buf[B_SPLIT].ptr,
+                                               c->buf[B_SPLIT_WIDE].ptr, split_wide_capacity(g.wide, g.n), cyc,
+                                               c->stream),
+                          "device H_per launch");
+        else
+            s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,
+                                                   (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi],
+                                                   (const uint64_t *)c->buf[B_ITEMS].ptr + goff[gi],
+                                                   (uint32_t)g.n, g.items, head + gi, accs, cyc,
+                                                   tuned_grid(c, g.ring, g.bucket, g.variant), c->stream),
+                          "rnw_persistent launch");
+        if (s) return s;
+        if (events) {
+            s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi + 1], c->stream), "event");
+            if (s) return s;
+        }
+    }
+    if (events) {
+        s = hip_check(c, hipEventRecord(c->ev1, c->stream), "event");
+        if (s) return s;
+    }
+    return enqueue_results(c, j, accs, want_per_job);
+}
+
+// What a captured graph depends on: the job table, the device buffers, the launch groups and the
+// options the launches take.
+static GraphKey graph_key(Dev *c, hperm_jobs *j) {
+    GraphKey k;
+    k.jobs_id = j->id;
+    k.nd = j->tab.desc.size();
+    k.np = j->tab.n_problems;
+    for (int b = 0; b < B_COUNT; ++b) k.bufs[b] = c->buf[b].ptr;
+    k.split = split_in_effect(c->opts);
+    k.s_leaf = c->opts.s_leaf;
+    k.host_prob = c->host_prob;
+    k.host_split = c->host_split;
+    k.tune_table = c->tune.get();
+    k.tune_version = c->tune ? c->tune->version : 0;
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](uint64_t x) { h = (h ^ x) * 1099511628211ull; };
+    for (const auto &g : j->qgroups) {
+        mix((uint64_t)g.ring);
+        mix((uint64_t)g.bucket);
+        mix((uint64_t)g.variant);
+        mix(g.n);
+        mix(g.items);
+        mix((uint64_t)g.mmax);
+        mix(g.wide);
+    }
+    k.groups = h;
+    return k;
+}
+
 hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool want_per_job) {
     const size_t nd = j->tab.desc.size();
     const int np = j->tab.n_problems;
@@ -582,6 +718,7 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         return set_error(c, HPERM_E_INVALID, "ORDER_ESTIMATE needs hperm_estimate first");
     c->want_per_job = want_per_job;
     c->persistent = persistent != 0;
+    c->graphed = false;
     c->launches.clear();
     if (!nd) return HPERM_OK;
     hperm_status s;
@@ -672,25 +809,11 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         if (s) return s;
     }
     JobAcc *accs = (JobAcc *)c->buf[B_ACCS].ptr;
-    unsigned long long *head = (unsigned long long *)c->buf[B_HEAD].ptr;
-    s = hip_check(c, launch_fill_u64((unsigned long long *)accs, nd * (sizeof(JobAcc) / 8), 0ull,
-                                     c->stream), "clear accumulators");
-    if (s) return s;
-    s = hip_check(c, launch_fill_u64(head, 64, 0ull, c->stream), "clear queue heads");
-    if (s) return s;
-    // per-job work cycles (opt-in, persistent runs): cleared here, downloaded by run_finish
-    unsigned long long *cyc = nullptr;
-    if (c->timed) {
-        cyc = (unsigned long long *)c->buf[B_CYCLES].ptr;
-        s = hip_check(c, launch_fill_u64(cyc, nd, 0ull, c->stream), "clear job cycles");
-        if (s) return s;
-    }
     const uint32_t *d_data = (const uint32_t *)c->buf[B_DATA].ptr;
-    s = hip_check(c, hipEventRecord(c->ev0, c->stream), "event");
+    s = ensure_host_prob(c, (size_t)np);   // Step 4's staging and the split counters, pinned
     if (s) return s;
     if (persistent) {
-        s = ensure_launch_events(c, j->qgroups.size());
-        if (s) return s;
+        c->launches.clear();
         for (size_t gi = 0; gi < j->qgroups.size(); ++gi) {
             const hperm_jobs::QueueGroup &g = j->qgroups[gi];
             hperm_launch_stat st{};
@@ -704,89 +827,78 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             st.row_updates = (uint64_t)g.updates;
             st.alg_slots = g.mults * ring_mul_slots(g.ring) + g.adds * ring_add_slots(g.ring) + g.updates;
             c->launches.push_back(st);
-            if (g.variant == kSplitVariant) {
-                c->split_launch = (int)gi;
-                s = hip_check(c, launch_fill_u64((unsigned long long *)c->buf[B_SPLIT].ptr, HP_SPLIT_STATS, 0ull, c->stream),
-                              "clear split counters");
-                if (s) return s;
+            if (g.variant == kSplitVariant) c->split_launch = (int)gi;
+        }
+        const bool graph = c->opts.use_graphs != 0 && !want_per_job && !c->timed;
+        c->graphed = graph;
+        if (!graph) {
+            s = ensure_launch_events(c, j->qgroups.size());
+            if (s) return s;
+            return enqueue_persistent_ops(c, j, d_desc, d_data, goff, true, want_per_job);
+        }
+        // the device part as a HIP graph: captured once per job table, buffers, launch groups
+        // and tuning, replayed afterwards (the queue upload above stays outside the graph)
+        GraphKey key = graph_key(c, j);
+        if (!c->graph_exec || !(c->graph_key == key)) {
+            if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+            c->graph_exec = nullptr;
+            s = hip_check(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+            if (s) return s;
+            const hperm_status s_ops = enqueue_persistent_ops(c, j, d_desc, d_data, goff, false, false);
+            hipGraph_t gr = nullptr;
+            const hipError_t e_end = hipStreamEndCapture(c->stream, &gr);
+            if (s_ops) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return s_ops;
             }
-            s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi], c->stream), "event");
+            s = hip_check(c, e_end, "hipStreamEndCapture");
             if (s) return s;
-            if (g.variant == kSplitVariant)
-                s = hip_check(c, launch_split_jobs(d_desc, d_data, (const float *)c->buf[B_BOUND].ptr,
-                                                   (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi], (uint32_t)g.n,
-                                                   (uint32_t)nd, split_in_effect(c->opts), g.mmax, c->opts.s_leaf,
-                                                   head + gi, accs, (unsigned long long *)c->buf[B_SPLIT].ptr,
-                                                   c->buf[B_SPLIT_WIDE].ptr, split_wide_capacity(g.wide, g.n), cyc,
-                                                   c->stream),
-                              "device H_per launch");
-            else
-                s = hip_check(c, launch_rnw_persistent(g.ring, g.bucket, g.variant, d_desc, d_data,
-                                                       (const uint32_t *)c->buf[B_QUEUE].ptr + goff[gi],
-                                                       (const uint64_t *)c->buf[B_ITEMS].ptr + goff[gi],
-                                                       (uint32_t)g.n, g.items, head + gi, accs, cyc,
-                                                       tuned_grid(c, g.ring, g.bucket, g.variant), c->stream),
-                              "rnw_persistent launch");
+            s = hip_check(c, hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0), "hipGraphInstantiate");
+            (void)hipGraphDestroy(gr);
             if (s) return s;
-            s = hip_check(c, hipEventRecord(c->launch_ev[2 * gi + 1], c->stream), "event");
-            if (s) return s;
+            c->graph_key = key;
+            c->graph_captures++;
         }
-    } else {
-        // one launch per job, natural order
-        for (size_t k = 0; k < nd; ++k) {
-            const JobDesc &d = desc_plain[k];
-            const int v = walk_variant(d, d.chunk_log2);
-            s = hip_check(c, launch_rnw_single(d.arith, bucket_of(d.m), v, d_desc, d_data, (uint32_t)k,
-                                               items_of(d.m, d.chunk_log2), accs, c->stream),
-                          "rnw_single launch");
-            if (s) return s;
-        }
-        hperm_launch_stat st{};
-        st.ring = -1;
-        st.bucket = -1;
-        st.n_jobs = (int32_t)nd;
-        for (size_t k = 0; k < nd; ++k) {
-            const JobDesc &d = desc_plain[k];
-            const uint64_t t = 1ull << (d.m - 1);
-            const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2, walk_variant(d, d.chunk_log2));
-            st.items += items_of(d.m, d.chunk_log2);
-            st.terms += t;
-            st.row_updates += (uint64_t)wk.updates;
-            st.alg_slots += wk.mults * ring_mul_slots(d.arith) + wk.adds * ring_add_slots(d.arith) + wk.updates;
-        }
-        c->launches.push_back(st);   // all single launches as one record (ms = whole span)
+        s = hip_check(c, hipEventRecord(c->ev0, c->stream), "event");
+        if (s) return s;
+        s = hip_check(c, hipGraphLaunch(c->graph_exec, c->stream), "hipGraphLaunch");
+        if (s) return s;
+        return hip_check(c, hipEventRecord(c->ev1, c->stream), "event");
     }
+    unsigned long long *head = (unsigned long long *)c->buf[B_HEAD].ptr;
+    s = hip_check(c, launch_fill_u64((unsigned long long *)accs, nd * (sizeof(JobAcc) / 8), 0ull,
+                                     c->stream), "clear accumulators");
+    if (s) return s;
+    s = hip_check(c, launch_fill_u64(head, 64, 0ull, c->stream), "clear queue heads");
+    if (s) return s;
+    s = hip_check(c, hipEventRecord(c->ev0, c->stream), "event");
+    if (s) return s;
+    // one launch per job, natural order
+    for (size_t k = 0; k < nd; ++k) {
+        const JobDesc &d = desc_plain[k];
+        const int v = walk_variant(d, d.chunk_log2);
+        s = hip_check(c, launch_rnw_single(d.arith, bucket_of(d.m), v, d_desc, d_data, (uint32_t)k,
+                                           items_of(d.m, d.chunk_log2), accs, c->stream),
+                      "rnw_single launch");
+        if (s) return s;
+    }
+    hperm_launch_stat st{};
+    st.ring = -1;
+    st.bucket = -1;
+    st.n_jobs = (int32_t)nd;
+    for (size_t k = 0; k < nd; ++k) {
+        const JobDesc &d = desc_plain[k];
+        const uint64_t t = 1ull << (d.m - 1);
+        const JobWork wk = job_work(d, j->tab.data.data(), d.chunk_log2, walk_variant(d, d.chunk_log2));
+        st.items += items_of(d.m, d.chunk_log2);
+        st.terms += t;
+        st.row_updates += (uint64_t)wk.updates;
+        st.alg_slots += wk.mults * ring_mul_slots(d.arith) + wk.adds * ring_add_slots(d.arith) + wk.updates;
+    }
+    c->launches.push_back(st);   // all single launches as one record (ms = whole span)
     s = hip_check(c, hipEventRecord(c->ev1, c->stream), "event");
     if (s) return s;
-    if (c->split_launch >= 0) {
-        s = hip_check(c, hipMemcpyAsync(c->split_stats, c->buf[B_SPLIT].ptr, sizeof(c->split_stats),
-                                        hipMemcpyDeviceToHost, c->stream), "download split counters");
-        if (s) return s;
-    }
-    if (want_per_job) {
-        c->host_acc.resize(nd);
-        return hip_check(c, hipMemcpyAsync(c->host_acc.data(), accs, nd * sizeof(JobAcc),
-                                           hipMemcpyDeviceToHost, c->stream), "download job values");
-    }
-    // Step 4 on the device: one accumulator per problem, staged in pinned host memory
-    ProbAcc *pd = (ProbAcc *)c->buf[B_PROB].ptr;
-    s = hip_check(c, launch_fill_u64((unsigned long long *)pd, (uint64_t)np * (sizeof(ProbAcc) / 8), 0ull,
-                                     c->stream), "clear problem accumulators");
-    if (s) return s;
-    s = hip_check(c, launch_recombine((const JobDesc *)c->buf[B_DESC].ptr, accs, (uint32_t)nd, pd, c->stream),
-                  "recombine launch");
-    if (s) return s;
-    if (c->host_prob_cap < (size_t)np) {
-        if (c->host_prob) (void)hipHostFree(c->host_prob);
-        c->host_prob = nullptr;
-        c->host_prob_cap = 0;
-        s = hip_check(c, hipHostMalloc((void **)&c->host_prob, (size_t)np * sizeof(ProbAcc), hipHostMallocDefault),
-                      "hipHostMalloc");
-        if (s) return s;
-        c->host_prob_cap = (size_t)np;
-    }
-    return hip_check(c, hipMemcpyAsync(c->host_prob, pd, np * sizeof(ProbAcc), hipMemcpyDeviceToHost,
-                                       c->stream), "download problem values");
+    return enqueue_results(c, j, accs, want_per_job);
 }
 
 hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_result *totals,
@@ -805,21 +917,22 @@ hperm_status run_finish(Dev *c, hperm_jobs *j, hperm_result *per_job, hperm_resu
         *t_rnw = ms * 1e-3;
         if (c->persistent) {
             for (size_t gi = 0; gi < c->launches.size(); ++gi) {
-                float lm = 0.0f;
-                (void)hipEventElapsedTime(&lm, c->launch_ev[2 * gi], c->launch_ev[2 * gi + 1]);
+                float lm = 0.0f;   // a replayed graph has no per-launch events: the whole span
+                if (c->graphed) lm = gi == 0 ? ms : 0.0f;
+                else (void)hipEventElapsedTime(&lm, c->launch_ev[2 * gi], c->launch_ev[2 * gi + 1]);
                 c->launches[gi].ms = lm;
             }
             if (c->split_launch >= 0) {
+                const unsigned long long *ss = c->host_split;
                 hperm_launch_stat &st = c->launches[(size_t)c->split_launch];
-                st.leaves = c->split_stats[0];
-                st.leaf_terms = c->split_stats[1];
-                st.splits = c->split_stats[2];
-                st.split_stops = c->split_stats[3];
-                st.deferred = c->split_stats[4];
-                st.deferred_bound = c->split_stats[7];
-                if (c->split_stats[5]) return set_error(c, HPERM_E_INTERNAL, "device H_per: leaf records lost");
-                if (c->split_stats[6])
-                    return set_error(c, HPERM_E_INTERNAL, "device H_per: a leaf value failed its integrity check");
+                st.leaves = ss[0];
+                st.leaf_terms = ss[1];
+                st.splits = ss[2];
+                st.split_stops = ss[3];
+                st.deferred = ss[4];
+                st.deferred_bound = ss[7];
+                if (ss[5]) return set_error(c, HPERM_E_INTERNAL, "device H_per: leaf records lost");
+                if (ss[6]) return set_error(c, HPERM_E_INTERNAL, "device H_per: a leaf value failed its integrity check");
             }
         } else if (!c->launches.empty()) {
             c->launches[0].ms = ms;
@@ -909,6 +1022,10 @@ void dev_release(Dev *d) {
     if (d->host_prob) (void)hipHostFree(d->host_prob);
     d->host_prob = nullptr;
     d->host_prob_cap = 0;
+    if (d->host_split) (void)hipHostFree(d->host_split);
+    d->host_split = nullptr;
+    if (d->graph_exec) (void)hipGraphExecDestroy(d->graph_exec);
+    d->graph_exec = nullptr;
     d->resident_jobs = 0;
     d->resident_list = 0;
 }
@@ -955,6 +1072,7 @@ static const char *check_opts(const hperm_opts *o) {
     if (o->host_threads < 0 || o->host_threads > 64) return "host_threads must be in [0, 64]";
     if (o->max_table_mib < 0) return "max_table_mib must be >= 0";
     if (o->time_jobs != 0 && o->time_jobs != 1) return "time_jobs must be 0 or 1";
+    if (o->use_graphs != 0 && o->use_graphs != 1) return "use_graphs must be 0 or 1";
     if (o->split_order != 0 && (o->split_order < HP_SPLIT_MIN_T || o->split_order >= HP_SPLIT_MAX_M))
         return "split_order must be 0 or in [7, 23]";
     if (o->device_expand < 0 || o->device_expand > HP_SPLIT_MAX_M) return "device_expand must be in [0, 24]";

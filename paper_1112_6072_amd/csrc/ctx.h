@@ -82,6 +82,28 @@ struct hperm_jobs {
 
 namespace hp {
 
+// What a captured run graph depends on (api.cpp, graph_key).
+struct GraphKey {
+    uint64_t jobs_id = 0;
+    size_t nd = 0;
+    int np = 0;
+    void *bufs[B_COUNT] = {};
+    int split = 0, s_leaf = 0;
+    void *host_prob = nullptr, *host_split = nullptr;
+    const void *tune_table = nullptr;
+    uint64_t tune_version = 0;
+    uint64_t groups = 0;
+    bool operator==(const GraphKey &o) const {
+        if (jobs_id != o.jobs_id || nd != o.nd || np != o.np || split != o.split || s_leaf != o.s_leaf ||
+            host_prob != o.host_prob || host_split != o.host_split || tune_table != o.tune_table ||
+            tune_version != o.tune_version || groups != o.groups)
+            return false;
+        for (int b = 0; b < B_COUNT; ++b)
+            if (bufs[b] != o.bufs[b]) return false;
+        return true;
+    }
+};
+
 // One independent set of device buffers, stream and events on which the GPU pipeline runs.
 // A context owns one; the serving loop gives every batch in flight its own.
 struct Dev {
@@ -103,7 +125,11 @@ struct Dev {
     bool persistent = true;
     bool timed = false;                        // per-job work cycles recorded (B_CYCLES)
     int split_launch = -1;                     // index of the device H_per launch, or -1
-    unsigned long long split_stats[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // its counters (B_SPLIT)
+    unsigned long long *host_split = nullptr;  // pinned: its counters (B_SPLIT)
+    bool graphed = false;                      // the last run replayed a graph
+    hipGraphExec_t graph_exec = nullptr;       // the captured device part of a persistent run
+    GraphKey graph_key;
+    uint64_t graph_captures = 0;
     std::vector<JobAcc> host_acc;              // per-job accumulators (per-job results only)
     ProbAcc *host_prob = nullptr;              // pinned, per-problem accumulators
     size_t host_prob_cap = 0;

@@ -239,6 +239,7 @@ struct Serving {
             d.opts = ctx->opts;
             d.tune = ctx->dev.tune;
             d.opts.time_jobs = 0;   // job timing is for the blocking stage calls only
+            d.opts.use_graphs = 0;  // every batch is a new job table: nothing to replay
             hperm_status s = HPERM_OK;
             if (d.opts.order == HPERM_ORDER_ESTIMATE || d.opts.order == HPERM_ORDER_EXACT_COST)
                 s = estimate_jobs(&d, &b->merged, d.opts.trials, d.opts.seed);
