@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import expand_leaves, kkl_key, native, per_brute, per_ryser
+from oracle import expand_leaves, kkl_key, native, per_brute, per_dp, per_ryser
 
 pytestmark = pytest.mark.gpu
 
@@ -248,6 +248,55 @@ def test_estimate_matches_oracle_larger_orders(hperm, ctx):
     for job, (A, key) in enumerate(zip(mats, keys)):
         want = kkl_key(A, 16, 777, job)
         assert abs(float(key) - want) < 2e-3, (job, key, want)
+
+
+def test_estimate_matches_oracle_buckets_32_40(hperm, ctx):
+    """The estimator's order buckets 25..32 (32 lanes per trial) and 33..40 (64 lanes per
+    trial, the pivot search crossing 32-lane halves): orders 25, 28, 32, 33, 36 and 40.
+
+    FP32 rounding grows like m^2 * 2^-24 (about 1e-4 at m = 40), inside 2e-3."""
+    mats = [leaf_like(m, 370 + m, k=3) for m in (25, 28, 32, 33, 36, 40)]
+    say("estimate parity, orders 25..40")
+    J = ctx.jobs_from_dense(mats)
+    keys = ctx.estimate(J, 8, 4242)
+    for job, (A, key) in enumerate(zip(mats, keys)):
+        want = kkl_key(A, 8, 4242, job)
+        assert abs(float(key) - want) < 2e-3, (job, A.shape[0], key, want)
+
+
+def test_wide_rings_on_expanded_problems(hperm):
+    """Problems whose expansion yields mod-2^128 and residue-ring jobs (a random 4-regular graph
+    on 40 vertices; a 3-permutation union on 38 vertices with values 1..6): every residue-ring
+    and mod-2^128 job of the union and a sample of the graph's jobs equal the oracle's
+    permanent of the job's sub-matrix, and the totals equal the oracle, on the R-NW path, with
+    the device continuation of H_per and on the device-expansion path."""
+    Q = W.random_quartic_matrix(40, 3)
+    U = W.permutation_union_matrix(38, 3, 6, 1, 6)
+    want = [native.hper_batch([Q], threads=8)[0], per_dp(U)]
+    for split in (0, 12):
+        c = hperm.Context({"split_order": split, "device_expand": 0})
+        try:
+            J = c.expand([Q, U])
+            d = J.describe()
+            say("wide rings, split", split, "jobs", len(d["m"]), np.unique(d["arith"], return_counts=True))
+            assert {2, 3} <= set(d["arith"].tolist())
+            tot, pj, _ = c.run(J, "natural", True, per_job=True)
+            assert tot == want
+            idx_u = [k for k in range(len(pj)) if d["problem"][k] == 1]
+            rng = np.random.default_rng(split)
+            idx_q = [k for k in range(len(pj)) if d["problem"][k] == 0]
+            wide_q = [k for k in idx_q if d["arith"][k] == 2]
+            pick = idx_u + sorted(rng.choice(wide_q, 24, replace=False).tolist()) + sorted(rng.choice(idx_q, 8, replace=False).tolist())
+            mats = [J.matrix(k).astype(np.int64).tolist() for k in pick]
+            assert [pj[k] for k in pick] == native.ryser_batch(mats, threads=8)
+        finally:
+            c.close()
+    c = hperm.Context()   # the default path: the graph on the device (the union's bound, above 2^102, keeps it on the host)
+    try:
+        assert c.permanent_batch([Q, U]) == want
+        assert [l["variant"] for l in c.last_launches()].count(4) == 1
+    finally:
+        c.close()
 
 
 def test_estimate_tracks_permanent(hperm, ctx):
