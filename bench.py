@@ -108,14 +108,17 @@ def cpu_baseline(m_cut: int, budget_s: float = 20.0):
                       f"counted as 2^(m-1) per job like the GPU path"}
 
 
-def serving_leg(hp, W, n_requests: int = 48, seed: int = 7, n_lo: int = 30, n_hi: int = 40):
+def serving_leg(hp, W, n_requests: int = 48, seed: int = 7, n_lo: int = 30, n_hi: int = 100,
+                limit_ms: int = 1000):
     """Continuous batching under a Poisson stream of mixed requests (3-regular, 4-regular and
     small-integer sparse matrices, n uniform in [n_lo, n_hi]). First the whole stream at once
-    (capacity = requests / makespan), then Poisson arrivals at half that rate; latencies are
-    the library's submit-to-completion times."""
+    (capacity = served requests / makespan), then Poisson arrivals at half that rate; latencies
+    are the library's submit-to-completion times of the served requests. Requests whose
+    estimated work exceeds limit_ms are refused (HPERM_E_TOOBIG), and integer requests whose
+    expansion leaves the supported entry range are refused (HPERM_E_RANGE); both are counted."""
     import numpy as np
     reqs = [A for _, A in W.serving_requests(n_requests, seed, n_lo, n_hi)]
-    ctx = hp.Context({"m_cut": 20, "trials": 32, "host_threads": 4})
+    ctx = hp.Context({"m_cut": 20, "trials": 32, "host_threads": 4, "serve_limit_ms": limit_ms})
     try:
         ctx.serve_start(4 * n_requests, 4 << 30)
         def collect(tickets):
@@ -123,7 +126,7 @@ def serving_leg(hp, W, n_requests: int = 48, seed: int = 7, n_lo: int = 30, n_hi
             for t in tickets:
                 try:
                     out.append(ctx.wait(t, 600.0))
-                except hp.HpermError as e:   # a request outside the supported range
+                except hp.HpermError as e:   # refused: beyond the work limit or the entry range
                     out.append((None, {"t_total_s": float("nan"), "error": e.status}))
             return out
 
@@ -131,8 +134,9 @@ def serving_leg(hp, W, n_requests: int = 48, seed: int = 7, n_lo: int = 30, n_hi
         tickets = [ctx.submit(A) for A in reqs]
         burst = collect(tickets)
         makespan = time.perf_counter() - t0
-        capacity = n_requests / makespan
-        rate = 0.5 * capacity
+        served = sum(v is not None for v, _ in burst)
+        capacity = served / makespan
+        rate = 0.5 * n_requests / makespan
         arrivals = W.poisson_arrivals(n_requests, rate, seed + 1)
         t0 = time.perf_counter()
         tickets = []
@@ -148,14 +152,20 @@ def serving_leg(hp, W, n_requests: int = 48, seed: int = 7, n_lo: int = 30, n_hi
         ctx.close()
     lat = np.array([st["t_total_s"] for v, st in paced if v is not None]) * 1e3
     lat_b = np.array([st["t_total_s"] for v, st in burst if v is not None]) * 1e3
+    errs = [st.get("error") for v, st in burst if v is None]
     same = [v for v, _ in burst] == [v for v, _ in paced]
-    return {"requests": n_requests, "n_range": [n_lo, n_hi],
-            "failed": sum(v is None for v, _ in paced),
+    served_n = [A.shape[0] for A, (v, _) in zip(reqs, burst) if v is not None]
+    return {"requests": n_requests, "n_range": [n_lo, n_hi], "work_limit_ms": limit_ms,
+            "served": served, "refused_work_limit": errs.count(-9), "refused_entry_range": errs.count(-2),
+            "failed_other": len(errs) - errs.count(-9) - errs.count(-2),
+            "served_n_max": max(served_n) if served_n else None,
             "mix": "1/3 each: 3-regular 0-1, 4-regular 0-1, 3-permutation union with values 1..4",
-            "capacity_problems_per_s": capacity,
-            "poisson_rate_per_s": rate, "problems_per_s": n_requests / wall,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "burst_p50_ms": float(np.percentile(lat_b, 50)), "burst_p99_ms": float(np.percentile(lat_b, 99)),
+            "capacity_served_per_s": capacity,
+            "poisson_rate_per_s": rate, "requests_per_s": n_requests / wall,
+            "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+            "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+            "burst_p50_ms": float(np.percentile(lat_b, 50)) if lat_b.size else None,
+            "burst_p99_ms": float(np.percentile(lat_b, 99)) if lat_b.size else None,
             "burst_and_paced_results_identical": same}
 
 
@@ -575,6 +585,8 @@ def main():
     if not args.no_serving:
         log("serving: burst, then Poisson arrivals at half the measured capacity")
         serving = serving_leg(hp, W)
+        log("serving, the narrower mix (n 30..40, no work limit)")
+        extra["serving_n30_40"] = serving_leg(hp, W, n_hi=40, limit_ms=0)
 
     large = None
     if not args.no_large:

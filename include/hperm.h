@@ -45,8 +45,10 @@ typedef enum hperm_status {
     HPERM_E_BUSY = -5,       /* serving: no free request slot */
     HPERM_E_CANCELLED = -6,  /* serving: the request was cancelled */
     HPERM_E_TIMEOUT = -7,    /* serving: wait timed out (the request keeps running) */
-    HPERM_E_INTERNAL = -8    /* an integrity check failed (a job value not divisible by
+    HPERM_E_INTERNAL = -8,   /* an integrity check failed (a job value not divisible by
                                 2^(m-1), a residue check mismatch); never returned silently */
+    HPERM_E_TOOBIG = -9      /* serving: the request's estimated work exceeds the serving
+                                limit (opts.serve_limit_ms) */
 } hperm_status;
 
 /* Job order of the device queue (Step 3 of Algorithm PH and its improved form). */
@@ -112,6 +114,11 @@ typedef struct hperm_opts {
                              times are then not available (the run's whole span is reported in
                              its first launch record). Not for runs with per-job results or job
                              timing. 0: every launch issued (default). */
+    int32_t serve_limit_ms;/* serving admission by work: a request whose estimated GPU time
+                             (hperm_tree_estimate with 64 descents, at the device path's leaf
+                             rate of about 2e8 leaves/s) exceeds this many milliseconds
+                             completes with HPERM_E_TOOBIG without device work. 0: no limit
+                             (default). */
 } hperm_opts;
 
 /* Result of one permanent. The value is non-negative: magnitude limbs, little-endian. */
@@ -381,6 +388,11 @@ hperm_status hperm_kendall_tau(int32_t n, const double *x, const double *y, doub
  * - a batch is one device queue over all of its requests' jobs (steps 3-6), run on one of
  *   two streams at the default priority, so that the next batch starts while the previous
  *   one runs; at most two batches are in flight;
+ * - a request the device expansion takes (opts.device_expand in effect, order above it, bound
+ *   below 2^102) runs instead on a third stream by the device expansion, together with the
+ *   other waiting requests of its order, overlapping the batches;
+ * - with opts.serve_limit_ms, a request whose estimated work exceeds the limit completes with
+ *   HPERM_E_TOOBIG (admission by work);
  * - a request completes when its batch does; its result is bit-identical to the blocking
  *   call's.
  * While serving, the context refuses blocking GPU calls, hperm_ctx_set_opts and

@@ -45,7 +45,8 @@ class Opts(ctypes.Structure):
                 ("persistent", ctypes.c_int32), ("host_threads", ctypes.c_int32),
                 ("max_table_mib", ctypes.c_int32), ("time_jobs", ctypes.c_int32),
                 ("split_order", ctypes.c_int32), ("device_expand", ctypes.c_int32),
-                ("device_expand_mib", ctypes.c_int32), ("use_graphs", ctypes.c_int32)]
+                ("device_expand_mib", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+                ("serve_limit_ms", ctypes.c_int32)]
 
 
 class Coeff(ctypes.Structure):

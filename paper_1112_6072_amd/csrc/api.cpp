@@ -443,7 +443,7 @@ static bool split_eligible(const JobDesc &d, int split) {
 }
 // The split order in effect: the device continuation follows H_per's rule only for s_leaf <= 5
 // (its nodes have at most two children).
-static int split_in_effect(const hperm_opts &o) { return o.s_leaf <= 5 ? o.split_order : 0; }
+int split_in_effect(const hperm_opts &o) { return o.s_leaf <= 5 ? o.split_order : 0; }
 uint64_t split_wide_total(const std::vector<JobDesc> &desc, const hperm_opts &o) {
     const int split = split_in_effect(o);
     uint64_t w = 0;
@@ -1030,6 +1030,23 @@ void dev_release(Dev *d) {
     d->resident_list = 0;
 }
 
+// The job order of the device expansion in effect: device_expand when it exceeds the split
+// order in effect, else 0 (off).
+int device_in_effect(const hperm_opts &o) {
+    const int t = split_in_effect(o);
+    return (t > 0 && o.device_expand > t) ? o.device_expand : 0;
+}
+
+// Problems the device expansion takes: order above T and a proven bound below 2^102.
+bool device_path(const hperm_opts &o, const CsrView &v) {
+    const int T = device_in_effect(o);
+    if (T <= 0 || v.n <= T) return false;
+    std::vector<uint32_t> root;
+    double lb = 0.0;
+    const int rc = pack_root_node(v, &root, &lb);
+    return rc == 0 && lb <= 102.0;
+}
+
 }  // namespace hp
 
 // ====================================================================== C ABI
@@ -1073,6 +1090,7 @@ static const char *check_opts(const hperm_opts *o) {
     if (o->max_table_mib < 0) return "max_table_mib must be >= 0";
     if (o->time_jobs != 0 && o->time_jobs != 1) return "time_jobs must be 0 or 1";
     if (o->use_graphs != 0 && o->use_graphs != 1) return "use_graphs must be 0 or 1";
+    if (o->serve_limit_ms < 0) return "serve_limit_ms must be >= 0";
     if (o->split_order != 0 && (o->split_order < HP_SPLIT_MIN_T || o->split_order >= HP_SPLIT_MAX_M))
         return "split_order must be 0 or in [7, 23]";
     if (o->device_expand < 0 || o->device_expand > HP_SPLIT_MAX_M) return "device_expand must be in [0, 24]";
@@ -1254,23 +1272,6 @@ static hperm_status batch_host_path(hperm_ctx *c, int32_t count, const int32_t *
         out[k].t_total_s = t2 - t0;
     }
     return HPERM_OK;
-}
-
-// The job order of the device expansion in effect: device_expand when it exceeds the split
-// order in effect, else 0 (off).
-static int device_in_effect(const hperm_opts &o) {
-    const int t = split_in_effect(o);
-    return (t > 0 && o.device_expand > t) ? o.device_expand : 0;
-}
-
-// Problems the device expansion takes: order above T and a proven bound below 2^102.
-static bool device_path(const hperm_opts &o, const CsrView &v) {
-    const int T = device_in_effect(o);
-    if (T <= 0 || v.n <= T) return false;
-    std::vector<uint32_t> root;
-    double lb = 0.0;
-    const int rc = pack_root_node(v, &root, &lb);
-    return rc == 0 && lb <= 102.0;
 }
 
 hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_t *n,
@@ -1577,6 +1578,7 @@ const char *hperm_status_string(hperm_status s) {
         case HPERM_E_CANCELLED: return "cancelled";
         case HPERM_E_TIMEOUT: return "timed out";
         case HPERM_E_INTERNAL: return "internal integrity check failed";
+        case HPERM_E_TOOBIG: return "estimated work beyond the serving limit";
     }
     return "unknown status";
 }

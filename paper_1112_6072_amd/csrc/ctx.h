@@ -202,6 +202,12 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int 
                                  size_t budget_bytes, std::vector<U512> *out, DexpStats *stats,
                                  DexpSample *sample = nullptr);
 
+// The split order and the device expansion's job order in effect (0: off), and whether a
+// problem takes the device expansion (api.cpp).
+int split_in_effect(const hperm_opts &o);
+int device_in_effect(const hperm_opts &o);
+bool device_path(const hperm_opts &o, const CsrView &v);
+
 // per(A) of a problem from its device accumulator (limb sums + CRT of the residue sums).
 U512 prob_value(const ProbAcc &q);
 void fill_result(const U512 &v, hperm_result *r);

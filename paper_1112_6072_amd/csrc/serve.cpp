@@ -7,6 +7,12 @@
 // jobs (estimate, one queue over all of the batch's jobs, persistent R-NW, recombination) on
 // one of two streams, so a new batch starts while the previous one still runs. A completion
 // thread finishes batches in launch order and delivers each request's exact result.
+//
+// Requests the device expansion takes (order above its job order, bound below 2^102) skip the
+// host expansion: a device lane runs them, with the other waiting requests of the same order,
+// by the device expansion on a stream of its own, so they overlap the batches. With a work
+// limit, a request whose estimated GPU time (Knuth's estimate of its expansion tree, rated at
+// the device path's measured leaf and subset-term rates) exceeds the limit is refused.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -15,7 +21,10 @@
 #include <thread>
 #include <unordered_map>
 
+#include <cmath>
+
 #include "ctx.h"
+#include "expand.h"
 #include "kernels.h"
 
 namespace hp {
@@ -32,6 +41,7 @@ struct Request {
     hperm_jobs jobs;
     size_t bytes = 0;   // device bytes of this request's share of a batch
     uint64_t wide = 0;  // bound on its deferred wide leaves (device H_per)
+    bool device = false;   // run by the device lane
     hperm_result result{};
     hperm_status status = HPERM_OK;
     std::string err;
@@ -78,7 +88,10 @@ struct Serving {
     std::mutex mu;
     std::condition_variable cv;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> reqs;
-    std::deque<Request *> pending, ready;
+    std::deque<Request *> pending, ready, dev_ready;
+    hipStream_t dev_stream = nullptr;   // the device lane's stream and buffers
+    Dev devx;
+    std::thread dev_lane;
     std::deque<std::unique_ptr<Batch>> inflight;
     uint64_t next_ticket = 1;
     bool stopping = false;
@@ -121,9 +134,45 @@ struct Serving {
                 pending.pop_front();
                 r->state = Request::EXPANDING;
             }
+            const CsrView view{r->n, r->rp.data(), r->ci.data(), r->val.data()};
+            if (ctx->opts.serve_limit_ms > 0 && r->n > 0) {
+                // admission by work: Knuth's estimate of the tree, rated at about 5 ns per leaf
+                // of the device continuation and 0.5 ns per R-NW subset-term
+                const hperm_opts &o = ctx->opts;
+                const int t = split_in_effect(o) > 0 ? split_in_effect(o) : o.m_cut;
+                const int T = device_in_effect(o) > 0 ? device_in_effect(o) : o.m_cut;
+                std::vector<double> nodes((size_t)r->n + 1), leaves((size_t)r->n + 1);
+                const int rc = estimate_tree(view, std::max(T, t), t, o.s_leaf, 64, r->ticket, nodes.data(),
+                                             leaves.data());
+                double ms = 0.0;
+                for (int p = 0; p <= r->n; ++p) ms += leaves[(size_t)p] * (5e-6 + std::ldexp(5e-10, p - 1));
+                if (rc == 0 && ms > o.serve_limit_ms) {
+                    std::lock_guard<std::mutex> lk(mu);
+                    r->status = HPERM_E_TOOBIG;
+                    r->err = "estimated work " + std::to_string((long long)ms) + " ms exceeds the serving limit of " +
+                             std::to_string(o.serve_limit_ms) + " ms";
+                    r->state = Request::DONE;
+                    r->t_done = now_s();
+                    cv.notify_all();
+                    continue;
+                }
+            }
+            if (device_path(ctx->opts, view)) {   // the device lane takes it
+                std::lock_guard<std::mutex> lk(mu);
+                if (r->cancelled) {
+                    r->state = Request::DONE;
+                    r->t_done = now_s();
+                } else {
+                    r->device = true;
+                    r->state = Request::READY;
+                    dev_ready.push_back(r);
+                }
+                cv.notify_all();
+                continue;
+            }
             ExpandParams prm = expand_params(ctx->opts);
             if (prm.threads == 0) prm.threads = 2;
-            std::vector<CsrView> probs{CsrView{r->n, r->rp.data(), r->ci.data(), r->val.data()}};
+            std::vector<CsrView> probs{view};
             std::string err;
             const int rc = expand_problems(probs, prm, &r->jobs.tab, &err);
             std::lock_guard<std::mutex> lk(mu);
@@ -255,6 +304,62 @@ struct Serving {
         cv.notify_all();
     }
 
+    // The device lane: the oldest waiting request's order and every waiting request of that
+    // order, expanded on the device together.
+    void device_loop() {
+        const size_t budget = (size_t)(ctx->opts.device_expand_mib > 0 ? ctx->opts.device_expand_mib : 8192) << 20;
+        for (;;) {
+            std::vector<Request *> grp;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv.wait(lk, [&] { return stopping || !dev_ready.empty(); });
+                if (stopping) return;
+                const int n = dev_ready.front()->n;
+                for (auto it = dev_ready.begin(); it != dev_ready.end();) {
+                    if ((*it)->n == n) {
+                        grp.push_back(*it);
+                        it = dev_ready.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
+                const double t = now_s();
+                for (Request *r : grp) {
+                    r->state = Request::RUNNING;
+                    r->t_admit = t;
+                }
+            }
+            std::vector<CsrView> views;
+            for (Request *r : grp) views.push_back(CsrView{r->n, r->rp.data(), r->ci.data(), r->val.data()});
+            devx.opts = ctx->opts;
+            devx.tune = ctx->dev.tune;
+            std::vector<U512> totals;
+            DexpStats st;
+            const hperm_status s = device_expand_group(&devx, views, device_in_effect(devx.opts),
+                                                       split_in_effect(devx.opts), devx.opts.s_leaf, budget, &totals, &st);
+            std::lock_guard<std::mutex> lk(mu);
+            const double t = now_s();
+            for (size_t k = 0; k < grp.size(); ++k) {
+                Request *r = grp[k];
+                r->status = s;
+                if (s) {
+                    r->err = devx.last_error;
+                } else {
+                    r->result = hperm_result{};
+                    fill_result(totals[k], &r->result);
+                    r->result.n_jobs = (int32_t)std::min<uint64_t>(st.jobs, 0x7fffffff);
+                    r->result.max_m = device_in_effect(devx.opts);
+                    r->result.arith_mask = 1 << HPERM_ARITH_W64;
+                    r->result.subset_terms = st.leaf_terms;
+                    r->result.t_rnw_s = st.split_s;
+                }
+                r->state = Request::DONE;
+                r->t_done = t;
+            }
+            cv.notify_all();
+        }
+    }
+
     // Whether some free slice holds `bytes` (caller holds mu).
     bool alloc_probe(size_t bytes) const {
         for (auto &f : free_list)
@@ -317,7 +422,10 @@ void serve_shutdown(hperm_ctx *c) {
     for (auto &t : sv->workers) t.join();
     sv->dispatcher.join();
     sv->completer.join();
+    if (sv->dev_lane.joinable()) sv->dev_lane.join();
     for (Dev &d : sv->devs) dev_release(&d);
+    dev_release(&sv->devx);
+    if (sv->dev_stream) (void)hipStreamDestroy(sv->dev_stream);
     for (hipStream_t s : sv->streams)
         if (s) (void)hipStreamDestroy(s);
     if (sv->arena) (void)hipFree(sv->arena);
@@ -357,8 +465,17 @@ hperm_status hperm_serve_start(hperm_ctx *c, int32_t max_requests, size_t arena_
         }
         sv->devs[k].stream = sv->streams[k];
     }
+    if (hipStreamCreateWithFlags(&sv->dev_stream, hipStreamNonBlocking) != hipSuccess) {
+        for (hipStream_t st : sv->streams) (void)hipStreamDestroy(st);
+        (void)hipFree(sv->arena);
+        delete sv;
+        return set_error(c, HPERM_E_DEVICE, "stream creation failed");
+    }
+    sv->devx.stream = sv->dev_stream;
+    sv->devx.last_error.reserve(256);
     c->serving = sv;
     for (int k = 0; k < 4; ++k) sv->workers.emplace_back([sv] { sv->expand_loop(); });
+    sv->dev_lane = std::thread([sv] { sv->device_loop(); });
     sv->dispatcher = std::thread([sv] { sv->dispatch_loop(); });
     sv->completer = std::thread([sv] { sv->complete_loop(); });
     return HPERM_OK;
@@ -462,7 +579,8 @@ hperm_status hperm_cancel(hperm_ctx *c, uint64_t ticket) {
         r->state = Request::DONE;
         r->t_done = now_s();
     } else if (r->state == Request::READY) {
-        sv->ready.erase(std::find(sv->ready.begin(), sv->ready.end(), r));
+        if (r->device) sv->dev_ready.erase(std::find(sv->dev_ready.begin(), sv->dev_ready.end(), r));
+        else sv->ready.erase(std::find(sv->ready.begin(), sv->ready.end(), r));
         r->state = Request::DONE;
         r->t_done = now_s();
     }

@@ -144,3 +144,30 @@ def test_serving_edge_cases(hperm):
         assert got == want
     finally:
         c.close()
+
+
+def test_serving_device_lane_and_work_limit(hperm):
+    """Requests above the device expansion's order run in the device lane (grouped by order,
+    overlapping the host batches) and come back equal to the oracle; with a work limit, a
+    request whose estimated work is far beyond it is refused with HPERM_E_TOOBIG while the
+    others are served."""
+    mats = [W.random_cubic_matrix(n, 40 + n) for n in (24, 30, 30, 36, 44)]
+    mats += [W.random_quartic_matrix(n, 50 + n) for n in (20, 26, 30)]
+    mats += [W.permutation_union_matrix(n, 3, 60 + n, 1, 3) for n in (18, 28, 34)]
+    want = native.hper_batch(mats, threads=8)
+    say("serving device lane", len(mats))
+    c = hperm.Context({"split_order": 12, "device_expand": 22, "serve_limit_ms": 2000})
+    try:
+        c.serve_start(64, 256 << 20)
+        tickets = [c.submit(A) for A in mats]
+        big = c.submit(W.random_cubic_matrix(100, 0))   # about 30 s of GPU time
+        got = [c.wait(t, 120.0) for t in tickets]
+        with pytest.raises(hperm.HpermError) as e:
+            c.wait(big, 60.0)
+        assert e.value.status == -9
+        c.serve_stop()
+    finally:
+        c.close()
+    assert [v for v, _ in got] == want
+    lanes = [st["max_m"] for _, st in got]
+    assert 22 in lanes and any(m != 22 for m in lanes)
