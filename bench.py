@@ -388,6 +388,54 @@ def large_single(hp, W, seeds=(0,)):
     return out
 
 
+def order_trials_study(hp, ctx, jobs, split=12, trial_set=(4, 8, 16, 32)):
+    """The estimate's budget and the queue order on the device continuation of H_per, where a
+    job is one wave's whole unit and its time follows its permanent: per trial budget the
+    estimate call's time and Kendall's tau of the jobs' measured wave times against the keys;
+    the device H_per launch time (median of 3) in estimate, natural, random and exact-cost
+    order; and list-scheduling efficiency of the measured times on k = the launch's resident
+    waves (the machines the queue actually feeds) as well as k = 32 (the paper's)."""
+    import numpy as np
+    out = {"split_order": split, "by_trials": {}, "launch_ms_by_order": {}}
+    ctx.set_opts(split_order=split, time_jobs=1)
+    try:
+        ctx.run(jobs, "natural", True)
+        T = jobs.cycles().astype(np.float64)
+    finally:
+        ctx.set_opts(time_jobs=0)
+    split_jobs = T > 0   # the jobs the device continuation took
+    for tr in trial_set:
+        t0 = time.perf_counter()
+        keys = ctx.estimate(jobs, tr, 1)
+        est_ms = (time.perf_counter() - t0) * 1e3
+        tau, z, _ = hp.kendall_tau(T[split_jobs], np.asarray(keys, np.float64)[split_jobs])
+        out["by_trials"][str(tr)] = {"estimate_call_ms": est_ms, "tau_time_key": tau, "z": z}
+    grid = 0
+    for order in ("estimate", "natural", "random", "exact_cost"):
+        ms = []
+        for _ in range(3):
+            ctx.run(jobs, order, True)
+            L = [L for L in ctx.last_launches() if L["variant"] == 3][0]
+            ms.append(L["ms"])
+            grid = int(L["reserved"])   # the launch's resident waves
+        out["launch_ms_by_order"][order] = sorted(ms)[1]
+    ctx.set_opts(split_order=0)
+    Tu = T[split_jobs].astype(np.uint64)
+    n = Tu.size
+    nat = np.arange(n)
+    keys = np.asarray(ctx.estimate(jobs, 32, 1), np.float64)[split_jobs]
+    desc = lambda v: np.lexsort((nat, -v))   # noqa: E731
+    eff = {}
+    for k in (32, grid):
+        eff[str(k)] = {}
+        for oname, order in (("natural", nat), ("estimate", desc(keys)), ("time", desc(Tu.astype(np.float64)))):
+            ms, _ = hp.list_schedule(Tu, order, k)
+            eff[str(k)][oname] = float(Tu.astype(np.float64).sum() / (k * ms)) if ms else 1.0
+    out["ls_efficiency"] = eff
+    out["machines_note"] = f"{grid} = the resident waves (one per block) of the device H_per launch"
+    return out
+
+
 def copy_probe(nbytes: int = 256 << 20, reps: int = 3):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -565,6 +613,8 @@ def main():
     log("device continuation of H_per on the n60 jobs")
     golden_vals = [int(golden[n]) for n in names] if golden else None
     extra["device_hper_n60"] = device_hper(hp, ctx, jobs, tot, mats, golden_vals, keys)
+    log("estimate budget and queue order on the device continuation of H_per")
+    extra["order_trials_study_n60"] = order_trials_study(hp, ctx, jobs)
     plain = None
     if not args.no_plain:
         log("plain: one launch per job, expansion order (best lane chunk of 3, 5, 7)")

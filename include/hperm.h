@@ -437,7 +437,8 @@ typedef struct hperm_launch_stat {
                                nodes it wrote, row_updates = its device H_per launches, ms =
                                the whole group on the device and alg_slots = the milliseconds
                                of its device H_per launches */
-    int32_t reserved;       /* variant 4: the problems of the group */
+    int32_t reserved;       /* variant 3: the launch's resident waves; variant 4: the problems
+                               of the group */
     uint64_t items;         /* work items (64 lanes x 2^chunk Gray indices each) */
     uint64_t terms;         /* subset-terms: sum of 2^(m-1) over the jobs */
     uint64_t row_updates;   /* row-value updates of the Gray steps inside lane chunks */

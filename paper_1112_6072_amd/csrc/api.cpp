@@ -826,8 +826,11 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             st.terms = g.terms;
             st.row_updates = (uint64_t)g.updates;
             st.alg_slots = g.mults * ring_mul_slots(g.ring) + g.adds * ring_add_slots(g.ring) + g.updates;
+            if (g.variant == kSplitVariant) {
+                c->split_launch = (int)gi;
+                st.reserved = split_grid(split_in_effect(c->opts), g.mmax);   // its resident waves
+            }
             c->launches.push_back(st);
-            if (g.variant == kSplitVariant) c->split_launch = (int)gi;
         }
         const bool graph = c->opts.use_graphs != 0 && !want_per_job && !c->timed;
         c->graphed = graph;

@@ -87,6 +87,8 @@ inline uint64_t split_wide_entries(int m) { return m > 16 ? (1ull << (m - 16)) -
 // at most its own root that way, when the rounding of the bound to float costs the margin).
 inline uint64_t split_wide_capacity(uint64_t wide, uint64_t njobs) { return wide + njobs + 1024; }
 size_t split_lds_bytes(int t, int mm);
+// Resident waves (one per block) of the device H_per kernel for target t and job order mm.
+int split_grid(int t, int mm);
 size_t split_wide_bytes(uint64_t entries);
 // Jobs of a host job table: queue[0..n) lists them (indices < njobs), mm is their largest order
 // (> t), job_bound[job] their proven log2 bounds (float, rounded up); per-job values into accs;

@@ -911,6 +911,12 @@ static hipError_t launch_split_pair(const SplitArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+int split_grid(int t, int mm) {
+    uint64_t grid = 0;
+    if (resident_grid((const void *)hper_split<false>, split_lds_bytes(t, mm), &grid) != hipSuccess) return 0;
+    return (int)grid;
+}
+
 hipError_t launch_split_jobs(const JobDesc *jobs, const uint32_t *data, const float *job_bound, const uint32_t *queue,
                              uint32_t n, uint32_t njobs, int t, int mm, int s_leaf, unsigned long long *head,
                              JobAcc *accs, unsigned long long *stats, void *wide, uint64_t wide_entries,
