@@ -553,8 +553,9 @@ def main():
     for ls in launches:
         for L in ls:
             key = (L["ring"], L["bucket"], L["variant"])
-            g = groups.setdefault(key, {"ms": 0.0, "alg": 0.0, "terms": 0, "jobs": 0, "n": 0})
+            g = groups.setdefault(key, {"ms": 0.0, "alg": 0.0, "terms": 0, "jobs": 0, "n": 0, "upd": 0})
             g["ms"] += L["ms"]
+            g["upd"] += L["row_updates"]
             g["jobs"] += L["n_jobs"]
             g["alg"] += L["alg_slots"]
             g["terms"] += L["terms"]
@@ -563,6 +564,16 @@ def main():
     avg_ms = dom["ms"] / dom["n"]
     alg_per_launch = dom["alg"] / dom["n"]
     achieved = alg_per_launch / (avg_ms * 1e-3)
+    # the launch's ring multiplies, recovered from its slot count (slots = mul x M + add x A + U
+    # with A = one ring addition per term, or per two terms in the paired walk, U = the row
+    # updates), and the same launch weighed with the half-rate multiplies at the issue costs a
+    # probe measured for them (v_mul_lo_u32 2.5 and v_mad_u64_u32 3.8 full-rate slots instead
+    # of 2 each; mod 2^64 only)
+    mul_slots, add_slots = {0: (5.0, 2.0), 1: (9.0, 4.0), 2: (33.0, 9.0)}[ring]
+    adds = dom["terms"] / dom["n"] / (2.0 if variant > 0 else 1.0)
+    mults = (alg_per_launch - add_slots * adds - dom["upd"] / dom["n"]) / mul_slots
+    probe_frac = ((alg_per_launch + mults * (2.5 + 3.8 - 4.0)) / (avg_ms * 1e-3) / ALU_PEAK
+                  if ring == 0 else None)
     rnw_ms = sum(g["ms"] for g in groups.values()) / args.steps
     ring_name = {0: "mod 2^64", 1: "mod 2^128", 2: "residues"}[ring]
 
@@ -693,7 +704,8 @@ def main():
                      "kernel": f"rnw_persistent ({ring_name}, orders <= {[16, 20, 24, 32, 40][bucket]}, "
                                f"{['step-pair walk', 'paired walk, two-row column 0', 'paired walk, three-row column 0'][variant]})",
                      "avg_launch_ms": avg_ms, "alg_slots_per_launch": alg_per_launch,
-                     "jobs_per_launch": dom["jobs"] // dom["n"], "terms_per_launch": dom["terms"] // dom["n"]},
+                     "jobs_per_launch": dom["jobs"] // dom["n"], "terms_per_launch": dom["terms"] // dom["n"],
+                     "ring_multiplies_per_launch": mults, "frac_with_probe_multiply_weights": probe_frac},
         "cpu_baseline": cpu,
         "cpu_baseline_ryser_sample": cpu_ryser,
         "large_single_problems": large,

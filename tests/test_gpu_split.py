@@ -257,3 +257,63 @@ def test_split_from_order_24(hperm, ctx):
     finally:
         ctx.set_opts(m_cut=20, split_order=0)
     assert got == [int(GOLDEN[name]) for name, _ in items]
+
+
+def refusing_job(hperm, m, seed):
+    """A job of order m whose first H_per split must be refused. The base pattern is a 0-1
+    cycle (row r on columns r and r+1 mod m) with row 0 cut to the single entry 2^11 at
+    column 0 and one extra 1 at (2, 1), rows and columns permuted by the seed: that row is
+    the unique sparsest line, and the odd entry's split scales the lowest zero column of
+    its row (in the job's stored order) by 2^11. One more 2^11 is placed, by a seeded
+    search, on an entry that the oracle's own first split of the stored job multiplies by
+    the first: a child entry reaches 2^22, beyond the entry limit, so the device keeps the
+    job whole (a leaf of order m); the bound keeps the job in the mod-2^64 ring."""
+    from oracle.permanent import choose_line, e2_children
+    rng = np.random.default_rng(seed)
+    base = np.zeros((m, m), np.uint32)
+    for r in range(1, m):
+        base[r, r] = base[r, (r + 1) % m] = 1
+    base[0, 0] = 1 << 11
+    base[2, 1] = 1
+    base = base[rng.permutation(m)][:, rng.permutation(m)]
+    host = hperm.Context(host_only=True)
+    try:
+        cand = [tuple(x) for x in np.argwhere(base == 1)]
+        for k in rng.permutation(len(cand)):
+            A = base.copy()
+            A[cand[k]] = 1 << 11
+            J = host.jobs_from_dense([A])
+            if J.describe()["arith"][0] != 1:
+                continue
+            B = J.matrix(0).astype(np.int64).tolist()
+            kind, idx, _ = choose_line(B)
+            if max(max(max(r) for r in C) for C in e2_children(B, kind, idx)) >= 1 << 22:
+                return A
+    finally:
+        host.close()
+    raise AssertionError(f"no refusing placement for m={m}, seed {seed}")
+
+
+@pytest.mark.parametrize("t", [7, 12])
+def test_split_refused_at_entry_limit(hperm, ctx, t):
+    """Jobs whose first split would merge two entries 2^11 into 2^22 (beyond the entry limit
+    of the device arithmetic): the device refuses the split and evaluates the job whole, at
+    order 14 and 16 by the leaf walk and at order 18 and 20 by the deferred 20-row replay;
+    every job value equals the oracle's permanent of the stored sub-matrix."""
+    mats = [refusing_job(hperm, m, 50 + m) for m in (14, 16, 18, 20)]
+    mats.append(W.permutation_union_matrix(18, 3, 61, 1, 2))    # an ordinary job beside them
+    J = ctx.jobs_from_dense(mats)
+    assert list(J.describe()["arith"]) == [1] * len(mats)
+    stored = job_mats(J)
+    say("split refused", t)
+    ctx.set_opts(split_order=t)
+    try:
+        totals, per_job, _ = ctx.run(J, "natural", True, per_job=True)
+        st = split_launch(ctx)
+    finally:
+        ctx.set_opts(split_order=0)
+    say("split refused stats", {k: st[k] for k in ("leaves", "splits", "split_stops", "deferred")})
+    assert per_job == native.ryser_batch(stored, threads=8)
+    assert totals == [sum(per_job)]
+    assert st["split_stops"] >= 4         # one refusal at each refusing job's root
+    assert st["deferred"] >= 2            # the order-18 and order-20 roots, kept whole
