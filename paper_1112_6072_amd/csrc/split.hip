@@ -113,16 +113,32 @@ __device__ __forceinline__ uint32_t argmin_lane(uint32_t count, bool valid, uint
     return w;
 }
 
-// Product of the R row values modulo 2^64: pairs exactly in 64 bits (|f| < 2^24), then a chain.
-template <int R>
-__device__ __forceinline__ uint64_t row_product(const int32_t (&f)[R]) {
-    uint64_t p = (uint64_t)((int64_t)f[0] * (int64_t)f[1]);
-#pragma unroll
-    for (int k = 1; k < R / 2; ++k) p *= (uint64_t)((int64_t)f[2 * k] * (int64_t)f[2 * k + 1]);
-    return p;
+// The product of two row values, exact in 64 bits (|x|, |y| < 2^24), kept as one value: the
+// empty asm stops the compiler from re-associating a product of such pairs into a chain of
+// 64 x 32-bit multiplies (five instructions each instead of one here).
+__device__ __forceinline__ uint64_t pmul(int32_t x, int32_t y) {
+    int64_t p = (int64_t)x * (int64_t)y;
+    asm("" : "+v"(p));
+    return (uint64_t)p;
 }
 
-// The same product modulo 2^128.
+// Product modulo 2^64 of rows LO..R-1 (R - LO even, at least 2): the pair products, then a
+// balanced tree of 64-bit multiplies.
+template <int R, int LO>
+__device__ __forceinline__ uint64_t pair_product(const int32_t (&f)[R]) {
+    constexpr int N = (R - LO) / 2;
+    uint64_t q[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) q[k] = pmul(f[LO + 2 * k], f[LO + 2 * k + 1]);
+#pragma unroll
+    for (int w = 1; w < N; w *= 2) {
+#pragma unroll
+        for (int k = 0; k + w < N; k += 2 * w) q[k] *= q[k + w];
+    }
+    return q[0];
+}
+
+// The same product modulo 2^128 (replay kernel).
 template <int R>
 __device__ __forceinline__ u128 row_product128(const int32_t (&f)[R]) {
     u128 p = (u128)(__int128)((int64_t)f[0] * (int64_t)f[1]);
@@ -131,8 +147,126 @@ __device__ __forceinline__ u128 row_product128(const int32_t (&f)[R]) {
     return p;
 }
 
+// Leaf tables of the main kernel (one per wave): Gray column j's deltas 2 b_ij at D + j PM,
+// their negatives at D + TNEG + j PM, the base values at D + 2 TNEG; rows p..PM-1 padded (delta
+// 0, base 1).
+constexpr int PM = PMAX;                 // table stride: rows of the widest leaf
+constexpr int TNEG = (PMAX - 1) * PMAX;
+__host__ __device__ constexpr int leaf_table_words() { return 2 * TNEG + PMAX; }
+
+// f += the deltas at d (a + or - table column), R rows.
 template <int R>
-__device__ __forceinline__ void add_rows(int32_t (&f)[R], const int32_t *d, bool add) {
+__device__ __forceinline__ void add_rows(int32_t (&f)[R], const int32_t *d) {
+#pragma unroll
+    for (int i = 0; i < R; i += 4) {
+        const int4 w = *(const int4 *)(d + i);
+        f[i] += w.x;
+        f[i + 1] += w.y;
+        f[i + 2] += w.z;
+        f[i + 3] += w.w;
+    }
+}
+
+// Row values of this lane's first Gray index (no Gray column below p - 7 is set in it).
+template <int R>
+__device__ __forceinline__ void start_rows(int32_t (&f)[R], int p, int lane, const int32_t *D) {
+    const int c = p - 7;
+    const uint32_t L = 1u << c;
+    const uint32_t kfirst = (lane & 1) ? (uint32_t)lane * L + L - 1 : (uint32_t)lane * L;
+    const uint32_t s0 = kfirst ^ (kfirst >> 1);
+    const int32_t *base = D + 2 * TNEG;
+#pragma unroll
+    for (int i = 0; i < R; i += 4) {
+        const int4 w = *(const int4 *)(base + i);
+        f[i] = w.x;
+        f[i + 1] = w.y;
+        f[i + 2] = w.z;
+        f[i + 3] = w.w;
+    }
+#pragma unroll 1
+    for (int j = c; j < p - 1; ++j) {
+        const int32_t in = -(int32_t)((s0 >> j) & 1);   // all ones when Gray column j is in
+        const int32_t *dj = D + j * PM;
+#pragma unroll
+        for (int i = 0; i < R; i += 4) {
+            const int4 w = *(const int4 *)(dj + i);
+            f[i] += w.x & in;
+            f[i + 1] += w.y & in;
+            f[i + 2] += w.z & in;
+            f[i + 3] += w.w & in;
+        }
+    }
+}
+
+// The table column of the flip at step s >= 1 (Gray column ctz(s), added when bit ctz(s) + 1
+// of s is clear).
+__device__ __forceinline__ const int32_t *flip_column(const int32_t *D, uint32_t s) {
+    const int j = __builtin_ctz(s);
+    return D + j * PM + (((s >> (j + 1)) & 1) ? TNEG : 0);
+}
+
+// This lane's share of V for a leaf of order p (7 <= p <= R): one term per step.
+template <int R>
+__device__ __forceinline__ uint64_t walk_plain(int p, int lane, const int32_t *D) {
+    const uint32_t L = 1u << (p - 7);
+    int32_t f[R];
+    start_rows<R>(f, p, lane, D);
+    uint64_t acc0 = pair_product<R, 0>(f), acc1 = 0;
+    for (uint32_t s = 1; s < L; s += 2) {
+        add_rows<R>(f, flip_column(D, s));   // odd steps flip Gray column 0
+        acc1 += pair_product<R, 0>(f);
+        if (s + 1 < L) {
+            add_rows<R>(f, flip_column(D, s + 1));
+            acc0 += pair_product<R, 0>(f);
+        }
+    }
+    return (lane & 1) ? acc1 - acc0 : acc0 - acc1;
+}
+
+// The same share with the steps taken in pairs (8 <= p <= R; Gray column 0 touches only rows
+// 0..BB-1). Steps s (even) and s + 1 differ only by Gray column 0, so their terms are A*P and
+// B*P with P the product of rows BB..R-1 and A, B the products of rows 0..BB-1 before and after
+// the flip: each pair costs one product of the other rows and one of the small block twice.
+template <int R, int BB>
+__device__ __forceinline__ uint64_t walk_paired(int p, int lane, const int32_t *D) {
+    const uint32_t L = 1u << (p - 7);
+    int32_t f[R];
+    start_rows<R>(f, p, lane, D);
+    int32_t dp[BB], dn[BB];   // Gray column 0's deltas and their negatives
+#pragma unroll
+    for (int i = 0; i < BB; ++i) {
+        dp[i] = D[i];
+        dn[i] = D[TNEG + i];
+    }
+    uint64_t acc = 0;
+    for (uint32_t s = 0;;) {
+        const bool add0 = (((s + 1) >> 1) & 1) == 0;   // step s + 1 adds Gray column 0
+        int32_t g[BB];
+#pragma unroll
+        for (int i = 0; i < BB; ++i) g[i] = f[i] + (add0 ? dp[i] : dn[i]);
+        const uint64_t rest = pair_product<R, BB>(f);
+        uint64_t a, b;
+        if constexpr (BB == 2) {
+            a = pmul(f[0], f[1]);
+            b = pmul(g[0], g[1]);
+        } else {
+            a = pmul(f[0], f[1]) * pmul(f[2], f[3]);
+            b = pmul(g[0], g[1]) * pmul(g[2], g[3]);
+        }
+        acc += (a - b) * rest;
+#pragma unroll
+        for (int i = 0; i < BB; ++i) f[i] = g[i];   // step s + 1 leaves Gray column 0 flipped
+        s += 2;
+        if (s >= L) break;
+        add_rows<R>(f, flip_column(D, s));          // step s flips Gray column ctz(s) >= 1
+    }
+    return (lane & 1) ? (uint64_t)0 - acc : acc;
+}
+
+// The replay kernel's walk modulo 2^128 over a table of stride ds (deltas only; a subtraction
+// is a branch: the replay is rare).
+template <int R>
+__device__ __forceinline__ void add_rows_dir(int32_t (&f)[R], const int32_t *d, bool add) {
     int32_t v[R];
 #pragma unroll
     for (int i = 0; i < R; i += 4) {
@@ -151,110 +285,35 @@ __device__ __forceinline__ void add_rows(int32_t (&f)[R], const int32_t *d, bool
     }
 }
 
-// Row values of this lane's first Gray index (no Gray column below p - 7 is set in it).
-template <int R>
-__device__ __forceinline__ void start_rows(int32_t (&f)[R], int p, int lane, const int32_t *D,
-                                           const int32_t *base, int ds) {
-    const int c = p - 7;
-    const uint32_t L = 1u << c;
-    const uint32_t kfirst = (lane & 1) ? (uint32_t)lane * L + L - 1 : (uint32_t)lane * L;
-    const uint32_t s0 = kfirst ^ (kfirst >> 1);
-#pragma unroll
-    for (int i = 0; i < R; i += 4) {
-        const int4 w = *(const int4 *)(base + i);
-        f[i] = w.x;
-        f[i + 1] = w.y;
-        f[i + 2] = w.z;
-        f[i + 3] = w.w;
-    }
-    for (int j = c; j < p - 1; ++j) {
-        const bool in = (s0 >> j) & 1;
-        const int32_t *dj = D + j * ds;
-#pragma unroll
-        for (int i = 0; i < R; ++i) f[i] += in ? dj[i] : 0;
-    }
-}
-
-// This lane's share of V for a leaf of order p (7 <= p <= R): one term per step.
-template <int R>
-__device__ __forceinline__ uint64_t walk_plain(int p, int lane, const int32_t *D, const int32_t *base, int ds) {
-    const uint32_t L = 1u << (p - 7);
-    int32_t f[R];
-    start_rows<R>(f, p, lane, D, base, ds);
-    uint64_t acc0 = row_product<R>(f), acc1 = 0;
-    for (uint32_t s = 1; s < L; s += 2) {
-        add_rows<R>(f, D, ((s >> 1) & 1) == 0);   // odd steps flip Gray column 0
-        acc1 += row_product<R>(f);
-        if (s + 1 < L) {
-            const uint32_t s2 = s + 1;
-            const int j = __builtin_ctz(s2);
-            add_rows<R>(f, D + j * ds, ((s2 >> (j + 1)) & 1) == 0);
-            acc0 += row_product<R>(f);
-        }
-    }
-    return (lane & 1) ? acc1 - acc0 : acc0 - acc1;
-}
-
-// The same share modulo 2^128.
 template <int R>
 __device__ __forceinline__ u128 walk_plain128(int p, int lane, const int32_t *D, const int32_t *base, int ds) {
     const uint32_t L = 1u << (p - 7);
     int32_t f[R];
-    start_rows<R>(f, p, lane, D, base, ds);
+    {
+        const int c = p - 7;
+        const uint32_t kfirst = (lane & 1) ? (uint32_t)lane * L + L - 1 : (uint32_t)lane * L;
+        const uint32_t s0 = kfirst ^ (kfirst >> 1);
+#pragma unroll
+        for (int i = 0; i < R; ++i) f[i] = base[i];
+        for (int j = c; j < p - 1; ++j) {
+            const int32_t in = -(int32_t)((s0 >> j) & 1);
+#pragma unroll
+            for (int i = 0; i < R; ++i) f[i] += D[j * ds + i] & in;
+        }
+    }
     u128 acc0 = row_product128<R>(f), acc1 = 0;
     for (uint32_t s = 1; s < L; s += 2) {
-        add_rows<R>(f, D, ((s >> 1) & 1) == 0);
+        add_rows_dir<R>(f, D, ((s >> 1) & 1) == 0);
         acc1 += row_product128<R>(f);
         if (s + 1 < L) {
             const uint32_t s2 = s + 1;
             const int j = __builtin_ctz(s2);
-            add_rows<R>(f, D + j * ds, ((s2 >> (j + 1)) & 1) == 0);
+            add_rows_dir<R>(f, D + j * ds, ((s2 >> (j + 1)) & 1) == 0);
             acc0 += row_product128<R>(f);
         }
     }
     return (lane & 1) ? acc1 - acc0 : acc0 - acc1;
 }
-
-// The same share with the steps taken in pairs (8 <= p <= R; Gray column 0 touches only rows
-// 0..BB-1). Steps s (even) and s + 1 differ only by Gray column 0, so their terms are A*P and
-// B*P with P the product of rows BB..R-1 and A, B the products of rows 0..BB-1 before and after
-// the flip: each pair costs one product of the other rows and one of the small block twice.
-template <int R, int BB>
-__device__ __forceinline__ uint64_t walk_paired(int p, int lane, const int32_t *D, const int32_t *base, int ds) {
-    const uint32_t L = 1u << (p - 7);
-    int32_t f[R];
-    start_rows<R>(f, p, lane, D, base, ds);
-    int32_t d0[BB];
-#pragma unroll
-    for (int i = 0; i < BB; ++i) d0[i] = D[i];
-    uint64_t acc = 0;
-    for (uint32_t s = 0; s < L; s += 2) {
-        if (s) {   // step s flips Gray column ctz(s) >= 1
-            const int j = __builtin_ctz(s);
-            add_rows<R>(f, D + j * ds, ((s >> (j + 1)) & 1) == 0);
-        }
-        const bool add0 = (((s + 1) >> 1) & 1) == 0;   // step s + 1 adds Gray column 0
-        int32_t g[BB];
-#pragma unroll
-        for (int i = 0; i < BB; ++i) g[i] = add0 ? f[i] + d0[i] : f[i] - d0[i];
-        uint64_t rest = (uint64_t)((int64_t)f[BB] * (int64_t)f[BB + 1]);
-#pragma unroll
-        for (int k = BB / 2 + 1; k < R / 2; ++k) rest *= (uint64_t)((int64_t)f[2 * k] * (int64_t)f[2 * k + 1]);
-        uint64_t a, b;
-        if constexpr (BB == 2) {
-            a = (uint64_t)((int64_t)f[0] * (int64_t)f[1]);
-            b = (uint64_t)((int64_t)g[0] * (int64_t)g[1]);
-        } else {
-            a = (uint64_t)((int64_t)f[0] * (int64_t)f[1]) * (uint64_t)((int64_t)f[2] * (int64_t)f[3]);
-            b = (uint64_t)((int64_t)g[0] * (int64_t)g[1]) * (uint64_t)((int64_t)g[2] * (int64_t)g[3]);
-        }
-        acc += (a - b) * rest;
-#pragma unroll
-        for (int i = 0; i < BB; ++i) f[i] = g[i];   // step s + 1 leaves Gray column 0 flipped
-    }
-    return (lane & 1) ? (uint64_t)0 - acc : acc;
-}
-
 
 // ------------------------------------------------------------------ per-wave LDS region
 // The node being walked lives in one physical mm x mm matrix M (row stride S = dstride(mm))
@@ -267,22 +326,27 @@ __device__ __forceinline__ uint64_t walk_paired(int p, int lane, const int32_t *
 // path keeps an undo record at its order u: its plan, its alive masks, copies of rmask, cmask
 // and rsum, and the lines its children overwrite.
 __host__ __device__ constexpr int lvl_words(int mm) { return align4(CTL + 5 * mm); }
+// The main kernel's region: M, the leaf tables, the node state, the undo records.
 __host__ __device__ constexpr int region_words2(int t, int mm) {
-    return mm * dstride(mm) + mm * dstride(mm) + align4(3 * mm) + 64 + (mm - t) * lvl_words(mm) + SW;
+    return mm * dstride(mm) + leaf_table_words() + align4(3 * mm) + 64 + (mm - t) * lvl_words(mm) + SW;
+}
+// The replay kernel's region: M, tables of every row (stride S), the node state; no records.
+__host__ __device__ constexpr int wide_region_words(int mm) {
+    return 2 * mm * dstride(mm) + align4(3 * mm) + 64 + SW;
 }
 
 struct Region {
     uint32_t *M;                    // mm x S
-    int32_t *D, *base;              // leaf tables: (mm - 1) x S Gray-column deltas, S base values
+    int32_t *D;                     // leaf tables (main kernel: leaf_table_words(); replay: mm x S)
     uint32_t *rmask, *cmask, *rsum; // the current node
     uint32_t *rmap, *cmap;          // leaf compaction: alive row / column of each logical index
-    uint32_t *lv0;                  // undo record of order t + 1
+    uint32_t *lv0;                  // undo record of order t + 1 (main kernel)
     int S, mm, t, lw;
-    __device__ Region(uint32_t *l, int t_, int mm_) : S(dstride(mm_)), mm(mm_), t(t_), lw(lvl_words(mm_)) {
+    __device__ Region(uint32_t *l, int t_, int mm_, int table_words)
+        : S(dstride(mm_)), mm(mm_), t(t_), lw(lvl_words(mm_)) {
         M = l;
         D = (int32_t *)(l + mm * S);
-        base = D + (mm - 1) * S;
-        rmask = (uint32_t *)(base + S);
+        rmask = (uint32_t *)(D + table_words);
         cmask = rmask + mm;
         rsum = cmask + mm;
         rmap = rmask + align4(3 * mm);
@@ -589,44 +653,91 @@ __device__ __forceinline__ void restore_node(const Region &rg, int u, int ch, bo
     wave_sync();
 }
 
-// Leaf tables in LDS for the current node of order p: D[j][i] = 2 b_ij for Gray column j (rows
-// beyond p: 0) and base_i = 2 b_{i,p-1} - R_i (rows beyond p: 1, so f = 1), the node's last
-// alive column being the fixed one, with its sparsest Gray column moved to Gray column 0 and
-// the rows it touches moved to the front (the product is invariant under both permutations).
-// Returns that column's nonzero count b. Needs p >= 2.
-__device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane) {
-    const uint32_t fx = 31u - (uint32_t)__builtin_clz(AC);   // the fixed (last) column
+// The leaf's row and column order: rmap / cmap list the node's alive rows and its alive
+// columns but the last (the fixed one, returned in *fx) in physical order; its sparsest Gray
+// column c0 (returned; *b its nonzero count, *touched its rows) is moved to Gray column 0 and
+// the rows it touches to the front (the product is invariant under both permutations).
+__device__ __forceinline__ uint32_t leaf_order(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane,
+                                               uint32_t *fx, uint32_t *b, uint32_t *touched) {
+    *fx = 31u - (uint32_t)__builtin_clz(AC);   // the fixed (last) column
     const uint32_t below = lane < 32 ? (1u << lane) - 1 : 0xffffffffu;
-    if (lane < 32 && ((AC >> lane) & 1) && (uint32_t)lane != fx) rg.cmap[__popc(AC & below)] = (uint32_t)lane;
+    if (lane < 32 && ((AC >> lane) & 1) && (uint32_t)lane != *fx) rg.cmap[__popc(AC & below)] = (uint32_t)lane;
     if (lane < 32 && ((AR >> lane) & 1)) rg.rmap[__popc(AR & below)] = (uint32_t)lane;
     wave_sync();
     const uint32_t cmk = lane < p - 1 ? rg.cmask[rg.cmap[lane]] : 0u;
-    uint32_t b;
-    const uint32_t c0 = argmin_lane((uint32_t)__popc(cmk), lane < p - 1, &b);
-    const uint32_t touched = (uint32_t)__builtin_amdgcn_readlane((int)cmk, (int)c0);   // physical rows
+    const uint32_t c0 = argmin_lane((uint32_t)__popc(cmk), lane < p - 1, b);
+    *touched = (uint32_t)__builtin_amdgcn_readlane((int)cmk, (int)c0);   // physical rows
+    return c0;
+}
+
+// Table row of the leaf's physical row r: the rows c0 touches first, then the others, each in
+// physical order.
+__device__ __forceinline__ int leaf_row(uint32_t r, uint32_t touched, uint32_t b, uint32_t AR) {
+    const uint32_t rb = (1u << r) - 1;
+    return ((touched >> r) & 1) ? __popc(touched & rb) : (int)b + __popc(~touched & AR & rb);
+}
+
+// Leaf tables of the main kernel for the current node of order p <= PMAX: D + j PM + i =
+// 2 b_ij for Gray column j, D + TNEG + j PM + i its negative, D + 2 TNEG + i = base_i =
+// 2 b_{i,p-1} - R_i (rows p..PM-1: deltas 0, base 1, so f = 1). Returns Gray column 0's
+// nonzero count b. Needs p >= 2.
+__device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane) {
+    uint32_t fx, b, touched;
+    const uint32_t c0 = leaf_order(rg, p, AR, AC, lane, &fx, &b, &touched);
     const int S = rg.S;
+    for (int e = lane; e < (p - 1) * PM; e += SW) {
+        const int j = e / PM, i = e - j * PM;
+        int32_t v = 0;
+        int pos = i;
+        if (i < p) {
+            const uint32_t r = rg.rmap[i];
+            pos = leaf_row(r, touched, b, AR);
+            const int g = j == 0 ? (int)c0 : (j == (int)c0 ? 0 : j);
+            v = 2 * (int32_t)rg.M[r * S + rg.cmap[g]];
+        }
+        rg.D[j * PM + pos] = v;
+        rg.D[TNEG + j * PM + pos] = -v;
+    }
+    if (lane < PM) {
+        int32_t v = 1;
+        int pos = lane;
+        if (lane < p) {
+            const uint32_t r = rg.rmap[lane];
+            pos = leaf_row(r, touched, b, AR);
+            v = 2 * (int32_t)rg.M[r * S + fx] - (int32_t)rg.rsum[r];
+        }
+        rg.D[2 * TNEG + pos] = v;
+    }
+    wave_sync();
+    return b;
+}
+
+// The replay kernel's tables (rows of stride S, every row of the node): D + j S + i = 2 b_ij,
+// base at D + (mm - 1) S. Returns nothing; the replay walks every step.
+__device__ __forceinline__ void leaf_tables_wide(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane) {
+    uint32_t fx, b, touched;
+    const uint32_t c0 = leaf_order(rg, p, AR, AC, lane, &fx, &b, &touched);
+    const int S = rg.S;
+    int32_t *base = rg.D + (rg.mm - 1) * S;
     for (int e = lane; e < (p - 1) * S; e += SW) {
         const int j = e / S, i = e - j * S;
         if (i < p) {
-            const uint32_t r = rg.rmap[i], rb = (1u << r) - 1;
-            const int pos = ((touched >> r) & 1) ? __popc(touched & rb) : (int)b + __popc(~touched & AR & rb);
+            const uint32_t r = rg.rmap[i];
             const int g = j == 0 ? (int)c0 : (j == (int)c0 ? 0 : j);
-            rg.D[j * S + pos] = 2 * (int32_t)rg.M[r * S + rg.cmap[g]];
+            rg.D[j * S + leaf_row(r, touched, b, AR)] = 2 * (int32_t)rg.M[r * S + rg.cmap[g]];
         } else {
             rg.D[e] = 0;
         }
     }
     if (lane < S) {
         if (lane < p) {
-            const uint32_t r = rg.rmap[lane], rb = (1u << r) - 1;
-            const int pos = ((touched >> r) & 1) ? __popc(touched & rb) : (int)b + __popc(~touched & AR & rb);
-            rg.base[pos] = 2 * (int32_t)rg.M[r * S + fx] - (int32_t)rg.rsum[r];
+            const uint32_t r = rg.rmap[lane];
+            base[leaf_row(r, touched, b, AR)] = 2 * (int32_t)rg.M[r * S + fx] - (int32_t)rg.rsum[r];
         } else {
-            rg.base[lane] = 1;
+            base[lane] = 1;
         }
     }
     wave_sync();
-    return b;
 }
 
 // This lane's share of V = (-1)^(p-1) 2^(p-1) per(leaf) modulo 2^64 for a leaf of order
@@ -634,12 +745,12 @@ __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, uint32_
 __device__ __forceinline__ uint64_t eval_leaf(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane) {
     const uint32_t b = leaf_tables(rg, p, AR, AC, lane);
     uint64_t v;
-    if (p >= 8 && p <= 12 && b <= 2) v = walk_paired<12, 2>(p, lane, rg.D, rg.base, rg.S);
-    else if (p >= 8 && p <= 12 && b <= 4) v = walk_paired<12, 4>(p, lane, rg.D, rg.base, rg.S);
-    else if (p <= 12) v = walk_plain<12>(p, lane, rg.D, rg.base, rg.S);
-    else if (b <= 2) v = walk_paired<16, 2>(p, lane, rg.D, rg.base, rg.S);
-    else if (b <= 4) v = walk_paired<16, 4>(p, lane, rg.D, rg.base, rg.S);
-    else v = walk_plain<16>(p, lane, rg.D, rg.base, rg.S);
+    if (p >= 8 && p <= 12 && b <= 2) v = walk_paired<12, 2>(p, lane, rg.D);
+    else if (p >= 8 && p <= 12 && b <= 4) v = walk_paired<12, 4>(p, lane, rg.D);
+    else if (p <= 12) v = walk_plain<12>(p, lane, rg.D);
+    else if (b <= 2) v = walk_paired<16, 2>(p, lane, rg.D);
+    else if (b <= 4) v = walk_paired<16, 4>(p, lane, rg.D);
+    else v = walk_plain<16>(p, lane, rg.D);
     wave_sync();   // the tables are rewritten by the next leaf
     return v;
 }
@@ -730,11 +841,15 @@ __device__ __forceinline__ int load_source(const Region &rg, const SplitArgs &a,
     }
 }
 
+// Four waves per SIMD: the register budget drops from 143 to 128 VGPRs (a few values of the
+// outer loop go to scratch around the leaf walk) and the latency-bound split steps get a third
+// more waves to interleave (measured 17 % faster on the order-20 jobs of the cubic graphs on
+// 60 vertices at t = 12).
 template <bool NODES>
-__global__ __launch_bounds__(SW) void hper_split(SplitArgs a) {
+__global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hper_split(SplitArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    const Region rg(lds, a.t, a.mm);
+    const Region rg(lds, a.t, a.mm, leaf_table_words());
     uint64_t n_leaves = 0, n_terms = 0, n_splits = 0, n_stops = 0, n_bad = 0, n_wide = 0;
     u128 pacc = 0;            // this wave's sum for problem pcur (nodes)
     uint32_t pcur = 0xffffffffu;
@@ -842,7 +957,7 @@ template <bool NODES>
 __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    const Region rg(lds, a.t, a.mm);
+    const Region rg(lds, a.t, a.mm, a.mm * dstride(a.mm));
     const uint64_t n = min((uint64_t)a.stats[4], (uint64_t)a.wide_cap);
     for (uint64_t w = blockIdx.x; w < n; w += gridDim.x) {
         const WideLeaf wl = a.wide[w];
@@ -860,10 +975,11 @@ __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
             if (!plan_split(rg, AR, AC, sparsest_line(rg, AR, AC, lane), lane, pl, false, o)) break;   // not reached:
             apply_child(rg, pl, (int)((path >> (m0 - o)) & 1), AR, AC, lane);   // the first pass split here
         }
-        leaf_tables(rg, p, AR, AC, lane);
+        leaf_tables_wide(rg, p, AR, AC, lane);
+        const int32_t *base = rg.D + (rg.mm - 1) * rg.S;
         u128 v;   // rows padded to the table's stride (20 or 24), never beyond it
-        if (rg.S == 20) v = walk_plain128<20>(p, lane, rg.D, rg.base, rg.S);
-        else v = walk_plain128<SMAX>(p, lane, rg.D, rg.base, rg.S);
+        if (rg.S == 20) v = walk_plain128<20>(p, lane, rg.D, base, rg.S);
+        else v = walk_plain128<SMAX>(p, lane, rg.D, base, rg.S);
         const u128 V = wave_sum128(v);
         bool bad;
         const u128 per = normalise128(V, p, &bad);
@@ -879,6 +995,7 @@ __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
 }  // namespace
 
 size_t split_lds_bytes(int t, int mm) { return (size_t)region_words2(t, mm) * sizeof(uint32_t); }
+static size_t wide_lds_bytes(int mm) { return (size_t)wide_region_words(mm) * sizeof(uint32_t); }
 size_t split_wide_bytes(uint64_t entries) { return (size_t)(entries ? entries : 1) * sizeof(WideLeaf); }
 
 static hipError_t resident_grid(const void *fn, size_t lds, uint64_t *grid) {
@@ -905,9 +1022,10 @@ static hipError_t launch_split_pair(const SplitArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(hper_split<NODES>, dim3((uint32_t)grid), dim3(SW), lds, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = resident_grid((const void *)hper_split_wide<NODES>, lds, &grid);
+    const size_t wlds = wide_lds_bytes(a.mm);
+    e = resident_grid((const void *)hper_split_wide<NODES>, wlds, &grid);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hper_split_wide<NODES>, dim3((uint32_t)grid), dim3(SW), lds, s, a);
+    hipLaunchKernelGGL(hper_split_wide<NODES>, dim3((uint32_t)grid), dim3(SW), wlds, s, a);
     return hipGetLastError();
 }
 
