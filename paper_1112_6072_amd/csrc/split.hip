@@ -50,7 +50,7 @@ namespace {
 
 constexpr int SW = 64;                   // one wave per block
 constexpr int SMAX = HP_SPLIT_MAX_M;     // largest job order
-constexpr int CTL = 16;                  // control words of an undo record
+constexpr int CTL = 8;                   // control words of an undo record
 constexpr int PMAX = 16;                 // widest leaf the main kernel evaluates
 // Words per Gray column of a leaf's delta table (every row; a multiple of 4 for the 16-byte
 // loads), for jobs of order <= mm.
@@ -325,7 +325,7 @@ __device__ __forceinline__ u128 walk_plain128(int p, int lane, const int32_t *D,
 // nonzero of column j; rsum[i], the sum of row i over alive columns. Every split node of the
 // path keeps an undo record at its order u: its plan, its alive masks, copies of rmask, cmask
 // and rsum, and the lines its children overwrite.
-__host__ __device__ constexpr int lvl_words(int mm) { return align4(CTL + 5 * mm); }
+__host__ __device__ constexpr int lvl_words(int mm) { return align4(CTL + 5 * mm); }   // see Ctl
 // The main kernel's region: M, the leaf tables, the node state, the undo records.
 __host__ __device__ constexpr int region_words2(int t, int mm) {
     return mm * dstride(mm) + leaf_table_words() + align4(3 * mm) + 64 + (mm - t) * lvl_words(mm) + SW;
@@ -356,13 +356,37 @@ struct Region {
     __device__ uint32_t *lvl(int u) const { return lv0 + (u - t - 1) * lw; }   // u in t+1 .. mm
 };
 
-struct Ctl {   // word offsets in an undo record
-    enum { IS_COL, IDX, NP, P0, Q0, CA0, CB0, P1, Q1, CA1, CB1, NEXT, AR, AC };
+// An undo record (order u): the split's weights ca0, cb0, ca1, cb1; one packed word (is_col,
+// line, number of pairs, P0, Q0, P1, Q1: 1 + 5 + 2 + 4 x 5 bits); the parent's alive rows and
+// columns; the child being walked; then the parent's line masks (rows, then columns), its row
+// sums and the lines its two children overwrite.
+struct Ctl {
+    enum { CA0, CB0, CA1, CB1, PACKED, AR, AC, NEXT };
 };
-__device__ __forceinline__ uint32_t *sv_r(const Region &rg, int u) { return rg.lvl(u) + CTL; }
-__device__ __forceinline__ uint32_t *sv_c(const Region &rg, int u) { return rg.lvl(u) + CTL + rg.mm; }
-__device__ __forceinline__ uint32_t *sv_s(const Region &rg, int u) { return rg.lvl(u) + CTL + 2 * rg.mm; }
+__device__ __forceinline__ uint32_t *sv_msk(const Region &rg, int u) { return rg.lvl(u) + CTL; }
+__device__ __forceinline__ uint32_t *sv_rs(const Region &rg, int u) { return rg.lvl(u) + CTL + 2 * rg.mm; }
 __device__ __forceinline__ uint32_t *sv_line(const Region &rg, int u, int ch) { return rg.lvl(u) + CTL + (3 + ch) * rg.mm; }
+__device__ __forceinline__ uint32_t pk_is_col(uint32_t w) { return w & 1u; }
+__device__ __forceinline__ uint32_t pk_line(uint32_t w) { return (w >> 1) & 31u; }
+__device__ __forceinline__ uint32_t pk_np(uint32_t w) { return (w >> 6) & 3u; }
+__device__ __forceinline__ uint32_t pk_P(uint32_t w, int c) { return (w >> (8 + 10 * c)) & 31u; }
+__device__ __forceinline__ uint32_t pk_Q(uint32_t w, int c) { return (w >> (13 + 10 * c)) & 31u; }
+
+// The current node's lines, held in registers: lane i < 32 holds row i (msk: its nonzeros over
+// the alive columns, rs: its sum over them), lane 32 + j holds column j (msk: its nonzeros over
+// the alive rows). Lanes of dead lines keep stale values that nothing reads.
+struct Lines {
+    uint32_t msk, rs;
+};
+
+// The lines of a node just loaded into the LDS masks (after its wave_sync).
+__device__ __forceinline__ Lines lines_from_lds(const Region &rg, int lane) {
+    const int k = lane & 31;
+    Lines ln;
+    ln.msk = k < rg.mm ? (lane < 32 ? rg.rmask[k] : rg.cmask[k]) : 0u;
+    ln.rs = lane < 32 && k < rg.mm ? rg.rsum[k] : 0u;
+    return ln;
+}
 
 // Clears the m x m corner of M; returns the alive mask of m lines.
 __device__ __forceinline__ uint32_t clear_node(const Region &rg, int m, int lane) {
@@ -441,14 +465,14 @@ __device__ __forceinline__ int load_node(const Region &rg, const uint32_t *node,
 }
 
 // Step 1 of H_per at the current node: (count << 6) | (32 * is_col + index) of the sparsest
-// line (rows before columns, then the lowest index; physical order is the node's line order).
-__device__ __forceinline__ uint32_t sparsest_line(const Region &rg, uint32_t AR, uint32_t AC, int lane) {
+// line (rows before columns, then the lowest index; physical order is the node's line order);
+// *nz receives that line's nonzero mask.
+__device__ __forceinline__ uint32_t sparsest_line(const Lines &ln, uint32_t AR, uint32_t AC, int lane, uint32_t *nz) {
     const bool row = lane < 32 && ((AR >> lane) & 1), col = lane >= 32 && ((AC >> (lane - 32)) & 1);
-    uint32_t cnt = 0;
-    if (row) cnt = (uint32_t)__popc(rg.rmask[lane]);
-    else if (col) cnt = (uint32_t)__popc(rg.cmask[lane - 32]);
+    const uint32_t cnt = row || col ? (uint32_t)__popc(ln.msk) : 0u;
     uint32_t s;
     const uint32_t w = argmin_lane(cnt, row || col, &s);
+    *nz = (uint32_t)__builtin_amdgcn_readlane((int)ln.msk, (int)w);
     return (s << 6) | w;
 }
 
@@ -459,19 +483,29 @@ struct Plan {
     uint32_t P[2], Q[2], ca[2], cb[2];
 };
 
+// What the plan read for its children, per lane: the entries at Q_c and P_c along the lane's
+// own line (rows of a row split, columns of a column split) and, on lanes i < 32, the entry of
+// row i on the split line (column splits).
+struct PairVals {
+    uint32_t q[2], p[2], lv;
+};
+
 __device__ __forceinline__ Plan load_plan(const Region &rg, int u) {
-    const uint32_t *ctl = rg.lvl(u);
+    const uint4 w0 = *(const uint4 *)rg.lvl(u);
+    const uint32_t pk = uni(rg.lvl(u)[Ctl::PACKED]);
     Plan pl;
-    pl.is_col = uni(ctl[Ctl::IS_COL]);
-    pl.line = uni(ctl[Ctl::IDX]);
-    pl.np = uni(ctl[Ctl::NP]);
+    pl.is_col = pk_is_col(pk);
+    pl.line = pk_line(pk);
+    pl.np = pk_np(pk);
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-        pl.P[c] = uni(ctl[Ctl::P0 + 4 * c]);
-        pl.Q[c] = uni(ctl[Ctl::Q0 + 4 * c]);
-        pl.ca[c] = uni(ctl[Ctl::CA0 + 4 * c]);
-        pl.cb[c] = uni(ctl[Ctl::CB0 + 4 * c]);
+        pl.P[c] = pk_P(pk, c);
+        pl.Q[c] = pk_Q(pk, c);
     }
+    pl.ca[0] = uni(w0.x);
+    pl.cb[0] = uni(w0.y);
+    pl.ca[1] = uni(w0.z);
+    pl.cb[1] = uni(w0.w);
     return pl;
 }
 
@@ -479,14 +513,13 @@ __device__ __forceinline__ Plan load_plan(const Region &rg, int u) {
 // with the lowest zero of the line at weight 0). Returns false when a child would break the
 // entry or row-sum bound. With `record` (a split of the main walk at order u) the plan, the
 // alive masks and the parent's state that the children overwrite go to the undo record.
-__device__ __forceinline__ bool plan_split(const Region &rg, uint32_t AR, uint32_t AC, uint32_t key, int lane,
-                                          Plan &pl, bool record, int u) {
+__device__ __forceinline__ bool plan_split(const Region &rg, uint32_t AR, uint32_t AC, uint32_t key, uint32_t nz,
+                                          const Lines &ln, int lane, Plan &pl, PairVals &pv, bool record, int u) {
     const uint32_t s = key >> 6, is_col = (key >> 5) & 1, line = key & 31;
     const int S = rg.S;
     const uint32_t *M = rg.M;
     const uint32_t other = is_col ? AR : AC;   // the positions along the line
-    const uint32_t lv = lane < 32 && ((other >> lane) & 1) ? (is_col ? M[lane * S + line] : M[line * S + lane]) : 0u;
-    uint32_t nz = uni(is_col ? rg.cmask[line] : rg.rmask[line]);
+    pv.lv = lane < 32 && ((other >> lane) & 1) ? (is_col ? M[lane * S + line] : M[line * S + lane]) : 0u;
     const uint32_t zero = (uint32_t)__builtin_ctz(~nz & other);
     uint32_t pos[4], val[4];
 #pragma unroll
@@ -496,30 +529,36 @@ __device__ __forceinline__ bool plan_split(const Region &rg, uint32_t AR, uint32
         if ((uint32_t)k < s) {
             pos[k] = (uint32_t)__builtin_ctz(nz);
             nz &= nz - 1;
-            val[k] = (uint32_t)__builtin_amdgcn_readlane((int)lv, (int)pos[k]);
+            val[k] = (uint32_t)__builtin_amdgcn_readlane((int)pv.lv, (int)pos[k]);
         }
     }
     const uint32_t np = (s + 1) / 2;
+    const int k = lane & 31;
+    // the lane's own line takes part in the merge: another alive row (row split) or another
+    // alive column (column split)
+    const bool mine = is_col ? lane >= 32 && ((AC >> k) & 1) && (uint32_t)k != line
+                             : lane < 32 && ((AR >> k) & 1) && (uint32_t)k != line;
     bool fail = false;
-    const bool arow = lane < 32 && ((AR >> lane) & 1) && (uint32_t)lane != line;   // other alive rows
-    const bool acol = lane < 32 && ((AC >> lane) & 1) && (uint32_t)lane != line;   // other alive columns
-    for (uint32_t ch = 0; ch < np; ++ch) {
-        const uint32_t P = pos[2 * ch], Q = pos[2 * ch + 1];
-        const uint64_t ca = val[2 * ch], cb = val[2 * ch + 1];
-        if (!is_col) {   // merged column; each other row loses P and Q and gains the merge
-            if (arow) {
-                const uint64_t mq = M[lane * S + Q], mp = M[lane * S + P];
-                const uint64_t mv = ca * mq + cb * mp;
-                fail = fail || mv >= HP_MAX_ENTRY || rg.rsum[lane] - mq - mp + mv >= HP_MAX_ROWSUM;
-            }
-        } else {         // merged row (its entries column by column); its sum from rows P and Q
-            if (acol) {
-                const uint64_t mv = ca * M[Q * S + lane] + cb * M[P * S + lane];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        pv.q[c] = pv.p[c] = 0;
+        if ((uint32_t)c < np) {
+            const uint32_t P = pos[2 * c], Q = pos[2 * c + 1];
+            const uint64_t ca = val[2 * c], cb = val[2 * c + 1];
+            if (mine) {
+                pv.q[c] = is_col ? M[Q * S + k] : M[k * S + Q];
+                pv.p[c] = is_col ? M[P * S + k] : M[k * S + P];
+                const uint64_t mv = ca * pv.q[c] + cb * pv.p[c];
                 fail = fail || mv >= HP_MAX_ENTRY;
+                if (!is_col) fail = fail || (uint64_t)ln.rs - pv.q[c] - pv.p[c] + mv >= HP_MAX_ROWSUM;
             }
-            const uint64_t rq = uni(rg.rsum[Q]) - (uint64_t)uni(M[Q * S + line]);
-            const uint64_t rp = uni(rg.rsum[P]) - (uint64_t)uni(M[P * S + line]);
-            fail = fail || ca * rq + cb * rp >= HP_MAX_ROWSUM;
+            if (is_col) {   // the merged row's sum from rows P and Q without the split column
+                const uint64_t rq = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)Q) -
+                                    (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pv.lv, (int)Q);
+                const uint64_t rp = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)P) -
+                                    (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pv.lv, (int)P);
+                fail = fail || ca * rq + cb * rp >= HP_MAX_ROWSUM;
+            }
         }
     }
     if (__ballot(fail) != 0) return false;
@@ -536,119 +575,104 @@ __device__ __forceinline__ bool plan_split(const Region &rg, uint32_t AR, uint32
     if (record) {
         uint32_t *ctl = rg.lvl(u);
         if (lane == 0) {
-            ctl[Ctl::IS_COL] = is_col;
-            ctl[Ctl::IDX] = line;
-            ctl[Ctl::NP] = np;
-            ctl[Ctl::P0] = pos[0];
-            ctl[Ctl::Q0] = pos[1];
-            ctl[Ctl::CA0] = val[0];
-            ctl[Ctl::CB0] = val[1];
-            ctl[Ctl::P1] = pos[2];
-            ctl[Ctl::Q1] = pos[3];
-            ctl[Ctl::CA1] = val[2];
-            ctl[Ctl::CB1] = val[3];
-            ctl[Ctl::NEXT] = 0;
-            ctl[Ctl::AR] = AR;
-            ctl[Ctl::AC] = AC;
+            const uint32_t pk = is_col | line << 1 | np << 6 | pos[0] << 8 | pos[1] << 13 | pos[2] << 18 | pos[3] << 23;
+            *(uint4 *)ctl = make_uint4(val[0], val[1], val[2], val[3]);
+            *(uint4 *)(ctl + 4) = make_uint4(pk, AR, AC, 0u);
         }
-        if (lane < rg.mm) {
-            sv_r(rg, u)[lane] = rg.rmask[lane];
-            sv_c(rg, u)[lane] = rg.cmask[lane];
-            sv_s(rg, u)[lane] = rg.rsum[lane];
+        if (k < rg.mm) {
+            sv_msk(rg, u)[(lane >> 5) * rg.mm + k] = ln.msk;
+            if (lane < 32) sv_rs(rg, u)[k] = ln.rs;
+        }
+        if (mine) {   // the lines the children overwrite: the pair's first line, per child
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {   // the lines the children overwrite
-                const uint32_t keep = min(pos[2 * c], pos[2 * c + 1]);
-                sv_line(rg, u, c)[lane] = is_col ? M[keep * S + lane] : M[lane * S + keep];
-            }
+            for (int c = 0; c < 2; ++c)
+                if ((uint32_t)c < np) sv_line(rg, u, c)[k] = pos[2 * c] < pos[2 * c + 1] ? pv.p[c] : pv.q[c];
         }
         wave_sync();
     }
     return true;
 }
 
-// Child `ch` of the current node (plan pl; alive masks AR, AC updated in place): the merged
-// line over the pair's first line, the other line and the split line dead, masks and row sums
-// updated.
-__device__ __forceinline__ void apply_child(const Region &rg, const Plan &pl, int ch, uint32_t &AR, uint32_t &AC, int lane) {
+// Child `ch` of the current node (plan pl; alive masks AR, AC and the lines ln updated): the
+// merged line over the pair's first line, the other line and the split line dead. With `pv`
+// the entries the plan read are used, else they are read from M.
+__device__ __forceinline__ void apply_child(const Region &rg, const Plan &pl, int ch, uint32_t &AR, uint32_t &AC,
+                                            Lines &ln, const PairVals *pv, int lane) {
     const int S = rg.S;
     uint32_t *M = rg.M;
     const uint32_t line = pl.line;
     const uint32_t P = ch ? pl.P[1] : pl.P[0], Q = ch ? pl.Q[1] : pl.Q[0];
     const uint32_t ca = ch ? pl.ca[1] : pl.ca[0], cb = ch ? pl.cb[1] : pl.cb[0];
     const uint32_t keep = min(P, Q), drop = max(P, Q);
+    const uint32_t kb = 1u << keep, db = 1u << drop;
+    const int k = lane & 31;
     if (!pl.is_col) {   // row `line` deleted; columns P, Q merged into column keep
-        const uint32_t AR2 = AR & ~(1u << line), AC2 = AC & ~(1u << drop);
-        const bool row = lane < 32 && ((AR2 >> lane) & 1);
-        uint32_t mv = 0, rm = 0, rs = 0;
+        const uint32_t AR2 = AR & ~(1u << line), AC2 = AC & ~db;
+        const bool row = lane < 32 && ((AR2 >> k) & 1);
+        uint32_t mv = 0;
         if (row) {
-            const uint32_t mq = M[lane * S + Q], mp = M[lane * S + P];
+            const uint32_t mq = pv ? (ch ? pv->q[1] : pv->q[0]) : M[k * S + Q];
+            const uint32_t mp = pv ? (ch ? pv->p[1] : pv->p[0]) : M[k * S + P];
             mv = ca * mq + cb * mp;
-            rm = (rg.rmask[lane] & ~((1u << keep) | (1u << drop))) | (mv ? 1u << keep : 0u);
-            rs = rg.rsum[lane] - mq - mp + mv;
+            ln.msk = (ln.msk & ~(kb | db)) | (mv ? kb : 0u);
+            ln.rs = ln.rs - mq - mp + mv;
         }
         const uint32_t newcol = (uint32_t)__ballot(row && mv != 0);
-        const bool col = lane < 32 && ((AC2 >> lane) & 1);
-        uint32_t cm = 0;
-        if (col) cm = (uint32_t)lane == keep ? newcol : rg.cmask[lane] & ~(1u << line);
-        wave_sync();
-        if (row) {
-            M[lane * S + keep] = mv;
-            rg.rmask[lane] = rm;
-            rg.rsum[lane] = rs;
-        }
-        if (col) rg.cmask[lane] = cm;
+        if (lane >= 32 && ((AC2 >> k) & 1)) ln.msk = (uint32_t)k == keep ? newcol : ln.msk & ~(1u << line);
+        if (row) M[k * S + keep] = mv;   // each lane rewrites its own row: no other lane reads it here
         AR = AR2;
         AC = AC2;
     } else {            // column `line` deleted; rows P, Q merged into row keep
-        const uint32_t AR2 = AR & ~(1u << drop), AC2 = AC & ~(1u << line);
-        const bool col = lane < 32 && ((AC2 >> lane) & 1);
-        uint32_t mv = 0, cm = 0;
+        const uint32_t AR2 = AR & ~db, AC2 = AC & ~(1u << line);
+        const uint32_t lv = pv ? pv->lv : (lane < 32 && ((AR >> k) & 1) ? M[k * S + line] : 0u);
+        const uint32_t rq = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)Q) -
+                            (uint32_t)__builtin_amdgcn_readlane((int)lv, (int)Q);
+        const uint32_t rp = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)P) -
+                            (uint32_t)__builtin_amdgcn_readlane((int)lv, (int)P);
+        const bool col = lane >= 32 && ((AC2 >> k) & 1);
+        uint32_t mv = 0;
         if (col) {
-            mv = ca * M[Q * S + lane] + cb * M[P * S + lane];
-            cm = (rg.cmask[lane] & ~((1u << keep) | (1u << drop))) | (mv ? 1u << keep : 0u);
+            const uint32_t mq = pv ? (ch ? pv->q[1] : pv->q[0]) : M[Q * S + k];
+            const uint32_t mp = pv ? (ch ? pv->p[1] : pv->p[0]) : M[P * S + k];
+            mv = ca * mq + cb * mp;
+            ln.msk = (ln.msk & ~(kb | db)) | (mv ? kb : 0u);
         }
-        const uint32_t newrow = (uint32_t)__ballot(col && mv != 0);
-        const bool row = lane < 32 && ((AR2 >> lane) & 1);
-        uint32_t rm = 0, rs = 0;
-        if (row) {
-            if ((uint32_t)lane == keep) {
-                rm = newrow;
-                rs = ca * (rg.rsum[Q] - M[Q * S + line]) + cb * (rg.rsum[P] - M[P * S + line]);
+        const uint32_t newrow = (uint32_t)(__ballot(col && mv != 0) >> 32);
+        if (lane < 32 && ((AR2 >> k) & 1)) {
+            if ((uint32_t)k == keep) {
+                ln.msk = newrow;
+                ln.rs = ca * rq + cb * rp;
             } else {
-                rm = rg.rmask[lane] & ~(1u << line);
-                rs = rg.rsum[lane] - M[lane * S + line];
+                ln.msk &= ~(1u << line);
+                ln.rs -= lv;
             }
         }
-        wave_sync();
-        if (col) {
-            M[keep * S + lane] = mv;
-            rg.cmask[lane] = cm;
-        }
-        if (row) {
-            rg.rmask[lane] = rm;
-            rg.rsum[lane] = rs;
-        }
+        if (col) M[keep * S + k] = mv;   // each lane rewrites its own column's entry
         AR = AR2;
         AC = AC2;
     }
     wave_sync();
 }
 
-// Back to the state of the split node at order u before child ch was applied: its masks, row
-// sums and alive lines, and the line child ch overwrote.
-__device__ __forceinline__ void restore_node(const Region &rg, int u, int ch, bool masks, int lane) {
+// Back to the state of the split node at order u before child ch was applied: the line child
+// ch overwrote and, with `masks`, the node's lines.
+__device__ __forceinline__ void restore_node(const Region &rg, int u, int ch, bool masks, Lines &ln, int lane) {
     const uint32_t *ctl = rg.lvl(u);
-    const uint32_t is_col = uni(ctl[Ctl::IS_COL]);
-    const uint32_t keep = min(uni(ctl[Ctl::P0 + 4 * ch]), uni(ctl[Ctl::Q0 + 4 * ch]));
-    if (lane < rg.mm) {
-        const uint32_t v = sv_line(rg, u, ch)[lane];
-        if (is_col) rg.M[keep * rg.S + lane] = v;
-        else rg.M[lane * rg.S + keep] = v;
-        if (masks) {
-            rg.rmask[lane] = sv_r(rg, u)[lane];
-            rg.cmask[lane] = sv_c(rg, u)[lane];
-            rg.rsum[lane] = sv_s(rg, u)[lane];
-        }
+    const uint32_t pk = uni(ctl[Ctl::PACKED]);
+    const uint32_t AR = uni(ctl[Ctl::AR]), AC = uni(ctl[Ctl::AC]);
+    const uint32_t is_col = pk_is_col(pk), line = pk_line(pk);
+    const uint32_t keep = min(pk_P(pk, ch), pk_Q(pk, ch));
+    const int k = lane & 31;
+    const bool mine = is_col ? lane >= 32 && ((AC >> k) & 1) && (uint32_t)k != line
+                             : lane < 32 && ((AR >> k) & 1) && (uint32_t)k != line;
+    if (mine) {
+        const uint32_t v = sv_line(rg, u, ch)[k];
+        if (is_col) rg.M[keep * rg.S + k] = v;
+        else rg.M[k * rg.S + keep] = v;
+    }
+    if (masks && k < rg.mm) {
+        ln.msk = sv_msk(rg, u)[(lane >> 5) * rg.mm + k];
+        if (lane < 32) ln.rs = sv_rs(rg, u)[k];
     }
     wave_sync();
 }
@@ -657,14 +681,16 @@ __device__ __forceinline__ void restore_node(const Region &rg, int u, int ch, bo
 // columns but the last (the fixed one, returned in *fx) in physical order; its sparsest Gray
 // column c0 (returned; *b its nonzero count, *touched its rows) is moved to Gray column 0 and
 // the rows it touches to the front (the product is invariant under both permutations).
-__device__ __forceinline__ uint32_t leaf_order(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane,
-                                               uint32_t *fx, uint32_t *b, uint32_t *touched) {
+__device__ __forceinline__ uint32_t leaf_order(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
+                                               int lane, uint32_t *fx, uint32_t *b, uint32_t *touched) {
     *fx = 31u - (uint32_t)__builtin_clz(AC);   // the fixed (last) column
-    const uint32_t below = lane < 32 ? (1u << lane) - 1 : 0xffffffffu;
-    if (lane < 32 && ((AC >> lane) & 1) && (uint32_t)lane != *fx) rg.cmap[__popc(AC & below)] = (uint32_t)lane;
-    if (lane < 32 && ((AR >> lane) & 1)) rg.rmap[__popc(AR & below)] = (uint32_t)lane;
+    // mbcnt: the set bits of a mask below this lane (lanes < 32)
+    if (lane < 32 && ((AC >> lane) & 1) && (uint32_t)lane != *fx) rg.cmap[__builtin_amdgcn_mbcnt_lo(AC, 0u)] = (uint32_t)lane;
+    if (lane < 32 && ((AR >> lane) & 1)) rg.rmap[__builtin_amdgcn_mbcnt_lo(AR, 0u)] = (uint32_t)lane;
     wave_sync();
-    const uint32_t cmk = lane < p - 1 ? rg.cmask[rg.cmap[lane]] : 0u;
+    const uint32_t src = lane < p - 1 ? 32u + rg.cmap[lane] : 32u;
+    const uint32_t cmk0 = (uint32_t)__shfl((int)ln.msk, (int)src);   // every lane takes part
+    const uint32_t cmk = lane < p - 1 ? cmk0 : 0u;
     const uint32_t c0 = argmin_lane((uint32_t)__popc(cmk), lane < p - 1, b);
     *touched = (uint32_t)__builtin_amdgcn_readlane((int)cmk, (int)c0);   // physical rows
     return c0;
@@ -681,9 +707,11 @@ __device__ __forceinline__ int leaf_row(uint32_t r, uint32_t touched, uint32_t b
 // 2 b_ij for Gray column j, D + TNEG + j PM + i its negative, D + 2 TNEG + i = base_i =
 // 2 b_{i,p-1} - R_i (rows p..PM-1: deltas 0, base 1, so f = 1). Returns Gray column 0's
 // nonzero count b. Needs p >= 2.
-__device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane) {
+__device__ __forceinline__ uint32_t leaf_tables(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
+                                                int lane) {
     uint32_t fx, b, touched;
-    const uint32_t c0 = leaf_order(rg, p, AR, AC, lane, &fx, &b, &touched);
+    const uint32_t c0 = leaf_order(rg, ln, p, AR, AC, lane, &fx, &b, &touched);
+    const uint32_t rsr = (uint32_t)__shfl((int)ln.rs, lane < p ? (int)rg.rmap[lane] : 0);   // row sum of table row `lane`
     const int S = rg.S;
     for (int e = lane; e < (p - 1) * PM; e += SW) {
         const int j = e / PM, i = e - j * PM;
@@ -704,7 +732,7 @@ __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, uint32_
         if (lane < p) {
             const uint32_t r = rg.rmap[lane];
             pos = leaf_row(r, touched, b, AR);
-            v = 2 * (int32_t)rg.M[r * S + fx] - (int32_t)rg.rsum[r];
+            v = 2 * (int32_t)rg.M[r * S + fx] - (int32_t)rsr;
         }
         rg.D[2 * TNEG + pos] = v;
     }
@@ -714,9 +742,11 @@ __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, int p, uint32_
 
 // The replay kernel's tables (rows of stride S, every row of the node): D + j S + i = 2 b_ij,
 // base at D + (mm - 1) S. Returns nothing; the replay walks every step.
-__device__ __forceinline__ void leaf_tables_wide(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane) {
+__device__ __forceinline__ void leaf_tables_wide(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
+                                                 int lane) {
     uint32_t fx, b, touched;
-    const uint32_t c0 = leaf_order(rg, p, AR, AC, lane, &fx, &b, &touched);
+    const uint32_t c0 = leaf_order(rg, ln, p, AR, AC, lane, &fx, &b, &touched);
+    const uint32_t rsr = (uint32_t)__shfl((int)ln.rs, lane < p ? (int)rg.rmap[lane] : 0);
     const int S = rg.S;
     int32_t *base = rg.D + (rg.mm - 1) * S;
     for (int e = lane; e < (p - 1) * S; e += SW) {
@@ -732,7 +762,7 @@ __device__ __forceinline__ void leaf_tables_wide(const Region &rg, int p, uint32
     if (lane < S) {
         if (lane < p) {
             const uint32_t r = rg.rmap[lane];
-            base[leaf_row(r, touched, b, AR)] = 2 * (int32_t)rg.M[r * S + fx] - (int32_t)rg.rsum[r];
+            base[leaf_row(r, touched, b, AR)] = 2 * (int32_t)rg.M[r * S + fx] - (int32_t)rsr;
         } else {
             base[lane] = 1;
         }
@@ -742,8 +772,9 @@ __device__ __forceinline__ void leaf_tables_wide(const Region &rg, int p, uint32
 
 // This lane's share of V = (-1)^(p-1) 2^(p-1) per(leaf) modulo 2^64 for a leaf of order
 // 7 <= p <= PMAX.
-__device__ __forceinline__ uint64_t eval_leaf(const Region &rg, int p, uint32_t AR, uint32_t AC, int lane) {
-    const uint32_t b = leaf_tables(rg, p, AR, AC, lane);
+__device__ __forceinline__ uint64_t eval_leaf(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
+                                              int lane) {
+    const uint32_t b = leaf_tables(rg, ln, p, AR, AC, lane);
     uint64_t v;
     if (p >= 8 && p <= 12 && b <= 2) v = walk_paired<12, 2>(p, lane, rg.D);
     else if (p >= 8 && p <= 12 && b <= 4) v = walk_paired<12, 4>(p, lane, rg.D);
@@ -756,8 +787,8 @@ __device__ __forceinline__ uint64_t eval_leaf(const Region &rg, int p, uint32_t 
 }
 
 // Proven log2 upper bounds of per(node): the product of its row sums, and of its column sums.
-__device__ __forceinline__ float rowsum_log2(const Region &rg, uint32_t AR, int lane) {
-    const float x = lane < 32 && ((AR >> lane) & 1) ? __log2f((float)rg.rsum[lane]) : 0.0f;   // < 2^24: exact
+__device__ __forceinline__ float rowsum_log2(const Lines &ln, uint32_t AR, int lane) {
+    const float x = lane < 32 && ((AR >> lane) & 1) ? __log2f((float)ln.rs) : 0.0f;   // < 2^24: exact
     return wave_sumf(x) + 1e-3f;   // margin for the hardware logarithm and the float sum
 }
 __device__ __forceinline__ float colsum_log2(const Region &rg, uint32_t AR, uint32_t AC, int lane) {
@@ -863,17 +894,20 @@ __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hp
         uint32_t problem;
         const int m0 = load_source<NODES>(rg, a, job, lane, &jb, &problem);
         uint32_t AR = (1u << m0) - 1, AC = AR;   // alive rows and columns of the current node
+        Lines ln = lines_from_lds(rg, lane);
         u128 acc = 0;   // per(B): the sum of the normalised leaves (wave-uniform)
         int o = m0;
         Plan pl;
+        PairVals pv;
         for (;;) {
-            const uint32_t key = sparsest_line(rg, AR, AC, lane);
+            uint32_t nz;
+            const uint32_t key = sparsest_line(ln, AR, AC, lane, &nz);
             const uint32_t s = key >> 6;
             if (s != 0) {
                 const bool leaf = o <= a.t || o <= 2 || (int)s >= a.s_leaf || s > 4;
                 if (!leaf) {
-                    if (plan_split(rg, AR, AC, key, lane, pl, true, o)) {
-                        apply_child(rg, pl, 0, AR, AC, lane);
+                    if (plan_split(rg, AR, AC, key, nz, ln, lane, pl, pv, true, o)) {
+                        apply_child(rg, pl, 0, AR, AC, ln, &pv, lane);
                         ++n_splits;
                         --o;
                         continue;
@@ -884,11 +918,11 @@ __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hp
                 n_terms += 1ull << (o - 1);
                 // exact modulo 2^64 when per(leaf) 2^(o-1) < 2^63 (bound: the job's, or the
                 // leaf's product of row sums)
-                bool ok64 = fminf(jb, rowsum_log2(rg, AR, lane)) + (float)o <= 62.5f;
+                bool ok64 = fminf(jb, rowsum_log2(ln, AR, lane)) + (float)o <= 62.5f;
                 if (!ok64 && o <= PMAX) ok64 = colsum_log2(rg, AR, AC, lane) + (float)o <= 62.5f;
                 if (ok64 && o <= PMAX) {
                     bool bad;
-                    const uint64_t per = normalise64(uni64(wave_sum64(eval_leaf(rg, o, AR, AC, lane))), o, &bad);
+                    const uint64_t per = normalise64(uni64(wave_sum64(eval_leaf(rg, ln, o, AR, AC, lane))), o, &bad);
                     n_bad += bad;
                     acc += per;
                 } else {   // replayed by the second kernel in 128-bit arithmetic
@@ -908,15 +942,15 @@ __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hp
             for (; up <= m0; ++up) {
                 uint32_t *ctl = rg.lvl(up);
                 const uint32_t cur = uni(ctl[Ctl::NEXT]), nx = cur + 1;
-                if (nx < uni(ctl[Ctl::NP])) {
-                    restore_node(rg, up, (int)cur, true, lane);
+                if (nx < pk_np(uni(ctl[Ctl::PACKED]))) {
+                    restore_node(rg, up, (int)cur, true, ln, lane);
                     AR = uni(ctl[Ctl::AR]);
                     AC = uni(ctl[Ctl::AC]);
                     if (lane == 0) ctl[Ctl::NEXT] = nx;
-                    apply_child(rg, load_plan(rg, up), (int)nx, AR, AC, lane);
+                    apply_child(rg, load_plan(rg, up), (int)nx, AR, AC, ln, nullptr, lane);
                     break;
                 }
-                restore_node(rg, up, (int)cur, false, lane);
+                restore_node(rg, up, (int)cur, false, ln, lane);
             }
             if (up > m0) break;
             o = up - 1;
@@ -970,12 +1004,16 @@ __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
         const int m0 = load_source<NODES>(rg, a, job, lane, &jb, &problem);
         if (p < 7 || p > m0 || m0 > a.mm) continue;
         uint32_t AR = (1u << m0) - 1, AC = AR;
+        Lines ln = lines_from_lds(rg, lane);
         Plan pl;
+        PairVals pv;
         for (int o = m0; o > p; --o) {
-            if (!plan_split(rg, AR, AC, sparsest_line(rg, AR, AC, lane), lane, pl, false, o)) break;   // not reached:
-            apply_child(rg, pl, (int)((path >> (m0 - o)) & 1), AR, AC, lane);   // the first pass split here
+            uint32_t nz;
+            const uint32_t key = sparsest_line(ln, AR, AC, lane, &nz);
+            if (!plan_split(rg, AR, AC, key, nz, ln, lane, pl, pv, false, o)) break;   // not reached:
+            apply_child(rg, pl, (int)((path >> (m0 - o)) & 1), AR, AC, ln, &pv, lane);   // the first pass split here
         }
-        leaf_tables_wide(rg, p, AR, AC, lane);
+        leaf_tables_wide(rg, ln, p, AR, AC, lane);
         const int32_t *base = rg.D + (rg.mm - 1) * rg.S;
         u128 v;   // rows padded to the table's stride (20 or 24), never beyond it
         if (rg.S == 20) v = walk_plain128<20>(p, lane, rg.D, base, rg.S);
