@@ -513,56 +513,57 @@ __device__ __forceinline__ Plan load_plan(const Region &rg, int u) {
 // with the lowest zero of the line at weight 0). Returns false when a child would break the
 // entry or row-sum bound. With `record` (a split of the main walk at order u) the plan, the
 // alive masks and the parent's state that the children overwrite go to the undo record.
-__device__ __forceinline__ bool plan_split(const Region &rg, uint32_t AR, uint32_t AC, uint32_t key, uint32_t nz,
-                                          const Lines &ln, int lane, Plan &pl, PairVals &pv, bool record, int u) {
-    const uint32_t s = key >> 6, is_col = (key >> 5) & 1, line = key & 31;
+// COL: the line is a column. Branch-free where it can be: the second pair's entries are read
+// even when there is one pair (its positions are then valid, its results unused).
+template <bool COL>
+__device__ __forceinline__ bool plan_split_t(const Region &rg, uint32_t AR, uint32_t AC, uint32_t s, uint32_t line,
+                                            uint32_t nz, const Lines &ln, int lane, Plan &pl, PairVals &pv,
+                                            bool record, int u) {
     const int S = rg.S;
     const uint32_t *M = rg.M;
-    const uint32_t other = is_col ? AR : AC;   // the positions along the line
-    pv.lv = lane < 32 && ((other >> lane) & 1) ? (is_col ? M[lane * S + line] : M[line * S + lane]) : 0u;
+    const uint32_t other = COL ? AR : AC;   // the positions along the line
+    pv.lv = lane < 32 && ((other >> lane) & 1) ? (COL ? M[lane * S + line] : M[line * S + lane]) : 0u;
     const uint32_t zero = (uint32_t)__builtin_ctz(~nz & other);
     uint32_t pos[4], val[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        pos[k] = zero;
-        val[k] = 0;
-        if ((uint32_t)k < s) {
-            pos[k] = (uint32_t)__builtin_ctz(nz);
-            nz &= nz - 1;
-            val[k] = (uint32_t)__builtin_amdgcn_readlane((int)pv.lv, (int)pos[k]);
-        }
+    for (int k = 0; k < 4; ++k) {   // bit 31 is never a position: ctz gives 31 once nz is empty
+        const uint32_t at = (uint32_t)__builtin_ctz(nz | 0x80000000u);
+        nz &= nz - 1;
+        pos[k] = (uint32_t)k < s ? at : zero;
+        val[k] = (uint32_t)__builtin_amdgcn_readlane((int)pv.lv, (int)pos[k]);
+        val[k] = (uint32_t)k < s ? val[k] : 0u;
     }
     const uint32_t np = (s + 1) / 2;
     const int k = lane & 31;
     // the lane's own line takes part in the merge: another alive row (row split) or another
     // alive column (column split)
-    const bool mine = is_col ? lane >= 32 && ((AC >> k) & 1) && (uint32_t)k != line
-                             : lane < 32 && ((AR >> k) & 1) && (uint32_t)k != line;
+    const bool mine = COL ? lane >= 32 && ((AC >> k) & 1) && (uint32_t)k != line
+                          : lane < 32 && ((AR >> k) & 1) && (uint32_t)k != line;
     bool fail = false;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
+        const uint32_t P = pos[2 * c], Q = pos[2 * c + 1];
+        const uint64_t ca = val[2 * c], cb = val[2 * c + 1];
+        const bool live = (uint32_t)c < np;
         pv.q[c] = pv.p[c] = 0;
-        if ((uint32_t)c < np) {
-            const uint32_t P = pos[2 * c], Q = pos[2 * c + 1];
-            const uint64_t ca = val[2 * c], cb = val[2 * c + 1];
-            if (mine) {
-                pv.q[c] = is_col ? M[Q * S + k] : M[k * S + Q];
-                pv.p[c] = is_col ? M[P * S + k] : M[k * S + P];
-                const uint64_t mv = ca * pv.q[c] + cb * pv.p[c];
-                fail = fail || mv >= HP_MAX_ENTRY;
-                if (!is_col) fail = fail || (uint64_t)ln.rs - pv.q[c] - pv.p[c] + mv >= HP_MAX_ROWSUM;
-            }
-            if (is_col) {   // the merged row's sum from rows P and Q without the split column
-                const uint64_t rq = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)Q) -
-                                    (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pv.lv, (int)Q);
-                const uint64_t rp = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)P) -
-                                    (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pv.lv, (int)P);
-                fail = fail || ca * rq + cb * rp >= HP_MAX_ROWSUM;
-            }
+        if (mine) {
+            pv.q[c] = COL ? M[Q * S + k] : M[k * S + Q];
+            pv.p[c] = COL ? M[P * S + k] : M[k * S + P];
+            const uint64_t mv = ca * pv.q[c] + cb * pv.p[c];
+            bool bad = mv >= HP_MAX_ENTRY;
+            if (!COL) bad = bad || (uint64_t)ln.rs - pv.q[c] - pv.p[c] + mv >= HP_MAX_ROWSUM;
+            fail = fail || (live && bad);
+        }
+        if (COL) {   // the merged row's sum from rows P and Q without the split column
+            const uint64_t rq = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)Q) -
+                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pv.lv, (int)Q);
+            const uint64_t rp = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)P) -
+                                (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pv.lv, (int)P);
+            fail = fail || (live && ca * rq + cb * rp >= HP_MAX_ROWSUM);
         }
     }
     if (__ballot(fail) != 0) return false;
-    pl.is_col = is_col;
+    pl.is_col = COL;
     pl.line = line;
     pl.np = np;
 #pragma unroll
@@ -575,7 +576,7 @@ __device__ __forceinline__ bool plan_split(const Region &rg, uint32_t AR, uint32
     if (record) {
         uint32_t *ctl = rg.lvl(u);
         if (lane == 0) {
-            const uint32_t pk = is_col | line << 1 | np << 6 | pos[0] << 8 | pos[1] << 13 | pos[2] << 18 | pos[3] << 23;
+            const uint32_t pk = (uint32_t)COL | line << 1 | np << 6 | pos[0] << 8 | pos[1] << 13 | pos[2] << 18 | pos[3] << 23;
             *(uint4 *)ctl = make_uint4(val[0], val[1], val[2], val[3]);
             *(uint4 *)(ctl + 4) = make_uint4(pk, AR, AC, 0u);
         }
@@ -585,19 +586,26 @@ __device__ __forceinline__ bool plan_split(const Region &rg, uint32_t AR, uint32
         }
         if (mine) {   // the lines the children overwrite: the pair's first line, per child
 #pragma unroll
-            for (int c = 0; c < 2; ++c)
-                if ((uint32_t)c < np) sv_line(rg, u, c)[k] = pos[2 * c] < pos[2 * c + 1] ? pv.p[c] : pv.q[c];
+            for (int c = 0; c < 2; ++c) sv_line(rg, u, c)[k] = pos[2 * c] < pos[2 * c + 1] ? pv.p[c] : pv.q[c];
         }
         wave_sync();
     }
     return true;
 }
 
+__device__ __forceinline__ bool plan_split(const Region &rg, uint32_t AR, uint32_t AC, uint32_t key, uint32_t nz,
+                                          const Lines &ln, int lane, Plan &pl, PairVals &pv, bool record, int u) {
+    const uint32_t s = key >> 6, line = key & 31;
+    return (key >> 5) & 1 ? plan_split_t<true>(rg, AR, AC, s, line, nz, ln, lane, pl, pv, record, u)
+                          : plan_split_t<false>(rg, AR, AC, s, line, nz, ln, lane, pl, pv, record, u);
+}
+
 // Child `ch` of the current node (plan pl; alive masks AR, AC and the lines ln updated): the
 // merged line over the pair's first line, the other line and the split line dead. With `pv`
 // the entries the plan read are used, else they are read from M.
-__device__ __forceinline__ void apply_child(const Region &rg, const Plan &pl, int ch, uint32_t &AR, uint32_t &AC,
-                                            Lines &ln, const PairVals *pv, int lane) {
+template <bool COL>
+__device__ __forceinline__ void apply_child_t(const Region &rg, const Plan &pl, int ch, uint32_t &AR, uint32_t &AC,
+                                              Lines &ln, const PairVals *pv, int lane) {
     const int S = rg.S;
     uint32_t *M = rg.M;
     const uint32_t line = pl.line;
@@ -606,7 +614,7 @@ __device__ __forceinline__ void apply_child(const Region &rg, const Plan &pl, in
     const uint32_t keep = min(P, Q), drop = max(P, Q);
     const uint32_t kb = 1u << keep, db = 1u << drop;
     const int k = lane & 31;
-    if (!pl.is_col) {   // row `line` deleted; columns P, Q merged into column keep
+    if (!COL) {   // row `line` deleted; columns P, Q merged into column keep
         const uint32_t AR2 = AR & ~(1u << line), AC2 = AC & ~db;
         const bool row = lane < 32 && ((AR2 >> k) & 1);
         uint32_t mv = 0;
@@ -616,13 +624,13 @@ __device__ __forceinline__ void apply_child(const Region &rg, const Plan &pl, in
             mv = ca * mq + cb * mp;
             ln.msk = (ln.msk & ~(kb | db)) | (mv ? kb : 0u);
             ln.rs = ln.rs - mq - mp + mv;
+            M[k * S + keep] = mv;   // each lane rewrites its own row: no other lane reads it here
         }
         const uint32_t newcol = (uint32_t)__ballot(row && mv != 0);
         if (lane >= 32 && ((AC2 >> k) & 1)) ln.msk = (uint32_t)k == keep ? newcol : ln.msk & ~(1u << line);
-        if (row) M[k * S + keep] = mv;   // each lane rewrites its own row: no other lane reads it here
         AR = AR2;
         AC = AC2;
-    } else {            // column `line` deleted; rows P, Q merged into row keep
+    } else {      // column `line` deleted; rows P, Q merged into row keep
         const uint32_t AR2 = AR & ~db, AC2 = AC & ~(1u << line);
         const uint32_t lv = pv ? pv->lv : (lane < 32 && ((AR >> k) & 1) ? M[k * S + line] : 0u);
         const uint32_t rq = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)Q) -
@@ -636,22 +644,24 @@ __device__ __forceinline__ void apply_child(const Region &rg, const Plan &pl, in
             const uint32_t mp = pv ? (ch ? pv->p[1] : pv->p[0]) : M[P * S + k];
             mv = ca * mq + cb * mp;
             ln.msk = (ln.msk & ~(kb | db)) | (mv ? kb : 0u);
+            M[keep * S + k] = mv;   // each lane rewrites its own column's entry
         }
         const uint32_t newrow = (uint32_t)(__ballot(col && mv != 0) >> 32);
         if (lane < 32 && ((AR2 >> k) & 1)) {
-            if ((uint32_t)k == keep) {
-                ln.msk = newrow;
-                ln.rs = ca * rq + cb * rp;
-            } else {
-                ln.msk &= ~(1u << line);
-                ln.rs -= lv;
-            }
+            const bool kp = (uint32_t)k == keep;
+            ln.msk = kp ? newrow : ln.msk & ~(1u << line);
+            ln.rs = kp ? ca * rq + cb * rp : ln.rs - lv;
         }
-        if (col) M[keep * S + k] = mv;   // each lane rewrites its own column's entry
         AR = AR2;
         AC = AC2;
     }
     wave_sync();
+}
+
+__device__ __forceinline__ void apply_child(const Region &rg, const Plan &pl, int ch, uint32_t &AR, uint32_t &AC,
+                                            Lines &ln, const PairVals *pv, int lane) {
+    if (pl.is_col) apply_child_t<true>(rg, pl, ch, AR, AC, ln, pv, lane);
+    else apply_child_t<false>(rg, pl, ch, AR, AC, ln, pv, lane);
 }
 
 // Back to the state of the split node at order u before child ch was applied: the line child
