@@ -436,6 +436,50 @@ def order_trials_study(hp, ctx, jobs, split=12, trial_set=(4, 8, 16, 32)):
     return out
 
 
+def regression_study(hp, W, ctx, jobs, split=12, sample=20000, seed=5):
+    """The regression of Section 3.1 (eqs. 4-6) on device-H_per times: T (the shader cycles of
+    a job's wave in a timed run of the device continuation) against P = per, |D| = |det|, S =
+    nonzeros, V1 and V2 = variances of the row and column sums; R^2 of the full model (Table
+    T1's figure), the factors stepwise selection keeps (F-to-enter 4.0, F-to-remove 3.9) and R^2
+    of T on P alone (eq. 6's form). Groups as in the paper: 100 random 0-1 matrices per (n, S)
+    (each one job, run whole on the device), and a sample of the n60 workload's order-20 jobs.
+    Factors constant within a group are left out (S of the n60 jobs varies; of a group, never)."""
+    import numpy as np
+    names = ["P", "|D|", "S", "V1", "V2"]
+
+    def analyse(T, P, inv):
+        X = np.column_stack([P, inv])
+        cols = [i for i in range(5) if np.ptp(X[:, i]) > 0]
+        _, r2 = hp.ols(X[:, cols], T)
+        chosen = [names[cols[c]] for c in hp.stepwise(X[:, cols], T)]
+        _, r2p = hp.ols(P[:, None], T)
+        return {"jobs": int(T.size), "r2_all_factors": r2, "stepwise_keeps": chosen, "r2_P_only": r2p,
+                "factors_left_out_as_constant": [names[i] for i in range(5) if i not in cols]}
+
+    out = {"split_order": split, "groups": {}}
+    ctx.set_opts(split_order=split, time_jobs=1)
+    try:
+        for n, mult in ((20, 4), (20, 5), (20, 6), (24, 4), (24, 5)):
+            mats = [W.random_01_matrix(n, mult * n, 100000 * n + 1000 * mult + s) for s in range(100)]
+            J = ctx.jobs_from_dense(mats)
+            arith = J.describe()["arith"]
+            _, per_job, _ = ctx.run(J, "natural", True, per_job=True)
+            T = J.cycles().astype(np.float64)
+            sel = [k for k in range(len(mats)) if arith[k] == 1 and per_job[k] > 0]   # device H_per jobs
+            inv = np.array([hp.matrix_invariants(mats[k]) for k in sel])
+            out["groups"][f"n{n}_S{mult}n"] = analyse(T[sel], np.array([float(per_job[k]) for k in sel]), inv)
+        _, per_job, _ = ctx.run(jobs, "natural", True, per_job=True)
+        T = jobs.cycles().astype(np.float64)
+        rng = np.random.default_rng(seed)
+        pick = np.sort(rng.choice(T.size, size=min(sample, T.size), replace=False))
+        pick = [int(k) for k in pick if T[k] > 0]
+        inv = np.array([hp.matrix_invariants(jobs.matrix(k)) for k in pick])
+        out["groups"]["n60_order20_jobs_sample"] = analyse(T[pick], np.array([float(per_job[k]) for k in pick]), inv)
+    finally:
+        ctx.set_opts(split_order=0, time_jobs=0)
+    return out
+
+
 def copy_probe(nbytes: int = 256 << 20, reps: int = 3):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -626,6 +670,8 @@ def main():
     extra["device_hper_n60"] = device_hper(hp, ctx, jobs, tot, mats, golden_vals, keys)
     log("estimate budget and queue order on the device continuation of H_per")
     extra["order_trials_study_n60"] = order_trials_study(hp, ctx, jobs)
+    log("regression study (Section 3.1)")
+    extra["regression_study"] = regression_study(hp, W, ctx, jobs)
     plain = None
     if not args.no_plain:
         log("plain: one launch per job, expansion order (best lane chunk of 3, 5, 7)")

@@ -101,8 +101,9 @@ typedef struct hperm_opts {
                              of order T, which the device continuation of H_per finishes; the
                              whole tree stays on the GPU in bounded memory; problems of one
                              order share one expansion (their results then report the group's
-                             job and subset-term counts and times). Other problems (and the
-                             serving loop) take the host path. Results are the same integers.
+                             job and subset-term counts and times). Other problems take the
+                             host path; the serving loop sends requests above order T to its
+                             device lane (hperm_serve_start). Results are the same integers.
                              0 (or T <= split order): off. */
     int32_t device_expand_mib; /* device memory for the expansion's level buffers in MiB
                              (0 = 8192); more memory means fewer, larger launches */
@@ -374,6 +375,29 @@ hperm_status hperm_list_schedule(int32_t n, const uint64_t *times, const int32_t
  * arrays, NaN, or every pair tied in x or in y). */
 hperm_status hperm_kendall_tau(int32_t n, const double *x, const double *y, double *tau,
                                double *z, double *p);
+
+/* The regression of Section 3.1 (eqs. 4-6): the time T of a sub-matrix against five of its
+ * invariants, T = a0 + a1 P + a2 |D| + a3 S + a4 V1 + a5 V2.
+ *
+ * hperm_matrix_invariants: of the dense m x m matrix a (row-major, caller's host memory,
+ * 1 <= m <= 128) out[0] = |det(a)| (partial-pivot elimination in long double: a float value),
+ * out[1] = S, the number of nonzeros, out[2] = V1 and out[3] = V2, the population variances of
+ * its row sums and of its column sums.
+ *
+ * hperm_ols: least squares of y[n] on the k columns of X (row-major n x k) with an intercept;
+ * coef[k + 1] receives a0, a1..ak and *r2 the coefficient of determination as the paper
+ * defines it, sum (yhat - ybar)^2 / sum (y - ybar)^2. HPERM_E_INVALID for NULL arrays,
+ * non-finite values, n < k + 2, a constant or linearly dependent column.
+ *
+ * hperm_stepwise: Efroymson's stepwise selection on the same data: from the intercept alone,
+ * the column with the largest partial F enters while that F exceeds f_enter; after each entry
+ * the model column with the smallest partial F leaves while that F is below f_remove
+ * (0 <= f_remove <= f_enter; 4.0 and 3.9 are the usual values). chosen[k] receives the chosen
+ * columns in entry order, *n_chosen their number. */
+hperm_status hperm_matrix_invariants(int32_t m, const uint32_t *a, double *out);
+hperm_status hperm_ols(int32_t n, int32_t k, const double *X, const double *y, double *coef, double *r2);
+hperm_status hperm_stepwise(int32_t n, int32_t k, const double *X, const double *y, double f_enter,
+                            double f_remove, int32_t *chosen, int32_t *n_chosen);
 
 /* ---- serving ------------------------------------------------------------------------ */
 

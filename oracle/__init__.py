@@ -18,14 +18,19 @@ ryser_c.c      plain Ryser in C with 128-bit wrap-around integers, threaded over
 schedule.py    the scheduling study (Sections 3.2-3.3): list scheduling to the least-loaded
                processor (Step 3 of Algorithm PH), brute-force optimal makespans, and
                Kendall's tau with the paper's tie correction.
+regression.py  the regression of Section 3.1 (eqs. 4-6): exact |det| by fraction-free
+               elimination, the five matrix invariants, least squares with the printed R^2,
+               and stepwise selection.
 """
 from .permanent import (per_brute, per_ryser, nw_doubled_sum, per_nw, e2_children, expand_leaves,
                         choose_line, per_hybrid, per_dp, per_auto)
 from .kkl import splitmix64, kkl_exponent, kkl_trial, kkl_key
 from .schedule import list_schedule, efficiency, kendall_tau, opt_makespan_brute
+from .regression import determinant_abs, invariants, ols, r_squared, stepwise
 
 __all__ = [
     "per_brute", "per_ryser", "nw_doubled_sum", "per_nw", "e2_children", "expand_leaves", "choose_line",
     "per_hybrid", "per_dp", "per_auto", "splitmix64", "kkl_exponent", "kkl_trial", "kkl_key",
     "list_schedule", "efficiency", "kendall_tau", "opt_makespan_brute",
+    "determinant_abs", "invariants", "ols", "r_squared", "stepwise",
 ]

@@ -134,6 +134,9 @@ _SIGS = {
     "hperm_tree_estimate": [ctypes.POINTER(Opts), _I32, _P, _P, _P, _I32, _U64, _P, _P],
     "hperm_autotune": [_P, _P, ctypes.c_char_p, _I32, ctypes.POINTER(TuneEntry), _I32, ctypes.POINTER(_I32)],
     "hperm_tune_clear": [_P],
+    "hperm_matrix_invariants": [_I32, _P, _P],
+    "hperm_ols": [_I32, _I32, _P, _P, _P, ctypes.POINTER(ctypes.c_double)],
+    "hperm_stepwise": [_I32, _I32, _P, _P, ctypes.c_double, ctypes.c_double, _P, ctypes.POINTER(_I32)],
     "hperm_kendall_tau": [_I32, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                           ctypes.POINTER(ctypes.c_double)],
 }
@@ -553,6 +556,45 @@ def kendall_tau(x, y) -> tuple[float, float, float]:
     if st != OK:
         raise HpermError(st, "kendall_tau")
     return tau.value, z.value, p.value
+
+
+def matrix_invariants(A) -> tuple[float, int, float, float]:
+    """(|D|, S, V1, V2) of a dense non-negative integer matrix: |det| (a float), the nonzero
+    count and the population variances of the row and column sums (Section 3.1)."""
+    a = np.ascontiguousarray(A, dtype=np.uint32)
+    if a.ndim != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("A must be square")
+    out = np.zeros(4, np.float64)
+    st = _lib.hperm_matrix_invariants(int(a.shape[0]), _ptr(a), _ptr(out))
+    if st != OK:
+        raise HpermError(st, "matrix_invariants")
+    return float(out[0]), int(out[1]), float(out[2]), float(out[3])
+
+
+def ols(X, y) -> tuple[np.ndarray, float]:
+    """Least squares of y on the columns of X with an intercept: (a0..ak, R^2 as the paper
+    defines it)."""
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    Xa = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(yy.size, -1))
+    coef = np.zeros(Xa.shape[1] + 1, np.float64)
+    r2 = ctypes.c_double()
+    st = _lib.hperm_ols(int(yy.size), int(Xa.shape[1]), _ptr(Xa), _ptr(yy), _ptr(coef), ctypes.byref(r2))
+    if st != OK:
+        raise HpermError(st, "ols")
+    return coef, r2.value
+
+
+def stepwise(X, y, f_enter: float = 4.0, f_remove: float = 3.9) -> list[int]:
+    """Efroymson's stepwise selection: the chosen columns of X in entry order."""
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    Xa = np.ascontiguousarray(np.asarray(X, dtype=np.float64).reshape(yy.size, -1))
+    chosen = np.zeros(Xa.shape[1], np.int32)
+    nc = _I32()
+    st = _lib.hperm_stepwise(int(yy.size), int(Xa.shape[1]), _ptr(Xa), _ptr(yy), float(f_enter), float(f_remove),
+                             _ptr(chosen), ctypes.byref(nc))
+    if st != OK:
+        raise HpermError(st, "stepwise")
+    return [int(c) for c in chosen[:nc.value]]
 
 
 def polynomial_interpolate(values, alternate: bool = False) -> list[int]:

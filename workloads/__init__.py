@@ -178,6 +178,15 @@ def random_sparse_int_matrix(n: int, density_per_row: int, seed: int, lo: int = 
     return A
 
 
+def random_01_matrix(n: int, nnz: int, seed: int) -> np.ndarray:
+    """n x n 0-1 matrix with ``nnz`` ones at uniformly random distinct positions (the random
+    matrices of a given size and sparsity of the regression study; zero lines allowed)."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros(n * n, dtype=np.uint32)
+    A[rng.choice(n * n, size=min(nnz, n * n), replace=False)] = 1
+    return A.reshape(n, n)
+
+
 def to_csr(A: np.ndarray) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
     """(row_ptr int32[n+1], col_idx int32[nnz], val uint32[nnz]) with sorted columns per row."""
     A = np.asarray(A)
