@@ -461,13 +461,13 @@ def regression_study(hp, W, ctx, jobs, split=12, sample=20000, seed=5):
     try:
         for n, mult in ((20, 4), (20, 5), (20, 6), (24, 4), (24, 5)):
             mats = [W.random_01_matrix(n, mult * n, 100000 * n + 1000 * mult + s) for s in range(100)]
-            J = ctx.jobs_from_dense(mats)
-            arith = J.describe()["arith"]
+            J = ctx.jobs_from_dense(mats)   # a matrix with an empty line gives no job
+            d = J.describe()
             _, per_job, _ = ctx.run(J, "natural", True, per_job=True)
             T = J.cycles().astype(np.float64)
-            sel = [k for k in range(len(mats)) if arith[k] == 1 and per_job[k] > 0]   # device H_per jobs
-            inv = np.array([hp.matrix_invariants(mats[k]) for k in sel])
-            out["groups"][f"n{n}_S{mult}n"] = analyse(T[sel], np.array([float(per_job[k]) for k in sel]), inv)
+            sel = [j for j in range(len(per_job)) if d["arith"][j] == 1 and per_job[j] > 0]   # device H_per jobs
+            inv = np.array([hp.matrix_invariants(mats[int(d["problem"][j])]) for j in sel])
+            out["groups"][f"n{n}_S{mult}n"] = analyse(T[sel], np.array([float(per_job[j]) for j in sel]), inv)
         _, per_job, _ = ctx.run(jobs, "natural", True, per_job=True)
         T = jobs.cycles().astype(np.float64)
         rng = np.random.default_rng(seed)

@@ -255,7 +255,9 @@ hperm_status hperm_expand_batch_csr(hperm_ctx *ctx, int32_t count, const int32_t
                                     const uint32_t *val, hperm_jobs **out);
 
 /* Jobs given directly: count dense row-major matrices, matrix k of order m[k] (1..40) at
- * a + off[k]; each job is evaluated by R-NW as it is (no expansion), as problem k. */
+ * a + off[k]; each job is evaluated by R-NW as it is (no expansion), as problem k. A matrix
+ * with an empty line (per = 0) gives no job: its problem's total is 0 and the job indices skip
+ * it (hperm_jobs_describe maps every job to its problem). */
 hperm_status hperm_jobs_from_dense(hperm_ctx *ctx, int32_t count, const int32_t *m,
                                    const int64_t *off, const uint32_t *a, hperm_jobs **out);
 
