@@ -417,19 +417,23 @@ __device__ __forceinline__ void write_children(const uint32_t *node, uint32_t ke
                     if (j == pr.P) ap = w >> 8;
                     if (j == pr.Q) aq = w >> 8;
                 }
-                const uint32_t mv = (uint32_t)((uint64_t)pr.ca * aq + (uint64_t)pr.cb * ap);
+                // presence from the full 64-bit value, as in the row lengths of the plan above:
+                // an out-of-range value (flagged) is stored truncated but never changes the
+                // node's shape
+                const uint64_t mv64 = (uint64_t)pr.ca * aq + (uint64_t)pr.cb * ap;
+                const uint32_t mv = (uint32_t)mv64;
                 bool merged = false;
                 uint32_t q = 0;
                 for (uint32_t e = 0; e < r.len[h]; ++e) {
                     const uint32_t w = ent[r.start[h] + e], j = w & 0xffu;
                     if (j == pr.P || j == pr.Q) continue;
                     if (!merged && j > keep) {
-                        if (mv) dst[q++] = (mv << 8) | keep;
+                        if (mv64) dst[q++] = (mv << 8) | keep;
                         merged = true;
                     }
                     dst[q++] = (w & ~0xffu) | (j - (j > drop));
                 }
-                if (!merged && mv) dst[q++] = (mv << 8) | keep;
+                if (!merged && mv64) dst[q++] = (mv << 8) | keep;
             } else if (i != keep) {
                 uint32_t q = 0;
                 for (uint32_t e = 0; e < r.len[h]; ++e) {

@@ -131,6 +131,9 @@ struct DexpRun {
             r = hip(hipStreamSynchronize(s), "device H_per");
             if (r) return r;
             st.split_s += now_s() - t0;
+            // the expansion's range flag (set by any write kernel of the levels above): checked
+            // here, at the first synchronisation after those writes, before any value is used
+            if (h.flags & 1) return fail(HPERM_E_RANGE, "an expanded entry reached 2^22 or a row sum 2^24");
             if (h.stats[6]) return fail(HPERM_E_INTERNAL, "device H_per: a leaf value failed its integrity check");
             if (!h.stats[5]) break;
             // the record buffer overflowed: the launch's sum is dropped and the launch repeated
@@ -222,16 +225,13 @@ struct DexpRun {
                     st.nodes += kids;
                     st.max_level_nodes = std::max<uint64_t>(st.max_level_nodes, kids);
                     if (kids) {
+                        // the write's range flag is read at the next synchronisation (the
+                        // continuation's results, or the end of the expansion): an entry out of
+                        // range changes values only, never the tree's shape or its addresses
                         r = hip(launch_dexp_write(level(o), offs(o), k, (uint32_t)chunk, P.keys, P.place,
                                                   level(o - 1), offs(o - 1), &P.misc->flags, s),
                                 "expansion write");
                         if (r) return r;
-                        r = hip(hipMemcpyAsync(tot, &P.misc->flags, 8, hipMemcpyDeviceToHost, s),
-                                "download expansion flags");
-                        if (r) return r;
-                        r = hip(hipStreamSynchronize(s), "expansion write");
-                        if (r) return r;
-                        if (tot[0] & 1) return fail(HPERM_E_RANGE, "an expanded entry reached 2^22 or a row sum 2^24");
                         // chunks of the next level are sized by the average room its nodes were
                         // given (the parent's words); a plan that outgrows a buffer halves them
                         P.maxw[o - 1 - P.T] = (uint32_t)((words + kids - 1) / kids);
@@ -350,6 +350,12 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int 
                     "upload root offsets");
     if (!s) s = run.hip(launch_fill_u64(&P.misc->grand, 3, 0ull, c->stream), "clear flags");
     if (!s) s = run.process(n, 0, live.size());
+    if (!s) {   // the range flag of writes after the last continuation launch
+        unsigned long long flags = 0;
+        s = run.hip(hipMemcpyAsync(&flags, &P.misc->flags, 8, hipMemcpyDeviceToHost, c->stream), "download flags");
+        if (!s) s = run.hip(hipStreamSynchronize(c->stream), "device expansion");
+        if (!s && (flags & 1)) s = run.fail(HPERM_E_RANGE, "an expanded entry reached 2^22 or a row sum 2^24");
+    }
     run.st.total_s = now_s() - t0;
     if (s) return set_error(c, s, run.err);
     if (sample) sample->complete = !run.stopped;
