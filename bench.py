@@ -192,6 +192,38 @@ def uneven_orders(hp, W, ctx, n_jobs: int = 600, seed: int = 11):
     return out
 
 
+def expansion_uneven(hp, W, ctx, mats, want, restore_m_cut, m_cut=12, m_cap=24, s_leaf=3):
+    """Queue orders on jobs of uneven order as the expansion produces them: the benchmark's 17
+    graphs expanded with H_per's stop rule at s_leaf = 3 (a node whose lines all hold three or
+    more nonzeros becomes a job once its order is at most m_cap; others are split down to
+    m_cut), which leaves jobs of orders m_cut..m_cap in two rings. Persistent R-NW milliseconds
+    in the paper's three orders (natural, exact cost, the estimate) and random; totals checked
+    against the oracle's values; the scheduling study on the same jobs."""
+    import numpy as np
+    ctx.set_opts(m_cut=m_cut, m_cap=m_cap, s_leaf=s_leaf, split_order=0)
+    try:
+        J = ctx.expand(mats)
+        keys = ctx.estimate(J, 32, 1)
+        out = {"m_cut": m_cut, "m_cap": m_cap, "s_leaf": s_leaf}
+        for order in ("estimate", "exact_cost", "natural", "random"):
+            ms = []
+            for _ in range(3):
+                tot, _, _ = ctx.run(J, order, True)
+                assert want is None or tot == want
+                ms.append(sum(L["ms"] for L in ctx.last_launches()))
+            out[order + "_ms"] = sorted(ms)[1]
+        d = J.describe()
+        vals, cnt = np.unique(d["m"], return_counts=True)
+        out["jobs"] = int(d["m"].size)
+        out["jobs_by_order"] = {int(v): int(c) for v, c in zip(vals, cnt)}
+        out["jobs_by_ring"] = {name: int((d["arith"] == k).sum()) for k, name in ((1, "mod 2^64"), (2, "mod 2^128"), (3, "residues"))}
+        out["subset_terms"] = int(d["terms"].astype(np.float64).sum())
+        out["schedule_study"] = schedule_study(hp, ctx, J, keys)
+    finally:   # the benchmark context's options (library defaults for m_cap and s_leaf)
+        ctx.set_opts(m_cut=restore_m_cut, m_cap=36, s_leaf=5, split_order=0)
+    return out
+
+
 def autotune_leg(hp, W, ctx, jobs, trials, want):
     """The autotuner on the benchmark's jobs and on the 600 uneven jobs: its table, and the R-NW
     milliseconds of the whole persistent run (estimate order, median of 3) with the defaults and
@@ -627,6 +659,8 @@ def main():
         ctx.run(jobs, order, True)
         extra[f"persistent_{order}_rnw_ms"] = sum(L["ms"] for L in ctx.last_launches())
     extra["uneven_jobs"] = uneven_orders(hp, W, ctx)
+    log("queue orders on jobs of uneven order from the expansion (s_leaf 3)")
+    extra["expansion_uneven_n60"] = expansion_uneven(hp, W, ctx, mats, vals, args.m_cut)
     extra["autotune"] = autotune_leg(hp, W, ctx, jobs, args.trials, tot)
     extra["hip_graphs"] = graph_leg(hp, W)
     # one problem alone: the truncated icosahedron (C60), median of 5 after a warm-up, on the
