@@ -13,7 +13,8 @@ matches the kernel source), the CPU oracle timed on a bounded sample, and a serv
 (continuous batching of mixed requests: capacity, then Poisson arrivals with p50/p99 latency).
 
     python bench.py [--steps K] [--warmup W] [--m-cut 20] [--no-cpu-baseline] [--no-plain]
-                    [--no-serving] [--copy-probe]
+                    [--no-serving] [--no-large] [--large-only c100|all] [--profile-split]
+                    [--copy-probe]
 """
 import argparse
 import hashlib
@@ -512,6 +513,43 @@ def regression_study(hp, W, ctx, jobs, split=12, sample=20000, seed=5):
     return out
 
 
+def split_profile_run():
+    """A short fixed sequence for profiling the device continuation of H_per: the n60
+    workload's order-20 host jobs at t = 12 five times (natural order), one timed run, then the
+    per(A) batch on the default path (device expansion to 22, continuation to 12) six times;
+    every total is checked against the oracle's stored values."""
+    import torch
+    import paper_1112_6072_amd as hp
+    import workloads as W
+    items = W.config_n60(16)
+    mats = [A for _, A in items]
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "oracle_values.json")))
+    want = [int(golden[n]) for n, _ in items]
+    ctx = hp.Context({"split_order": 12, "device_expand": 0})
+    out = {}
+    try:
+        J = ctx.expand(mats)
+        ms = []
+        for _ in range(5):
+            tot, _, _ = ctx.run(J, "natural", True)
+            assert tot == want, "totals"
+            ms.append([L for L in ctx.last_launches() if L["variant"] == 3][0]["ms"])
+        out["split_ms_n60_t12"] = sorted(ms)[2]
+        ctx.set_opts(time_jobs=1)
+        ctx.run(J, "natural", True)
+        ctx.set_opts(time_jobs=0, device_expand=22)
+        walls = []
+        for _ in range(6):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            assert ctx.permanent_batch(mats) == want, "per(A)"
+            walls.append(time.perf_counter() - t0)
+        out["per_a_default_ms"] = sorted(walls[1:])[2] * 1e3
+    finally:
+        ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def copy_probe(nbytes: int = 256 << 20, reps: int = 3):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -536,10 +574,15 @@ def main():
     ap.add_argument("--large-only", choices=["c100", "all"], default=None,
                     help="only run the large single problems (C100, or C100 and random cubic n=100) and "
                          "print their record (for profiling)")
+    ap.add_argument("--profile-split", action="store_true",
+                    help="only the short fixed sequence used to profile the device continuation of H_per")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device-to-device copy of 256 MiB three times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
+    if args.profile_split:
+        split_profile_run()
+        return
     if args.copy_probe:
         copy_probe()
         return
