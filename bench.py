@@ -193,7 +193,7 @@ def uneven_orders(hp, W, ctx, n_jobs: int = 600, seed: int = 11):
     return out
 
 
-def expansion_uneven(hp, W, ctx, mats, want, restore_m_cut, m_cut=12, m_cap=24, s_leaf=3):
+def expansion_uneven(hp, W, ctx, mats, want, restore_m_cut, plain=True, m_cut=12, m_cap=24, s_leaf=3):
     """Queue orders on jobs of uneven order as the expansion produces them: the benchmark's 17
     graphs expanded with H_per's stop rule at s_leaf = 3 (a node whose lines all hold three or
     more nonzeros becomes a job once its order is at most m_cap; others are split down to
@@ -213,6 +213,11 @@ def expansion_uneven(hp, W, ctx, mats, want, restore_m_cut, m_cut=12, m_cap=24, 
                 assert want is None or tot == want
                 ms.append(sum(L["ms"] for L in ctx.last_launches()))
             out[order + "_ms"] = sorted(ms)[1]
+        if plain:   # one launch per job in expansion order: the unbatched comparator
+            tot, _, _ = ctx.run(J, "natural", False)
+            assert want is None or tot == want
+            out["plain_one_launch_per_job_ms"] = ctx.last_launches()[0]["ms"]
+            out["lpt_vs_plain"] = out["plain_one_launch_per_job_ms"] / out["estimate_ms"]
         d = J.describe()
         vals, cnt = np.unique(d["m"], return_counts=True)
         out["jobs"] = int(d["m"].size)
@@ -550,6 +555,32 @@ def split_profile_run():
     print(json.dumps(out), flush=True)
 
 
+def n80_batch(hp, W, golden):
+    """The batched configuration's eight cubic girth >= 5 graphs on 80 vertices, per(A) of the
+    batch on the library's default path (median of 3 calls), checked against the oracle's
+    stored values."""
+    import torch
+    items = W.config_n80(8)
+    mats = [A for _, A in items]
+    ctx = hp.Context({"device_expand_mib": 16384})
+    try:
+        walls, got, st = [], None, None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            got, st = ctx.permanent_batch(mats, with_stats=True)
+            walls.append(time.perf_counter() - t0)
+        dev = [L for L in ctx.last_launches() if L["variant"] == 4]
+    finally:
+        ctx.close()
+    return {"graphs": len(mats), "per_a_wall_ms_batch": sorted(walls)[1] * 1e3,
+            "verified_vs_oracle": bool(golden) and got == [int(golden[n]) for n, _ in items],
+            "jobs_order22": int(sum(L["n_jobs"] for L in dev)), "expansion_nodes": int(sum(L["items"] for L in dev)),
+            "device_hper_launches": int(sum(L["row_updates"] for L in dev)),
+            "note": "the host path at m_cut 20 expands this batch into 27.4 M jobs of order 20 "
+                    "(1.3e13 subset-terms; its R-NW alone took 10.8 s)"}
+
+
 def copy_probe(nbytes: int = 256 << 20, reps: int = 3):
     import torch
     src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
@@ -703,7 +734,7 @@ def main():
         extra[f"persistent_{order}_rnw_ms"] = sum(L["ms"] for L in ctx.last_launches())
     extra["uneven_jobs"] = uneven_orders(hp, W, ctx)
     log("queue orders on jobs of uneven order from the expansion (s_leaf 3)")
-    extra["expansion_uneven_n60"] = expansion_uneven(hp, W, ctx, mats, vals, args.m_cut)
+    extra["expansion_uneven_n60"] = expansion_uneven(hp, W, ctx, mats, vals, args.m_cut, plain=not args.no_plain)
     extra["autotune"] = autotune_leg(hp, W, ctx, jobs, args.trials, tot)
     extra["hip_graphs"] = graph_leg(hp, W)
     # one problem alone: the truncated icosahedron (C60), median of 5 after a warm-up, on the
@@ -749,6 +780,8 @@ def main():
     extra["order_trials_study_n60"] = order_trials_study(hp, ctx, jobs)
     log("regression study (Section 3.1)")
     extra["regression_study"] = regression_study(hp, W, ctx, jobs)
+    log("the n80 batch (8 cubic graphs on 80 vertices) on the default path")
+    extra["n80_batch"] = n80_batch(hp, W, golden)
     plain = None
     if not args.no_plain:
         log("plain: one launch per job, expansion order (best lane chunk of 3, 5, 7)")
