@@ -171,3 +171,36 @@ def test_serving_device_lane_and_work_limit(hperm):
     assert [v for v, _ in got] == want
     lanes = [st["max_m"] for _, st in got]
     assert 22 in lanes and any(m != 22 for m in lanes)
+
+
+def test_serving_large_requests_equal_oracle(hperm):
+    """The benchmark's graphs as serving requests at full size: the 17 cubic graphs on 60
+    vertices and the 8 on 80 vertices (the device lane), interleaved with small requests (the
+    batch path), all in flight together; every result equals the oracle's stored value (and the
+    small ones the C oracle)."""
+    import json
+    import os
+    golden = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                         "oracle_values.json")))
+    big = W.config_n60(16) + W.config_n80(8)
+    small = stream(12, 23)
+    want_small = native.hper_batch(small, threads=8)
+    say("serving large requests", len(big), "small", len(small))
+    c = hperm.Context({"split_order": 12, "device_expand": 22, "device_expand_mib": 4096})
+    try:
+        c.serve_start(64, 256 << 20)
+        tickets = []
+        for k, (_, A) in enumerate(big):
+            tickets.append(c.submit(A))
+            if k < len(small):
+                tickets.append(c.submit(small[k]))
+        got = [c.wait(t, 300.0)[0] for t in tickets]
+        c.serve_stop()
+    finally:
+        c.close()
+    want = []
+    for k, (name, _) in enumerate(big):
+        want.append(int(golden[name]))
+        if k < len(small):
+            want.append(want_small[k])
+    assert got == want
