@@ -211,6 +211,23 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *ctx, int32_t count, const int3
                                        const int32_t *row_ptr, const int32_t *col_idx,
                                        const uint32_t *val, hperm_result *out);
 
+/* per(A_k) modulo a prime for a batch of problems (layout as hperm_permanent_batch_csr), by the
+ * device path in modular arithmetic: the expansion (2) of Algorithm H_per on the device with
+ * every merged entry reduced modulo the prime, the device continuation of H_per, each leaf's
+ * Nijenhuis-Wilf sum taken modulo the prime and normalised by the inverse of 2^(p-1), sums of
+ * residues. Entries are reduced on entry, so no bound applies: the residues of values of any
+ * size, for exact reconstruction by the Chinese remainder theorem over several primes (the
+ * permanental polynomial beyond 2^180). prime: an odd prime below 2^18 (so every row sum of a
+ * node of order <= 64 stays below 2^24). Every n[k] must exceed the device expansion's order
+ * (opts.device_expand, 22 when off) and be at most 64; opts.split_order (12 when off) is the
+ * continuation's target. residues[count] (caller-owned) receives per(A_k) mod prime.
+ * Errors: HPERM_E_INVALID (bad arrays, orders, a modulus that is not an odd prime below 2^18,
+ * or the context is serving), HPERM_E_NOMEM, HPERM_E_DEVICE, HPERM_E_INTERNAL. */
+hperm_status hperm_permanent_mod_batch_csr(hperm_ctx *ctx, int32_t count, const int32_t *n,
+                                           const int64_t *rp_off, const int64_t *nz_off,
+                                           const int32_t *row_ptr, const int32_t *col_idx,
+                                           const uint32_t *val, uint32_t prime, uint64_t *residues);
+
 /* One signed integer coefficient: |c| = sum_k limb[k] * 2^(64k), negative when c < 0. */
 typedef struct hperm_coeff {
     uint64_t limb[8];
@@ -223,11 +240,14 @@ typedef struct hperm_coeff {
  * hperm_permanent_csr). Computed from per(xI + A) at x = 0..n, n + 1 problems of one batched
  * pass (xI + A has non-negative entries; per(xI + A) = sum_k a_k x^k with a_k the sum of the
  * permanents of the principal sub-matrices of order n - k, and c_k = (-1)^(n-k) a_k), then
- * exact integer interpolation on the host. For n <= 40 the evaluations run with m_cut raised
- * to n (each xI + A is one R-NW job: no expansion, whose merges would multiply the large
- * diagonal entries); the context's options are restored afterwards. coeffs[n + 1] is
- * caller-owned. The bound of per(nI + A) must stay below 2^180 (e.g. cubic graphs up to
- * n = 34). Must not be called while serving or concurrently with other calls on the context.
+ * exact integer interpolation on the host. When the bound of per(nI + A) stays below 2^180 the
+ * evaluations are exact integers, with m_cut raised to n for n <= 40 (each xI + A is one R-NW
+ * job: no expansion, whose merges would multiply the large diagonal entries). Beyond that bound,
+ * for device-expansion orders 23..64, each evaluation is taken modulo K + 1 primes below 2^18
+ * (hperm_permanent_mod_batch_csr), where K primes cover the bound, reconstructed by the
+ * Chinese remainder theorem over K of them and checked against the last one (e.g. C60: 22
+ * primes). The context's options are restored afterwards. coeffs[n + 1] is caller-owned.
+ * Must not be called while serving or concurrently with other calls on the context.
  * Errors: as for
  * hperm_permanent_batch_csr; HPERM_E_RANGE when a bound or an intermediate exceeds the
  * supported range; HPERM_E_INTERNAL when the interpolation fails its exactness checks. */

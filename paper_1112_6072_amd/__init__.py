@@ -111,6 +111,7 @@ _SIGS = {
     "hperm_permanent_dense": [_P, _I32, _P, ctypes.POINTER(Result)],
     "hperm_permanent_dense_noalloc": [_P, _I32, _P, ctypes.POINTER(Result)],
     "hperm_permanent_batch_csr": [_P, _I32, _P, _P, _P, _P, _P, _P, _P],
+    "hperm_permanent_mod_batch_csr": [_P, _I32, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P],
     "hperm_expand_batch_csr": [_P, _I32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)],
     "hperm_jobs_from_dense": [_P, _I32, _P, _P, _P, ctypes.POINTER(_P)],
     "hperm_jobs_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)],
@@ -342,6 +343,16 @@ class Context:
         if with_stats:
             return vals, [out[k].stats() for k in range(len(mats))]
         return vals
+
+    def permanent_mod_batch(self, mats, prime: int) -> list[int]:
+        """per(A) mod prime for each matrix (odd prime below 2^18, orders above the device
+        expansion's order up to 64), on the device path in modular arithmetic."""
+        n, rp_off, nz_off, rp, ci, va = _batch_csr(mats)
+        out = np.zeros(max(len(mats), 1), np.uint64)
+        st = _lib.hperm_permanent_mod_batch_csr(self.handle, len(mats), _ptr(n), _ptr(rp_off), _ptr(nz_off),
+                                                _ptr(rp), _ptr(ci), _ptr(va), int(prime), _ptr(out))
+        self._check(st, "permanent_mod_batch")
+        return [int(out[k]) for k in range(len(mats))]
 
     def permanent_dense(self, A) -> int:
         """per(A) through hperm_permanent_dense (expansion as the options say)."""

@@ -1277,6 +1277,52 @@ static hperm_status batch_host_path(hperm_ctx *c, int32_t count, const int32_t *
     return HPERM_OK;
 }
 
+hperm_status hperm_permanent_mod_batch_csr(hperm_ctx *c, int32_t count, const int32_t *n, const int64_t *rp_off,
+                                           const int64_t *nz_off, const int32_t *row_ptr, const int32_t *col_idx,
+                                           const uint32_t *val, uint32_t prime, uint64_t *residues) {
+    if (c && c->host_only) return set_error(c, HPERM_E_DEVICE, "host-only context");
+    if (!c || !residues) return HPERM_E_INVALID;
+    if (c->serving) return set_error(c, HPERM_E_INVALID, "the context is serving");
+    if (count < 0 || (count > 0 && (!n || !rp_off || !nz_off))) return set_error(c, HPERM_E_INVALID, "bad batch arrays");
+    if (prime < 3 || prime >= (1u << 18) || !(prime & 1u)) return set_error(c, HPERM_E_INVALID, "an odd prime below 2^18");
+    for (uint32_t d = 3; d * d <= prime; d += 2)
+        if (prime % d == 0) return set_error(c, HPERM_E_INVALID, "the modulus must be prime");
+    std::lock_guard<std::mutex> lk(c->call_mu);
+    c->dev.last_error.clear();
+    c->dev.opts = c->opts;
+    c->dev.launches.clear();
+    const int T = device_in_effect(c->opts) ? device_in_effect(c->opts) : 22;
+    const int t = split_in_effect(c->opts) ? split_in_effect(c->opts) : 12;
+    for (int k = 0; k < count; ++k) {
+        CsrView v{n[k], row_ptr ? row_ptr + rp_off[k] : nullptr, col_idx ? col_idx + nz_off[k] : nullptr,
+                  val ? val + nz_off[k] : nullptr};
+        const std::string why = validate_csr(v);
+        if (!why.empty()) return set_error(c, HPERM_E_INVALID, "problem " + std::to_string(k) + ": " + why);
+        if (n[k] <= T || n[k] > 64)
+            return set_error(c, HPERM_E_INVALID, "modular evaluation: orders above the device expansion's, up to 64");
+    }
+    const size_t budget = (size_t)(c->opts.device_expand_mib > 0 ? c->opts.device_expand_mib : 8192) << 20;
+    std::vector<int> order_of((size_t)count);
+    for (int k = 0; k < count; ++k) order_of[(size_t)k] = k;
+    std::stable_sort(order_of.begin(), order_of.end(), [&](int x, int y) { return n[x] < n[y]; });
+    for (size_t g0 = 0; g0 < order_of.size();) {   // problems of one order share one expansion
+        size_t g1 = g0;
+        while (g1 < order_of.size() && n[order_of[g1]] == n[order_of[g0]]) ++g1;
+        std::vector<CsrView> grp;
+        for (size_t q = g0; q < g1; ++q) {
+            const int k = order_of[q];
+            grp.push_back(CsrView{n[k], row_ptr + rp_off[k], col_idx + nz_off[k], val + nz_off[k]});
+        }
+        std::vector<U512> totals;
+        DexpStats st;
+        hperm_status s = device_expand_group(&c->dev, grp, T, t, c->opts.s_leaf, budget, &totals, &st, nullptr, prime);
+        if (s) return s;
+        for (size_t q = g0; q < g1; ++q) residues[order_of[q]] = totals[q - g0].w[0];
+        g0 = g1;
+    }
+    return HPERM_OK;
+}
+
 hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_t *n,
                                        const int64_t *rp_off, const int64_t *nz_off,
                                        const int32_t *row_ptr, const int32_t *col_idx,

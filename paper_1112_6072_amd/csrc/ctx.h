@@ -197,10 +197,11 @@ struct DexpSample {
 hperm_status device_expand_problem(Dev *c, const CsrView &a, int T, int t, int s_leaf, size_t budget_bytes, U512 *out,
                                    DexpStats *stats, DexpSample *sample = nullptr);
 // The same for several problems of one order n > T at once: their trees share the level
-// buffers and the launches; out[k] receives per(A_k).
+// buffers and the launches; out[k] receives per(A_k). modp (a prime below 2^18, orders up to 64):
+// modular mode, out[k] = per(A_k) mod modp (entries reduced on entry; no bound applies).
 hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int T, int t, int s_leaf,
                                  size_t budget_bytes, std::vector<U512> *out, DexpStats *stats,
-                                 DexpSample *sample = nullptr);
+                                 DexpSample *sample = nullptr, uint32_t modp = 0);
 
 // The split order and the device expansion's job order in effect (0: off), and whether a
 // problem takes the device expansion (api.cpp).

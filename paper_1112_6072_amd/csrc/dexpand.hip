@@ -15,6 +15,9 @@
 //      >= 2^22 or row sum >= 2^24 is reported (the limits every job keeps).
 // Nodes whose sparsest line has five or more nonzeros are split the same way (ceil(s/2)
 // children): above the job order R-NW cannot take them, and the expansion is an identity.
+// Modular mode (a prime p < 2^18): every merged entry is reduced modulo p, so entries stay below
+// p and row sums below 2^24 for nodes of order up to 64; the tree then computes per(A) mod p
+// (the permanental polynomial's evaluations by residues).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -55,6 +58,10 @@ __device__ __forceinline__ uint32_t wave_excl(uint32_t v, int lane, uint32_t *to
     *total = (uint32_t)__shfl((int)x, WV - 1);
     return x - v;
 }
+
+// A merged entry in the expansion's arithmetic: exact, or reduced modulo p in modular mode
+// (p > 0: per(A) modulo p, every entry kept below p).
+__device__ __forceinline__ uint64_t merged(uint64_t v, uint32_t modp) { return modp ? v % modp : v; }
 
 // A node's rows: lane holds rows lane and lane + 64 (length, first entry index).
 struct Rows {
@@ -238,7 +245,7 @@ __device__ __forceinline__ uint32_t nth_bit(uint64_t lo, uint64_t hi, uint32_t k
 __device__ __forceinline__ void write_children(const uint32_t *node, uint32_t key, uint64_t child_idx, uint64_t wbase,
                                                uint32_t *lenb, uint32_t *cst, uint32_t *__restrict__ out,
                                                uint64_t *__restrict__ out_off, unsigned long long *__restrict__ flags,
-                                               int lane) {
+                                               uint32_t modp, int lane) {
     const uint32_t h0 = uni(node[0]);
     const int o = (int)(h0 & 0xffu);
     const float pbound = __uint_as_float(uni(node[1]));
@@ -309,7 +316,7 @@ __device__ __forceinline__ void write_children(const uint32_t *node, uint32_t ke
                         rest += v;
                     }
                 }
-                const uint64_t mv = (uint64_t)pr.ca * aq + (uint64_t)pr.cb * ap;
+                const uint64_t mv = merged((uint64_t)pr.ca * aq + (uint64_t)pr.cb * ap, modp);
                 bad = bad || mv >= HP_MAX_ENTRY;
                 olen[h] = cnt + (mv != 0);
                 osum[h] = rest + mv;
@@ -357,6 +364,7 @@ __device__ __forceinline__ void write_children(const uint32_t *node, uint32_t ke
                         mv += (uint64_t)pr.cb * (wp >> 8);
                         ++b;
                     }
+                    mv = merged(mv, modp);
                     if (j == line || mv == 0) continue;
                     bad = bad || mv >= HP_MAX_ENTRY;
                     ++cnt;
@@ -420,7 +428,7 @@ __device__ __forceinline__ void write_children(const uint32_t *node, uint32_t ke
                 // presence from the full 64-bit value, as in the row lengths of the plan above:
                 // an out-of-range value (flagged) is stored truncated but never changes the
                 // node's shape
-                const uint64_t mv64 = (uint64_t)pr.ca * aq + (uint64_t)pr.cb * ap;
+                const uint64_t mv64 = merged((uint64_t)pr.ca * aq + (uint64_t)pr.cb * ap, modp);
                 const uint32_t mv = (uint32_t)mv64;
                 bool merged = false;
                 uint32_t q = 0;
@@ -456,6 +464,7 @@ __device__ __forceinline__ void write_children(const uint32_t *node, uint32_t ke
                         mv += (uint64_t)pr.cb * (wp >> 8);
                         ++b;
                     }
+                    mv = merged(mv, modp);
                     if (j == line || mv == 0) continue;
                     dst[q++] = ((uint32_t)mv << 8) | (j - (j > line));
                 }
@@ -477,7 +486,7 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
                                                   uint64_t first, uint32_t n, const uint32_t *__restrict__ keys,
                                                   const uint64_t *__restrict__ place,
                                                   uint32_t *__restrict__ out, uint64_t *__restrict__ out_off,
-                                                  unsigned long long *__restrict__ flags) {
+                                                  unsigned long long *__restrict__ flags, uint32_t modp) {
     __shared__ uint32_t len_all[BLK / WV][MAXO];
     __shared__ __attribute__((aligned(16))) uint32_t node_all[BLK / WV][NODE_LDS];
     __shared__ __attribute__((aligned(16))) uint32_t child_all[BLK / WV][NODE_LDS];
@@ -495,9 +504,9 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
         uint32_t *nb = node_all[wv];
         for (uint32_t q = (uint32_t)lane; q < pw; q += WV) nb[q] = node[q];
         wave_sync();
-        write_children(nb, key, child_idx, wbase, len_all[wv], child_all[wv], out, out_off, flags, lane);
+        write_children(nb, key, child_idx, wbase, len_all[wv], child_all[wv], out, out_off, flags, modp, lane);
     } else {
-        write_children(node, key, child_idx, wbase, len_all[wv], nullptr, out, out_off, flags, lane);
+        write_children(node, key, child_idx, wbase, len_all[wv], nullptr, out, out_off, flags, modp, lane);
     }
 }
 
@@ -529,10 +538,11 @@ hipError_t launch_dexp_scan(const uint64_t *in, uint32_t n, uint64_t *tile_sums,
 
 hipError_t launch_dexp_write(const uint32_t *lvl, const uint64_t *off, uint64_t first, uint32_t n, const uint32_t *keys,
                              const uint64_t *place, uint32_t *out, uint64_t *out_off, unsigned long long *flags,
-                             hipStream_t s) {
+                             uint32_t modp, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint32_t blocks = (n + BLK / WV - 1) / (BLK / WV);
-    hipLaunchKernelGGL(dexp_write, dim3(blocks), dim3(BLK), 0, s, lvl, off, first, n, keys, place, out, out_off, flags);
+    hipLaunchKernelGGL(dexp_write, dim3(blocks), dim3(BLK), 0, s, lvl, off, first, n, keys, place, out, out_off, flags,
+                       modp);
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ hipError_t launch_dexp_scan(const uint64_t *in, uint32_t n, uint64_t *tile_sums,
 // flags[0] |= 1 on a range error.
 hipError_t launch_dexp_write(const uint32_t *lvl, const uint64_t *off, uint64_t first, uint32_t n, const uint32_t *keys,
                              const uint64_t *place, uint32_t *out, uint64_t *out_off, unsigned long long *flags,
-                             hipStream_t s);
+                             uint32_t modp, hipStream_t s);
 
 namespace {
 
@@ -45,6 +45,7 @@ struct Misc {
 
 struct Plan {
     int n = 0, T = 0, t = 0, s_leaf = 5;
+    uint32_t modp = 0;                 // modular mode: a prime below 2^18 (0: exact)
     uint64_t W = 0, N = 0;             // words and node offsets per level
     uint32_t *levels = nullptr;        // level o at levels + (o - T) * W
     uint64_t *offs = nullptr;          // level o's offsets at offs + (o - T) * N
@@ -120,7 +121,7 @@ struct DexpRun {
                 if (r) return r;
             }
             r = hip(launch_split_nodes(level(P.T), offs(P.T), (uint32_t)n, P.t, P.T, P.s_leaf, &m->head, accs,
-                                       P.probs, m->stats, P.wide, P.wide_entries, s),
+                                       P.probs, m->stats, P.wide, P.wide_entries, P.modp, s),
                     "device H_per launch");
             if (r) return r;
             r = hip(hipMemcpyAsync(&h, m, sizeof(Misc), hipMemcpyDeviceToHost, s), "download split results");
@@ -229,7 +230,7 @@ struct DexpRun {
                         // continuation's results, or the end of the expansion): an entry out of
                         // range changes values only, never the tree's shape or its addresses
                         r = hip(launch_dexp_write(level(o), offs(o), k, (uint32_t)chunk, P.keys, P.place,
-                                                  level(o - 1), offs(o - 1), &P.misc->flags, s),
+                                                  level(o - 1), offs(o - 1), &P.misc->flags, P.modp, s),
                                 "expansion write");
                         if (r) return r;
                         // chunks of the next level are sized by the average room its nodes were
@@ -250,8 +251,36 @@ struct DexpRun {
     }
 };
 
-hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int T, int t, int s_leaf,
-                                 size_t budget_bytes, std::vector<U512> *out, DexpStats *stats, DexpSample *sample) {
+hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, int T, int t, int s_leaf,
+                                 size_t budget_bytes, std::vector<U512> *out, DexpStats *stats, DexpSample *sample,
+                                 uint32_t modp) {
+    // modular mode: the inputs' entries reduced modulo p (zeros dropped) before packing
+    std::vector<std::vector<int32_t>> mrp, mci;
+    std::vector<std::vector<uint32_t>> mva;
+    std::vector<CsrView> reduced;
+    if (modp) {
+        if (modp < 3 || modp >= (1u << 18) || (!probs_in.empty() && probs_in[0].n > 64))
+            return set_error(c, HPERM_E_INVALID, "modular device expansion: a prime below 2^18, orders up to 64");
+        for (const CsrView &a : probs_in) {
+            mrp.emplace_back();
+            mci.emplace_back();
+            mva.emplace_back();
+            mrp.back().push_back(0);
+            for (int i = 0; i < a.n; ++i) {
+                for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
+                    if (a.val[e] % modp) {
+                        mci.back().push_back(a.col_idx[e]);
+                        mva.back().push_back(a.val[e] % modp);
+                    }
+                mrp.back().push_back((int32_t)mci.back().size());
+            }
+            mci.back().push_back(0);   // non-empty arrays
+            mva.back().push_back(0);
+        }
+        for (size_t k = 0; k < probs_in.size(); ++k)
+            reduced.push_back(CsrView{probs_in[k].n, mrp[k].data(), mci[k].data(), mva[k].data()});
+    }
+    const std::vector<CsrView> &probs = modp ? reduced : probs_in;
     DexpRun run{c, Plan{}, {}, DexpStats{}, std::string(), HPERM_OK};
     if (sample) {
         run.sample_max = sample->max_jobs;
@@ -281,7 +310,7 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int 
         const int rc = pack_root_node(probs[(size_t)k], &root, &bounds[(size_t)k]);
         if (rc == 1) continue;
         if (rc) return set_error(c, rc == -2 ? HPERM_E_RANGE : HPERM_E_INVALID, "device expansion: input out of range");
-        if (bounds[(size_t)k] > 102.0)
+        if (!modp && bounds[(size_t)k] > 102.0)
             return set_error(c, HPERM_E_RANGE, "device expansion: the permanent bound exceeds 2^102");
         root[2] = (uint32_t)k;
         root_off.push_back(roots.size());
@@ -299,6 +328,7 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int 
     P.T = T;
     P.t = t;
     P.s_leaf = s_leaf;
+    P.modp = modp;
     P.nprob = count;
     const int L = n - T + 1;
     // per level: 7/8 of its share in words, 1/8 in 8-byte offsets; the plan arrays for half a
@@ -359,10 +389,18 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int 
     run.st.total_s = now_s() - t0;
     if (s) return set_error(c, s, run.err);
     if (sample) sample->complete = !run.stopped;
-    if (!run.stopped)
+    if (modp) {   // the sums of residues, reduced
+        for (U512 &v : run.total) {
+            u128 r = 0;
+            for (int w = 7; w >= 0; --w) r = ((r << 64) | v.w[w]) % modp;
+            v = U512();
+            v.w[0] = (uint64_t)r;
+        }
+    } else if (!run.stopped) {
         for (int k : live)
             if (run.total[(size_t)k].bits() > (int)std::ceil(bounds[(size_t)k]) + 1)
                 return set_error(c, HPERM_E_INTERNAL, "device expansion: a result exceeds its proven bound");
+    }
     *out = run.total;
     if (stats) *stats = run.st;
     return HPERM_OK;

@@ -100,8 +100,10 @@ hipError_t launch_split_jobs(const JobDesc *jobs, const uint32_t *data, const fl
 // Nodes of the device expansion: node k at nodes + node_off[k], k < n, all of order mm (> t);
 // their values are summed into probs[problem of the node]; accs (nullable) receives each
 // node's value.
+// modp: 0 exact; else a prime below 2^18 and the nodes' values are taken modulo it (the nodes
+// must come from a device expansion in the same modular mode).
 hipError_t launch_split_nodes(const uint32_t *nodes, const uint64_t *node_off, uint32_t n, int t, int mm, int s_leaf,
                               unsigned long long *head, JobAcc *accs, ProbAcc *probs, unsigned long long *stats,
-                              void *wide, uint64_t wide_entries, hipStream_t s);
+                              void *wide, uint64_t wide_entries, uint32_t modp, hipStream_t s);
 
 }  // namespace hp

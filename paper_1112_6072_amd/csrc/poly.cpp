@@ -9,10 +9,12 @@
 // integer interpolation: forward differences give the Newton coefficients e_k =
 // Delta^k p(0) / k! (integers, as p has integer coefficients), and p(x) = sum_k e_k x(x-1)..(x-k+1)
 // is expanded by Horner's rule in that basis, p = e_0 + x(e_1 + (x-1)(e_2 + ...)).
+#include <math.h>
 #include <stdint.h>
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -55,6 +57,49 @@ void add_diagonal(int32_t n, const int32_t *rp, const int32_t *ci, const uint32_
         }
     }
     orp.push_back((int32_t)(oci.size() - base));
+}
+
+uint64_t powmod(uint64_t b, uint64_t e, uint64_t m) {
+    uint64_t r = 1 % m;
+    b %= m;
+    for (; e; e >>= 1) {
+        if (e & 1) r = r * b % m;
+        b = b * b % m;
+    }
+    return r;
+}
+
+bool is_prime(uint32_t v) {
+    if (v < 2) return false;
+    for (uint32_t d = 2; d * d <= v; ++d)
+        if (v % d == 0) return false;
+    return true;
+}
+
+// The value in [0, prod p) with the given residues (Garner's mixed-radix form).
+U512 crt(const std::vector<uint32_t> &p, const uint64_t *r) {
+    const size_t K = p.size();
+    std::vector<uint64_t> v(K);
+    for (size_t k = 0; k < K; ++k) {
+        uint64_t t = 0, prod = 1;   // the mixed-radix value so far modulo p_k, and p_0..p_{k-1} mod p_k
+        for (size_t j = k; j-- > 0;) t = (t * p[j] + v[j]) % p[k];
+        for (size_t j = 0; j < k; ++j) prod = prod * p[j] % p[k];
+        v[k] = (r[k] % p[k] + p[k] - t) % p[k] * powmod(prod, p[k] - 2, p[k]) % p[k];
+    }
+    U512 x;
+    for (size_t k = K; k-- > 0;) {
+        x.mul_u64(p[k]);
+        U512 a;
+        a.w[0] = v[k];
+        x.add(a);
+    }
+    return x;
+}
+
+uint64_t mod_u512(const U512 &x, uint64_t m) {
+    hp::u128 r = 0;
+    for (int w = 7; w >= 0; --w) r = ((r << 64) | x.w[w]) % m;
+    return (uint64_t)r;
 }
 
 S512 from_limbs(const uint64_t *limb) {
@@ -157,6 +202,7 @@ hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32
     s = hperm_expand_batch_csr(ctx, 1, sizes.data() + n, rp_off.data() + n, nz_off.data() + n, rp.data(),
                                ci.data(), va.data(), &probe);
     if (probe) hperm_jobs_free(probe);
+    const bool modular = s == HPERM_E_RANGE && n > 22 && n <= 64;
     if (!s)
         s = hperm_permanent_batch_csr(ctx, np, sizes.data(), rp_off.data(), nz_off.data(), rp.data(),
                                       ci.data(), va.data(), res.data());
@@ -164,10 +210,52 @@ hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32
         const hperm_status r = hperm_ctx_set_opts(ctx, &saved);
         if (!s) s = r;
     }
-    if (s) return s;
     std::vector<uint64_t> values((size_t)np * 8);
-    for (int x = 0; x < np; ++x)
-        for (int k = 0; k < 8; ++k) values[(size_t)x * 8 + k] = res[(size_t)x].limb[k];
+    if (modular) {
+        // beyond the exact rings: per(xI + A) modulo K + 1 primes below 2^18, K of them covering
+        // the bound of per(nI + A) (the product of its row sums), the values rebuilt by the
+        // Chinese remainder theorem and each checked against the last prime
+        double bound = 0.0;
+        for (int32_t i = 0; i < n; ++i) {
+            uint64_t rs = (uint64_t)n;
+            for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) rs += val[e];
+            bound += std::log2((double)rs);
+        }
+        std::vector<uint32_t> primes;
+        double cover = 0.0;
+        for (uint32_t q = (1u << 18) - 1; q > 3 && cover <= bound + 1.0; q -= 2)
+            if (is_prime(q)) {
+                primes.push_back(q);
+                cover += std::log2((double)q);
+            }
+        if (cover > 500.0) return HPERM_E_RANGE;   // beyond the 512-bit values
+        for (uint32_t q = primes.back() - 2; q > 3; q -= 2)   // one more prime: the check
+            if (is_prime(q)) {
+                primes.push_back(q);
+                break;
+            }
+        const size_t K = primes.size() - 1;
+        std::vector<uint64_t> r((size_t)np * primes.size());
+        for (size_t j = 0; j < primes.size(); ++j) {
+            std::vector<uint64_t> rj((size_t)np);
+            s = hperm_permanent_mod_batch_csr(ctx, np, sizes.data(), rp_off.data(), nz_off.data(), rp.data(),
+                                              ci.data(), va.data(), primes[j], rj.data());
+            if (s) return s;
+            for (int x = 0; x < np; ++x) r[(size_t)x * primes.size() + j] = rj[(size_t)x];
+        }
+        const std::vector<uint32_t> base(primes.begin(), primes.begin() + (long)K);
+        for (int x = 0; x < np; ++x) {
+            const uint64_t *rx = r.data() + (size_t)x * primes.size();
+            const U512 v = crt(base, rx);
+            if (mod_u512(v, primes[K]) != rx[K]) return HPERM_E_INTERNAL;   // residues that disagree
+            for (int k = 0; k < 8; ++k) values[(size_t)x * 8 + k] = v.w[k];
+        }
+        s = HPERM_OK;
+    } else {
+        if (s) return s;
+        for (int x = 0; x < np; ++x)
+            for (int k = 0; k < 8; ++k) values[(size_t)x * 8 + k] = res[(size_t)x].limb[k];
+    }
     // p(x) = per(xI + A); c_k = (-1)^(n-k) a_k
     const hperm_status si = hperm_polynomial_interpolate(n, values.data(), 1, coeffs);
     if (si == HPERM_E_INVALID) return HPERM_E_INTERNAL;   // values from the device that no

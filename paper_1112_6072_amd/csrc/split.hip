@@ -36,6 +36,11 @@
 // start subset holds a column below p - 7, and the term of step s has the sign (-1)^(s + z).
 // Rows beyond p are padded with f = 1. Leaves have order p >= t >= 7.
 //
+// Modular mode (SplitArgs.modp, a prime p < 2^18; nodes of the device expansion in the same
+// mode): merged entries are reduced modulo p, every leaf is evaluated modulo p in FP64 (exact:
+// operands and products stay below 2^53) and normalised with the inverse of 2^(p-1), and the
+// sums are residues: per(B) mod p.
+//
 // Results: per-job values (JobAcc, flagged normalised) for the host's job tables; for the
 // device expansion's nodes, each wave sums its jobs' values per problem and adds them into the
 // problem accumulators (ProbAcc), and per-node values are written only when asked for.
@@ -315,6 +320,99 @@ __device__ __forceinline__ u128 walk_plain128(int p, int lane, const int32_t *D,
     return (lane & 1) ? acc1 - acc0 : acc0 - acc1;
 }
 
+// ---- modular mode: per(B) modulo a prime p < 2^18 (the permanental polynomial's residues) ----
+// FP64 arithmetic: every operand and product below 2^53 is exact, and x mod p is
+// x - floor(x / p) p with the quotient from the rounded reciprocal off by at most one, which
+// two corrections absorb.
+struct ModP {
+    double p, pinv;
+};
+__device__ __forceinline__ double red_f(double x, const ModP &m) {   // |x| < 2^53 -> [0, p)
+    double r = __builtin_fma(-floor(x * m.pinv), m.p, x);
+    r = r < 0.0 ? r + m.p : r;
+    return r >= m.p ? r - m.p : r;
+}
+
+// The product of the R row values modulo p: exact pair products (|f| < 2^24), reduced, chained.
+template <int R>
+__device__ __forceinline__ double mod_product(const int32_t (&f)[R], const ModP &m) {
+    double r = red_f((double)f[0] * (double)f[1], m);
+#pragma unroll
+    for (int k = 1; k < R / 2; ++k) r = red_f(r * red_f((double)f[2 * k] * (double)f[2 * k + 1], m), m);
+    return r;
+}
+
+// This lane's share of V modulo p (in [0, p)) for a leaf of order 7 <= p <= R in the main
+// kernel's tables (one term per step).
+template <int R>
+__device__ __forceinline__ uint64_t walk_mod(int p, int lane, const int32_t *D, const ModP &m) {
+    const uint32_t L = 1u << (p - 7);
+    int32_t f[R];
+    start_rows<R>(f, p, lane, D);
+    double acc0 = mod_product<R>(f, m), acc1 = 0.0;
+    for (uint32_t s = 1; s < L; s += 2) {
+        add_rows<R>(f, flip_column(D, s));
+        acc1 += mod_product<R>(f, m);
+        acc1 = acc1 >= m.p ? acc1 - m.p : acc1;
+        if (s + 1 < L) {
+            add_rows<R>(f, flip_column(D, s + 1));
+            acc0 += mod_product<R>(f, m);
+            acc0 = acc0 >= m.p ? acc0 - m.p : acc0;
+        }
+    }
+    double v = (lane & 1) ? acc1 - acc0 : acc0 - acc1;
+    v = v < 0.0 ? v + m.p : v;
+    return (uint64_t)v;
+}
+
+// The same over the replay kernel's tables (stride ds, base separate).
+template <int R>
+__device__ __forceinline__ uint64_t walk_mod_wide(int p, int lane, const int32_t *D, const int32_t *base, int ds,
+                                                  const ModP &m) {
+    const uint32_t L = 1u << (p - 7);
+    int32_t f[R];
+    {
+        const int c = p - 7;
+        const uint32_t kfirst = (lane & 1) ? (uint32_t)lane * L + L - 1 : (uint32_t)lane * L;
+        const uint32_t s0 = kfirst ^ (kfirst >> 1);
+#pragma unroll
+        for (int i = 0; i < R; ++i) f[i] = base[i];
+        for (int j = c; j < p - 1; ++j) {
+            const int32_t in = -(int32_t)((s0 >> j) & 1);
+#pragma unroll
+            for (int i = 0; i < R; ++i) f[i] += D[j * ds + i] & in;
+        }
+    }
+    double acc0 = mod_product<R>(f, m), acc1 = 0.0;
+    for (uint32_t s = 1; s < L; s += 2) {
+        add_rows_dir<R>(f, D, ((s >> 1) & 1) == 0);
+        acc1 += mod_product<R>(f, m);
+        acc1 = acc1 >= m.p ? acc1 - m.p : acc1;
+        if (s + 1 < L) {
+            const uint32_t s2 = s + 1;
+            const int j = __builtin_ctz(s2);
+            add_rows_dir<R>(f, D + j * ds, ((s2 >> (j + 1)) & 1) == 0);
+            acc0 += mod_product<R>(f, m);
+            acc0 = acc0 >= m.p ? acc0 - m.p : acc0;
+        }
+    }
+    double v = (lane & 1) ? acc1 - acc0 : acc0 - acc1;
+    v = v < 0.0 ? v + m.p : v;
+    return (uint64_t)v;
+}
+
+// per(leaf) modulo p from the lanes' shares of V = (-1)^(p-1) 2^(p-1) per(leaf): the wave's sum,
+// times (-1)^(p-1) and the inverse of 2^(p-1) (2^-1 = (q + 1) / 2 for the odd prime q).
+__device__ __forceinline__ uint64_t mod_normalise(uint64_t share, int p, const ModP &m) {
+    const double V = red_f((double)uni64(wave_sum64(share)), m);   // below 64 p < 2^24
+    const double half = (m.p + 1.0) * 0.5;
+    double inv = 1.0;
+    for (int k = 1; k < p; ++k) inv = red_f(inv * half, m);
+    double r = red_f(V * inv, m);
+    if ((p - 1) & 1) r = r == 0.0 ? 0.0 : m.p - r;
+    return (uint64_t)r;
+}
+
 // ------------------------------------------------------------------ per-wave LDS region
 // The node being walked lives in one physical mm x mm matrix M (row stride S = dstride(mm))
 // with masks of its alive rows and columns: a split marks its deleted row (or column) and the
@@ -342,8 +440,9 @@ struct Region {
     uint32_t *rmap, *cmap;          // leaf compaction: alive row / column of each logical index
     uint32_t *lv0;                  // undo record of order t + 1 (main kernel)
     int S, mm, t, lw;
-    __device__ Region(uint32_t *l, int t_, int mm_, int table_words)
-        : S(dstride(mm_)), mm(mm_), t(t_), lw(lvl_words(mm_)) {
+    uint32_t modp = 0;              // modular mode: merged entries reduced modulo this prime
+    __device__ Region(uint32_t *l, int t_, int mm_, int table_words, uint32_t modp_ = 0)
+        : S(dstride(mm_)), mm(mm_), t(t_), lw(lvl_words(mm_)), modp(modp_) {
         M = l;
         D = (int32_t *)(l + mm * S);
         rmask = (uint32_t *)(D + table_words);
@@ -549,12 +648,15 @@ __device__ __forceinline__ bool plan_split_t(const Region &rg, uint32_t AR, uint
         if (mine) {
             pv.q[c] = COL ? M[Q * S + k] : M[k * S + Q];
             pv.p[c] = COL ? M[P * S + k] : M[k * S + P];
-            const uint64_t mv = ca * pv.q[c] + cb * pv.p[c];
+            uint64_t mv = ca * pv.q[c] + cb * pv.p[c];
+            if (rg.modp) mv %= rg.modp;
             bool bad = mv >= HP_MAX_ENTRY;
             if (!COL) bad = bad || (uint64_t)ln.rs - pv.q[c] - pv.p[c] + mv >= HP_MAX_ROWSUM;
             fail = fail || (live && bad);
         }
-        if (COL) {   // the merged row's sum from rows P and Q without the split column
+        // the merged row's sum from rows P and Q without the split column (modular mode: every
+        // entry stays below p, so every row sum below 2^24, and the bound is not needed)
+        if (COL && !rg.modp) {
             const uint64_t rq = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)Q) -
                                 (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)pv.lv, (int)Q);
             const uint64_t rp = (uint32_t)__builtin_amdgcn_readlane((int)ln.rs, (int)P) -
@@ -621,7 +723,7 @@ __device__ __forceinline__ void apply_child_t(const Region &rg, const Plan &pl, 
         if (row) {
             const uint32_t mq = pv ? (ch ? pv->q[1] : pv->q[0]) : M[k * S + Q];
             const uint32_t mp = pv ? (ch ? pv->p[1] : pv->p[0]) : M[k * S + P];
-            mv = ca * mq + cb * mp;
+            mv = rg.modp ? (uint32_t)(((uint64_t)ca * mq + (uint64_t)cb * mp) % rg.modp) : ca * mq + cb * mp;
             ln.msk = (ln.msk & ~(kb | db)) | (mv ? kb : 0u);
             ln.rs = ln.rs - mq - mp + mv;
             M[k * S + keep] = mv;   // each lane rewrites its own row: no other lane reads it here
@@ -642,15 +744,23 @@ __device__ __forceinline__ void apply_child_t(const Region &rg, const Plan &pl, 
         if (col) {
             const uint32_t mq = pv ? (ch ? pv->q[1] : pv->q[0]) : M[Q * S + k];
             const uint32_t mp = pv ? (ch ? pv->p[1] : pv->p[0]) : M[P * S + k];
-            mv = ca * mq + cb * mp;
+            mv = rg.modp ? (uint32_t)(((uint64_t)ca * mq + (uint64_t)cb * mp) % rg.modp) : ca * mq + cb * mp;
             ln.msk = (ln.msk & ~(kb | db)) | (mv ? kb : 0u);
             M[keep * S + k] = mv;   // each lane rewrites its own column's entry
         }
         const uint32_t newrow = (uint32_t)(__ballot(col && mv != 0) >> 32);
+        // the merged row's sum: from rows P and Q, or (modular mode, entries reduced) the sum
+        // of its new entries
+        uint32_t krs = ca * rq + cb * rp;
+        if (rg.modp) {
+            uint32_t part = col ? mv : 0u;
+            for (int o = 32; o; o >>= 1) part += (uint32_t)__shfl_xor((int)part, o);
+            krs = part;
+        }
         if (lane < 32 && ((AR2 >> k) & 1)) {
             const bool kp = (uint32_t)k == keep;
             ln.msk = kp ? newrow : ln.msk & ~(1u << line);
-            ln.rs = kp ? ca * rq + cb * rp : ln.rs - lv;
+            ln.rs = kp ? krs : ln.rs - lv;
         }
         AR = AR2;
         AC = AC2;
@@ -865,6 +975,7 @@ struct SplitArgs {
     WideLeaf *wide;
     uint32_t wide_cap;
     unsigned long long *cycles;   // nullable
+    uint32_t modp;                // 0: exact; else a prime below 2^18: per(B) modulo it
 };
 
 namespace {
@@ -886,11 +997,12 @@ __device__ __forceinline__ int load_source(const Region &rg, const SplitArgs &a,
 // outer loop go to scratch around the leaf walk) and the latency-bound split steps get a third
 // more waves to interleave (measured 17 % faster on the order-20 jobs of the cubic graphs on
 // 60 vertices at t = 12).
-template <bool NODES>
+template <bool NODES, bool MOD>
 __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hper_split(SplitArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    const Region rg(lds, a.t, a.mm, leaf_table_words());
+    const Region rg(lds, a.t, a.mm, leaf_table_words(), MOD ? a.modp : 0u);   // exact kernel: 0, folded
+    const ModP mp{(double)a.modp, a.modp ? 1.0 / (double)a.modp : 0.0};
     uint64_t n_leaves = 0, n_terms = 0, n_splits = 0, n_stops = 0, n_bad = 0, n_wide = 0;
     u128 pacc = 0;            // this wave's sum for problem pcur (nodes)
     uint32_t pcur = 0xffffffffu;
@@ -927,10 +1039,17 @@ __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hp
                 ++n_leaves;
                 n_terms += 1ull << (o - 1);
                 // exact modulo 2^64 when per(leaf) 2^(o-1) < 2^63 (bound: the job's, or the
-                // leaf's product of row sums)
-                bool ok64 = fminf(jb, rowsum_log2(ln, AR, lane)) + (float)o <= 62.5f;
+                // leaf's product of row sums); modular mode: every leaf up to order 16 here
+                bool ok64 = MOD;
+                if (!ok64) ok64 = fminf(jb, rowsum_log2(ln, AR, lane)) + (float)o <= 62.5f;
                 if (!ok64 && o <= PMAX) ok64 = colsum_log2(rg, AR, AC, lane) + (float)o <= 62.5f;
-                if (ok64 && o <= PMAX) {
+                if (MOD && o <= PMAX) {
+                    leaf_tables(rg, ln, o, AR, AC, lane);
+                    const uint64_t share = o <= 12 ? walk_mod<12>(o, lane, rg.D, mp) : walk_mod<16>(o, lane, rg.D, mp);
+                    wave_sync();   // the tables are rewritten by the next leaf
+                    acc += mod_normalise(share, o, mp);
+                    if (acc >= (u128)rg.modp) acc -= rg.modp;
+                } else if (ok64 && o <= PMAX) {
                     bool bad;
                     const uint64_t per = normalise64(uni64(wave_sum64(eval_leaf(rg, ln, o, AR, AC, lane))), o, &bad);
                     n_bad += bad;
@@ -997,11 +1116,12 @@ __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hp
 // The deferred leaves: each wave replays one leaf's path from its job's matrix (the same
 // line choices and pairs), evaluates the leaf modulo 2^128 and adds its normalised value to
 // the job (and, for nodes, to the problem).
-template <bool NODES>
+template <bool NODES, bool MOD>
 __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    const Region rg(lds, a.t, a.mm, a.mm * dstride(a.mm));
+    const Region rg(lds, a.t, a.mm, a.mm * dstride(a.mm), MOD ? a.modp : 0u);
+    const ModP mp{(double)a.modp, a.modp ? 1.0 / (double)a.modp : 0.0};
     const uint64_t n = min((uint64_t)a.stats[4], (uint64_t)a.wide_cap);
     for (uint64_t w = blockIdx.x; w < n; w += gridDim.x) {
         const WideLeaf wl = a.wide[w];
@@ -1025,12 +1145,18 @@ __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
         }
         leaf_tables_wide(rg, ln, p, AR, AC, lane);
         const int32_t *base = rg.D + (rg.mm - 1) * rg.S;
-        u128 v;   // rows padded to the table's stride (20 or 24), never beyond it
-        if (rg.S == 20) v = walk_plain128<20>(p, lane, rg.D, base, rg.S);
-        else v = walk_plain128<SMAX>(p, lane, rg.D, base, rg.S);
-        const u128 V = wave_sum128(v);
-        bool bad;
-        const u128 per = normalise128(V, p, &bad);
+        bool bad = false;
+        u128 per;
+        if (MOD) {   // modular mode: the leaf's residue
+            const uint64_t share = rg.S == 20 ? walk_mod_wide<20>(p, lane, rg.D, base, rg.S, mp)
+                                              : walk_mod_wide<SMAX>(p, lane, rg.D, base, rg.S, mp);
+            per = mod_normalise(share, p, mp);
+        } else {
+            u128 v;   // rows padded to the table's stride (20 or 24), never beyond it
+            if (rg.S == 20) v = walk_plain128<20>(p, lane, rg.D, base, rg.S);
+            else v = walk_plain128<SMAX>(p, lane, rg.D, base, rg.S);
+            per = normalise128(wave_sum128(v), p, &bad);
+        }
         if (lane == 0) {
             if (bad) atomicAdd(a.stats + 6, 1ull);
             if (a.accs) add_limbs(a.accs[job].l, per);
@@ -1058,28 +1184,37 @@ static hipError_t resident_grid(const void *fn, size_t lds, uint64_t *grid) {
     return hipSuccess;
 }
 
+template <bool NODES, bool MOD>
+static hipError_t launch_split_kernels(const SplitArgs &a, hipStream_t s) {
+    const size_t lds = split_lds_bytes(a.t, a.mm);
+    uint64_t grid = 0;
+    hipError_t e = resident_grid((const void *)hper_split<NODES, MOD>, lds, &grid);
+    if (e != hipSuccess) return e;
+    if (grid > a.n) grid = a.n;
+    hipLaunchKernelGGL((hper_split<NODES, MOD>), dim3((uint32_t)grid), dim3(SW), lds, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t wlds = wide_lds_bytes(a.mm);
+    e = resident_grid((const void *)hper_split_wide<NODES, MOD>, wlds, &grid);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((hper_split_wide<NODES, MOD>), dim3((uint32_t)grid), dim3(SW), wlds, s, a);
+    return hipGetLastError();
+}
+
 template <bool NODES>
 static hipError_t launch_split_pair(const SplitArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     if (a.t < HP_SPLIT_MIN_T || a.t >= HP_SPLIT_MAX_M || a.mm <= a.t || a.mm > HP_SPLIT_MAX_M) return hipErrorInvalidValue;
-    const size_t lds = split_lds_bytes(a.t, a.mm);
-    uint64_t grid = 0;
-    hipError_t e = resident_grid((const void *)hper_split<NODES>, lds, &grid);
-    if (e != hipSuccess) return e;
-    if (grid > a.n) grid = a.n;
-    hipLaunchKernelGGL(hper_split<NODES>, dim3((uint32_t)grid), dim3(SW), lds, s, a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t wlds = wide_lds_bytes(a.mm);
-    e = resident_grid((const void *)hper_split_wide<NODES>, wlds, &grid);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(hper_split_wide<NODES>, dim3((uint32_t)grid), dim3(SW), wlds, s, a);
-    return hipGetLastError();
+    if (a.modp) {   // the modular kernels exist for the device expansion's nodes only
+        if (!NODES || a.modp < 3 || a.modp >= (1u << 18)) return hipErrorInvalidValue;
+        return launch_split_kernels<true, true>(a, s);
+    }
+    return launch_split_kernels<NODES, false>(a, s);
 }
 
 int split_grid(int t, int mm) {
     uint64_t grid = 0;
-    if (resident_grid((const void *)hper_split<false>, split_lds_bytes(t, mm), &grid) != hipSuccess) return 0;
+    if (resident_grid((const void *)hper_split<false, false>, split_lds_bytes(t, mm), &grid) != hipSuccess) return 0;
     return (int)grid;
 }
 
@@ -1108,7 +1243,7 @@ hipError_t launch_split_jobs(const JobDesc *jobs, const uint32_t *data, const fl
 
 hipError_t launch_split_nodes(const uint32_t *nodes, const uint64_t *node_off, uint32_t n, int t, int mm, int s_leaf,
                               unsigned long long *head, JobAcc *accs, ProbAcc *probs, unsigned long long *stats,
-                              void *wide, uint64_t wide_entries, hipStream_t s) {
+                              void *wide, uint64_t wide_entries, uint32_t modp, hipStream_t s) {
     SplitArgs a{};
     a.nodes = nodes;
     a.node_off = node_off;
@@ -1123,6 +1258,7 @@ hipError_t launch_split_nodes(const uint32_t *nodes, const uint64_t *node_off, u
     a.stats = stats;
     a.wide = (WideLeaf *)wide;
     a.wide_cap = (uint32_t)(wide_entries < 0xffffffffull ? wide_entries : 0xffffffffull);
+    a.modp = modp;
     return launch_split_pair<true>(a, s);
 }
 

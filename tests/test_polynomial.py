@@ -1,13 +1,44 @@
 """The permanental polynomial per(xI - A): the oracle's two routes against each other and
 against closed forms, then the library (GPU) against the oracle."""
+import itertools
+import json
 import math
+import os
 
 import numpy as np
 import pytest
 
 import workloads as W
 from oracle import per_brute
+from oracle.permanent import per_dp
 from oracle.polynomial import interpolate, perpoly_interpolate, perpoly_subsets
+
+C60_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c60_permanental_polynomial.json")
+
+
+def c60_coefficients() -> list[int]:
+    with open(C60_GOLDEN) as fh:
+        return [int(v) for v in json.load(fh)["coefficients"]]
+
+
+def cycles(adj, k: int) -> int:
+    """Number of cycles of length k >= 3 in a simple graph (each found from its least vertex,
+    once per direction)."""
+    count = 0
+
+    def walk(start, v, depth, seen):
+        nonlocal count
+        for w in adj[v]:
+            if w == start and depth == k:
+                count += 1
+            elif w > start and w not in seen and depth < k:
+                seen.add(w)
+                walk(start, w, depth + 1, seen)
+                seen.discard(w)
+
+    for s in range(len(adj)):
+        walk(s, s, 1, {s})
+    return count // 2
 
 
 @pytest.fixture(scope="module")
@@ -69,6 +100,31 @@ def test_native_interpolation_matches_oracle(hostlib):
         hostlib.polynomial_interpolate([0, 0, 1])
 
 
+def test_c60_stored_polynomial_closed_forms():
+    """The stored coefficients of per(xI - A) for C60 against graph counts. For a 0-1 symmetric
+    A with zero diagonal, a_(n-s) (the sum of the permanents of the principal sub-matrices of order
+    s) counts the covers of s vertices by disjoint edges and cycles, a cycle of length >= 3 counting
+    twice (its two directions). With no triangles or 4-cycles: c_n = 1, c_(n-1) = 0,
+    c_(n-2) = |E|, c_(n-3) = 0, c_(n-4) = pairs of disjoint edges, c_(n-5) = -2 (5-cycles),
+    c_(n-6) = triples of disjoint edges + 2 (6-cycles); c_0 = per(A) by the oracle's H_per."""
+    from oracle import native
+    c = c60_coefficients()
+    adj = W.read_appendix_adjacency("c60")
+    n = len(adj)
+    assert len(c) == n + 1 == 61
+    E = [(i, j) for i in range(n) for j in adj[i] if i < j]
+    assert cycles(adj, 3) == 0 and cycles(adj, 4) == 0
+    c5, c6 = cycles(adj, 5), cycles(adj, 6)
+    assert (c5, c6) == (12, 20)   # the pentagons and hexagons of the fullerene
+    m2 = sum(1 for a, b in itertools.combinations(E, 2) if len({*a, *b}) == 4)
+    m3 = sum(1 for a, b, d in itertools.combinations(E, 3) if len({*a, *b, *d}) == 6)
+    assert c[60] == 1 and c[59] == 0 and c[58] == len(E) == 90 and c[57] == 0
+    assert c[56] == m2 and c[55] == -2 * c5 and c[54] == m3 + 2 * c6
+    assert c[0] == native.hper_batch([W.adjacency_matrix(adj)], threads=4)[0]
+    # signs alternate with n - k: every a_k is a sum of non-negative permanents
+    assert all(v == 0 or (v < 0) == bool((n - k) & 1) for k, v in enumerate(c))
+
+
 @pytest.mark.gpu
 def test_library_matches_oracle(hperm):
     c = hperm.Context()
@@ -86,9 +142,76 @@ def test_library_matches_oracle(hperm):
         got = c.permanental_polynomial(G)
         assert got[24] == 1 and got[23] == 0 and got[22] == 36
         assert got[0] == c.permanent(G)
-        # per(nI + A) of a cubic graph on 40 vertices exceeds the supported bound
+        # orders above 64 whose values pass the exact rings' 2^180 are refused
         with pytest.raises(hperm.HpermError) as e:
-            c.permanental_polynomial(W.random_cubic_matrix(40, 0))
+            c.permanental_polynomial(W.random_cubic_matrix(70, 0))
         assert e.value.status == -2
+    finally:
+        c.close()
+
+
+@pytest.mark.gpu
+def test_modular_polynomial_matches_oracle(hperm):
+    """Orders 23..64 past 2^180: the values modulo primes below 2^18 and the Chinese remainder
+    theorem. A cubic graph on 40 vertices (per(40I + A) about 2^217) against the oracle's
+    frontier DP and interpolation."""
+    c = hperm.Context()
+    try:
+        G = W.random_cubic_matrix(40, 0)
+        got = c.permanental_polynomial(G)
+        assert got == perpoly_interpolate(G.astype(np.int64))
+    finally:
+        c.close()
+
+
+@pytest.mark.gpu
+def test_mod_batch_equals_exact_residues(hperm):
+    """per(A) mod p on the device path against exact values reduced mod p: the n = 60 cubic
+    batch (oracle's stored values) and weighted cubic graphs with entries beyond p (frontier DP),
+    for the largest prime below 2^18, 65537 and small primes."""
+    import json as _json
+    gold = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_values.json")
+    with open(gold) as fh:
+        stored = _json.load(fh)
+    mats, exact = [], []
+    for name, A in W.config_n60():
+        mats.append(A)
+        exact.append(int(stored[name]))
+    rng = np.random.default_rng(23)
+    for n, seed in ((24, 1), (30, 3), (44, 5)):
+        A = (W.random_cubic_matrix(n, seed).astype(np.int64) * rng.integers(1, 1 << 20, (n, n))).astype(np.uint32)
+        mats.append(A)
+        exact.append(per_dp(A.astype(np.int64).tolist()))
+    c = hperm.Context()
+    try:
+        for p in (262139, 65537, 7, 3):
+            got = c.permanent_mod_batch(mats, p)
+            assert got == [v % p for v in exact], p
+        with pytest.raises(hperm.HpermError):
+            c.permanent_mod_batch(mats[:1], 65535)   # not prime
+        with pytest.raises(hperm.HpermError):
+            c.permanent_mod_batch([W.random_cubic_matrix(20, 0)], 65537)   # order within the expansion
+    finally:
+        c.close()
+
+
+@pytest.mark.gpu
+def test_c60_evaluations_equal_stored_polynomial(hperm):
+    """C60 at full size on sampled points: per(xI + A) mod p on the device path equals
+    sum_k |c_k| x^k mod p from the stored coefficients (x = 0, 1 and 60; per(60I + A) is about
+    2^358). Each point with x > 0 is a tree of about 2e9 leaves (every row gains the diagonal),
+    so the whole polynomial (61 points, 21 primes) is a long run, not a test."""
+    import time
+    coeffs = c60_coefficients()
+    A = W.adjacency_matrix(W.read_appendix_adjacency("c60")).astype(np.uint32)
+    xs = (0, 1, 60)
+    mats = [A + np.uint32(x) * np.eye(60, dtype=np.uint32) for x in xs]
+    p = 262139
+    c = hperm.Context()
+    try:
+        t0 = time.perf_counter()
+        got = c.permanent_mod_batch(mats, p)
+        print(f"C60 per(xI + A) mod {p} at x = {xs}: {time.perf_counter() - t0:.2f} s", flush=True)
+        assert got == [sum(abs(v) * x ** k for k, v in enumerate(coeffs)) % p for x in xs]
     finally:
         c.close()
