@@ -243,10 +243,13 @@ typedef struct hperm_coeff {
  * exact integer interpolation on the host. When the bound of per(nI + A) stays below 2^180 the
  * evaluations are exact integers, with m_cut raised to n for n <= 40 (each xI + A is one R-NW
  * job: no expansion, whose merges would multiply the large diagonal entries). Beyond that bound,
- * for device-expansion orders 23..64, each evaluation is taken modulo K + 1 primes below 2^18
- * (hperm_permanent_mod_batch_csr), where K primes cover the bound, reconstructed by the
- * Chinese remainder theorem over K of them and checked against the last one (e.g. C60: 22
- * primes). The context's options are restored afterwards. coeffs[n + 1] is caller-owned.
+ * for device-expansion orders 23..64, the n + 1 evaluations are taken modulo each of K + 1
+ * primes below 2^18 (hperm_permanent_mod_batch_csr) and interpolated modulo that prime; each
+ * a_k is rebuilt by the Chinese remainder theorem over K primes whose product exceeds a bound
+ * on the coefficients (a_k <= e_{n-k}(g), the elementary symmetric function of g_i = the row
+ * sums, or Bregman's (r_i!)^(1/r_i) for a 0-1 matrix) and checked against the last prime
+ * (C60: 7 primes, 427 evaluations of order 60, each a tree of about 2e9 leaves).
+ * The context's options are restored afterwards. coeffs[n + 1] is caller-owned.
  * Must not be called while serving or concurrently with other calls on the context.
  * Errors: as for
  * hperm_permanent_batch_csr; HPERM_E_RANGE when a bound or an intermediate exceeds the

@@ -102,6 +102,32 @@ uint64_t mod_u512(const U512 &x, uint64_t m) {
     return (uint64_t)r;
 }
 
+// The coefficients of the degree-n polynomial through (x, y_x), x = 0..n, modulo the prime
+// p > n: forward differences, Newton coefficients Delta^k p(0) / k!, and Horner's rule in the
+// falling-factorial basis, as in the exact interpolation.
+std::vector<uint64_t> interpolate_mod(const std::vector<uint64_t> &y, uint64_t p) {
+    const size_t np = y.size();
+    std::vector<uint64_t> d(y);
+    for (size_t k = 1; k < np; ++k)
+        for (size_t i = np - 1; i >= k; --i) d[i] = (d[i] + p - d[i - 1]) % p;
+    uint64_t fact = 1;
+    for (size_t k = 2; k < np; ++k) {
+        fact = fact * k % p;
+        d[k] = d[k] * powmod(fact, p - 2, p) % p;
+    }
+    std::vector<uint64_t> poly(np, 0);
+    poly[0] = d[np - 1];
+    for (size_t k = np - 1; k-- > 0;) {
+        const size_t deg = np - 2 - k;   // degree of poly before this step
+        for (size_t j = deg + 1; j-- > 0;) {
+            poly[j + 1] = (poly[j + 1] + poly[j]) % p;
+            poly[j] = (p - poly[j] * (k % p) % p) % p;
+        }
+        poly[0] = (poly[0] + d[k]) % p;
+    }
+    return poly;
+}
+
 S512 from_limbs(const uint64_t *limb) {
     S512 v;
     for (int k = 0; k < 8; ++k) v.mag.w[k] = limb[k];
@@ -162,6 +188,84 @@ hperm_status hperm_polynomial_interpolate(int32_t n, const uint64_t *values, int
     return HPERM_OK;
 }
 
+namespace {
+
+// per(xI - A) for orders 23..64 beyond the exact rings. The coefficients of per(xI + A) are
+// a_k = sum over the principal sub-matrices A_S of order n - k of per(A_S), and
+// per(A_S) <= prod_{i in S} g_i with g_i the row sum of A (or, for a 0-1 matrix, Bregman's
+// (r_i!)^(1/r_i)), so a_k <= e_{n-k}(g), the elementary symmetric function. per(xI + A) is
+// evaluated at x = 0..n modulo K + 1 primes below 2^18 (the device path's modular mode), the
+// polynomial interpolated modulo each prime, and each coefficient rebuilt by the Chinese
+// remainder theorem over the K primes whose product exceeds the bound, then checked against
+// the last prime. The values reach the bound of the largest evaluation, the coefficients far
+// less (C60: values about 2^355, coefficients below 2^50, bound 2^90: 7 primes, not 22).
+hperm_status modular_polynomial(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr, const uint32_t *val,
+                                const std::vector<int32_t> &sizes, const std::vector<int64_t> &rp_off,
+                                const std::vector<int64_t> &nz_off, const std::vector<int32_t> &rp,
+                                const std::vector<int32_t> &ci, const std::vector<uint32_t> &va,
+                                hperm_coeff *coeffs) {
+    const int np = n + 1;
+    bool zero_one = true;
+    std::vector<long double> g((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        uint64_t rs = 0;
+        for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            rs += val[e];
+            zero_one = zero_one && val[e] <= 1;
+        }
+        g[(size_t)i] = (long double)rs;
+    }
+    if (zero_one)
+        for (int32_t i = 0; i < n; ++i) {   // Bregman: (r!)^(1/r)
+            const long double r = g[(size_t)i];
+            g[(size_t)i] = r > 0 ? std::exp(std::lgamma(r + 1.0L) / r) : 0.0L;
+        }
+    std::vector<long double> e((size_t)np, 0.0L);   // e_j(g), j = 0..n
+    e[0] = 1.0L;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = i + 1; j >= 1; --j) e[(size_t)j] += e[(size_t)j - 1] * g[(size_t)i];
+    long double emax = 1.0L;
+    for (int j = 0; j < np; ++j) emax = std::max(emax, e[(size_t)j]);
+    const double bound = (double)std::log2(emax) * (1.0 + 1e-9) + 1.0;   // rounding of the sums
+    std::vector<uint32_t> primes;
+    double cover = 0.0;
+    for (uint32_t q = (1u << 18) - 1; q > 3 && cover <= bound + 1.0; q -= 2)
+        if (is_prime(q)) {
+            primes.push_back(q);
+            cover += std::log2((double)q);
+        }
+    if (cover > 500.0) return HPERM_E_RANGE;   // beyond the 512-bit coefficients
+    for (uint32_t q = primes.back() - 2; q > 3; q -= 2)   // one more prime: the check
+        if (is_prime(q)) {
+            primes.push_back(q);
+            break;
+        }
+    const size_t K = primes.size() - 1;
+    std::vector<uint64_t> cr((size_t)np * primes.size());   // coefficient x prime
+    for (size_t j = 0; j < primes.size(); ++j) {
+        std::vector<uint64_t> y((size_t)np);
+        const hperm_status s = hperm_permanent_mod_batch_csr(ctx, np, sizes.data(), rp_off.data(), nz_off.data(),
+                                                             rp.data(), ci.data(), va.data(), primes[j], y.data());
+        if (s) return s;
+        const std::vector<uint64_t> c = interpolate_mod(y, primes[j]);
+        for (int k = 0; k < np; ++k) cr[(size_t)k * primes.size() + j] = c[(size_t)k];
+    }
+    const std::vector<uint32_t> base(primes.begin(), primes.begin() + (long)K);
+    for (int k = 0; k < np; ++k) {
+        const uint64_t *rk = cr.data() + (size_t)k * primes.size();
+        const U512 a = crt(base, rk);
+        if (mod_u512(a, primes[K]) != rk[K]) return HPERM_E_INTERNAL;   // residues that disagree
+        memset(&coeffs[k], 0, sizeof(hperm_coeff));
+        for (int w = 0; w < 8; ++w) coeffs[k].limb[w] = a.w[w];
+        coeffs[k].nlimb = a.nlimb();
+        coeffs[k].negative = (coeffs[k].nlimb && ((n - k) & 1)) ? 1 : 0;   // c_k = (-1)^(n-k) a_k
+    }
+    if (!(coeffs[n].nlimb == 1 && coeffs[n].limb[0] == 1)) return HPERM_E_INTERNAL;   // monic
+    return HPERM_OK;
+}
+
+}  // namespace
+
 hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
                                           const int32_t *col_idx, const uint32_t *val,
                                           hperm_coeff *coeffs) {
@@ -210,52 +314,11 @@ hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32
         const hperm_status r = hperm_ctx_set_opts(ctx, &saved);
         if (!s) s = r;
     }
+    if (modular) return modular_polynomial(ctx, n, row_ptr, val, sizes, rp_off, nz_off, rp, ci, va, coeffs);
+    if (s) return s;
     std::vector<uint64_t> values((size_t)np * 8);
-    if (modular) {
-        // beyond the exact rings: per(xI + A) modulo K + 1 primes below 2^18, K of them covering
-        // the bound of per(nI + A) (the product of its row sums), the values rebuilt by the
-        // Chinese remainder theorem and each checked against the last prime
-        double bound = 0.0;
-        for (int32_t i = 0; i < n; ++i) {
-            uint64_t rs = (uint64_t)n;
-            for (int32_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) rs += val[e];
-            bound += std::log2((double)rs);
-        }
-        std::vector<uint32_t> primes;
-        double cover = 0.0;
-        for (uint32_t q = (1u << 18) - 1; q > 3 && cover <= bound + 1.0; q -= 2)
-            if (is_prime(q)) {
-                primes.push_back(q);
-                cover += std::log2((double)q);
-            }
-        if (cover > 500.0) return HPERM_E_RANGE;   // beyond the 512-bit values
-        for (uint32_t q = primes.back() - 2; q > 3; q -= 2)   // one more prime: the check
-            if (is_prime(q)) {
-                primes.push_back(q);
-                break;
-            }
-        const size_t K = primes.size() - 1;
-        std::vector<uint64_t> r((size_t)np * primes.size());
-        for (size_t j = 0; j < primes.size(); ++j) {
-            std::vector<uint64_t> rj((size_t)np);
-            s = hperm_permanent_mod_batch_csr(ctx, np, sizes.data(), rp_off.data(), nz_off.data(), rp.data(),
-                                              ci.data(), va.data(), primes[j], rj.data());
-            if (s) return s;
-            for (int x = 0; x < np; ++x) r[(size_t)x * primes.size() + j] = rj[(size_t)x];
-        }
-        const std::vector<uint32_t> base(primes.begin(), primes.begin() + (long)K);
-        for (int x = 0; x < np; ++x) {
-            const uint64_t *rx = r.data() + (size_t)x * primes.size();
-            const U512 v = crt(base, rx);
-            if (mod_u512(v, primes[K]) != rx[K]) return HPERM_E_INTERNAL;   // residues that disagree
-            for (int k = 0; k < 8; ++k) values[(size_t)x * 8 + k] = v.w[k];
-        }
-        s = HPERM_OK;
-    } else {
-        if (s) return s;
-        for (int x = 0; x < np; ++x)
-            for (int k = 0; k < 8; ++k) values[(size_t)x * 8 + k] = res[(size_t)x].limb[k];
-    }
+    for (int x = 0; x < np; ++x)
+        for (int k = 0; k < 8; ++k) values[(size_t)x * 8 + k] = res[(size_t)x].limb[k];
     // p(x) = per(xI + A); c_k = (-1)^(n-k) a_k
     const hperm_status si = hperm_polynomial_interpolate(n, values.data(), 1, coeffs);
     if (si == HPERM_E_INVALID) return HPERM_E_INTERNAL;   // values from the device that no

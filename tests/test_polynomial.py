@@ -152,14 +152,19 @@ def test_library_matches_oracle(hperm):
 
 @pytest.mark.gpu
 def test_modular_polynomial_matches_oracle(hperm):
-    """Orders 23..64 past 2^180: the values modulo primes below 2^18 and the Chinese remainder
-    theorem. A cubic graph on 40 vertices (per(40I + A) about 2^217) against the oracle's
-    frontier DP and interpolation."""
+    """Orders 23..64 past 2^180: the polynomial modulo primes below 2^18 and the Chinese
+    remainder theorem on its coefficients. A cubic graph on 40 vertices (per(40I + A) about
+    2^217; the 0-1 bound on the coefficients) and a weighted cubic graph on 36 vertices with
+    diagonal entries (the row-sum bound) against the oracle's frontier DP and interpolation."""
+    rng = np.random.default_rng(40)
+    G = W.random_cubic_matrix(40, 0)
+    H = (W.random_cubic_matrix(36, 2).astype(np.int64) * rng.integers(1, 8, (36, 36))
+         + np.diag(rng.integers(0, 3, 36))).astype(np.uint32)
     c = hperm.Context()
     try:
-        G = W.random_cubic_matrix(40, 0)
-        got = c.permanental_polynomial(G)
-        assert got == perpoly_interpolate(G.astype(np.int64))
+        for A in (G, H):
+            got = c.permanental_polynomial(A)
+            assert got == perpoly_interpolate(A.astype(np.int64)), A.shape
     finally:
         c.close()
 
@@ -200,7 +205,7 @@ def test_c60_evaluations_equal_stored_polynomial(hperm):
     """C60 at full size on sampled points: per(xI + A) mod p on the device path equals
     sum_k |c_k| x^k mod p from the stored coefficients (x = 0, 1 and 60; per(60I + A) is about
     2^358). Each point with x > 0 is a tree of about 2e9 leaves (every row gains the diagonal),
-    so the whole polynomial (61 points, 21 primes) is a long run, not a test."""
+    so the whole polynomial (61 points, 7 primes) is a long run, not a test."""
     import time
     coeffs = c60_coefficients()
     A = W.adjacency_matrix(W.read_appendix_adjacency("c60")).astype(np.uint32)
