@@ -59,9 +59,24 @@ __device__ __forceinline__ uint32_t wave_excl(uint32_t v, int lane, uint32_t *to
     return x - v;
 }
 
+// The modulus of modular mode (p = 0: exact arithmetic), with its FP64 reciprocal.
+struct Modulus {
+    uint32_t p;
+    double pd, pinv;
+};
+__device__ __forceinline__ Modulus modulus(uint32_t p) { return Modulus{p, (double)p, p ? 1.0 / (double)p : 0.0}; }
+
 // A merged entry in the expansion's arithmetic: exact, or reduced modulo p in modular mode
-// (p > 0: per(A) modulo p, every entry kept below p).
-__device__ __forceinline__ uint64_t merged(uint64_t v, uint32_t modp) { return modp ? v % modp : v; }
+// (p > 0: per(A) modulo p, every entry kept below p). There v = ca q + cb p < 2^37, exact in
+// FP64: v - floor(v / p) p with the quotient off by at most one, corrected.
+__device__ __forceinline__ uint64_t merged(uint64_t v, const Modulus &m) {
+    if (!m.p) return v;
+    const double x = (double)v;
+    double r = __builtin_fma(-floor(x * m.pinv), m.pd, x);
+    r = r < 0.0 ? r + m.pd : r;
+    r = r >= m.pd ? r - m.pd : r;
+    return (uint64_t)r;
+}
 
 // A node's rows: lane holds rows lane and lane + 64 (length, first entry index).
 struct Rows {
@@ -245,7 +260,7 @@ __device__ __forceinline__ uint32_t nth_bit(uint64_t lo, uint64_t hi, uint32_t k
 __device__ __forceinline__ void write_children(const uint32_t *node, uint32_t key, uint64_t child_idx, uint64_t wbase,
                                                uint32_t *lenb, uint32_t *cst, uint32_t *__restrict__ out,
                                                uint64_t *__restrict__ out_off, unsigned long long *__restrict__ flags,
-                                               uint32_t modp, int lane) {
+                                               const Modulus &modp, int lane) {
     const uint32_t h0 = uni(node[0]);
     const int o = (int)(h0 & 0xffu);
     const float pbound = __uint_as_float(uni(node[1]));
@@ -486,7 +501,8 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
                                                   uint64_t first, uint32_t n, const uint32_t *__restrict__ keys,
                                                   const uint64_t *__restrict__ place,
                                                   uint32_t *__restrict__ out, uint64_t *__restrict__ out_off,
-                                                  unsigned long long *__restrict__ flags, uint32_t modp) {
+                                                  unsigned long long *__restrict__ flags, uint32_t prime) {
+    const Modulus modp = modulus(prime);
     __shared__ uint32_t len_all[BLK / WV][MAXO];
     __shared__ __attribute__((aligned(16))) uint32_t node_all[BLK / WV][NODE_LDS];
     __shared__ __attribute__((aligned(16))) uint32_t child_all[BLK / WV][NODE_LDS];

@@ -441,8 +441,10 @@ struct Region {
     uint32_t *lv0;                  // undo record of order t + 1 (main kernel)
     int S, mm, t, lw;
     uint32_t modp = 0;              // modular mode: merged entries reduced modulo this prime
+    ModP mp{0.0, 0.0};
     __device__ Region(uint32_t *l, int t_, int mm_, int table_words, uint32_t modp_ = 0)
         : S(dstride(mm_)), mm(mm_), t(t_), lw(lvl_words(mm_)), modp(modp_) {
+        if (modp_) mp = ModP{(double)modp_, 1.0 / (double)modp_};
         M = l;
         D = (int32_t *)(l + mm * S);
         rmask = (uint32_t *)(D + table_words);
@@ -453,6 +455,8 @@ struct Region {
         lv0 = cmap + 32;
     }
     __device__ uint32_t *lvl(int u) const { return lv0 + (u - t - 1) * lw; }   // u in t+1 .. mm
+    // a merged entry ca q + cb p (< 2^37) modulo the prime, in FP64 (no integer division)
+    __device__ uint32_t reduce(uint64_t v) const { return (uint32_t)red_f((double)v, mp); }
 };
 
 // An undo record (order u): the split's weights ca0, cb0, ca1, cb1; one packed word (is_col,
@@ -649,7 +653,7 @@ __device__ __forceinline__ bool plan_split_t(const Region &rg, uint32_t AR, uint
             pv.q[c] = COL ? M[Q * S + k] : M[k * S + Q];
             pv.p[c] = COL ? M[P * S + k] : M[k * S + P];
             uint64_t mv = ca * pv.q[c] + cb * pv.p[c];
-            if (rg.modp) mv %= rg.modp;
+            if (rg.modp) mv = rg.reduce(mv);
             bool bad = mv >= HP_MAX_ENTRY;
             if (!COL) bad = bad || (uint64_t)ln.rs - pv.q[c] - pv.p[c] + mv >= HP_MAX_ROWSUM;
             fail = fail || (live && bad);
@@ -723,7 +727,7 @@ __device__ __forceinline__ void apply_child_t(const Region &rg, const Plan &pl, 
         if (row) {
             const uint32_t mq = pv ? (ch ? pv->q[1] : pv->q[0]) : M[k * S + Q];
             const uint32_t mp = pv ? (ch ? pv->p[1] : pv->p[0]) : M[k * S + P];
-            mv = rg.modp ? (uint32_t)(((uint64_t)ca * mq + (uint64_t)cb * mp) % rg.modp) : ca * mq + cb * mp;
+            mv = rg.modp ? rg.reduce((uint64_t)ca * mq + (uint64_t)cb * mp) : ca * mq + cb * mp;
             ln.msk = (ln.msk & ~(kb | db)) | (mv ? kb : 0u);
             ln.rs = ln.rs - mq - mp + mv;
             M[k * S + keep] = mv;   // each lane rewrites its own row: no other lane reads it here
@@ -744,7 +748,7 @@ __device__ __forceinline__ void apply_child_t(const Region &rg, const Plan &pl, 
         if (col) {
             const uint32_t mq = pv ? (ch ? pv->q[1] : pv->q[0]) : M[Q * S + k];
             const uint32_t mp = pv ? (ch ? pv->p[1] : pv->p[0]) : M[P * S + k];
-            mv = rg.modp ? (uint32_t)(((uint64_t)ca * mq + (uint64_t)cb * mp) % rg.modp) : ca * mq + cb * mp;
+            mv = rg.modp ? rg.reduce((uint64_t)ca * mq + (uint64_t)cb * mp) : ca * mq + cb * mp;
             ln.msk = (ln.msk & ~(kb | db)) | (mv ? kb : 0u);
             M[keep * S + k] = mv;   // each lane rewrites its own column's entry
         }
@@ -1002,7 +1006,7 @@ __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hp
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
     const Region rg(lds, a.t, a.mm, leaf_table_words(), MOD ? a.modp : 0u);   // exact kernel: 0, folded
-    const ModP mp{(double)a.modp, a.modp ? 1.0 / (double)a.modp : 0.0};
+    const ModP mp = rg.mp;
     uint64_t n_leaves = 0, n_terms = 0, n_splits = 0, n_stops = 0, n_bad = 0, n_wide = 0;
     u128 pacc = 0;            // this wave's sum for problem pcur (nodes)
     uint32_t pcur = 0xffffffffu;
@@ -1121,7 +1125,7 @@ __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
     const Region rg(lds, a.t, a.mm, a.mm * dstride(a.mm), MOD ? a.modp : 0u);
-    const ModP mp{(double)a.modp, a.modp ? 1.0 / (double)a.modp : 0.0};
+    const ModP mp = rg.mp;
     const uint64_t n = min((uint64_t)a.stats[4], (uint64_t)a.wide_cap);
     for (uint64_t w = blockIdx.x; w < n; w += gridDim.x) {
         const WideLeaf wl = a.wide[w];
