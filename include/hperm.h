@@ -174,8 +174,17 @@ size_t hperm_ctx_arena_required(const hperm_ctx *ctx);
  * col_idx[nnz] strictly increasing within a row, values val[nnz] (uint32, zeros allowed).
  * The problem statement of Algorithm H_per (Section 2.1) with non-negative integer entries.
  * n = 0 gives 1; a zero row or column gives 0 without GPU work.
+ * Paths: the device expansion and continuation in exact rings (order above opts.device_expand,
+ * proven bound below 2^102), else the host expansion with R-NW (bound below 2^180). When
+ * either refuses a problem for its range (an expanded entry reaching 2^22, a row sum 2^24, or
+ * the bound) and the problem's order exceeds opts.device_expand (in effect), it is evaluated
+ * exactly by residues instead: the device path modulo K + 1 primes p with n (p - 1) < 2^24
+ * (hperm_permanent_mod_batch_csr), K of them covering the bound min(prod row sums, prod column
+ * sums), rebuilt by the Chinese remainder theorem and checked against the last (arith_mask
+ * then names the residue ring).
  * Errors: HPERM_E_INVALID (n < 0 or n > 128, malformed CSR); HPERM_E_RANGE (an expanded
- * entry reaches 2^22 or a row sum 2^24, or the proven bound on per(A) exceeds 2^180);
+ * entry reaches 2^22 or a row sum 2^24, or the proven bound on per(A) exceeds 2^180, for a
+ * problem the residue evaluation does not take; or a bound beyond 2^500);
  * HPERM_E_DEVICE; HPERM_E_NOMEM (device memory, or the job table outgrows max_table_mib);
  * HPERM_E_INTERNAL. */
 hperm_status hperm_permanent_csr(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
@@ -217,10 +226,11 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *ctx, int32_t count, const int3
  * Nijenhuis-Wilf sum taken modulo the prime and normalised by the inverse of 2^(p-1), sums of
  * residues. Entries are reduced on entry, so no bound applies: the residues of values of any
  * size, for exact reconstruction by the Chinese remainder theorem over several primes (the
- * permanental polynomial beyond 2^180). prime: an odd prime below 2^18 (so every row sum of a
- * node of order <= 64 stays below 2^24). Every n[k] must exceed the device expansion's order
- * (opts.device_expand, 22 when off) and be at most 64; opts.split_order (12 when off) is the
- * continuation's target. residues[count] (caller-owned) receives per(A_k) mod prime.
+ * permanental polynomial beyond 2^180, per(A) beyond the exact paths' range). prime: an odd
+ * prime below 2^18 with n[k] (prime - 1) < 2^24 (so every row sum of a node stays below 2^24).
+ * Every n[k] must exceed the device expansion's order (opts.device_expand, 22 when off) and be
+ * at most 128; opts.split_order (12 when off) is the continuation's target. residues[count]
+ * (caller-owned) receives per(A_k) mod prime.
  * Errors: HPERM_E_INVALID (bad arrays, orders, a modulus that is not an odd prime below 2^18,
  * or the context is serving), HPERM_E_NOMEM, HPERM_E_DEVICE, HPERM_E_INTERNAL. */
 hperm_status hperm_permanent_mod_batch_csr(hperm_ctx *ctx, int32_t count, const int32_t *n,
@@ -485,9 +495,11 @@ typedef struct hperm_launch_stat {
                                (device_expand): then n_jobs = its jobs of order T, items = the
                                nodes it wrote, row_updates = its device H_per launches, ms =
                                the whole group on the device and alg_slots = the milliseconds
-                               of its device H_per launches */
-    int32_t reserved;       /* variant 3: the launch's resident waves; variant 4: the problems
-                               of the group */
+                               of its device H_per launches; 5 for such a group evaluated by
+                               residues (ring 2; the figures summed over its primes, and
+                               row_updates = the number of primes) */
+    int32_t reserved;       /* variant 3: the launch's resident waves; variant 4 or 5: the
+                               problems of the group */
     uint64_t items;         /* work items (64 lanes x 2^chunk Gray indices each) */
     uint64_t terms;         /* subset-terms: sum of 2^(m-1) over the jobs */
     uint64_t row_updates;   /* row-value updates of the Gray steps inside lane chunks */

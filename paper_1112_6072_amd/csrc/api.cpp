@@ -1040,6 +1040,13 @@ int device_in_effect(const hperm_opts &o) {
     return (t > 0 && o.device_expand > t) ? o.device_expand : 0;
 }
 
+// Problems the residue evaluation can take when the exact paths refuse them (an entry or a
+// bound out of their range): order above the device expansion's, within its nodes.
+bool residue_path(const hperm_opts &o, int n) {
+    const int T = device_in_effect(o);
+    return T > 0 && n > T && n <= HP_MAX_N;
+}
+
 // Problems the device expansion takes: order above T and a proven bound below 2^102.
 bool device_path(const hperm_opts &o, const CsrView &v) {
     const int T = device_in_effect(o);
@@ -1298,8 +1305,9 @@ hperm_status hperm_permanent_mod_batch_csr(hperm_ctx *c, int32_t count, const in
                   val ? val + nz_off[k] : nullptr};
         const std::string why = validate_csr(v);
         if (!why.empty()) return set_error(c, HPERM_E_INVALID, "problem " + std::to_string(k) + ": " + why);
-        if (n[k] <= T || n[k] > 64)
-            return set_error(c, HPERM_E_INVALID, "modular evaluation: orders above the device expansion's, up to 64");
+        if (n[k] <= T || n[k] > HP_MAX_N || (uint64_t)n[k] * (prime - 1) >= (1u << 24))
+            return set_error(c, HPERM_E_INVALID,
+                             "modular evaluation: orders above the device expansion's, with n (p - 1) < 2^24");
     }
     const size_t budget = (size_t)(c->opts.device_expand_mib > 0 ? c->opts.device_expand_mib : 8192) << 20;
     std::vector<int> order_of((size_t)count);
@@ -1343,8 +1351,8 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
         if (!why.empty()) return set_error(c, HPERM_E_INVALID, "problem " + std::to_string(k) + ": " + why);
         (device_path(c->opts, v) ? dev_idx : host_idx).push_back(k);
     }
-    if (dev_idx.empty()) return batch_host_path(c, count, n, rp_off, nz_off, row_ptr, col_idx, val, out);
     std::vector<hperm_result> res(count);
+    std::vector<int> res_idx;   // problems for the residue evaluation
     if (!host_idx.empty()) {
         std::vector<int32_t> hn;
         std::vector<int64_t> hr, hz;
@@ -1356,8 +1364,31 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
         std::vector<hperm_result> hres(host_idx.size());
         hperm_status s = batch_host_path(c, (int32_t)host_idx.size(), hn.data(), hr.data(), hz.data(), row_ptr, col_idx,
                                          val, hres.data());
-        if (s) return s;
-        for (size_t q = 0; q < host_idx.size(); ++q) res[host_idx[q]] = hres[q];
+        if (s == HPERM_E_RANGE) {
+            // one problem at a time: those out of the host path's range (the 2^180 bound, or an
+            // expanded entry past 2^22) go to the residue evaluation where it takes them
+            for (size_t q = 0; q < host_idx.size(); ++q) {
+                const int k = host_idx[q];
+                s = batch_host_path(c, 1, hn.data() + q, hr.data() + q, hz.data() + q, row_ptr, col_idx, val,
+                                    hres.data() + q);
+                if (s == HPERM_E_RANGE && residue_path(c->opts, n[k])) {
+                    res_idx.push_back(k);
+                    s = HPERM_OK;
+                    continue;
+                }
+                if (s) return s;
+                res[k] = hres[q];
+            }
+            c->dev.last_error.clear();
+        } else if (s) {
+            return s;
+        } else {
+            for (size_t q = 0; q < host_idx.size(); ++q) res[host_idx[q]] = hres[q];
+        }
+        if (dev_idx.empty() && res_idx.empty()) {
+            for (int k = 0; k < count; ++k) out[k] = res[k];
+            return HPERM_OK;
+        }
     }
     if (host_idx.empty()) c->dev.launches.clear();
     const size_t budget = (size_t)(c->opts.device_expand_mib > 0 ? c->opts.device_expand_mib : 8192) << 20;
@@ -1377,6 +1408,12 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
         DexpStats st;
         hperm_status s = device_expand_group(&c->dev, grp, device_in_effect(c->opts), split_in_effect(c->opts),
                                              c->opts.s_leaf, budget, &totals, &st);
+        if (s == HPERM_E_RANGE) {   // an expanded entry past 2^22: the residue evaluation
+            for (size_t q = g0; q < g1; ++q) res_idx.push_back(order_of[q]);
+            c->dev.last_error.clear();
+            g0 = g1;
+            continue;
+        }
         if (s) return s;
         const double t1 = now_s();
         for (size_t q = g0; q < g1; ++q) {
@@ -1409,6 +1446,57 @@ hperm_status hperm_permanent_batch_csr(hperm_ctx *c, int32_t count, const int32_
         ls.deferred = st.deferred;
         ls.deferred_bound = st.deferred_bound;
         ls.alg_slots = st.split_s * 1e3;   // the device H_per launches' share of ms
+        c->dev.launches.push_back(ls);
+        g0 = g1;
+    }
+    // the residue evaluation, problems of one order together
+    std::stable_sort(res_idx.begin(), res_idx.end(), [&](int x, int y) { return n[x] < n[y]; });
+    for (size_t g0 = 0; g0 < res_idx.size();) {
+        size_t g1 = g0;
+        while (g1 < res_idx.size() && n[res_idx[g1]] == n[res_idx[g0]]) ++g1;
+        const double t0 = now_s();
+        std::vector<CsrView> grp;
+        for (size_t q = g0; q < g1; ++q) {
+            const int k = res_idx[q];
+            grp.push_back(CsrView{n[k], row_ptr + rp_off[k], col_idx + nz_off[k], val + nz_off[k]});
+        }
+        std::vector<U512> totals;
+        DexpStats st;
+        int np = 0;
+        const hperm_status s = device_expand_residues(&c->dev, grp, device_in_effect(c->opts), split_in_effect(c->opts),
+                                                      c->opts.s_leaf, budget, &totals, &st, &np);
+        if (s) return s;
+        const double t1 = now_s();
+        for (size_t q = g0; q < g1; ++q) {
+            hperm_result &r = res[res_idx[q]];
+            memset(&r, 0, sizeof(r));
+            fill_result(totals[q - g0], &r);
+            r.n_jobs = (int32_t)std::min<uint64_t>(st.jobs, 0x7fffffff);   // the group's figures, all primes
+            r.max_m = device_in_effect(c->opts);
+            r.arith_mask = 1 << (HPERM_ARITH_RES);
+            r.subset_terms = st.leaf_terms;
+            r.t_rnw_s = st.split_s;
+            r.t_expand_s = st.total_s - st.split_s;
+            r.t_total_s = t1 - t0;
+        }
+        hperm_launch_stat ls{};
+        ls.ring = HP_RES;
+        ls.bucket = bucket_of(device_in_effect(c->opts));
+        ls.n_jobs = (int32_t)std::min<uint64_t>(st.jobs, 0x7fffffff);
+        ls.persistent = 1;
+        ls.variant = 5;
+        ls.reserved = (int32_t)(g1 - g0);
+        ls.items = st.nodes;
+        ls.terms = st.leaf_terms;
+        ls.row_updates = np;
+        ls.ms = st.total_s * 1e3;
+        ls.leaves = st.leaves;
+        ls.leaf_terms = st.leaf_terms;
+        ls.splits = st.splits;
+        ls.split_stops = st.split_stops;
+        ls.deferred = st.deferred;
+        ls.deferred_bound = st.deferred_bound;
+        ls.alg_slots = st.split_s * 1e3;
         c->dev.launches.push_back(ls);
         g0 = g1;
     }

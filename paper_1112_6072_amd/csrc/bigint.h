@@ -2,6 +2,9 @@
 #pragma once
 #include <stdint.h>
 
+#include <cmath>
+#include <vector>
+
 namespace hp {
 
 typedef unsigned __int128 u128;
@@ -133,5 +136,63 @@ inline uint64_t powmod(uint64_t a, uint64_t e, uint64_t p) {
 
 // Inverse modulo a prime p (Fermat).
 inline uint64_t invmod(uint64_t a, uint64_t p) { return powmod(a, p - 2, p); }
+
+// Whether v is prime (trial division).
+inline bool is_prime_u32(uint32_t v) {
+    if (v < 2) return false;
+    for (uint32_t d = 2; (uint64_t)d * d <= v; ++d)
+        if (v % d == 0) return false;
+    return true;
+}
+
+// Odd primes below `below`, largest first, until their product exceeds 2^(bits + 1), then one
+// more (a check prime). Empty when the primes below `below` run out first.
+inline std::vector<uint32_t> residue_primes(uint32_t below, double bits) {
+    std::vector<uint32_t> p;
+    double cover = 0.0;
+    uint32_t q = below > 3 ? below - 1 : 0;
+    if (!(q & 1)) --q;
+    bool done = false;
+    for (; q >= 3; q -= 2)
+        if (is_prime_u32(q)) {
+            if (done) {
+                p.push_back(q);
+                return p;
+            }
+            p.push_back(q);
+            cover += std::log2((double)q);
+            done = cover > bits + 1.0;
+        }
+    return {};
+}
+
+// The value in [0, p_0 ... p_(K-1)) with residues r[k] modulo the distinct primes p[k] < 2^32
+// (Garner's mixed-radix form: x = v_0 + p_0 (v_1 + p_1 (v_2 + ...))). The product must stay
+// below 2^512.
+inline U512 crt_garner(const std::vector<uint32_t> &p, const uint64_t *r) {
+    const size_t K = p.size();
+    std::vector<uint64_t> v(K);
+    for (size_t k = 0; k < K; ++k) {
+        uint64_t t = 0, prod = 1;   // the mixed-radix value so far, and p_0 .. p_(k-1), modulo p_k
+        for (size_t j = k; j-- > 0;) t = (t * p[j] + v[j]) % p[k];
+        for (size_t j = 0; j < k; ++j) prod = prod * p[j] % p[k];
+        v[k] = (r[k] % p[k] + p[k] - t) % p[k] * invmod(prod, p[k]) % p[k];
+    }
+    U512 x;
+    for (size_t k = K; k-- > 0;) {
+        x.mul_u64(p[k]);
+        U512 a;
+        a.w[0] = v[k];
+        x.add(a);
+    }
+    return x;
+}
+
+// x modulo m (m < 2^63).
+inline uint64_t mod_u512(const U512 &x, uint64_t m) {
+    u128 r = 0;
+    for (int w = 7; w >= 0; --w) r = ((r << 64) | x.w[w]) % m;
+    return (uint64_t)r;
+}
 
 }  // namespace hp

@@ -197,17 +197,30 @@ struct DexpSample {
 hperm_status device_expand_problem(Dev *c, const CsrView &a, int T, int t, int s_leaf, size_t budget_bytes, U512 *out,
                                    DexpStats *stats, DexpSample *sample = nullptr);
 // The same for several problems of one order n > T at once: their trees share the level
-// buffers and the launches; out[k] receives per(A_k). modp (a prime below 2^18, orders up to 64):
-// modular mode, out[k] = per(A_k) mod modp (entries reduced on entry; no bound applies).
+// buffers and the launches; out[k] receives per(A_k). modp (a prime below 2^18 with
+// n (modp - 1) < 2^24): modular mode, out[k] = per(A_k) mod modp (entries reduced on entry; no
+// bound applies).
 hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int T, int t, int s_leaf,
                                  size_t budget_bytes, std::vector<U512> *out, DexpStats *stats,
                                  DexpSample *sample = nullptr, uint32_t modp = 0);
+// The largest modulus of modular mode for order n: min(2^18, (2^24 - 1) / n + 1).
+uint32_t residue_prime_limit(int n);
+// log2 of min(prod of row sums, prod of column sums), a bound on per(A) (0 for a zero line).
+double residue_bound_bits(const CsrView &a);
+// per(A_k) exactly for problems of one order n > T without the exact path's limits (entries and
+// bound): the device path in modular mode modulo K + 1 primes below residue_prime_limit(n), K of
+// them covering min(prod row sums, prod column sums), rebuilt by the Chinese remainder theorem
+// and checked against the last. The stats sum over the primes; *nprimes receives K + 1.
+hperm_status device_expand_residues(Dev *c, const std::vector<CsrView> &probs, int T, int t, int s_leaf,
+                                    size_t budget_bytes, std::vector<U512> *out, DexpStats *stats, int *nprimes);
 
 // The split order and the device expansion's job order in effect (0: off), and whether a
 // problem takes the device expansion (api.cpp).
 int split_in_effect(const hperm_opts &o);
 int device_in_effect(const hperm_opts &o);
 bool device_path(const hperm_opts &o, const CsrView &v);
+// Whether the residue evaluation takes a problem of order n the exact paths refuse for range.
+bool residue_path(const hperm_opts &o, int n);
 
 // per(A) of a problem from its device accumulator (limb sums + CRT of the residue sums).
 U512 prob_value(const ProbAcc &q);

@@ -259,8 +259,9 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, i
     std::vector<std::vector<uint32_t>> mva;
     std::vector<CsrView> reduced;
     if (modp) {
-        if (modp < 3 || modp >= (1u << 18) || (!probs_in.empty() && probs_in[0].n > 64))
-            return set_error(c, HPERM_E_INVALID, "modular device expansion: a prime below 2^18, orders up to 64");
+        for (const CsrView &a : probs_in)   // entries below p keep every row sum below 2^24
+            if (modp < 3 || modp >= (1u << 18) || (uint64_t)a.n * (modp - 1) >= (1u << 24))
+                return set_error(c, HPERM_E_INVALID, "modular device expansion: a prime p below 2^18 with n (p - 1) < 2^24");
         for (const CsrView &a : probs_in) {
             mrp.emplace_back();
             mci.emplace_back();
@@ -403,6 +404,81 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, i
     }
     *out = run.total;
     if (stats) *stats = run.st;
+    return HPERM_OK;
+}
+
+uint32_t residue_prime_limit(int n) {
+    return (uint32_t)std::min<uint64_t>(1u << 18, ((1u << 24) - 1) / (uint64_t)std::max(n, 1) + 1);
+}
+
+double residue_bound_bits(const CsrView &a) {
+    const int n = a.n;
+    std::vector<double> cs((size_t)n, 0.0);
+    double rb = 0.0, cb = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double rs = 0.0;
+        for (int32_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e) {
+            rs += a.val[e];
+            cs[(size_t)a.col_idx[e]] += a.val[e];
+        }
+        if (rs == 0.0) return 0.0;
+        rb += std::log2(rs);
+    }
+    for (int j = 0; j < n; ++j) {
+        if (cs[(size_t)j] == 0.0) return 0.0;
+        cb += std::log2(cs[(size_t)j]);
+    }
+    return std::min(rb, cb) * (1.0 + 1e-12);   // the sums' rounding
+}
+
+hperm_status device_expand_residues(Dev *c, const std::vector<CsrView> &probs, int T, int t, int s_leaf,
+                                    size_t budget_bytes, std::vector<U512> *out, DexpStats *stats, int *nprimes) {
+    out->assign(probs.size(), U512());
+    if (probs.empty()) return HPERM_OK;
+    const int n = probs[0].n;
+    // the largest proven bound over the problems
+    double bits = 0.0;
+    for (const CsrView &a : probs) {
+        if (a.n != n) return set_error(c, HPERM_E_INVALID, "residue evaluation: problems of one order");
+        bits = std::max(bits, residue_bound_bits(a));
+    }
+    const std::vector<uint32_t> primes = residue_primes(residue_prime_limit(n), bits);
+    double cover = 0.0;
+    for (uint32_t q : primes) cover += std::log2((double)q);
+    if (primes.empty() || cover > 511.0)
+        return set_error(c, HPERM_E_RANGE, "residue evaluation: the permanent bound exceeds 2^500");
+    const size_t K = primes.size() - 1, P = primes.size();
+    std::vector<uint64_t> r(probs.size() * P);
+    DexpStats all;
+    for (size_t j = 0; j < P; ++j) {
+        std::vector<U512> tot;
+        DexpStats st;
+        const hperm_status s = device_expand_group(c, probs, T, t, s_leaf, budget_bytes, &tot, &st, nullptr, primes[j]);
+        if (s) return s;
+        for (size_t k = 0; k < probs.size(); ++k) r[k * P + j] = tot[k].w[0];
+        all.jobs += st.jobs;
+        all.nodes += st.nodes;
+        all.max_level_nodes = std::max(all.max_level_nodes, st.max_level_nodes);
+        all.launches += st.launches;
+        all.relaunches += st.relaunches;
+        all.leaves += st.leaves;
+        all.leaf_terms += st.leaf_terms;
+        all.splits += st.splits;
+        all.split_stops += st.split_stops;
+        all.deferred += st.deferred;
+        all.deferred_bound += st.deferred_bound;
+        all.split_s += st.split_s;
+        all.total_s += st.total_s;
+    }
+    const std::vector<uint32_t> base(primes.begin(), primes.begin() + (long)K);
+    for (size_t k = 0; k < probs.size(); ++k) {
+        const uint64_t *rk = r.data() + k * P;
+        (*out)[k] = crt_garner(base, rk);
+        if (mod_u512((*out)[k], primes[K]) != rk[K])
+            return set_error(c, HPERM_E_INTERNAL, "residue evaluation: the check prime disagrees");
+    }
+    if (stats) *stats = all;
+    if (nprimes) *nprimes = (int)P;
     return HPERM_OK;
 }
 

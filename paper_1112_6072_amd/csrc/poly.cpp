@@ -59,49 +59,6 @@ void add_diagonal(int32_t n, const int32_t *rp, const int32_t *ci, const uint32_
     orp.push_back((int32_t)(oci.size() - base));
 }
 
-uint64_t powmod(uint64_t b, uint64_t e, uint64_t m) {
-    uint64_t r = 1 % m;
-    b %= m;
-    for (; e; e >>= 1) {
-        if (e & 1) r = r * b % m;
-        b = b * b % m;
-    }
-    return r;
-}
-
-bool is_prime(uint32_t v) {
-    if (v < 2) return false;
-    for (uint32_t d = 2; d * d <= v; ++d)
-        if (v % d == 0) return false;
-    return true;
-}
-
-// The value in [0, prod p) with the given residues (Garner's mixed-radix form).
-U512 crt(const std::vector<uint32_t> &p, const uint64_t *r) {
-    const size_t K = p.size();
-    std::vector<uint64_t> v(K);
-    for (size_t k = 0; k < K; ++k) {
-        uint64_t t = 0, prod = 1;   // the mixed-radix value so far modulo p_k, and p_0..p_{k-1} mod p_k
-        for (size_t j = k; j-- > 0;) t = (t * p[j] + v[j]) % p[k];
-        for (size_t j = 0; j < k; ++j) prod = prod * p[j] % p[k];
-        v[k] = (r[k] % p[k] + p[k] - t) % p[k] * powmod(prod, p[k] - 2, p[k]) % p[k];
-    }
-    U512 x;
-    for (size_t k = K; k-- > 0;) {
-        x.mul_u64(p[k]);
-        U512 a;
-        a.w[0] = v[k];
-        x.add(a);
-    }
-    return x;
-}
-
-uint64_t mod_u512(const U512 &x, uint64_t m) {
-    hp::u128 r = 0;
-    for (int w = 7; w >= 0; --w) r = ((r << 64) | x.w[w]) % m;
-    return (uint64_t)r;
-}
-
 // The coefficients of the degree-n polynomial through (x, y_x), x = 0..n, modulo the prime
 // p > n: forward differences, Newton coefficients Delta^k p(0) / k!, and Horner's rule in the
 // falling-factorial basis, as in the exact interpolation.
@@ -113,7 +70,7 @@ std::vector<uint64_t> interpolate_mod(const std::vector<uint64_t> &y, uint64_t p
     uint64_t fact = 1;
     for (size_t k = 2; k < np; ++k) {
         fact = fact * k % p;
-        d[k] = d[k] * powmod(fact, p - 2, p) % p;
+        d[k] = d[k] * hp::invmod(fact, p) % p;
     }
     std::vector<uint64_t> poly(np, 0);
     poly[0] = d[np - 1];
@@ -227,19 +184,12 @@ hperm_status modular_polynomial(hperm_ctx *ctx, int32_t n, const int32_t *row_pt
     long double emax = 1.0L;
     for (int j = 0; j < np; ++j) emax = std::max(emax, e[(size_t)j]);
     const double bound = (double)std::log2(emax) * (1.0 + 1e-9) + 1.0;   // rounding of the sums
-    std::vector<uint32_t> primes;
+    // (residue_primes adds one more bit)
+    const std::vector<uint32_t> primes = hp::residue_primes(1u << 18, bound);
+    if (primes.empty()) return HPERM_E_RANGE;
     double cover = 0.0;
-    for (uint32_t q = (1u << 18) - 1; q > 3 && cover <= bound + 1.0; q -= 2)
-        if (is_prime(q)) {
-            primes.push_back(q);
-            cover += std::log2((double)q);
-        }
+    for (uint32_t q : primes) cover += std::log2((double)q);
     if (cover > 500.0) return HPERM_E_RANGE;   // beyond the 512-bit coefficients
-    for (uint32_t q = primes.back() - 2; q > 3; q -= 2)   // one more prime: the check
-        if (is_prime(q)) {
-            primes.push_back(q);
-            break;
-        }
     const size_t K = primes.size() - 1;
     std::vector<uint64_t> cr((size_t)np * primes.size());   // coefficient x prime
     for (size_t j = 0; j < primes.size(); ++j) {
@@ -253,8 +203,8 @@ hperm_status modular_polynomial(hperm_ctx *ctx, int32_t n, const int32_t *row_pt
     const std::vector<uint32_t> base(primes.begin(), primes.begin() + (long)K);
     for (int k = 0; k < np; ++k) {
         const uint64_t *rk = cr.data() + (size_t)k * primes.size();
-        const U512 a = crt(base, rk);
-        if (mod_u512(a, primes[K]) != rk[K]) return HPERM_E_INTERNAL;   // residues that disagree
+        const U512 a = hp::crt_garner(base, rk);
+        if (hp::mod_u512(a, primes[K]) != rk[K]) return HPERM_E_INTERNAL;   // residues that disagree
         memset(&coeffs[k], 0, sizeof(hperm_coeff));
         for (int w = 0; w < 8; ++w) coeffs[k].limb[w] = a.w[w];
         coeffs[k].nlimb = a.nlimb();

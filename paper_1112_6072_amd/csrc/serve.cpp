@@ -10,9 +10,13 @@
 //
 // Requests the device expansion takes (order above its job order, bound below 2^102) skip the
 // host expansion: a device lane runs them, with the other waiting requests of the same order,
-// by the device expansion on a stream of its own, so they overlap the batches. With a work
-// limit, a request whose estimated GPU time (Knuth's estimate of its expansion tree, rated at
-// the device path's measured leaf and subset-term rates) exceeds the limit is refused.
+// by the device expansion on a stream of its own, so they overlap the batches. Requests the
+// host expansion refuses for range (an expanded entry past 2^22, or the 2^180 bound) go to the
+// device lane too when their order exceeds the device expansion's: it evaluates them exactly by
+// residues (one device pass per prime, the Chinese remainder theorem). With a work limit, a
+// request whose estimated GPU time (Knuth's estimate of its expansion tree, rated at the
+// device path's measured leaf and subset-term rates, times twice the primes by residues)
+// exceeds the limit is refused.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -42,6 +46,7 @@ struct Request {
     size_t bytes = 0;   // device bytes of this request's share of a batch
     uint64_t wide = 0;  // bound on its deferred wide leaves (device H_per)
     bool device = false;   // run by the device lane
+    bool residues = false; // ... by residues (the exact paths refuse it for range)
     hperm_result result{};
     hperm_status status = HPERM_OK;
     std::string err;
@@ -135,6 +140,7 @@ struct Serving {
                 r->state = Request::EXPANDING;
             }
             const CsrView view{r->n, r->rp.data(), r->ci.data(), r->val.data()};
+            double est_ms = 0.0;   // the work estimate (0 without a limit)
             if (ctx->opts.serve_limit_ms > 0 && r->n > 0) {
                 // admission by work: Knuth's estimate of the tree, rated at about 5 ns per leaf
                 // of the device continuation and 0.5 ns per R-NW subset-term
@@ -146,6 +152,7 @@ struct Serving {
                                              leaves.data());
                 double ms = 0.0;
                 for (int p = 0; p <= r->n; ++p) ms += leaves[(size_t)p] * (5e-6 + std::ldexp(5e-10, p - 1));
+                if (rc == 0) est_ms = ms;
                 if (rc == 0 && ms > o.serve_limit_ms) {
                     std::lock_guard<std::mutex> lk(mu);
                     r->status = HPERM_E_TOOBIG;
@@ -180,6 +187,25 @@ struct Serving {
                 r->jobs.tab = JobTable();
                 r->state = Request::DONE;
                 r->t_done = now_s();
+            } else if (rc == -2 && residue_path(ctx->opts, r->n)) {
+                // out of the exact paths' range: the device lane evaluates it by residues, one
+                // device pass per prime (each rated at twice the exact pass's work)
+                r->jobs.tab = JobTable();
+                const size_t np = residue_primes(residue_prime_limit(r->n), residue_bound_bits(view)).size();
+                const double ms = est_ms * 2.0 * (double)np;
+                if (ctx->opts.serve_limit_ms > 0 && ms > ctx->opts.serve_limit_ms) {
+                    r->status = HPERM_E_TOOBIG;
+                    r->err = "estimated work " + std::to_string((long long)ms) + " ms by residues (" +
+                             std::to_string(np) + " primes) exceeds the serving limit of " +
+                             std::to_string(ctx->opts.serve_limit_ms) + " ms";
+                    r->state = Request::DONE;
+                    r->t_done = now_s();
+                } else {
+                    r->device = true;
+                    r->residues = true;
+                    r->state = Request::READY;
+                    dev_ready.push_back(r);
+                }
             } else if (rc) {
                 r->status = rc == -2 ? HPERM_E_RANGE : rc == -3 ? HPERM_E_NOMEM : HPERM_E_INVALID;
                 r->err = err;
@@ -305,7 +331,8 @@ struct Serving {
     }
 
     // The device lane: the oldest waiting request's order and every waiting request of that
-    // order, expanded on the device together.
+    // order (and of its kind: exact, or by residues), expanded on the device together. An exact
+    // group refused for range (an expanded entry past 2^22) is evaluated again by residues.
     void device_loop() {
         const size_t budget = (size_t)(ctx->opts.device_expand_mib > 0 ? ctx->opts.device_expand_mib : 8192) << 20;
         for (;;) {
@@ -315,8 +342,9 @@ struct Serving {
                 cv.wait(lk, [&] { return stopping || !dev_ready.empty(); });
                 if (stopping) return;
                 const int n = dev_ready.front()->n;
+                const bool byres = dev_ready.front()->residues;
                 for (auto it = dev_ready.begin(); it != dev_ready.end();) {
-                    if ((*it)->n == n) {
+                    if ((*it)->n == n && (*it)->residues == byres) {
                         grp.push_back(*it);
                         it = dev_ready.erase(it);
                     } else {
@@ -335,8 +363,16 @@ struct Serving {
             devx.tune = ctx->dev.tune;
             std::vector<U512> totals;
             DexpStats st;
-            const hperm_status s = device_expand_group(&devx, views, device_in_effect(devx.opts),
-                                                       split_in_effect(devx.opts), devx.opts.s_leaf, budget, &totals, &st);
+            bool byres = grp[0]->residues;
+            hperm_status s = HPERM_OK;
+            if (!byres) {
+                s = device_expand_group(&devx, views, device_in_effect(devx.opts), split_in_effect(devx.opts),
+                                        devx.opts.s_leaf, budget, &totals, &st);
+                byres = s == HPERM_E_RANGE && residue_path(devx.opts, grp[0]->n);
+            }
+            if (byres)
+                s = device_expand_residues(&devx, views, device_in_effect(devx.opts), split_in_effect(devx.opts),
+                                           devx.opts.s_leaf, budget, &totals, &st, nullptr);
             std::lock_guard<std::mutex> lk(mu);
             const double t = now_s();
             for (size_t k = 0; k < grp.size(); ++k) {
@@ -349,7 +385,7 @@ struct Serving {
                     fill_result(totals[k], &r->result);
                     r->result.n_jobs = (int32_t)std::min<uint64_t>(st.jobs, 0x7fffffff);
                     r->result.max_m = device_in_effect(devx.opts);
-                    r->result.arith_mask = 1 << HPERM_ARITH_W64;
+                    r->result.arith_mask = 1 << (byres ? HPERM_ARITH_RES : HPERM_ARITH_W64);
                     r->result.subset_terms = st.leaf_terms;
                     r->result.t_rnw_s = st.split_s;
                 }
