@@ -115,8 +115,9 @@ def serving_leg(hp, W, n_requests: int = 48, seed: int = 7, n_lo: int = 30, n_hi
     small-integer sparse matrices, n uniform in [n_lo, n_hi]). First the whole stream at once
     (capacity = served requests / makespan), then Poisson arrivals at half that rate; latencies
     are the library's submit-to-completion times of the served requests. Requests whose
-    estimated work exceeds limit_ms are refused (HPERM_E_TOOBIG), and integer requests whose
-    expansion leaves the supported entry range are refused (HPERM_E_RANGE); both are counted."""
+    estimated work exceeds limit_ms are refused (HPERM_E_TOOBIG); integer requests whose
+    expansion leaves the exact paths' entry range are served by residues (the device path modulo
+    primes, CRT), counted apart, and refused (HPERM_E_RANGE) only beyond that path's reach."""
     import numpy as np
     reqs = [A for _, A in W.serving_requests(n_requests, seed, n_lo, n_hi)]
     ctx = hp.Context({"m_cut": 20, "trials": 32, "host_threads": 4, "serve_limit_ms": limit_ms})
@@ -156,8 +157,10 @@ def serving_leg(hp, W, n_requests: int = 48, seed: int = 7, n_lo: int = 30, n_hi
     errs = [st.get("error") for v, st in burst if v is None]
     same = [v for v, _ in burst] == [v for v, _ in paced]
     served_n = [A.shape[0] for A, (v, _) in zip(reqs, burst) if v is not None]
+    by_res = [A.shape[0] for A, (v, st) in zip(reqs, burst) if v is not None and st.get("arith_mask") == 1 << 3]
     return {"requests": n_requests, "n_range": [n_lo, n_hi], "work_limit_ms": limit_ms,
-            "served": served, "refused_work_limit": errs.count(-9), "refused_entry_range": errs.count(-2),
+            "served": served, "served_by_residues": len(by_res), "served_by_residues_n": sorted(by_res),
+            "refused_work_limit": errs.count(-9), "refused_entry_range": errs.count(-2),
             "failed_other": len(errs) - errs.count(-9) - errs.count(-2),
             "served_n_max": max(served_n) if served_n else None,
             "mix": "1/3 each: 3-regular 0-1, 4-regular 0-1, 3-permutation union with values 1..4",

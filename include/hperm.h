@@ -345,9 +345,10 @@ hperm_status hperm_device_expand_sample(hperm_ctx *ctx, int32_t n, const int32_t
  * 2.1: split while the sparsest line has 1..4 nonzeros) down to the target order t of the device
  * continuation (m_cut when it is off). Along a descent the product of the child counts above a
  * node estimates the number of nodes at its order without bias. nodes[n + 1] and leaves[n + 1]
- * receive the estimated nodes and leaves of each order 0..n (mean over the descents). seed
- * drives SplitMix64. Errors: HPERM_E_INVALID (options, malformed matrix, NULL arrays,
- * samples < 1), HPERM_E_RANGE (an expanded entry beyond the supported range). */
+ * receive the estimated nodes and leaves of each order 0..n (mean over the descents). The
+ * tree's shape depends on the nonzero pattern only, so the descents walk the 0-1 pattern: any
+ * entry values are accepted. seed drives SplitMix64. Errors: HPERM_E_INVALID (options,
+ * malformed matrix, NULL arrays, samples < 1). */
 hperm_status hperm_tree_estimate(const hperm_opts *opts, int32_t n, const int32_t *row_ptr,
                                  const int32_t *col_idx, const uint32_t *val, int32_t samples,
                                  uint64_t seed, double *nodes, double *leaves);

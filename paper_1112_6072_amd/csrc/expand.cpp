@@ -959,6 +959,9 @@ int pack_root_node(const CsrView &a, std::vector<uint32_t> *out, double *log2b) 
 // Knuth's estimator of the size of the expansion tree: random root-to-leaf descents, each child
 // taken with equal probability; along a path, the product of the child counts of the nodes
 // above a node is an unbiased estimate of the number of nodes at that depth (here: order).
+// The tree's shape depends on the nonzero pattern only (a merged entry ca q + cb p with ca, cb
+// > 0 is nonzero exactly when q or p is), so the descents walk the 0-1 pattern, every child's
+// entries reset to 1: no value can leave the entry range.
 int estimate_tree(const CsrView &a, int T, int t, int s_leaf, int samples, uint64_t seed, double *nodes,
                   double *leaves) {
     const int n = a.n;
@@ -975,7 +978,7 @@ int estimate_tree(const CsrView &a, int T, int t, int s_leaf, int samples, uint6
         for (int e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e)
             if (a.val[e]) {
                 root.ci[o] = (uint8_t)a.col_idx[e];
-                root.v[o++] = a.val[e];
+                root.v[o++] = 1;
             }
     }
     root.rp[n] = o;
@@ -1017,6 +1020,7 @@ int estimate_tree(const CsrView &a, int T, int t, int s_leaf, int samples, uint6
                     make_child_col(cur, line, pairs[k].p, pairs[k].q, pairs[k].ca, pairs[k].cb, &nxt);
                 else
                     make_child(cur, line, pairs[k].p, pairs[k].q, pairs[k].ca, pairs[k].cb, &nxt);
+                for (int e = 0; e < nxt.nnz; ++e) nxt.v[e] = 1;
                 std::swap(cur, nxt);
                 w *= np;
             }

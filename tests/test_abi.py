@@ -185,3 +185,19 @@ def test_tree_estimate_exact_and_unbiased(hp):
         exact = len(expand_leaves(np.asarray(A, dtype=np.int64), 12, 10 ** 9, 40))
         _, lv = hp.tree_estimate(A, samples=20000, seed=5, split_order=12, device_expand=12, m_cut=12)
         assert abs(lv.sum() - exact) <= 0.05 * exact, (lv.sum(), exact)
+
+
+def test_tree_estimate_any_values(hp):
+    """The tree's shape depends on the nonzero pattern only: the estimate for an integer matrix
+    whose expansion leaves the exact entry range (a union of three permutations, values 1..4,
+    48 vertices) equals its 0-1 pattern's with the same descents, and is close to the oracle's
+    exact leaf count of the valued matrix."""
+    A = W.permutation_union_matrix(48, 3, 48)
+    P = (A > 0).astype(np.uint32)
+    kw = dict(split_order=12, device_expand=12, m_cut=12)
+    a = hp.tree_estimate(A, samples=500, seed=3, **kw)
+    b = hp.tree_estimate(P, samples=500, seed=3, **kw)
+    assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
+    exact = len(expand_leaves(A.astype(np.int64), 12, 10 ** 9, 60))
+    _, lv = hp.tree_estimate(A, samples=20000, seed=5, **kw)
+    assert abs(lv.sum() - exact) <= 0.05 * exact, (lv.sum(), exact)

@@ -29,7 +29,7 @@ def out_of_range_cases():
         # expanded entries pass 2^22 on the host path (bounds 2^137, 2^163)
         ("union48", W.permutation_union_matrix(48, 3, 48)),
         ("union56", W.permutation_union_matrix(56, 3, 56)),
-        # the bound (2^463) passes the host path's 2^180
+        # the bound (2^425) passes the host path's 2^180
         ("cubic40_w2^10", (W.random_cubic_matrix(40, 11).astype(np.int64)
                            * rng.integers(1, 1 << 10, (40, 40))).astype(np.uint32)),
     ]
