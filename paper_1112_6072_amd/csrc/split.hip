@@ -268,6 +268,65 @@ __device__ __forceinline__ uint64_t walk_paired(int p, int lane, const int32_t *
     return (lane & 1) ? (uint64_t)0 - acc : acc;
 }
 
+// Product modulo 2^64 of rows LO..R-1 (any count >= 2).
+template <int R, int LO>
+__device__ __forceinline__ uint64_t rest_product(const int32_t (&f)[R]) {
+    if constexpr ((R - LO) % 2 == 0) return pair_product<R, LO>(f);
+    else return pair_product<R, LO + 1>(f) * (uint64_t)(int64_t)f[LO];
+}
+
+// Product modulo 2^64 of N = 2 or 3 row values.
+template <int N>
+__device__ __forceinline__ uint64_t small_product(const int32_t (&x)[N]) {
+    if constexpr (N == 2) return pmul(x[0], x[1]);
+    else return pmul(x[0], x[1]) * (uint64_t)(int64_t)x[2];
+}
+
+// The same share with the steps taken in blocks of four (9 <= p <= R): Gray column 0 touches
+// only rows 0..NA-1 and Gray column 1 only rows NA..NA+NB-1 (disjoint; filler rows that
+// neither touches pad the two groups). In the block of steps 4q .. 4q+3 every other column is
+// fixed and the four terms take both values of columns 0 and 1, with signs (-1)^(q+z) times
+// +, -, +, - in the reflected code's order, so their sum factors as
+//     (-1)^(q+z) (A0 - A1) (B0 - B1) P,
+// where A0, A1 are the products of rows 0..NA-1 without and with column 0, B0, B1 those of
+// rows NA..NA+NB-1 without and with column 1, P the product of the other rows, all taken with
+// columns 0 and 1 out (the values h). A block costs one product of the other rows, four small
+// ones and two multiplies, where the paired walk takes two products of the other rows.
+template <int R, int NA, int NB>
+__device__ __forceinline__ uint64_t walk_quad(int p, int lane, const int32_t *D) {
+    const uint32_t L = 1u << (p - 7);   // a multiple of 4
+    int32_t h[R];
+    start_rows<R>(h, p, lane, D);       // no Gray column below p - 7 is set: h itself
+    int32_t da[NA], db[NB];             // column 0's deltas on rows 0..NA-1, column 1's on NA..
+#pragma unroll
+    for (int i = 0; i < NA; ++i) da[i] = D[i];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) db[i] = D[PM + NA + i];
+    uint64_t acc = 0;
+    for (uint32_t s = 0;;) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            int32_t a0[NA], a1[NA], b0[NB], b1[NB];
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+                a0[i] = h[i];
+                a1[i] = h[i] + da[i];
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                b0[i] = h[NA + i];
+                b1[i] = h[NA + i] + db[i];
+            }
+            const uint64_t x = (small_product<NA>(a0) - small_product<NA>(a1)) *
+                               (small_product<NB>(b0) - small_product<NB>(b1)) * rest_product<R, NA + NB>(h);
+            acc = half ? acc - x : acc + x;   // blocks alternate in sign
+            s += 4;
+            if (s >= L) return (lane & 1) ? (uint64_t)0 - acc : acc;
+            add_rows<R>(h, flip_column(D, s));   // step s flips Gray column ctz(s) >= 2
+        }
+    }
+}
+
 // The replay kernel's walk modulo 2^128 over a table of stride ds (deltas only; a subtraction
 // is a branch: the replay is rare).
 template <int R>
@@ -806,7 +865,8 @@ __device__ __forceinline__ void restore_node(const Region &rg, int u, int ch, bo
 // column c0 (returned; *b its nonzero count, *touched its rows) is moved to Gray column 0 and
 // the rows it touches to the front (the product is invariant under both permutations).
 __device__ __forceinline__ uint32_t leaf_order(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
-                                               int lane, uint32_t *fx, uint32_t *b, uint32_t *touched) {
+                                               int lane, uint32_t *fx, uint32_t *b, uint32_t *touched,
+                                               uint32_t *lane_cmk = nullptr) {
     *fx = 31u - (uint32_t)__builtin_clz(AC);   // the fixed (last) column
     // mbcnt: the set bits of a mask below this lane (lanes < 32)
     if (lane < 32 && ((AC >> lane) & 1) && (uint32_t)lane != *fx) rg.cmap[__builtin_amdgcn_mbcnt_lo(AC, 0u)] = (uint32_t)lane;
@@ -817,7 +877,64 @@ __device__ __forceinline__ uint32_t leaf_order(const Region &rg, const Lines &ln
     const uint32_t cmk = lane < p - 1 ? cmk0 : 0u;
     const uint32_t c0 = argmin_lane((uint32_t)__popc(cmk), lane < p - 1, b);
     *touched = (uint32_t)__builtin_amdgcn_readlane((int)cmk, (int)c0);   // physical rows
+    if (lane_cmk) *lane_cmk = cmk;
     return c0;
+}
+
+// The main kernel's leaf layout. Gray column 0 is the sparsest column c0 (rows A); for the
+// four-step walk Gray column 1 is the sparsest column c1 whose rows B avoid A. Table rows: A,
+// then fillers (rows neither column touches) up to pa, then B, fillers up to pa + pb, then the
+// other rows, each group in physical order. Without the four-step walk pa = |A| and pb = |B|.
+struct LeafPlan {
+    uint32_t fx;        // the fixed (last) column
+    uint32_t c0, k1;    // c0; the position of c1 after c0 moved to Gray column 0 (1: none)
+    uint32_t ta, tb;    // physical rows of A and B
+    uint32_t na, nb;    // |A|, |B| (nb = 0: no c1)
+    uint32_t pa, pb;    // the groups' sizes in the table
+    bool quad;          // the four-step walk applies
+};
+
+__device__ __forceinline__ LeafPlan leaf_plan(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
+                                              int lane) {
+    LeafPlan lp;
+    uint32_t cmk;
+    lp.c0 = leaf_order(rg, ln, p, AR, AC, lane, &lp.fx, &lp.na, &lp.ta, &cmk);
+    const bool cand = lane < p - 1 && (uint32_t)lane != lp.c0 && (cmk & lp.ta) == 0u && cmk != 0u;
+    lp.nb = 0;
+    lp.tb = 0;
+    lp.k1 = 1;
+    if (__ballot(cand) != 0 && p >= 9 && lp.na <= 3) {
+        uint32_t nb;
+        const uint32_t c1 = argmin_lane((uint32_t)__popc(cmk), cand, &nb);
+        if (nb <= 3) {
+            lp.nb = nb;
+            lp.tb = (uint32_t)__builtin_amdgcn_readlane((int)cmk, (int)c1);
+            lp.k1 = c1 == 0u ? lp.c0 : c1;
+        }
+    }
+    lp.quad = lp.nb != 0;   // 1 <= |A| <= |B| <= 3 (c0 is the sparsest column)
+    lp.pa = lp.quad ? (lp.na <= 2 ? 2u : 3u) : lp.na;
+    lp.pb = lp.quad ? (lp.pa == 2u && lp.nb <= 2 ? 2u : 3u) : lp.nb;
+    return lp;
+}
+
+// Table row of the leaf's physical row r under the plan.
+__device__ __forceinline__ int leaf_row4(uint32_t r, const LeafPlan &lp, uint32_t AR) {
+    const uint32_t rb = (1u << r) - 1;
+    if ((lp.ta >> r) & 1) return __popc(lp.ta & rb);
+    if ((lp.tb >> r) & 1) return (int)lp.pa + __popc(lp.tb & rb);
+    const int fa = (int)(lp.pa - lp.na), fb = (int)(lp.pb - lp.nb);
+    const int o = __popc(AR & ~lp.ta & ~lp.tb & rb);
+    if (o < fa) return (int)lp.na + o;
+    if (o < fa + fb) return (int)(lp.pa + lp.nb) + (o - fa);
+    return (int)(lp.pa + lp.pb) + (o - fa - fb);
+}
+
+// The leaf's Gray column behind table column j: c0 moved to 0 (swapped with 0), then c1 to 1.
+__device__ __forceinline__ int leaf_col(int j, const LeafPlan &lp) {
+    const int c0 = (int)lp.c0, k = (int)lp.k1;
+    const int x = j == 1 ? k : (j == k ? 1 : j);
+    return x == 0 ? c0 : (x == c0 ? 0 : x);
 }
 
 // Table row of the leaf's physical row r: the rows c0 touches first, then the others, each in
@@ -831,10 +948,9 @@ __device__ __forceinline__ int leaf_row(uint32_t r, uint32_t touched, uint32_t b
 // 2 b_ij for Gray column j, D + TNEG + j PM + i its negative, D + 2 TNEG + i = base_i =
 // 2 b_{i,p-1} - R_i (rows p..PM-1: deltas 0, base 1, so f = 1). Returns Gray column 0's
 // nonzero count b. Needs p >= 2.
-__device__ __forceinline__ uint32_t leaf_tables(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
+__device__ __forceinline__ LeafPlan leaf_tables(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
                                                 int lane) {
-    uint32_t fx, b, touched;
-    const uint32_t c0 = leaf_order(rg, ln, p, AR, AC, lane, &fx, &b, &touched);
+    const LeafPlan lp = leaf_plan(rg, ln, p, AR, AC, lane);
     const uint32_t rsr = (uint32_t)__shfl((int)ln.rs, lane < p ? (int)rg.rmap[lane] : 0);   // row sum of table row `lane`
     const int S = rg.S;
     for (int e = lane; e < (p - 1) * PM; e += SW) {
@@ -843,9 +959,8 @@ __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, const Lines &l
         int pos = i;
         if (i < p) {
             const uint32_t r = rg.rmap[i];
-            pos = leaf_row(r, touched, b, AR);
-            const int g = j == 0 ? (int)c0 : (j == (int)c0 ? 0 : j);
-            v = 2 * (int32_t)rg.M[r * S + rg.cmap[g]];
+            pos = leaf_row4(r, lp, AR);
+            v = 2 * (int32_t)rg.M[r * S + rg.cmap[leaf_col(j, lp)]];
         }
         rg.D[j * PM + pos] = v;
         rg.D[TNEG + j * PM + pos] = -v;
@@ -855,13 +970,13 @@ __device__ __forceinline__ uint32_t leaf_tables(const Region &rg, const Lines &l
         int pos = lane;
         if (lane < p) {
             const uint32_t r = rg.rmap[lane];
-            pos = leaf_row(r, touched, b, AR);
-            v = 2 * (int32_t)rg.M[r * S + fx] - (int32_t)rsr;
+            pos = leaf_row4(r, lp, AR);
+            v = 2 * (int32_t)rg.M[r * S + lp.fx] - (int32_t)rsr;
         }
         rg.D[2 * TNEG + pos] = v;
     }
     wave_sync();
-    return b;
+    return lp;
 }
 
 // The replay kernel's tables (rows of stride S, every row of the node): D + j S + i = 2 b_ij,
@@ -898,9 +1013,16 @@ __device__ __forceinline__ void leaf_tables_wide(const Region &rg, const Lines &
 // 7 <= p <= PMAX.
 __device__ __forceinline__ uint64_t eval_leaf(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
                                               int lane) {
-    const uint32_t b = leaf_tables(rg, ln, p, AR, AC, lane);
+    const LeafPlan lp = leaf_tables(rg, ln, p, AR, AC, lane);
+    const uint32_t b = lp.na;
     uint64_t v;
-    if (p >= 8 && p <= 12 && b <= 2) v = walk_paired<12, 2>(p, lane, rg.D);
+    if (lp.quad) {   // p >= 9
+        const uint32_t k = lp.pa == 2 ? (lp.pb == 2 ? 0u : 1u) : 2u;
+        if (p <= 12) v = k == 0 ? walk_quad<12, 2, 2>(p, lane, rg.D)
+                               : (k == 1 ? walk_quad<12, 2, 3>(p, lane, rg.D) : walk_quad<12, 3, 3>(p, lane, rg.D));
+        else v = k == 0 ? walk_quad<16, 2, 2>(p, lane, rg.D)
+                        : (k == 1 ? walk_quad<16, 2, 3>(p, lane, rg.D) : walk_quad<16, 3, 3>(p, lane, rg.D));
+    } else if (p >= 8 && p <= 12 && b <= 2) v = walk_paired<12, 2>(p, lane, rg.D);
     else if (p >= 8 && p <= 12 && b <= 4) v = walk_paired<12, 4>(p, lane, rg.D);
     else if (p <= 12) v = walk_plain<12>(p, lane, rg.D);
     else if (b <= 2) v = walk_paired<16, 2>(p, lane, rg.D);

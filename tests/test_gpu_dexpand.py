@@ -14,6 +14,7 @@ import pytest
 
 import workloads as W
 from oracle import expand_leaves, native
+from oracle.permanent import per_dp
 
 pytestmark = pytest.mark.gpu
 
@@ -164,7 +165,7 @@ def test_random_cubic_100_first_jobs(hperm, seed):
 def test_device_expansion_limits(hperm):
     """Options out of range are refused; a problem at or below T, with a bound beyond 2^102 or
     with a zero column takes the host path; merged entries reaching 2^22 in the device
-    expansion are refused with HPERM_E_RANGE, never a wrong value."""
+    expansion leave the exact rings and are evaluated by residues."""
     with pytest.raises(hperm.HpermError):
         hperm.Context({"split_order": 12, "device_expand": 25})
     for opts in ({"split_order": 12, "device_expand": 12}, {"split_order": 0, "device_expand": 20}):
@@ -187,15 +188,17 @@ def test_device_expansion_limits(hperm):
         assert got == [native.hper_batch([small])[0], math.factorial(22), math.factorial(30), 0]
         assert kinds.count(4) == 1
         # column 0 holds 2^21 in every row (column-sum bound 2^55): the first split merges it
-        # into 2^22
+        # into 2^22, past the exact rings' entry limit; the group is evaluated again by residues
+        # (exact, never a wrong value)
         big = np.zeros((30, 30), np.uint32)
         big[:, 0] = 1 << 21
         for i in range(1, 30):
             big[i, i] = 1
         for i in range(29):
             big[i, i + 1] = 1
-        with pytest.raises(hperm.HpermError) as e:
-            c.permanent(big)
-        assert e.value.status == -2
+        got, st = c.permanent_batch([big], with_stats=True)
+        assert got == [per_dp(big.astype(np.int64).tolist())]
+        assert st[0]["arith_mask"] == 1 << 3
+        assert [l["variant"] for l in c.last_launches()][-1] == 5
     finally:
         c.close()

@@ -103,3 +103,22 @@ def test_serving_out_of_range_requests(hperm):
         assert [s["arith_mask"] == RES for _, s in out] == [True, False, True, False, False]
     finally:
         c.close()
+
+
+@pytest.mark.gpu
+def test_largest_order_by_residues(hperm):
+    """Order 128 (the largest input): per(2I + P) = 2^128 + 1 for the cyclic shift P, whose bound
+    3^128 = 2^203 passes the host path's 2^180, by residues (primes below 2^17, so that 128 (p - 1)
+    < 2^24); a bound beyond 2^500 (17^128) is refused."""
+    eye = np.eye(128, dtype=np.uint32)
+    P = np.roll(eye, 1, axis=1)
+    c = hperm.Context()
+    try:
+        got, st = c.permanent_batch([2 * eye + P], with_stats=True)
+        assert got == [2 ** 128 + 1]
+        assert st[0]["arith_mask"] == RES
+        with pytest.raises(hperm.HpermError) as e:
+            c.permanent(16 * eye + P)
+        assert e.value.status == -2
+    finally:
+        c.close()
