@@ -156,6 +156,7 @@ __device__ __forceinline__ u128 row_product128(const int32_t (&f)[R]) {
 // their negatives at D + TNEG + j PM, the base values at D + 2 TNEG; rows p..PM-1 padded (delta
 // 0, base 1).
 constexpr int PM = PMAX;                 // table stride: rows of the widest leaf
+static_assert(SW == 4 * PM, "leaf tables: one row per lane in each quarter of the wave");
 constexpr int TNEG = (PMAX - 1) * PMAX;
 __host__ __device__ constexpr int leaf_table_words() { return 2 * TNEG + PMAX; }
 
@@ -951,30 +952,18 @@ __device__ __forceinline__ int leaf_row(uint32_t r, uint32_t touched, uint32_t b
 __device__ __forceinline__ LeafPlan leaf_tables(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
                                                 int lane) {
     const LeafPlan lp = leaf_plan(rg, ln, p, AR, AC, lane);
-    const uint32_t rsr = (uint32_t)__shfl((int)ln.rs, lane < p ? (int)rg.rmap[lane] : 0);   // row sum of table row `lane`
-    const int S = rg.S;
-    for (int e = lane; e < (p - 1) * PM; e += SW) {
-        const int j = e / PM, i = e - j * PM;
-        int32_t v = 0;
-        int pos = i;
-        if (i < p) {
-            const uint32_t r = rg.rmap[i];
-            pos = leaf_row4(r, lp, AR);
-            v = 2 * (int32_t)rg.M[r * S + rg.cmap[leaf_col(j, lp)]];
-        }
+    // lane = logical row i (its table row computed once) and a quarter of the Gray columns
+    const int i = lane & (PM - 1), jq = lane >> 4;
+    const uint32_t r = i < p ? rg.rmap[i] : 0u;
+    const uint32_t rsr = (uint32_t)__shfl((int)ln.rs, (int)r);   // every lane takes part
+    const int pos = i < p ? leaf_row4(r, lp, AR) : i;            // padding rows keep their place
+    const uint32_t *Mr = rg.M + r * rg.S;
+    for (int j = jq; j < p - 1; j += SW / PM) {
+        const int32_t v = i < p ? 2 * (int32_t)Mr[rg.cmap[leaf_col(j, lp)]] : 0;
         rg.D[j * PM + pos] = v;
         rg.D[TNEG + j * PM + pos] = -v;
     }
-    if (lane < PM) {
-        int32_t v = 1;
-        int pos = lane;
-        if (lane < p) {
-            const uint32_t r = rg.rmap[lane];
-            pos = leaf_row4(r, lp, AR);
-            v = 2 * (int32_t)rg.M[r * S + lp.fx] - (int32_t)rsr;
-        }
-        rg.D[2 * TNEG + pos] = v;
-    }
+    if (jq == 0) rg.D[2 * TNEG + pos] = i < p ? 2 * (int32_t)Mr[lp.fx] - (int32_t)rsr : 1;
     wave_sync();
     return lp;
 }
