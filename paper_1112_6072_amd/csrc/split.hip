@@ -461,6 +461,69 @@ __device__ __forceinline__ uint64_t walk_mod_wide(int p, int lane, const int32_t
     return (uint64_t)v;
 }
 
+// The product of rows LO..R-1 modulo p (at least two rows; |f| < 2^23): exact pair products
+// reduced, chained (an odd count takes its first row as a single factor).
+template <int R, int LO>
+__device__ __forceinline__ double mod_rows(const int32_t (&f)[R], const ModP &m) {
+    constexpr int K = R - LO;
+    constexpr int P0 = LO + (K & 1);   // first row of the pairs
+    double r = red_f((double)f[P0] * (double)f[P0 + 1], m);
+#pragma unroll
+    for (int k = P0 + 2; k < R; k += 2) r = red_f(r * red_f((double)f[k] * (double)f[k + 1], m), m);
+    if constexpr (K & 1) r = red_f(r * (double)f[LO], m);
+    return r;
+}
+
+// The product of N = 2 or 3 row values modulo p.
+template <int N>
+__device__ __forceinline__ double mod_small(const int32_t (&x)[N], const ModP &m) {
+    double r = red_f((double)x[0] * (double)x[1], m);
+    if constexpr (N == 3) r = red_f(r * (double)x[2], m);
+    return r;
+}
+
+// The four-step walk (walk_quad) modulo p: the block sum (-1)^(q+z) (A0 - A1)(B0 - B1) P with
+// every factor reduced. Returns this lane's share in [0, p).
+template <int R, int NA, int NB>
+__device__ __forceinline__ uint64_t walk_mod_quad(int p, int lane, const int32_t *D, const ModP &m) {
+    const uint32_t L = 1u << (p - 7);   // a multiple of 4
+    int32_t h[R];
+    start_rows<R>(h, p, lane, D);
+    int32_t da[NA], db[NB];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) da[i] = D[i];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) db[i] = D[PM + NA + i];
+    double acc = 0.0;   // in [0, p)
+    for (uint32_t s = 0;;) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            int32_t a0[NA], a1[NA], b0[NB], b1[NB];
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+                a0[i] = h[i];
+                a1[i] = h[i] + da[i];
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                b0[i] = h[NA + i];
+                b1[i] = h[NA + i] + db[i];
+            }
+            const double da_ = mod_small<NA>(a0, m) - mod_small<NA>(a1, m) + m.p;   // [1, 2p)
+            const double db_ = mod_small<NB>(b0, m) - mod_small<NB>(b1, m) + m.p;
+            const double x = red_f(red_f(da_ * db_, m) * mod_rows<R, NA + NB>(h, m), m);
+            acc = half ? acc - x : acc + x;   // blocks alternate in sign
+            acc = acc < 0.0 ? acc + m.p : (acc >= m.p ? acc - m.p : acc);
+            s += 4;
+            if (s >= L) {
+                const double v = (lane & 1) ? (acc == 0.0 ? 0.0 : m.p - acc) : acc;
+                return (uint64_t)v;
+            }
+            add_rows<R>(h, flip_column(D, s));
+        }
+    }
+}
+
 // per(leaf) modulo p from the lanes' shares of V = (-1)^(p-1) 2^(p-1) per(leaf): the wave's sum,
 // times (-1)^(p-1) and the inverse of 2^(p-1) (2^-1 = (q + 1) / 2 for the odd prime q).
 __device__ __forceinline__ uint64_t mod_normalise(uint64_t share, int p, const ModP &m) {
@@ -1159,8 +1222,21 @@ __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hp
                 if (!ok64) ok64 = fminf(jb, rowsum_log2(ln, AR, lane)) + (float)o <= 62.5f;
                 if (!ok64 && o <= PMAX) ok64 = colsum_log2(rg, AR, AC, lane) + (float)o <= 62.5f;
                 if (MOD && o <= PMAX) {
-                    leaf_tables(rg, ln, o, AR, AC, lane);
-                    const uint64_t share = o <= 12 ? walk_mod<12>(o, lane, rg.D, mp) : walk_mod<16>(o, lane, rg.D, mp);
+                    const LeafPlan lp = leaf_tables(rg, ln, o, AR, AC, lane);
+                    uint64_t share;
+                    if (lp.quad) {
+                        const uint32_t k = lp.pa == 2 ? (lp.pb == 2 ? 0u : 1u) : 2u;
+                        if (o <= 12)
+                            share = k == 0 ? walk_mod_quad<12, 2, 2>(o, lane, rg.D, mp)
+                                           : (k == 1 ? walk_mod_quad<12, 2, 3>(o, lane, rg.D, mp)
+                                                     : walk_mod_quad<12, 3, 3>(o, lane, rg.D, mp));
+                        else
+                            share = k == 0 ? walk_mod_quad<16, 2, 2>(o, lane, rg.D, mp)
+                                           : (k == 1 ? walk_mod_quad<16, 2, 3>(o, lane, rg.D, mp)
+                                                     : walk_mod_quad<16, 3, 3>(o, lane, rg.D, mp));
+                    } else {
+                        share = o <= 12 ? walk_mod<12>(o, lane, rg.D, mp) : walk_mod<16>(o, lane, rg.D, mp);
+                    }
                     wave_sync();   // the tables are rewritten by the next leaf
                     acc += mod_normalise(share, o, mp);
                     if (acc >= (u128)rg.modp) acc -= rg.modp;
