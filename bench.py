@@ -594,6 +594,75 @@ def copy_probe(nbytes: int = 256 << 20, reps: int = 3):
     print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "reps": reps}))
 
 
+def c60_primes() -> list:
+    """The primes of the library's residue route for C60's permanental polynomial: the largest
+    primes below 2^18 whose product passes the coefficient bound max_k C(60, k) g^k (g =
+    (3!)^(1/3), Bregman's factor of a row with three ones) by more than a bit, then one more (the
+    check): the six largest."""
+    import math
+    g = 6 ** (1 / 3)
+    bound = max(math.log2(math.comb(60, k)) + k * math.log2(g) for k in range(61)) * (1 + 1e-9) + 1
+    out, cover, q, done = [], 0.0, (1 << 18) - 1, False
+    while True:
+        if all(q % d for d in range(2, int(q ** 0.5) + 1)):
+            out.append(q)
+            if done:
+                return out
+            cover += math.log2(q)
+            done = cover > bound + 1
+        q -= 2
+
+
+def c60_residues_part(j: int, batch: int = 8):
+    """per(xI + A) of C60 (the appendix's graph) modulo the j-th prime of c60_primes(), for
+    x = 0..60, on the device path in modular arithmetic, `batch` points per call (a progress line
+    after each); saved to gpurun_out/c60_residues_<j>.json for --c60-combine."""
+    import numpy as np
+    import paper_1112_6072_amd as hp
+    import workloads as W
+    primes = c60_primes()
+    A = W.adjacency_matrix(W.read_appendix_adjacency("c60")).astype(np.uint32)
+    eye = np.eye(60, dtype=np.uint32)
+    ctx = hp.Context()
+    res, device_s = [], 0.0
+    try:
+        for x0 in range(0, 61, batch):
+            xs = list(range(x0, min(61, x0 + batch)))
+            t0 = time.perf_counter()
+            res += ctx.permanent_mod_batch([A + np.uint32(x) * eye for x in xs], primes[j])
+            dt = time.perf_counter() - t0
+            device_s += dt
+            log(f"C60 prime {j} ({primes[j]}): x = {xs[0]}..{xs[-1]} in {dt:.1f} s")
+    finally:
+        ctx.close()
+    out = {"prime_index": j, "prime": primes[j], "residues": res, "seconds": device_s}
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(ROOT, "gpurun_out", f"c60_residues_{j}.json"), "w") as fh:
+        json.dump(out, fh)
+    print(json.dumps({k: v for k, v in out.items() if k != "residues"}), flush=True)
+
+
+def c60_combine():
+    """C60's permanental polynomial from the saved residues of every prime (host step of the
+    library: per-prime interpolation and the Chinese remainder theorem, checked against the last
+    prime), against the oracle's stored coefficients."""
+    import paper_1112_6072_amd as hp
+    primes = c60_primes()
+    parts = []
+    for j in range(len(primes)):
+        with open(os.path.join(ROOT, "gpurun_out", f"c60_residues_{j}.json")) as fh:
+            parts.append(json.load(fh))
+        assert parts[-1]["prime"] == primes[j]
+    coeffs = hp.polynomial_from_residues(primes, [p["residues"] for p in parts], alternate=True)
+    with open(os.path.join(ROOT, "tests", "golden", "c60_permanental_polynomial.json")) as fh:
+        want = [int(v) for v in json.load(fh)["coefficients"]]
+    seconds = sum(p["seconds"] for p in parts)
+    print(json.dumps({"graph": "C60 (appendix adjacency)", "primes": primes, "points": 61,
+                      "device_seconds": seconds, "seconds_per_point": seconds / (61 * len(primes)),
+                      "c60": coeffs[60], "c59": coeffs[59], "c58": coeffs[58], "c0": coeffs[0],
+                      "equal_to_oracle": coeffs == want}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -613,7 +682,17 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a device-to-device copy of 256 MiB three times (the reference kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
+    ap.add_argument("--c60-residues", type=int, default=None, metavar="J",
+                    help="only per(xI + A) of C60 modulo the J-th of its polynomial's six primes, x = 0..60")
+    ap.add_argument("--c60-combine", action="store_true",
+                    help="only C60's permanental polynomial from the saved residues of all six primes")
     args = ap.parse_args()
+    if args.c60_residues is not None:
+        c60_residues_part(args.c60_residues)
+        return
+    if args.c60_combine:
+        c60_combine()
+        return
     if args.profile_split:
         split_profile_run()
         return

@@ -258,7 +258,7 @@ typedef struct hperm_coeff {
  * a_k is rebuilt by the Chinese remainder theorem over K primes whose product exceeds a bound
  * on the coefficients (a_k <= e_{n-k}(g), the elementary symmetric function of g_i = the row
  * sums, or Bregman's (r_i!)^(1/r_i) for a 0-1 matrix) and checked against the last prime
- * (C60: 7 primes, 427 evaluations of order 60, each a tree of about 2e9 leaves).
+ * (C60: 6 primes, 366 evaluations of order 60, each a tree of about 2e9 leaves).
  * The context's options are restored afterwards. coeffs[n + 1] is caller-owned.
  * Must not be called while serving or concurrently with other calls on the context.
  * Errors: as for
@@ -277,6 +277,19 @@ hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32
  * takes), HPERM_E_RANGE (an intermediate beyond 500 bits). */
 hperm_status hperm_polynomial_interpolate(int32_t n, const uint64_t *values, int32_t alternate,
                                           hperm_coeff *coeffs);
+
+/* The residue form of that host step (the permanental polynomial beyond 2^180): a polynomial p
+ * of degree <= n with coefficients a_k in [0, P), P the product of primes[0..nprimes-2], from
+ * residues[j * (n + 1) + x] = p(x) mod primes[j], x = 0..n: p interpolated modulo each prime
+ * (forward differences, Newton coefficients with the inverses of k!), each a_k rebuilt by the
+ * Chinese remainder theorem over the first nprimes - 1 primes and checked against the last.
+ * With alternate != 0, coefficient k is negated when n - k is odd. primes: distinct primes
+ * above n, below 2^32, with P below 2^511; coeffs[n + 1]. Errors: HPERM_E_INVALID (n out of
+ * 0..128, nprimes < 2, NULL arrays, a modulus that is not such a prime, or residues the check
+ * prime contradicts: a coefficient outside [0, P) or a wrong residue), HPERM_E_RANGE (P
+ * beyond 2^511). */
+hperm_status hperm_polynomial_from_residues(int32_t n, int32_t nprimes, const uint32_t *primes,
+                                            const uint64_t *residues, int32_t alternate, hperm_coeff *coeffs);
 
 /* ---- stages (tests and benchmarks) ------------------------------------------------ */
 

@@ -112,6 +112,7 @@ _SIGS = {
     "hperm_permanent_dense_noalloc": [_P, _I32, _P, ctypes.POINTER(Result)],
     "hperm_permanent_batch_csr": [_P, _I32, _P, _P, _P, _P, _P, _P, _P],
     "hperm_permanent_mod_batch_csr": [_P, _I32, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P],
+    "hperm_polynomial_from_residues": [_I32, _I32, _P, _P, _I32, _P],
     "hperm_expand_batch_csr": [_P, _I32, _P, _P, _P, _P, _P, _P, ctypes.POINTER(_P)],
     "hperm_jobs_from_dense": [_P, _I32, _P, _P, _P, ctypes.POINTER(_P)],
     "hperm_jobs_info": [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)],
@@ -626,4 +627,20 @@ def polynomial_interpolate(values, alternate: bool = False) -> list[int]:
     st = _lib.hperm_polynomial_interpolate(n, _ptr(limbs), 1 if alternate else 0, out)
     if st != OK:
         raise HpermError(st, "polynomial_interpolate")
+    return [out[k].value for k in range(n + 1)]
+
+
+def polynomial_from_residues(primes, residues, alternate: bool = False) -> list[int]:
+    """Coefficients (low to high) of the polynomial with non-negative coefficients below the
+    product of primes[:-1] whose values at x = 0..n are residues[j][x] modulo primes[j]: per-prime
+    interpolation and the Chinese remainder theorem, checked against the last prime."""
+    pr = np.ascontiguousarray(primes, dtype=np.uint32)
+    res = np.ascontiguousarray(residues, dtype=np.uint64)
+    if res.ndim != 2 or res.shape[0] != pr.size:
+        raise ValueError("one row of residues per prime")
+    n = res.shape[1] - 1
+    out = (Coeff * max(n + 1, 1))()
+    st = _lib.hperm_polynomial_from_residues(n, int(pr.size), _ptr(pr), _ptr(res), 1 if alternate else 0, out)
+    if st != OK:
+        raise HpermError(st, "polynomial_from_residues")
     return [out[k].value for k in range(n + 1)]

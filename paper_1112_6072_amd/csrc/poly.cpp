@@ -155,7 +155,7 @@ namespace {
 // polynomial interpolated modulo each prime, and each coefficient rebuilt by the Chinese
 // remainder theorem over the K primes whose product exceeds the bound, then checked against
 // the last prime. The values reach the bound of the largest evaluation, the coefficients far
-// less (C60: values about 2^355, coefficients below 2^50, bound 2^90: 7 primes, not 22).
+// less (C60: values about 2^355, coefficients below 2^50, bound 2^86.4: 6 primes, not 22).
 hperm_status modular_polynomial(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr, const uint32_t *val,
                                 const std::vector<int32_t> &sizes, const std::vector<int64_t> &rp_off,
                                 const std::vector<int64_t> &nz_off, const std::vector<int32_t> &rp,
@@ -190,31 +190,55 @@ hperm_status modular_polynomial(hperm_ctx *ctx, int32_t n, const int32_t *row_pt
     double cover = 0.0;
     for (uint32_t q : primes) cover += std::log2((double)q);
     if (cover > 500.0) return HPERM_E_RANGE;   // beyond the 512-bit coefficients
-    const size_t K = primes.size() - 1;
-    std::vector<uint64_t> cr((size_t)np * primes.size());   // coefficient x prime
+    std::vector<uint64_t> y((size_t)np * primes.size());   // prime x point
     for (size_t j = 0; j < primes.size(); ++j) {
-        std::vector<uint64_t> y((size_t)np);
         const hperm_status s = hperm_permanent_mod_batch_csr(ctx, np, sizes.data(), rp_off.data(), nz_off.data(),
-                                                             rp.data(), ci.data(), va.data(), primes[j], y.data());
+                                                             rp.data(), ci.data(), va.data(), primes[j],
+                                                             y.data() + j * (size_t)np);
         if (s) return s;
-        const std::vector<uint64_t> c = interpolate_mod(y, primes[j]);
-        for (int k = 0; k < np; ++k) cr[(size_t)k * primes.size() + j] = c[(size_t)k];
     }
-    const std::vector<uint32_t> base(primes.begin(), primes.begin() + (long)K);
-    for (int k = 0; k < np; ++k) {
-        const uint64_t *rk = cr.data() + (size_t)k * primes.size();
-        const U512 a = hp::crt_garner(base, rk);
-        if (hp::mod_u512(a, primes[K]) != rk[K]) return HPERM_E_INTERNAL;   // residues that disagree
-        memset(&coeffs[k], 0, sizeof(hperm_coeff));
-        for (int w = 0; w < 8; ++w) coeffs[k].limb[w] = a.w[w];
-        coeffs[k].nlimb = a.nlimb();
-        coeffs[k].negative = (coeffs[k].nlimb && ((n - k) & 1)) ? 1 : 0;   // c_k = (-1)^(n-k) a_k
-    }
+    const hperm_status s = hperm_polynomial_from_residues(n, (int32_t)primes.size(), primes.data(), y.data(), 1, coeffs);
+    if (s == HPERM_E_INVALID) return HPERM_E_INTERNAL;   // residues that disagree
+    if (s) return s;
     if (!(coeffs[n].nlimb == 1 && coeffs[n].limb[0] == 1)) return HPERM_E_INTERNAL;   // monic
     return HPERM_OK;
 }
 
 }  // namespace
+
+hperm_status hperm_polynomial_from_residues(int32_t n, int32_t nprimes, const uint32_t *primes,
+                                            const uint64_t *residues, int32_t alternate, hperm_coeff *coeffs) {
+    if (n < 0 || n > 128 || nprimes < 2 || !primes || !residues || !coeffs) return HPERM_E_INVALID;
+    const int np = n + 1;
+    std::vector<uint32_t> pr(primes, primes + nprimes);
+    double cover = 0.0;
+    for (int j = 0; j < nprimes; ++j) {
+        if (pr[(size_t)j] <= (uint32_t)n || !hp::is_prime_u32(pr[(size_t)j])) return HPERM_E_INVALID;
+        for (int i = 0; i < j; ++i)
+            if (pr[(size_t)i] == pr[(size_t)j]) return HPERM_E_INVALID;
+        if (j + 1 < nprimes) cover += std::log2((double)pr[(size_t)j]);
+    }
+    if (cover > 511.0) return HPERM_E_RANGE;   // the product of the CRT primes must fit 512 bits
+    const size_t P = pr.size(), K = P - 1;
+    std::vector<uint64_t> cr((size_t)np * P);   // coefficient x prime
+    for (size_t j = 0; j < P; ++j) {
+        std::vector<uint64_t> y(residues + j * (size_t)np, residues + (j + 1) * (size_t)np);
+        for (uint64_t &v : y) v %= pr[j];
+        const std::vector<uint64_t> c = interpolate_mod(y, pr[j]);
+        for (int k = 0; k < np; ++k) cr[(size_t)k * P + j] = c[(size_t)k];
+    }
+    const std::vector<uint32_t> base(pr.begin(), pr.begin() + (long)K);
+    for (int k = 0; k < np; ++k) {
+        const uint64_t *rk = cr.data() + (size_t)k * P;
+        const U512 a = hp::crt_garner(base, rk);
+        if (hp::mod_u512(a, pr[K]) != rk[K]) return HPERM_E_INVALID;   // the check prime disagrees
+        memset(&coeffs[k], 0, sizeof(hperm_coeff));
+        for (int w = 0; w < 8; ++w) coeffs[k].limb[w] = a.w[w];
+        coeffs[k].nlimb = a.nlimb();
+        coeffs[k].negative = (alternate && coeffs[k].nlimb && ((n - k) & 1)) ? 1 : 0;
+    }
+    return HPERM_OK;
+}
 
 hperm_status hperm_permanental_polynomial(hperm_ctx *ctx, int32_t n, const int32_t *row_ptr,
                                           const int32_t *col_idx, const uint32_t *val,

@@ -205,7 +205,7 @@ def test_c60_evaluations_equal_stored_polynomial(hperm):
     """C60 at full size on sampled points: per(xI + A) mod p on the device path equals
     sum_k |c_k| x^k mod p from the stored coefficients (x = 0, 1 and 60; per(60I + A) is about
     2^358). Each point with x > 0 is a tree of about 2e9 leaves (every row gains the diagonal),
-    so the whole polynomial (61 points, 7 primes) is a long run, not a test."""
+    so the whole polynomial (61 points, 6 primes) is a long run, not a test."""
     import time
     coeffs = c60_coefficients()
     A = W.adjacency_matrix(W.read_appendix_adjacency("c60")).astype(np.uint32)
@@ -220,3 +220,34 @@ def test_c60_evaluations_equal_stored_polynomial(hperm):
         assert got == [sum(abs(v) * x ** k for k, v in enumerate(coeffs)) % p for x in xs]
     finally:
         c.close()
+
+
+def c60_primes() -> list[int]:
+    """The six largest primes below 2^18 (the residue route's primes for C60: five cover the
+    coefficient bound max_k C(60, k) 6^(k/3) = 2^86.4 with two bits to spare, the sixth checks)."""
+    out, q = [], (1 << 18) - 1
+    while len(out) < 6:
+        if all(q % d for d in range(2, int(q ** 0.5) + 1)):
+            out.append(q)
+        q -= 2
+    return out
+
+
+def test_polynomial_from_residues(hostlib):
+    """The residue host step on C60's stored polynomial: its values at x = 0..60 reduced modulo
+    the six primes give back the coefficients with alternating signs; a wrong residue, or too
+    few primes for the coefficients, is caught by the check prime."""
+    c = c60_coefficients()
+    a = [abs(v) for v in c]
+    primes = c60_primes()
+    res = [[sum(ak * x ** k for k, ak in enumerate(a)) % p for x in range(61)] for p in primes]
+    assert hostlib.polynomial_from_residues(primes, res, alternate=True) == c
+    assert hostlib.polynomial_from_residues(primes, res) == a
+    bad = [row[:] for row in res]
+    bad[2][17] = (bad[2][17] + 1) % primes[2]
+    with pytest.raises(hostlib.HpermError):
+        hostlib.polynomial_from_residues(primes, bad)
+    with pytest.raises(hostlib.HpermError):   # two primes: 36 bits for 50-bit coefficients
+        hostlib.polynomial_from_residues(primes[:2] + primes[-1:], [res[0], res[1], res[-1]])
+    with pytest.raises(hostlib.HpermError):   # not a prime
+        hostlib.polynomial_from_residues([65535, 65537], [[0] * 61, [0] * 61])
