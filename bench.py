@@ -613,10 +613,10 @@ def c60_primes() -> list:
         q -= 2
 
 
-def c60_residues_part(j: int, batch: int = 8):
+def c60_residues_part(j: int, out_dir: str, batch: int = 8):
     """per(xI + A) of C60 (the appendix's graph) modulo the j-th prime of c60_primes(), for
     x = 0..60, on the device path in modular arithmetic, `batch` points per call (a progress line
-    after each); saved to gpurun_out/c60_residues_<j>.json for --c60-combine."""
+    after each); saved to <out_dir>/c60_residues_<j>.json for --c60-combine."""
     import numpy as np
     import paper_1112_6072_amd as hp
     import workloads as W
@@ -636,13 +636,13 @@ def c60_residues_part(j: int, batch: int = 8):
     finally:
         ctx.close()
     out = {"prime_index": j, "prime": primes[j], "residues": res, "seconds": device_s}
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", f"c60_residues_{j}.json"), "w") as fh:
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, f"c60_residues_{j}.json"), "w") as fh:
         json.dump(out, fh)
     print(json.dumps({k: v for k, v in out.items() if k != "residues"}), flush=True)
 
 
-def c60_combine():
+def c60_combine(out_dir: str):
     """C60's permanental polynomial from the saved residues of every prime (host step of the
     library: per-prime interpolation and the Chinese remainder theorem, checked against the last
     prime), against the oracle's stored coefficients."""
@@ -650,7 +650,7 @@ def c60_combine():
     primes = c60_primes()
     parts = []
     for j in range(len(primes)):
-        with open(os.path.join(ROOT, "gpurun_out", f"c60_residues_{j}.json")) as fh:
+        with open(os.path.join(out_dir, f"c60_residues_{j}.json")) as fh:
             parts.append(json.load(fh))
         assert parts[-1]["prime"] == primes[j]
     coeffs = hp.polynomial_from_residues(primes, [p["residues"] for p in parts], alternate=True)
@@ -686,12 +686,13 @@ def main():
                     help="only per(xI + A) of C60 modulo the J-th of its polynomial's six primes, x = 0..60")
     ap.add_argument("--c60-combine", action="store_true",
                     help="only C60's permanental polynomial from the saved residues of all six primes")
+    ap.add_argument("--out-dir", default=".", help="where --c60-residues saves and --c60-combine reads")
     args = ap.parse_args()
     if args.c60_residues is not None:
-        c60_residues_part(args.c60_residues)
+        c60_residues_part(args.c60_residues, args.out_dir)
         return
     if args.c60_combine:
-        c60_combine()
+        c60_combine(args.out_dir)
         return
     if args.profile_split:
         split_profile_run()
