@@ -510,7 +510,8 @@ typedef struct hperm_launch_stat {
                                nodes it wrote, row_updates = its device H_per launches, ms =
                                the whole group on the device and alg_slots = the milliseconds
                                of its device H_per launches; 5 for such a group evaluated by
-                               residues (ring 2; the figures summed over its primes, and
+                               residues (ring 2; the figures of its one pass, which takes
+                               every problem once per prime, and
                                row_updates = the number of primes) */
     int32_t reserved;       /* variant 3: the launch's resident waves; variant 4 or 5: the
                                problems of the group */

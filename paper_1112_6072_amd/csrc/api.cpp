@@ -1323,7 +1323,8 @@ hperm_status hperm_permanent_mod_batch_csr(hperm_ctx *c, int32_t count, const in
         }
         std::vector<U512> totals;
         DexpStats st;
-        hperm_status s = device_expand_group(&c->dev, grp, T, t, c->opts.s_leaf, budget, &totals, &st, nullptr, prime);
+        const std::vector<uint32_t> moduli(grp.size(), prime);
+        hperm_status s = device_expand_group(&c->dev, grp, T, t, c->opts.s_leaf, budget, &totals, &st, nullptr, &moduli);
         if (s) return s;
         for (size_t q = g0; q < g1; ++q) residues[order_of[q]] = totals[q - g0].w[0];
         g0 = g1;

@@ -197,12 +197,12 @@ struct DexpSample {
 hperm_status device_expand_problem(Dev *c, const CsrView &a, int T, int t, int s_leaf, size_t budget_bytes, U512 *out,
                                    DexpStats *stats, DexpSample *sample = nullptr);
 // The same for several problems of one order n > T at once: their trees share the level
-// buffers and the launches; out[k] receives per(A_k). modp (a prime below 2^18 with
-// n (modp - 1) < 2^24): modular mode, out[k] = per(A_k) mod modp (entries reduced on entry; no
-// bound applies).
+// buffers and the launches; out[k] receives per(A_k). moduli (one prime below 2^18 per problem,
+// with n (p - 1) < 2^24): modular mode, out[k] = per(A_k) mod moduli[k] (entries reduced on
+// entry; no bound applies); problems under different primes share the pass.
 hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs, int T, int t, int s_leaf,
                                  size_t budget_bytes, std::vector<U512> *out, DexpStats *stats,
-                                 DexpSample *sample = nullptr, uint32_t modp = 0);
+                                 DexpSample *sample = nullptr, const std::vector<uint32_t> *moduli = nullptr);
 // The largest modulus of modular mode for order n: min(2^18, (2^24 - 1) / n + 1).
 uint32_t residue_prime_limit(int n);
 // log2 of min(prod of row sums, prod of column sums), a bound on per(A) (0 for a zero line).
@@ -210,7 +210,8 @@ double residue_bound_bits(const CsrView &a);
 // per(A_k) exactly for problems of one order n > T without the exact path's limits (entries and
 // bound): the device path in modular mode modulo K + 1 primes below residue_prime_limit(n), K of
 // them covering min(prod row sums, prod column sums), rebuilt by the Chinese remainder theorem
-// and checked against the last. The stats sum over the primes; *nprimes receives K + 1.
+// and checked against the last, in one device pass (each problem once per prime). *nprimes
+// receives K + 1.
 hperm_status device_expand_residues(Dev *c, const std::vector<CsrView> &probs, int T, int t, int s_leaf,
                                     size_t budget_bytes, std::vector<U512> *out, DexpStats *stats, int *nprimes);
 

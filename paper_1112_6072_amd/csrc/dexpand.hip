@@ -15,9 +15,10 @@
 //      >= 2^22 or row sum >= 2^24 is reported (the limits every job keeps).
 // Nodes whose sparsest line has five or more nonzeros are split the same way (ceil(s/2)
 // children): above the job order R-NW cannot take them, and the expansion is an identity.
-// Modular mode (a prime p < 2^18): every merged entry is reduced modulo p, so entries stay below
-// p and row sums below 2^24 for nodes of order up to 64; the tree then computes per(A) mod p
-// (the permanental polynomial's evaluations by residues).
+// Modular mode (a prime p < 2^18 per problem, with n (p - 1) < 2^24): every merged entry is
+// reduced modulo its problem's p, so entries stay below p and row sums below 2^24; the tree
+// then computes per(A) mod p (the permanental polynomial's evaluations, and per(A) past the
+// exact rings, by residues).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -501,8 +502,8 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
                                                   uint64_t first, uint32_t n, const uint32_t *__restrict__ keys,
                                                   const uint64_t *__restrict__ place,
                                                   uint32_t *__restrict__ out, uint64_t *__restrict__ out_off,
-                                                  unsigned long long *__restrict__ flags, uint32_t prime) {
-    const Modulus modp = modulus(prime);
+                                                  unsigned long long *__restrict__ flags,
+                                                  const uint32_t *__restrict__ primes) {
     __shared__ uint32_t len_all[BLK / WV][MAXO];
     __shared__ __attribute__((aligned(16))) uint32_t node_all[BLK / WV][NODE_LDS];
     __shared__ __attribute__((aligned(16))) uint32_t child_all[BLK / WV][NODE_LDS];
@@ -514,6 +515,7 @@ __global__ __launch_bounds__(BLK) void dexp_write(const uint32_t *__restrict__ l
     const uint32_t *node = lvl + uni64(off[first + k]);
     const uint32_t h0 = uni(node[0]);
     const uint32_t pw = hp_node_words((int)(h0 & 0xffu), (int)(h0 >> 8));
+    const Modulus modp = modulus(primes ? uni(primes[uni(node[2])]) : 0u);   // the node's problem's prime
     const uint64_t pl = uni64(place[k]);
     const uint64_t child_idx = pl >> 36, wbase = pl & ((1ull << 36) - 1);
     if (pw <= (uint32_t)NODE_LDS) {   // coalesced copy in, children built in LDS, copied out
@@ -554,11 +556,11 @@ hipError_t launch_dexp_scan(const uint64_t *in, uint32_t n, uint64_t *tile_sums,
 
 hipError_t launch_dexp_write(const uint32_t *lvl, const uint64_t *off, uint64_t first, uint32_t n, const uint32_t *keys,
                              const uint64_t *place, uint32_t *out, uint64_t *out_off, unsigned long long *flags,
-                             uint32_t modp, hipStream_t s) {
+                             const uint32_t *primes, hipStream_t s) {
     if (n == 0) return hipSuccess;
     const uint32_t blocks = (n + BLK / WV - 1) / (BLK / WV);
     hipLaunchKernelGGL(dexp_write, dim3(blocks), dim3(BLK), 0, s, lvl, off, first, n, keys, place, out, out_off, flags,
-                       modp);
+                       primes);
     return hipGetLastError();
 }
 

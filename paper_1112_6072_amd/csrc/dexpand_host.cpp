@@ -29,7 +29,7 @@ hipError_t launch_dexp_scan(const uint64_t *in, uint32_t n, uint64_t *tile_sums,
 // flags[0] |= 1 on a range error.
 hipError_t launch_dexp_write(const uint32_t *lvl, const uint64_t *off, uint64_t first, uint32_t n, const uint32_t *keys,
                              const uint64_t *place, uint32_t *out, uint64_t *out_off, unsigned long long *flags,
-                             uint32_t modp, hipStream_t s);
+                             const uint32_t *primes, hipStream_t s);
 
 namespace {
 
@@ -45,7 +45,7 @@ struct Misc {
 
 struct Plan {
     int n = 0, T = 0, t = 0, s_leaf = 5;
-    uint32_t modp = 0;                 // modular mode: a prime below 2^18 (0: exact)
+    const uint32_t *modps = nullptr;   // modular mode: each problem's prime, on the device (nullptr: exact)
     uint64_t W = 0, N = 0;             // words and node offsets per level
     uint32_t *levels = nullptr;        // level o at levels + (o - T) * W
     uint64_t *offs = nullptr;          // level o's offsets at offs + (o - T) * N
@@ -121,7 +121,7 @@ struct DexpRun {
                 if (r) return r;
             }
             r = hip(launch_split_nodes(level(P.T), offs(P.T), (uint32_t)n, P.t, P.T, P.s_leaf, &m->head, accs,
-                                       P.probs, m->stats, P.wide, P.wide_entries, P.modp, s),
+                                       P.probs, m->stats, P.wide, P.wide_entries, P.modps, s),
                     "device H_per launch");
             if (r) return r;
             r = hip(hipMemcpyAsync(&h, m, sizeof(Misc), hipMemcpyDeviceToHost, s), "download split results");
@@ -230,7 +230,7 @@ struct DexpRun {
                         // continuation's results, or the end of the expansion): an entry out of
                         // range changes values only, never the tree's shape or its addresses
                         r = hip(launch_dexp_write(level(o), offs(o), k, (uint32_t)chunk, P.keys, P.place,
-                                                  level(o - 1), offs(o - 1), &P.misc->flags, P.modp, s),
+                                                  level(o - 1), offs(o - 1), &P.misc->flags, P.modps, s),
                                 "expansion write");
                         if (r) return r;
                         // chunks of the next level are sized by the average room its nodes were
@@ -253,16 +253,21 @@ struct DexpRun {
 
 hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, int T, int t, int s_leaf,
                                  size_t budget_bytes, std::vector<U512> *out, DexpStats *stats, DexpSample *sample,
-                                 uint32_t modp) {
-    // modular mode: the inputs' entries reduced modulo p (zeros dropped) before packing
+                                 const std::vector<uint32_t> *moduli) {
+    // modular mode: each input's entries reduced modulo its prime (zeros dropped) before packing
     std::vector<std::vector<int32_t>> mrp, mci;
     std::vector<std::vector<uint32_t>> mva;
     std::vector<CsrView> reduced;
-    if (modp) {
-        for (const CsrView &a : probs_in)   // entries below p keep every row sum below 2^24
-            if (modp < 3 || modp >= (1u << 18) || (uint64_t)a.n * (modp - 1) >= (1u << 24))
+    if (moduli) {
+        if (moduli->size() != probs_in.size()) return set_error(c, HPERM_E_INVALID, "modular device expansion: one prime per problem");
+        for (size_t k = 0; k < probs_in.size(); ++k) {   // entries below p keep every row sum below 2^24
+            const uint32_t modp = (*moduli)[k];
+            if (modp < 3 || modp >= (1u << 18) || (uint64_t)probs_in[k].n * (modp - 1) >= (1u << 24))
                 return set_error(c, HPERM_E_INVALID, "modular device expansion: a prime p below 2^18 with n (p - 1) < 2^24");
-        for (const CsrView &a : probs_in) {
+        }
+        for (size_t k = 0; k < probs_in.size(); ++k) {
+            const CsrView &a = probs_in[k];
+            const uint32_t modp = (*moduli)[k];
             mrp.emplace_back();
             mci.emplace_back();
             mva.emplace_back();
@@ -281,7 +286,7 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, i
         for (size_t k = 0; k < probs_in.size(); ++k)
             reduced.push_back(CsrView{probs_in[k].n, mrp[k].data(), mci[k].data(), mva[k].data()});
     }
-    const std::vector<CsrView> &probs = modp ? reduced : probs_in;
+    const std::vector<CsrView> &probs = moduli ? reduced : probs_in;
     DexpRun run{c, Plan{}, {}, DexpStats{}, std::string(), HPERM_OK};
     if (sample) {
         run.sample_max = sample->max_jobs;
@@ -311,7 +316,7 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, i
         const int rc = pack_root_node(probs[(size_t)k], &root, &bounds[(size_t)k]);
         if (rc == 1) continue;
         if (rc) return set_error(c, rc == -2 ? HPERM_E_RANGE : HPERM_E_INVALID, "device expansion: input out of range");
-        if (!modp && bounds[(size_t)k] > 102.0)
+        if (!moduli && bounds[(size_t)k] > 102.0)
             return set_error(c, HPERM_E_RANGE, "device expansion: the permanent bound exceeds 2^102");
         root[2] = (uint32_t)k;
         root_off.push_back(roots.size());
@@ -329,7 +334,6 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, i
     P.T = T;
     P.t = t;
     P.s_leaf = s_leaf;
-    P.modp = modp;
     P.nprob = count;
     const int L = n - T + 1;
     // per level: 7/8 of its share in words, 1/8 in 8-byte offsets; the plan arrays for half a
@@ -346,7 +350,7 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, i
     s = ensure_buf(c, B_DX_OFFS, (size_t)L * P.N * 8);
     if (s) return s;
     s = ensure_buf(c, B_DX_AUX, half * 4 + 256 + 2 * half * 8 + 512 + tiles * 8 + 256 + sizeof(Misc) + 256 +
-                                    (size_t)count * sizeof(ProbAcc) + 256);
+                                    (size_t)count * sizeof(ProbAcc) + 256 + (size_t)count * 4 + 256);
     if (s) return s;
     // deferred leaves are rare (orders above 16, or bounds beyond 64 bits): a first buffer of
     // 2^20 records, grown when a launch reports more
@@ -368,6 +372,7 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, i
     P.tiles = (uint64_t *)take(tiles * 8);
     P.misc = (Misc *)take(sizeof(Misc));
     P.probs = (ProbAcc *)take((size_t)count * sizeof(ProbAcc));
+    uint32_t *modps = (uint32_t *)take((size_t)count * 4);
     P.wide = c->buf[B_SPLIT_WIDE].ptr;
     P.maxw.assign((size_t)L, 0);
     P.maxw[(size_t)L - 1] = maxroot;
@@ -379,6 +384,11 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, i
     if (!s)
         s = run.hip(hipMemcpyAsync(run.offs(n), root_off.data(), root_off.size() * 8, hipMemcpyHostToDevice, c->stream),
                     "upload root offsets");
+    if (!s && moduli) {
+        s = run.hip(hipMemcpyAsync(modps, moduli->data(), (size_t)count * 4, hipMemcpyHostToDevice, c->stream),
+                    "upload primes");
+        P.modps = modps;
+    }
     if (!s) s = run.hip(launch_fill_u64(&P.misc->grand, 3, 0ull, c->stream), "clear flags");
     if (!s) s = run.process(n, 0, live.size());
     if (!s) {   // the range flag of writes after the last continuation launch
@@ -390,12 +400,12 @@ hperm_status device_expand_group(Dev *c, const std::vector<CsrView> &probs_in, i
     run.st.total_s = now_s() - t0;
     if (s) return set_error(c, s, run.err);
     if (sample) sample->complete = !run.stopped;
-    if (modp) {   // the sums of residues, reduced
-        for (U512 &v : run.total) {
-            u128 r = 0;
-            for (int w = 7; w >= 0; --w) r = ((r << 64) | v.w[w]) % modp;
+    if (moduli) {   // the sums of residues, reduced
+        for (size_t k = 0; k < run.total.size(); ++k) {
+            U512 &v = run.total[k];
+            const uint64_t r = mod_u512(v, (*moduli)[k]);
             v = U512();
-            v.w[0] = (uint64_t)r;
+            v.w[0] = r;
         }
     } else if (!run.stopped) {
         for (int k : live)
@@ -448,28 +458,21 @@ hperm_status device_expand_residues(Dev *c, const std::vector<CsrView> &probs, i
     if (primes.empty() || cover > 511.0)
         return set_error(c, HPERM_E_RANGE, "residue evaluation: the permanent bound exceeds 2^500");
     const size_t K = primes.size() - 1, P = primes.size();
-    std::vector<uint64_t> r(probs.size() * P);
+    // one device pass: every problem once per prime (problem k under prime j at j * count + k)
+    std::vector<CsrView> all_probs;
+    std::vector<uint32_t> moduli;
+    for (size_t j = 0; j < P; ++j)
+        for (const CsrView &a : probs) {
+            all_probs.push_back(a);
+            moduli.push_back(primes[j]);
+        }
+    std::vector<U512> tot;
     DexpStats all;
-    for (size_t j = 0; j < P; ++j) {
-        std::vector<U512> tot;
-        DexpStats st;
-        const hperm_status s = device_expand_group(c, probs, T, t, s_leaf, budget_bytes, &tot, &st, nullptr, primes[j]);
-        if (s) return s;
-        for (size_t k = 0; k < probs.size(); ++k) r[k * P + j] = tot[k].w[0];
-        all.jobs += st.jobs;
-        all.nodes += st.nodes;
-        all.max_level_nodes = std::max(all.max_level_nodes, st.max_level_nodes);
-        all.launches += st.launches;
-        all.relaunches += st.relaunches;
-        all.leaves += st.leaves;
-        all.leaf_terms += st.leaf_terms;
-        all.splits += st.splits;
-        all.split_stops += st.split_stops;
-        all.deferred += st.deferred;
-        all.deferred_bound += st.deferred_bound;
-        all.split_s += st.split_s;
-        all.total_s += st.total_s;
-    }
+    const hperm_status s = device_expand_group(c, all_probs, T, t, s_leaf, budget_bytes, &tot, &all, nullptr, &moduli);
+    if (s) return s;
+    std::vector<uint64_t> r(probs.size() * P);
+    for (size_t j = 0; j < P; ++j)
+        for (size_t k = 0; k < probs.size(); ++k) r[k * P + j] = tot[j * probs.size() + k].w[0];
     const std::vector<uint32_t> base(primes.begin(), primes.begin() + (long)K);
     for (size_t k = 0; k < probs.size(); ++k) {
         const uint64_t *rk = r.data() + k * P;

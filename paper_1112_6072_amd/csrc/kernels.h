@@ -104,6 +104,6 @@ hipError_t launch_split_jobs(const JobDesc *jobs, const uint32_t *data, const fl
 // must come from a device expansion in the same modular mode).
 hipError_t launch_split_nodes(const uint32_t *nodes, const uint64_t *node_off, uint32_t n, int t, int mm, int s_leaf,
                               unsigned long long *head, JobAcc *accs, ProbAcc *probs, unsigned long long *stats,
-                              void *wide, uint64_t wide_entries, uint32_t modp, hipStream_t s);
+                              void *wide, uint64_t wide_entries, const uint32_t *modps, hipStream_t s);
 
 }  // namespace hp

@@ -36,8 +36,8 @@
 // start subset holds a column below p - 7, and the term of step s has the sign (-1)^(s + z).
 // Rows beyond p are padded with f = 1. Leaves have order p >= t >= 7.
 //
-// Modular mode (SplitArgs.modp, a prime p < 2^18; nodes of the device expansion in the same
-// mode): merged entries are reduced modulo p, every leaf is evaluated modulo p in FP64 (exact:
+// Modular mode (SplitArgs.modps, a prime p < 2^18 per problem; nodes of the device expansion in
+// the same mode): merged entries are reduced modulo the job's problem's p, every leaf is evaluated modulo p in FP64 (exact:
 // operands and products stay below 2^53) and normalised with the inverse of 2^(p-1), and the
 // sums are residues: per(B) mod p.
 //
@@ -578,6 +578,11 @@ struct Region {
         lv0 = cmap + 32;
     }
     __device__ uint32_t *lvl(int u) const { return lv0 + (u - t - 1) * lw; }   // u in t+1 .. mm
+    // modular mode: the prime of the job being walked
+    __device__ void set_modulus(uint32_t p) {
+        modp = p;
+        mp = ModP{(double)p, 1.0 / (double)p};
+    }
     // a merged entry ca q + cb p (< 2^37) modulo the prime, in FP64 (no integer division)
     __device__ uint32_t reduce(uint64_t v) const { return (uint32_t)red_f((double)v, mp); }
 };
@@ -1153,7 +1158,7 @@ struct SplitArgs {
     WideLeaf *wide;
     uint32_t wide_cap;
     unsigned long long *cycles;   // nullable
-    uint32_t modp;                // 0: exact; else a prime below 2^18: per(B) modulo it
+    const uint32_t *modps;        // nullptr: exact; else per problem a prime below 2^18: per(B) modulo it
 };
 
 namespace {
@@ -1179,8 +1184,7 @@ template <bool NODES, bool MOD>
 __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hper_split(SplitArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    const Region rg(lds, a.t, a.mm, leaf_table_words(), MOD ? a.modp : 0u);   // exact kernel: 0, folded
-    const ModP mp = rg.mp;
+    Region rg(lds, a.t, a.mm, leaf_table_words());
     uint64_t n_leaves = 0, n_terms = 0, n_splits = 0, n_stops = 0, n_bad = 0, n_wide = 0;
     u128 pacc = 0;            // this wave's sum for problem pcur (nodes)
     uint32_t pcur = 0xffffffffu;
@@ -1193,6 +1197,7 @@ __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hp
         float jb;
         uint32_t problem;
         const int m0 = load_source<NODES>(rg, a, job, lane, &jb, &problem);
+        if constexpr (MOD) rg.set_modulus(uni(a.modps[problem]));   // the job's problem's prime
         uint32_t AR = (1u << m0) - 1, AC = AR;   // alive rows and columns of the current node
         Lines ln = lines_from_lds(rg, lane);
         u128 acc = 0;   // per(B): the sum of the normalised leaves (wave-uniform)
@@ -1227,18 +1232,18 @@ __global__ __launch_bounds__(SW) __attribute__((amdgpu_waves_per_eu(4))) void hp
                     if (lp.quad) {
                         const uint32_t k = lp.pa == 2 ? (lp.pb == 2 ? 0u : 1u) : 2u;
                         if (o <= 12)
-                            share = k == 0 ? walk_mod_quad<12, 2, 2>(o, lane, rg.D, mp)
-                                           : (k == 1 ? walk_mod_quad<12, 2, 3>(o, lane, rg.D, mp)
-                                                     : walk_mod_quad<12, 3, 3>(o, lane, rg.D, mp));
+                            share = k == 0 ? walk_mod_quad<12, 2, 2>(o, lane, rg.D, rg.mp)
+                                           : (k == 1 ? walk_mod_quad<12, 2, 3>(o, lane, rg.D, rg.mp)
+                                                     : walk_mod_quad<12, 3, 3>(o, lane, rg.D, rg.mp));
                         else
-                            share = k == 0 ? walk_mod_quad<16, 2, 2>(o, lane, rg.D, mp)
-                                           : (k == 1 ? walk_mod_quad<16, 2, 3>(o, lane, rg.D, mp)
-                                                     : walk_mod_quad<16, 3, 3>(o, lane, rg.D, mp));
+                            share = k == 0 ? walk_mod_quad<16, 2, 2>(o, lane, rg.D, rg.mp)
+                                           : (k == 1 ? walk_mod_quad<16, 2, 3>(o, lane, rg.D, rg.mp)
+                                                     : walk_mod_quad<16, 3, 3>(o, lane, rg.D, rg.mp));
                     } else {
-                        share = o <= 12 ? walk_mod<12>(o, lane, rg.D, mp) : walk_mod<16>(o, lane, rg.D, mp);
+                        share = o <= 12 ? walk_mod<12>(o, lane, rg.D, rg.mp) : walk_mod<16>(o, lane, rg.D, rg.mp);
                     }
                     wave_sync();   // the tables are rewritten by the next leaf
-                    acc += mod_normalise(share, o, mp);
+                    acc += mod_normalise(share, o, rg.mp);
                     if (acc >= (u128)rg.modp) acc -= rg.modp;
                 } else if (ok64 && o <= PMAX) {
                     bool bad;
@@ -1311,8 +1316,7 @@ template <bool NODES, bool MOD>
 __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int lane = threadIdx.x;
-    const Region rg(lds, a.t, a.mm, a.mm * dstride(a.mm), MOD ? a.modp : 0u);
-    const ModP mp = rg.mp;
+    Region rg(lds, a.t, a.mm, a.mm * dstride(a.mm));
     const uint64_t n = min((uint64_t)a.stats[4], (uint64_t)a.wide_cap);
     for (uint64_t w = blockIdx.x; w < n; w += gridDim.x) {
         const WideLeaf wl = a.wide[w];
@@ -1323,6 +1327,7 @@ __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
         float jb;
         uint32_t problem;
         const int m0 = load_source<NODES>(rg, a, job, lane, &jb, &problem);
+        if constexpr (MOD) rg.set_modulus(uni(a.modps[problem]));
         if (p < 7 || p > m0 || m0 > a.mm) continue;
         uint32_t AR = (1u << m0) - 1, AC = AR;
         Lines ln = lines_from_lds(rg, lane);
@@ -1339,9 +1344,9 @@ __global__ __launch_bounds__(SW) void hper_split_wide(SplitArgs a) {
         bool bad = false;
         u128 per;
         if (MOD) {   // modular mode: the leaf's residue
-            const uint64_t share = rg.S == 20 ? walk_mod_wide<20>(p, lane, rg.D, base, rg.S, mp)
-                                              : walk_mod_wide<SMAX>(p, lane, rg.D, base, rg.S, mp);
-            per = mod_normalise(share, p, mp);
+            const uint64_t share = rg.S == 20 ? walk_mod_wide<20>(p, lane, rg.D, base, rg.S, rg.mp)
+                                              : walk_mod_wide<SMAX>(p, lane, rg.D, base, rg.S, rg.mp);
+            per = mod_normalise(share, p, rg.mp);
         } else {
             u128 v;   // rows padded to the table's stride (20 or 24), never beyond it
             if (rg.S == 20) v = walk_plain128<20>(p, lane, rg.D, base, rg.S);
@@ -1396,8 +1401,8 @@ template <bool NODES>
 static hipError_t launch_split_pair(const SplitArgs &a, hipStream_t s) {
     if (a.n == 0) return hipSuccess;
     if (a.t < HP_SPLIT_MIN_T || a.t >= HP_SPLIT_MAX_M || a.mm <= a.t || a.mm > HP_SPLIT_MAX_M) return hipErrorInvalidValue;
-    if (a.modp) {   // the modular kernels exist for the device expansion's nodes only
-        if (!NODES || a.modp < 3 || a.modp >= (1u << 18)) return hipErrorInvalidValue;
+    if (a.modps) {   // the modular kernels exist for the device expansion's nodes only
+        if (!NODES) return hipErrorInvalidValue;
         return launch_split_kernels<true, true>(a, s);
     }
     return launch_split_kernels<NODES, false>(a, s);
@@ -1434,7 +1439,7 @@ hipError_t launch_split_jobs(const JobDesc *jobs, const uint32_t *data, const fl
 
 hipError_t launch_split_nodes(const uint32_t *nodes, const uint64_t *node_off, uint32_t n, int t, int mm, int s_leaf,
                               unsigned long long *head, JobAcc *accs, ProbAcc *probs, unsigned long long *stats,
-                              void *wide, uint64_t wide_entries, uint32_t modp, hipStream_t s) {
+                              void *wide, uint64_t wide_entries, const uint32_t *modps, hipStream_t s) {
     SplitArgs a{};
     a.nodes = nodes;
     a.node_off = node_off;
@@ -1449,7 +1454,7 @@ hipError_t launch_split_nodes(const uint32_t *nodes, const uint64_t *node_off, u
     a.stats = stats;
     a.wide = (WideLeaf *)wide;
     a.wide_cap = (uint32_t)(wide_entries < 0xffffffffull ? wide_entries : 0xffffffffull);
-    a.modp = modp;
+    a.modps = modps;
     return launch_split_pair<true>(a, s);
 }
 
