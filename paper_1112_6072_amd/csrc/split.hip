@@ -1015,8 +1015,9 @@ __device__ __forceinline__ int leaf_row(uint32_t r, uint32_t touched, uint32_t b
 
 // Leaf tables of the main kernel for the current node of order p <= PMAX: D + j PM + i =
 // 2 b_ij for Gray column j, D + TNEG + j PM + i its negative, D + 2 TNEG + i = base_i =
-// 2 b_{i,p-1} - R_i (rows p..PM-1: deltas 0, base 1, so f = 1). Returns Gray column 0's
-// nonzero count b. Needs p >= 2.
+// 2 b_{i,p-1} - R_i (rows p..PM-1: deltas 0, base 1, so f = 1), rows and columns laid out by
+// the leaf plan, which it returns (Gray column 0's rows and count; column 1 of the four-step
+// walk). Needs p >= 2.
 __device__ __forceinline__ LeafPlan leaf_tables(const Region &rg, const Lines &ln, int p, uint32_t AR, uint32_t AC,
                                                 int lane) {
     const LeafPlan lp = leaf_plan(rg, ln, p, AR, AC, lane);
