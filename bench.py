@@ -613,10 +613,10 @@ def c60_primes() -> list:
         q -= 2
 
 
-def c60_residues_part(j: int, out_dir: str, batch: int = 8):
+def c60_residues_part(j: int, out_dir: str, points=None, batch: int = 8):
     """per(xI + A) of C60 (the appendix's graph) modulo the j-th prime of c60_primes(), for
-    x = 0..60, on the device path in modular arithmetic, `batch` points per call (a progress line
-    after each); saved to <out_dir>/c60_residues_<j>.json for --c60-combine."""
+    x = 0..60 (or the given points), on the device path in modular arithmetic, `batch` points per
+    call (a progress line after each); saved to <out_dir>/c60_residues_<j>.json for --c60-combine."""
     import numpy as np
     import paper_1112_6072_amd as hp
     import workloads as W
@@ -626,8 +626,9 @@ def c60_residues_part(j: int, out_dir: str, batch: int = 8):
     ctx = hp.Context()
     res, device_s = [], 0.0
     try:
-        for x0 in range(0, 61, batch):
-            xs = list(range(x0, min(61, x0 + batch)))
+        pts = list(range(61)) if points is None else list(points)
+        for b0 in range(0, len(pts), batch):
+            xs = pts[b0:b0 + batch]
             t0 = time.perf_counter()
             res += ctx.permanent_mod_batch([A + np.uint32(x) * eye for x in xs], primes[j])
             dt = time.perf_counter() - t0
@@ -635,7 +636,7 @@ def c60_residues_part(j: int, out_dir: str, batch: int = 8):
             log(f"C60 prime {j} ({primes[j]}): x = {xs[0]}..{xs[-1]} in {dt:.1f} s")
     finally:
         ctx.close()
-    out = {"prime_index": j, "prime": primes[j], "residues": res, "seconds": device_s}
+    out = {"prime_index": j, "prime": primes[j], "points": pts, "residues": res, "seconds": device_s}
     os.makedirs(out_dir, exist_ok=True)
     with open(os.path.join(out_dir, f"c60_residues_{j}.json"), "w") as fh:
         json.dump(out, fh)
@@ -652,7 +653,7 @@ def c60_combine(out_dir: str):
     for j in range(len(primes)):
         with open(os.path.join(out_dir, f"c60_residues_{j}.json")) as fh:
             parts.append(json.load(fh))
-        assert parts[-1]["prime"] == primes[j]
+        assert parts[-1]["prime"] == primes[j] and parts[-1].get("points", list(range(61))) == list(range(61))
     coeffs = hp.polynomial_from_residues(primes, [p["residues"] for p in parts], alternate=True)
     with open(os.path.join(ROOT, "tests", "golden", "c60_permanental_polynomial.json")) as fh:
         want = [int(v) for v in json.load(fh)["coefficients"]]
@@ -687,9 +688,12 @@ def main():
     ap.add_argument("--c60-combine", action="store_true",
                     help="only C60's permanental polynomial from the saved residues of all six primes")
     ap.add_argument("--out-dir", default=".", help="where --c60-residues saves and --c60-combine reads")
+    ap.add_argument("--c60-points", default=None, metavar="X,Y",
+                    help="with --c60-residues: only these points x (e.g. one point, for profiling)")
     args = ap.parse_args()
     if args.c60_residues is not None:
-        c60_residues_part(args.c60_residues, args.out_dir)
+        pts = [int(v) for v in args.c60_points.split(",")] if args.c60_points else None
+        c60_residues_part(args.c60_residues, args.out_dir, pts)
         return
     if args.c60_combine:
         c60_combine(args.out_dir)
