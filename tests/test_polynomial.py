@@ -192,6 +192,9 @@ def test_mod_batch_equals_exact_residues(hperm):
         for p in (262139, 65537, 7, 3):
             got = c.permanent_mod_batch(mats, p)
             assert got == [v % p for v in exact], p
+        c.set_opts(split_order=14)   # leaves of order 14: the residue walk with 16 rows
+        assert c.permanent_mod_batch(mats, 262139) == [v % 262139 for v in exact]
+        c.set_opts(split_order=12)
         with pytest.raises(hperm.HpermError):
             c.permanent_mod_batch(mats[:1], 65535)   # not prime
         with pytest.raises(hperm.HpermError):
