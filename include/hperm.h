@@ -463,7 +463,9 @@ hperm_status hperm_stepwise(int32_t n, int32_t k, const double *X, const double 
  *   one runs; at most two batches are in flight;
  * - a request the device expansion takes (opts.device_expand in effect, order above it, bound
  *   below 2^102) runs instead on a third stream by the device expansion, together with the
- *   other waiting requests of its order, overlapping the batches;
+ *   other waiting requests of its order, overlapping the batches; so does, by residues (as in
+ *   hperm_permanent_csr), a request above that order that the host expansion refuses for
+ *   range, its work estimate counted once per prime, twice over;
  * - with opts.serve_limit_ms, a request whose estimated work exceeds the limit completes with
  *   HPERM_E_TOOBIG (admission by work);
  * - a request completes when its batch does; its result is bit-identical to the blocking
