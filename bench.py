@@ -806,8 +806,10 @@ def main():
     # updates), and the same launch weighed with the half-rate multiplies at the issue costs a
     # probe measured for them (v_mul_lo_u32 2.5 and v_mad_u64_u32 3.8 full-rate slots instead
     # of 2 each; mod 2^64 only)
+    WALK_NAMES = {0: "step-pair walk", 1: "paired walk, two-row column 0",
+                  2: "paired walk, three-row column 0", 6: "four-step walk, two disjoint columns"}
     mul_slots, add_slots = {0: (5.0, 2.0), 1: (9.0, 4.0), 2: (33.0, 9.0)}[ring]
-    adds = dom["terms"] / dom["n"] / (2.0 if variant > 0 else 1.0)
+    adds = dom["terms"] / dom["n"] / {0: 1.0, 1: 2.0, 2: 2.0, 6: 4.0}[variant]
     mults = (alg_per_launch - add_slots * adds - dom["upd"] / dom["n"]) / mul_slots
     probe_frac = ((alg_per_launch + mults * (2.5 + 3.8 - 4.0)) / (avg_ms * 1e-3) / ALU_PEAK
                   if ring == 0 else None)
@@ -945,7 +947,7 @@ def main():
                      "unit": "VALU lane-slots/s", "frac": achieved / ALU_PEAK,
                      "traffic": traffic_from_profile(),
                      "kernel": f"rnw_persistent ({ring_name}, orders <= {[16, 20, 24, 32, 40][bucket]}, "
-                               f"{['step-pair walk', 'paired walk, two-row column 0', 'paired walk, three-row column 0'][variant]})",
+                               f"{WALK_NAMES[variant]})",
                      "avg_launch_ms": avg_ms, "alg_slots_per_launch": alg_per_launch,
                      "jobs_per_launch": dom["jobs"] // dom["n"], "terms_per_launch": dom["terms"] // dom["n"],
                      "ring_multiplies_per_launch": mults, "frac_with_probe_multiply_weights": probe_frac},

@@ -353,7 +353,11 @@ static double ring_add_slots(int ring) { return ring == HP_W64 ? 2.0 : ring == H
 // addition. In the paired walk (variant v = 1, 2; b = v + 1 rows below the pair boundary) the
 // L / 2 flips of column 0 give way to one pair sum each (two products of b rows and one
 // multiply by the suffix above them: 2(b - 1) + 1 ring multiplies and one ring addition per
-// pair), and the other flips re-multiply only from row b up.
+// pair), and the other flips re-multiply only from row b up. In the four-step walk (variant 6;
+// column 0 on rows 0..1, column 1 on rows of 2..4) the flips of columns 0 and 1 give way to
+// one block sum per four steps (the products of rows 0..1 and of rows 2..4 without and with
+// their column, their differences' product and the multiply by the suffix: 8 ring multiplies
+// and one ring addition), and the other flips re-multiply only from row 5 up.
 struct JobWork {
     double mults, adds, updates;
 };
@@ -364,6 +368,16 @@ static JobWork job_work(const JobDesc &d, const uint32_t *data, int chunk, int v
     const double L = std::ldexp(1.0, chunk);
     const double chunks = std::ldexp(1.0, m - 1) / L;
     double mults = m, updates = 0, adds = L;
+    if (variant == 6) {
+        const double b = 5.0;   // the kernel's boundary row
+        mults += L / 4 * (2.0 * b - 2.0);
+        for (int j = 2; j < chunk && j + 1 < m; ++j) {
+            const double flips = L / std::ldexp(1.0, j + 1);
+            updates += flips * (cs[j + 1] - cs[j]);
+            mults += flips * std::max(0.0, (double)hi[j] - b);
+        }
+        return {chunks * mults, chunks * L / 4, chunks * updates};
+    }
     for (int j = 0; j < chunk && j + 1 < m; ++j) {
         const double flips = L / std::ldexp(1.0, j + 1);
         updates += flips * (cs[j + 1] - cs[j]);
@@ -455,7 +469,9 @@ uint64_t split_wide_total(const std::vector<JobDesc> &desc, const hperm_opts &o)
 static void build_queue_groups(hperm_jobs *j, int split) {
     const std::vector<JobDesc> &dsc = j->tab.desc;
     const size_t nd = dsc.size();
-    constexpr int NV = 3;
+    constexpr int NV = 4;   // walks 0, 1, 2 and the four-step walk (variant 6) at index 3
+    auto vindex = [](int v) { return v == 6 ? 3 : v; };
+    auto vof = [](int i) { return i == 3 ? 6 : i; };
     constexpr int NG = HP_RNW_BUCKETS * HP_NRING * NV;
     constexpr int SPLIT_G = NG;   // the device H_per group
     constexpr uint64_t kSmallGroupItems = 16384;
@@ -470,7 +486,7 @@ static void build_queue_groups(hperm_jobs *j, int split) {
             j->qitems[k] = 1;
         } else {
             g = ((HP_RNW_BUCKETS - 1 - bucket_of(d.m)) * HP_NRING + (HP_NRING - 1 - d.arith)) * NV +
-                walk_variant(d, d.chunk_log2);
+                vindex(walk_variant(d, d.chunk_log2));
             j->qitems[k] = items_of(d.m, d.chunk_log2);
         }
         raw[k] = (uint8_t)g;
@@ -485,7 +501,7 @@ static void build_queue_groups(hperm_jobs *j, int split) {
     hperm_jobs::QueueGroup acc[NG + 1];
     for (int g = 0; g < NG; ++g)
         acc[g] = hperm_jobs::QueueGroup{HP_NRING - 1 - (g / NV) % HP_NRING, HP_RNW_BUCKETS - 1 - g / (NV * HP_NRING),
-                                        g % NV, 0, 0, 0, 0.0, 0.0, 0.0};
+                                        vof(g % NV), 0, 0, 0, 0.0, 0.0, 0.0};
     acc[SPLIT_G] = hperm_jobs::QueueGroup{HP_W64, bucket_of(HP_SPLIT_MAX_M), kSplitVariant, 0, 0, 0, 0.0, 0.0, 0.0};
     for (size_t k = 0; k < nd; ++k) {
         const JobDesc &d = dsc[k];
@@ -516,11 +532,11 @@ static void build_queue_groups(hperm_jobs *j, int split) {
 
 // The lane chunk of a job under a tuning offset (the limits of the expansion's own choice:
 // at most 12, at most m - 1, at least m - 32).
-static int tuned_chunk(int m, int c0, int delta) {
+static int tuned_chunk(int m, int c0, int delta, int cmin) {
     int c = c0 + delta;
     if (c > 12) c = 12;
     if (c > m - 1) c = std::max(0, m - 1);
-    if (c < 1) c = std::min(1, std::max(0, m - 1));
+    if (c < cmin) c = std::min(cmin, std::max(0, m - 1));
     if (c < m - 32) c = m - 32;
     return c;
 }
@@ -548,8 +564,10 @@ static void apply_tuning(Dev *c, hperm_jobs *j) {
         JobDesc d0 = d;
         d0.chunk_log2 = j->chunk0[k];
         int want = d0.chunk_log2;
-        const auto it = table.find(tune_key(d.arith, bucket_of(d.m), walk_variant(d0, d0.chunk_log2)));
-        if (it != table.end() && d0.chunk_log2 > 0) want = tuned_chunk(d.m, d0.chunk_log2, it->second.chunk_delta);
+        const int v0 = walk_variant(d0, d0.chunk_log2);
+        const auto it = table.find(tune_key(d.arith, bucket_of(d.m), v0));
+        if (it != table.end() && d0.chunk_log2 > 0)
+            want = tuned_chunk(d.m, d0.chunk_log2, it->second.chunk_delta, v0 == 6 ? 2 : 1);
         if (d.chunk_log2 != want) {
             d.chunk_log2 = (uint8_t)want;
             changed = true;

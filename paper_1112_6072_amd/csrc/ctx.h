@@ -41,7 +41,10 @@ struct TuneTable {
     std::map<int, TuneEntry> e;   // key: tune_key(ring, bucket, variant)
     uint64_t version = 0;         // bumped on every change
 };
-inline int tune_key(int ring, int bucket, int variant) { return (ring * 8 + bucket) * 4 + variant; }
+inline int tune_key(int ring, int bucket, int variant) { return (ring * 8 + bucket) * 8 + variant; }
+inline int tune_key_ring(int key) { return key / 64; }
+inline int tune_key_bucket(int key) { return (key / 8) % 8; }
+inline int tune_key_variant(int key) { return key % 8; }
 
 }  // namespace hp
 

@@ -365,18 +365,43 @@ static void emit_job_oriented(const NodeT &a, int problem, double root_log2, con
     int fixed = 0;
     for (int j = 1; j < m; ++j)
         if (cnt[j] > cnt[fixed]) fixed = j;
+    double lb = std::min(log2_bound(a), root_log2);
+    const double need = lb + m;   // |V| <= 2^(m-1) per, plus a sign bit
+    if (lb > 180.0) throw RangeError{"the permanent bound exceeds 2^180"};
+    const int auto_ring = need <= 62.5 ? HP_W64 : (need <= 126.5 ? HP_W128 : HP_RES);
+    int ring = auto_ring;
+    if (prm.arith == 1) ring = HP_W64;
+    if (prm.arith == 2) ring = HP_W128;
+    if (prm.arith == 3) ring = HP_RES;
+    // a forced ring narrower than the bound allows could wrap: refuse it
+    if (ring < auto_ring)
+        throw RangeError{"the requested arithmetic is too narrow for this problem's bound"};
     int gray[HP_MAX_M];
-    // greedy choice as a branch-free minimum of keys (new rows, nonzeros, column index)
+    // greedy choice as a branch-free minimum of keys (new rows, nonzeros, column index). For a
+    // mod 2^64 job whose first Gray column reaches at most two rows, Gray column 1 is instead
+    // the sparsest column (at most three rows) that avoids those rows, if there is one: the
+    // kernels then take the walk's steps four at a time.
     uint64_t avail = (m == 64 ? ~0ull : ((1ull << m) - 1)) & ~(1ull << fixed);
     uint64_t covered = 0;
+    bool quad = false;
     for (int g = 0; g + 1 < m; ++g) {
         uint32_t bestkey = ~0u;
-        for (uint64_t rest = avail; rest; rest &= rest - 1) {
-            const int j = __builtin_ctzll(rest);
-            const uint32_t key = ((uint32_t)__builtin_popcountll(colrows[j] & ~covered) << 16) |
-                                 ((uint32_t)cnt[j] << 8) | (uint32_t)j;
-            bestkey = std::min(bestkey, key);
+        if (g == 1 && ring == HP_W64 && m >= 4 && __builtin_popcountll(covered) <= 2) {
+            for (uint64_t rest = avail; rest; rest &= rest - 1) {
+                const int j = __builtin_ctzll(rest);
+                const int rows = __builtin_popcountll(colrows[j]);
+                if ((colrows[j] & covered) == 0 && rows >= 1 && rows <= 3)
+                    bestkey = std::min(bestkey, ((uint32_t)rows << 16) | ((uint32_t)cnt[j] << 8) | (uint32_t)j);
+            }
+            quad = bestkey != ~0u;
         }
+        if (!quad || g != 1)
+            for (uint64_t rest = avail; rest; rest &= rest - 1) {
+                const int j = __builtin_ctzll(rest);
+                const uint32_t key = ((uint32_t)__builtin_popcountll(colrows[j] & ~covered) << 16) |
+                                     ((uint32_t)cnt[j] << 8) | (uint32_t)j;
+                bestkey = std::min(bestkey, key);
+            }
         const int best = (int)(bestkey & 0xff);
         avail &= ~(1ull << best);
         gray[g] = best;
@@ -415,17 +440,6 @@ static void emit_job_oriented(const NodeT &a, int problem, double root_log2, con
     for (int i = 0; i < m; ++i)
         if (rsum[i] >= HP_MAX_ROWSUM) throw RangeError{"a job row sum reached 2^24"};
 
-    double lb = std::min(log2_bound(a), root_log2);
-    const double need = lb + m;   // |V| <= 2^(m-1) per, plus a sign bit
-    if (lb > 180.0) throw RangeError{"the permanent bound exceeds 2^180"};
-    const int auto_ring = need <= 62.5 ? HP_W64 : (need <= 126.5 ? HP_W128 : HP_RES);
-    int ring = auto_ring;
-    if (prm.arith == 1) ring = HP_W64;
-    if (prm.arith == 2) ring = HP_W128;
-    if (prm.arith == 3) ring = HP_RES;
-    // a forced ring narrower than the bound allows could wrap: refuse it
-    if (ring < auto_ring)
-        throw RangeError{"the requested arithmetic is too narrow for this problem's bound"};
 
     JobDesc d;
     const size_t base = hp_align_words(out->data.size());
@@ -474,6 +488,11 @@ static void emit_job_oriented(const NodeT &a, int problem, double root_log2, con
     hi[m - 1] = (uint32_t)m;
     if (m >= 2 && hi[0] <= 2) d.flags |= HP_FLAG_COL0_TWO_ROWS;
     else if (m >= 3 && hi[0] == 3) d.flags |= HP_FLAG_COL0_THREE_ROWS;
+    // column 0 on rows 0..1, column 1 on rows 2..3 or 2..4 (disjoint, so all of level 1): the
+    // kernels' four-step walk takes B as rows 2..4 (row 4 untouched by column 1 for |B| = 2)
+    if (quad && m >= 5 && hi[0] == 2 && (hi[1] == 4 || hi[1] == 5) &&
+        __builtin_popcountll(colrows[gray[0]]) == 2 && (uint32_t)__builtin_popcountll(colrows[gray[1]]) == hi[1] - 2)
+        d.flags |= HP_FLAG_QUAD;
     if (transposed) d.flags |= HP_FLAG_TRANSPOSED;
     uint32_t *ent = w + 3 * m;
     uint32_t pos[HP_MAX_M];

@@ -60,6 +60,9 @@ static_assert(sizeof(JobDesc) == 16, "JobDesc layout");
 constexpr uint8_t HP_FLAG_COL0_TWO_ROWS = 1;
 constexpr uint8_t HP_FLAG_COL0_THREE_ROWS = 2;   // hi[0] = 3
 constexpr uint8_t HP_FLAG_TRANSPOSED = 4;
+// mod 2^64 jobs of order >= 5 whose Gray column 0 touches rows 0..1 and column 1 only rows
+// 2..hi[1]-1 with hi[1] = 4 or 5: the four-step walk applies
+constexpr uint8_t HP_FLAG_QUAD = 8;
 
 static inline uint32_t hp_job_words(int m, int nnz) { return 5u * (uint32_t)m + (uint32_t)nnz; }
 

@@ -83,6 +83,7 @@ struct RingW64 {
     struct P { uint64_t v; };
     using Small = int64_t;
     using USmall = uint64_t;
+    static constexpr bool kFourStep = true;   // the four-step walk's block sums wrap modulo 2^64
     __device__ static P pair_mul(const P &s, Small d) { return {s.v * (uint64_t)d}; }
     // -p = (p xor ~0) + 1: the accumulator adds p xor mask and counts the +1s apart
     struct Acc { uint64_t v; uint32_t n; };
@@ -108,6 +109,7 @@ struct RingW64 {
 };
 
 struct RingW128 {
+    static constexpr bool kFourStep = false;
     struct P { uint32_t x0, x1, x2, x3; };
     using Small = __int128;
     using USmall = unsigned __int128;
@@ -180,6 +182,7 @@ __device__ __forceinline__ uint64_t mulmod_signed(uint64_t r, __int128 d) {
 }
 
 struct RingRes {
+    static constexpr bool kFourStep = false;
     struct P { uint64_t r0, r1, r2; };
     using Acc = P;
     using Small = __int128;
@@ -359,6 +362,28 @@ __device__ __forceinline__ uint32_t block_of(uint32_t h) {
         HP_BLOCK_F(0)                                                                      \
     }
 
+// A flip in the four-step walk (boundary row HB = QB + 1, a block top): blocks QB and up are
+// recomputed in full, the blocks below (rows 0 .. HB-1, columns 0 and 1 held out) only get
+// their new row values.
+#define HP_FLIP_Q(TOP, DJ, DIR, QB)                                                        \
+    {                                                                                      \
+        const uint32_t top_ = (TOP);                                                       \
+        const float *const dj = (DJ);                                                      \
+        const float dir_ = (DIR);                                                          \
+        const float dir = dir_;                                                            \
+        const uint32_t top = top_;                                                         \
+        if (top >= 5) {                                                                    \
+            _Pragma("unroll") for (int B = NB - 1; B >= 5; --B) if ((int)top >= B) {       \
+                HP_BLOCK(B)                                                                \
+            }                                                                              \
+        }                                                                                  \
+        if ((QB) <= 4) { if (top >= 4) { HP_BLOCK(4) } } else { HP_BLOCK_F(4) }           \
+        if ((QB) <= 3) { if (top >= 3) { HP_BLOCK(3) } } else { HP_BLOCK_F(3) }           \
+        if ((QB) <= 2) { if (top >= 2) { HP_BLOCK(2) } } else { HP_BLOCK_F(2) }           \
+        if ((QB) <= 1) { if (top >= 1) { HP_BLOCK(1) } } else { HP_BLOCK_F(1) }           \
+        HP_BLOCK_F(0)                                                                      \
+    }
+
 // V = 0: the walk in step pairs below, for every job. V = 1, 2 (jobs whose column 0 reaches
 // only the first b = V + 1 rows, lane chunks of at least 2 Gray indices): the paired walk.
 // The two terms of a pair (t even, t + 1) differ only in Gray column 0, so rows 0 .. b-1 are
@@ -368,11 +393,14 @@ __device__ __forceinline__ uint32_t block_of(uint32_t h) {
 // suffix product and sign word of the rows above. X is a small integer, exact in the ring's
 // Small type; for b = 2 it is d_0 g_1 + d_1 g_0 + d_0 d_1. The other flips recompute S and G
 // only from row b up and move g_0 .. g_{b-1}.
-template <class R, int MAXM, int V>
+template <class R, int MAXM, int V0>
 __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__restrict__ data,
                                          uint64_t item, int lane, JobAcc *dst, float *tab) {
     static_assert(MAXM <= 40, "job orders up to 40");
-    static_assert(V == 0 || V == 1 || V == 2, "walk variant");
+    static_assert(V0 >= 0 && V0 <= 3, "walk variant");
+    // V = 3, the four-step walk, exists for the 64-bit ring only (the host gives it no other
+    // jobs); the other rings' instantiations of it are the two-row walk
+    constexpr int V = (V0 == 3 && !R::kFourStep) ? 1 : V0;
     constexpr int STRIDE = Tab<MAXM>::STRIDE;
     constexpr int NB = Blocks<MAXM>::N;
     const int m = jd.m;
@@ -464,6 +492,44 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
                 HP_FLIP((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj)
             }
         }
+    } else if constexpr (V == 3) {
+        // Four-step walk (mod 2^64 jobs flagged by the host, lane chunks of at least 4 steps):
+        // Gray column 0 touches only rows 0..1 (A), column 1 only rows of 2..4 (B; row 4, when
+        // column 1 misses it, is a factor of both B products and so of the sum), and f holds
+        // rows 0..4 with both columns out. In the block of steps t..t+3 (t = 4q) every other
+        // column is fixed and the four terms, with signs (-1)^q (+, -, +, -) in the reflected
+        // code's order, sum to (-1)^q (A0 - A1)(B0 - B1) times the rows from 5 up: A0, A1 the
+        // products of A without and with column 0, B0, B1 those of B without and with column 1.
+        // One multiply of the suffix S_5 per four terms, and the flips (columns 2 and up)
+        // recompute the suffix products from row 5 up only.
+        constexpr int HB = 5;
+        float d0[2], d1[3];   // column 0's deltas on rows 0..1, column 1's on rows 2..4
+#pragma unroll
+        for (int i = 0; i < 2; ++i) d0[i] = __uint_as_float(uni(__float_as_uint(tab[i])));
+#pragma unroll
+        for (int i = 2; i < HB; ++i) d1[i - 2] = __uint_as_float(uni(__float_as_uint(tab[STRIDE + i])));
+#define HP_QUAD_BLOCK()                                                                    \
+    {                                                                                      \
+        const int64_t a0 = (int64_t)(int32_t)f[0] * (int64_t)(int32_t)f[1];                \
+        const int64_t a1 = (int64_t)(int32_t)(f[0] + d0[0]) * (int64_t)(int32_t)(f[1] + d0[1]); \
+        const uint64_t b0 = (uint64_t)((int64_t)(int32_t)f[2] * (int64_t)(int32_t)f[3]) *  \
+                            (uint64_t)(int64_t)(int32_t)f[4];                              \
+        const uint64_t b1 = (uint64_t)((int64_t)(int32_t)(f[2] + d1[0]) * (int64_t)(int32_t)(f[3] + d1[1])) * \
+                            (uint64_t)(int64_t)(int32_t)(f[4] + d1[2]);                    \
+        const uint64_t x = ((uint64_t)a0 - (uint64_t)a1) * (b0 - b1);                      \
+        const uint32_t smask = 0u - ((t >> 2) & 1u);   /* all ones: minus (odd blocks) */  \
+        R::acc(acc, R::pair_mul(S[HB], (int64_t)x), (uint32_t)((int)G[HB] >> 31) ^ smask); \
+    }
+        uint32_t t = 0;
+        HP_QUAD_BLOCK()
+        while ((uint64_t)t + 4 < L) {   // L is a multiple of 4 (the host gives this walk c >= 2)
+            const int j = __builtin_ctz(t + 4);   // >= 2
+            const float dirj = __uint_as_float(0x3f800000u | ((((t + 4) >> (j + 1)) & 1u) << 31));
+            HP_FLIP_Q((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj, HB - 1)
+            t += 4;
+            HP_QUAD_BLOCK()
+        }
+#undef HP_QUAD_BLOCK
     } else {
         constexpr int PB = V + 1;   // rows 0 .. PB-1 below the pair boundary
         using Sm = typename R::Small;
@@ -513,6 +579,7 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
     if (k0 >= nterms) acc = R::acc_zero();   // lanes past the end of a short job contribute nothing
     R::flush(acc, dst, lane);
 }
+#undef HP_FLIP_Q
 #undef HP_FLIP_P
 #undef HP_BLOCK_F
 #undef HP_FLIP
@@ -527,7 +594,7 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
 // 66 unconstrained, and the one value that then spills is stored and reloaded once per item,
 // outside the Gray loop. (The same limit made the three-row walk slower.)
 template <class R, int MAXM, int V>
-__global__ __launch_bounds__(BLOCK, (MAXM == 20 && V == 1 ? 8 : 1)) void rnw_persistent(const JobDesc *__restrict__ jobs,
+__global__ __launch_bounds__(BLOCK, (MAXM == 20 && (V == 1 || V == 3) ? 8 : 1)) void rnw_persistent(const JobDesc *__restrict__ jobs,
                                                         const uint32_t *__restrict__ data,
                                                         const uint32_t *__restrict__ queue,
                                                         const uint64_t *__restrict__ item_end,
@@ -996,6 +1063,8 @@ int est_bucket_of(int m) { return m <= 16 ? 0 : (m <= 20 ? 1 : (m <= 24 ? 2 : (m
 
 int walk_variant(const JobDesc &d, int chunk_log2) {
     if (chunk_log2 < 1) return 0;
+    if ((d.flags & HP_FLAG_QUAD) && (d.flags & HP_FLAG_COL0_TWO_ROWS) && d.arith == HP_W64 && chunk_log2 >= 2)
+        return 6;   // the four-step walk
     return (d.flags & HP_FLAG_COL0_TWO_ROWS) ? 1 : (d.flags & HP_FLAG_COL0_THREE_ROWS) ? 2 : 0;
 }
 
@@ -1045,8 +1114,10 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
 
 // Kernel of an order bucket and walk variant.
 #define HP_FN(K, MAXM)                                                                     \
-    (variant == 1 ? (const void *)K<RING_T, MAXM, 1>                                       \
-                  : variant == 2 ? (const void *)K<RING_T, MAXM, 2> : (const void *)K<RING_T, MAXM, 0>)
+    (variant == 1   ? (const void *)K<RING_T, MAXM, 1>                                     \
+     : variant == 2 ? (const void *)K<RING_T, MAXM, 2>                                     \
+     : variant == 6 ? (const void *)K<RING_T, MAXM, 3>                                     \
+                    : (const void *)K<RING_T, MAXM, 0>)
 static const void *persistent_fn(int bucket, int variant, bool timed) {
     if (!timed) {
         switch (bucket) {

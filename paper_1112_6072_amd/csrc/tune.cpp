@@ -21,11 +21,11 @@ const int kDeltas[] = {-3, -2, -1, 0, 1};
 const int kGrids[] = {100, 75, 50};
 const uint64_t kSampleTerms = 1ull << 33;   // about 4 ms of the mod-2^64 walk per trial
 
-int tuned_chunk_of(int m, int c0, int delta) {   // as the queue builder applies it
+int tuned_chunk_of(int m, int c0, int delta, int cmin) {   // as the queue builder applies it
     int c = c0 + delta;
     if (c > 12) c = 12;
     if (c > m - 1) c = std::max(0, m - 1);
-    if (c < 1) c = std::min(1, std::max(0, m - 1));
+    if (c < cmin) c = std::min(cmin, std::max(0, m - 1));
     if (c < m - 32) c = m - 32;
     return c;
 }
@@ -174,7 +174,7 @@ extern "C" hperm_status hperm_autotune(hperm_ctx *c, hperm_jobs *j, const char *
         }
         for (auto &gk : groups) {
             const int key = gk.first;
-            const int ring = key / 32, bucket = (key / 4) % 8, variant = key % 4;
+            const int ring = tune_key_ring(key), bucket = tune_key_bucket(key), variant = tune_key_variant(key);
             bool cached = false;
             {
                 std::lock_guard<std::mutex> tl(d->tune->mu);
@@ -215,7 +215,8 @@ extern "C" hperm_status hperm_autotune(hperm_ctx *c, hperm_jobs *j, const char *
                 int sig = 0;
                 for (size_t k = 0; k < K; ++k) {
                     td[k] = j->tab.desc[sample[k]];
-                    const int ch = tuned_chunk_of(td[k].m, j->chunk0[sample[k]], delta);
+                    // the four-step walk (variant 6) needs lane chunks of 4 steps at least
+                    const int ch = tuned_chunk_of(td[k].m, j->chunk0[sample[k]], delta, variant == 6 ? 2 : 1);
                     td[k].chunk_log2 = (uint8_t)ch;
                     if (k == 0) sig = ch;
                     ie[k] = acc += items_for(td[k].m, ch);
@@ -292,9 +293,9 @@ extern "C" hperm_status hperm_autotune(hperm_ctx *c, hperm_jobs *j, const char *
         std::lock_guard<std::mutex> tl(d->tune->mu);
         for (const auto &kv : d->tune->e) {
             hperm_tune_entry e{};
-            e.ring = kv.first / 32;
-            e.bucket = (kv.first / 4) % 8;
-            e.variant = kv.first % 4;
+            e.ring = tune_key_ring(kv.first);
+            e.bucket = tune_key_bucket(kv.first);
+            e.variant = tune_key_variant(kv.first);
             e.chunk_delta = kv.second.chunk_delta;
             e.grid_pct = kv.second.grid_pct;
             e.from_cache = kv.second.ms_default == 0.0;

@@ -349,7 +349,11 @@ def test_paired_walk_small_chunks(hperm, chunk):
         c.close()
     assert per_job == native.ryser_batch(expand_leaves(A, 14), threads=8)
     assert totals == [int(GOLDEN["cubic24_seed7"])]
-    assert variants & {1, 2}
+    assert variants & {1, 2, 6}
+    if chunk >= 2:
+        assert 6 in variants   # the four-step walk needs lane chunks of four steps
+    else:
+        assert 6 not in variants
 
 
 def test_largest_orders_and_sizes(hperm, ctx):
