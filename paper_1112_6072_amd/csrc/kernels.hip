@@ -503,29 +503,47 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
         // One multiply of the suffix S_5 per four terms, and the flips (columns 2 and up)
         // recompute the suffix products from row 5 up only.
         constexpr int HB = 5;
-        float d0[2], d1[3];   // column 0's deltas on rows 0..1, column 1's on rows 2..4
-#pragma unroll
-        for (int i = 0; i < 2; ++i) d0[i] = __uint_as_float(uni(__float_as_uint(tab[i])));
-#pragma unroll
-        for (int i = 2; i < HB; ++i) d1[i - 2] = __uint_as_float(uni(__float_as_uint(tab[STRIDE + i])));
+        // column 0's deltas on rows 0..1 and column 1's on rows 2..4, as wave-uniform integers
+        const int e0 = (int)__uint_as_float(uni(__float_as_uint(tab[0])));
+        const int e1 = (int)__uint_as_float(uni(__float_as_uint(tab[1])));
+        const int e2 = (int)__uint_as_float(uni(__float_as_uint(tab[STRIDE + 2])));
+        const int e3 = (int)__uint_as_float(uni(__float_as_uint(tab[STRIDE + 3])));
+        const int e4 = (int)__uint_as_float(uni(__float_as_uint(tab[STRIDE + 4])));
+        const int64_t k01 = (int64_t)uni64((uint64_t)((int64_t)e0 * e1));
+        // Block sum: with g the rows without columns 0 and 1, A1 - A0 = e0 g1 + e1 g0 + e0 e1
+        // (below 2^49 in magnitude) and B1 - B0 = (g2+e2)(g3+e3)(g4+e4) - g2 g3 g4 (modulo
+        // 2^64); their product is (A0 - A1)(B0 - B1). Every row value with or without a
+        // column stays below 2^24 in magnitude, so the shifted rows are exact 32-bit sums.
 #define HP_QUAD_BLOCK()                                                                    \
     {                                                                                      \
-        const int64_t a0 = (int64_t)(int32_t)f[0] * (int64_t)(int32_t)f[1];                \
-        const int64_t a1 = (int64_t)(int32_t)(f[0] + d0[0]) * (int64_t)(int32_t)(f[1] + d0[1]); \
-        const uint64_t b0 = (uint64_t)((int64_t)(int32_t)f[2] * (int64_t)(int32_t)f[3]) *  \
-                            (uint64_t)(int64_t)(int32_t)f[4];                              \
-        const uint64_t b1 = (uint64_t)((int64_t)(int32_t)(f[2] + d1[0]) * (int64_t)(int32_t)(f[3] + d1[1])) * \
-                            (uint64_t)(int64_t)(int32_t)(f[4] + d1[2]);                    \
-        const uint64_t x = ((uint64_t)a0 - (uint64_t)a1) * (b0 - b1);                      \
+        const int g0_ = (int)f[0], g1_ = (int)f[1], g2_ = (int)f[2], g3_ = (int)f[3], g4_ = (int)f[4]; \
+        const int64_t da = k01 + (int64_t)e0 * g1_ + (int64_t)e1 * g0_;                   \
+        const uint64_t b0 = (uint64_t)((int64_t)g2_ * g3_) * (uint64_t)(int64_t)g4_;      \
+        const uint64_t b1 = (uint64_t)((int64_t)(g2_ + e2) * (int64_t)(g3_ + e3)) *       \
+                            (uint64_t)(int64_t)(g4_ + e4);                                 \
+        const uint64_t x = (uint64_t)da * (b1 - b0);                                      \
         const uint32_t smask = 0u - ((t >> 2) & 1u);   /* all ones: minus (odd blocks) */  \
         R::acc(acc, R::pair_mul(S[HB], (int64_t)x), (uint32_t)((int)G[HB] >> 31) ^ smask); \
     }
+        // Blocks at t = 0, 4, .., L - 4 (L is a multiple of 4: the host gives this walk c >= 2).
+        // Between blocks t and t + 4 column ctz(t + 4) >= 2 flips: column 2 after every other
+        // block (its top block fixed for the item), a higher column after the rest.
+        const uint32_t top2 = (uint32_t)(tops >> 8) & 15u;
         uint32_t t = 0;
         HP_QUAD_BLOCK()
-        while ((uint64_t)t + 4 < L) {   // L is a multiple of 4 (the host gives this walk c >= 2)
-            const int j = __builtin_ctz(t + 4);   // >= 2
-            const float dirj = __uint_as_float(0x3f800000u | ((((t + 4) >> (j + 1)) & 1u) << 31));
-            HP_FLIP_Q((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj, HB - 1)
+        while ((uint64_t)t + 4 < L) {   // t is a multiple of 8 here
+            {
+                const float dir2 = __uint_as_float(0x3f800000u | ((((t + 4) >> 3) & 1u) << 31));
+                HP_FLIP_Q(top2, tab + 2 * STRIDE, dir2, HB - 1)
+            }
+            t += 4;
+            HP_QUAD_BLOCK()
+            if ((uint64_t)t + 4 >= L) break;
+            {
+                const int j = __builtin_ctz(t + 4);   // >= 3
+                const float dirj = __uint_as_float(0x3f800000u | ((((t + 4) >> (j + 1)) & 1u) << 31));
+                HP_FLIP_Q((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj, HB - 1)
+            }
             t += 4;
             HP_QUAD_BLOCK()
         }
