@@ -807,9 +807,10 @@ def main():
     # probe measured for them (v_mul_lo_u32 2.5 and v_mad_u64_u32 3.8 full-rate slots instead
     # of 2 each; mod 2^64 only)
     WALK_NAMES = {0: "step-pair walk", 1: "paired walk, two-row column 0",
-                  2: "paired walk, three-row column 0", 6: "four-step walk, two disjoint columns"}
+                  2: "paired walk, three-row column 0", 6: "four-step walk, two-row column 0",
+                  7: "four-step walk, three-row column 0"}
     mul_slots, add_slots = {0: (5.0, 2.0), 1: (9.0, 4.0), 2: (33.0, 9.0)}[ring]
-    adds = dom["terms"] / dom["n"] / {0: 1.0, 1: 2.0, 2: 2.0, 6: 4.0}[variant]
+    adds = dom["terms"] / dom["n"] / {0: 1.0, 1: 2.0, 2: 2.0, 6: 4.0, 7: 4.0}[variant]
     mults = (alg_per_launch - add_slots * adds - dom["upd"] / dom["n"]) / mul_slots
     probe_frac = ((alg_per_launch + mults * (2.5 + 3.8 - 4.0)) / (avg_ms * 1e-3) / ALU_PEAK
                   if ring == 0 else None)

@@ -353,11 +353,12 @@ static double ring_add_slots(int ring) { return ring == HP_W64 ? 2.0 : ring == H
 // addition. In the paired walk (variant v = 1, 2; b = v + 1 rows below the pair boundary) the
 // L / 2 flips of column 0 give way to one pair sum each (two products of b rows and one
 // multiply by the suffix above them: 2(b - 1) + 1 ring multiplies and one ring addition per
-// pair), and the other flips re-multiply only from row b up. In the four-step walk (variant 6;
-// column 0 on rows 0..1, column 1 on rows of 2..4) the flips of columns 0 and 1 give way to
-// one block sum per four steps (the products of rows 0..1 and of rows 2..4 without and with
-// their column, their differences' product and the multiply by the suffix: 8 ring multiplies
-// and one ring addition), and the other flips re-multiply only from row 5 up.
+// pair), and the other flips re-multiply only from row b up. In the four-step walks (variant
+// 6: column 0 on rows 0..1, column 1 on rows of 2..4, b = 5; variant 7: rows 0..2 and rows of
+// 3..5, b = 6) the flips of columns 0 and 1 give way to one block sum per four steps (the
+// products of A and of B without and with their column, their differences' product and the
+// multiply by the suffix: 2b - 2 ring multiplies and one ring addition), and the other flips
+// re-multiply only from row b up.
 struct JobWork {
     double mults, adds, updates;
 };
@@ -368,8 +369,8 @@ static JobWork job_work(const JobDesc &d, const uint32_t *data, int chunk, int v
     const double L = std::ldexp(1.0, chunk);
     const double chunks = std::ldexp(1.0, m - 1) / L;
     double mults = m, updates = 0, adds = L;
-    if (variant == 6) {
-        const double b = 5.0;   // the kernel's boundary row
+    if (variant >= 6) {
+        const double b = variant == 6 ? 5.0 : 6.0;   // the kernel's boundary row
         mults += L / 4 * (2.0 * b - 2.0);
         for (int j = 2; j < chunk && j + 1 < m; ++j) {
             const double flips = L / std::ldexp(1.0, j + 1);
@@ -469,9 +470,9 @@ uint64_t split_wide_total(const std::vector<JobDesc> &desc, const hperm_opts &o)
 static void build_queue_groups(hperm_jobs *j, int split) {
     const std::vector<JobDesc> &dsc = j->tab.desc;
     const size_t nd = dsc.size();
-    constexpr int NV = 4;   // walks 0, 1, 2 and the four-step walk (variant 6) at index 3
-    auto vindex = [](int v) { return v == 6 ? 3 : v; };
-    auto vof = [](int i) { return i == 3 ? 6 : i; };
+    constexpr int NV = 5;   // walks 0, 1, 2 and the four-step walks (variants 6, 7) at indices 3, 4
+    auto vindex = [](int v) { return v >= 6 ? v - 3 : v; };
+    auto vof = [](int i) { return i >= 3 ? i + 3 : i; };
     constexpr int NG = HP_RNW_BUCKETS * HP_NRING * NV;
     constexpr int SPLIT_G = NG;   // the device H_per group
     constexpr uint64_t kSmallGroupItems = 16384;
@@ -567,7 +568,7 @@ static void apply_tuning(Dev *c, hperm_jobs *j) {
         const int v0 = walk_variant(d0, d0.chunk_log2);
         const auto it = table.find(tune_key(d.arith, bucket_of(d.m), v0));
         if (it != table.end() && d0.chunk_log2 > 0)
-            want = tuned_chunk(d.m, d0.chunk_log2, it->second.chunk_delta, v0 == 6 ? 2 : 1);
+            want = tuned_chunk(d.m, d0.chunk_log2, it->second.chunk_delta, v0 >= 6 ? 2 : 1);
         if (d.chunk_log2 != want) {
             d.chunk_log2 = (uint8_t)want;
             changed = true;

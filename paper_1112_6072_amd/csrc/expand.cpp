@@ -378,7 +378,7 @@ static void emit_job_oriented(const NodeT &a, int problem, double root_log2, con
         throw RangeError{"the requested arithmetic is too narrow for this problem's bound"};
     int gray[HP_MAX_M];
     // greedy choice as a branch-free minimum of keys (new rows, nonzeros, column index). For a
-    // mod 2^64 job whose first Gray column reaches at most two rows, Gray column 1 is instead
+    // mod 2^64 job whose first Gray column reaches at most three rows, Gray column 1 is instead
     // the sparsest column (at most three rows) that avoids those rows, if there is one: the
     // kernels then take the walk's steps four at a time.
     uint64_t avail = (m == 64 ? ~0ull : ((1ull << m) - 1)) & ~(1ull << fixed);
@@ -386,7 +386,7 @@ static void emit_job_oriented(const NodeT &a, int problem, double root_log2, con
     bool quad = false;
     for (int g = 0; g + 1 < m; ++g) {
         uint32_t bestkey = ~0u;
-        if (g == 1 && ring == HP_W64 && m >= 4 && __builtin_popcountll(covered) <= 2) {
+        if (g == 1 && ring == HP_W64 && m >= 5 && __builtin_popcountll(covered) <= 3) {
             for (uint64_t rest = avail; rest; rest &= rest - 1) {
                 const int j = __builtin_ctzll(rest);
                 const int rows = __builtin_popcountll(colrows[j]);
@@ -488,10 +488,14 @@ static void emit_job_oriented(const NodeT &a, int problem, double root_log2, con
     hi[m - 1] = (uint32_t)m;
     if (m >= 2 && hi[0] <= 2) d.flags |= HP_FLAG_COL0_TWO_ROWS;
     else if (m >= 3 && hi[0] == 3) d.flags |= HP_FLAG_COL0_THREE_ROWS;
-    // column 0 on rows 0..1, column 1 on rows 2..3 or 2..4 (disjoint, so all of level 1): the
-    // kernels' four-step walk takes B as rows 2..4 (row 4 untouched by column 1 for |B| = 2)
-    if (quad && m >= 5 && hi[0] == 2 && (hi[1] == 4 || hi[1] == 5) &&
-        __builtin_popcountll(colrows[gray[0]]) == 2 && (uint32_t)__builtin_popcountll(colrows[gray[1]]) == hi[1] - 2)
+    // the four-step walks: column 0 on rows 0..a-1 (a = 2 or 3, all of level 0) and column 1
+    // on rows a .. hi[1]-1 (disjoint, so all of level 1) with hi[1] <= a + 3; the kernels take
+    // B as rows a..a+2 (rows that column 1 misses are common factors)
+    const uint32_t qa = hi[0];
+    if (quad && (qa == 2 || qa == 3) && m >= (int)qa + 3 && hi[1] > qa && hi[1] <= qa + 3 &&
+        (uint32_t)__builtin_popcountll(colrows[gray[0]]) == qa &&
+        (uint32_t)__builtin_popcountll(colrows[gray[1]]) == hi[1] - qa &&
+        (colrows[gray[0]] & colrows[gray[1]]) == 0)
         d.flags |= HP_FLAG_QUAD;
     if (transposed) d.flags |= HP_FLAG_TRANSPOSED;
     uint32_t *ent = w + 3 * m;

@@ -362,9 +362,9 @@ __device__ __forceinline__ uint32_t block_of(uint32_t h) {
         HP_BLOCK_F(0)                                                                      \
     }
 
-// A flip in the four-step walk (boundary row HB = QB + 1, a block top): blocks QB and up are
-// recomputed in full, the blocks below (rows 0 .. HB-1, columns 0 and 1 held out) only get
-// their new row values.
+// A flip in the four-step walks (QB = 4 or 5, the block whose first row is the boundary row):
+// blocks QB and up are recomputed in full, the blocks below (rows of A and B, whose values
+// are held without columns 0 and 1) only get their new row values.
 #define HP_FLIP_Q(TOP, DJ, DIR, QB)                                                        \
     {                                                                                      \
         const uint32_t top_ = (TOP);                                                       \
@@ -397,10 +397,11 @@ template <class R, int MAXM, int V0>
 __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__restrict__ data,
                                          uint64_t item, int lane, JobAcc *dst, float *tab) {
     static_assert(MAXM <= 40, "job orders up to 40");
-    static_assert(V0 >= 0 && V0 <= 3, "walk variant");
-    // V = 3, the four-step walk, exists for the 64-bit ring only (the host gives it no other
-    // jobs); the other rings' instantiations of it are the two-row walk
-    constexpr int V = (V0 == 3 && !R::kFourStep) ? 1 : V0;
+    static_assert(V0 >= 0 && V0 <= 4, "walk variant");
+    // V = 3, 4, the four-step walks, exist for the 64-bit ring only (the host gives them no
+    // other jobs, and the other rings have no such kernels)
+    static_assert(V0 < 3 || R::kFourStep, "four-step walks are mod 2^64 only");
+    constexpr int V = V0;
     constexpr int STRIDE = Tab<MAXM>::STRIDE;
     constexpr int NB = Blocks<MAXM>::N;
     const int m = jd.m;
@@ -492,36 +493,50 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
                 HP_FLIP((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj)
             }
         }
-    } else if constexpr (V == 3) {
-        // Four-step walk (mod 2^64 jobs flagged by the host, lane chunks of at least 4 steps):
-        // Gray column 0 touches only rows 0..1 (A), column 1 only rows of 2..4 (B; row 4, when
-        // column 1 misses it, is a factor of both B products and so of the sum), and f holds
-        // rows 0..4 with both columns out. In the block of steps t..t+3 (t = 4q) every other
-        // column is fixed and the four terms, with signs (-1)^q (+, -, +, -) in the reflected
-        // code's order, sum to (-1)^q (A0 - A1)(B0 - B1) times the rows from 5 up: A0, A1 the
-        // products of A without and with column 0, B0, B1 those of B without and with column 1.
-        // One multiply of the suffix S_5 per four terms, and the flips (columns 2 and up)
-        // recompute the suffix products from row 5 up only.
-        constexpr int HB = 5;
-        // column 0's deltas on rows 0..1 and column 1's on rows 2..4, as wave-uniform integers
-        const int e0 = (int)__uint_as_float(uni(__float_as_uint(tab[0])));
-        const int e1 = (int)__uint_as_float(uni(__float_as_uint(tab[1])));
-        const int e2 = (int)__uint_as_float(uni(__float_as_uint(tab[STRIDE + 2])));
-        const int e3 = (int)__uint_as_float(uni(__float_as_uint(tab[STRIDE + 3])));
-        const int e4 = (int)__uint_as_float(uni(__float_as_uint(tab[STRIDE + 4])));
-        const int64_t k01 = (int64_t)uni64((uint64_t)((int64_t)e0 * e1));
-        // Block sum: with g the rows without columns 0 and 1, A1 - A0 = e0 g1 + e1 g0 + e0 e1
-        // (below 2^49 in magnitude) and B1 - B0 = (g2+e2)(g3+e3)(g4+e4) - g2 g3 g4 (modulo
-        // 2^64); their product is (A0 - A1)(B0 - B1). Every row value with or without a
-        // column stays below 2^24 in magnitude, so the shifted rows are exact 32-bit sums.
+    } else if constexpr (V >= 3) {
+        // Four-step walks (mod 2^64 jobs flagged by the host, lane chunks of at least 4 steps),
+        // V = 3 with HA = 2, V = 4 with HA = 3: Gray column 0 touches exactly rows 0..HA-1 (A)
+        // and column 1 only rows of HA..HB-1, HB = HA + 3 (B; a row of B that column 1 misses
+        // is a factor of both B products and so of the sum); f holds rows 0..HB-1 with both
+        // columns out. In the block of steps t..t+3 (t = 4q) every other column is fixed and
+        // the four terms, with signs (-1)^q (+, -, +, -) in the reflected code's order, sum to
+        // (-1)^q (A0 - A1)(B0 - B1) times the rows from HB up: A0, A1 the products of A
+        // without and with column 0, B0, B1 those of B without and with column 1. One
+        // multiply of the suffix S_HB per four terms, and the flips (columns 2 and up)
+        // recompute the suffix products from row HB up only (HB is a block's first row: block
+        // QB and up are recomputed in full, the blocks below get their new row values).
+        constexpr int HA = V - 1;
+        constexpr int HB = HA + 3;
+        constexpr int QB = HA == 2 ? 4 : 5;
+        // column 0's deltas on rows 0..HA-1 and column 1's on rows HA..HB-1, as wave-uniform
+        // integers
+        int ea[HA], eb[3];
+#pragma unroll
+        for (int i = 0; i < HA; ++i) ea[i] = (int)__uint_as_float(uni(__float_as_uint(tab[i])));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) eb[i] = (int)__uint_as_float(uni(__float_as_uint(tab[STRIDE + HA + i])));
+        const int64_t k01 = (int64_t)uni64((uint64_t)((int64_t)ea[0] * ea[1]));
+        // Block sum: with g the rows without columns 0 and 1, A1 - A0 (for HA = 2 formed as
+        // e0 g1 + e1 g0 + e0 e1, below 2^49 in magnitude) times B1 - B0 (modulo 2^64) is
+        // (A0 - A1)(B0 - B1). Every row value with or without a column stays below 2^24 in
+        // magnitude, so the shifted rows are exact 32-bit sums.
 #define HP_QUAD_BLOCK()                                                                    \
     {                                                                                      \
-        const int g0_ = (int)f[0], g1_ = (int)f[1], g2_ = (int)f[2], g3_ = (int)f[3], g4_ = (int)f[4]; \
-        const int64_t da = k01 + (int64_t)e0 * g1_ + (int64_t)e1 * g0_;                   \
-        const uint64_t b0 = (uint64_t)((int64_t)g2_ * g3_) * (uint64_t)(int64_t)g4_;      \
-        const uint64_t b1 = (uint64_t)((int64_t)(g2_ + e2) * (int64_t)(g3_ + e3)) *       \
-                            (uint64_t)(int64_t)(g4_ + e4);                                 \
-        const uint64_t x = (uint64_t)da * (b1 - b0);                                      \
+        int g_[HB];                                                                        \
+        _Pragma("unroll") for (int i_ = 0; i_ < HB; ++i_) g_[i_] = (int)f[i_];             \
+        uint64_t da;                                                                       \
+        if constexpr (HA == 2) {                                                           \
+            da = (uint64_t)(k01 + (int64_t)ea[0] * g_[1] + (int64_t)ea[1] * g_[0]);        \
+        } else {                                                                           \
+            const uint64_t a0 = (uint64_t)((int64_t)g_[0] * g_[1]) * (uint64_t)(int64_t)g_[2]; \
+            const uint64_t a1 = (uint64_t)((int64_t)(g_[0] + ea[0]) * (int64_t)(g_[1] + ea[1])) * \
+                                (uint64_t)(int64_t)(g_[2] + ea[2]);                        \
+            da = a1 - a0;                                                                  \
+        }                                                                                  \
+        const uint64_t b0 = (uint64_t)((int64_t)g_[HA] * g_[HA + 1]) * (uint64_t)(int64_t)g_[HA + 2]; \
+        const uint64_t b1 = (uint64_t)((int64_t)(g_[HA] + eb[0]) * (int64_t)(g_[HA + 1] + eb[1])) * \
+                            (uint64_t)(int64_t)(g_[HA + 2] + eb[2]);                       \
+        const uint64_t x = da * (b1 - b0);                                                 \
         const uint32_t smask = 0u - ((t >> 2) & 1u);   /* all ones: minus (odd blocks) */  \
         R::acc(acc, R::pair_mul(S[HB], (int64_t)x), (uint32_t)((int)G[HB] >> 31) ^ smask); \
     }
@@ -534,7 +549,7 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
         while ((uint64_t)t + 4 < L) {   // t is a multiple of 8 here
             {
                 const float dir2 = __uint_as_float(0x3f800000u | ((((t + 4) >> 3) & 1u) << 31));
-                HP_FLIP_Q(top2, tab + 2 * STRIDE, dir2, HB - 1)
+                HP_FLIP_Q(top2, tab + 2 * STRIDE, dir2, QB)
             }
             t += 4;
             HP_QUAD_BLOCK()
@@ -542,7 +557,7 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
             {
                 const int j = __builtin_ctz(t + 4);   // >= 3
                 const float dirj = __uint_as_float(0x3f800000u | ((((t + 4) >> (j + 1)) & 1u) << 31));
-                HP_FLIP_Q((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj, HB - 1)
+                HP_FLIP_Q((uint32_t)(tops >> (4 * j)) & 15u, tab + j * STRIDE, dirj, QB)
             }
             t += 4;
             HP_QUAD_BLOCK()
@@ -1081,8 +1096,8 @@ int est_bucket_of(int m) { return m <= 16 ? 0 : (m <= 20 ? 1 : (m <= 24 ? 2 : (m
 
 int walk_variant(const JobDesc &d, int chunk_log2) {
     if (chunk_log2 < 1) return 0;
-    if ((d.flags & HP_FLAG_QUAD) && (d.flags & HP_FLAG_COL0_TWO_ROWS) && d.arith == HP_W64 && chunk_log2 >= 2)
-        return 6;   // the four-step walk
+    if ((d.flags & HP_FLAG_QUAD) && d.arith == HP_W64 && chunk_log2 >= 2)
+        return (d.flags & HP_FLAG_COL0_TWO_ROWS) ? 6 : 7;   // the four-step walks
     return (d.flags & HP_FLAG_COL0_TWO_ROWS) ? 1 : (d.flags & HP_FLAG_COL0_THREE_ROWS) ? 2 : 0;
 }
 
@@ -1117,15 +1132,23 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
 #endif  // HP_PART == 0
 
 #if HP_PART >= 1
+// HP_V6, HP_V7: the kernels of launch variants 6 and 7 (the four-step walks, which only the
+// 64-bit ring has; the host gives the other rings no such jobs)
 #if HP_PART == 1
 #define RING_T RingW64
 #define RING_SUFFIX w64
+#define HP_V6 3
+#define HP_V7 4
 #elif HP_PART == 2
 #define RING_T RingW128
 #define RING_SUFFIX w128
+#define HP_V6 1
+#define HP_V7 2
 #else
 #define RING_T RingRes
 #define RING_SUFFIX res
+#define HP_V6 1
+#define HP_V7 2
 #endif
 #define CAT2(a, b) a##_##b
 #define CAT(a, b) CAT2(a, b)
@@ -1134,7 +1157,8 @@ hipError_t launch_estimate(int bucket, const JobDesc *jobs, const uint32_t *data
 #define HP_FN(K, MAXM)                                                                     \
     (variant == 1   ? (const void *)K<RING_T, MAXM, 1>                                     \
      : variant == 2 ? (const void *)K<RING_T, MAXM, 2>                                     \
-     : variant == 6 ? (const void *)K<RING_T, MAXM, 3>                                     \
+     : variant == 6 ? (const void *)K<RING_T, MAXM, HP_V6>                                 \
+     : variant == 7 ? (const void *)K<RING_T, MAXM, HP_V7>                                 \
                     : (const void *)K<RING_T, MAXM, 0>)
 static const void *persistent_fn(int bucket, int variant, bool timed) {
     if (!timed) {

@@ -215,8 +215,8 @@ extern "C" hperm_status hperm_autotune(hperm_ctx *c, hperm_jobs *j, const char *
                 int sig = 0;
                 for (size_t k = 0; k < K; ++k) {
                     td[k] = j->tab.desc[sample[k]];
-                    // the four-step walk (variant 6) needs lane chunks of 4 steps at least
-                    const int ch = tuned_chunk_of(td[k].m, j->chunk0[sample[k]], delta, variant == 6 ? 2 : 1);
+                    // the four-step walks (variants 6, 7) need lane chunks of 4 steps at least
+                    const int ch = tuned_chunk_of(td[k].m, j->chunk0[sample[k]], delta, variant >= 6 ? 2 : 1);
                     td[k].chunk_log2 = (uint8_t)ch;
                     if (k == 0) sig = ch;
                     ie[k] = acc += items_for(td[k].m, ch);

@@ -93,6 +93,36 @@ def test_arith_mode_choice_from_bounds(hp):
     assert list(d["arith"]) == [hp.ARITH_RES]
 
 
+def test_gray_order_for_the_four_step_walks(hp):
+    """For a mod 2^64 job whose first Gray column reaches at most three rows, Gray column 1 is
+    the sparsest column (of at most three rows) that avoids those rows when one exists, and
+    the job's rows are ordered column 0's first, then column 1's (the layout the kernels'
+    four-step walks take: A = rows 0..a-1, B = rows of a..a+2)."""
+    shapes = {2: 0, 3: 0}
+    for seed in range(6):
+        ctx = hp.Context({"m_cut": 14}, host_only=True)
+        J = ctx.expand([W.random_cubic_matrix(26, seed)])
+        d = J.describe()
+        for k in range(len(d["m"])):
+            A = J.matrix(k)
+            m = A.shape[0]
+            r0 = set(np.nonzero(A[:, 0])[0])
+            a = len(r0)
+            if d["arith"][k] != hp.ARITH_W64 or a > 3 or m < 5:
+                continue
+            assert r0 == set(range(a))
+            cand = [len(np.nonzero(A[:, j])[0]) for j in range(1, m - 1)
+                    if not r0 & set(np.nonzero(A[:, j])[0]) and 1 <= len(np.nonzero(A[:, j])[0]) <= 3]
+            if not cand:
+                continue
+            r1 = set(np.nonzero(A[:, 1])[0])
+            assert not r0 & r1 and len(r1) == min(cand)
+            assert r1 == set(range(a, a + len(r1)))
+            if a >= 2 and m >= a + 3:
+                shapes[a] += 1
+    assert shapes[2] > 0 and shapes[3] > 0
+
+
 def test_terms_and_orders(hp):
     ctx = hp.Context({"m_cut": 14}, host_only=True)
     d = ctx.expand([W.random_cubic_matrix(24, 0)]).describe()
