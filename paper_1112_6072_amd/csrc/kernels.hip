@@ -866,7 +866,6 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
     const int wave = threadIdx.x >> 6;
     const int grp = lane / GROUP;             // trial slot inside the wave
     const int r = lane % GROUP;               // row held by this lane
-    const int gbase = lane - r;               // first lane of the group
     const int m = jd.m;
     const int nnz = (int)jd.nnz;
     const uint32_t *w = data + (size_t)jd.data_off * HP_DATA_ALIGN;
@@ -878,28 +877,30 @@ __global__ __launch_bounds__(BLOCK, (MAXM <= 24 ? 6 : 3)) void kkl_estimate(cons
 
     // The job's nonzeros once per block: for entry e, the counter bits (original row << 6 |
     // original column, of the untransposed sub-matrix) of its random draw and its byte
-    // position in a staged matrix. Gray
-    // entries first, then one slot per row for the fixed column (b_i,fixed = base_i + the
-    // row's Gray entries; a zero entry gets no draw).
+    // position in a staged matrix. Gray entries first (thread j < m-1 takes Gray column j's
+    // entries, so the loads of all columns are in flight at once), then one slot per row for
+    // the fixed column: b_i,fixed = base_i + the row's Gray entries, summed by LDS atomics into
+    // fixv (a zero entry gets no draw).
+    __shared__ int fixv[MAXM];
     const int tid = threadIdx.x;
     const bool tr = (jd.flags & HP_FLAG_TRANSPOSED) != 0;   // draws follow the untransposed job
-    for (int col = 0; col < m - 1; ++col) {
-        const uint32_t b = uni(cs[col]);
-        const uint32_t n = uni(cs[col + 1]) - b;
-        const uint32_t ccol = uni(cmap[col]);
-        for (uint32_t q = (uint32_t)tid; q < n; q += BLOCK) {
-            const int row = (int)(ent[b + q] & 0xff);
-            ekey[b + q] = tr ? ((ccol << 6) | rmap[row]) : ((rmap[row] << 6) | ccol);
-            epos[b + q] = (uint16_t)(row * Sh::LD + col);
+    if (tid < m) fixv[tid] = (int)w[tid];
+    __syncthreads();
+    if (tid < m - 1) {
+        const uint32_t b = cs[tid], e = cs[tid + 1];
+        const uint32_t ccol = cmap[tid];
+        for (uint32_t q = b; q < e; ++q) {
+            const uint32_t pk = ent[q];
+            const int row = (int)(pk & 0xff);
+            atomicAdd(&fixv[row], (int)(pk >> 9));
+            const uint32_t rr = rmap[row];
+            ekey[q] = tr ? ((ccol << 6) | rr) : ((rr << 6) | ccol);
+            epos[q] = (uint16_t)(row * Sh::LD + tid);
         }
     }
+    __syncthreads();
     if (tid < m) {
-        int gsum = 0;
-        for (int e = 0; e < nnz; ++e) {
-            const uint32_t pk = ent[e];
-            if ((int)(pk & 0xff) == tid) gsum += (int)(pk >> 9);
-        }
-        const bool nz = ((int)w[tid] + gsum) != 0;
+        const bool nz = fixv[tid] != 0;
         ekey[nnz + tid] = !nz ? ~0u : tr ? ((cmap[m - 1] << 6) | rmap[tid]) : ((rmap[tid] << 6) | cmap[m - 1]);
         epos[nnz + tid] = (uint16_t)(tid * Sh::LD + (m - 1));
     }
