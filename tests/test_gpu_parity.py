@@ -106,6 +106,25 @@ def test_job_orders_rows_32_to_40(hperm, ctx):
     assert totals == [2, 2]
 
 
+def test_four_step_walks_every_order_bucket(hperm, ctx):
+    """Sparse 0-1 jobs of orders 12..40 in the 64-bit ring whose first Gray columns take the
+    four-step walks' shapes (column 0 on two or three rows, column 1 on rows disjoint from
+    them): cubic graphs (three-row shape) and unions of two or three permutations (mostly the
+    two-row shape), one or more per order bucket, job by job against the oracle's DP."""
+    mats = ([W.random_cubic_matrix(n, 40 + n) for n in (12, 18, 22, 28, 32)]
+            + [W.permutation_union_matrix(n, 3, 60 + n, 1, 1) for n in (16, 20, 24, 30, 33)]
+            + [W.permutation_union_matrix(n, 2, 60 + n, 1, 1) for n in (22, 37, 40)])
+    want = [per_dp(A.astype(np.int64).tolist()) for A in mats]
+    say("four-step walks, orders", [A.shape[0] for A in mats])
+    J = ctx.jobs_from_dense(mats)
+    assert set(J.describe()["arith"]) == {hperm.ARITH_W64}
+    totals, per_job, _ = ctx.run(J, "natural", True, per_job=True)
+    launches = {(L["bucket"], L["variant"]) for L in ctx.last_launches()}
+    assert per_job == want
+    assert totals == want
+    assert {(b, 7) for b in (0, 2, 3)} <= launches and {(b, 6) for b in (0, 2, 3, 4)} <= launches
+
+
 # ------------------------------------------------------------------ expansion + R-NW
 @pytest.mark.parametrize("m_cut", [10, 14])
 def test_leaf_values_match_oracle_leaves(hperm, ctx, m_cut):
