@@ -811,7 +811,9 @@ def main():
                   7: "four-step walk, three-row column 0"}
     mul_slots, add_slots = {0: (5.0, 2.0), 1: (9.0, 4.0), 2: (33.0, 9.0)}[ring]
     adds = dom["terms"] / dom["n"] / {0: 1.0, 1: 2.0, 2: 2.0, 6: 4.0, 7: 4.0}[variant]
-    mults = (alg_per_launch - add_slots * adds - dom["upd"] / dom["n"]) / mul_slots
+    # the four-step walks' full-rate block slots (FP32 products, conversions, 24-bit product)
+    extra = dom["terms"] / dom["n"] / 4.0 * {6: 17.0, 7: 20.0}.get(variant, 0.0)
+    mults = (alg_per_launch - add_slots * adds - dom["upd"] / dom["n"] - extra) / mul_slots
     probe_frac = ((alg_per_launch + mults * (2.5 + 3.8 - 4.0)) / (avg_ms * 1e-3) / ALU_PEAK
                   if ring == 0 else None)
     rnw_ms = sum(g["ms"] for g in groups.values()) / args.steps

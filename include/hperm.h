@@ -518,7 +518,7 @@ typedef struct hperm_launch_stat {
                                walks (mod 2^64, lane chunks of 4 indices or more) of jobs whose
                                Gray column 0 reaches exactly the first a = 2 / 3 rows and Gray
                                column 1 (with rows disjoint from column 0's) only rows of
-                               a..a+2 */
+                               a..a+2, rows 0..a+2 having row sums below 2^7 */
     int32_t reserved;       /* variant 3: the launch's resident waves; variant 4 or 5: the
                                problems of the group */
     uint64_t items;         /* work items (64 lanes x 2^chunk Gray indices each) */
@@ -533,9 +533,11 @@ typedef struct hperm_launch_stat {
                                each flip of column 0 is replaced by one pair sum (2(b-1) + 1
                                ring multiplies, one ring addition per two terms) and the other
                                flips multiply only hi[j] - b rows. In the four-step walks
-                               (variant 6 / 7, b = 5 / 6) each block of four terms is one
-                               product of two differences (2(b-1) ring multiplies, one ring
-                               addition) and the flips of column j >= 2 multiply hi[j] - b rows. One ring multiply by a 32-bit factor costs mul = 5
+                               (variant 6 / 7, b = 5 / 6) each block of four terms counts the
+                               FP32 products and differences of its rows 0..b-1 (13 / 16
+                               slots), two conversions and a 24-bit product (4), the 64 x
+                               64-bit multiply by the suffix (1.4 ring multiplies) and one ring
+                               addition; the flips of column j >= 2 multiply hi[j] - b rows. One ring multiply by a 32-bit factor costs mul = 5
                                (mod 2^64), 9 (mod 2^128) or 3 * 11 (residues) slots and one
                                ring addition add = 2, 4 or 3 * 3 slots; v_mad_u64_u32 and
                                v_mul_lo_u32 count 2 slots (half rate), other ops 1 */

@@ -355,12 +355,16 @@ static double ring_add_slots(int ring) { return ring == HP_W64 ? 2.0 : ring == H
 // multiply by the suffix above them: 2(b - 1) + 1 ring multiplies and one ring addition per
 // pair), and the other flips re-multiply only from row b up. In the four-step walks (variant
 // 6: column 0 on rows 0..1, column 1 on rows of 2..4, b = 5; variant 7: rows 0..2 and rows of
-// 3..5, b = 6) the flips of columns 0 and 1 give way to one block sum per four steps (the
-// products of A and of B without and with their column, their differences' product and the
-// multiply by the suffix: 2b - 2 ring multiplies and one ring addition), and the other flips
-// re-multiply only from row b up.
+// 3..5, b = 6; row values below 2^7) the flips of columns 0 and 1 give way to one block sum
+// per four steps: the products of A and of B without and with their column and the two
+// differences in FP32 (2(a - 1) + 4 multiplies, a + 3 shifted rows, 2 differences: 13 / 16
+// full-rate slots), two conversions and one 24-bit product of the differences (4 slots), the
+// 64 x 64-bit multiply by the suffix (7 slots at the weights below: 1.4 ring multiplies) and
+// one ring addition. The other flips re-multiply only from row b up. `extra` holds the
+// full-rate slots that are neither ring operations nor row updates.
 struct JobWork {
     double mults, adds, updates;
+    double extra = 0.0;
 };
 static JobWork job_work(const JobDesc &d, const uint32_t *data, int chunk, int variant) {
     const int m = d.m;
@@ -371,13 +375,15 @@ static JobWork job_work(const JobDesc &d, const uint32_t *data, int chunk, int v
     double mults = m, updates = 0, adds = L;
     if (variant >= 6) {
         const double b = variant == 6 ? 5.0 : 6.0;   // the kernel's boundary row
-        mults += L / 4 * (2.0 * b - 2.0);
+        const double blocks = L / 4;
+        mults += blocks * 1.4;
+        const double extra = blocks * (variant == 6 ? 17.0 : 20.0);
         for (int j = 2; j < chunk && j + 1 < m; ++j) {
             const double flips = L / std::ldexp(1.0, j + 1);
             updates += flips * (cs[j + 1] - cs[j]);
             mults += flips * std::max(0.0, (double)hi[j] - b);
         }
-        return {chunks * mults, chunks * L / 4, chunks * updates};
+        return {chunks * mults, chunks * blocks, chunks * updates, chunks * extra};
     }
     for (int j = 0; j < chunk && j + 1 < m; ++j) {
         const double flips = L / std::ldexp(1.0, j + 1);
@@ -519,6 +525,7 @@ static void build_queue_groups(hperm_jobs *j, int split) {
         q.mults += wk.mults;
         q.adds += wk.adds;
         q.updates += wk.updates;
+        q.extra += wk.extra;
     }
     int index[NG + 1];
     j->qgroups.clear();
@@ -844,7 +851,7 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
             st.items = g.items;
             st.terms = g.terms;
             st.row_updates = (uint64_t)g.updates;
-            st.alg_slots = g.mults * ring_mul_slots(g.ring) + g.adds * ring_add_slots(g.ring) + g.updates;
+            st.alg_slots = g.mults * ring_mul_slots(g.ring) + g.adds * ring_add_slots(g.ring) + g.updates + g.extra;
             if (g.variant == kSplitVariant) {
                 c->split_launch = (int)gi;
                 st.reserved = split_grid(split_in_effect(c->opts), g.mmax);   // its resident waves
@@ -915,7 +922,7 @@ hperm_status run_enqueue(Dev *c, hperm_jobs *j, int order, int persistent, bool 
         st.items += items_of(d.m, d.chunk_log2);
         st.terms += t;
         st.row_updates += (uint64_t)wk.updates;
-        st.alg_slots += wk.mults * ring_mul_slots(d.arith) + wk.adds * ring_add_slots(d.arith) + wk.updates;
+        st.alg_slots += wk.mults * ring_mul_slots(d.arith) + wk.adds * ring_add_slots(d.arith) + wk.updates + wk.extra;
     }
     c->launches.push_back(st);   // all single launches as one record (ms = whole span)
     s = hip_check(c, hipEventRecord(c->ev1, c->stream), "event");

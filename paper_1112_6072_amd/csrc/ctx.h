@@ -64,6 +64,7 @@ struct hperm_jobs {
         double mults, adds, updates;
         int mmax = 0;        // device H_per group: largest job order
         uint64_t wide = 0;   // ... and the bound on its deferred wide leaves
+        double extra = 0.0;  // full-rate slots besides ring operations and row updates
     };
     // the estimator's job list (jobs grouped by its order buckets, natural order inside) and
     // the bucket offsets, also filled once

@@ -490,9 +490,14 @@ static void emit_job_oriented(const NodeT &a, int problem, double root_log2, con
     else if (m >= 3 && hi[0] == 3) d.flags |= HP_FLAG_COL0_THREE_ROWS;
     // the four-step walks: column 0 on rows 0..a-1 (a = 2 or 3, all of level 0) and column 1
     // on rows a .. hi[1]-1 (disjoint, so all of level 1) with hi[1] <= a + 3; the kernels take
-    // B as rows a..a+2 (rows that column 1 misses are common factors)
+    // B as rows a..a+2 (rows that column 1 misses are common factors). Their block sums use
+    // 24-bit products, exact when rows 0..a+2 have row sums below 2^7; other jobs keep the
+    // paired walks.
     const uint32_t qa = hi[0];
-    if (quad && (qa == 2 || qa == 3) && m >= (int)qa + 3 && hi[1] > qa && hi[1] <= qa + 3 &&
+    uint64_t qsum = 0;
+    for (int i = 0; i < m; ++i)
+        if (newrow[i] < (int)qa + 3) qsum = std::max(qsum, rsum[i]);
+    if (quad && qsum < 128 && (qa == 2 || qa == 3) && m >= (int)qa + 3 && hi[1] > qa && hi[1] <= qa + 3 &&
         (uint32_t)__builtin_popcountll(colrows[gray[0]]) == qa &&
         (uint32_t)__builtin_popcountll(colrows[gray[1]]) == hi[1] - qa &&
         (colrows[gray[0]] & colrows[gray[1]]) == 0)

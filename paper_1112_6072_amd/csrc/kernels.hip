@@ -21,6 +21,9 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;   // 4 waves; every wave works on its own item
 
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+// x as a signed 24-bit value (its bits 24..31 replaced by copies of bit 23): a product of two
+// such values compiles to the full-rate 24-bit multiplier. Only for values known to fit.
+__device__ __forceinline__ int s24(int x) { return (int)((uint32_t)x << 8) >> 8; }
 __device__ __forceinline__ uint64_t uni64(uint64_t x) {
     return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
 }
@@ -508,37 +511,36 @@ __device__ __forceinline__ void rnw_item(const JobDesc &jd, const uint32_t *__re
         constexpr int HA = V - 1;
         constexpr int HB = HA + 3;
         constexpr int QB = HA == 2 ? 4 : 5;
-        // column 0's deltas on rows 0..HA-1 and column 1's on rows HA..HB-1, as wave-uniform
-        // integers
-        int ea[HA], eb[3];
+        // column 0's deltas on rows 0..HA-1 and column 1's on rows HA..HB-1 (wave-uniform)
+        float dA[HA], dB[3];
 #pragma unroll
-        for (int i = 0; i < HA; ++i) ea[i] = (int)__uint_as_float(uni(__float_as_uint(tab[i])));
+        for (int i = 0; i < HA; ++i) dA[i] = __uint_as_float(uni(__float_as_uint(tab[i])));
 #pragma unroll
-        for (int i = 0; i < 3; ++i) eb[i] = (int)__uint_as_float(uni(__float_as_uint(tab[STRIDE + HA + i])));
-        const int64_t k01 = (int64_t)uni64((uint64_t)((int64_t)ea[0] * ea[1]));
-        // Block sum: with g the rows without columns 0 and 1, A1 - A0 (for HA = 2 formed as
-        // e0 g1 + e1 g0 + e0 e1, below 2^49 in magnitude) times B1 - B0 (modulo 2^64) is
-        // (A0 - A1)(B0 - B1). Every row value with or without a column stays below 2^24 in
-        // magnitude, so the shifted rows are exact 32-bit sums.
+        for (int i = 0; i < 3; ++i) dB[i] = __uint_as_float(uni(__float_as_uint(tab[STRIDE + HA + i])));
+        // Block sum. The host gives these walks only jobs whose rows 0..HB-1 have row sums
+        // below 2^7, so every value of those rows, with or without a column, is an integer
+        // below 2^7 in magnitude: products of up to three are below 2^21 and A1 - A0, B1 - B0
+        // below 2^22, all exact in FP32 (the last product and difference fused). The two
+        // differences then go through the 24-bit multiplier (low and high halves, full rate)
+        // into the 64-bit x = (A1 - A0)(B1 - B0) = (A0 - A1)(B0 - B1), and only the suffix
+        // multiply is 64-bit.
 #define HP_QUAD_BLOCK()                                                                    \
     {                                                                                      \
-        int g_[HB];                                                                        \
-        _Pragma("unroll") for (int i_ = 0; i_ < HB; ++i_) g_[i_] = (int)f[i_];             \
-        uint64_t da;                                                                       \
+        float da;                                                                          \
         if constexpr (HA == 2) {                                                           \
-            da = (uint64_t)(k01 + (int64_t)ea[0] * g_[1] + (int64_t)ea[1] * g_[0]);        \
+            da = __builtin_fmaf(f[0] + dA[0], f[1] + dA[1], -(f[0] * f[1]));               \
         } else {                                                                           \
-            const uint64_t a0 = (uint64_t)((int64_t)g_[0] * g_[1]) * (uint64_t)(int64_t)g_[2]; \
-            const uint64_t a1 = (uint64_t)((int64_t)(g_[0] + ea[0]) * (int64_t)(g_[1] + ea[1])) * \
-                                (uint64_t)(int64_t)(g_[2] + ea[2]);                        \
-            da = a1 - a0;                                                                  \
+            const float a0 = f[0] * f[1] * f[2];                                           \
+            da = __builtin_fmaf((f[0] + dA[0]) * (f[1] + dA[1]), f[2] + dA[2], -a0);       \
         }                                                                                  \
-        const uint64_t b0 = (uint64_t)((int64_t)g_[HA] * g_[HA + 1]) * (uint64_t)(int64_t)g_[HA + 2]; \
-        const uint64_t b1 = (uint64_t)((int64_t)(g_[HA] + eb[0]) * (int64_t)(g_[HA + 1] + eb[1])) * \
-                            (uint64_t)(int64_t)(g_[HA + 2] + eb[2]);                       \
-        const uint64_t x = da * (b1 - b0);                                                 \
+        const float b0 = f[HA] * f[HA + 1] * f[HA + 2];                                    \
+        const float db = __builtin_fmaf((f[HA] + dB[0]) * (f[HA + 1] + dB[1]), f[HA + 2] + dB[2], -b0); \
+        int64_t x = (int64_t)s24((int)da) * (int64_t)s24((int)db);                         \
+        /* keep x one 24-bit product (the compiler would otherwise multiply S by each    */ \
+        /* difference in turn, two 64 x 32-bit products)                                 */ \
+        asm("" : "+v"(x));                                                                 \
         const uint32_t smask = 0u - ((t >> 2) & 1u);   /* all ones: minus (odd blocks) */  \
-        R::acc(acc, R::pair_mul(S[HB], (int64_t)x), (uint32_t)((int)G[HB] >> 31) ^ smask); \
+        R::acc(acc, R::pair_mul(S[HB], x), (uint32_t)((int)G[HB] >> 31) ^ smask);          \
     }
         // Blocks at t = 0, 4, .., L - 4 (L is a multiple of 4: the host gives this walk c >= 2).
         // Between blocks t and t + 4 column ctz(t + 4) >= 2 flips: column 2 after every other
