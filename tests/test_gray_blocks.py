@@ -138,3 +138,56 @@ def test_blocks_on_the_expansions_jobs():
         if min(seen.values()) >= 2:
             break
     assert min(seen.values()) >= 1
+
+
+def fp32_block_diffs(row, d0, d1, RA, RB):
+    """A1 - A0 and B1 - B0 as the kernels take them for rows of at most three values: the
+    product of the first two in FP32, then the third product and the difference fused (one
+    rounding of the exact value), each converted to an integer."""
+    def diff(idx, d):
+        h = [np.float32(row[i] + d[i]) for i in idx]
+        g = [np.float32(row[i]) for i in idx]
+        p0 = np.float32(g[0] * g[1]) if len(idx) > 1 else g[0]
+        p1 = np.float32(h[0] * h[1]) if len(idx) > 1 else h[0]
+        if len(idx) == 3:
+            # fused multiply-add: the exact p1 * h2 - p0 * g2 rounded once to FP32
+            q0 = np.float32(float(p0) * float(g[2]))
+            return int(np.float32(float(p1) * float(h[2]) - float(q0)))
+        return int(np.float32(float(p1) - float(p0)))
+    return diff(RA, d0), diff(RB, d1)
+
+
+@pytest.mark.parametrize("a", [2, 3])
+def test_fp32_block_sums_exact_below_2_7(a):
+    """With rows of A and B whose values stay below 2^7 in magnitude (row sums up to 127), the
+    FP32 block differences equal the integer ones in every block and fit the 24-bit
+    multiplier's operands (below 2^23); larger row sums break one or the other."""
+    rng = np.random.default_rng(40 + a)
+    m = 9
+    for trial in range(6):
+        A = np.zeros((m, m), np.int64)
+        for i in range(m):
+            cols = rng.choice(m, 3, replace=False)
+            A[i, cols] = rng.integers(1, 32, 3)
+        A[:, 0] = 0
+        A[:a, 0] = rng.integers(1, 32, a)
+        A[:, 1] = 0
+        A[a:a + 3, 1] = rng.integers(1, 32, 3)   # at most 4 entries below 32: row sums below 2^7
+        assert A.sum(1).max() < 128
+        RA, RB = list(range(a)), list(range(a, a + 3))
+        f, g = gray_rows(A, list(range(m - 1)), m - 1)
+        d0, d1 = 2 * A[:, 0], 2 * A[:, 1]
+        for q in range(f.shape[0] // 4):
+            t = 4 * q
+            row = f[t] - d0 * (g[t] & 1) - d1 * ((g[t] >> 1) & 1)
+            assert np.abs(row[:a + 3]).max() < 128 and np.abs((row + d0)[:a]).max() < 128
+            da, db = fp32_block_diffs(row, d0, d1, RA, RB)
+            assert da == int(np.prod(row[RA] + d0[RA])) - int(np.prod(row[RA]))
+            assert db == int(np.prod(row[RB] + d1[RB])) - int(np.prod(row[RB]))
+            assert abs(da) < 1 << 22 and abs(db) < 1 << 22
+    # past the bound: at row sums of 2^8 a difference of two products of three (-255^3 against
+    # 255^3) leaves the 24-bit multiplier's operand range, and at 2^9 an odd product of three
+    # no longer fits FP32's 24-bit significand
+    assert 2 * 255 ** 3 >= 1 << 23
+    big = [np.float32(511), np.float32(509), np.float32(503)]
+    assert int(np.float32(float(np.float32(big[0] * big[1])) * float(big[2]))) != 511 * 509 * 503
